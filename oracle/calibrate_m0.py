@@ -1,0 +1,86 @@
+"""Calibrate the mass shift m0 of each synthetic workload (oracle script; test
+infrastructure only).  Writes synth/m0.json.
+
+Reading: for the mu = 0 operator D(m0) = D_0 + m0 I (D_0 = the stencil with
+A = Gamma5 H), m0 solves  min Re eig(D(m0)) = rho * max |eig(D(m0))|.
+f(m0) = m0 + min Re eig(D_0) - rho * max |m0 + eig(D_0)| has slope >= 1 - rho
+> 0, so the root is unique and bisection finds it.  Small lattices use every
+eigenvalue (dense eig); larger ones use ARPACK (scipy.sparse.linalg.eigs) for
+the eigenvalues of smallest and largest real part, the only ones that decide
+f for a spectrum symmetric about the real axis shifted to the right.
+
+Usage: python -m oracle.calibrate_m0 c1 c2 ...
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+import numpy as np
+import scipy.linalg as sla
+import scipy.sparse.linalg as spla
+
+from . import operator as dop
+
+
+def m0_root(eigs: np.ndarray, rho: float) -> float:
+    lo = -float(eigs.real.min())
+    f = lambda m0: m0 + eigs.real.min() - rho * np.abs(m0 + eigs).max()
+    hi = lo + 1.0
+    while f(hi) < 0:
+        hi = lo + 2 * (hi - lo)
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(mid) < 0:
+            lo = mid
+        else:
+            hi = mid
+    return 0.5 * (lo + hi)
+
+
+def calibrate(name: str, dense_limit: int = 8192, arpack_tol: float = 1e-9):
+    import torch  # noqa: F401  (synth uses torch)
+    import synth
+    w = synth.WORKLOADS[name]
+    A0 = synth.self_blocks(w.dims, w.n_tv, 0.0, w.seed).numpy()
+    B = synth.hop_blocks(w.dims, w.n_tv, w.seed).numpy()
+    op = dop.build(w.dims, A0, B, 0.0)
+    t0 = time.time()
+    if op.N <= dense_limit:
+        ev = sla.eigvals(dop.dense(op))
+        method = "dense eig"
+    else:
+        N = op.N
+        lin = spla.LinearOperator(
+            (N, N), matvec=lambda v: dop.apply(op, v.reshape(op.V, op.n)).reshape(-1),
+            dtype=np.complex128)
+        sr = spla.eigs(lin, k=8, which="SR", tol=arpack_tol, ncv=80,
+                       maxiter=100000, return_eigenvectors=False)
+        lr = spla.eigs(lin, k=8, which="LR", tol=arpack_tol, ncv=80,
+                       maxiter=100000, return_eigenvectors=False)
+        ev = np.concatenate([sr, lr])
+        method = "ARPACK SR/LR (k=8, ncv=80)"
+    m0 = m0_root(ev, w.rho)
+    shifted = ev + m0
+    return {"m0": m0, "rho_target": w.rho,
+            "rho_achieved": float(shifted.real.min() / np.abs(shifted).max()),
+            "min_re_D0": float(ev.real.min()), "max_re_D0": float(ev.real.max()),
+            "method": method, "seconds": time.time() - t0}
+
+
+def main(names):
+    import synth
+    path = synth.M0_TABLE
+    tab = synth.load_m0_table()
+    for name in names:
+        tab[name] = calibrate(name)
+        print(name, tab[name], flush=True)
+        with open(path + ".tmp", "w") as f:
+            json.dump(tab, f, indent=1, sort_keys=True)
+        os.replace(path + ".tmp", path)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])
