@@ -1,0 +1,222 @@
+/*
+ * dcsolve.h - C ABI of the MI355X coarsest-level solver.
+ *
+ * The library solves D_c x = b for the coarsest-level operator of an
+ * aggregation-based multigrid for lattice QCD (Espinoza-Valverde, Frommer,
+ * Ramirez-Hidalgo, Rottmann, "Coarsest-level improvements in multigrid for
+ * lattice QCD on large-scale computers"):
+ *   - D_c is a nearest-neighbour block stencil on a periodic 4D lattice
+ *     (Sec. 2.2, coarsest-level structure) with n = 2*n_tv variables per site:
+ *       (D psi)_x = A_x psi_x + i*mu*Gamma5 psi_x
+ *                 + sum_mu B[x,mu] psi_{x+mu} + sum_mu Gamma5 B[x-mu,mu]^H Gamma5 psi_{x-mu},
+ *     Gamma5 = diag(+1 (n_tv times), -1 (n_tv times)), mu the twisted mass
+ *     (Sec. 2.1, twisted-mass operator).
+ *   - the solver is restarted GMRES (Sec. 3.1) with optional block-Jacobi left
+ *     preconditioning (Sec. 3.2), GMRES-polynomial right preconditioning from
+ *     Leja-ordered harmonic Ritz values (Sec. 3.3, Alg. 2, Alg. 3), and GCRO-DR
+ *     deflated restarts with recycling across right-hand sides (Sec. 3.4),
+ *     rebuilt lazily after the matrix changes (Sec. 3.6).
+ *
+ * Conventions for every entry point:
+ *   - Complex numbers are interleaved (re, im).  "complex128" = 2 doubles,
+ *     "complex64" = 2 floats.
+ *   - Lattice sites are numbered x = x0 + L0*(x1 + L1*(x2 + L2*x3)); direction
+ *     mu = 0..3 moves x_mu by +1, periodically.
+ *   - Vectors are [V][n] complex, site-major.  Blocks are [n][n] row-major
+ *     (entry (i, j) at i*n + j; row i is the output variable).
+ *   - Device pointers point to memory on the current HIP device; `stream` is a
+ *     hipStream_t (NULL = the null stream).  All device work of a call is
+ *     enqueued on that stream; calls that return host values synchronise it.
+ *   - Return value: DC_OK (0), a positive status (result written, see below)
+ *     or a negative error; nothing is thrown across the ABI.  After a negative
+ *     return, dc_last_error() gives a message (thread-local).
+ *   - Ownership: the library copies what it keeps.  Handles own their device
+ *     memory (allocated with hipMalloc at build time and on first use of a
+ *     solver variant) and free it in destroy_coarse_op.
+ *   - A handle is used by one host thread and one stream at a time.
+ */
+#ifndef DCSOLVE_H
+#define DCSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dc_op_s* dc_op_t;
+
+/* status codes */
+enum {
+  DC_OK = 0,
+  DC_NOT_CONVERGED = 1,   /* cap reached: best iterate written, stats valid   */
+  DC_ERR_INVALID = -1,    /* bad argument (null pointer, size, option)        */
+  DC_ERR_HIP = -2,        /* a HIP runtime call failed                        */
+  DC_ERR_STATE = -4,      /* handle state does not allow the call             */
+  DC_ERR_NOMEM = -5       /* device allocation failed                         */
+};
+
+/* block storage precisions kept by a handle (bit mask); FP64 is always kept */
+enum { DC_STORE_F64 = 1, DC_STORE_F32 = 2, DC_STORE_F16S = 4 };
+
+/* arithmetic of a Krylov solve / apply:
+ *  F64  : FP64 blocks and vectors
+ *  F32  : FP32 blocks and vectors, dot products accumulated in FP64
+ *  F16S : FP16 blocks with one FP32 scale per block, FP32 vectors */
+enum { DC_PREC_F64 = 0, DC_PREC_F32 = 1, DC_PREC_F16S = 2 };
+
+/* where caller-supplied block arrays live */
+enum { DC_WHERE_HOST = 0, DC_WHERE_DEVICE = 1 };
+
+typedef struct {
+  int32_t dims[4];  /* L0..L3 >= 1                                              */
+  int32_t n_tv;     /* 1..32: n = 2*n_tv variables per site                     */
+  int32_t store;    /* DC_STORE_* mask; F64 is added if missing                 */
+  int32_t where;    /* DC_WHERE_HOST or DC_WHERE_DEVICE                         */
+  double mu;        /* twisted mass (0 = clover-Wilson)                         */
+} dc_op_desc;
+
+typedef struct {
+  int32_t m;            /* basis vectors per cycle: GMRES(m), GCRO-DR(m, k)     */
+  int32_t k;            /* recycled vectors (0 = plain restarted GMRES)         */
+  int32_t d;            /* polynomial: number of harmonic Ritz values (<=1 off) */
+  int32_t u;            /* recycle-space refreshes before it is frozen          */
+  int32_t max_cycles;   /* cap on restart cycles of one (inner) solve           */
+  int32_t block_jacobi; /* 1: left block-Jacobi preconditioner (Sec. 3.2)       */
+  int32_t prec;         /* DC_PREC_* of the Krylov solve                        */
+  int32_t outer;        /* 1: FP64 flexible GMRES outer loop around the solve   */
+  int32_t m_outer;      /* outer basis size                                     */
+  int32_t max_outer;    /* cap on outer iterations                              */
+  double inner_tol;     /* relative residual asked of each inner solve          */
+  uint64_t seed;        /* seed of the polynomial's random start vector         */
+  const void* v0;       /* optional start vector of the polynomial construction,
+                           device complex128 [V][n]; NULL = seeded Gaussian      */
+} dc_solve_opts;
+
+typedef struct {
+  int32_t status;       /* DC_OK / DC_NOT_CONVERGED                              */
+  int32_t cycles;       /* restart cycles (inner cycles when an outer loop runs)  */
+  int32_t iters;        /* Arnoldi steps                                          */
+  int32_t matvecs;      /* applications of D_c (any precision)                    */
+  int32_t outer_iters;  /* flexible-GMRES outer iterations (0 without one)        */
+  int32_t rebuilt;      /* bit 0: polynomial rebuilt, bit 1: recycle space built  */
+  double rel_res_true;  /* ||b - D_c x|| / ||b|| computed in FP64 at the end      */
+  double rel_res_est;   /* last least-squares residual estimate (relative)        */
+  double t_setup_ms;    /* polynomial / recycle construction time in this call    */
+  double t_solve_ms;    /* wall time of the call                                  */
+} dc_solve_stats;
+
+/* Fill `o` with defaults: m=30, k=0, d=0, u=10, max_cycles=100000,
+ * block_jacobi=0, prec=F64, outer=0, m_outer=10, max_outer=50,
+ * inner_tol=1e-4, seed=0, v0=NULL. */
+int dc_default_opts(dc_solve_opts* o);
+
+/* Build a handle for D_c (Sec. 2.2; twisted mass Sec. 2.1).
+ *   self_blocks: complex128 [V][n][n], the self couplings A_x (without the
+ *                twisted-mass term, which the library adds from desc->mu);
+ *   hop_blocks : complex128 [V][4][n][n], B[x,mu] coupling x to x+mu; the
+ *                coupling of x+mu back to x is Gamma5 B[x,mu]^H Gamma5.
+ * Both on host or device as desc->where says; they are copied (re-laid out,
+ * and converted to the stored precisions), so the caller may free them once
+ * the stream has synchronised.  Errors: DC_ERR_INVALID for null pointers,
+ * dims < 1, n_tv outside 1..32; DC_ERR_NOMEM; DC_ERR_HIP. */
+int build_coarse_op(const dc_op_desc* desc, const void* self_blocks,
+                    const void* hop_blocks, void* stream, dc_op_t* out);
+
+/* Replace the blocks (same layout and sizes as build_coarse_op) and mark the
+ * block-Jacobi inverse, the polynomial and the recycle space stale, so that
+ * the next solve rebuilds them in that order (Sec. 3.6). */
+int update_coarse_op(dc_op_t op, const void* self_blocks, const void* hop_blocks,
+                     void* stream);
+
+/* Free everything the handle owns (synchronises its last stream). */
+void destroy_coarse_op(dc_op_t op);
+
+/* out = D_c in (adjoint = 0) or D_c^H in (adjoint = 1) with the blocks of
+ * precision `prec`; in/out device [V][n], complex128 for DC_PREC_F64 and
+ * complex64 otherwise; in and out must not overlap.  The adjoint uses
+ * D^H = Gamma5 D(-mu) Gamma5.  DC_ERR_INVALID if the precision is not stored. */
+int dc_apply(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* out,
+             void* stream);
+
+/* out = B^{-1} in with B the block diagonal of the self couplings A_x + i mu
+ * Gamma5 (Sec. 3.2); complex128 device vectors. Builds the inverses if stale. */
+int dc_apply_block_jacobi(dc_op_t op, const void* in, void* out, void* stream);
+
+/* Build (or rebuild) the preconditioning polynomial of `opts` (Alg. 3, first
+ * three steps): opts->d Arnoldi steps of the (block-Jacobi preconditioned)
+ * operator in precision opts->prec from opts->v0 (or a seeded Gaussian),
+ * harmonic Ritz values, Leja order (Alg. 2).  theta_out (host, may be NULL)
+ * receives 2*d doubles (re, im) in Leja order; *d_used the number kept (fewer
+ * than d after an early breakdown). */
+int dc_poly_setup(dc_op_t op, const dc_solve_opts* opts, void* stream,
+                  double* theta_out, int32_t* d_used);
+
+/* out = q(A~) in with the polynomial built for (opts->prec, opts->block_jacobi)
+ * (Sec. 3.3, Newton-like form, d-1 applications); vectors as in dc_apply. */
+int dc_poly_apply(dc_op_t op, const dc_solve_opts* opts, const void* in, void* out,
+                  void* stream);
+
+/* Run `steps` Arnoldi steps (Alg. 1, classical Gram-Schmidt applied twice) of
+ * the operator selected by opts (precision, block Jacobi, polynomial if
+ * opts->d > 1) from the device vector v (complex128 [V][n], normalised
+ * inside).  hbar_out (host) receives the (steps+1) x steps Hessenberg matrix,
+ * column-major complex128; *steps_done the steps completed before a breakdown. */
+int dc_arnoldi(dc_op_t op, const dc_solve_opts* opts, const void* v, int32_t steps,
+               void* stream, double* hbar_out, int32_t* steps_done);
+
+/* Solve D_c x_r = b_r for r < n_rhs to true relative residual tol[r]
+ * (||b - D_c x|| / ||b|| in FP64).  b, x: device complex128 [n_rhs][V][n];
+ * tol: host [n_rhs]; use_x0 = 1 takes x as the initial guess, else x0 = 0;
+ * stats: host [n_rhs] or NULL.  The right-hand sides are solved one after
+ * another and share the polynomial and the recycle space (Sec. 3.4: recycling
+ * across right-hand sides).  Returns DC_OK if every solve converged, else
+ * DC_NOT_CONVERGED with the best iterates written. */
+int solve_coarse(dc_op_t op, const dc_solve_opts* opts, int32_t n_rhs, const void* b,
+                 void* x, const double* tol, int32_t use_x0, void* stream,
+                 dc_solve_stats* stats);
+
+/* Same for D_c^H x = b, through Gamma5: D(mu)^H = Gamma5 D(-mu) Gamma5, so
+ * x = Gamma5 solve(D(-mu), Gamma5 b).  For mu = 0 this reuses the polynomial
+ * and recycle space of solve_coarse; for mu != 0 the D(-mu) variant keeps its
+ * own, built on first use. */
+int solve_coarse_adjoint(dc_op_t op, const dc_solve_opts* opts, int32_t n_rhs,
+                         const void* b, void* x, const double* tol, int32_t use_x0,
+                         void* stream, dc_solve_stats* stats);
+
+/* Gradient of a real loss with respect to the hop blocks, given lambda =
+ * D^{-H} dL/dx and x (device complex128 [V][n]).
+ *   tied = 0: grad device complex128 [V][8][n][n]; direction mu < 4 is the
+ *             coupling x -> x+mu: -lambda_x x_{x+mu}^H; direction 4+mu the
+ *             coupling x -> x-mu: -lambda_x x_{x-mu}^H.
+ *   tied = 1: grad device complex128 [V][4][n][n] w.r.t. B[x,mu] whose
+ *             backward coupling is Gamma5 B^H Gamma5:
+ *             -lambda_x x_{x+mu}^H - Gamma5 x_x lambda_{x+mu}^H Gamma5.
+ * (grad = dL/dRe + i dL/dIm of each entry.) */
+int dc_grad_hops(dc_op_t op, const void* lambda, const void* x, void* grad,
+                 int32_t tied, void* stream);
+
+/* Neighbour table used by the kernels, copied to host int32 [8][V]:
+ * rows 0..3 = x + mu, rows 4..7 = x - mu. */
+int dc_neighbours(dc_op_t op, int32_t* out);
+
+/* FP16 block codes and scales in the input layout (for checking the
+ * quantisation): codes host uint16 [V][5][n][n][2] (re, im bit patterns;
+ * block 0 = A_x, 1 + mu = B[x,mu]), scales host float [V][5].
+ * DC_ERR_INVALID if FP16 storage was not requested. */
+int dc_export_f16(dc_op_t op, uint16_t* codes, float* scales);
+
+/* Copy the current recycle space of the solver variant (opts->prec,
+ * opts->block_jacobi, opts->d, adjoint) to device complex128 [k][V][n]
+ * arrays U and C (either may be NULL); *k_out = its dimension (0 if none). */
+int dc_export_recycle(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint,
+                      void* U, void* C, int32_t* k_out, void* stream);
+
+/* Message of the last error on this thread ("" if none). */
+const char* dc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DCSOLVE_H */

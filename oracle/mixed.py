@@ -101,21 +101,28 @@ def fgmres(A, b, tol, m, max_cycles, precond, x0=None):
 def lowprec_apply(op, store: str):
     """The operator with blocks stored in reduced precision ('f32' or 'f16s'),
     applied in complex64 arithmetic (FP32 accumulation); input and output are
-    complex128 [V, n] (cast on the way in and out)."""
+    complex128 [V, n] (cast on the way in and out).
+
+    Reading: the self blocks are stored as given, without the twisted-mass
+    term, and i*mu*Gamma5 psi is added in the accumulation precision.  (In FP16
+    with a per-block scale, mu ~ 1e-3 would otherwise fall below the
+    quantisation step of blocks whose entries are O(1).)"""
     from .operator import gamma5
+    A0 = op.A0 if op.A0 is not None else op.A
     if store == "f32":
-        A = round_fp32(op.A)
+        A = round_fp32(A0)
         B = round_fp32(op.B)
     elif store == "f16s":
-        A = dequantize_fp16(*quantize_fp16(op.A))
+        A = dequantize_fp16(*quantize_fp16(A0))
         B = dequantize_fp16(*quantize_fp16(op.B))
     else:
         raise ValueError(store)
     g5 = gamma5(op.n).astype(np.float32)
+    tm = np.float32(op.mu)
 
     def apply(psi):
         p = psi.astype(np.complex64)
-        out = np.einsum("sij,sj->si", A, p)
+        out = np.einsum("sij,sj->si", A, p) + (1j * tm) * (g5 * p)
         for mu in range(4):
             f = op.fwd[mu]
             b = op.bwd[mu]

@@ -41,6 +41,7 @@ class CoarseOp:
     mu: float
     fwd: np.ndarray      # [4, V]
     bwd: np.ndarray      # [4, V]
+    A0: np.ndarray | None = None   # self blocks as given (without i*mu*Gamma5)
 
     @property
     def V(self):
@@ -53,22 +54,24 @@ class CoarseOp:
 
 def build(dims, self_blocks, hop_blocks, mu: float = 0.0) -> CoarseOp:
     """Assemble the operator: copy the blocks and add i*mu*Gamma5 to A."""
-    A = np.array(self_blocks, dtype=np.complex128, copy=True)
+    A0 = np.array(self_blocks, dtype=np.complex128, copy=True)
     B = np.array(hop_blocks, dtype=np.complex128, copy=True)
+    A = A0.copy()
     V, n, _ = A.shape
     g5 = gamma5(n)
     idx = np.arange(n)
     A[:, idx, idx] += 1j * mu * g5
     fwd, bwd = neighbours(dims)
-    return CoarseOp(tuple(int(d) for d in dims), n, A, B, float(mu), fwd, bwd)
+    return CoarseOp(tuple(int(d) for d in dims), n, A, B, float(mu), fwd, bwd, A0)
 
 
 def with_mu(op: CoarseOp, mu_new: float) -> CoarseOp:
     """Same blocks, twisted mass replaced by mu_new."""
-    A = op.A.copy()
+    A0 = op.A0 if op.A0 is not None else op.A
+    A = A0.copy()
     idx = np.arange(op.n)
-    A[:, idx, idx] += 1j * (mu_new - op.mu) * gamma5(op.n)
-    return CoarseOp(op.dims, op.n, A, op.B, float(mu_new), op.fwd, op.bwd)
+    A[:, idx, idx] += 1j * mu_new * gamma5(op.n)
+    return CoarseOp(op.dims, op.n, A, op.B, float(mu_new), op.fwd, op.bwd, A0)
 
 
 def apply(op: CoarseOp, psi: np.ndarray) -> np.ndarray:

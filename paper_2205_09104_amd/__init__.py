@@ -1,0 +1,284 @@
+"""MI355X coarsest-level solver: Python binding of libdcsolve.so.
+
+Thin argument marshalling over the C ABI (include/dcsolve.h): PyTorch supplies
+device memory and the current HIP stream; every step of the solve runs in the
+library's HIP kernels.  Tensors are complex128 (FP64 paths) or complex64
+(reduced-precision applies) on the current CUDA/HIP device, shaped [V, n] for
+vectors, [V, n, n] for self blocks and [V, 4, n, n] for forward hop blocks.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass, field
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (DC_PREC_F16S, DC_PREC_F32, DC_PREC_F64, DC_STORE_F16S, DC_STORE_F32,
+                   DC_STORE_F64, DcError, check, load)
+
+PREC = {"f64": DC_PREC_F64, "f32": DC_PREC_F32, "f16s": DC_PREC_F16S}
+STORE = {"f64": DC_STORE_F64, "f32": DC_STORE_F32, "f16s": DC_STORE_F16S}
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr())
+
+
+def _vec_dtype(prec: str):
+    return torch.complex128 if prec == "f64" else torch.complex64
+
+
+@dataclass
+class Opts:
+    """Solver options (mirror of dc_solve_opts)."""
+    m: int = 30
+    k: int = 0
+    d: int = 0
+    u: int = 10
+    max_cycles: int = 100000
+    block_jacobi: int = 0
+    prec: str = "f64"
+    outer: int = 0
+    m_outer: int = 10
+    max_outer: int = 50
+    inner_tol: float = 1e-4
+    seed: int = 0
+    v0: torch.Tensor | None = field(default=None, repr=False)
+
+    def to_c(self) -> _lib.SolveOpts:
+        o = _lib.SolveOpts()
+        o.m, o.k, o.d, o.u = self.m, self.k, self.d, self.u
+        o.max_cycles, o.block_jacobi = self.max_cycles, self.block_jacobi
+        o.prec = PREC[self.prec]
+        o.outer, o.m_outer, o.max_outer = self.outer, self.m_outer, self.max_outer
+        o.inner_tol, o.seed = float(self.inner_tol), int(self.seed)
+        if self.v0 is not None:
+            assert self.v0.dtype == torch.complex128 and self.v0.is_cuda
+            o.v0 = self.v0.data_ptr()
+        return o
+
+
+class CoarseOp:
+    """Handle of the coarse operator D_c (build_coarse_op)."""
+
+    def __init__(self, self_blocks: torch.Tensor, hop_blocks: torch.Tensor, dims, mu=0.0,
+                 store=("f64",), stream=None):
+        lib = load()
+        assert self_blocks.dtype == torch.complex128 and hop_blocks.dtype == torch.complex128
+        V, n, n2 = self_blocks.shape
+        assert n == n2 and n % 2 == 0 and hop_blocks.shape == (V, 4, n, n)
+        self.dims = tuple(int(d) for d in dims)
+        assert int(np.prod(self.dims)) == V
+        self.V, self.n, self.mu = V, n, float(mu)
+        self.store = tuple(store)
+        desc = _lib.OpDesc()
+        for i in range(4):
+            desc.dims[i] = self.dims[i]
+        desc.n_tv = n // 2
+        desc.store = sum(STORE[s] for s in set(store) | {"f64"})
+        on_dev = self_blocks.is_cuda
+        assert hop_blocks.is_cuda == on_dev
+        desc.where = _lib.DC_WHERE_DEVICE if on_dev else _lib.DC_WHERE_HOST
+        desc.mu = self.mu
+        sb = self_blocks.contiguous()
+        hb = hop_blocks.contiguous()
+        h = C.c_void_p()
+        check(lib.build_coarse_op(C.byref(desc), _ptr(sb), _ptr(hb), _stream_ptr(stream)
+                                  if on_dev or torch.cuda.is_available() else None,
+                                  C.byref(h)))
+        self._h = h
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            load().destroy_coarse_op(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def update(self, self_blocks, hop_blocks, stream=None):
+        check(load().update_coarse_op(self._h, _ptr(self_blocks.contiguous()),
+                                      _ptr(hop_blocks.contiguous()), _stream_ptr(stream)))
+
+    # -- operator
+    def empty(self, prec="f64", batch=None):
+        shape = (self.V, self.n) if batch is None else (batch, self.V, self.n)
+        return torch.empty(shape, dtype=_vec_dtype(prec), device="cuda")
+
+    def apply(self, x: torch.Tensor, prec="f64", adjoint=False, out=None, stream=None):
+        x = x.contiguous()
+        assert x.dtype == _vec_dtype(prec) and x.shape == (self.V, self.n)
+        out = self.empty(prec) if out is None else out
+        check(load().dc_apply(self._h, PREC[prec], int(adjoint), _ptr(x), _ptr(out),
+                              _stream_ptr(stream)))
+        return out
+
+    def grad_hops(self, lam: torch.Tensor, x: torch.Tensor, tied=True, stream=None):
+        g = torch.empty((self.V, 4 if tied else 8, self.n, self.n), dtype=torch.complex128,
+                        device="cuda")
+        check(load().dc_grad_hops(self._h, _ptr(lam.contiguous()), _ptr(x.contiguous()),
+                                  _ptr(g), int(tied), _stream_ptr(stream)))
+        return g
+
+    def neighbours(self) -> np.ndarray:
+        out = np.empty((8, self.V), dtype=np.int32)
+        check(load().dc_neighbours(self._h, out.ctypes.data_as(C.POINTER(C.c_int32))))
+        return out
+
+    def export_f16(self):
+        codes = np.empty((self.V, 5, self.n, self.n, 2), dtype=np.uint16)
+        scales = np.empty((self.V, 5), dtype=np.float32)
+        check(load().dc_export_f16(self._h, codes.ctypes.data_as(C.POINTER(C.c_uint16)),
+                                   scales.ctypes.data_as(C.POINTER(C.c_float))))
+        return codes, scales
+
+    # -- polynomial / Arnoldi
+    def poly_setup(self, opts: Opts, stream=None) -> np.ndarray:
+        th = np.zeros(2 * max(opts.d, 1), dtype=np.float64)
+        du = C.c_int32()
+        o = opts.to_c()
+        check(load().dc_poly_setup(self._h, C.byref(o), _stream_ptr(stream),
+                                   th.ctypes.data_as(C.POINTER(C.c_double)), C.byref(du)))
+        return (th[0::2] + 1j * th[1::2])[:du.value]
+
+    def poly_apply(self, x: torch.Tensor, opts: Opts, stream=None):
+        x = x.contiguous()
+        out = torch.empty_like(x)
+        o = opts.to_c()
+        check(load().dc_poly_apply(self._h, C.byref(o), _ptr(x), _ptr(out), _stream_ptr(stream)))
+        return out
+
+    def arnoldi(self, v: torch.Tensor, steps: int, opts: Opts, stream=None):
+        hb = np.zeros(2 * (steps + 1) * steps, dtype=np.float64)
+        sd = C.c_int32()
+        o = opts.to_c()
+        check(load().dc_arnoldi(self._h, C.byref(o), _ptr(v.contiguous()), int(steps),
+                                _stream_ptr(stream), hb.ctypes.data_as(C.POINTER(C.c_double)),
+                                C.byref(sd)))
+        H = (hb[0::2] + 1j * hb[1::2]).reshape(steps, steps + 1).T
+        return H[:sd.value + 1, :sd.value], sd.value
+
+    # -- solves
+    def solve(self, b: torch.Tensor, tol, opts: Opts | None = None, x0=None, adjoint=False,
+              stream=None):
+        """Solve D_c x = b (or D_c^H x = b).  b: [V, n] or [R, V, n] complex128.
+        Returns (x, [stats dict per right-hand side], return code)."""
+        opts = opts or Opts()
+        single = b.dim() == 2
+        bb = (b[None] if single else b).contiguous()
+        R = bb.shape[0]
+        assert bb.dtype == torch.complex128 and bb.shape[1:] == (self.V, self.n)
+        if x0 is not None:
+            x = (x0[None] if single else x0).clone().contiguous()
+        else:
+            x = torch.empty_like(bb)
+        tols = np.broadcast_to(np.asarray(tol, dtype=np.float64), (R,)).copy()
+        stats = (_lib.SolveStats * R)()
+        o = opts.to_c()
+        fn = load().solve_coarse_adjoint if adjoint else load().solve_coarse
+        rc = check(fn(self._h, C.byref(o), R, _ptr(bb), _ptr(x),
+                      tols.ctypes.data_as(C.POINTER(C.c_double)), int(x0 is not None),
+                      _stream_ptr(stream), stats))
+        st = [stats[i].as_dict() for i in range(R)]
+        return (x[0] if single else x), st, rc
+
+    def export_recycle(self, opts: Opts, adjoint=False, stream=None):
+        k = max(opts.k, 1)
+        U = torch.zeros((k, self.V, self.n), dtype=torch.complex128, device="cuda")
+        Cm = torch.zeros_like(U)
+        kk = C.c_int32()
+        o = opts.to_c()
+        check(load().dc_export_recycle(self._h, C.byref(o), int(adjoint), _ptr(U), _ptr(Cm),
+                                       C.byref(kk), _stream_ptr(stream)))
+        return U[:kk.value], Cm[:kk.value]
+
+
+class CoarseSolve(torch.autograd.Function):
+    """x = D_c^{-1} b with gradients for b and the (tied) forward hop blocks.
+
+    backward: lambda = D_c^{-H} g (adjoint solve through Gamma5), grad_b = lambda,
+    grad_B[x, mu] = -lambda_x x_{x+mu}^H - Gamma5 x_x lambda_{x+mu}^H Gamma5.
+    `hops` must be the tensor the handle `op` was built from.
+    """
+
+    @staticmethod
+    def forward(ctx, b, hops, op: CoarseOp, opts: Opts, tol: float):
+        x, st, rc = op.solve(b.detach(), tol, opts)
+        if rc != 0:
+            raise DcError(rc, f"forward solve did not converge: {st}")
+        ctx.op, ctx.opts, ctx.tol = op, opts, tol
+        ctx.save_for_backward(x)
+        return x
+
+    @staticmethod
+    def backward(ctx, g):
+        (x,) = ctx.saved_tensors
+        lam, st, rc = ctx.op.solve(g.contiguous(), ctx.tol, ctx.opts, adjoint=True)
+        if rc != 0:
+            raise DcError(rc, f"adjoint solve did not converge: {st}")
+        grad_hops = ctx.op.grad_hops(lam, x, tied=True) if ctx.needs_input_grad[1] else None
+        return lam, grad_hops, None, None, None
+
+
+# host-only dense helpers (no device needed)
+def dense_eig(A: np.ndarray, vectors=False):
+    lib = load()
+    n = A.shape[0]
+    a = _colmajor(A)
+    w = np.zeros(2 * n)
+    Z = np.zeros(2 * n * n) if vectors else None
+    check(lib.dc_dense_eig(n, a.ctypes.data_as(C.POINTER(C.c_double)),
+                           w.ctypes.data_as(C.POINTER(C.c_double)),
+                           Z.ctypes.data_as(C.POINTER(C.c_double)) if vectors else None))
+    ev = w[0::2] + 1j * w[1::2]
+    if not vectors:
+        return ev
+    Zc = (Z[0::2] + 1j * Z[1::2]).reshape(n, n).T
+    return ev, Zc
+
+
+def _colmajor(A):
+    return np.ascontiguousarray(np.asarray(A, dtype=np.complex128).T).view(np.float64).ravel()
+
+
+def dense_lstsq(A: np.ndarray, b: np.ndarray):
+    lib = load()
+    rows, cols = A.shape
+    a = _colmajor(A)
+    bb = np.ascontiguousarray(np.asarray(b, dtype=np.complex128)).view(np.float64)
+    x = np.zeros(2 * cols)
+    rn = C.c_double()
+    check(lib.dc_dense_lstsq(rows, cols, a.ctypes.data_as(C.POINTER(C.c_double)),
+                             bb.ctypes.data_as(C.POINTER(C.c_double)),
+                             x.ctypes.data_as(C.POINTER(C.c_double)), C.byref(rn)))
+    return x[0::2] + 1j * x[1::2], rn.value
+
+
+def harmonic_ritz(Hbar: np.ndarray):
+    lib = load()
+    d = Hbar.shape[1]
+    h = _colmajor(Hbar)
+    th = np.zeros(2 * d)
+    check(lib.dc_harmonic_ritz(d, h.ctypes.data_as(C.POINTER(C.c_double)),
+                               th.ctypes.data_as(C.POINTER(C.c_double))))
+    return th[0::2] + 1j * th[1::2]
+
+
+def leja_order(theta: np.ndarray):
+    lib = load()
+    t = np.ascontiguousarray(np.asarray(theta, dtype=np.complex128)).view(np.float64)
+    out = np.zeros_like(t)
+    check(lib.dc_leja_order(len(theta), t.ctypes.data_as(C.POINTER(C.c_double)),
+                            out.ctypes.data_as(C.POINTER(C.c_double))))
+    return out[0::2] + 1j * out[1::2]

@@ -1,0 +1,1111 @@
+// HIP kernels for gfx950 (CDNA4): coarse-operator apply, Gram-Schmidt
+// reductions, tall-skinny combinations, conversions and the gradient kernel.
+#include "kernels.hpp"
+
+#include <hip/hip_fp16.h>
+
+namespace dc {
+
+namespace {
+
+constexpr int kWave = 64;
+
+template <typename T>
+__device__ inline T shfl_xor(T v, int m) {
+  return __shfl_xor(v, m, kWave);
+}
+
+__device__ inline double gam(int i, int n) { return i < (n >> 1) ? 1.0 : -1.0; }
+
+template <typename R>
+__device__ inline cx<R> ld(const cx<R>* p) {
+  return *p;
+}
+
+// Block-wide sum of W doubles per thread (blockDim.x a multiple of 64, <= 1024)
+// followed by the deterministic last-block-done grid reduction into result[0..W).
+template <int W>
+__device__ void grid_reduce(double (&v)[W], Reducer red, double* result) {
+  __shared__ double sh[16][W];
+  __shared__ bool last;
+  const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+#pragma unroll
+  for (int t = 0; t < W; ++t) {
+    double s = v[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += shfl_xor(s, o);
+    if (lane == 0) sh[wave][t] = s;
+  }
+  __syncthreads();
+  const int bid = blockIdx.x + blockIdx.y * gridDim.x;
+  const int nblk = gridDim.x * gridDim.y;
+  if (threadIdx.x < W) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += sh[w][threadIdx.x];
+    red.partials[size_t(bid) * W + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(red.counter, 1u);
+    last = (prev == unsigned(nblk - 1));
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    for (int t = threadIdx.x; t < W; t += blockDim.x) {
+      double s = 0.0;
+      for (int b = 0; b < nblk; ++b) s += __builtin_nontemporal_load(&red.partials[size_t(b) * W + t]);
+      result[t] = s;
+    }
+    if (threadIdx.x == 0) *red.counter = 0u;
+  }
+}
+
+// ------------------------------------------------------------------ layout
+// Tiled layout: block = 8 x 8 lane grid of T x T sub-tiles; lane l = lr*8+lc
+// owns rows lr*T .. lr*T+T-1 and columns lc*T .. lc*T+T-1; its element
+// e = a*T + b is (lr*T + a, lc*T + b).  Element e of lane l lives in 16-byte
+// unit (e / EPL)*64 + l, slot e % EPL.
+
+__device__ uint16_t f64_to_f16_rne(double x) {
+  const uint64_t b = __double_as_longlong(x);
+  const uint16_t sign = uint16_t((b >> 48) & 0x8000u);
+  const int exp = int((b >> 52) & 0x7ff);
+  const uint64_t mant = b & ((uint64_t(1) << 52) - 1);
+  if (exp == 0x7ff) return sign | 0x7c00u | (mant ? 0x200u : 0u);
+  if (exp == 0) return sign;  // FP64 subnormals are far below the FP16 range
+  const int e = exp - 1023;
+  if (e > 15) return sign | 0x7c00u;
+  const uint64_t m = mant | (uint64_t(1) << 52);
+  const int shift = (e >= -14) ? 42 : 42 + (-14 - e);
+  if (shift >= 64) return sign;
+  uint64_t keep = m >> shift;
+  const uint64_t rem = m & ((uint64_t(1) << shift) - 1);
+  const uint64_t half = uint64_t(1) << (shift - 1);
+  if (rem > half || (rem == half && (keep & 1))) keep += 1;
+  if (e >= -14) {
+    uint32_t hexp = uint32_t(e + 15);
+    if (keep >= (uint64_t(1) << 11)) {
+      keep >>= 1;
+      hexp += 1;
+    }
+    if (hexp >= 31) return sign | 0x7c00u;
+    return uint16_t(sign | (hexp << 10) | uint32_t(keep & 0x3ffu));
+  }
+  return uint16_t(sign | uint32_t(keep));  // subnormal (or the smallest normal)
+}
+
+__global__ void k_layout(const z64* __restrict__ self_in, const z64* __restrict__ hops_in,
+                         int V, int n, z64* __restrict__ o64, z32* __restrict__ o32,
+                         uint32_t* __restrict__ o16, float* __restrict__ sc16) {
+  const int blk = blockIdx.x;  // site*5 + slot
+  const int site = blk / 5, slot = blk % 5;
+  const size_t nn = size_t(n) * n;
+  const z64* src = (slot == 0) ? self_in + size_t(site) * nn
+                               : hops_in + (size_t(site) * 4 + (slot - 1)) * nn;
+  const int T = (n + 7) / 8;
+  const int TT = T * T;
+  // block max of |Re|, |Im| for the FP16 scale
+  __shared__ double smax[256];
+  double mx = 0.0;
+  for (size_t t = threadIdx.x; t < nn; t += blockDim.x) {
+    const z64 z = src[t];
+    mx = fmax(mx, fmax(fabs(z.re), fabs(z.im)));
+  }
+  smax[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) smax[threadIdx.x] = fmax(smax[threadIdx.x], smax[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const float scale = float(smax[0]);
+  const double dscale = double(scale);
+  if (o16 && threadIdx.x == 0) sc16[blk] = scale;
+  const int tt64 = ((TT + 0) / 1) * 1, tt32 = (TT + 1) / 2 * 2, tt16 = (TT + 3) / 4 * 4;
+  const int total = 64 * tt16;  // covers every padded position of every layout
+  for (int t = threadIdx.x; t < total; t += blockDim.x) {
+    const int lane = t & 63, e = t >> 6;
+    const int lr = lane >> 3, lc = lane & 7;
+    const int a = e / T, bcol = e - a * T;
+    const int i = lr * T + a, j = lc * T + bcol;
+    z64 z = mk(0.0, 0.0);
+    if (e < TT && i < n && j < n) z = src[size_t(i) * n + j];
+    if (o64 && e < tt64) o64[size_t(blk) * tt64 * 64 + size_t(e) * 64 + lane] = z;
+    if (o32 && e < tt32)
+      o32[size_t(blk) * tt32 * 64 + (size_t(e >> 1) * 64 + lane) * 2 + (e & 1)] =
+          mk(float(z.re), float(z.im));
+    if (o16) {
+      uint16_t cr = 0, ci = 0;
+      if (dscale > 0.0) {
+        cr = f64_to_f16_rne(z.re / dscale);
+        ci = f64_to_f16_rne(z.im / dscale);
+      }
+      o16[size_t(blk) * tt16 * 64 + (size_t(e >> 2) * 64 + lane) * 4 + (e & 3)] =
+          uint32_t(cr) | (uint32_t(ci) << 16);
+    }
+  }
+}
+
+__global__ void k_neighbours(int* nbr, int L0, int L1, int L2, int L3) {
+  const int V = L0 * L1 * L2 * L3;
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= V) return;
+  int c[4];
+  c[0] = x % L0;
+  c[1] = (x / L0) % L1;
+  c[2] = (x / (L0 * L1)) % L2;
+  c[3] = x / (L0 * L1 * L2);
+  const int L[4] = {L0, L1, L2, L3};
+  for (int mu = 0; mu < 4; ++mu) {
+    for (int dir = 0; dir < 2; ++dir) {
+      int d[4] = {c[0], c[1], c[2], c[3]};
+      d[mu] = dir == 0 ? (d[mu] + 1) % L[mu] : (d[mu] + L[mu] - 1) % L[mu];
+      nbr[(dir * 4 + mu) * V + x] = d[0] + L0 * (d[1] + L1 * (d[2] + L2 * d[3]));
+    }
+  }
+}
+
+// ------------------------------------------------------------------ apply
+// Element loaders of one lane's sub-tile for each storage precision.
+template <int T, int P>
+struct Tile;
+
+template <int T>
+struct Tile<T, P64> {
+  using A = double;
+  static constexpr int TT = T * T;
+  static constexpr int UNITS = TT;  // one complex double per 16-byte unit
+  __device__ static void load(const void* base, int lane, cx<double> (&m)[TT]) {
+    const double2* p = static_cast<const double2*>(base);
+#pragma unroll
+    for (int e = 0; e < TT; ++e) {
+      const double2 v = p[e * 64 + lane];
+      m[e] = mk(v.x, v.y);
+    }
+  }
+};
+
+template <int T>
+struct Tile<T, P32> {
+  using A = float;
+  static constexpr int TT = T * T;
+  static constexpr int UNITS = (TT + 1) / 2;
+  __device__ static void load(const void* base, int lane, cx<float> (&m)[TT]) {
+    const float4* p = static_cast<const float4*>(base);
+#pragma unroll
+    for (int u = 0; u < UNITS; ++u) {
+      const float4 v = p[u * 64 + lane];
+      m[2 * u] = mk(v.x, v.y);
+      if (2 * u + 1 < TT) m[2 * u + 1] = mk(v.z, v.w);
+    }
+  }
+};
+
+__device__ inline float h2f(uint32_t bits16) {
+  return __half2float(__ushort_as_half(static_cast<unsigned short>(bits16 & 0xffffu)));
+}
+
+template <int T>
+struct Tile<T, P16S> {
+  using A = float;
+  static constexpr int TT = T * T;
+  static constexpr int UNITS = (TT + 3) / 4;
+  __device__ static void load(const void* base, int lane, cx<float> (&m)[TT]) {
+    const uint4* p = static_cast<const uint4*>(base);
+#pragma unroll
+    for (int u = 0; u < UNITS; ++u) {
+      const uint4 v = p[u * 64 + lane];
+      const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (4 * u + q < TT) m[4 * u + q] = mk(h2f(w[q]), h2f(w[q] >> 16));
+    }
+  }
+};
+
+template <int P>
+struct VecOf {
+  using R = float;
+};
+template <>
+struct VecOf<P64> {
+  using R = double;
+};
+
+// One workgroup (5 waves) per site; wave w < 4 handles the hop block B[x, w],
+// wave 4 the self block A[x].  Each wave reads its block once (16-byte loads,
+// 1 KB contiguous per wave and load) and forms from registers both the forward
+// product B psi_{x+mu} (row sums, reduced over the 8 lanes of a lane-row) and
+// the backward product Gamma5 B^H Gamma5 psi_x (column sums, reduced over the 8
+// lanes of a lane-column).
+template <int T, int P>
+__global__ __launch_bounds__(320) void k_apply_blocks(
+    const void* __restrict__ blocks, const float* __restrict__ scales,
+    const cx<typename VecOf<P>::R>* __restrict__ psi, cx<typename VecOf<P>::R>* __restrict__ gbuf,
+    const int* __restrict__ nbr, int V, int n, int chunk, double tm, const int* __restrict__ done) {
+  using TL = Tile<T, P>;
+  using A = typename TL::A;
+  using VR = typename VecOf<P>::R;
+  if (done && *done) return;
+  // XCD-aware order: workgroup b runs on XCD b % 8; each XCD gets a contiguous
+  // range of sites so that neighbour vectors are shared through its L2.
+  const int b = blockIdx.x;
+  const int site = (b & 7) * chunk + (b >> 3);
+  if (site >= V) return;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lr = lane >> 3, lc = lane & 7;
+  const int slot = (wave < 4) ? 1 + wave : 0;
+  constexpr int TT = TL::TT;
+  const size_t blk_units = size_t(TL::UNITS) * 64;
+  const uint4* bp = static_cast<const uint4*>(blocks) + (size_t(site) * 5 + slot) * blk_units;
+
+  cx<A> m[TT];
+  TL::load(bp, lane, m);
+
+  const int src = (wave < 4) ? nbr[wave * V + site] : site;
+  cx<A> pc[T], pr[T];
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+    const int col = lc * T + q;
+    pc[q] = mk(A(0), A(0));
+    if (col < n) {
+      const cx<VR> z = psi[size_t(src) * n + col];
+      pc[q] = mk(A(z.re), A(z.im));
+    }
+    const int row = lr * T + q;
+    pr[q] = mk(A(0), A(0));
+    if (row < n) {
+      const cx<VR> z = psi[size_t(site) * n + row];
+      const A g = A(gam(row, n));
+      pr[q] = mk(A(g * A(z.re)), A(g * A(z.im)));
+    }
+  }
+  cx<A> f[T], g[T];
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+    f[q] = mk(A(0), A(0));
+    g[q] = mk(A(0), A(0));
+  }
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+      const cx<A> z = m[a * T + c];
+      f[a].re += z.re * pc[c].re - z.im * pc[c].im;
+      f[a].im += z.re * pc[c].im + z.im * pc[c].re;
+      g[c].re += z.re * pr[a].re + z.im * pr[a].im;
+      g[c].im += z.re * pr[a].im - z.im * pr[a].re;
+    }
+  if (P == P16S) {
+    const A s = A(scales[size_t(site) * 5 + slot]);
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      f[q].re *= s;
+      f[q].im *= s;
+      g[q].re *= s;
+      g[q].im *= s;
+    }
+  }
+  // row sums over lc (lanes lr*8 .. lr*8+7), column sums over lr (stride 8)
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      f[q].re += shfl_xor(f[q].re, o);
+      f[q].im += shfl_xor(f[q].im, o);
+    }
+  }
+  if (wave < 4) {
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+#pragma unroll
+      for (int o = 8; o < 64; o <<= 1) {
+        g[q].re += shfl_xor(g[q].re, o);
+        g[q].im += shfl_xor(g[q].im, o);
+      }
+    }
+  }
+  __shared__ cx<A> fpart[5][64];
+  if (lc == 0) {
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      const int row = lr * T + q;
+      if (row < n) fpart[wave][row] = f[q];
+    }
+  }
+  if (wave < 4 && lr == 0) {
+    const int dst = src;  // x + mu receives Gamma5 B[x,mu]^H Gamma5 psi_x
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      const int col = lc * T + q;
+      if (col < n) {
+        const A gg = A(gam(col, n));
+        gbuf[(size_t(dst) * 5 + wave) * n + col] = mk(VR(gg * g[q].re), VR(gg * g[q].im));
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < n) {
+    const int i = threadIdx.x;
+    cx<A> s = fpart[4][i];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      s.re += fpart[w][i].re;
+      s.im += fpart[w][i].im;
+    }
+    if (tm != 0.0) {  // i * tm * Gamma5 psi_x, exact in the accumulation precision
+      const cx<VR> z = psi[size_t(site) * n + i];
+      const A t = A(tm * gam(i, n));
+      s.re -= t * A(z.im);
+      s.im += t * A(z.re);
+    }
+    gbuf[(size_t(site) * 5 + 4) * n + i] = mk(VR(s.re), VR(s.im));
+  }
+}
+
+template <typename VR>
+__device__ inline cx<VR> gather5(const cx<VR>* __restrict__ gbuf, size_t i, int n) {
+  const size_t site = i / n, c = i - site * n;
+  const size_t base = site * 5 * n + c;
+  cx<VR> s = gbuf[base + 4 * size_t(n)];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const cx<VR> t = gbuf[base + size_t(w) * n];
+    s.re += t.re;
+    s.im += t.im;
+  }
+  return s;
+}
+
+template <typename VR>
+__global__ void k_gather_store(const cx<VR>* __restrict__ gbuf, cx<VR>* __restrict__ out,
+                               size_t N, int n, const int* __restrict__ done) {
+  if (done && *done) return;
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  out[i] = gather5(gbuf, i, n);
+}
+
+template <typename VR>
+__global__ void k_gather_poly(const cx<VR>* __restrict__ gbuf, cx<VR>* __restrict__ prod,
+                              cx<VR>* __restrict__ y, size_t N, int n, z64 ca, z64 cb,
+                              const int* __restrict__ done) {
+  if (done && *done) return;
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const cx<VR> s = gather5(gbuf, i, n);
+  cx<VR> p = prod[i];
+  const VR ar = VR(ca.re), ai = VR(ca.im), br = VR(cb.re), bi = VR(cb.im);
+  p.re -= ar * s.re - ai * s.im;
+  p.im -= ar * s.im + ai * s.re;
+  prod[i] = p;
+  cx<VR> yy = y[i];
+  yy.re += br * p.re - bi * p.im;
+  yy.im += br * p.im + bi * p.re;
+  y[i] = yy;
+}
+
+template <typename VR>
+__global__ void k_gather_poly_first(const cx<VR>* __restrict__ gbuf, const cx<VR>* __restrict__ v,
+                                    cx<VR>* __restrict__ prod, cx<VR>* __restrict__ y, size_t N,
+                                    int n, z64 c0, z64 ca, z64 cb, const int* __restrict__ done) {
+  if (done && *done) return;
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= N) return;
+  const cx<VR> s = gather5(gbuf, i, n);
+  const cx<VR> vv = v[i];
+  cx<VR> p = vv;
+  const VR ar = VR(ca.re), ai = VR(ca.im), br = VR(cb.re), bi = VR(cb.im);
+  const VR zr = VR(c0.re), zi = VR(c0.im);
+  p.re -= ar * s.re - ai * s.im;
+  p.im -= ar * s.im + ai * s.re;
+  prod[i] = p;
+  cx<VR> yy;
+  yy.re = zr * vv.re - zi * vv.im + (br * p.re - bi * p.im);
+  yy.im = zr * vv.im + zi * vv.re + (br * p.im + bi * p.re);
+  y[i] = yy;
+}
+
+template <typename VR>
+__global__ void k_gather_resid(const cx<VR>* __restrict__ gbuf, const cx<VR>* __restrict__ b,
+                               cx<VR>* __restrict__ out, size_t N, int n, Reducer red,
+                               double* result) {
+  double acc[1] = {0.0};
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N;
+       i += size_t(gridDim.x) * blockDim.x) {
+    const cx<VR> s = gather5(gbuf, i, n);
+    const cx<VR> bb = b[i];
+    const cx<VR> r = mk(VR(bb.re - s.re), VR(bb.im - s.im));
+    out[i] = r;
+    acc[0] += double(r.re) * double(r.re) + double(r.im) * double(r.im);
+  }
+  grid_reduce<1>(acc, red, result);
+}
+
+// ------------------------------------------------------------------ BLAS
+constexpr int kQG = 16;  // dot products per workgroup group
+
+template <typename VR>
+__global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0, int q0,
+                                                  const cx<VR>* __restrict__ b1, int q1,
+                                                  size_t N, const cx<VR>* __restrict__ w,
+                                                  int want_norm, Reducer red, double* result,
+                                                  const int* __restrict__ done) {
+  if (done && *done) return;
+  const int Q = q0 + q1 + (want_norm ? 1 : 0);
+  const int g0 = blockIdx.y * kQG;
+  double acc[2 * kQG];
+#pragma unroll
+  for (int t = 0; t < 2 * kQG; ++t) acc[t] = 0.0;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const cx<VR> wv = w[i];
+    const double wr = wv.re, wi = wv.im;
+#pragma unroll
+    for (int t = 0; t < kQG; ++t) {
+      const int q = g0 + t;
+      if (q < Q) {
+        cx<VR> v;
+        if (q < q0) v = b0[size_t(q) * N + i];
+        else if (q < q0 + q1) v = b1[size_t(q - q0) * N + i];
+        else v = wv;
+        const double vr = v.re, vi = v.im;
+        acc[2 * t] += vr * wr + vi * wi;      // conj(v) * w
+        acc[2 * t + 1] += vr * wi - vi * wr;
+      }
+    }
+  }
+  // reduce: one grid reduction across all (x, y) blocks of 2*kQG values each;
+  // block (x, y) stores its group's values, the last block sums per group.
+  __shared__ double sh[4][2 * kQG];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int t = 0; t < 2 * kQG; ++t) {
+    double s = acc[t];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += shfl_xor(s, o);
+    if (lane == 0) sh[wave][t] = s;
+  }
+  __syncthreads();
+  const int gx = gridDim.x;
+  if (threadIdx.x < 2 * kQG) {
+    double s = 0.0;
+    for (int wv = 0; wv < int(blockDim.x >> 6); ++wv) s += sh[wv][threadIdx.x];
+    red.partials[(size_t(blockIdx.y) * gx + blockIdx.x) * (2 * kQG) + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(red.counter, 1u);
+    last = (prev == unsigned(gx * gridDim.y - 1));
+  }
+  __syncthreads();
+  if (last) {
+    __threadfence();
+    for (int t = threadIdx.x; t < int(gridDim.y) * 2 * kQG; t += blockDim.x) {
+      const int gy = t / (2 * kQG), c = t % (2 * kQG);
+      const int q = gy * kQG + c / 2;
+      if (q >= Q) continue;
+      double s = 0.0;
+      for (int bx = 0; bx < gx; ++bx)
+        s += __builtin_nontemporal_load(&red.partials[(size_t(gy) * gx + bx) * (2 * kQG) + c]);
+      result[2 * q + (c & 1)] = s;
+    }
+    if (threadIdx.x == 0) *red.counter = 0u;
+  }
+}
+
+template <typename VR>
+__global__ __launch_bounds__(256) void k_multiaxpy(cx<VR>* __restrict__ w,
+                                                   const cx<VR>* __restrict__ b0, int q0,
+                                                   const cx<VR>* __restrict__ b1, int q1,
+                                                   size_t N, const double* __restrict__ coef,
+                                                   int want_norm, Reducer red, double* result,
+                                                   const int* __restrict__ done) {
+  if (done && *done) return;
+  double nacc[1] = {0.0};
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const cx<VR> wv = w[i];
+    double sr = wv.re, si = wv.im;
+    for (int q = 0; q < q0 + q1; ++q) {
+      const cx<VR> v = (q < q0) ? b0[size_t(q) * N + i] : b1[size_t(q - q0) * N + i];
+      const double cr = coef[2 * q], ci = coef[2 * q + 1];
+      sr -= cr * double(v.re) - ci * double(v.im);
+      si -= cr * double(v.im) + ci * double(v.re);
+    }
+    const cx<VR> o = mk(VR(sr), VR(si));
+    w[i] = o;
+    nacc[0] += double(o.re) * double(o.re) + double(o.im) * double(o.im);
+  }
+  if (want_norm) grid_reduce<1>(nacc, red, result);
+}
+
+constexpr int kCombR = 16;  // outputs per pass of the combine kernel
+
+template <typename VR>
+__global__ __launch_bounds__(256) void k_combine(const cx<VR>* __restrict__ b0, int q0,
+                                                 const cx<VR>* __restrict__ b1, int q1,
+                                                 size_t N, const double* __restrict__ coef,
+                                                 int R, cx<VR>* __restrict__ out, int accumulate) {
+  const int Q = q0 + q1;
+  const int r0 = blockIdx.y * kCombR;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    double ar[kCombR], ai[kCombR];
+#pragma unroll
+    for (int t = 0; t < kCombR; ++t) ar[t] = ai[t] = 0.0;
+    for (int q = 0; q < Q; ++q) {
+      const cx<VR> v = (q < q0) ? b0[size_t(q) * N + i] : b1[size_t(q - q0) * N + i];
+      const double vr = v.re, vi = v.im;
+#pragma unroll
+      for (int t = 0; t < kCombR; ++t) {
+        const int r = r0 + t;
+        if (r < R) {
+          const double cr = coef[2 * (size_t(r) * Q + q)], ci = coef[2 * (size_t(r) * Q + q) + 1];
+          ar[t] += cr * vr - ci * vi;
+          ai[t] += cr * vi + ci * vr;
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kCombR; ++t) {
+      const int r = r0 + t;
+      if (r < R) {
+        cx<VR>* o = out + size_t(r) * N + i;
+        if (accumulate) {
+          const cx<VR> old = *o;
+          *o = mk(VR(double(old.re) + ar[t]), VR(double(old.im) + ai[t]));
+        } else {
+          *o = mk(VR(ar[t]), VR(ai[t]));
+        }
+      }
+    }
+  }
+}
+
+template <typename VR>
+__global__ void k_scale(const cx<VR>* __restrict__ in, cx<VR>* __restrict__ out, size_t N,
+                        const double* __restrict__ sdev, double s, const int* __restrict__ done) {
+  if (done && *done) return;
+  const double sc = sdev ? *sdev : s;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const cx<VR> z = in[i];
+    out[i] = mk(VR(z.re * sc), VR(z.im * sc));
+  }
+}
+
+template <typename VR>
+__global__ void k_cscale(const cx<VR>* in, cx<VR>* out, size_t N, z64 c,
+                         const int* __restrict__ done) {
+  if (done && *done) return;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const cx<VR> z = in[i];
+    out[i] = mk(VR(c.re * double(z.re) - c.im * double(z.im)),
+                VR(c.re * double(z.im) + c.im * double(z.re)));
+  }
+}
+
+template <typename VR>
+__global__ void k_scale_step(cx<VR>* v, size_t N, const double* __restrict__ inv_h,
+                             const int* __restrict__ jdone, int j) {
+  if (*jdone != j + 1) return;
+  const double sc = *inv_h;
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const cx<VR> z = v[i];
+    v[i] = mk(VR(double(z.re) * sc), VR(double(z.im) * sc));
+  }
+}
+
+template <typename VR>
+__global__ void k_zero(cx<VR>* x, size_t N) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride)
+    x[i] = mk(VR(0), VR(0));
+}
+
+template <typename VR>
+__global__ void k_axpy(z64 a, const cx<VR>* __restrict__ x, cx<VR>* __restrict__ y, size_t N) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const cx<VR> xv = x[i];
+    cx<VR> yv = y[i];
+    yv.re = VR(double(yv.re) + a.re * double(xv.re) - a.im * double(xv.im));
+    yv.im = VR(double(yv.im) + a.re * double(xv.im) + a.im * double(xv.re));
+    y[i] = yv;
+  }
+}
+
+template <typename VR>
+__global__ void k_norm2(const cx<VR>* __restrict__ x, size_t N, Reducer red, double* result) {
+  double acc[1] = {0.0};
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const cx<VR> z = x[i];
+    acc[0] += double(z.re) * double(z.re) + double(z.im) * double(z.im);
+  }
+  grid_reduce<1>(acc, red, result);
+}
+
+template <typename VR>
+__global__ void k_gamma5(const cx<VR>* in, cx<VR>* out, size_t N, int n) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const int c = int(i % n);
+    const cx<VR> z = in[i];
+    out[i] = (c < (n >> 1)) ? z : mk(VR(-z.re), VR(-z.im));
+  }
+}
+
+__global__ void k_cvt64to32(const z64* __restrict__ in, z32* __restrict__ out, size_t N, int n,
+                            int g5) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const z64 z = in[i];
+    const double s = (g5 && int(i % n) >= (n >> 1)) ? -1.0 : 1.0;
+    out[i] = mk(float(s * z.re), float(s * z.im));
+  }
+}
+
+__global__ void k_cvt32to64(const z32* __restrict__ in, z64* __restrict__ out, size_t N, int n,
+                            int g5) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const z32 z = in[i];
+    const double s = (g5 && int(i % n) >= (n >> 1)) ? -1.0 : 1.0;
+    out[i] = mk(s * double(z.re), s * double(z.im));
+  }
+}
+
+// Philox4x32-10 (Salmon et al., SC'11) and Box-Muller, as in the input generator.
+__device__ void philox(uint32_t c[4], uint32_t k0, uint32_t k1) {
+  for (int r = 0; r < 10; ++r) {
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+    if (r < 9) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+  }
+}
+
+__global__ void k_gaussian(z64* out, size_t N, uint64_t seed, uint32_t stream_id) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    uint32_t c[4] = {uint32_t(i), uint32_t(uint64_t(i) >> 32), stream_id, 0u};
+    philox(c, uint32_t(seed), uint32_t(seed >> 32));
+    const double two53 = 9007199254740992.0;
+    const double u1 = (double(uint64_t(c[0] >> 5) * 67108864ull + (c[1] >> 6)) + 0.5) / two53;
+    const double u2 = (double(uint64_t(c[2] >> 5) * 67108864ull + (c[3] >> 6)) + 0.5) / two53;
+    const double r = sqrt(-2.0 * log(u1)) * 0.70710678118654752440;
+    double sn, cs;
+    sincos(6.283185307179586477 * u2, &sn, &cs);
+    out[i] = mk(r * cs, r * sn);
+  }
+}
+
+// ------------------------------------------------------------------ Arnoldi
+__global__ void k_arnoldi_init(ArnoldiDev a, double beta) {
+  if (threadIdx.x == 0) {
+    *a.done = 0;
+    *a.jdone = 0;
+    *a.brk_flag = 0;
+    *a.est = beta;
+    double* g = a.giv;
+    for (int i = 0; i < 2 * (a.ldh + 1); ++i) g[i] = 0.0;
+    g[0] = beta;
+  }
+}
+
+// Givens storage in a.giv: g[0..ldh] (complex), then c[0..ldh) (real, stored
+// in the even slots of complex entries), then s[0..ldh) (complex).
+__global__ void k_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const double* c1,
+                                 const double* c2, const double* nrm2, double target,
+                                 double brk) {
+  if (*a.done) return;
+  if (threadIdx.x != 0) return;
+  double* Hc = a.H + 2 * size_t(j) * a.ldh;
+  for (int i = 0; i < kC; ++i) {
+    a.Bk[2 * (size_t(j) * a.ldb + i)] = c1[2 * i] + c2[2 * i];
+    a.Bk[2 * (size_t(j) * a.ldb + i) + 1] = c1[2 * i + 1] + c2[2 * i + 1];
+  }
+  for (int i = 0; i <= j; ++i) {
+    Hc[2 * i] = c1[2 * (kC + i)] + c2[2 * (kC + i)];
+    Hc[2 * i + 1] = c1[2 * (kC + i) + 1] + c2[2 * (kC + i) + 1];
+  }
+  const double wn0 = sqrt(fmax(c1[2 * (kC + j + 1)], 0.0));  // ||A v_j|| before orthogonalisation
+  const double h = sqrt(fmax(*nrm2, 0.0));
+  const bool breakdown = !(h > brk * wn0);
+  Hc[2 * (j + 1)] = breakdown ? 0.0 : h;
+  Hc[2 * (j + 1) + 1] = 0.0;
+  *a.inv_h = breakdown ? 0.0 : 1.0 / h;
+  double* g = a.giv;
+  double* cs = a.giv + 2 * (a.ldh + 1);
+  double* sn = cs + 2 * a.ldh;
+  // carry the running entry through the previous rotations:
+  // [h_i; h_{i+1}] <- [[c_i, s_i], [-conj(s_i), c_i]] [h_i; h_{i+1}]
+  double xr = Hc[0], xi = Hc[1];
+  for (int i = 0; i < j; ++i) {
+    const double c = cs[2 * i], sr = sn[2 * i], si = sn[2 * i + 1];
+    const double yr = Hc[2 * (i + 1)], yi = Hc[2 * (i + 1) + 1];
+    const double nyr = -(sr * xr + si * xi) + c * yr;
+    const double nyi = -(sr * xi - si * xr) + c * yi;
+    xr = nyr;
+    xi = nyi;
+  }
+  const double hh = Hc[2 * (j + 1)];
+  const double ax = sqrt(xr * xr + xi * xi);
+  double c, sr, si;
+  if (hh == 0.0) {
+    c = 1.0;
+    sr = si = 0.0;
+  } else if (ax == 0.0) {
+    c = 0.0;
+    sr = 1.0;
+    si = 0.0;
+  } else {
+    const double r = sqrt(ax * ax + hh * hh);
+    c = ax / r;
+    sr = (xr / ax) * hh / r;  // s = (x/|x|) h / r
+    si = (xi / ax) * hh / r;
+  }
+  cs[2 * j] = c;
+  cs[2 * j + 1] = 0.0;
+  sn[2 * j] = sr;
+  sn[2 * j + 1] = si;
+  const double gr = g[2 * j], gi = g[2 * j + 1];
+  g[2 * j] = c * gr;
+  g[2 * j + 1] = c * gi;
+  g[2 * (j + 1)] = -(sr * gr + si * gi);  // -conj(s) g_j
+  g[2 * (j + 1) + 1] = -(sr * gi - si * gr);
+  const double est = sqrt(g[2 * (j + 1)] * g[2 * (j + 1)] + g[2 * (j + 1) + 1] * g[2 * (j + 1) + 1]);
+  *a.est = est;
+  *a.jdone = j + 1;
+  if (breakdown) *a.brk_flag = 1;
+  if (breakdown || est <= target || j + 1 >= steps) *a.done = 1;
+}
+
+// ------------------------------------------------------------------ gradient
+__global__ void k_grad_hops(const z64* __restrict__ lam, const z64* __restrict__ x,
+                            z64* __restrict__ grad, const int* __restrict__ nbr, int V, int n,
+                            int tied) {
+  const int site = blockIdx.x;
+  const int dir = blockIdx.y;  // 0..7 untied, 0..3 tied
+  const int y = nbr[dir * V + site];
+  const size_t nn = size_t(n) * n;
+  z64* out = grad + (size_t(site) * (tied ? 4 : 8) + dir) * nn;
+  for (size_t t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int i = int(t / n), j = int(t % n);
+    const z64 l = lam[size_t(site) * n + i];
+    const z64 xv = x[size_t(y) * n + j];
+    // -lambda_x,i * conj(x_y,j)
+    double gr = -(l.re * xv.re + l.im * xv.im);
+    double gi = -(l.im * xv.re - l.re * xv.im);
+    if (tied) {
+      // - g5_i x_x,i conj(lambda_y,j) g5_j
+      const z64 xx = x[size_t(site) * n + i];
+      const z64 ly = lam[size_t(y) * n + j];
+      const double s = gam(i, n) * gam(j, n);
+      gr -= s * (xx.re * ly.re + xx.im * ly.im);
+      gi -= s * (xx.im * ly.re - xx.re * ly.im);
+    }
+    out[t] = mk(gr, gi);
+  }
+}
+
+inline unsigned grid_for(size_t N, int threads, unsigned cap = 4096) {
+  size_t b = (N + threads - 1) / threads;
+  if (b < 1) b = 1;
+  if (b > cap) b = cap;
+  return unsigned(b);
+}
+
+}  // namespace
+
+// ====================================================================== launchers
+
+void launch_layout_blocks(const z64* self_in, const z64* hops_in, int V, int n, void* out64,
+                          void* out32, void* out16, float* scales16, hipStream_t st) {
+  hipLaunchKernelGGL(k_layout, dim3(unsigned(V) * 5u), dim3(256), 0, st, self_in, hops_in, V, n,
+                     static_cast<z64*>(out64), static_cast<z32*>(out32),
+                     static_cast<uint32_t*>(out16), scales16);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_neighbours(int* nbr, int L0, int L1, int L2, int L3, hipStream_t st) {
+  const int V = L0 * L1 * L2 * L3;
+  hipLaunchKernelGGL(k_neighbours, dim3((V + 255) / 256), dim3(256), 0, st, nbr, L0, L1, L2, L3);
+  DC_HIP(hipGetLastError());
+}
+
+template <int P>
+static void apply_T(int n, int V, const void* blocks, const float* scales, const void* in,
+                    void* gbuf, const int* nbr, double tm, const int* done, hipStream_t st) {
+  using VR = typename VecOf<P>::R;
+  const int chunk = (V + 7) / 8;
+  const dim3 grid(unsigned(chunk) * 8u), block(320);
+  const auto* pin = static_cast<const cx<VR>*>(in);
+  auto* pg = static_cast<cx<VR>*>(gbuf);
+  switch (tile_T(n)) {
+#define DC_CASE(TV)                                                                      \
+  case TV:                                                                               \
+    hipLaunchKernelGGL((k_apply_blocks<TV, P>), grid, block, 0, st, blocks, scales, pin, \
+                       pg, nbr, V, n, chunk, tm, done);                                  \
+    break;
+    DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
+#undef DC_CASE
+    default:
+      throw InvalidArg("block size n > 64 is not supported");
+  }
+  DC_HIP(hipGetLastError());
+}
+
+void launch_apply_blocks(Prec p, int n, int V, const void* blocks, const float* scales,
+                         const void* in, void* gbuf, const int* nbr, double tm, const int* done,
+                         hipStream_t st) {
+  if (p == P64) apply_T<P64>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
+  else if (p == P32) apply_T<P32>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
+  else apply_T<P16S>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
+}
+
+void launch_gather_store(Prec p, int n, int V, const void* gbuf, void* out, const int* done,
+                         hipStream_t st) {
+  const size_t N = size_t(V) * n;
+  const dim3 grid(unsigned((N + 255) / 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_gather_store<double>, grid, block, 0, st,
+                       static_cast<const z64*>(gbuf), static_cast<z64*>(out), N, n, done);
+  else
+    hipLaunchKernelGGL(k_gather_store<float>, grid, block, 0, st,
+                       static_cast<const z32*>(gbuf), static_cast<z32*>(out), N, n, done);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_gather_poly(Prec p, int n, int V, const void* gbuf, void* prod, void* y, z64 ca,
+                        z64 cb, const int* done, hipStream_t st) {
+  const size_t N = size_t(V) * n;
+  const dim3 grid(unsigned((N + 255) / 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_gather_poly<double>, grid, block, 0, st, static_cast<const z64*>(gbuf),
+                       static_cast<z64*>(prod), static_cast<z64*>(y), N, n, ca, cb, done);
+  else
+    hipLaunchKernelGGL(k_gather_poly<float>, grid, block, 0, st, static_cast<const z32*>(gbuf),
+                       static_cast<z32*>(prod), static_cast<z32*>(y), N, n, ca, cb, done);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_gather_poly_first(Prec p, int n, int V, const void* gbuf, const void* v, void* prod,
+                              void* y, z64 c0, z64 ca, z64 cb, const int* done, hipStream_t st) {
+  const size_t N = size_t(V) * n;
+  const dim3 grid(unsigned((N + 255) / 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_gather_poly_first<double>, grid, block, 0, st,
+                       static_cast<const z64*>(gbuf), static_cast<const z64*>(v),
+                       static_cast<z64*>(prod), static_cast<z64*>(y), N, n, c0, ca, cb, done);
+  else
+    hipLaunchKernelGGL(k_gather_poly_first<float>, grid, block, 0, st,
+                       static_cast<const z32*>(gbuf), static_cast<const z32*>(v),
+                       static_cast<z32*>(prod), static_cast<z32*>(y), N, n, c0, ca, cb, done);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_gather_resid(Prec p, int n, int V, const void* gbuf, const void* b, void* out,
+                         Reducer red, double* result, hipStream_t st) {
+  const size_t N = size_t(V) * n;
+  const dim3 grid(grid_for(N, 256, kMaxRedBlocks)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_gather_resid<double>, grid, block, 0, st, static_cast<const z64*>(gbuf),
+                       static_cast<const z64*>(b), static_cast<z64*>(out), N, n, red, result);
+  else
+    hipLaunchKernelGGL(k_gather_resid<float>, grid, block, 0, st, static_cast<const z32*>(gbuf),
+                       static_cast<const z32*>(b), static_cast<z32*>(out), N, n, red, result);
+  DC_HIP(hipGetLastError());
+}
+
+static unsigned dot_blocks(size_t N, int groups) {
+  // aim for ~4 waves of 256 threads per CU over all groups, each thread >= 4 elements
+  size_t want = 1024 / size_t(groups > 0 ? groups : 1);
+  if (want < 16) want = 16;
+  size_t bymem = (N + 1023) / 1024;
+  size_t b = want < bymem ? want : bymem;
+  if (b < 1) b = 1;
+  if (b * size_t(groups) > size_t(kMaxRedBlocks)) b = size_t(kMaxRedBlocks) / size_t(groups);
+  return unsigned(b);
+}
+
+void launch_multidot(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
+                     const void* w, int want_norm, Reducer red, double* result, const int* done,
+                     hipStream_t st) {
+  const int Q = q0 + q1 + (want_norm ? 1 : 0);
+  if (Q == 0) return;
+  const int gy = (Q + kQG - 1) / kQG;
+  const dim3 grid(dot_blocks(N, gy), unsigned(gy)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_multidot<double>, grid, block, 0, st, static_cast<const z64*>(b0), q0,
+                       static_cast<const z64*>(b1), q1, N, static_cast<const z64*>(w), want_norm,
+                       red, result, done);
+  else
+    hipLaunchKernelGGL(k_multidot<float>, grid, block, 0, st, static_cast<const z32*>(b0), q0,
+                       static_cast<const z32*>(b1), q1, N, static_cast<const z32*>(w), want_norm,
+                       red, result, done);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, int q1, size_t N,
+                      const double* coef, int want_norm, Reducer red, double* result,
+                      const int* done, hipStream_t st) {
+  const dim3 grid(grid_for(N, 256, kMaxRedBlocks)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_multiaxpy<double>, grid, block, 0, st, static_cast<z64*>(w),
+                       static_cast<const z64*>(b0), q0, static_cast<const z64*>(b1), q1, N, coef,
+                       want_norm, red, result, done);
+  else
+    hipLaunchKernelGGL(k_multiaxpy<float>, grid, block, 0, st, static_cast<z32*>(w),
+                       static_cast<const z32*>(b0), q0, static_cast<const z32*>(b1), q1, N, coef,
+                       want_norm, red, result, done);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
+                    const double* coef, int R, void* out, int accumulate, hipStream_t st) {
+  if (R <= 0) return;
+  const int gy = (R + kCombR - 1) / kCombR;
+  const dim3 grid(grid_for(N, 256, 2048), unsigned(gy)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_combine<double>, grid, block, 0, st, static_cast<const z64*>(b0), q0,
+                       static_cast<const z64*>(b1), q1, N, coef, R, static_cast<z64*>(out),
+                       accumulate);
+  else
+    hipLaunchKernelGGL(k_combine<float>, grid, block, 0, st, static_cast<const z32*>(b0), q0,
+                       static_cast<const z32*>(b1), q1, N, coef, R, static_cast<z32*>(out),
+                       accumulate);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_scale(Prec p, const void* in, void* out, size_t N, const double* scale_dev, double s,
+                  const int* done, hipStream_t st) {
+  const dim3 grid(grid_for(N, 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_scale<double>, grid, block, 0, st, static_cast<const z64*>(in),
+                       static_cast<z64*>(out), N, scale_dev, s, done);
+  else
+    hipLaunchKernelGGL(k_scale<float>, grid, block, 0, st, static_cast<const z32*>(in),
+                       static_cast<z32*>(out), N, scale_dev, s, done);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_cscale(Prec p, const void* in, void* out, size_t N, z64 c, const int* done,
+                   hipStream_t st) {
+  const dim3 grid(grid_for(N, 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_cscale<double>, grid, block, 0, st, static_cast<const z64*>(in),
+                       static_cast<z64*>(out), N, c, done);
+  else
+    hipLaunchKernelGGL(k_cscale<float>, grid, block, 0, st, static_cast<const z32*>(in),
+                       static_cast<z32*>(out), N, c, done);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_scale_step(Prec p, void* v, size_t N, const double* inv_h, const int* jdone, int j,
+                       hipStream_t st) {
+  const dim3 grid(grid_for(N, 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_scale_step<double>, grid, block, 0, st, static_cast<z64*>(v), N, inv_h,
+                       jdone, j);
+  else
+    hipLaunchKernelGGL(k_scale_step<float>, grid, block, 0, st, static_cast<z32*>(v), N, inv_h,
+                       jdone, j);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_zero(Prec p, void* x, size_t N, hipStream_t st) {
+  const dim3 grid(grid_for(N, 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_zero<double>, grid, block, 0, st, static_cast<z64*>(x), N);
+  else
+    hipLaunchKernelGGL(k_zero<float>, grid, block, 0, st, static_cast<z32*>(x), N);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_axpy(Prec p, z64 a, const void* x, void* y, size_t N, hipStream_t st) {
+  const dim3 grid(grid_for(N, 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_axpy<double>, grid, block, 0, st, a, static_cast<const z64*>(x),
+                       static_cast<z64*>(y), N);
+  else
+    hipLaunchKernelGGL(k_axpy<float>, grid, block, 0, st, a, static_cast<const z32*>(x),
+                       static_cast<z32*>(y), N);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_norm2(Prec p, const void* x, size_t N, Reducer red, double* result, hipStream_t st) {
+  const dim3 grid(grid_for(N, 256, kMaxRedBlocks)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_norm2<double>, grid, block, 0, st, static_cast<const z64*>(x), N, red,
+                       result);
+  else
+    hipLaunchKernelGGL(k_norm2<float>, grid, block, 0, st, static_cast<const z32*>(x), N, red,
+                       result);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_gamma5(Prec p, const void* in, void* out, int V, int n, hipStream_t st) {
+  const size_t N = size_t(V) * n;
+  const dim3 grid(grid_for(N, 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_gamma5<double>, grid, block, 0, st, static_cast<const z64*>(in),
+                       static_cast<z64*>(out), N, n);
+  else
+    hipLaunchKernelGGL(k_gamma5<float>, grid, block, 0, st, static_cast<const z32*>(in),
+                       static_cast<z32*>(out), N, n);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_convert_64to32(const z64* in, z32* out, size_t N, int n, int g5, hipStream_t st) {
+  hipLaunchKernelGGL(k_cvt64to32, dim3(grid_for(N, 256)), dim3(256), 0, st, in, out, N, n, g5);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_convert_32to64(const z32* in, z64* out, size_t N, int n, int g5, hipStream_t st) {
+  hipLaunchKernelGGL(k_cvt32to64, dim3(grid_for(N, 256)), dim3(256), 0, st, in, out, N, n, g5);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_gaussian(z64* out, size_t N, uint64_t seed, uint32_t stream_id, hipStream_t st) {
+  hipLaunchKernelGGL(k_gaussian, dim3(grid_for(N, 256)), dim3(256), 0, st, out, N, seed,
+                     stream_id);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const double* c1,
+                           const double* c2, const double* nrm2, double target, double brk,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_arnoldi_finish, dim3(1), dim3(64), 0, st, a, steps, kC, j, c1, c2, nrm2,
+                     target, brk);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_arnoldi_init(ArnoldiDev a, double beta, hipStream_t st) {
+  hipLaunchKernelGGL(k_arnoldi_init, dim3(1), dim3(64), 0, st, a, beta);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_grad_hops(const z64* lam, const z64* x, z64* grad, const int* nbr, int V, int n,
+                      int tied, hipStream_t st) {
+  hipLaunchKernelGGL(k_grad_hops, dim3(unsigned(V), tied ? 4u : 8u), dim3(256), 0, st, lam, x,
+                     grad, nbr, V, n, tied);
+  DC_HIP(hipGetLastError());
+}
+
+}  // namespace dc

@@ -1,0 +1,115 @@
+// Launchers of the HIP kernels (implemented in kernels.hip).  All launchers
+// enqueue on `st` and return immediately; `done` (may be null) is a device flag
+// that makes every kernel of a pending Arnoldi cycle exit at entry once set.
+#pragma once
+
+#include "common.hpp"
+
+namespace dc {
+
+// Deterministic grid reduction scratch: per-block partial sums plus a counter
+// that the last block to finish uses to sum the partials in block order.
+struct Reducer {
+  double* partials = nullptr;   // capacity: kMaxRedBlocks * kRedWidth doubles
+  unsigned* counter = nullptr;  // zero between launches
+};
+constexpr int kMaxRedBlocks = 1024;
+constexpr int kRedWidth = 32;  // doubles per block (16 complex dots)
+
+// ---------------------------------------------------------------- operator
+// Re-lay out FP64 input blocks (self [V][n][n] + hops [V][4][n][n], device,
+// row-major) into the tiled per-lane layout of each requested precision.
+void launch_layout_blocks(const z64* self_in, const z64* hops_in, int V, int n,
+                          void* out64, void* out32, void* out16, float* scales16,
+                          hipStream_t st);
+
+// Neighbour table int32 [8][V]: rows 0..3 = x + mu, rows 4..7 = x - mu.
+void launch_neighbours(int* nbr, int L0, int L1, int L2, int L3, hipStream_t st);
+
+// Apply, stage 1: per site, read the 5 stored blocks once; write the site's own
+// sum (self + forward hops + i*tm*Gamma5 psi) into slot 4 of gbuf[x] and the
+// backward-hop contribution Gamma5 B[x,mu]^H Gamma5 psi_x into slot mu of
+// gbuf[x+mu].  gbuf: [V][5][n] in the vector precision.
+void launch_apply_blocks(Prec p, int n, int V, const void* blocks, const float* scales,
+                         const void* in, void* gbuf, const int* nbr, double tm,
+                         const int* done, hipStream_t st);
+
+// Apply, stage 2 (sum of the 5 slots) with an epilogue.
+//   store : out = s
+//   poly  : prod = prod - ca*s;  y = y + cb*prod         (polynomial chain step)
+//   resid : out = b - s; result[0] = ||out||^2           (true residual)
+void launch_gather_store(Prec p, int n, int V, const void* gbuf, void* out,
+                         const int* done, hipStream_t st);
+void launch_gather_poly(Prec p, int n, int V, const void* gbuf, void* prod, void* y,
+                        z64 ca, z64 cb, const int* done, hipStream_t st);
+//   poly_first : s = A v;  prod = v - ca*s;  y = c0*v + cb*prod  (first chain step)
+void launch_gather_poly_first(Prec p, int n, int V, const void* gbuf, const void* v, void* prod,
+                              void* y, z64 c0, z64 ca, z64 cb, const int* done, hipStream_t st);
+void launch_gather_resid(Prec p, int n, int V, const void* gbuf, const void* b, void* out,
+                         Reducer red, double* result, hipStream_t st);
+
+// ---------------------------------------------------------------- BLAS-1/2
+// result[q] = basis_q^H w (complex, q < q0 + q1; basis_q = b0 + q*N for q < q0,
+// b1 + (q-q0)*N after), and if want_norm result[q0+q1] = ||w||^2 (real part).
+void launch_multidot(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
+                     const void* w, int want_norm, Reducer red, double* result,
+                     const int* done, hipStream_t st);
+// w -= sum_q coef[q] basis_q (coef device complex [q0+q1]); if want_norm,
+// result[0] = ||w||^2 after the update.
+void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, int q1,
+                      size_t N, const double* coef, int want_norm, Reducer red,
+                      double* result, const int* done, hipStream_t st);
+// out_r (= or +=) sum_q coef[r*Q + q] basis_q for r < R, Q = q0 + q1; coef
+// device complex; outputs are R vectors with stride N.
+void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
+                    const double* coef, int R, void* out, int accumulate, hipStream_t st);
+// out = in * (*scale_dev) (scale real, device) or in * s (if scale_dev null).
+void launch_scale(Prec p, const void* in, void* out, size_t N, const double* scale_dev,
+                  double s, const int* done, hipStream_t st);
+// out = c * in (complex c); in == out allowed
+void launch_cscale(Prec p, const void* in, void* out, size_t N, z64 c, const int* done,
+                   hipStream_t st);
+// v *= *inv_h if *jdone == j + 1 (normalise the new Arnoldi vector of step j)
+void launch_scale_step(Prec p, void* v, size_t N, const double* inv_h, const int* jdone, int j,
+                       hipStream_t st);
+// x = 0
+void launch_zero(Prec p, void* x, size_t N, hipStream_t st);
+// y = a*x + y (complex a)
+void launch_axpy(Prec p, z64 a, const void* x, void* y, size_t N, hipStream_t st);
+// result[0] = ||x||^2
+void launch_norm2(Prec p, const void* x, size_t N, Reducer red, double* result, hipStream_t st);
+// out = Gamma5 in (per-site sign); in == out allowed
+void launch_gamma5(Prec p, const void* in, void* out, int V, int n, hipStream_t st);
+// precision conversions (with optional Gamma5): out = g5? * in
+void launch_convert_64to32(const z64* in, z32* out, size_t N, int n, int g5, hipStream_t st);
+void launch_convert_32to64(const z32* in, z64* out, size_t N, int n, int g5, hipStream_t st);
+// standard complex Gaussians from Philox4x32-10 (counter = (index, stream, 0))
+void launch_gaussian(z64* out, size_t N, uint64_t seed, uint32_t stream_id, hipStream_t st);
+
+// ---------------------------------------------------------------- Arnoldi
+// One-wave bookkeeping kernel after the two Gram-Schmidt passes of step j:
+// H(:, j) = c1 + c2 (the V part), Bk(:, j) = (C part), h_{j+1,j} = sqrt(nrm2),
+// Givens update of the residual estimate, done flag on convergence
+// (estimate <= target) or breakdown (h_{j+1,j} <= brk * ||A v_j||).
+struct ArnoldiDev {
+  int ldh = 0;      // leading dimension of H (>= steps + 1)
+  int ldb = 1;      // leading dimension of Bk (>= kC, >= 1)
+  double* H;        // complex ldh x steps column-major
+  double* Bk;       // complex ldb x steps column-major
+  double* giv;      // complex g[ldh+1], c[ldh] (real parts used), s[ldh]
+  double* inv_h;    // 1 / h_{j+1,j}
+  double* est;      // |g[j+1]|
+  int* done;        // cycle flag
+  int* jdone;       // steps completed
+  int* brk_flag;    // 1 if the cycle ended by breakdown
+};
+void launch_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const double* c1,
+                           const double* c2, const double* nrm2, double target, double brk,
+                           hipStream_t st);
+void launch_arnoldi_init(ArnoldiDev a, double beta, hipStream_t st);
+
+// ---------------------------------------------------------------- gradient
+void launch_grad_hops(const z64* lam, const z64* x, z64* grad, const int* nbr, int V, int n,
+                      int tied, hipStream_t st);
+
+}  // namespace dc

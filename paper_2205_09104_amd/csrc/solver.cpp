@@ -1,0 +1,864 @@
+// Coarse-operator handle and Krylov solvers: restarted GMRES (Sec. 3.1),
+// GMRES-polynomial right preconditioning (Sec. 3.3), GCRO-DR deflated restarts
+// with recycling (Sec. 3.4, algorithm of Parks et al. 2006), lazy rebuild after
+// a matrix change (Sec. 3.6), and an FP64 flexible-GMRES outer loop around a
+// reduced-precision inner solve.  Every vector operation runs in the HIP
+// kernels of kernels.hip; the host keeps only the small dense problems
+// (Hessenberg least squares, harmonic Ritz values and vectors, QR of k x k
+// systems), done redundantly as the paper does per process.
+#include "solver.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+namespace dc {
+
+void DevBuf::alloc(size_t b) {
+  release();
+  if (b == 0) return;
+  const hipError_t e = hipMalloc(&p, b);
+  if (e != hipSuccess) {
+    p = nullptr;
+    (void)hipGetLastError();
+    throw NoMem("hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
+  }
+  bytes = b;
+}
+
+void DevBuf::release() {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+  bytes = 0;
+}
+
+static size_t block_units(int n, Prec p) {
+  const int epl = (p == P64) ? 1 : (p == P32 ? 2 : 4);
+  return size_t(tile_elems(n, epl) / epl) * 64;  // 16-byte units per block
+}
+
+const void* Op::blocks(Prec p) const {
+  if (p == P64) return blk64.p;
+  if (p == P32) return blk32.p;
+  return blk16.p;
+}
+
+Variant& Op::variant(Prec p, int sign, int bj, int d) {
+  auto key = std::make_tuple(int(p), sign, bj, d);
+  auto it = variants.find(key);
+  if (it != variants.end()) return *it->second;
+  auto v = std::make_unique<Variant>();
+  v->prec = p;
+  v->sign = sign;
+  v->bj = bj;
+  v->d = d;
+  Variant& ref = *v;
+  variants.emplace(key, std::move(v));
+  return ref;
+}
+
+static void copy_blocks_in(Op& op, const void* self_blocks, const void* hop_blocks, bool on_device,
+                           hipStream_t st) {
+  const size_t nn = size_t(op.n) * op.n;
+  const z64* dself = static_cast<const z64*>(self_blocks);
+  const z64* dhops = static_cast<const z64*>(hop_blocks);
+  DevBuf stage;
+  if (!on_device) {
+    stage.alloc(size_t(op.V) * 5 * nn * sizeof(z64));
+    z64* s = stage.as<z64>();
+    DC_HIP(hipMemcpyAsync(s, self_blocks, size_t(op.V) * nn * sizeof(z64), hipMemcpyHostToDevice, st));
+    DC_HIP(hipMemcpyAsync(s + size_t(op.V) * nn, hop_blocks, size_t(op.V) * 4 * nn * sizeof(z64),
+                          hipMemcpyHostToDevice, st));
+    dself = s;
+    dhops = s + size_t(op.V) * nn;
+  }
+  launch_layout_blocks(dself, dhops, op.V, op.n, op.blk64.p, op.blk32.p, op.blk16.p,
+                       op.sc16.as<float>(), st);
+  DC_HIP(hipStreamSynchronize(st));
+}
+
+void op_build(Op& op, const int dims[4], int n_tv, int store, double mu, const void* self_blocks,
+              const void* hop_blocks, bool on_device, hipStream_t st) {
+  for (int i = 0; i < 4; ++i) {
+    if (dims[i] < 1) throw InvalidArg("lattice extents must be >= 1");
+    op.dims[i] = dims[i];
+  }
+  if (n_tv < 1 || n_tv > 32) throw InvalidArg("n_tv must be in 1..32");
+  if (!self_blocks || !hop_blocks) throw InvalidArg("null block pointer");
+  if (!std::isfinite(mu)) throw InvalidArg("mu must be finite");
+  const long long V = 1LL * dims[0] * dims[1] * dims[2] * dims[3];
+  if (V > (1LL << 30)) throw InvalidArg("lattice too large");
+  op.V = int(V);
+  op.n = 2 * n_tv;
+  op.store = store | 1;
+  op.mu = mu;
+  op.stream = st;
+  op.nbr.alloc(size_t(8) * op.V * sizeof(int));
+  launch_neighbours(op.nbr.as<int>(), dims[0], dims[1], dims[2], dims[3], st);
+  const size_t nb = size_t(op.V) * 5;
+  op.blk64.alloc(nb * block_units(op.n, P64) * 16);
+  if (op.store & 2) op.blk32.alloc(nb * block_units(op.n, P32) * 16);
+  if (op.store & 4) {
+    op.blk16.alloc(nb * block_units(op.n, P16S) * 16);
+    op.sc16.alloc(nb * sizeof(float));
+  }
+  op.gbuf64.alloc(size_t(op.V) * 5 * op.n * sizeof(z64));
+  if (op.store & 6) op.gbuf32.alloc(size_t(op.V) * 5 * op.n * sizeof(z32));
+  op.redpart.alloc(size_t(kMaxRedBlocks) * kRedWidth * sizeof(double));
+  op.redcnt.alloc(256);
+  DC_HIP(hipMemsetAsync(op.redcnt.p, 0, 256, st));
+  op.scal.alloc(256);
+  copy_blocks_in(op, self_blocks, hop_blocks, on_device, st);
+}
+
+void op_update(Op& op, const void* self_blocks, const void* hop_blocks, bool on_device,
+               hipStream_t st) {
+  if (!self_blocks || !hop_blocks) throw InvalidArg("null block pointer");
+  copy_blocks_in(op, self_blocks, hop_blocks, on_device, st);
+  op.version += 1;  // block Jacobi, polynomial and recycle space become stale
+}
+
+static void check_prec(const Op& op, Prec p) {
+  if (p == P32 && !(op.store & 2)) throw InvalidArg("FP32 blocks were not stored (desc.store)");
+  if (p == P16S && !(op.store & 4)) throw InvalidArg("FP16 blocks were not stored (desc.store)");
+  if (p != P64 && p != P32 && p != P16S) throw InvalidArg("unknown precision");
+}
+
+static size_t vec_bytes(Prec p) { return p == P64 ? sizeof(z64) : sizeof(z32); }
+
+void op_apply(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_t st) {
+  check_prec(op, p);
+  if (!in || !out) throw InvalidArg("null vector pointer");
+  if (in == out) throw InvalidArg("in and out must not overlap");
+  if (!adjoint) {
+    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
+                        op.mu, nullptr, st);
+    launch_gather_store(p, op.n, op.V, op.gbuf(p), out, nullptr, st);
+  } else {
+    // D(mu)^H = Gamma5 D(-mu) Gamma5
+    launch_gamma5(p, in, out, op.V, op.n, st);
+    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), out, op.gbuf(p),
+                        op.nbr.as<int>(), -op.mu, nullptr, st);
+    launch_gather_store(p, op.n, op.V, op.gbuf(p), out, nullptr, st);
+    launch_gamma5(p, out, out, op.V, op.n, st);
+  }
+}
+
+void op_apply_bj(Op&, const void*, void*, hipStream_t) {
+  throw InvalidArg("block-Jacobi preconditioning is not available in this build");
+}
+
+// ============================================================================ Krylov
+
+namespace {
+
+template <typename VR>
+struct Krylov {
+  using Z = cx<VR>;
+  Op& op;
+  Variant& var;
+  const SolveOpts& o;
+  Prec p;
+  double tm;  // twisted mass used in the apply (sign * mu)
+  hipStream_t st;
+  size_t N;
+  int ldh = 0, kmax = 0, nbasis = 0;
+  // device workspace (owned by the variant so it persists across calls)
+  DevBuf& ws;
+  DevBuf& sm;
+  Z *Vb = nullptr, *Ctmp = nullptr, *Utmp = nullptr, *prod = nullptr, *ybuf = nullptr,
+    *tmp = nullptr, *tmp2 = nullptr, *rhat = nullptr, *rtrue = nullptr;
+  double *res1 = nullptr, *res2 = nullptr, *nrm = nullptr, *coef = nullptr, *scal = nullptr;
+  ArnoldiDev ad{};
+  long matvecs = 0;
+  double brk;
+
+  Krylov(Op& op_, Variant& v, const SolveOpts& o_, DevBuf& ws_, DevBuf& sm_, int steps_max,
+         hipStream_t st_)
+      : op(op_), var(v), o(o_), p(v.prec), tm(v.sign * op_.mu), st(st_), N(op_.N()), ws(ws_),
+        sm(sm_) {
+    brk = (p == P64) ? 1e-14 : 1e-6;
+    kmax = std::max(o.k, 0);
+    ldh = std::max(steps_max, std::max(o.d, 1)) + 2;
+    nbasis = ldh + 1;
+    const size_t vb = N * sizeof(Z);
+    const size_t nvec = size_t(nbasis) + 2 * size_t(kmax) + 6;
+    ws.ensure(nvec * vb);
+    Z* base = ws.as<Z>();
+    Vb = base;
+    Ctmp = Vb + size_t(nbasis) * N;
+    Utmp = Ctmp + size_t(kmax) * N;
+    prod = Utmp + size_t(kmax) * N;
+    ybuf = prod + N;
+    tmp = ybuf + N;
+    tmp2 = tmp + N;
+    rhat = tmp2 + N;
+    rtrue = rhat + N;
+    // small area (doubles)
+    const size_t q = size_t(kmax + ldh + 4);
+    const size_t nd = 2 * q * 2 + 8 + 2 * size_t(std::max(kmax + ldh + 2, 1)) * std::max(kmax, 2) +
+                      2 * size_t(ldh) * ldh + 2 * size_t(std::max(kmax, 1)) * ldh +
+                      2 * 3 * size_t(ldh + 1) + 64;
+    sm.ensure(nd * sizeof(double) + 64 * sizeof(int));
+    double* d = sm.as<double>();
+    res1 = d;
+    res2 = res1 + 2 * q;
+    nrm = res2 + 2 * q;
+    scal = nrm + 4;  // inv_h, est
+    coef = scal + 4;
+    double* after_coef = coef + 2 * size_t(std::max(kmax + ldh + 2, 1)) * std::max(kmax, 2);
+    ad.ldh = ldh;
+    ad.ldb = std::max(kmax, 1);
+    ad.H = after_coef;
+    ad.Bk = ad.H + 2 * size_t(ldh) * ldh;
+    ad.giv = ad.Bk + 2 * size_t(ad.ldb) * ldh;
+    double* end = ad.giv + 2 * 3 * size_t(ldh + 1);
+    ad.inv_h = scal;
+    ad.est = scal + 1;
+    int* ip = reinterpret_cast<int*>(end + 8);
+    ad.done = ip;
+    ad.jdone = ip + 1;
+    ad.brk_flag = ip + 2;
+  }
+
+  Z* V(int j) const { return Vb + size_t(j) * N; }
+  Z* Uv() const { return var.U.as<Z>(); }
+  Z* Cv() const { return var.C.as<Z>(); }
+
+  // A~ in = D in (one matvec)
+  void A(const Z* in, Z* out, const int* done) {
+    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
+                        tm, done, st);
+    launch_gather_store(p, op.n, op.V, op.gbuf(p), out, done, st);
+    ++matvecs;
+  }
+
+  bool has_poly() const { return var.d > 1 && int(var.theta.size()) > 1; }
+
+  // out = q(A~) in  (Newton-like form, d-1 matvecs); out must differ from in
+  void Q(const Z* in, Z* out, const int* done) {
+    const auto& th = var.theta;
+    const int d = int(th.size());
+    auto inv = [](cd t) { const cd r = 1.0 / t; return mk(r.real(), r.imag()); };
+    if (d <= 1) {
+      const z64 c = (d == 1) ? inv(th[0]) : mk(1.0, 0.0);
+      launch_cscale(p, in, out, N, c, done, st);
+      return;
+    }
+    // i = 1: prod = v - A v / theta_0;  y = v / theta_0 + prod / theta_1
+    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
+                        tm, done, st);
+    launch_gather_poly_first(p, op.n, op.V, op.gbuf(p), in, prod, out, inv(th[0]), inv(th[0]),
+                             inv(th[1]), done, st);
+    ++matvecs;
+    for (int i = 2; i < d; ++i) {
+      launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), prod, op.gbuf(p),
+                          op.nbr.as<int>(), tm, done, st);
+      launch_gather_poly(p, op.n, op.V, op.gbuf(p), prod, out, inv(th[i - 1]), inv(th[i]), done, st);
+      ++matvecs;
+    }
+  }
+
+  // out = A~ q(A~) in
+  void Ahat(const Z* in, Z* out, const int* done) {
+    if (!has_poly()) {
+      A(in, out, done);
+      return;
+    }
+    Q(in, ybuf, done);
+    A(ybuf, out, done);
+  }
+
+  // r = b - D x (true residual in the variant's precision); returns ||r||
+  double true_resid(const Z* x, const Z* b, Z* r) {
+    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), x, op.gbuf(p), op.nbr.as<int>(),
+                        tm, nullptr, st);
+    launch_gather_resid(p, op.n, op.V, op.gbuf(p), b, r, op.red(), nrm, st);
+    ++matvecs;
+    double h;
+    DC_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+    DC_HIP(hipStreamSynchronize(st));
+    return std::sqrt(std::max(h, 0.0));
+  }
+
+  double norm(const Z* x) {
+    launch_norm2(p, x, N, op.red(), nrm, st);
+    double h;
+    DC_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+    DC_HIP(hipStreamSynchronize(st));
+    return std::sqrt(std::max(h, 0.0));
+  }
+
+  // Gram-Schmidt of V(j+1) against [C, V(0..j)] (classical, applied twice),
+  // then the bookkeeping kernel and normalisation.
+  void orth_step(int j, int kC, int steps, double target) {
+    Z* w = V(j + 1);
+    const Z* Cb = kC ? Cv() : nullptr;
+    launch_multidot(p, Cb, kC, V(0), j + 1, N, w, 1, op.red(), res1, ad.done, st);
+    launch_multiaxpy(p, w, Cb, kC, V(0), j + 1, N, res1, 0, op.red(), nrm, ad.done, st);
+    launch_multidot(p, Cb, kC, V(0), j + 1, N, w, 0, op.red(), res2, ad.done, st);
+    launch_multiaxpy(p, w, Cb, kC, V(0), j + 1, N, res2, 1, op.red(), nrm, ad.done, st);
+    launch_arnoldi_finish(ad, steps, kC, j, res1, res2, nrm, target, brk, st);
+    launch_scale_step(p, w, N, ad.inv_h, ad.jdone, j, st);
+  }
+
+  struct CycleOut {
+    int jd = 0;
+    bool breakdown = false;
+    double est = 0;
+    Mat H;   // (jd+1) x jd
+    Mat Bk;  // kC x jd
+  };
+
+  // One Arnoldi cycle of up to `steps` steps of A^ from rv (norm beta), with
+  // deflation against the first kC columns of C.  The device stops the cycle
+  // when the least-squares residual estimate reaches `target` (not before
+  // min_steps steps) or on breakdown.
+  CycleOut cycle(const Z* rv, double beta, int steps, int kC, double target, int min_steps) {
+    launch_scale(p, rv, V(0), N, nullptr, 1.0 / beta, nullptr, st);
+    launch_arnoldi_init(ad, beta, st);
+    for (int j = 0; j < steps; ++j) {
+      Ahat(V(j), V(j + 1), ad.done);
+      orth_step(j, kC, steps, (j + 1 < min_steps) ? -1.0 : target);
+    }
+    CycleOut c;
+    int flags[3];
+    DC_HIP(hipMemcpyAsync(flags, ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    double est;
+    DC_HIP(hipMemcpyAsync(&est, ad.est, sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> Hh(2 * size_t(ldh) * ldh);
+    DC_HIP(hipMemcpyAsync(Hh.data(), ad.H, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    std::vector<double> Bh(2 * size_t(ad.ldb) * ldh);
+    if (kC) DC_HIP(hipMemcpyAsync(Bh.data(), ad.Bk, Bh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    DC_HIP(hipStreamSynchronize(st));
+    c.jd = flags[1];
+    c.breakdown = flags[2] != 0;
+    c.est = est;
+    c.H = Mat(c.jd + 1, c.jd);
+    for (int jj = 0; jj < c.jd; ++jj)
+      for (int i = 0; i <= jj + 1; ++i)
+        c.H(i, jj) = cd(Hh[2 * (size_t(jj) * ldh + i)], Hh[2 * (size_t(jj) * ldh + i) + 1]);
+    c.Bk = Mat(kC, c.jd);
+    for (int jj = 0; jj < c.jd; ++jj)
+      for (int i = 0; i < kC; ++i)
+        c.Bk(i, jj) = cd(Bh[2 * (size_t(jj) * ad.ldb + i)], Bh[2 * (size_t(jj) * ad.ldb + i) + 1]);
+    return c;
+  }
+
+  void upload_coef(const std::vector<cd>& c) {
+    std::vector<double> h(2 * c.size());
+    for (size_t i = 0; i < c.size(); ++i) {
+      h[2 * i] = c[i].real();
+      h[2 * i + 1] = c[i].imag();
+    }
+    DC_HIP(hipMemcpyAsync(coef, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
+    // the host vector must stay alive until the copy has run
+    DC_HIP(hipStreamSynchronize(st));
+  }
+
+  // x += q(A~) (sum_q c_q basis_q)
+  void add_preconditioned(Z* x, const Z* b0, int q0, const Z* b1, int q1,
+                          const std::vector<cd>& c) {
+    upload_coef(c);
+    if (!has_poly()) {
+      launch_combine(p, b0, q0, b1, q1, N, coef, 1, x, 1, st);
+      return;
+    }
+    launch_combine(p, b0, q0, b1, q1, N, coef, 1, tmp, 0, st);
+    Q(tmp, tmp2, nullptr);
+    launch_axpy(p, mk(1.0, 0.0), tmp2, x, N, st);
+  }
+
+  void ensure_recycle_storage() {
+    const size_t vb = N * sizeof(Z) * size_t(std::max(kmax, 1));
+    var.U.ensure(vb);
+    var.C.ensure(vb);
+  }
+
+  void refresh_unorm() {
+    var.unorm.assign(var.kcur, 1.0);
+    for (int i = 0; i < var.kcur; ++i) var.unorm[i] = norm(Uv() + size_t(i) * N);
+  }
+
+  // New recycle space from an (unpreconditioned-residual) GMRES cycle:
+  // harmonic Ritz vectors of H_m for the k smallest |theta|.
+  void construct_recycle(const CycleOut& c) {
+    const int jd = c.jd;
+    const int kk = std::min(kmax, jd);
+    if (kk <= 0) return;
+    std::vector<cd> th;
+    Mat Zv;
+    if (!harmonic_ritz(c.H, th, &Zv)) return;
+    const auto idx = smallest_k(th, kk);
+    Mat P(jd, kk);
+    for (int t = 0; t < kk; ++t)
+      for (int i = 0; i < jd; ++i) P(i, t) = Zv(i, idx[t]);
+    Mat Qm, R;
+    qr_thin(matmul(c.H, P), Qm, R);
+    const Mat PR = matmul(P, tri_inverse(R));
+    ensure_recycle_storage();
+    // C = V_{jd+1} Q ; U = V_jd P R^{-1}
+    std::vector<cd> cq(size_t(kk) * (jd + 1)), cu(size_t(kk) * jd);
+    for (int r = 0; r < kk; ++r) {
+      for (int q = 0; q <= jd; ++q) cq[size_t(r) * (jd + 1) + q] = Qm(q, r);
+      for (int q = 0; q < jd; ++q) cu[size_t(r) * jd + q] = PR(q, r);
+    }
+    upload_coef(cq);
+    launch_combine(p, nullptr, 0, V(0), jd + 1, N, coef, kk, Cv(), 0, st);
+    upload_coef(cu);
+    launch_combine(p, nullptr, 0, V(0), jd, N, coef, kk, Uv(), 0, st);
+    var.kcur = kk;
+    var.updates = 1;
+    var.recycle_version = op.version;
+    refresh_unorm();
+  }
+
+  // Solve D x = b to relative true residual tol; b, x device vectors of this
+  // precision.  Returns true if converged.
+  bool solve(const Z* b, Z* x, double tol, bool use_x0, int max_cycles, SolveStats& stt,
+             double& relres) {
+    const long mv0 = matvecs;
+    if (!use_x0) launch_zero(p, x, N, st);
+    const double bn = norm(b);
+    if (bn == 0.0) {
+      launch_zero(p, x, N, st);
+      relres = 0.0;
+      return true;
+    }
+    if (var.recycle_version != op.version) {  // matrix changed: rebuild lazily
+      var.kcur = 0;
+      var.updates = 0;
+    }
+    const int k = kmax;
+    const int m = o.m;
+    double rn = true_resid(x, b, rtrue);
+    relres = rn / bn;
+    if (relres <= tol) {
+      stt.matvecs += int(matvecs - mv0);
+      return true;
+    }
+    // left preconditioning is off: rhat = r
+    DC_HIP(hipMemcpyAsync(rhat, rtrue, N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    double beta = rn;
+    const double target_abs = tol * bn;
+    int cycles = 0;
+    bool converged = false;
+    if (k > 0 && var.kcur > 0) {
+      // new right-hand side: x += q(A~) U C^H r; r -= C C^H r
+      launch_multidot(p, Cv(), var.kcur, nullptr, 0, N, rhat, 0, op.red(), res1, nullptr, st);
+      launch_multiaxpy(p, rhat, Cv(), var.kcur, nullptr, 0, N, res1, 1, op.red(), nrm, nullptr, st);
+      if (!has_poly()) {
+        launch_combine(p, Uv(), var.kcur, nullptr, 0, N, res1, 1, x, 1, st);
+      } else {
+        launch_combine(p, Uv(), var.kcur, nullptr, 0, N, res1, 1, tmp, 0, st);
+        Q(tmp, tmp2, nullptr);
+        launch_axpy(p, mk(1.0, 0.0), tmp2, x, N, st);
+      }
+      beta = norm(rhat);
+    } else if (k > 0) {
+      // construction cycle: GMRES(m) of at least k steps
+      const int steps = std::min(m, ldh - 2);
+      CycleOut c = cycle(rhat, beta, steps, 0, target_abs, k);
+      ++cycles;
+      stt.iters += c.jd;
+      std::vector<cd> e1(c.jd + 1, cd(0.0));
+      e1[0] = beta;
+      double lsres;
+      const auto y = lstsq(c.H, e1, &lsres);
+      add_preconditioned(x, nullptr, 0, V(0), c.jd, y);
+      // rhat = V_{jd+1} (beta e1 - H y)
+      std::vector<cd> rr(c.jd + 1);
+      const auto Hy = matmul(c.H, [&] { Mat t(c.jd, 1); for (int i = 0; i < c.jd; ++i) t(i, 0) = y[i]; return t; }());
+      for (int i = 0; i <= c.jd; ++i) rr[i] = e1[i] - Hy(i, 0);
+      upload_coef(rr);
+      launch_combine(p, nullptr, 0, V(0), c.jd + 1, N, coef, 1, rhat, 0, st);
+      stt.rel_res_est = lsres / bn;
+      stt.rebuilt |= 2;
+      construct_recycle(c);
+      beta = norm(rhat);
+    }
+    while (true) {
+      rn = true_resid(x, b, rtrue);
+      relres = rn / bn;
+      if (relres <= tol) {
+        converged = true;
+        break;
+      }
+      if (cycles >= max_cycles) break;
+      if (k == 0 || var.kcur == 0) {
+        // plain GMRES(m) cycle from the true residual
+        const int steps = std::min(m, ldh - 2);
+        CycleOut c = cycle(rtrue, rn, steps, 0, target_abs, 0);
+        ++cycles;
+        stt.iters += c.jd;
+        std::vector<cd> e1(c.jd + 1, cd(0.0));
+        e1[0] = rn;
+        double lsres;
+        const auto y = lstsq(c.H, e1, &lsres);
+        stt.rel_res_est = lsres / bn;
+        add_preconditioned(x, nullptr, 0, V(0), c.jd, y);
+        if (c.jd == 0) break;  // immediate breakdown: nothing more to gain
+        continue;
+      }
+      // GCRO-DR cycle
+      const int kk = var.kcur;
+      const int steps = std::min(m - kk, ldh - 2);
+      if (steps < 1) throw InvalidArg("GCRO-DR needs m > k");
+      CycleOut c = cycle(rhat, beta, steps, kk, target_abs, 0);
+      ++cycles;
+      stt.iters += c.jd;
+      const int jd = c.jd;
+      // G = [[D_k, B_k], [0, Hbar]]
+      Mat G(kk + jd + 1, kk + jd);
+      for (int i = 0; i < kk; ++i) G(i, i) = 1.0 / var.unorm[i];
+      for (int jj = 0; jj < jd; ++jj) {
+        for (int i = 0; i < kk; ++i) G(i, kk + jj) = c.Bk(i, jj);
+        for (int i = 0; i <= jj + 1; ++i) G(kk + i, kk + jj) = c.H(i, jj);
+      }
+      std::vector<cd> rhs(kk + jd + 1, cd(0.0));
+      rhs[kk] = beta;
+      double lsres;
+      const auto y = lstsq(G, rhs, &lsres);
+      stt.rel_res_est = lsres / bn;
+      // x += q(A~) Vhat y, Vhat = [U D_k, V_jd]
+      std::vector<cd> cy(kk + jd);
+      for (int i = 0; i < kk; ++i) cy[i] = y[i] / var.unorm[i];
+      for (int i = 0; i < jd; ++i) cy[kk + i] = y[kk + i];
+      add_preconditioned(x, Uv(), kk, V(0), jd, cy);
+      // rhat -= What (G y), What = [C, V_{jd+1}]
+      Mat ym(kk + jd, 1);
+      for (int i = 0; i < kk + jd; ++i) ym(i, 0) = y[i];
+      const Mat Gy = matmul(G, ym);
+      std::vector<cd> gy(kk + jd + 1);
+      for (int i = 0; i < kk + jd + 1; ++i) gy[i] = Gy(i, 0);
+      upload_coef(gy);
+      launch_multiaxpy(p, rhat, Cv(), kk, V(0), jd + 1, N, coef, 1, op.red(), nrm, nullptr, st);
+      double h;
+      DC_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+      DC_HIP(hipStreamSynchronize(st));
+      beta = std::sqrt(std::max(h, 0.0));
+      if (var.updates < o.u && jd > 0) refresh_recycle(c, G);
+      if (jd == 0) break;
+    }
+    stt.cycles += cycles;
+    stt.matvecs += int(matvecs - mv0);
+    return converged;
+  }
+
+  // Refresh U, C from the generalised harmonic Ritz problem
+  // G^H G z = theta G^H (What^H Vhat) z.
+  void refresh_recycle(const CycleOut& c, const Mat& G) {
+    const int kk = var.kcur, jd = c.jd;
+    const int nr = kk + jd + 1, nc = kk + jd;
+    // What^H Vhat = [[C^H U D_k, 0], [V^H U D_k, I]]
+    Mat WV(nr, nc);
+    for (int i = 0; i < kk; ++i) {
+      launch_multidot(p, Cv(), kk, V(0), jd + 1, N, Uv() + size_t(i) * N, 0, op.red(), res1,
+                      nullptr, st);
+      std::vector<double> h(2 * size_t(nr));
+      DC_HIP(hipMemcpyAsync(h.data(), res1, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      DC_HIP(hipStreamSynchronize(st));
+      for (int r = 0; r < nr; ++r) WV(r, i) = cd(h[2 * r], h[2 * r + 1]) / var.unorm[i];
+    }
+    for (int jj = 0; jj < jd; ++jj) WV(kk + jj, kk + jj) = 1.0;
+    const Mat GH = adjoint(G);
+    Mat Bm = matmul(GH, WV);
+    Mat Am = matmul(GH, G);
+    if (!lu_solve(Bm, Am)) return;  // Am <- Bm^{-1} Am
+    std::vector<cd> th;
+    Mat Zv;
+    if (!eig(Am, th, &Zv)) return;
+    const auto idx = smallest_k(th, kk);
+    Mat P(nc, kk);
+    for (int t = 0; t < kk; ++t)
+      for (int i = 0; i < nc; ++i) P(i, t) = Zv(i, idx[t]);
+    Mat Qm, R;
+    qr_thin(matmul(G, P), Qm, R);
+    const Mat PR = matmul(P, tri_inverse(R));
+    // C_new = What Q (inputs C, V_{jd+1}); U_new = Vhat P R^{-1} (inputs U D_k, V_jd)
+    std::vector<cd> cq(size_t(kk) * nr), cu(size_t(kk) * nc);
+    for (int r = 0; r < kk; ++r) {
+      for (int q = 0; q < nr; ++q) cq[size_t(r) * nr + q] = Qm(q, r);
+      for (int q = 0; q < nc; ++q)
+        cu[size_t(r) * nc + q] = (q < kk) ? PR(q, r) / var.unorm[q] : PR(q, r);
+    }
+    upload_coef(cq);
+    launch_combine(p, Cv(), kk, V(0), jd + 1, N, coef, kk, Ctmp, 0, st);
+    upload_coef(cu);
+    launch_combine(p, Uv(), kk, V(0), jd, N, coef, kk, Utmp, 0, st);
+    DC_HIP(hipMemcpyAsync(Cv(), Ctmp, size_t(kk) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    DC_HIP(hipMemcpyAsync(Uv(), Utmp, size_t(kk) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    var.updates += 1;
+    refresh_unorm();
+  }
+};
+
+template <typename VR>
+void build_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st) {
+  using Z = cx<VR>;
+  SolveOpts po = o;
+  po.k = 0;
+  Krylov<VR> K(op, var, po, var.ws, var.sm, std::max(o.d, o.m), st);
+  var.theta.clear();  // build with A~ itself (no polynomial yet)
+  const size_t N = op.N();
+  // start vector: caller's v0 (complex128) or a seeded Gaussian
+  DevBuf v64;
+  const z64* src = static_cast<const z64*>(o.v0);
+  if (!src) {
+    v64.alloc(N * sizeof(z64));
+    launch_gaussian(v64.as<z64>(), N, o.seed, 4u, st);
+    src = v64.as<z64>();
+  }
+  if (var.prec == P64) {
+    DC_HIP(hipMemcpyAsync(K.tmp, src, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+  } else {
+    launch_convert_64to32(src, reinterpret_cast<z32*>(K.tmp), N, op.n, 0, st);
+  }
+  const double beta = K.norm(K.tmp);
+  if (beta == 0.0) throw InvalidArg("polynomial start vector is zero");
+  auto c = K.cycle(K.tmp, beta, o.d, 0, -1.0, 0);
+  std::vector<cd> th;
+  if (c.breakdown) {
+    Mat Hs = block(c.H, 0, 0, c.jd, c.jd);
+    if (!eig(Hs, th, nullptr)) throw InvalidArg("eigenvalue iteration failed");
+  } else {
+    if (!harmonic_ritz(c.H, th, nullptr)) throw InvalidArg("harmonic Ritz computation failed");
+  }
+  for (const auto& t : th)
+    if (!(std::abs(t) > 0.0) || !std::isfinite(t.real()) || !std::isfinite(t.imag()))
+      throw InvalidArg("degenerate harmonic Ritz value");
+  var.theta = leja_order(th);
+  var.poly_version = op.version;
+  (void)sizeof(Z);
+}
+
+void ensure_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st, SolveStats* stt) {
+  if (o.d <= 1) {
+    var.theta.clear();
+    return;
+  }
+  if (var.poly_version == op.version && int(var.theta.size()) > 0) return;
+  if (var.prec == P64) build_poly<double>(op, var, o, st);
+  else build_poly<float>(op, var, o, st);
+  if (stt) stt->rebuilt |= 1;
+}
+
+double ms_since(std::chrono::steady_clock::time_point t0) {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta) {
+  check_prec(op, o.prec);
+  if (o.d < 1) throw InvalidArg("d must be >= 1");
+  if (o.block_jacobi) throw InvalidArg("block-Jacobi preconditioning is not available in this build");
+  Variant& var = op.variant(o.prec, +1, 0, o.d);
+  var.poly_version = -1;
+  if (var.prec == P64) build_poly<double>(op, var, o, st);
+  else build_poly<float>(op, var, o, st);
+  theta = var.theta;
+  return int(theta.size());
+}
+
+void op_poly_apply(Op& op, const SolveOpts& o, const void* in, void* out, hipStream_t st) {
+  check_prec(op, o.prec);
+  if (!in || !out || in == out) throw InvalidArg("bad vector pointers");
+  Variant& var = op.variant(o.prec, +1, o.block_jacobi, o.d);
+  if (var.poly_version != op.version) throw BadState("polynomial not built for this operator");
+  if (var.prec == P64) {
+    Krylov<double> K(op, var, o, var.ws, var.sm, std::max(o.m, o.d), st);
+    K.Q(static_cast<const z64*>(in), static_cast<z64*>(out), nullptr);
+  } else {
+    Krylov<float> K(op, var, o, var.ws, var.sm, std::max(o.m, o.d), st);
+    K.Q(static_cast<const z32*>(in), static_cast<z32*>(out), nullptr);
+  }
+}
+
+int op_arnoldi(Op& op, const SolveOpts& o, const void* v, int steps, hipStream_t st,
+               std::vector<cd>& hbar) {
+  check_prec(op, o.prec);
+  if (!v || steps < 1) throw InvalidArg("bad Arnoldi arguments");
+  Variant& var = op.variant(o.prec, +1, o.block_jacobi, o.d);
+  ensure_poly(op, var, o, st, nullptr);
+  auto run = [&](auto tag) -> int {
+    using VR = decltype(tag);
+    Krylov<VR> K(op, var, o, var.ws, var.sm, std::max(steps, o.d), st);
+    const z64* src = static_cast<const z64*>(v);
+    if (var.prec == P64) DC_HIP(hipMemcpyAsync(K.tmp, src, op.N() * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    else launch_convert_64to32(src, reinterpret_cast<z32*>(K.tmp), op.N(), op.n, 0, st);
+    const double beta = K.norm(K.tmp);
+    auto c = K.cycle(K.tmp, beta, steps, 0, -1.0, 0);
+    hbar.assign(size_t(steps + 1) * steps, cd(0.0));
+    for (int j = 0; j < c.jd; ++j)
+      for (int i = 0; i <= j + 1; ++i) hbar[size_t(j) * (steps + 1) + i] = c.H(i, j);
+    return c.jd;
+  };
+  if (var.prec == P64) return run(double(0));
+  return run(float(0));
+}
+
+// ||b - D x|| / ||b|| (or with D^H) in FP64, using the handle's scratch.
+static double fp64_relres(Op& op, const z64* x, const z64* b, int adjoint, hipStream_t st) {
+  const size_t N = op.N();
+  op.t64a.ensure(N * sizeof(z64));
+  op.t64b.ensure(N * sizeof(z64));
+  double* d = op.scal.as<double>();
+  launch_norm2(P64, b, N, op.red(), d, st);
+  if (!adjoint) {
+    launch_apply_blocks(P64, op.n, op.V, op.blocks(P64), nullptr, x, op.gbuf(P64),
+                        op.nbr.as<int>(), op.mu, nullptr, st);
+    launch_gather_resid(P64, op.n, op.V, op.gbuf(P64), b, op.t64a.p, op.red(), d + 1, st);
+  } else {
+    op_apply(op, P64, 1, x, op.t64a.p, st);
+    launch_scale(P64, op.t64a.p, op.t64b.p, N, nullptr, -1.0, nullptr, st);
+    launch_axpy(P64, mk(1.0, 0.0), b, op.t64b.p, N, st);
+    launch_norm2(P64, op.t64b.p, N, op.red(), d + 1, st);
+  }
+  double h[2];
+  DC_HIP(hipMemcpyAsync(h, d, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  const double bn = std::sqrt(std::max(h[0], 0.0)), rn = std::sqrt(std::max(h[1], 0.0));
+  return bn > 0 ? rn / bn : 0.0;
+}
+
+int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, void* x,
+             const double* tol, int use_x0, hipStream_t st, SolveStats* stats) {
+  check_prec(op, o.prec);
+  if (!b || !x || !tol || n_rhs < 0) throw InvalidArg("null pointer or negative n_rhs");
+  if (o.m < 1 || o.k < 0 || o.max_cycles < 0 || o.u < 0) throw InvalidArg("bad solver options");
+  if (o.k > 0 && o.k >= o.m) throw InvalidArg("GCRO-DR needs m > k");
+  if (o.block_jacobi) throw InvalidArg("block-Jacobi preconditioning is not available in this build");
+  if (o.outer && o.prec == P64) throw InvalidArg("the outer loop wraps a reduced-precision solve");
+  if (o.outer && (o.m_outer < 1 || o.max_outer < 1 || !(o.inner_tol > 0.0)))
+    throw InvalidArg("bad outer-loop options");
+  for (int r = 0; r < n_rhs; ++r)
+    if (!(tol[r] > 0.0)) throw InvalidArg("tolerances must be positive");
+  const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
+  const size_t N = op.N();
+  int all_ok = 1;
+  for (int r = 0; r < n_rhs; ++r) {
+    const auto t0 = std::chrono::steady_clock::now();
+    SolveStats s;
+    const z64* br = static_cast<const z64*>(b) + size_t(r) * N;
+    z64* xr = static_cast<z64*>(x) + size_t(r) * N;
+    Variant& var = op.variant(o.prec, sign, 0, o.d);
+    const auto ts = std::chrono::steady_clock::now();
+    ensure_poly(op, var, o, st, &s);
+    s.t_setup_ms = ms_since(ts);
+    // adjoint through Gamma5: x = Gamma5 solve(D(-mu), Gamma5 b)
+    const z64* bb = br;
+    z64* xx = xr;
+    if (adjoint) {
+      op.t64a.ensure(N * sizeof(z64));
+      op.t64b.ensure(N * sizeof(z64));
+      launch_gamma5(P64, br, op.t64a.p, op.V, op.n, st);
+      if (use_x0) launch_gamma5(P64, xr, op.t64b.p, op.V, op.n, st);
+      bb = op.t64a.as<z64>();
+      xx = op.t64b.as<z64>();
+    }
+    double rel = 0.0;
+    if (o.prec == P64) {
+      Krylov<double> K(op, var, o, var.ws, var.sm, o.m, st);
+      K.solve(bb, xx, tol[r], use_x0 != 0, o.max_cycles, s, rel);
+    } else if (!o.outer) {
+      Krylov<float> K(op, var, o, var.ws, var.sm, o.m, st);
+      op.t32a.ensure(N * sizeof(z32));
+      op.t32b.ensure(N * sizeof(z32));
+      z32* b32 = op.t32a.as<z32>();
+      z32* x32 = op.t32b.as<z32>();
+      launch_convert_64to32(bb, b32, N, op.n, 0, st);
+      if (use_x0) launch_convert_64to32(xx, x32, N, op.n, 0, st);
+      K.solve(b32, x32, tol[r], use_x0 != 0, o.max_cycles, s, rel);
+      launch_convert_32to64(x32, xx, N, op.n, 0, st);
+    } else {
+      // FP64 flexible GMRES outer loop; its preconditioner is the
+      // reduced-precision solve of the variant (polynomial + recycling)
+      SolveOpts oo = o;
+      oo.k = 0;
+      oo.d = 0;
+      oo.m = o.m_outer;
+      Variant& vo = op.variant(P64, sign, 0, -1);  // holds the outer workspace
+      Krylov<double> KO(op, vo, oo, vo.ws, vo.sm, o.m_outer, st);
+      op.zouter.ensure(size_t(o.m_outer) * N * sizeof(z64));
+      z64* Zb = op.zouter.as<z64>();
+      Krylov<float> KI(op, var, o, var.ws, var.sm, o.m, st);
+      op.t32a.ensure(N * sizeof(z32));
+      op.t32b.ensure(N * sizeof(z32));
+      z32* b32 = op.t32a.as<z32>();
+      z32* x32 = op.t32b.as<z32>();
+      if (!use_x0) launch_zero(P64, xx, N, st);
+      const double bn = KO.norm(bb);
+      int outer_done = 0;
+      while (bn > 0.0) {
+        const double rn = KO.true_resid(xx, bb, KO.rtrue);
+        rel = rn / bn;
+        if (rel <= tol[r] || outer_done >= o.max_outer) break;
+        launch_scale(P64, KO.rtrue, KO.V(0), N, nullptr, 1.0 / rn, nullptr, st);
+        launch_arnoldi_init(KO.ad, rn, st);
+        int jd = 0;
+        for (int j = 0; j < o.m_outer && outer_done < o.max_outer; ++j) {
+          launch_convert_64to32(KO.V(j), b32, N, op.n, 0, st);
+          double irel;
+          KI.solve(b32, x32, o.inner_tol, false, o.max_cycles, s, irel);
+          launch_convert_32to64(x32, Zb + size_t(j) * N, N, op.n, 0, st);
+          KO.A(Zb + size_t(j) * N, KO.V(j + 1), nullptr);
+          KO.orth_step(j, 0, o.m_outer, tol[r] * bn);
+          ++outer_done;
+          int flags[3];
+          DC_HIP(hipMemcpyAsync(flags, KO.ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+          DC_HIP(hipStreamSynchronize(st));
+          jd = flags[1];
+          if (flags[0]) break;
+        }
+        std::vector<double> Hh(2 * size_t(KO.ldh) * KO.ldh);
+        DC_HIP(hipMemcpyAsync(Hh.data(), KO.ad.H, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        DC_HIP(hipStreamSynchronize(st));
+        Mat H(jd + 1, jd);
+        for (int jj = 0; jj < jd; ++jj)
+          for (int i = 0; i <= jj + 1; ++i)
+            H(i, jj) = cd(Hh[2 * (size_t(jj) * KO.ldh + i)], Hh[2 * (size_t(jj) * KO.ldh + i) + 1]);
+        std::vector<cd> e1(jd + 1, cd(0.0));
+        e1[0] = rn;
+        double lsres;
+        const auto y = lstsq(H, e1, &lsres);
+        s.rel_res_est = lsres / bn;
+        KO.upload_coef(y);
+        launch_combine(P64, nullptr, 0, Zb, jd, N, KO.coef, 1, xx, 1, st);
+        if (jd == 0) break;
+      }
+      s.outer_iters = outer_done;
+      s.matvecs += int(KO.matvecs);
+    }
+    if (adjoint) launch_gamma5(P64, xx, xr, op.V, op.n, st);
+    (void)rel;
+    s.rel_res_true = fp64_relres(op, xr, br, adjoint, st);
+    const bool conv = s.rel_res_true <= tol[r];
+    s.status = conv ? 0 : 1;
+    if (!conv) all_ok = 0;
+    s.t_solve_ms = ms_since(t0);
+    if (stats) stats[r] = s;
+  }
+  return all_ok ? 0 : 1;
+}
+
+int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st) {
+  const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
+  Variant& var = op.variant(o.prec, sign, o.block_jacobi, o.d);
+  const size_t N = op.N();
+  if (var.kcur == 0) return 0;
+  if (var.prec == P64) {
+    if (U) DC_HIP(hipMemcpyAsync(U, var.U.p, size_t(var.kcur) * N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    if (C) DC_HIP(hipMemcpyAsync(C, var.C.p, size_t(var.kcur) * N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+  } else {
+    for (int i = 0; i < var.kcur; ++i) {
+      if (U) launch_convert_32to64(var.U.as<z32>() + size_t(i) * N, static_cast<z64*>(U) + size_t(i) * N, N, op.n, 0, st);
+      if (C) launch_convert_32to64(var.C.as<z32>() + size_t(i) * N, static_cast<z64*>(C) + size_t(i) * N, N, op.n, 0, st);
+    }
+  }
+  DC_HIP(hipStreamSynchronize(st));
+  return var.kcur;
+}
+
+}  // namespace dc

@@ -1,0 +1,107 @@
+// Coarse operator handle and the Krylov solvers driving the HIP kernels.
+#pragma once
+
+#include <map>
+#include <memory>
+#include <tuple>
+#include <vector>
+
+#include "dense.hpp"
+#include "kernels.hpp"
+
+namespace dc {
+
+// Owning device allocation.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  explicit DevBuf(size_t b) { alloc(b); }
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf& operator=(DevBuf&& o) noexcept {
+    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    return *this;
+  }
+  ~DevBuf() { release(); }
+  void alloc(size_t b);
+  void ensure(size_t b) { if (b > bytes) alloc(b); }
+  void release();
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct SolveOpts {
+  int m = 30, k = 0, d = 0, u = 10, max_cycles = 100000;
+  int block_jacobi = 0;
+  Prec prec = P64;
+  int outer = 0, m_outer = 10, max_outer = 50;
+  double inner_tol = 1e-4;
+  uint64_t seed = 0;
+  const void* v0 = nullptr;  // device complex128 [V][n]
+};
+
+struct SolveStats {
+  int status = 0, cycles = 0, iters = 0, matvecs = 0, outer_iters = 0, rebuilt = 0;
+  double rel_res_true = 0, rel_res_est = 0, t_setup_ms = 0, t_solve_ms = 0;
+};
+
+struct Op;
+
+// State of one solver variant: (precision, sign of mu, block Jacobi, d).
+struct Variant {
+  Prec prec;
+  int sign;        // +1: D(mu); -1: D(-mu) (adjoint through Gamma5)
+  int bj;
+  int d;
+  // polynomial
+  std::vector<cd> theta;
+  long poly_version = -1;
+  // recycle space (vectors of the variant's precision)
+  DevBuf U, C;
+  int kcur = 0;
+  int updates = 0;
+  long recycle_version = -1;
+  std::vector<double> unorm;   // ||u_i||
+  DevBuf ws, sm;               // Krylov workspace: vectors and small device arrays
+};
+
+struct Op {
+  int dims[4] = {0, 0, 0, 0};
+  int V = 0, n = 0, store = 0;
+  double mu = 0.0;
+  long version = 0;     // bumped by update_coarse_op
+  hipStream_t stream = nullptr;
+  DevBuf nbr, blk64, blk32, blk16, sc16;
+  DevBuf bj64, bj32, bj16, bjsc16;  // block-Jacobi inverses (tiled)
+  long bj_version = -1;
+  DevBuf gbuf64, gbuf32;
+  DevBuf redpart, redcnt;   // reducer scratch
+  DevBuf scal;              // a few device doubles
+  DevBuf t64a, t64b, t32a, t32b, zouter;  // per-solve vector scratch, kept across calls
+  Reducer red() const { return Reducer{redpart.as<double>(), redcnt.as<unsigned>()}; }
+  std::map<std::tuple<int, int, int, int>, std::unique_ptr<Variant>> variants;
+  size_t N() const { return size_t(V) * n; }
+  Variant& variant(Prec p, int sign, int bj, int d);
+  const void* blocks(Prec p) const;
+  const float* scales(Prec p) const { return p == P16S ? sc16.as<float>() : nullptr; }
+  void* gbuf(Prec p) const { return p == P64 ? gbuf64.p : gbuf32.p; }
+};
+
+void op_build(Op& op, const int dims[4], int n_tv, int store, double mu, const void* self_blocks,
+              const void* hop_blocks, bool on_device, hipStream_t st);
+void op_update(Op& op, const void* self_blocks, const void* hop_blocks, bool on_device,
+               hipStream_t st);
+
+// Precision-level entry points used by the C ABI.
+void op_apply(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_t st);
+void op_apply_bj(Op& op, const void* in, void* out, hipStream_t st);
+int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta);
+void op_poly_apply(Op& op, const SolveOpts& o, const void* in, void* out, hipStream_t st);
+int op_arnoldi(Op& op, const SolveOpts& o, const void* v, int steps, hipStream_t st,
+               std::vector<cd>& hbar);
+int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, void* x,
+             const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
+int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st);
+
+}  // namespace dc
