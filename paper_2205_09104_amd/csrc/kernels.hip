@@ -234,53 +234,191 @@ struct VecOf<P64> {
   using R = double;
 };
 
-// One workgroup (5 waves) per site; wave w < 4 handles the hop block B[x, w],
-// wave 4 the self block A[x].  Each wave reads its block once (16-byte loads,
-// 1 KB contiguous per wave and load) and forms from registers both the forward
-// product B psi_{x+mu} (row sums, reduced over the 8 lanes of a lane-row) and
-// the backward product Gamma5 B^H Gamma5 psi_x (column sums, reduced over the 8
-// lanes of a lane-column).
+// Cross-lane sums inside a wavefront.  Lanes are l = lr*8 + lc.  Row sums
+// (over lc, lanes l^1, l^2, l^4) use DPP quad permutes and the half-row mirror;
+// column sums (over lr, lanes l^8, l^16, l^32) use a DPP row rotation by 8 and
+// the gfx950 permlane16/32 swaps, whose two outputs add to v[l] + v[l^16]
+// (resp. v[l^32]) in every lane.
+__device__ inline int dpp_xor1(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+__device__ inline int dpp_xor2(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
+__device__ inline int dpp_hmirror(int v) { return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false); }
+__device__ inline int dpp_ror8(int v) { return __builtin_amdgcn_mov_dpp(v, 0x128, 0xF, 0xF, false); }
+
+template <int CTL>
+__device__ inline float dppf(float v) {
+  int i = __float_as_int(v);
+  if (CTL == 1) i = dpp_xor1(i);
+  if (CTL == 2) i = dpp_xor2(i);
+  if (CTL == 4) i = dpp_hmirror(i);
+  if (CTL == 8) i = dpp_ror8(i);
+  return __int_as_float(i);
+}
+template <int CTL>
+__device__ inline double dppd(double v) {
+  const long long b = __double_as_longlong(v);
+  const float lo = dppf<CTL>(__int_as_float(int(b & 0xffffffff)));
+  const float hi = dppf<CTL>(__int_as_float(int(b >> 32)));
+  return __longlong_as_double((long long)(unsigned(__float_as_int(lo))) |
+                              ((long long)(__float_as_int(hi)) << 32));
+}
+__device__ inline float dpp_any(float v, int ctl) {
+  return ctl == 1 ? dppf<1>(v) : ctl == 2 ? dppf<2>(v) : ctl == 4 ? dppf<4>(v) : dppf<8>(v);
+}
+
+__device__ inline float sum_row8(float v) {  // over lc
+  v += dppf<1>(v);
+  v += dppf<2>(v);
+  v += dppf<4>(v);
+  return v;
+}
+__device__ inline double sum_row8(double v) {
+  v += dppd<1>(v);
+  v += dppd<2>(v);
+  v += dppd<4>(v);
+  return v;
+}
+__device__ inline float swap_sum16(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline float swap_sum32(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ inline double swap_pair16(double v, double& other) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(b & 0xffffffff), hi = unsigned(b >> 32);
+  const auto rl = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto rh = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  other = __longlong_as_double((long long)rl[1] | ((long long)rh[1] << 32));
+  return __longlong_as_double((long long)rl[0] | ((long long)rh[0] << 32));
+}
+__device__ inline double swap_pair32(double v, double& other) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = unsigned(b & 0xffffffff), hi = unsigned(b >> 32);
+  const auto rl = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+  const auto rh = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+  other = __longlong_as_double((long long)rl[1] | ((long long)rh[1] << 32));
+  return __longlong_as_double((long long)rl[0] | ((long long)rh[0] << 32));
+}
+__device__ inline float sum_col8(float v) {  // over lr
+  v += dppf<8>(v);
+  v = swap_sum16(v);
+  return swap_sum32(v);
+}
+__device__ inline double sum_col8(double v) {
+  v += dppd<8>(v);
+  double o;
+  double a = swap_pair16(v, o);
+  v = a + o;
+  a = swap_pair32(v, o);
+  return a + o;
+}
+
+// gbuf slots per site: 0..3 receive the backward hops Gamma5 B[x-mu,mu]^H
+// Gamma5 psi_{x-mu}; 4 the self block (with i*tm*Gamma5 psi_x); 5..8 the
+// forward hops B[x,mu] psi_{x+mu}.
+constexpr int kSlots = 9;
+
+// Block element access: FP64 / FP32 tiles are decoded into complex values,
+// FP16 tiles stay packed (re in the low, im in the high half of a 32-bit
+// word) and are widened inside the mixed-precision FMAs.
 template <int T, int P>
-__global__ __launch_bounds__(320) void k_apply_blocks(
-    const void* __restrict__ blocks, const float* __restrict__ scales,
+struct TileRegs {
+  cx<typename Tile<T, P>::A> m[T * T];
+  __device__ void load(const void* base, int lane) { Tile<T, P>::load(base, lane, m); }
+  __device__ float re(int e) const { return m[e].re; }
+};
+
+template <int T>
+struct TileRegs<T, P16S> {
+  static constexpr int TT = T * T;
+  static constexpr int UNITS = (TT + 3) / 4;
+  uint32_t w[UNITS * 4];
+  __device__ void load(const void* base, int lane) {
+    const uint4* p = static_cast<const uint4*>(base);
+#pragma unroll
+    for (int u = 0; u < UNITS; ++u) {
+      const uint4 v = p[u * 64 + lane];
+      w[4 * u] = v.x;
+      w[4 * u + 1] = v.y;
+      w[4 * u + 2] = v.z;
+      w[4 * u + 3] = v.w;
+    }
+  }
+};
+
+__device__ inline float lo_h(uint32_t w) {
+  return float(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w & 0xffffu)));
+}
+__device__ inline float hi_h(uint32_t w) {
+  return float(__builtin_bit_cast(_Float16, static_cast<unsigned short>(w >> 16)));
+}
+
+// Accumulate one lane's sub-tile: f_a += z_ac pc_c and (hop blocks)
+// g_c += conj(z_ac) pr_a.  npc_im = -Im(pc), npr_re = -Re(pr) avoid sign flips
+// per element.
+template <int T, int P, bool HOP, typename A>
+__device__ inline void tile_products(const TileRegs<T, P>& R, const cx<A> (&pc)[T],
+                                     const A (&npc_im)[T], const cx<A> (&pr)[T],
+                                     const A (&npr_re)[T], cx<A> (&f)[T], cx<A> (&g)[T]) {
+#pragma unroll
+  for (int a = 0; a < T; ++a)
+#pragma unroll
+    for (int c = 0; c < T; ++c) {
+      A zr, zi;
+      if constexpr (P == P16S) {
+        zr = lo_h(R.w[a * T + c]);
+        zi = hi_h(R.w[a * T + c]);
+      } else {
+        zr = R.m[a * T + c].re;
+        zi = R.m[a * T + c].im;
+      }
+      f[a].re = fma(zr, pc[c].re, f[a].re);
+      f[a].re = fma(zi, npc_im[c], f[a].re);
+      f[a].im = fma(zr, pc[c].im, f[a].im);
+      f[a].im = fma(zi, pc[c].re, f[a].im);
+      if constexpr (HOP) {
+        g[c].re = fma(zr, pr[a].re, g[c].re);
+        g[c].re = fma(zi, pr[a].im, g[c].re);
+        g[c].im = fma(zr, pr[a].im, g[c].im);
+        g[c].im = fma(zi, npr_re[a], g[c].im);
+      }
+    }
+}
+
+// One stored block of one site, processed by one wave.
+template <int T, int P, bool FULL, bool HOP>
+__device__ __forceinline__ void apply_one_block(
+    const uint4* __restrict__ bp, const float* __restrict__ scales,
     const cx<typename VecOf<P>::R>* __restrict__ psi, cx<typename VecOf<P>::R>* __restrict__ gbuf,
-    const int* __restrict__ nbr, int V, int n, int chunk, double tm, const int* __restrict__ done) {
-  using TL = Tile<T, P>;
-  using A = typename TL::A;
+    int item, int site, int slot, int src, int n, double tm) {
+  using A = typename Tile<T, P>::A;
   using VR = typename VecOf<P>::R;
-  if (done && *done) return;
-  // XCD-aware order: workgroup b runs on XCD b % 8; each XCD gets a contiguous
-  // range of sites so that neighbour vectors are shared through its L2.
-  const int b = blockIdx.x;
-  const int site = (b & 7) * chunk + (b >> 3);
-  if (site >= V) return;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lane = threadIdx.x;
   const int lr = lane >> 3, lc = lane & 7;
-  const int slot = (wave < 4) ? 1 + wave : 0;
-  constexpr int TT = TL::TT;
-  const size_t blk_units = size_t(TL::UNITS) * 64;
-  const uint4* bp = static_cast<const uint4*>(blocks) + (size_t(site) * 5 + slot) * blk_units;
-
-  cx<A> m[TT];
-  TL::load(bp, lane, m);
-
-  const int src = (wave < 4) ? nbr[wave * V + site] : site;
+  TileRegs<T, P> R;
+  R.load(bp, lane);
   cx<A> pc[T], pr[T];
+  A npc_im[T], npr_re[T];
 #pragma unroll
   for (int q = 0; q < T; ++q) {
     const int col = lc * T + q;
     pc[q] = mk(A(0), A(0));
-    if (col < n) {
+    if (FULL || col < n) {
       const cx<VR> z = psi[size_t(src) * n + col];
       pc[q] = mk(A(z.re), A(z.im));
     }
-    const int row = lr * T + q;
+    npc_im[q] = -pc[q].im;
     pr[q] = mk(A(0), A(0));
-    if (row < n) {
-      const cx<VR> z = psi[size_t(site) * n + row];
-      const A g = A(gam(row, n));
-      pr[q] = mk(A(g * A(z.re)), A(g * A(z.im)));
+    if (HOP) {
+      const int row = lr * T + q;
+      if (FULL || row < n) {
+        const cx<VR> z = psi[size_t(site) * n + row];
+        pr[q] = (row < (n >> 1)) ? mk(A(z.re), A(z.im)) : mk(A(-z.re), A(-z.im));
+      }
     }
+    npr_re[q] = -pr[q].re;
   }
   cx<A> f[T], g[T];
 #pragma unroll
@@ -288,88 +426,91 @@ __global__ __launch_bounds__(320) void k_apply_blocks(
     f[q] = mk(A(0), A(0));
     g[q] = mk(A(0), A(0));
   }
-#pragma unroll
-  for (int a = 0; a < T; ++a)
-#pragma unroll
-    for (int c = 0; c < T; ++c) {
-      const cx<A> z = m[a * T + c];
-      f[a].re += z.re * pc[c].re - z.im * pc[c].im;
-      f[a].im += z.re * pc[c].im + z.im * pc[c].re;
-      g[c].re += z.re * pr[a].re + z.im * pr[a].im;
-      g[c].im += z.re * pr[a].im - z.im * pr[a].re;
-    }
-  if (P == P16S) {
-    const A s = A(scales[size_t(site) * 5 + slot]);
-#pragma unroll
-    for (int q = 0; q < T; ++q) {
-      f[q].re *= s;
-      f[q].im *= s;
-      g[q].re *= s;
-      g[q].im *= s;
-    }
-  }
-  // row sums over lc (lanes lr*8 .. lr*8+7), column sums over lr (stride 8)
+  tile_products<T, P, HOP>(R, pc, npc_im, pr, npr_re, f, g);
+  A s = A(1);
+  if (P == P16S) s = A(scales[item]);
 #pragma unroll
   for (int q = 0; q < T; ++q) {
-#pragma unroll
-    for (int o = 1; o < 8; o <<= 1) {
-      f[q].re += shfl_xor(f[q].re, o);
-      f[q].im += shfl_xor(f[q].im, o);
-    }
+    f[q].re = sum_row8(f[q].re) * s;
+    f[q].im = sum_row8(f[q].im) * s;
   }
-  if (wave < 4) {
-#pragma unroll
-    for (int q = 0; q < T; ++q) {
-#pragma unroll
-      for (int o = 8; o < 64; o <<= 1) {
-        g[q].re += shfl_xor(g[q].re, o);
-        g[q].im += shfl_xor(g[q].im, o);
-      }
-    }
-  }
-  __shared__ cx<A> fpart[5][64];
   if (lc == 0) {
+    cx<VR>* dst = gbuf + (size_t(site) * kSlots + (HOP ? 4 + slot : 4)) * n;
 #pragma unroll
     for (int q = 0; q < T; ++q) {
       const int row = lr * T + q;
-      if (row < n) fpart[wave][row] = f[q];
-    }
-  }
-  if (wave < 4 && lr == 0) {
-    const int dst = src;  // x + mu receives Gamma5 B[x,mu]^H Gamma5 psi_x
-#pragma unroll
-    for (int q = 0; q < T; ++q) {
-      const int col = lc * T + q;
-      if (col < n) {
-        const A gg = A(gam(col, n));
-        gbuf[(size_t(dst) * 5 + wave) * n + col] = mk(VR(gg * g[q].re), VR(gg * g[q].im));
+      if (FULL || row < n) {
+        cx<A> v = f[q];
+        if (!HOP && tm != 0.0) {  // i * tm * Gamma5 psi_x in the accumulation precision
+          const A t = A(row < (n >> 1) ? tm : -tm);
+          const cx<VR> z = psi[size_t(site) * n + row];
+          v.re -= t * A(z.im);
+          v.im += t * A(z.re);
+        }
+        dst[row] = mk(VR(v.re), VR(v.im));
       }
     }
   }
-  __syncthreads();
-  if (threadIdx.x < n) {
-    const int i = threadIdx.x;
-    cx<A> s = fpart[4][i];
+  if constexpr (HOP) {
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-      s.re += fpart[w][i].re;
-      s.im += fpart[w][i].im;
+    for (int q = 0; q < T; ++q) {
+      g[q].re = sum_col8(g[q].re) * s;
+      g[q].im = sum_col8(g[q].im) * s;
     }
-    if (tm != 0.0) {  // i * tm * Gamma5 psi_x, exact in the accumulation precision
-      const cx<VR> z = psi[size_t(site) * n + i];
-      const A t = A(tm * gam(i, n));
-      s.re -= t * A(z.im);
-      s.im += t * A(z.re);
+    if (lr == 0) {
+      cx<VR>* dst = gbuf + (size_t(src) * kSlots + (slot - 1)) * n;  // x + mu receives it
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        const int col = lc * T + q;
+        if (FULL || col < n) {
+          const A gg = (col < (n >> 1)) ? A(1) : A(-1);
+          dst[col] = mk(VR(gg * g[q].re), VR(gg * g[q].im));
+        }
+      }
     }
-    gbuf[(size_t(site) * 5 + 4) * n + i] = mk(VR(s.re), VR(s.im));
   }
 }
 
+// One 64-lane workgroup per (site, stored block).  The wave reads its block
+// once with 16-byte loads (1 KB contiguous per load instruction) and forms
+// from registers both the forward product B psi_{x+mu} (row sums) and the
+// backward product Gamma5 B^H Gamma5 psi_x (column sums).  No barrier: waves
+// of different sites overlap their loads with each other's arithmetic.
+template <int T, int P, bool FULL>
+__global__ __launch_bounds__(64) void k_apply_blocks(
+    const void* __restrict__ blocks, const float* __restrict__ scales,
+    const cx<typename VecOf<P>::R>* __restrict__ psi, cx<typename VecOf<P>::R>* __restrict__ gbuf,
+    const int* __restrict__ nbr, int V, int n, int chunk, double tm, const int* __restrict__ done) {
+  if (done && *done) return;
+  // XCD-aware order: workgroup b runs on XCD b % 8; each XCD gets a
+  // contiguous range of (site, block) items, so a site's blocks are streamed
+  // together and neighbour vectors are shared through that XCD's L2.
+  const int b = blockIdx.x;
+  const int item = (b & 7) * chunk + (b >> 3);
+  if (item >= 5 * V) return;
+  const int site = item / 5, slot = item - 5 * site;  // slot 0 = A, 1 + mu = B[x, mu]
+  const size_t blk_units = size_t(Tile<T, P>::UNITS) * 64;
+  const uint4* bp = static_cast<const uint4*>(blocks) + size_t(item) * blk_units;
+  if (slot == 0) {
+    apply_one_block<T, P, FULL, false>(bp, scales, psi, gbuf, item, site, 0, site, n, tm);
+  } else {
+    const int src = nbr[(slot - 1) * V + site];
+    apply_one_block<T, P, FULL, true>(bp, scales, psi, gbuf, item, site, slot, src, n, tm);
+  }
+}
+
+// Sum of the 9 slots in a fixed order: self, forward hops, backward hops.
 template <typename VR>
 __device__ inline cx<VR> gather5(const cx<VR>* __restrict__ gbuf, size_t i, int n) {
   const size_t site = i / n, c = i - site * n;
-  const size_t base = site * 5 * n + c;
+  const size_t base = site * kSlots * n + c;
   cx<VR> s = gbuf[base + 4 * size_t(n)];
+#pragma unroll
+  for (int w = 5; w < 9; ++w) {
+    const cx<VR> t = gbuf[base + size_t(w) * n];
+    s.re += t.re;
+    s.im += t.im;
+  }
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     const cx<VR> t = gbuf[base + size_t(w) * n];
@@ -853,15 +994,20 @@ template <int P>
 static void apply_T(int n, int V, const void* blocks, const float* scales, const void* in,
                     void* gbuf, const int* nbr, double tm, const int* done, hipStream_t st) {
   using VR = typename VecOf<P>::R;
-  const int chunk = (V + 7) / 8;
-  const dim3 grid(unsigned(chunk) * 8u), block(320);
+  const int chunk = (5 * V + 7) / 8;
+  const dim3 grid(unsigned(chunk) * 8u), block(64);
   const auto* pin = static_cast<const cx<VR>*>(in);
   auto* pg = static_cast<cx<VR>*>(gbuf);
+  const bool full = (n % 8) == 0;
   switch (tile_T(n)) {
-#define DC_CASE(TV)                                                                      \
-  case TV:                                                                               \
-    hipLaunchKernelGGL((k_apply_blocks<TV, P>), grid, block, 0, st, blocks, scales, pin, \
-                       pg, nbr, V, n, chunk, tm, done);                                  \
+#define DC_CASE(TV)                                                                          \
+  case TV:                                                                                   \
+    if (full)                                                                                \
+      hipLaunchKernelGGL((k_apply_blocks<TV, P, true>), grid, block, 0, st, blocks, scales,  \
+                         pin, pg, nbr, V, n, chunk, tm, done);                               \
+    else                                                                                     \
+      hipLaunchKernelGGL((k_apply_blocks<TV, P, false>), grid, block, 0, st, blocks, scales, \
+                         pin, pg, nbr, V, n, chunk, tm, done);                               \
     break;
     DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
 #undef DC_CASE

@@ -26,15 +26,16 @@ void launch_layout_blocks(const z64* self_in, const z64* hops_in, int V, int n,
 // Neighbour table int32 [8][V]: rows 0..3 = x + mu, rows 4..7 = x - mu.
 void launch_neighbours(int* nbr, int L0, int L1, int L2, int L3, hipStream_t st);
 
-// Apply, stage 1: per site, read the 5 stored blocks once; write the site's own
-// sum (self + forward hops + i*tm*Gamma5 psi) into slot 4 of gbuf[x] and the
-// backward-hop contribution Gamma5 B[x,mu]^H Gamma5 psi_x into slot mu of
-// gbuf[x+mu].  gbuf: [V][5][n] in the vector precision.
+// Apply, stage 1: each stored block is read once; the self block writes
+// A_x psi_x + i*tm*Gamma5 psi_x into slot 4 of gbuf[x], the hop block B[x,mu]
+// writes B psi_{x+mu} into slot 5+mu of gbuf[x] and the backward contribution
+// Gamma5 B^H Gamma5 psi_x into slot mu of gbuf[x+mu].  gbuf: [V][9][n] in the
+// vector precision.
 void launch_apply_blocks(Prec p, int n, int V, const void* blocks, const float* scales,
                          const void* in, void* gbuf, const int* nbr, double tm,
                          const int* done, hipStream_t st);
 
-// Apply, stage 2 (sum of the 5 slots) with an epilogue.
+// Apply, stage 2 (sum of the 9 slots in a fixed order) with an epilogue.
 //   store : out = s
 //   poly  : prod = prod - ca*s;  y = y + cb*prod         (polynomial chain step)
 //   resid : out = b - s; result[0] = ||out||^2           (true residual)

@@ -103,8 +103,8 @@ void op_build(Op& op, const int dims[4], int n_tv, int store, double mu, const v
     op.blk16.alloc(nb * block_units(op.n, P16S) * 16);
     op.sc16.alloc(nb * sizeof(float));
   }
-  op.gbuf64.alloc(size_t(op.V) * 5 * op.n * sizeof(z64));
-  if (op.store & 6) op.gbuf32.alloc(size_t(op.V) * 5 * op.n * sizeof(z32));
+  op.gbuf64.alloc(size_t(op.V) * 9 * op.n * sizeof(z64));
+  if (op.store & 6) op.gbuf32.alloc(size_t(op.V) * 9 * op.n * sizeof(z32));
   op.redpart.alloc(size_t(kMaxRedBlocks) * kRedWidth * sizeof(double));
   op.redcnt.alloc(256);
   DC_HIP(hipMemsetAsync(op.redcnt.p, 0, 256, st));
