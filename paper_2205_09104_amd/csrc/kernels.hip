@@ -520,6 +520,209 @@ __device__ inline cx<VR> gather5(const cx<VR>* __restrict__ gbuf, size_t i, int 
   return s;
 }
 
+// ------------------------------------------------------------------ block Jacobi
+// In-place Gauss-Jordan inversion (partial pivoting) of each site's self
+// block A_x + i*tm*Gamma5, one workgroup per site, matrix in LDS; the inverse
+// is written in the tiled layout of every requested precision.
+__device__ void write_tiled(const z64* M, int n, int blk, z64* o64, z32* o32, uint32_t* o16,
+                            float* sc16, double* red) {
+  const int T = (n + 7) / 8, TT = T * T;
+  const int tt32 = (TT + 1) / 2 * 2, tt16 = (TT + 3) / 4 * 4;
+  double mx = 0.0;
+  for (int t = threadIdx.x; t < n * n; t += blockDim.x)
+    mx = fmax(mx, fmax(fabs(M[t].re), fabs(M[t].im)));
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  const float scale = float(red[0]);
+  const double dscale = double(scale);
+  if (o16 && threadIdx.x == 0) sc16[blk] = scale;
+  for (int t = threadIdx.x; t < 64 * tt16; t += blockDim.x) {
+    const int lane = t & 63, e = t >> 6;
+    const int i = (lane >> 3) * T + e / T, j = (lane & 7) * T + e % T;
+    z64 z = mk(0.0, 0.0);
+    if (e < TT && i < n && j < n) z = M[i * n + j];
+    if (o64 && e < TT) o64[size_t(blk) * TT * 64 + size_t(e) * 64 + lane] = z;
+    if (o32 && e < tt32)
+      o32[size_t(blk) * tt32 * 64 + (size_t(e >> 1) * 64 + lane) * 2 + (e & 1)] =
+          mk(float(z.re), float(z.im));
+    if (o16) {
+      uint16_t cr = 0, ci = 0;
+      if (dscale > 0.0) {
+        cr = f64_to_f16_rne(z.re / dscale);
+        ci = f64_to_f16_rne(z.im / dscale);
+      }
+      o16[size_t(blk) * tt16 * 64 + (size_t(e >> 2) * 64 + lane) * 4 + (e & 3)] =
+          uint32_t(cr) | (uint32_t(ci) << 16);
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_invert_blocks(const z64* __restrict__ tiled64, int n,
+                                                       double tm, z64* o64, z32* o32,
+                                                       uint32_t* o16, float* sc16,
+                                                       int* __restrict__ singular) {
+  extern __shared__ z64 M[];               // n*n entries
+  __shared__ int perm[64];
+  __shared__ double red[256];
+  __shared__ int piv_row;
+  __shared__ z64 pivot_row[64];
+  __shared__ z64 pivot_col[64];
+  const int site = blockIdx.x;
+  const int nn = n * n;
+  const int T = (n + 7) / 8, TT = T * T;
+  const z64* src = tiled64 + size_t(site) * 5 * TT * 64;  // slot 0 of the site: A_x
+  for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+    const int i = t / n, j = t % n;
+    const int lane = (i / T) * 8 + j / T, e = (i % T) * T + (j % T);
+    z64 z = src[size_t(e) * 64 + lane];
+    if (i == j) z.im += (i < (n >> 1)) ? tm : -tm;
+    M[t] = z;
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    // pivot: largest |M[i][k]| for i >= k (first wave; ties to the lower row)
+    if (threadIdx.x < 64) {
+      double best = -1.0;
+      int bi = k;
+      for (int i = k + int(threadIdx.x); i < n; i += 64) {
+        const double a = fabs(M[i * n + k].re) + fabs(M[i * n + k].im);
+        if (a > best) { best = a; bi = i; }
+      }
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ob = __shfl_xor(best, o, 64);
+        const int oi = __shfl_xor(bi, o, 64);
+        if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+      }
+      if (threadIdx.x == 0) {
+        piv_row = bi;
+        perm[k] = bi;
+        if (!(best > 0.0)) *singular = 1;
+      }
+    }
+    __syncthreads();
+    const int p = piv_row;
+    if (p != k)
+      for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        const z64 a = M[k * n + j];
+        M[k * n + j] = M[p * n + j];
+        M[p * n + j] = a;
+      }
+    __syncthreads();
+    const z64 akk = M[k * n + k];
+    const double den = akk.re * akk.re + akk.im * akk.im;
+    const z64 d = den > 0.0 ? mk(akk.re / den, -akk.im / den) : mk(0.0, 0.0);  // 1 / a_kk
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const z64 a = (j == k) ? mk(1.0, 0.0) : M[k * n + j];
+      pivot_row[j] = mk(a.re * d.re - a.im * d.im, a.re * d.im + a.im * d.re);
+      pivot_col[j] = M[j * n + k];
+    }
+    __syncthreads();
+    for (int t = threadIdx.x; t < nn; t += blockDim.x) {
+      const int i = t / n, j = t % n;
+      if (i == k) {
+        M[t] = pivot_row[j];
+      } else {
+        const z64 f = pivot_col[i];
+        const z64 r = (j == k) ? mk(0.0, 0.0) : M[t];
+        const z64 pr = pivot_row[j];
+        // M[i][j] = (j == k ? 0 : M[i][j]) - f * pivot_row[j]
+        M[t] = mk(r.re - (f.re * pr.re - f.im * pr.im), r.im - (f.re * pr.im + f.im * pr.re));
+      }
+    }
+    __syncthreads();
+  }
+  // undo the row interchanges as column interchanges, last first
+  for (int k = n - 1; k >= 0; --k) {
+    const int p = perm[k];
+    if (p != k)
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const z64 a = M[i * n + k];
+        M[i * n + k] = M[i * n + p];
+        M[i * n + p] = a;
+      }
+    __syncthreads();
+  }
+  write_tiled(M, n, site, o64, o32, o16, sc16, red);
+}
+
+// out_x = M_x t_x with M_x the stored inverse and t either the sum of the 9
+// gbuf slots (t = D psi) or a plain vector; one wave per site; epilogue as in
+// the gather kernels (0 store, 1 poly_first, 2 poly).
+template <int T, int P, bool FULL, bool FROMBUF, int EPI>
+__global__ __launch_bounds__(64) void k_block_jacobi(
+    const void* __restrict__ blocks, const float* __restrict__ scales,
+    const cx<typename VecOf<P>::R>* __restrict__ tin, cx<typename VecOf<P>::R>* out,
+    const cx<typename VecOf<P>::R>* vin, cx<typename VecOf<P>::R>* y, int V, int n, int chunk,
+    z64 c0, z64 ca, z64 cb, const int* __restrict__ done) {
+  using A = typename Tile<T, P>::A;
+  using VR = typename VecOf<P>::R;
+  if (done && *done) return;
+  const int b = blockIdx.x;
+  const int site = (b & 7) * chunk + (b >> 3);
+  if (site >= V) return;
+  const int lane = threadIdx.x, lr = lane >> 3, lc = lane & 7;
+  const size_t blk_units = size_t(Tile<T, P>::UNITS) * 64;
+  TileRegs<T, P> R;
+  R.load(static_cast<const uint4*>(blocks) + size_t(site) * blk_units, lane);
+  cx<A> pc[T], pr[T], f[T], g[T];
+  A npc_im[T], npr_re[T];
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+    const int col = lc * T + q;
+    cx<A> t = mk(A(0), A(0));
+    if (FULL || col < n) {
+      if (FROMBUF) {
+        const cx<VR> z = gather5(tin, size_t(site) * n + col, n);
+        t = mk(A(z.re), A(z.im));
+      } else {
+        const cx<VR> z = tin[size_t(site) * n + col];
+        t = mk(A(z.re), A(z.im));
+      }
+    }
+    pc[q] = t;
+    npc_im[q] = -t.im;
+    pr[q] = mk(A(0), A(0));
+    npr_re[q] = A(0);
+    f[q] = mk(A(0), A(0));
+    g[q] = mk(A(0), A(0));
+  }
+  tile_products<T, P, false>(R, pc, npc_im, pr, npr_re, f, g);
+  A s = A(1);
+  if (P == P16S) s = A(scales[site]);
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+    f[q].re = sum_row8(f[q].re) * s;
+    f[q].im = sum_row8(f[q].im) * s;
+  }
+  if (lc != 0) return;
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+    const int row = lr * T + q;
+    if (!(FULL || row < n)) continue;
+    const size_t i = size_t(site) * n + row;
+    const VR sr = VR(f[q].re), si = VR(f[q].im);
+    if (EPI == 0) {
+      out[i] = mk(sr, si);
+    } else {
+      const cx<VR> base = (EPI == 1) ? vin[i] : out[i];
+      cx<VR> p = base;
+      p.re -= VR(ca.re) * sr - VR(ca.im) * si;
+      p.im -= VR(ca.re) * si + VR(ca.im) * sr;
+      out[i] = p;
+      cx<VR> yy = (EPI == 1) ? mk(VR(VR(c0.re) * base.re - VR(c0.im) * base.im),
+                                  VR(VR(c0.re) * base.im + VR(c0.im) * base.re))
+                             : y[i];
+      yy.re += VR(cb.re) * p.re - VR(cb.im) * p.im;
+      yy.im += VR(cb.re) * p.im + VR(cb.im) * p.re;
+      y[i] = yy;
+    }
+  }
+}
+
 template <typename VR>
 __global__ void k_gather_store(const cx<VR>* __restrict__ gbuf, cx<VR>* __restrict__ out,
                                size_t N, int n, const int* __restrict__ done) {
@@ -1023,6 +1226,82 @@ void launch_apply_blocks(Prec p, int n, int V, const void* blocks, const float* 
   if (p == P64) apply_T<P64>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
   else if (p == P32) apply_T<P32>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
   else apply_T<P16S>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
+}
+
+void launch_invert_blocks(const void* tiled64, int V, int n, double tm, void* out64, void* out32,
+                          void* out16, float* scales16, int* singular, hipStream_t st) {
+  const size_t lds = size_t(n) * n * sizeof(z64);
+  DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_invert_blocks),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  hipLaunchKernelGGL(k_invert_blocks, dim3(unsigned(V)), dim3(256), lds, st,
+                     static_cast<const z64*>(tiled64), n, tm,
+                     static_cast<z64*>(out64), static_cast<z32*>(out32),
+                     static_cast<uint32_t*>(out16), scales16, singular);
+  DC_HIP(hipGetLastError());
+}
+
+template <int P, bool FROMBUF, int EPI>
+static void bj_T(int n, int V, const void* blocks, const float* scales, const void* tin, void* out,
+                 const void* vin, void* y, z64 c0, z64 ca, z64 cb, const int* done,
+                 hipStream_t st) {
+  using VR = typename VecOf<P>::R;
+  const int chunk = (V + 7) / 8;
+  const dim3 grid(unsigned(chunk) * 8u), block(64);
+  const auto* ti = static_cast<const cx<VR>*>(tin);
+  auto* o = static_cast<cx<VR>*>(out);
+  const auto* vi = static_cast<const cx<VR>*>(vin);
+  auto* yy = static_cast<cx<VR>*>(y);
+  const bool full = (n % 8) == 0;
+  switch (tile_T(n)) {
+#define DC_CASE(TV)                                                                              \
+  case TV:                                                                                       \
+    if (full)                                                                                    \
+      hipLaunchKernelGGL((k_block_jacobi<TV, P, true, FROMBUF, EPI>), grid, block, 0, st, blocks, \
+                         scales, ti, o, vi, yy, V, n, chunk, c0, ca, cb, done);                  \
+    else                                                                                         \
+      hipLaunchKernelGGL((k_block_jacobi<TV, P, false, FROMBUF, EPI>), grid, block, 0, st,       \
+                         blocks, scales, ti, o, vi, yy, V, n, chunk, c0, ca, cb, done);          \
+    break;
+    DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
+#undef DC_CASE
+    default:
+      throw InvalidArg("block size n > 64 is not supported");
+  }
+  DC_HIP(hipGetLastError());
+}
+
+template <bool FROMBUF, int EPI>
+static void bj_P(Prec p, int n, int V, const void* blocks, const float* scales, const void* tin,
+                 void* out, const void* vin, void* y, z64 c0, z64 ca, z64 cb, const int* done,
+                 hipStream_t st) {
+  if (p == P64) bj_T<P64, FROMBUF, EPI>(n, V, blocks, scales, tin, out, vin, y, c0, ca, cb, done, st);
+  else if (p == P32) bj_T<P32, FROMBUF, EPI>(n, V, blocks, scales, tin, out, vin, y, c0, ca, cb, done, st);
+  else bj_T<P16S, FROMBUF, EPI>(n, V, blocks, scales, tin, out, vin, y, c0, ca, cb, done, st);
+}
+
+void launch_bj_vec(Prec p, int n, int V, const void* inv, const float* scales, const void* in,
+                   void* out, hipStream_t st) {
+  const z64 z = mk(0.0, 0.0);
+  bj_P<false, 0>(p, n, V, inv, scales, in, out, nullptr, nullptr, z, z, z, nullptr, st);
+}
+
+void launch_bj_gather_store(Prec p, int n, int V, const void* inv, const float* scales,
+                            const void* gbuf, void* out, const int* done, hipStream_t st) {
+  const z64 z = mk(0.0, 0.0);
+  bj_P<true, 0>(p, n, V, inv, scales, gbuf, out, nullptr, nullptr, z, z, z, done, st);
+}
+
+void launch_bj_gather_poly_first(Prec p, int n, int V, const void* inv, const float* scales,
+                                 const void* gbuf, const void* v, void* prod, void* y, z64 c0,
+                                 z64 ca, z64 cb, const int* done, hipStream_t st) {
+  bj_P<true, 1>(p, n, V, inv, scales, gbuf, prod, v, y, c0, ca, cb, done, st);
+}
+
+void launch_bj_gather_poly(Prec p, int n, int V, const void* inv, const float* scales,
+                           const void* gbuf, void* prod, void* y, z64 ca, z64 cb, const int* done,
+                           hipStream_t st) {
+  const z64 z = mk(0.0, 0.0);
+  bj_P<true, 2>(p, n, V, inv, scales, gbuf, prod, nullptr, y, z, ca, cb, done, st);
 }
 
 void launch_gather_store(Prec p, int n, int V, const void* gbuf, void* out, const int* done,

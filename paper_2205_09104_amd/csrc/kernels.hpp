@@ -49,6 +49,26 @@ void launch_gather_poly_first(Prec p, int n, int V, const void* gbuf, const void
 void launch_gather_resid(Prec p, int n, int V, const void* gbuf, const void* b, void* out,
                          Reducer red, double* result, hipStream_t st);
 
+// ---------------------------------------------------------------- block Jacobi
+// Inverse of each site's self block A_x + i*tm*Gamma5 (Gauss-Jordan with
+// partial pivoting), read from the tiled FP64 operator storage (slot 0) and
+// written tiled in each requested precision; *singular is set to 1 if a zero
+// pivot occurs.
+void launch_invert_blocks(const void* tiled64, int V, int n, double tm, void* out64, void* out32,
+                          void* out16, float* scales16, int* singular, hipStream_t st);
+// out = B^{-1} in (plain vector)
+void launch_bj_vec(Prec p, int n, int V, const void* inv, const float* scales, const void* in,
+                   void* out, hipStream_t st);
+// out = B^{-1} (sum of the gbuf slots), and the polynomial-chain variants
+void launch_bj_gather_store(Prec p, int n, int V, const void* inv, const float* scales,
+                            const void* gbuf, void* out, const int* done, hipStream_t st);
+void launch_bj_gather_poly_first(Prec p, int n, int V, const void* inv, const float* scales,
+                                 const void* gbuf, const void* v, void* prod, void* y, z64 c0,
+                                 z64 ca, z64 cb, const int* done, hipStream_t st);
+void launch_bj_gather_poly(Prec p, int n, int V, const void* inv, const float* scales,
+                           const void* gbuf, void* prod, void* y, z64 ca, z64 cb, const int* done,
+                           hipStream_t st);
+
 // ---------------------------------------------------------------- BLAS-1/2
 // result[q] = basis_q^H w (complex, q < q0 + q1; basis_q = b0 + q*N for q < q0,
 // b1 + (q-q0)*N after), and if want_norm result[q0+q1] = ||w||^2 (real part).

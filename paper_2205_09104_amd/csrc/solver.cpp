@@ -145,8 +145,37 @@ void op_apply(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_
   }
 }
 
-void op_apply_bj(Op&, const void*, void*, hipStream_t) {
-  throw InvalidArg("block-Jacobi preconditioning is not available in this build");
+const Op::BJ& Op::ensure_bj(int sign, hipStream_t st) {
+  BJ& b = bj[sign > 0 ? 0 : 1];
+  if (b.version == version) return b;
+  const size_t nb = size_t(V);
+  b.b64.ensure(nb * block_units(n, P64) * 16);
+  if (store & 2) b.b32.ensure(nb * block_units(n, P32) * 16);
+  if (store & 4) {
+    b.b16.ensure(nb * block_units(n, P16S) * 16);
+    b.sc16.ensure(nb * sizeof(float));
+  }
+  int* flag = reinterpret_cast<int*>(scal.as<double>() + 16);
+  DC_HIP(hipMemsetAsync(flag, 0, sizeof(int), st));
+  launch_invert_blocks(blk64.p, V, n, sign * mu, b.b64.p, (store & 2) ? b.b32.p : nullptr,
+                       (store & 4) ? b.b16.p : nullptr, (store & 4) ? b.sc16.as<float>() : nullptr,
+                       flag, st);
+  int h = 0;
+  DC_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
+  DC_HIP(hipStreamSynchronize(st));
+  if (h) throw BadState("a self block is singular: block-Jacobi preconditioning is not defined");
+  b.version = version;
+  return b;
+}
+
+static const void* bj_blocks(const Op::BJ& b, Prec p) {
+  return p == P64 ? b.b64.p : (p == P32 ? b.b32.p : b.b16.p);
+}
+
+void op_apply_bj(Op& op, const void* in, void* out, hipStream_t st) {
+  if (!in || !out || in == out) throw InvalidArg("bad vector pointers");
+  const Op::BJ& b = op.ensure_bj(+1, st);
+  launch_bj_vec(P64, op.n, op.V, b.b64.p, nullptr, in, out, st);
 }
 
 // ============================================================================ Krylov
@@ -173,12 +202,19 @@ struct Krylov {
   ArnoldiDev ad{};
   long matvecs = 0;
   double brk;
+  const void* bjinv = nullptr;   // block-Jacobi inverses of this precision, if used
+  const float* bjsc = nullptr;
 
   Krylov(Op& op_, Variant& v, const SolveOpts& o_, DevBuf& ws_, DevBuf& sm_, int steps_max,
          hipStream_t st_)
       : op(op_), var(v), o(o_), p(v.prec), tm(v.sign * op_.mu), st(st_), N(op_.N()), ws(ws_),
         sm(sm_) {
     brk = (p == P64) ? 1e-14 : 1e-6;
+    if (v.bj) {
+      const Op::BJ& b = op.ensure_bj(v.sign, st);
+      bjinv = bj_blocks(b, p);
+      bjsc = (p == P16S) ? b.sc16.as<float>() : nullptr;
+    }
     kmax = std::max(o.k, 0);
     ldh = std::max(steps_max, std::max(o.d, 1)) + 2;
     nbasis = ldh + 1;
@@ -226,12 +262,19 @@ struct Krylov {
   Z* Uv() const { return var.U.as<Z>(); }
   Z* Cv() const { return var.C.as<Z>(); }
 
-  // A~ in = D in (one matvec)
+  // A~ in = (B^{-1}) D in (one matvec)
   void A(const Z* in, Z* out, const int* done) {
     launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
                         tm, done, st);
-    launch_gather_store(p, op.n, op.V, op.gbuf(p), out, done, st);
+    if (bjinv) launch_bj_gather_store(p, op.n, op.V, bjinv, bjsc, op.gbuf(p), out, done, st);
+    else launch_gather_store(p, op.n, op.V, op.gbuf(p), out, done, st);
     ++matvecs;
+  }
+
+  // rhat = B^{-1} r (or a copy without block Jacobi)
+  void left_precondition(const Z* r, Z* out) {
+    if (bjinv) launch_bj_vec(p, op.n, op.V, bjinv, bjsc, r, out, st);
+    else DC_HIP(hipMemcpyAsync(out, r, N * sizeof(Z), hipMemcpyDeviceToDevice, st));
   }
 
   bool has_poly() const { return var.d > 1 && int(var.theta.size()) > 1; }
@@ -249,13 +292,21 @@ struct Krylov {
     // i = 1: prod = v - A v / theta_0;  y = v / theta_0 + prod / theta_1
     launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
                         tm, done, st);
-    launch_gather_poly_first(p, op.n, op.V, op.gbuf(p), in, prod, out, inv(th[0]), inv(th[0]),
-                             inv(th[1]), done, st);
+    if (bjinv)
+      launch_bj_gather_poly_first(p, op.n, op.V, bjinv, bjsc, op.gbuf(p), in, prod, out, inv(th[0]),
+                                  inv(th[0]), inv(th[1]), done, st);
+    else
+      launch_gather_poly_first(p, op.n, op.V, op.gbuf(p), in, prod, out, inv(th[0]), inv(th[0]),
+                               inv(th[1]), done, st);
     ++matvecs;
     for (int i = 2; i < d; ++i) {
       launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), prod, op.gbuf(p),
                           op.nbr.as<int>(), tm, done, st);
-      launch_gather_poly(p, op.n, op.V, op.gbuf(p), prod, out, inv(th[i - 1]), inv(th[i]), done, st);
+      if (bjinv)
+        launch_bj_gather_poly(p, op.n, op.V, bjinv, bjsc, op.gbuf(p), prod, out, inv(th[i - 1]),
+                              inv(th[i]), done, st);
+      else
+        launch_gather_poly(p, op.n, op.V, op.gbuf(p), prod, out, inv(th[i - 1]), inv(th[i]), done, st);
       ++matvecs;
     }
   }
@@ -438,10 +489,12 @@ struct Krylov {
       stt.matvecs += int(matvecs - mv0);
       return true;
     }
-    // left preconditioning is off: rhat = r
-    DC_HIP(hipMemcpyAsync(rhat, rtrue, N * sizeof(Z), hipMemcpyDeviceToDevice, st));
-    double beta = rn;
-    const double target_abs = tol * bn;
+    // left-preconditioned residual rhat = B^{-1} r; the least-squares estimates
+    // track ||rhat||, so the in-cycle target is scaled by ||rhat|| / ||r||
+    left_precondition(rtrue, rhat);
+    double beta = bjinv ? norm(rhat) : rn;
+    const double ratio = beta / rn;
+    const double target_abs = tol * bn * ratio;
     int cycles = 0;
     bool converged = false;
     if (k > 0 && var.kcur > 0) {
@@ -487,13 +540,18 @@ struct Krylov {
       }
       if (cycles >= max_cycles) break;
       if (k == 0 || var.kcur == 0) {
-        // plain GMRES(m) cycle from the true residual
+        // plain GMRES(m) cycle from the (left-preconditioned) true residual
         const int steps = std::min(m, ldh - 2);
-        CycleOut c = cycle(rtrue, rn, steps, 0, target_abs, 0);
+        double b0 = rn;
+        if (bjinv) {
+          left_precondition(rtrue, rhat);
+          b0 = norm(rhat);
+        }
+        CycleOut c = cycle(bjinv ? rhat : rtrue, b0, steps, 0, target_abs, 0);
         ++cycles;
         stt.iters += c.jd;
         std::vector<cd> e1(c.jd + 1, cd(0.0));
-        e1[0] = rn;
+        e1[0] = b0;
         double lsres;
         const auto y = lstsq(c.H, e1, &lsres);
         stt.rel_res_est = lsres / bn;
@@ -653,8 +711,7 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta) {
   check_prec(op, o.prec);
   if (o.d < 1) throw InvalidArg("d must be >= 1");
-  if (o.block_jacobi) throw InvalidArg("block-Jacobi preconditioning is not available in this build");
-  Variant& var = op.variant(o.prec, +1, 0, o.d);
+  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d);
   var.poly_version = -1;
   if (var.prec == P64) build_poly<double>(op, var, o, st);
   else build_poly<float>(op, var, o, st);
@@ -665,7 +722,7 @@ int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& t
 void op_poly_apply(Op& op, const SolveOpts& o, const void* in, void* out, hipStream_t st) {
   check_prec(op, o.prec);
   if (!in || !out || in == out) throw InvalidArg("bad vector pointers");
-  Variant& var = op.variant(o.prec, +1, o.block_jacobi, o.d);
+  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d);
   if (var.poly_version != op.version) throw BadState("polynomial not built for this operator");
   if (var.prec == P64) {
     Krylov<double> K(op, var, o, var.ws, var.sm, std::max(o.m, o.d), st);
@@ -680,7 +737,7 @@ int op_arnoldi(Op& op, const SolveOpts& o, const void* v, int steps, hipStream_t
                std::vector<cd>& hbar) {
   check_prec(op, o.prec);
   if (!v || steps < 1) throw InvalidArg("bad Arnoldi arguments");
-  Variant& var = op.variant(o.prec, +1, o.block_jacobi, o.d);
+  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d);
   ensure_poly(op, var, o, st, nullptr);
   auto run = [&](auto tag) -> int {
     using VR = decltype(tag);
@@ -729,7 +786,6 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
   if (!b || !x || !tol || n_rhs < 0) throw InvalidArg("null pointer or negative n_rhs");
   if (o.m < 1 || o.k < 0 || o.max_cycles < 0 || o.u < 0) throw InvalidArg("bad solver options");
   if (o.k > 0 && o.k >= o.m) throw InvalidArg("GCRO-DR needs m > k");
-  if (o.block_jacobi) throw InvalidArg("block-Jacobi preconditioning is not available in this build");
   if (o.outer && o.prec == P64) throw InvalidArg("the outer loop wraps a reduced-precision solve");
   if (o.outer && (o.m_outer < 1 || o.max_outer < 1 || !(o.inner_tol > 0.0)))
     throw InvalidArg("bad outer-loop options");
@@ -743,7 +799,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
     SolveStats s;
     const z64* br = static_cast<const z64*>(b) + size_t(r) * N;
     z64* xr = static_cast<z64*>(x) + size_t(r) * N;
-    Variant& var = op.variant(o.prec, sign, 0, o.d);
+    Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d);
     const auto ts = std::chrono::steady_clock::now();
     ensure_poly(op, var, o, st, &s);
     s.t_setup_ms = ms_since(ts);
@@ -845,7 +901,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
 
 int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st) {
   const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
-  Variant& var = op.variant(o.prec, sign, o.block_jacobi, o.d);
+  Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d);
   const size_t N = op.N();
   if (var.kcur == 0) return 0;
   if (var.prec == P64) {

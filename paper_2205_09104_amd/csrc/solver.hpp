@@ -73,8 +73,11 @@ struct Op {
   long version = 0;     // bumped by update_coarse_op
   hipStream_t stream = nullptr;
   DevBuf nbr, blk64, blk32, blk16, sc16;
-  DevBuf bj64, bj32, bj16, bjsc16;  // block-Jacobi inverses (tiled)
-  long bj_version = -1;
+  struct BJ {                        // block-Jacobi inverses (tiled), per sign of mu
+    DevBuf b64, b32, b16, sc16;
+    long version = -1;
+  } bj[2];
+  const BJ& ensure_bj(int sign, hipStream_t st);
   DevBuf gbuf64, gbuf32;
   DevBuf redpart, redcnt;   // reducer scratch
   DevBuf scal;              // a few device doubles

@@ -211,3 +211,45 @@ def test_edge_cases():
         gop2.solve(bb[0], 1e-10, Opts(prec="f32"))       # FP32 storage not requested
     with pytest.raises(DcError):
         gop2.solve(bb[0], -1.0, Opts())                  # non-positive tolerance
+
+
+# ---------------------------------------------------------------- block Jacobi
+
+@pytest.mark.parametrize("mu", [0.0, 0.15])
+def test_block_jacobi_apply_matches_oracle(mu):
+    log("block jacobi apply", mu)
+    gop, oop = make_pair((3, 2, 2, 2), 6, 2.0, mu=mu)
+    x = rand_vec(oop.V, oop.n, 71).numpy()
+    ref = dop.apply_block_jacobi(dop.block_jacobi_inverse(oop), x)
+    from paper_2205_09104_amd import _lib
+    import ctypes as C
+    out = torch.empty((oop.V, oop.n), dtype=torch.complex128, device="cuda")
+    xg = torch.from_numpy(x).cuda()
+    _lib.check(_lib.load().dc_apply_block_jacobi(gop._h, C.c_void_p(xg.data_ptr()),
+                                                 C.c_void_p(out.data_ptr()),
+                                                 C.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    assert rel(out.cpu().numpy(), ref) <= 1e-13
+
+
+@pytest.mark.parametrize("cfg", ["gmres", "poly", "gcrodr", "mixed"])
+def test_block_jacobi_solves(c1, cfg):
+    from paper_2205_09104_amd import Opts
+    from oracle import poly as op_
+    gop, oop, w, b, xref = c1
+    log("block jacobi solve", cfg)
+    opts = {"gmres": Opts(m=30, block_jacobi=1),
+            "poly": Opts(m=30, d=4, block_jacobi=1, seed=2),
+            "gcrodr": Opts(m=38, k=8, d=4, block_jacobi=1, seed=2),
+            "mixed": Opts(m=38, k=8, d=4, block_jacobi=1, prec="f32", outer=1, seed=2)}[cfg]
+    x, st, rc = gop.solve(b.cuda(), 1e-10, opts)
+    assert rc == 0, st
+    assert oracle_relres(oop, x.cpu().numpy(), b.numpy()) <= 1e-10
+    assert rel(x.cpu().numpy(), xref) <= 1e-6
+    if cfg == "gmres":
+        # the oracle's block-Jacobi preconditioned GMRES(30) reaches the same residual
+        Binv = dop.block_jacobi_inverse(oop)
+        Bi = lambda v: dop.apply_block_jacobi(Binv, v.reshape(oop.V, oop.n)).reshape(-1)
+        from oracle.krylov import gmres as ogmres
+        xo, io = ogmres(flat(oop), b.numpy().reshape(-1), 1e-10, 30, 5000, left=Bi)
+        assert io.converged
+        print("iterations gpu", st[0]["iters"], "oracle", io.iters)
