@@ -140,6 +140,15 @@ void destroy_coarse_op(dc_op_t op);
 int dc_apply(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* out,
              void* stream);
 
+/* Multi-right-hand-side apply (MFMA): out_r = D_c in_r (adjoint = 0) or
+ * D_c^H in_r (adjoint = 1) for r < n_rhs; in, out device [n_rhs][V][n],
+ * complex128 for DC_PREC_F64 (FP64 MFMA) and complex64 otherwise (FP32 MFMA;
+ * FP16 blocks are widened to FP32 on chip).  Each block times an n x n_rhs
+ * panel is a dense complex contraction (the same operator as dc_apply, one
+ * launch for all right-hand sides).  in and out must not overlap. */
+int dc_apply_multi(dc_op_t op, int32_t prec, int32_t adjoint, int32_t n_rhs, const void* in,
+                   void* out, void* stream);
+
 /* out = B^{-1} in with B the block diagonal of the self couplings A_x + i mu
  * Gamma5 (Sec. 3.2); complex128 device vectors. Builds the inverses if stale. */
 int dc_apply_block_jacobi(dc_op_t op, const void* in, void* out, void* stream);

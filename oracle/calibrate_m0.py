@@ -62,7 +62,7 @@ def m0_root(eigs: np.ndarray, rho: float) -> float:
     return 0.5 * (lo + hi)
 
 
-def calibrate(name: str, dense_limit: int = 8192, arpack_tol: float = 1e-8):
+def calibrate(name: str, dense_limit: int = 8192, arpack_tol: float = 1e-6, ncv: int = 300):
     import torch  # noqa: F401  (synth uses torch)
     import synth
     w = synth.WORKLOADS[name]
@@ -76,12 +76,12 @@ def calibrate(name: str, dense_limit: int = 8192, arpack_tol: float = 1e-8):
     else:
         N = op.N
         lin = spla.LinearOperator((N, N), matvec=_torch_matvec(op), dtype=np.complex128)
-        sr = spla.eigs(lin, k=8, which="SR", tol=arpack_tol, ncv=80,
+        sr = spla.eigs(lin, k=2, which="SR", tol=arpack_tol, ncv=ncv,
                        maxiter=100000, return_eigenvectors=False)
-        lr = spla.eigs(lin, k=8, which="LR", tol=arpack_tol, ncv=80,
+        lr = spla.eigs(lin, k=2, which="LR", tol=arpack_tol, ncv=ncv,
                        maxiter=100000, return_eigenvectors=False)
         ev = np.concatenate([sr, lr])
-        method = "ARPACK SR/LR (k=8, ncv=80)"
+        method = f"ARPACK SR/LR (k=2, ncv={ncv}, tol={arpack_tol:g})"
     m0 = m0_root(ev, w.rho)
     shifted = ev + m0
     return {"m0": m0, "rho_target": w.rho,

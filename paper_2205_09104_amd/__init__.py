@@ -124,6 +124,15 @@ class CoarseOp:
                               _stream_ptr(stream)))
         return out
 
+    def apply_multi(self, X: torch.Tensor, prec="f64", adjoint=False, out=None, stream=None):
+        """Y[r] = D X[r] for X of shape [R, V, n] (one MFMA launch)."""
+        X = X.contiguous()
+        assert X.dtype == _vec_dtype(prec) and X.shape[1:] == (self.V, self.n)
+        out = torch.empty_like(X) if out is None else out
+        check(load().dc_apply_multi(self._h, PREC[prec], int(adjoint), X.shape[0], _ptr(X),
+                                    _ptr(out), _stream_ptr(stream)))
+        return out
+
     def grad_hops(self, lam: torch.Tensor, x: torch.Tensor, tied=True, stream=None):
         g = torch.empty((self.V, 4 if tied else 8, self.n, self.n), dtype=torch.complex128,
                         device="cuda")

@@ -54,6 +54,8 @@ SIGNATURES = {
     "destroy_coarse_op": (None, [C.c_void_p]),
     "dc_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                            C.c_void_p]),
+    "dc_apply_multi": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]),
     "dc_apply_block_jacobi": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "dc_poly_setup": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p,
                                 C.POINTER(C.c_double), C.POINTER(C.c_int32)]),

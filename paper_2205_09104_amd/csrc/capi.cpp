@@ -152,6 +152,16 @@ int dc_apply(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* ou
   });
 }
 
+int dc_apply_multi(dc_op_t op, int32_t prec, int32_t adjoint, int32_t n_rhs, const void* in,
+                   void* out, void* stream) {
+  return guarded([&] {
+    if (!op) throw dc::InvalidArg("null handle");
+    if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
+    dc::op_apply_multi(op->op, dc::Prec(prec), adjoint, n_rhs, in, out, as_stream(stream));
+    return DC_OK;
+  });
+}
+
 int dc_apply_block_jacobi(dc_op_t op, const void* in, void* out, void* stream) {
   return guarded([&] {
     if (!op) throw dc::InvalidArg("null handle");

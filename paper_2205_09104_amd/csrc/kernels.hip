@@ -723,6 +723,174 @@ __global__ __launch_bounds__(64) void k_block_jacobi(
   }
 }
 
+// ------------------------------------------------------------------ multi-RHS apply
+// Y_r = D X_r for R right-hand sides at once.  One workgroup (4 waves) per
+// site accumulates the 9 couplings of the site into an n x R output panel
+// held in MFMA accumulators: each coupling stages its block (as the vector
+// precision) and the source panel in LDS, and the complex product runs as the
+// real GEMM [[Re M, -Im M], [Im M, Re M]] [Re P; Im P] on 16x16x4 MFMA tiles.
+// Backward hops Gamma5 B^H Gamma5 read the staged forward block transposed.
+// Every stored block is read once per site that uses it (9 block reads per
+// site; the MFMA work, 72 V n^2 R flops, dominates for R >= 16).
+template <typename VT>
+struct Mfma;
+template <>
+struct Mfma<float> {
+  using acc_t = __attribute__((ext_vector_type(4))) float;
+  __device__ static acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int q) { return lk * 4 + q; }
+};
+template <>
+struct Mfma<double> {
+  using acc_t = __attribute__((ext_vector_type(4))) double;
+  __device__ static acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  __device__ static int row(int lk, int q) { return lk + 4 * q; }
+};
+
+constexpr int kMultiMaxTiles = 8;   // output tiles per wave (2n/16 * ceil(R/16) / 4)
+
+template <int P, typename VT>
+__global__ __launch_bounds__(256) void k_apply_multi(
+    const void* __restrict__ blocks, const float* __restrict__ scales,
+    const cx<VT>* const* __restrict__ xin, cx<VT>* const* __restrict__ yout, int R,
+    const int* __restrict__ nbr, int V, int n, int np, double tm, int g5io) {
+  using acc_t = typename Mfma<VT>::acc_t;
+  extern __shared__ unsigned char smem[];
+  const int ldm = np + 1;                     // padded row stride of the staged block
+  const int ldp = np + 1;                     // padded column stride of the panel
+  cx<VT>* Ml = reinterpret_cast<cx<VT>*>(smem);          // [np][ldm]
+  cx<VT>* Pl = Ml + size_t(np) * ldm;                     // [Rc][ldp]
+  const int site = blockIdx.x;
+  const int r0 = blockIdx.y * 64;
+  const int Rc = min(64, R - r0);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int lrow = lane & 15, lk = lane >> 4;
+  const int T = (n + 7) / 8, TT = T * T;
+  const int epl = (P == P64) ? 1 : (P == P32 ? 2 : 4);
+  const int tte = (TT + epl - 1) / epl * epl;
+  const int rtiles = (2 * np) / 16, ctiles = (Rc + 15) / 16;
+  const int ntiles = rtiles * ctiles;
+  acc_t acc[kMultiMaxTiles];
+#pragma unroll
+  for (int t = 0; t < kMultiMaxTiles; ++t) acc[t] = acc_t{0, 0, 0, 0};
+
+  for (int c = 0; c < 9; ++c) {
+    // coupling c: 0 self, 1..4 forward hop mu = c-1, 5..8 backward hop mu = c-5
+    int src, blk;
+    bool trans = false;
+    if (c == 0) {
+      src = site;
+      blk = site * 5;
+    } else if (c < 5) {
+      src = nbr[(c - 1) * V + site];
+      blk = site * 5 + c;
+    } else {
+      src = nbr[(4 + c - 5) * V + site];       // x - mu
+      blk = src * 5 + (c - 4);                 // B[x-mu, mu]
+      trans = true;
+    }
+    // stage the block (row-major, vector precision); zero padding
+    const float sc = (P == P16S) ? scales[blk] : 1.0f;
+    for (int t = threadIdx.x; t < np * np; t += blockDim.x) {
+      const int i = t / np, j = t % np;
+      cx<VT> z = mk(VT(0), VT(0));
+      if (i < n && j < n) {
+        const int l = (i / T) * 8 + j / T, e = (i % T) * T + (j % T);
+        const size_t off = size_t(blk) * tte * 64 + (size_t(e / epl) * 64 + l) * epl + (e % epl);
+        if (P == P64) {
+          const z64 v = static_cast<const z64*>(blocks)[off];
+          z = mk(VT(v.re), VT(v.im));
+        } else if (P == P32) {
+          const z32 v = static_cast<const z32*>(blocks)[off];
+          z = mk(VT(v.re), VT(v.im));
+        } else {
+          const uint32_t w = static_cast<const uint32_t*>(blocks)[off];
+          z = mk(VT(lo_h(w) * sc), VT(hi_h(w) * sc));
+        }
+        if (c == 0 && i == j) z.im += VT(i < (n >> 1) ? tm : -tm);  // i * tm * Gamma5
+      }
+      Ml[i * ldm + j] = z;
+    }
+    // stage the source panel: column r = x_r at site src (Gamma5 applied if asked)
+    for (int t = threadIdx.x; t < Rc * np; t += blockDim.x) {
+      const int r = t / np, k = t % np;
+      cx<VT> z = mk(VT(0), VT(0));
+      if (k < n) {
+        z = xin[r0 + r][size_t(src) * n + k];
+        if ((g5io & 1) && k >= (n >> 1)) z = mk(VT(-z.re), VT(-z.im));
+      }
+      Pl[r * ldp + k] = z;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < kMultiMaxTiles; ++it) {
+      const int t = wave + 4 * it;
+      if (t >= ntiles) break;
+      const int rt = t % rtiles, ct = t / rtiles;
+      const int row = rt * 16 + lrow;          // output row of the real-expanded GEMM
+      const int ri = row < np ? row : row - np;
+      const bool row_im = row >= np;
+      const int col = ct * 16 + lrow;          // right-hand side of the B fragment
+      acc_t a_ = acc[it];
+      for (int ks = 0; ks < (2 * np) / 4; ++ks) {
+        const int k = ks * 4 + lk;
+        const int kj = k < np ? k : k - np;
+        const bool k_im = k >= np;
+        // A = [[Re M, -Im M], [Im M, Re M]] at (row, k)
+        cx<VT> m;
+        if (!trans) {
+          m = Ml[ri * ldm + kj];
+        } else {  // (Gamma5 B^H Gamma5)[ri][kj] = g_ri g_kj conj(B[kj][ri])
+          const cx<VT> bz = Ml[kj * ldm + ri];
+          const VT sg = ((ri < (n >> 1)) == (kj < (n >> 1))) ? VT(1) : VT(-1);
+          m = mk(VT(sg * bz.re), VT(-sg * bz.im));
+        }
+        const VT a = (row_im == k_im) ? m.re : (row_im ? m.im : -m.im);
+        // B = [Re P; Im P] at (k, col)
+        VT bv = VT(0);
+        if (col < Rc) {
+          const cx<VT> pz = Pl[col * ldp + kj];
+          bv = k_im ? pz.im : pz.re;
+        }
+        a_ = Mfma<VT>::mma(a, bv, a_);
+      }
+      acc[it] = a_;
+    }
+    __syncthreads();
+  }
+  // accumulator tile -> LDS panel [r][i] (complex) -> coalesced stores
+  cx<VT>* Ol = Pl;  // reuse the panel area: [Rc][ldp]
+#pragma unroll
+  for (int it = 0; it < kMultiMaxTiles; ++it) {
+    const int t = wave + 4 * it;
+    if (t >= ntiles) break;
+    const int rt = t % rtiles, ct = t / rtiles;
+    const int col = ct * 16 + lrow;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      // accumulator value q of a lane: row 4*(lane/16)+q for the FP32 16x16x4
+      // MFMA, row lane/16 + 4*q for the FP64 one
+      const int row = rt * 16 + Mfma<VT>::row(lk, q);
+      if (col < Rc) {
+        const int ri = row < np ? row : row - np;
+        VT* dst = reinterpret_cast<VT*>(&Ol[col * ldp + ri]);
+        dst[row < np ? 0 : 1] = acc[it][q];
+      }
+    }
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < Rc * n; t += blockDim.x) {
+    const int r = t / n, i = t % n;
+    cx<VT> z = Ol[r * ldp + i];
+    if ((g5io & 2) && i >= (n >> 1)) z = mk(VT(-z.re), VT(-z.im));
+    yout[r0 + r][size_t(site) * n + i] = z;
+  }
+}
+
 template <typename VR>
 __global__ void k_gather_store(const cx<VR>* __restrict__ gbuf, cx<VR>* __restrict__ out,
                                size_t N, int n, const int* __restrict__ done) {
@@ -1302,6 +1470,45 @@ void launch_bj_gather_poly(Prec p, int n, int V, const void* inv, const float* s
                            hipStream_t st) {
   const z64 z = mk(0.0, 0.0);
   bj_P<true, 2>(p, n, V, inv, scales, gbuf, prod, nullptr, y, z, ca, cb, done, st);
+}
+
+size_t multi_lds_bytes(int n, bool dbl) {
+  const int np = (n + 7) / 8 * 8;
+  const size_t e = dbl ? sizeof(z64) : sizeof(z32);
+  return (size_t(np) * (np + 1) + size_t(64) * (np + 1)) * e;
+}
+
+void launch_apply_multi(Prec p, int n, int V, const void* blocks, const float* scales,
+                        const void* const* xin, void* const* yout, int R, const int* nbr, double tm,
+                        int g5io, hipStream_t st) {
+  const int np = (n + 7) / 8 * 8;
+  const int ctiles_max = 4;
+  if ((2 * np / 16) * ctiles_max > 4 * kMultiMaxTiles) throw InvalidArg("block too large for the multi-RHS kernel");
+  const dim3 grid(unsigned(V), unsigned((R + 63) / 64)), block(256);
+  if (p == P64) {
+    const size_t lds = multi_lds_bytes(n, true);
+    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<P64, double>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+    hipLaunchKernelGGL((k_apply_multi<P64, double>), grid, block, lds, st, blocks, scales,
+                       reinterpret_cast<const z64* const*>(xin), reinterpret_cast<z64* const*>(yout),
+                       R, nbr, V, n, np, tm, g5io);
+  } else {
+    const size_t lds = multi_lds_bytes(n, false);
+    if (p == P32) {
+      DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<P32, float>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+      hipLaunchKernelGGL((k_apply_multi<P32, float>), grid, block, lds, st, blocks, scales,
+                         reinterpret_cast<const z32* const*>(xin), reinterpret_cast<z32* const*>(yout),
+                         R, nbr, V, n, np, tm, g5io);
+    } else {
+      DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<P16S, float>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+      hipLaunchKernelGGL((k_apply_multi<P16S, float>), grid, block, lds, st, blocks, scales,
+                         reinterpret_cast<const z32* const*>(xin), reinterpret_cast<z32* const*>(yout),
+                         R, nbr, V, n, np, tm, g5io);
+    }
+  }
+  DC_HIP(hipGetLastError());
 }
 
 void launch_gather_store(Prec p, int n, int V, const void* gbuf, void* out, const int* done,

@@ -69,6 +69,15 @@ void launch_bj_gather_poly(Prec p, int n, int V, const void* inv, const float* s
                            const void* gbuf, void* prod, void* y, z64 ca, z64 cb, const int* done,
                            hipStream_t st);
 
+// ---------------------------------------------------------------- multi-RHS apply
+// yout[r] = D xin[r] for r < R (device arrays of R vector pointers, vectors in
+// the precision's vector type), MFMA based; g5io bit 0 multiplies inputs and
+// bit 1 outputs by Gamma5 (adjoint through Gamma5 D(-mu) Gamma5 with tm = -mu).
+void launch_apply_multi(Prec p, int n, int V, const void* blocks, const float* scales,
+                        const void* const* xin, void* const* yout, int R, const int* nbr, double tm,
+                        int g5io, hipStream_t st);
+size_t multi_lds_bytes(int n, bool dbl);
+
 // ---------------------------------------------------------------- BLAS-1/2
 // result[q] = basis_q^H w (complex, q < q0 + q1; basis_q = b0 + q*N for q < q0,
 // b1 + (q-q0)*N after), and if want_norm result[q0+q1] = ||w||^2 (real part).

@@ -178,6 +178,27 @@ void op_apply_bj(Op& op, const void* in, void* out, hipStream_t st) {
   launch_bj_vec(P64, op.n, op.V, b.b64.p, nullptr, in, out, st);
 }
 
+void op_apply_multi(Op& op, Prec p, int adjoint, int R, const void* in, void* out, hipStream_t st) {
+  check_prec(op, p);
+  if (R < 0) throw InvalidArg("n_rhs must be >= 0");
+  if (R == 0) return;
+  if (!in || !out || in == out) throw InvalidArg("bad vector pointers");
+  const size_t vb = op.N() * vec_bytes(p);
+  std::vector<const void*> h(2 * size_t(R));
+  for (int r = 0; r < R; ++r) {
+    h[r] = static_cast<const char*>(in) + size_t(r) * vb;
+    h[R + r] = static_cast<char*>(out) + size_t(r) * vb;
+  }
+  op.ptrs.ensure(h.size() * sizeof(void*));
+  DC_HIP(hipMemcpyAsync(op.ptrs.p, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+  void** table = op.ptrs.as<void*>();
+  const void* const* xin = const_cast<const void* const*>(table);
+  void* const* yout = table + R;
+  launch_apply_multi(p, op.n, op.V, op.blocks(p), op.scales(p), xin, yout, R, op.nbr.as<int>(),
+                     adjoint ? -op.mu : op.mu, adjoint ? 3 : 0, st);
+  DC_HIP(hipStreamSynchronize(st));  // the host pointer table must outlive the copy
+}
+
 // ============================================================================ Krylov
 
 namespace {

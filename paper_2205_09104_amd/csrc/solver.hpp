@@ -82,6 +82,7 @@ struct Op {
   DevBuf redpart, redcnt;   // reducer scratch
   DevBuf scal;              // a few device doubles
   DevBuf t64a, t64b, t32a, t32b, zouter;  // per-solve vector scratch, kept across calls
+  DevBuf ptrs;              // device pointer arrays of the multi-RHS apply
   Reducer red() const { return Reducer{redpart.as<double>(), redcnt.as<unsigned>()}; }
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<Variant>> variants;
   size_t N() const { return size_t(V) * n; }
@@ -99,6 +100,7 @@ void op_update(Op& op, const void* self_blocks, const void* hop_blocks, bool on_
 // Precision-level entry points used by the C ABI.
 void op_apply(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_t st);
 void op_apply_bj(Op& op, const void* in, void* out, hipStream_t st);
+void op_apply_multi(Op& op, Prec p, int adjoint, int R, const void* in, void* out, hipStream_t st);
 int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta);
 void op_poly_apply(Op& op, const SolveOpts& o, const void* in, void* out, hipStream_t st);
 int op_arnoldi(Op& op, const SolveOpts& o, const void* v, int steps, hipStream_t st,

@@ -111,3 +111,26 @@ def test_apply_rejects_bad_arguments():
     x = torch.zeros((oop.V, oop.n), dtype=torch.complex64, device="cuda")
     with pytest.raises(DcError):
         gop.apply(x, prec="f32")          # FP32 storage not requested
+
+
+@pytest.mark.parametrize("dims,ntv,R", [((2, 3, 2, 2), 4, 5), ((4, 4, 4, 4), 8, 12),
+                                        ((3, 2, 1, 2), 5, 17), ((2, 2, 2, 3), 24, 64),
+                                        ((2, 2, 2, 2), 32, 70)])
+@pytest.mark.parametrize("mu", [0.0, 0.3])
+def test_apply_multi_matches_oracle(dims, ntv, R, mu):
+    log("apply multi", dims, ntv, R, mu)
+    gop, oop = make_pair(dims, ntv, 2.5, mu=mu, store=("f64", "f32", "f16s"))
+    X = np.stack([rand_vec(oop.V, oop.n, 80, r).numpy() for r in range(R)])
+    Xg = torch.from_numpy(X).cuda()
+    ref = np.stack([dop.apply(oop, x) for x in X])
+    refa = np.stack([dop.apply_adjoint(oop, x) for x in X])
+    assert rel(gop.apply_multi(Xg).cpu().numpy(), ref) <= 1e-13
+    assert rel(gop.apply_multi(Xg, adjoint=True).cpu().numpy(), refa) <= 1e-13
+    X32 = Xg.to(torch.complex64)
+    lo = np.stack([mixed.lowprec_apply(oop, "f32")(x) for x in X])
+    assert rel(gop.apply_multi(X32, prec="f32").cpu().numpy(), lo) <= 2e-6
+    lo16 = np.stack([mixed.lowprec_apply(oop, "f16s")(x) for x in X])
+    assert rel(gop.apply_multi(X32, prec="f16s").cpu().numpy(), lo16) <= 2e-6
+    # same result as R single applies through the other kernel
+    single = torch.stack([gop.apply(X32[r], prec="f32") for r in range(R)])
+    assert rel(gop.apply_multi(X32, prec="f32").cpu().numpy(), single.cpu().numpy()) <= 2e-6
