@@ -751,33 +751,39 @@ struct Mfma<double> {
   __device__ static int row(int lk, int q) { return lk + 4 * q; }
 };
 
-constexpr int kMultiMaxTiles = 8;   // output tiles per wave (2n/16 * ceil(R/16) / 4)
+// Output tiles per wave: (NP/16) row tiles x ceil(R/16) column tiles over 4
+// waves; each tile keeps a real and an imaginary accumulator.
+constexpr int kMultiMaxTiles = 4;
 
-template <int P, typename VT>
+template <int NP, int P, typename VT>
 __global__ __launch_bounds__(256) void k_apply_multi(
     const void* __restrict__ blocks, const float* __restrict__ scales,
     const cx<VT>* const* __restrict__ xin, cx<VT>* const* __restrict__ yout, int R,
-    const int* __restrict__ nbr, int V, int n, int np, double tm, int g5io) {
+    const int* __restrict__ nbr, int V, int n, double tm, int g5io) {
   using acc_t = typename Mfma<VT>::acc_t;
+  constexpr int LD = NP + 1;                  // padded row stride of every LDS plane
   extern __shared__ unsigned char smem[];
-  const int ldm = np + 1;                     // padded row stride of the staged block
-  const int ldp = np + 1;                     // padded column stride of the panel
-  cx<VT>* Ml = reinterpret_cast<cx<VT>*>(smem);          // [np][ldm]
-  cx<VT>* Pl = Ml + size_t(np) * ldm;                     // [Rc][ldp]
+  VT* Mr = reinterpret_cast<VT*>(smem);       // [NP][LD] coupling matrix, real part
+  VT* Mi = Mr + NP * LD;                      // imaginary part
+  VT* Pr = Mi + NP * LD;                      // [64][LD] panel: row r = x_r at the source
+  VT* Pi = Pr + 64 * LD;
   const int site = blockIdx.x;
   const int r0 = blockIdx.y * 64;
   const int Rc = min(64, R - r0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int lrow = lane & 15, lk = lane >> 4;
+  const int l16 = lane & 15, lk = lane >> 4;
   const int T = (n + 7) / 8, TT = T * T;
   const int epl = (P == P64) ? 1 : (P == P32 ? 2 : 4);
   const int tte = (TT + epl - 1) / epl * epl;
-  const int rtiles = (2 * np) / 16, ctiles = (Rc + 15) / 16;
-  const int ntiles = rtiles * ctiles;
-  acc_t acc[kMultiMaxTiles];
+  constexpr int RT = NP / 16;
+  const int CT = (Rc + 15) / 16;
+  const int ntiles = RT * CT;
+  acc_t cre[kMultiMaxTiles], cim[kMultiMaxTiles];
 #pragma unroll
-  for (int t = 0; t < kMultiMaxTiles; ++t) acc[t] = acc_t{0, 0, 0, 0};
-
+  for (int t = 0; t < kMultiMaxTiles; ++t) {
+    cre[t] = acc_t{0, 0, 0, 0};
+    cim[t] = acc_t{0, 0, 0, 0};
+  }
   for (int c = 0; c < 9; ++c) {
     // coupling c: 0 self, 1..4 forward hop mu = c-1, 5..8 backward hop mu = c-5
     int src, blk;
@@ -793,99 +799,94 @@ __global__ __launch_bounds__(256) void k_apply_multi(
       blk = src * 5 + (c - 4);                 // B[x-mu, mu]
       trans = true;
     }
-    // stage the block (row-major, vector precision); zero padding
     const float sc = (P == P16S) ? scales[blk] : 1.0f;
-    for (int t = threadIdx.x; t < np * np; t += blockDim.x) {
-      const int i = t / np, j = t % np;
-      cx<VT> z = mk(VT(0), VT(0));
+    // stage the coupling matrix M as two planes (for a backward hop
+    // Gamma5 B^H Gamma5: M[i][j] = g_i g_j conj(B[j][i])); zero padding
+    for (int t = threadIdx.x; t < NP * NP; t += blockDim.x) {
+      const int i = t / NP, j = t % NP;
+      VT re = VT(0), im = VT(0);
       if (i < n && j < n) {
-        const int l = (i / T) * 8 + j / T, e = (i % T) * T + (j % T);
+        const int bi = trans ? j : i, bj = trans ? i : j;   // entry of the stored block
+        const int l = (bi / T) * 8 + bj / T, e = (bi % T) * T + (bj % T);
         const size_t off = size_t(blk) * tte * 64 + (size_t(e / epl) * 64 + l) * epl + (e % epl);
         if (P == P64) {
           const z64 v = static_cast<const z64*>(blocks)[off];
-          z = mk(VT(v.re), VT(v.im));
+          re = VT(v.re);
+          im = VT(v.im);
         } else if (P == P32) {
           const z32 v = static_cast<const z32*>(blocks)[off];
-          z = mk(VT(v.re), VT(v.im));
+          re = VT(v.re);
+          im = VT(v.im);
         } else {
           const uint32_t w = static_cast<const uint32_t*>(blocks)[off];
-          z = mk(VT(lo_h(w) * sc), VT(hi_h(w) * sc));
+          re = VT(lo_h(w) * sc);
+          im = VT(hi_h(w) * sc);
         }
-        if (c == 0 && i == j) z.im += VT(i < (n >> 1) ? tm : -tm);  // i * tm * Gamma5
+        if (trans) {
+          const VT sg = ((i < (n >> 1)) == (j < (n >> 1))) ? VT(1) : VT(-1);
+          re = sg * re;
+          im = -sg * im;
+        }
+        if (c == 0 && i == j) im += VT(i < (n >> 1) ? tm : -tm);  // i * tm * Gamma5
       }
-      Ml[i * ldm + j] = z;
+      Mr[i * LD + j] = re;
+      Mi[i * LD + j] = im;
     }
-    // stage the source panel: column r = x_r at site src (Gamma5 applied if asked)
-    for (int t = threadIdx.x; t < Rc * np; t += blockDim.x) {
-      const int r = t / np, k = t % np;
+    for (int t = threadIdx.x; t < 64 * NP; t += blockDim.x) {
+      const int r = t / NP, k = t % NP;
       cx<VT> z = mk(VT(0), VT(0));
-      if (k < n) {
+      if (k < n && r < Rc) {
         z = xin[r0 + r][size_t(src) * n + k];
         if ((g5io & 1) && k >= (n >> 1)) z = mk(VT(-z.re), VT(-z.im));
       }
-      Pl[r * ldp + k] = z;
+      Pr[r * LD + k] = z.re;
+      Pi[r * LD + k] = z.im;
     }
     __syncthreads();
+    // C += M P:  Re C += Mr Pr - Mi Pi,  Im C += Mr Pi + Mi Pr  (16x16x4 tiles)
 #pragma unroll
     for (int it = 0; it < kMultiMaxTiles; ++it) {
       const int t = wave + 4 * it;
       if (t >= ntiles) break;
-      const int rt = t % rtiles, ct = t / rtiles;
-      const int row = rt * 16 + lrow;          // output row of the real-expanded GEMM
-      const int ri = row < np ? row : row - np;
-      const bool row_im = row >= np;
-      const int col = ct * 16 + lrow;          // right-hand side of the B fragment
-      acc_t a_ = acc[it];
-      for (int ks = 0; ks < (2 * np) / 4; ++ks) {
-        const int k = ks * 4 + lk;
-        const int kj = k < np ? k : k - np;
-        const bool k_im = k >= np;
-        // A = [[Re M, -Im M], [Im M, Re M]] at (row, k)
-        cx<VT> m;
-        if (!trans) {
-          m = Ml[ri * ldm + kj];
-        } else {  // (Gamma5 B^H Gamma5)[ri][kj] = g_ri g_kj conj(B[kj][ri])
-          const cx<VT> bz = Ml[kj * ldm + ri];
-          const VT sg = ((ri < (n >> 1)) == (kj < (n >> 1))) ? VT(1) : VT(-1);
-          m = mk(VT(sg * bz.re), VT(-sg * bz.im));
-        }
-        const VT a = (row_im == k_im) ? m.re : (row_im ? m.im : -m.im);
-        // B = [Re P; Im P] at (k, col)
-        VT bv = VT(0);
-        if (col < Rc) {
-          const cx<VT> pz = Pl[col * ldp + kj];
-          bv = k_im ? pz.im : pz.re;
-        }
-        a_ = Mfma<VT>::mma(a, bv, a_);
+      const int rt = t % RT, ct = t / RT;
+      const VT* ar = Mr + (rt * 16 + l16) * LD + lk;
+      const VT* ai = Mi + (rt * 16 + l16) * LD + lk;
+      const VT* br = Pr + (ct * 16 + l16) * LD + lk;
+      const VT* bi = Pi + (ct * 16 + l16) * LD + lk;
+      acc_t xr = cre[it], xi = cim[it];
+#pragma unroll
+      for (int k = 0; k < NP; k += 4) {
+        const VT a_r = ar[k], a_i = ai[k], b_r = br[k], b_i = bi[k];
+        xr = Mfma<VT>::mma(a_r, b_r, xr);
+        xr = Mfma<VT>::mma(a_i, -b_i, xr);
+        xi = Mfma<VT>::mma(a_r, b_i, xi);
+        xi = Mfma<VT>::mma(a_i, b_r, xi);
       }
-      acc[it] = a_;
+      cre[it] = xr;
+      cim[it] = xi;
     }
     __syncthreads();
   }
-  // accumulator tile -> LDS panel [r][i] (complex) -> coalesced stores
-  cx<VT>* Ol = Pl;  // reuse the panel area: [Rc][ldp]
+  // accumulators -> LDS panel planes (row r = right-hand side) -> coalesced stores
 #pragma unroll
   for (int it = 0; it < kMultiMaxTiles; ++it) {
     const int t = wave + 4 * it;
     if (t >= ntiles) break;
-    const int rt = t % rtiles, ct = t / rtiles;
-    const int col = ct * 16 + lrow;
+    const int rt = t % RT, ct = t / RT;
+    const int col = ct * 16 + l16;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       // accumulator value q of a lane: row 4*(lane/16)+q for the FP32 16x16x4
       // MFMA, row lane/16 + 4*q for the FP64 one
       const int row = rt * 16 + Mfma<VT>::row(lk, q);
-      if (col < Rc) {
-        const int ri = row < np ? row : row - np;
-        VT* dst = reinterpret_cast<VT*>(&Ol[col * ldp + ri]);
-        dst[row < np ? 0 : 1] = acc[it][q];
-      }
+      Pr[col * LD + row] = cre[it][q];
+      Pi[col * LD + row] = cim[it][q];
     }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < Rc * n; t += blockDim.x) {
     const int r = t / n, i = t % n;
-    cx<VT> z = Ol[r * ldp + i];
+    cx<VT> z = mk(Pr[r * LD + i], Pi[r * LD + i]);
     if ((g5io & 2) && i >= (n >> 1)) z = mk(VT(-z.re), VT(-z.im));
     yout[r0 + r][size_t(site) * n + i] = z;
   }
@@ -1472,43 +1473,46 @@ void launch_bj_gather_poly(Prec p, int n, int V, const void* inv, const float* s
   bj_P<true, 2>(p, n, V, inv, scales, gbuf, prod, nullptr, y, z, ca, cb, done, st);
 }
 
+static int multi_np(int n) { return (n + 15) / 16 * 16; }
+
 size_t multi_lds_bytes(int n, bool dbl) {
-  const int np = (n + 7) / 8 * 8;
-  const size_t e = dbl ? sizeof(z64) : sizeof(z32);
-  return (size_t(np) * (np + 1) + size_t(64) * (np + 1)) * e;
+  const int np = multi_np(n);
+  return size_t(2) * (size_t(np) + 64) * (np + 1) * (dbl ? sizeof(double) : sizeof(float));
+}
+
+template <int NP, int P, typename VT>
+static void multi_launch(int n, int V, const void* blocks, const float* scales,
+                         const void* const* xin, void* const* yout, int R, const int* nbr,
+                         double tm, int g5io, hipStream_t st) {
+  const size_t lds = multi_lds_bytes(n, sizeof(VT) == 8);
+  DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<NP, P, VT>),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
+  const dim3 grid(unsigned(V), unsigned((R + 63) / 64)), block(256);
+  hipLaunchKernelGGL((k_apply_multi<NP, P, VT>), grid, block, lds, st, blocks, scales,
+                     reinterpret_cast<const cx<VT>* const*>(xin),
+                     reinterpret_cast<cx<VT>* const*>(yout), R, nbr, V, n, tm, g5io);
+  DC_HIP(hipGetLastError());
+}
+
+template <int NP>
+static void multi_np_launch(Prec p, int n, int V, const void* blocks, const float* scales,
+                            const void* const* xin, void* const* yout, int R, const int* nbr,
+                            double tm, int g5io, hipStream_t st) {
+  if (p == P64) multi_launch<NP, P64, double>(n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st);
+  else if (p == P32) multi_launch<NP, P32, float>(n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st);
+  else multi_launch<NP, P16S, float>(n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st);
 }
 
 void launch_apply_multi(Prec p, int n, int V, const void* blocks, const float* scales,
                         const void* const* xin, void* const* yout, int R, const int* nbr, double tm,
                         int g5io, hipStream_t st) {
-  const int np = (n + 7) / 8 * 8;
-  const int ctiles_max = 4;
-  if ((2 * np / 16) * ctiles_max > 4 * kMultiMaxTiles) throw InvalidArg("block too large for the multi-RHS kernel");
-  const dim3 grid(unsigned(V), unsigned((R + 63) / 64)), block(256);
-  if (p == P64) {
-    const size_t lds = multi_lds_bytes(n, true);
-    DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<P64, double>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-    hipLaunchKernelGGL((k_apply_multi<P64, double>), grid, block, lds, st, blocks, scales,
-                       reinterpret_cast<const z64* const*>(xin), reinterpret_cast<z64* const*>(yout),
-                       R, nbr, V, n, np, tm, g5io);
-  } else {
-    const size_t lds = multi_lds_bytes(n, false);
-    if (p == P32) {
-      DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<P32, float>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-      hipLaunchKernelGGL((k_apply_multi<P32, float>), grid, block, lds, st, blocks, scales,
-                         reinterpret_cast<const z32* const*>(xin), reinterpret_cast<z32* const*>(yout),
-                         R, nbr, V, n, np, tm, g5io);
-    } else {
-      DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<P16S, float>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-      hipLaunchKernelGGL((k_apply_multi<P16S, float>), grid, block, lds, st, blocks, scales,
-                         reinterpret_cast<const z32* const*>(xin), reinterpret_cast<z32* const*>(yout),
-                         R, nbr, V, n, np, tm, g5io);
-    }
+  switch (multi_np(n)) {
+    case 16: multi_np_launch<16>(p, n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st); break;
+    case 32: multi_np_launch<32>(p, n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st); break;
+    case 48: multi_np_launch<48>(p, n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st); break;
+    case 64: multi_np_launch<64>(p, n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st); break;
+    default: throw InvalidArg("block size n > 64 is not supported");
   }
-  DC_HIP(hipGetLastError());
 }
 
 void launch_gather_store(Prec p, int n, int V, const void* gbuf, void* out, const int* done,
