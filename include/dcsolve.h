@@ -194,6 +194,21 @@ int solve_coarse_adjoint(dc_op_t op, const dc_solve_opts* opts, int32_t n_rhs,
                          const void* b, void* x, const double* tol, int32_t use_x0,
                          void* stream, dc_solve_stats* stats);
 
+/* Batched solve: the n_rhs systems D_c x_r = b_r (adjoint = 1: D_c^H x_r = b_r)
+ * advance in lockstep, each with its own Krylov space, and share one MFMA
+ * multi-right-hand-side apply per step (dc_apply_multi); per-right-hand-side
+ * tolerances tol[r]; converged right-hand sides leave the active set at cycle
+ * ends.  Restarted GMRES(m) with the polynomial of opts->d and block Jacobi of
+ * opts->block_jacobi (Sec. 3.1-3.3); if opts->k > 0 and a recycle space was
+ * built by solve_coarse for the same variant, every cycle is deflated against
+ * it (Sec. 3.4), without refreshing it.  With opts->prec F32/F16S the batch is
+ * the inner solve of an FP64 iterative-refinement loop (x += ||r|| solve(r/||r||)
+ * to opts->inner_tol, at most opts->max_outer times).  b, x, tol, stats as in
+ * solve_coarse.  Returns DC_OK if all converged, else DC_NOT_CONVERGED. */
+int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, int32_t n_rhs,
+                       const void* b, void* x, const double* tol, int32_t use_x0, void* stream,
+                       dc_solve_stats* stats);
+
 /* Gradient of a real loss with respect to the hop blocks, given lambda =
  * D^{-H} dL/dx and x (device complex128 [V][n]).
  *   tied = 0: grad device complex128 [V][8][n][n]; direction mu < 4 is the

@@ -202,6 +202,22 @@ class CoarseOp:
         st = [stats[i].as_dict() for i in range(R)]
         return (x[0] if single else x), st, rc
 
+    def solve_batch(self, b: torch.Tensor, tol, opts: Opts | None = None, x0=None,
+                    adjoint=False, stream=None):
+        """Batched lockstep solve of R systems, b: [R, V, n] complex128; tol scalar or [R]."""
+        opts = opts or Opts()
+        bb = b.contiguous()
+        R = bb.shape[0]
+        assert bb.dtype == torch.complex128 and bb.shape[1:] == (self.V, self.n)
+        x = x0.clone().contiguous() if x0 is not None else torch.empty_like(bb)
+        tols = np.broadcast_to(np.asarray(tol, dtype=np.float64), (R,)).copy()
+        stats = (_lib.SolveStats * R)()
+        o = opts.to_c()
+        rc = check(load().solve_coarse_batch(self._h, C.byref(o), int(adjoint), R, _ptr(bb),
+                                             _ptr(x), tols.ctypes.data_as(C.POINTER(C.c_double)),
+                                             int(x0 is not None), _stream_ptr(stream), stats))
+        return x, [stats[i].as_dict() for i in range(R)], rc
+
     def export_recycle(self, opts: Opts, adjoint=False, stream=None):
         k = max(opts.k, 1)
         U = torch.zeros((k, self.V, self.n), dtype=torch.complex128, device="cuda")

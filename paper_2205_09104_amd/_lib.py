@@ -69,6 +69,9 @@ SIGNATURES = {
     "solve_coarse_adjoint": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32,
                                        C.c_void_p, C.c_void_p, C.POINTER(C.c_double),
                                        C.c_int32, C.c_void_p, C.POINTER(SolveStats)]),
+    "solve_coarse_batch": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_int32,
+                                     C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int32,
+                                     C.c_void_p, C.POINTER(SolveStats)]),
     "dc_grad_hops": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
                                C.c_void_p]),
     "dc_neighbours": (C.c_int, [C.c_void_p, C.POINTER(C.c_int32)]),

@@ -234,6 +234,20 @@ int solve_coarse_adjoint(dc_op_t op, const dc_solve_opts* opts, int32_t n_rhs, c
   return solve_common(op, opts, 1, n_rhs, b, x, tol, use_x0, stream, stats);
 }
 
+int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, int32_t n_rhs,
+                       const void* b, void* x, const double* tol, int32_t use_x0, void* stream,
+                       dc_solve_stats* stats) {
+  return guarded([&] {
+    if (!op || !opts) throw dc::InvalidArg("null handle or options");
+    std::vector<dc::SolveStats> st(n_rhs > 0 ? n_rhs : 0);
+    const int rc = dc::op_solve_batch(op->op, convert(opts), adjoint, n_rhs, b, x, tol, use_x0,
+                                      as_stream(stream), st.data());
+    if (stats)
+      for (int r = 0; r < n_rhs; ++r) copy_stats(st[r], stats + r);
+    return rc == 0 ? DC_OK : DC_NOT_CONVERGED;
+  });
+}
+
 int dc_grad_hops(dc_op_t op, const void* lambda, const void* x, void* grad, int32_t tied,
                  void* stream) {
   return guarded([&] {

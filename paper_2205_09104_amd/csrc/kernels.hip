@@ -723,6 +723,35 @@ __global__ __launch_bounds__(64) void k_block_jacobi(
   }
 }
 
+// ------------------------------------------------------------------ batched chain step
+// For r < R (device pointer arrays): first step (first != 0):
+//   prod_r = v_r - ca t_r;  y_r = c0 v_r + cb prod_r,
+// later steps: prod_r -= ca t_r;  y_r += cb prod_r  (t_r = A~ of the chain input).
+template <typename VR>
+__global__ void k_chain_multi(const cx<VR>* const* __restrict__ t, const cx<VR>* const* __restrict__ v,
+                              cx<VR>* const* __restrict__ prod, cx<VR>* const* __restrict__ y,
+                              size_t N, z64 c0, z64 ca, z64 cb, int first) {
+  const int r = blockIdx.y;
+  const cx<VR>* tr = t[r];
+  cx<VR>* pr = prod[r];
+  cx<VR>* yr = y[r];
+  const VR ar = VR(ca.re), ai = VR(ca.im), br = VR(cb.re), bi = VR(cb.im);
+  const VR zr = VR(c0.re), zi = VR(c0.im);
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const cx<VR> s = tr[i];
+    const cx<VR> base = first ? v[r][i] : pr[i];
+    cx<VR> p = base;
+    p.re -= ar * s.re - ai * s.im;
+    p.im -= ar * s.im + ai * s.re;
+    pr[i] = p;
+    cx<VR> yy = first ? mk(VR(zr * base.re - zi * base.im), VR(zr * base.im + zi * base.re)) : yr[i];
+    yy.re += br * p.re - bi * p.im;
+    yy.im += br * p.im + bi * p.re;
+    yr[i] = yy;
+  }
+}
+
 // ------------------------------------------------------------------ multi-RHS apply
 // Y_r = D X_r for R right-hand sides at once.  One workgroup (4 waves) per
 // site accumulates the 9 couplings of the site into an n x R output panel
@@ -1474,6 +1503,24 @@ void launch_bj_gather_poly(Prec p, int n, int V, const void* inv, const float* s
 }
 
 static int multi_np(int n) { return (n + 15) / 16 * 16; }
+
+void launch_chain_multi(Prec p, const void* const* t, const void* const* v, void* const* prod,
+                        void* const* y, int R, size_t N, z64 c0, z64 ca, z64 cb, int first,
+                        hipStream_t st) {
+  if (R <= 0) return;
+  const dim3 grid(grid_for(N, 256, 512), unsigned(R)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_chain_multi<double>, grid, block, 0, st,
+                       reinterpret_cast<const z64* const*>(t), reinterpret_cast<const z64* const*>(v),
+                       reinterpret_cast<z64* const*>(prod), reinterpret_cast<z64* const*>(y), N, c0,
+                       ca, cb, first);
+  else
+    hipLaunchKernelGGL(k_chain_multi<float>, grid, block, 0, st,
+                       reinterpret_cast<const z32* const*>(t), reinterpret_cast<const z32* const*>(v),
+                       reinterpret_cast<z32* const*>(prod), reinterpret_cast<z32* const*>(y), N, c0,
+                       ca, cb, first);
+  DC_HIP(hipGetLastError());
+}
 
 size_t multi_lds_bytes(int n, bool dbl) {
   const int np = multi_np(n);

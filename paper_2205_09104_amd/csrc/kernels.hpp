@@ -77,6 +77,11 @@ void launch_apply_multi(Prec p, int n, int V, const void* blocks, const float* s
                         const void* const* xin, void* const* yout, int R, const int* nbr, double tm,
                         int g5io, hipStream_t st);
 size_t multi_lds_bytes(int n, bool dbl);
+// batched polynomial-chain step over R vectors (device pointer arrays):
+//   first:  prod = v - ca t;  y = c0 v + cb prod;   else: prod -= ca t;  y += cb prod
+void launch_chain_multi(Prec p, const void* const* t, const void* const* v, void* const* prod,
+                        void* const* y, int R, size_t N, z64 c0, z64 ca, z64 cb, int first,
+                        hipStream_t st);
 
 // ---------------------------------------------------------------- BLAS-1/2
 // result[q] = basis_q^H w (complex, q < q0 + q1; basis_q = b0 + q*N for q < q0,

@@ -218,7 +218,7 @@ struct Krylov {
   DevBuf& ws;
   DevBuf& sm;
   Z *Vb = nullptr, *Ctmp = nullptr, *Utmp = nullptr, *prod = nullptr, *ybuf = nullptr,
-    *tmp = nullptr, *tmp2 = nullptr, *rhat = nullptr, *rtrue = nullptr;
+    *tmp = nullptr, *tmp2 = nullptr, *rhat = nullptr, *rtrue = nullptr, *ta = nullptr, *tb = nullptr;
   double *res1 = nullptr, *res2 = nullptr, *nrm = nullptr, *coef = nullptr, *scal = nullptr;
   ArnoldiDev ad{};
   long matvecs = 0;
@@ -226,8 +226,9 @@ struct Krylov {
   const void* bjinv = nullptr;   // block-Jacobi inverses of this precision, if used
   const float* bjsc = nullptr;
 
+  // recycle_tmp = false: no U/C refresh buffers (members of a batched solve)
   Krylov(Op& op_, Variant& v, const SolveOpts& o_, DevBuf& ws_, DevBuf& sm_, int steps_max,
-         hipStream_t st_)
+         hipStream_t st_, bool recycle_tmp = true)
       : op(op_), var(v), o(o_), p(v.prec), tm(v.sign * op_.mu), st(st_), N(op_.N()), ws(ws_),
         sm(sm_) {
     brk = (p == P64) ? 1e-14 : 1e-6;
@@ -240,18 +241,21 @@ struct Krylov {
     ldh = std::max(steps_max, std::max(o.d, 1)) + 2;
     nbasis = ldh + 1;
     const size_t vb = N * sizeof(Z);
-    const size_t nvec = size_t(nbasis) + 2 * size_t(kmax) + 6;
+    const int ktmp = recycle_tmp ? kmax : 0;
+    const size_t nvec = size_t(nbasis) + 2 * size_t(ktmp) + 8;
     ws.ensure(nvec * vb);
     Z* base = ws.as<Z>();
     Vb = base;
     Ctmp = Vb + size_t(nbasis) * N;
-    Utmp = Ctmp + size_t(kmax) * N;
-    prod = Utmp + size_t(kmax) * N;
+    Utmp = Ctmp + size_t(ktmp) * N;
+    prod = Utmp + size_t(ktmp) * N;
     ybuf = prod + N;
     tmp = ybuf + N;
     tmp2 = tmp + N;
     rhat = tmp2 + N;
     rtrue = rhat + N;
+    ta = rtrue + N;
+    tb = ta + N;
     // small area (doubles)
     const size_t q = size_t(kmax + ldh + 4);
     const size_t nd = 2 * q * 2 + 8 + 2 * size_t(std::max(kmax + ldh + 2, 1)) * std::max(kmax, 2) +
@@ -916,6 +920,437 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
     if (!conv) all_ok = 0;
     s.t_solve_ms = ms_since(t0);
     if (stats) stats[r] = s;
+  }
+  return all_ok ? 0 : 1;
+}
+
+// ============================================================================ batched
+// R right-hand sides solved in lockstep (independent Krylov spaces, one MFMA
+// multi-apply per step for all active right-hand sides): restarted GMRES(m)
+// with the variant's polynomial and block-Jacobi preconditioners and, when the
+// variant already holds a recycle space, deflation against it (frozen: the
+// shared space is not refreshed by the batch).  Converged right-hand sides
+// drop out of the active set at cycle ends.
+
+namespace {
+
+template <typename VR>
+struct Batch {
+  using Z = cx<VR>;
+  Op& op;
+  Variant& var;
+  const SolveOpts& o;
+  Prec p;
+  hipStream_t st;
+  size_t N;
+  int R;
+  std::vector<std::unique_ptr<Krylov<VR>>> K;
+  std::vector<int> act;           // active right-hand sides
+  DevBuf tab;                     // device pointer tables for the active set
+  int ldh;
+  long matvecs = 0;
+  // table layout (pointers): [slot][Ra]
+  enum { T_PROD, T_Y, T_TA, T_TB, T_TMP, T_TMP2, T_X, T_B, T_RT, T_NFIX };
+
+  Batch(Op& op_, Variant& v, const SolveOpts& o_, int R_, hipStream_t st_,
+        std::vector<DevBuf>& ws, std::vector<DevBuf>& sm)
+      : op(op_), var(v), o(o_), p(v.prec), st(st_), N(op_.N()), R(R_) {
+    SolveOpts ko = o;
+    ko.k = var.kcur;  // dot-product arrays sized for the (frozen) deflation space
+    for (int r = 0; r < R; ++r)
+      K.emplace_back(std::make_unique<Krylov<VR>>(op, var, ko, ws[r], sm[r], o.m, st, false));
+    ldh = K[0]->ldh;
+  }
+
+  // pointer tables of the current active set: fixed slots, then basis V_j
+  const Z* const* fixed(int slot) const {
+    return reinterpret_cast<const Z* const*>(tab.as<void*>() + size_t(slot) * act.size());
+  }
+  Z* const* fixedw(int slot) const {
+    return reinterpret_cast<Z* const*>(tab.as<void*>() + size_t(slot) * act.size());
+  }
+  Z* const* basis(int j) const {
+    return reinterpret_cast<Z* const*>(tab.as<void*>() + size_t(T_NFIX + j) * act.size());
+  }
+
+  void upload_tables(const std::vector<Z*>& x, const std::vector<const Z*>& b) {
+    const size_t Ra = act.size();
+    std::vector<void*> h((T_NFIX + ldh + 1) * Ra);
+    for (size_t a = 0; a < Ra; ++a) {
+      Krylov<VR>& k = *K[act[a]];
+      h[T_PROD * Ra + a] = k.prod;
+      h[T_Y * Ra + a] = k.ybuf;
+      h[T_TA * Ra + a] = k.ta;
+      h[T_TB * Ra + a] = k.tb;
+      h[T_TMP * Ra + a] = k.tmp;
+      h[T_TMP2 * Ra + a] = k.tmp2;
+      h[T_X * Ra + a] = x[act[a]];
+      h[T_B * Ra + a] = const_cast<Z*>(b[act[a]]);
+      h[T_RT * Ra + a] = k.rtrue;
+      for (int j = 0; j <= ldh; ++j) h[(T_NFIX + j) * Ra + a] = k.V(j);
+    }
+    tab.ensure(h.size() * sizeof(void*));
+    DC_HIP(hipMemcpyAsync(tab.p, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+    DC_HIP(hipStreamSynchronize(st));
+    htab = std::move(h);
+  }
+
+  std::vector<void*> htab;  // host copy of the device pointer tables
+
+  // host copy of the Ra pointers of a device table slot
+  template <typename PT>
+  std::vector<Z*> host_of(PT dev) const {
+    const size_t off = size_t(reinterpret_cast<const char*>(dev) - static_cast<const char*>(tab.p)) / sizeof(void*);
+    std::vector<Z*> out(act.size());
+    for (size_t a = 0; a < act.size(); ++a) out[a] = static_cast<Z*>(htab[off + a]);
+    return out;
+  }
+
+  // out_a = A~ in_a for the active set (A~ = B^{-1} D with block Jacobi)
+  void A(const Z* const* in, Z* const* out) {
+    const int Ra = int(act.size());
+    const bool bj = K[0]->bjinv != nullptr;
+    launch_apply_multi(p, op.n, op.V, op.blocks(p), op.scales(p),
+                       reinterpret_cast<const void* const*>(in),
+                       reinterpret_cast<void* const*>(bj ? fixedw(T_TB) : out), Ra,
+                       op.nbr.as<int>(), var.sign * op.mu, 0, st);
+    if (bj) {
+      const std::vector<Z*> ho = host_of(out);
+      for (int a = 0; a < Ra; ++a)
+        launch_bj_vec(p, op.n, op.V, K[0]->bjinv, K[0]->bjsc, K[act[a]]->tb, ho[a], st);
+    }
+    matvecs += 1;
+  }
+
+  // out_a = q(A~) in_a (Newton-like chain), out distinct from in
+  void Q(const Z* const* in, Z* const* out) {
+    const auto& th = var.theta;
+    const int d = int(th.size());
+    auto inv = [](cd t) { const cd r = 1.0 / t; return mk(r.real(), r.imag()); };
+    const int Ra = int(act.size());
+    if (d <= 1) {
+      const std::vector<Z*> ho = host_of(out);
+      const std::vector<Z*> hi = host_of(in);
+      const z64 c = (d == 1) ? inv(th[0]) : mk(1.0, 0.0);
+      for (int a = 0; a < Ra; ++a) launch_cscale(p, hi[a], ho[a], N, c, nullptr, st);
+      return;
+    }
+    A(in, fixedw(T_TA));
+    launch_chain_multi(p, reinterpret_cast<const void* const*>(fixed(T_TA)),
+                       reinterpret_cast<const void* const*>(in),
+                       reinterpret_cast<void* const*>(fixedw(T_PROD)),
+                       reinterpret_cast<void* const*>(out), Ra, N, inv(th[0]), inv(th[0]),
+                       inv(th[1]), 1, st);
+    for (int i = 2; i < d; ++i) {
+      A(fixed(T_PROD), fixedw(T_TA));
+      launch_chain_multi(p, reinterpret_cast<const void* const*>(fixed(T_TA)), nullptr,
+                         reinterpret_cast<void* const*>(fixedw(T_PROD)),
+                         reinterpret_cast<void* const*>(out), Ra, N, mk(0.0, 0.0), inv(th[i - 1]),
+                         inv(th[i]), 0, st);
+    }
+  }
+
+  void Ahat(const Z* const* in, Z* const* out) {
+    if (var.d > 1 && int(var.theta.size()) > 1) {
+      Q(in, fixedw(T_Y));
+      A(fixed(T_Y), out);
+    } else {
+      A(in, out);
+    }
+  }
+
+  // true residuals r_a = b_a - D x_a (in the batch precision); returns ||r_a||
+  std::vector<double> true_resid() {
+    const int Ra = int(act.size());
+    launch_apply_multi(p, op.n, op.V, op.blocks(p), op.scales(p),
+                       reinterpret_cast<const void* const*>(fixed(T_X)),
+                       reinterpret_cast<void* const*>(fixedw(T_TA)), Ra, op.nbr.as<int>(),
+                       var.sign * op.mu, 0, st);
+    matvecs += 1;
+    std::vector<double> rn(Ra);
+    for (int a = 0; a < Ra; ++a) {
+      Krylov<VR>& k = *K[act[a]];
+      launch_scale(p, k.ta, k.rtrue, N, nullptr, -1.0, nullptr, st);
+      launch_axpy(p, mk(1.0, 0.0), bptr[act[a]], k.rtrue, N, st);
+      launch_norm2(p, k.rtrue, N, op.red(), k.nrm, st);
+    }
+    for (int a = 0; a < Ra; ++a) {
+      DC_HIP(hipMemcpyAsync(&rn[a], K[act[a]]->nrm, sizeof(double), hipMemcpyDeviceToHost, st));
+      DC_HIP(hipStreamSynchronize(st));
+      rn[a] = std::sqrt(std::max(rn[a], 0.0));
+    }
+    return rn;
+  }
+
+  std::vector<const Z*> bptr;
+
+  // Solve D x_r = b_r for all r to tolerances tol[r]; returns converged flags.
+  std::vector<int> solve(const std::vector<const Z*>& b, const std::vector<Z*>& x,
+                         const std::vector<double>& tol, bool use_x0, int max_cycles,
+                         std::vector<SolveStats>& stt, std::vector<double>& relres) {
+    bptr = b;
+    std::vector<int> conv(R, 0);
+    std::vector<double> bn(R);
+    for (int r = 0; r < R; ++r) {
+      if (!use_x0) launch_zero(p, x[r], N, st);
+      bn[r] = K[r]->norm(b[r]);
+      if (bn[r] == 0.0) {
+        launch_zero(p, x[r], N, st);
+        conv[r] = 1;
+        relres[r] = 0.0;
+      }
+    }
+    const int kC = var.kcur;
+    const bool poly = var.d > 1 && int(var.theta.size()) > 1;
+    const int steps = std::min(o.m - kC, ldh - 2);
+    if (steps < 1) throw InvalidArg("batched solve needs m > k");
+    std::vector<int> cycles(R, 0);
+    for (int cyc = 0;; ++cyc) {
+      act.clear();
+      for (int r = 0; r < R; ++r)
+        if (!conv[r] && cycles[r] <= max_cycles) act.push_back(r);
+      if (act.empty()) break;
+      upload_tables(x, b);
+      const long mv0 = matvecs;
+      const std::vector<double> rn = true_resid();
+      std::vector<int> keep;
+      for (size_t a = 0; a < act.size(); ++a) {
+        const int r = act[a];
+        relres[r] = rn[a] / bn[r];
+        stt[r].matvecs += int(matvecs - mv0);
+        if (relres[r] <= tol[r]) conv[r] = 1;
+        else if (cycles[r] < max_cycles) keep.push_back(r);
+      }
+      if (keep.empty()) break;
+      if (keep.size() != act.size()) {
+        act = keep;
+        upload_tables(x, b);
+      }
+      const int Ra = int(act.size());
+      // start vectors: rhat = B^{-1} r, deflated against C (x += q U C^H rhat)
+      std::vector<double> beta(Ra), target(Ra);
+      for (int a = 0; a < Ra; ++a) {
+        Krylov<VR>& k = *K[act[a]];
+        k.left_precondition(k.rtrue, k.rhat);
+        const double b0 = k.bjinv ? k.norm(k.rhat) : rn[a];
+        target[a] = tol[act[a]] * bn[act[a]] * (b0 / std::max(relres[act[a]] * bn[act[a]], 1e-300));
+        if (kC > 0) {
+          launch_multidot(p, k.Cv(), kC, nullptr, 0, N, k.rhat, 0, op.red(), k.res1, nullptr, st);
+          launch_multiaxpy(p, k.rhat, k.Cv(), kC, nullptr, 0, N, k.res1, 0, op.red(), k.nrm,
+                           nullptr, st);
+          launch_combine(p, k.Uv(), kC, nullptr, 0, N, k.res1, 1, k.tmp, 0, st);
+        }
+        beta[a] = (kC > 0) ? k.norm(k.rhat) : b0;
+      }
+      if (kC > 0) {  // x += q(A~) U c for all active right-hand sides
+        if (poly) Q(fixed(T_TMP), fixedw(T_TMP2));
+        for (int a = 0; a < Ra; ++a) {
+          Krylov<VR>& k = *K[act[a]];
+          launch_axpy(p, mk(1.0, 0.0), poly ? k.tmp2 : k.tmp, x[act[a]], N, st);
+        }
+      }
+      for (int a = 0; a < Ra; ++a) {
+        Krylov<VR>& k = *K[act[a]];
+        launch_scale(p, k.rhat, k.V(0), N, nullptr, 1.0 / beta[a], nullptr, st);
+        launch_arnoldi_init(k.ad, beta[a], st);
+      }
+      const long mv1 = matvecs;
+      for (int j = 0; j < steps; ++j) {
+        Ahat(basis(j), basis(j + 1));
+        for (int a = 0; a < Ra; ++a) K[act[a]]->orth_step(j, kC, steps, target[a]);
+      }
+      // per right-hand side: least squares and the update of x
+      for (int a = 0; a < Ra; ++a) {
+        const int r = act[a];
+        Krylov<VR>& k = *K[r];
+        int flags[3];
+        DC_HIP(hipMemcpyAsync(flags, k.ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+        std::vector<double> Hh(2 * size_t(k.ldh) * k.ldh), Bh(2 * size_t(k.ad.ldb) * k.ldh);
+        DC_HIP(hipMemcpyAsync(Hh.data(), k.ad.H, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        if (kC) DC_HIP(hipMemcpyAsync(Bh.data(), k.ad.Bk, Bh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        DC_HIP(hipStreamSynchronize(st));
+        const int jd = flags[1];
+        stt[r].iters += jd;
+        stt[r].matvecs += int(matvecs - mv1);
+        cycles[r] += 1;
+        stt[r].cycles += 1;
+        Mat G(kC + jd + 1, kC + jd);
+        for (int i = 0; i < kC; ++i) G(i, i) = 1.0 / var.unorm[i];
+        for (int jj = 0; jj < jd; ++jj) {
+          for (int i = 0; i < kC; ++i)
+            G(i, kC + jj) = cd(Bh[2 * (size_t(jj) * k.ad.ldb + i)], Bh[2 * (size_t(jj) * k.ad.ldb + i) + 1]);
+          for (int i = 0; i <= jj + 1; ++i)
+            G(kC + i, kC + jj) = cd(Hh[2 * (size_t(jj) * k.ldh + i)], Hh[2 * (size_t(jj) * k.ldh + i) + 1]);
+        }
+        std::vector<cd> rhs(kC + jd + 1, cd(0.0));
+        rhs[kC] = beta[a];
+        double lsres = 0.0;
+        const auto y = lstsq(G, rhs, &lsres);
+        stt[r].rel_res_est = lsres / bn[r];
+        std::vector<cd> cy(kC + jd);
+        for (int i = 0; i < kC; ++i) cy[i] = y[i] / var.unorm[i];
+        for (int i = 0; i < jd; ++i) cy[kC + i] = y[kC + i];
+        k.upload_coef(cy);
+        launch_combine(p, kC ? k.Uv() : nullptr, kC, k.V(0), jd, N, k.coef, 1,
+                       poly ? k.tmp : x[r], poly ? 0 : 1, st);
+      }
+      if (poly) {
+        Q(fixed(T_TMP), fixedw(T_TMP2));
+        for (int a = 0; a < Ra; ++a)
+          launch_axpy(p, mk(1.0, 0.0), K[act[a]]->tmp2, x[act[a]], N, st);
+      }
+    }
+    return conv;
+  }
+};
+
+}  // namespace
+
+int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b, void* x,
+                   const double* tol, int use_x0, hipStream_t st, SolveStats* stats) {
+  check_prec(op, o.prec);
+  if (!b || !x || !tol || R < 0) throw InvalidArg("null pointer or negative n_rhs");
+  if (o.m < 1 || o.max_cycles < 0) throw InvalidArg("bad solver options");
+  for (int r = 0; r < R; ++r)
+    if (!(tol[r] > 0.0)) throw InvalidArg("tolerances must be positive");
+  if (R == 0) return 0;
+  const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
+  const size_t N = op.N();
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<SolveStats> stt(R);
+  Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d);
+  const auto ts = std::chrono::steady_clock::now();
+  ensure_poly(op, var, o, st, &stt[0]);
+  if (var.recycle_version != op.version) var.kcur = 0;
+  const double t_setup = ms_since(ts);
+  const int kC = (o.k > 0) ? var.kcur : 0;
+  const int kc_saved = var.kcur;
+  var.kcur = kC;
+  op.bws.resize(std::max<size_t>(op.bws.size(), size_t(R)));
+  op.bsm.resize(std::max<size_t>(op.bsm.size(), size_t(R)));
+  // caller vectors (complex128); adjoint through Gamma5 on copies
+  op.bx64.ensure(size_t(R) * N * sizeof(z64));
+  op.bb64.ensure(size_t(R) * N * sizeof(z64));
+  z64* B64 = op.bb64.as<z64>();
+  z64* X64 = op.bx64.as<z64>();
+  for (int r = 0; r < R; ++r) {
+    const z64* br = static_cast<const z64*>(b) + size_t(r) * N;
+    z64* xr = static_cast<z64*>(x) + size_t(r) * N;
+    if (adjoint) {
+      launch_gamma5(P64, br, B64 + size_t(r) * N, op.V, op.n, st);
+      if (use_x0) launch_gamma5(P64, xr, X64 + size_t(r) * N, op.V, op.n, st);
+    } else {
+      DC_HIP(hipMemcpyAsync(B64 + size_t(r) * N, br, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+      if (use_x0) DC_HIP(hipMemcpyAsync(X64 + size_t(r) * N, xr, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    }
+  }
+  std::vector<double> tl(tol, tol + R), rel(R, 0.0);
+  if (o.prec == P64) {
+    Batch<double> Bt(op, var, o, R, st, op.bws, op.bsm);
+    std::vector<const z64*> bp(R);
+    std::vector<z64*> xp(R);
+    for (int r = 0; r < R; ++r) {
+      bp[r] = B64 + size_t(r) * N;
+      xp[r] = X64 + size_t(r) * N;
+    }
+    Bt.solve(bp, xp, tl, use_x0 != 0, o.max_cycles, stt, rel);
+  } else {
+    // FP64 iterative refinement around the batched reduced-precision solve:
+    // x += ||r|| solve32(D, r / ||r||) until the FP64 residual meets tol
+    if (!use_x0) for (int r = 0; r < R; ++r) launch_zero(P64, X64 + size_t(r) * N, N, st);
+    op.b32.ensure(size_t(R) * N * sizeof(z32));
+    op.x32.ensure(size_t(R) * N * sizeof(z32));
+    op.r64.ensure(size_t(R) * N * sizeof(z64));
+    z32* B32 = op.b32.as<z32>();
+    z32* X32 = op.x32.as<z32>();
+    z64* R64 = op.r64.as<z64>();
+    std::vector<int> done(R, 0);
+    std::vector<double> bn(R);
+    for (int r = 0; r < R; ++r) {
+      launch_norm2(P64, B64 + size_t(r) * N, N, op.red(), op.scal.as<double>(), st);
+      DC_HIP(hipMemcpyAsync(&bn[r], op.scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
+      DC_HIP(hipStreamSynchronize(st));
+      bn[r] = std::sqrt(bn[r]);
+      if (bn[r] == 0.0) done[r] = 1;
+    }
+    for (int outer = 0; outer <= o.max_outer; ++outer) {
+      std::vector<int> act;
+      for (int r = 0; r < R; ++r)
+        if (!done[r]) act.push_back(r);
+      if (act.empty()) break;
+      std::vector<const void*> hx, hy;
+      for (int r : act) {
+        hx.push_back(X64 + size_t(r) * N);
+        hy.push_back(R64 + size_t(r) * N);
+      }
+      std::vector<const void*> h(hx);
+      h.insert(h.end(), hy.begin(), hy.end());
+      op.ptrs.ensure(h.size() * sizeof(void*));
+      DC_HIP(hipMemcpyAsync(op.ptrs.p, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+      DC_HIP(hipStreamSynchronize(st));
+      void** tbl = op.ptrs.as<void*>();
+      launch_apply_multi(P64, op.n, op.V, op.blocks(P64), nullptr, const_cast<const void* const*>(tbl),
+                         tbl + act.size(), int(act.size()), op.nbr.as<int>(), sign * op.mu, 0, st);
+      std::vector<int> inner_r;
+      std::vector<double> scale;
+      for (size_t a = 0; a < act.size(); ++a) {
+        const int r = act[a];
+        z64* rr = R64 + size_t(r) * N;
+        launch_scale(P64, rr, rr, N, nullptr, -1.0, nullptr, st);
+        launch_axpy(P64, mk(1.0, 0.0), B64 + size_t(r) * N, rr, N, st);
+        launch_norm2(P64, rr, N, op.red(), op.scal.as<double>(), st);
+        double h2;
+        DC_HIP(hipMemcpyAsync(&h2, op.scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        DC_HIP(hipStreamSynchronize(st));
+        const double rn = std::sqrt(std::max(h2, 0.0));
+        rel[r] = rn / bn[r];
+        if (rel[r] <= tl[r] || outer == o.max_outer) {
+          done[r] = 1;
+          continue;
+        }
+        stt[r].outer_iters += 1;
+        inner_r.push_back(r);
+        scale.push_back(rn);
+        launch_convert_64to32(rr, B32 + size_t(r) * N, N, op.n, 0, st);
+        launch_cscale(P32, B32 + size_t(r) * N, B32 + size_t(r) * N, N, mk(1.0 / rn, 0.0), nullptr, st);
+      }
+      if (inner_r.empty()) break;
+      // inner batched solve on the still-active right-hand sides
+      std::vector<const z32*> bp;
+      std::vector<z32*> xp;
+      std::vector<double> itol;
+      std::vector<SolveStats> ist(inner_r.size());
+      std::vector<double> irel(inner_r.size());
+      for (int r : inner_r) {
+        bp.push_back(B32 + size_t(r) * N);
+        xp.push_back(X32 + size_t(r) * N);
+        itol.push_back(o.inner_tol);
+      }
+      Batch<float> Bi(op, var, o, int(inner_r.size()), st, op.bws, op.bsm);
+      Bi.solve(bp, xp, itol, false, o.max_cycles, ist, irel);
+      for (size_t i = 0; i < inner_r.size(); ++i) {
+        const int r = inner_r[i];
+        stt[r].iters += ist[i].iters;
+        stt[r].cycles += ist[i].cycles;
+        stt[r].matvecs += ist[i].matvecs + 1;
+        launch_convert_32to64(X32 + size_t(r) * N, R64 + size_t(r) * N, N, op.n, 0, st);
+        launch_axpy(P64, mk(scale[i], 0.0), R64 + size_t(r) * N, X64 + size_t(r) * N, N, st);
+      }
+    }
+  }
+  var.kcur = kc_saved;
+  int all_ok = 1;
+  for (int r = 0; r < R; ++r) {
+    const z64* br = static_cast<const z64*>(b) + size_t(r) * N;
+    z64* xr = static_cast<z64*>(x) + size_t(r) * N;
+    if (adjoint) launch_gamma5(P64, X64 + size_t(r) * N, xr, op.V, op.n, st);
+    else DC_HIP(hipMemcpyAsync(xr, X64 + size_t(r) * N, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    stt[r].rel_res_true = fp64_relres(op, xr, br, adjoint, st);
+    stt[r].status = stt[r].rel_res_true <= tol[r] ? 0 : 1;
+    if (stt[r].status) all_ok = 0;
+    stt[r].t_setup_ms = (r == 0) ? t_setup : 0.0;
+    stt[r].t_solve_ms = ms_since(t0);
+    if (stats) stats[r] = stt[r];
   }
   return all_ok ? 0 : 1;
 }

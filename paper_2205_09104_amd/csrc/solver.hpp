@@ -83,6 +83,8 @@ struct Op {
   DevBuf scal;              // a few device doubles
   DevBuf t64a, t64b, t32a, t32b, zouter;  // per-solve vector scratch, kept across calls
   DevBuf ptrs;              // device pointer arrays of the multi-RHS apply
+  std::vector<DevBuf> bws, bsm;            // per right-hand-side workspaces of batched solves
+  DevBuf bx64, bb64, b32, x32, r64;        // batched-solve vectors
   Reducer red() const { return Reducer{redpart.as<double>(), redcnt.as<unsigned>()}; }
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<Variant>> variants;
   size_t N() const { return size_t(V) * n; }
@@ -108,5 +110,7 @@ int op_arnoldi(Op& op, const SolveOpts& o, const void* v, int steps, hipStream_t
 int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, void* x,
              const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
 int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st);
+int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b, void* x,
+                   const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
 
 }  // namespace dc

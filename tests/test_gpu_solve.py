@@ -253,3 +253,44 @@ def test_block_jacobi_solves(c1, cfg):
         xo, io = ogmres(flat(oop), b.numpy().reshape(-1), 1e-10, 30, 5000, left=Bi)
         assert io.converged
         print("iterations gpu", st[0]["iters"], "oracle", io.iters)
+
+
+# ---------------------------------------------------------------- batched solves
+
+@pytest.mark.parametrize("cfg", ["gmres", "poly", "deflated", "f32", "f16s", "bj"])
+def test_batched_solve(c1, cfg):
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, b, xref = c1
+    log("batched", cfg)
+    R = 6
+    B = torch.stack([synth.rhs(w.dims, w.n_tv, 20 + r) for r in range(R)])
+    tols = synth.tolerances_loguniform(R, 1e-10, 1e-6, seed=1)
+    opts = {"gmres": Opts(m=30),
+            "poly": Opts(m=30, d=4, seed=2),
+            "deflated": Opts(m=38, k=8, d=4, seed=2),
+            "f32": Opts(m=30, d=4, prec="f32", outer=1, inner_tol=1e-3, seed=2),
+            "f16s": Opts(m=30, d=4, prec="f16s", outer=1, inner_tol=1e-3, seed=2),
+            "bj": Opts(m=30, d=4, block_jacobi=1, seed=2)}[cfg]
+    if cfg == "deflated":      # build the shared recycle space with one single solve
+        gop.solve(b.cuda(), 1e-10, opts)
+    X, st, rc = gop.solve_batch(B.cuda(), tols, opts)
+    assert rc == 0, st
+    for r in range(R):
+        assert oracle_relres(oop, X[r].cpu().numpy(), B[r].numpy()) <= tols[r]
+        assert st[r]["rel_res_true"] <= tols[r]
+    if cfg in ("gmres", "poly"):
+        # lockstep batching does not change each right-hand side's iteration
+        for r in (0, R - 1):
+            x1, s1, _ = gop.solve(B[r].cuda(), tols[r], opts)
+            assert abs(s1[0]["iters"] - st[r]["iters"]) <= opts.m, (s1[0]["iters"], st[r]["iters"])
+
+
+def test_batched_adjoint():
+    from paper_2205_09104_amd import Opts
+    log("batched adjoint")
+    gop, oop = make_pair((3, 2, 2, 2), 4, 3.2, mu=0.05, store=("f64", "f32"))
+    B = torch.stack([rand_vec(oop.V, oop.n, 90, r) for r in range(3)])
+    X, st, rc = gop.solve_batch(B.cuda(), 1e-11, Opts(m=20, d=4), adjoint=True)
+    assert rc == 0
+    for r in range(3):
+        assert oracle_relres(oop, X[r].cpu().numpy(), B[r].numpy(), adjoint=True) <= 1e-11
