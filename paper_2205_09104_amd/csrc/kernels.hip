@@ -22,12 +22,13 @@ __device__ inline cx<R> ld(const cx<R>* p) {
   return *p;
 }
 
-// Block-wide sum of W doubles per thread (blockDim.x a multiple of 64, <= 1024)
-// followed by the deterministic last-block-done grid reduction into result[0..W).
+// Block-wide sum of W doubles per thread (blockDim.x a multiple of 64, <= 1024),
+// written as this block's partial: partials[w * nblk + block].  A second
+// kernel (k_finalize) sums the partials of each value in a fixed order, so
+// every reduction is deterministic.
 template <int W>
-__device__ void grid_reduce(double (&v)[W], Reducer red, double* result) {
+__device__ void block_partials(double (&v)[W], double* partials) {
   __shared__ double sh[16][W];
-  __shared__ bool last;
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
 #pragma unroll
@@ -43,24 +44,21 @@ __device__ void grid_reduce(double (&v)[W], Reducer red, double* result) {
   if (threadIdx.x < W) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += sh[w][threadIdx.x];
-    red.partials[size_t(bid) * W + threadIdx.x] = s;
+    partials[size_t(threadIdx.x) * nblk + bid] = s;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(red.counter, 1u);
-    last = (prev == unsigned(nblk - 1));
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    for (int t = threadIdx.x; t < W; t += blockDim.x) {
-      double s = 0.0;
-      for (int b = 0; b < nblk; ++b) s += __builtin_nontemporal_load(&red.partials[size_t(b) * W + t]);
-      result[t] = s;
-    }
-    if (threadIdx.x == 0) *red.counter = 0u;
-  }
+}
+
+// result[v] = sum_b partials[v * nparts + b]; one 64-lane wave per value.
+__global__ __launch_bounds__(64) void k_finalize(const double* __restrict__ partials, int nparts,
+                                                 double* __restrict__ result,
+                                                 const int* __restrict__ done) {
+  if (done && *done) return;
+  const int v = blockIdx.x;
+  double s = 0.0;
+  for (int b = threadIdx.x; b < nparts; b += 64) s += partials[size_t(v) * nparts + b];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += shfl_xor(s, o);
+  if (threadIdx.x == 0) result[v] = s;
 }
 
 // ------------------------------------------------------------------ layout
@@ -983,49 +981,80 @@ __global__ void k_gather_resid(const cx<VR>* __restrict__ gbuf, const cx<VR>* __
     out[i] = r;
     acc[0] += double(r.re) * double(r.re) + double(r.im) * double(r.im);
   }
-  grid_reduce<1>(acc, red, result);
+  block_partials<1>(acc, red.partials);
 }
 
 // ------------------------------------------------------------------ BLAS
-constexpr int kQG = 16;  // dot products per workgroup group
+// Dot products and updates against a basis of Q vectors.  Each thread takes
+// E elements per pass and issues the loads of all G basis vectors of a chunk
+// before any arithmetic, so 2*G*E independent loads are in flight per lane
+// (a load-use-load chain would leave one).  Accumulation is in FP64.
+constexpr int kDotE = 2;     // elements per thread per pass
+constexpr int kAxpyG = 16;   // basis vectors per chunk of the update kernel
 
 template <typename VR>
+__device__ inline const cx<VR>* basis_ptr(const cx<VR>* b0, int q0, const cx<VR>* b1, size_t N,
+                                          int q) {
+  return q < q0 ? b0 + size_t(q) * N : b1 + size_t(q - q0) * N;
+}
+
+// result value v = blockIdx.y * 2G + t of the group; t = 2*(q - g0) + re/im
+template <typename VR, int G>
 __global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0, int q0,
                                                   const cx<VR>* __restrict__ b1, int q1,
                                                   size_t N, const cx<VR>* __restrict__ w,
-                                                  int want_norm, Reducer red, double* result,
+                                                  int want_norm, Reducer red,
                                                   const int* __restrict__ done) {
   if (done && *done) return;
-  const int Q = q0 + q1 + (want_norm ? 1 : 0);
-  const int g0 = blockIdx.y * kQG;
-  double acc[2 * kQG];
+  const int Qb = q0 + q1;
+  const int g0 = blockIdx.y * G;
+  const cx<VR>* ptr[G];
 #pragma unroll
-  for (int t = 0; t < 2 * kQG; ++t) acc[t] = 0.0;
-  const size_t stride = size_t(gridDim.x) * blockDim.x;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
-    const cx<VR> wv = w[i];
-    const double wr = wv.re, wi = wv.im;
-#pragma unroll
-    for (int t = 0; t < kQG; ++t) {
-      const int q = g0 + t;
-      if (q < Q) {
-        cx<VR> v;
-        if (q < q0) v = b0[size_t(q) * N + i];
-        else if (q < q0 + q1) v = b1[size_t(q - q0) * N + i];
-        else v = wv;
-        const double vr = v.re, vi = v.im;
-        acc[2 * t] += vr * wr + vi * wi;      // conj(v) * w
-        acc[2 * t + 1] += vr * wi - vi * wr;
-      }
-    }
+  for (int t = 0; t < G; ++t) {
+    const int q = g0 + t;
+    ptr[t] = q < Qb ? basis_ptr(b0, q0, b1, N, q) : w;  // past the basis: w itself (the norm)
   }
-  // reduce: one grid reduction across all (x, y) blocks of 2*kQG values each;
-  // block (x, y) stores its group's values, the last block sums per group.
-  __shared__ double sh[4][2 * kQG];
-  __shared__ bool last;
+  double acc[2 * G];
+#pragma unroll
+  for (int t = 0; t < 2 * G; ++t) acc[t] = 0.0;
+  const size_t chunk = size_t(blockDim.x) * kDotE;
+  const size_t stride = size_t(gridDim.x) * chunk;
+  for (size_t base = size_t(blockIdx.x) * chunk + threadIdx.x; base < N; base += stride) {
+    size_t idx[kDotE];
+    double wr[kDotE], wi[kDotE];
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+      const size_t i = base + size_t(e) * blockDim.x;
+      idx[e] = i < N ? i : N - 1;
+    }
+    cx<VR> v[G][kDotE], wv[kDotE];
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) wv[e] = w[idx[e]];
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+#pragma unroll
+      for (int e = 0; e < kDotE; ++e) v[t][e] = ptr[t][idx[e]];
+    __builtin_amdgcn_sched_barrier(0);  // keep every load ahead of the arithmetic
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+      const bool ok = base + size_t(e) * blockDim.x < N;
+      wr[e] = ok ? double(wv[e].re) : 0.0;
+      wi[e] = ok ? double(wv[e].im) : 0.0;
+    }
+#pragma unroll
+    for (int t = 0; t < G; ++t)
+#pragma unroll
+      for (int e = 0; e < kDotE; ++e) {
+        const double vr = v[t][e].re, vi = v[t][e].im;
+        acc[2 * t] = fma(vr, wr[e], fma(vi, wi[e], acc[2 * t]));        // Re conj(v) w
+        acc[2 * t + 1] = fma(vr, wi[e], fma(-vi, wr[e], acc[2 * t + 1]));  // Im conj(v) w
+      }
+  }
+  (void)want_norm;
+  __shared__ double sh[4][2 * G];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-  for (int t = 0; t < 2 * kQG; ++t) {
+  for (int t = 0; t < 2 * G; ++t) {
     double s = acc[t];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += shfl_xor(s, o);
@@ -1033,30 +1062,10 @@ __global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0,
   }
   __syncthreads();
   const int gx = gridDim.x;
-  if (threadIdx.x < 2 * kQG) {
+  if (threadIdx.x < 2 * G) {
     double s = 0.0;
-    for (int wv = 0; wv < int(blockDim.x >> 6); ++wv) s += sh[wv][threadIdx.x];
-    red.partials[(size_t(blockIdx.y) * gx + blockIdx.x) * (2 * kQG) + threadIdx.x] = s;
-  }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(red.counter, 1u);
-    last = (prev == unsigned(gx * gridDim.y - 1));
-  }
-  __syncthreads();
-  if (last) {
-    __threadfence();
-    for (int t = threadIdx.x; t < int(gridDim.y) * 2 * kQG; t += blockDim.x) {
-      const int gy = t / (2 * kQG), c = t % (2 * kQG);
-      const int q = gy * kQG + c / 2;
-      if (q >= Q) continue;
-      double s = 0.0;
-      for (int bx = 0; bx < gx; ++bx)
-        s += __builtin_nontemporal_load(&red.partials[(size_t(gy) * gx + bx) * (2 * kQG) + c]);
-      result[2 * q + (c & 1)] = s;
-    }
-    if (threadIdx.x == 0) *red.counter = 0u;
+    for (int wv2 = 0; wv2 < int(blockDim.x >> 6); ++wv2) s += sh[wv2][threadIdx.x];
+    red.partials[(size_t(blockIdx.y) * 2 * G + threadIdx.x) * gx + blockIdx.x] = s;
   }
 }
 
@@ -1065,25 +1074,56 @@ __global__ __launch_bounds__(256) void k_multiaxpy(cx<VR>* __restrict__ w,
                                                    const cx<VR>* __restrict__ b0, int q0,
                                                    const cx<VR>* __restrict__ b1, int q1,
                                                    size_t N, const double* __restrict__ coef,
-                                                   int want_norm, Reducer red, double* result,
+                                                   int want_norm, Reducer red,
                                                    const int* __restrict__ done) {
   if (done && *done) return;
+  const int Q = q0 + q1;
   double nacc[1] = {0.0};
-  const size_t stride = size_t(gridDim.x) * blockDim.x;
-  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
-    const cx<VR> wv = w[i];
-    double sr = wv.re, si = wv.im;
-    for (int q = 0; q < q0 + q1; ++q) {
-      const cx<VR> v = (q < q0) ? b0[size_t(q) * N + i] : b1[size_t(q - q0) * N + i];
-      const double cr = coef[2 * q], ci = coef[2 * q + 1];
-      sr -= cr * double(v.re) - ci * double(v.im);
-      si -= cr * double(v.im) + ci * double(v.re);
+  const size_t chunk = size_t(blockDim.x) * kDotE;
+  const size_t stride = size_t(gridDim.x) * chunk;
+  for (size_t base = size_t(blockIdx.x) * chunk + threadIdx.x; base < N; base += stride) {
+    size_t idx[kDotE];
+    double sr[kDotE], si[kDotE];
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+      const size_t i = base + size_t(e) * blockDim.x;
+      idx[e] = i < N ? i : N - 1;
+      const cx<VR> wv = w[idx[e]];
+      sr[e] = wv.re;
+      si[e] = wv.im;
     }
-    const cx<VR> o = mk(VR(sr), VR(si));
-    w[i] = o;
-    nacc[0] += double(o.re) * double(o.re) + double(o.im) * double(o.im);
+    for (int qc = 0; qc < Q; qc += kAxpyG) {
+      cx<VR> v[kAxpyG][kDotE];
+#pragma unroll
+      for (int t = 0; t < kAxpyG; ++t) {
+        const int q = min(qc + t, Q - 1);
+        const cx<VR>* p = basis_ptr(b0, q0, b1, N, q);
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) v[t][e] = p[idx[e]];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < kAxpyG; ++t) {
+        const int q = qc + t;
+        const double cr = q < Q ? coef[2 * q] : 0.0, ci = q < Q ? coef[2 * q + 1] : 0.0;
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) {
+          const double vr = v[t][e].re, vi = v[t][e].im;
+          sr[e] = fma(-cr, vr, fma(ci, vi, sr[e]));
+          si[e] = fma(-cr, vi, fma(-ci, vr, si[e]));
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+      if (base + size_t(e) * blockDim.x < N) {
+        const cx<VR> o = mk(VR(sr[e]), VR(si[e]));
+        w[idx[e]] = o;
+        nacc[0] += double(o.re) * double(o.re) + double(o.im) * double(o.im);
+      }
+    }
   }
-  if (want_norm) grid_reduce<1>(nacc, red, result);
+  if (want_norm) block_partials<1>(nacc, red.partials);
 }
 
 constexpr int kCombR = 16;  // outputs per pass of the combine kernel
@@ -1185,14 +1225,17 @@ __global__ void k_axpy(z64 a, const cx<VR>* __restrict__ x, cx<VR>* __restrict__
 }
 
 template <typename VR>
-__global__ void k_norm2(const cx<VR>* __restrict__ x, size_t N, Reducer red, double* result) {
+__global__ __launch_bounds__(256) void k_norm2(const cx<VR>* __restrict__ x, size_t N,
+                                               Reducer red) {
+  // column blockIdx.y of [q][N]; partial of block (bx, by) at by * gx + bx
+  const cx<VR>* col = x + size_t(blockIdx.y) * N;
   double acc[1] = {0.0};
   const size_t stride = size_t(gridDim.x) * blockDim.x;
   for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
-    const cx<VR> z = x[i];
+    const cx<VR> z = col[i];
     acc[0] += double(z.re) * double(z.re) + double(z.im) * double(z.im);
   }
-  grid_reduce<1>(acc, red, result);
+  block_partials<1>(acc, red.partials);
 }
 
 template <typename VR>
@@ -1603,10 +1646,27 @@ void launch_gather_poly_first(Prec p, int n, int V, const void* gbuf, const void
   DC_HIP(hipGetLastError());
 }
 
+// blocks of a single-value reduction over N elements: >= 4 elements per
+// thread, at most 512 partials
+static unsigned red_blocks(size_t N) {
+  size_t b = (N + 1023) / 1024;
+  if (b < 1) b = 1;
+  if (b > 512) b = 512;
+  return unsigned(b);
+}
+
+static void finalize(const double* partials, int nvals, int nparts, double* result,
+                     const int* done, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(unsigned(nvals)), dim3(64), 0, st, partials, nparts, result,
+                     done);
+  DC_HIP(hipGetLastError());
+}
+
 void launch_gather_resid(Prec p, int n, int V, const void* gbuf, const void* b, void* out,
                          Reducer red, double* result, hipStream_t st) {
   const size_t N = size_t(V) * n;
-  const dim3 grid(grid_for(N, 256, kMaxRedBlocks)), block(256);
+  const unsigned nb = red_blocks(N);
+  const dim3 grid(nb), block(256);
   if (p == P64)
     hipLaunchKernelGGL(k_gather_resid<double>, grid, block, 0, st, static_cast<const z64*>(gbuf),
                        static_cast<const z64*>(b), static_cast<z64*>(out), N, n, red, result);
@@ -1614,17 +1674,42 @@ void launch_gather_resid(Prec p, int n, int V, const void* gbuf, const void* b, 
     hipLaunchKernelGGL(k_gather_resid<float>, grid, block, 0, st, static_cast<const z32*>(gbuf),
                        static_cast<const z32*>(b), static_cast<z32*>(out), N, n, red, result);
   DC_HIP(hipGetLastError());
+  finalize(red.partials, 1, int(nb), result, nullptr, st);
 }
 
-static unsigned dot_blocks(size_t N, int groups) {
-  // aim for ~4 waves of 256 threads per CU over all groups, each thread >= 4 elements
-  size_t want = 1024 / size_t(groups > 0 ? groups : 1);
-  if (want < 16) want = 16;
-  size_t bymem = (N + 1023) / 1024;
-  size_t b = want < bymem ? want : bymem;
+// blocks per dot group: about one pass per thread, bounded by the partials
+// capacity over all groups and values
+static unsigned dot_blocks(size_t N, int values) {
+  size_t b = (N + 256 * kDotE - 1) / (256 * kDotE);
+  const size_t cap = size_t(kRedCap) / size_t(values > 0 ? values : 1);
+  if (b > cap) b = cap;
+  if (b > 1024) b = 1024;
   if (b < 1) b = 1;
-  if (b * size_t(groups) > size_t(kMaxRedBlocks)) b = size_t(kMaxRedBlocks) / size_t(groups);
   return unsigned(b);
+}
+
+template <typename VR, int G>
+static void multidot_g(const void* b0, int q0, const void* b1, int q1, size_t N, const void* w,
+                       int want_norm, Reducer red, const int* done, int Q, hipStream_t st,
+                       unsigned* gx_out) {
+  const int gy = (Q + G - 1) / G;
+  const unsigned gx = dot_blocks(N, gy * 2 * G);
+  hipLaunchKernelGGL((k_multidot<VR, G>), dim3(gx, unsigned(gy)), dim3(256), 0, st,
+                     static_cast<const cx<VR>*>(b0), q0, static_cast<const cx<VR>*>(b1), q1, N,
+                     static_cast<const cx<VR>*>(w), want_norm, red, done);
+  *gx_out = gx;
+}
+
+template <typename VR>
+static unsigned multidot_t(const void* b0, int q0, const void* b1, int q1, size_t N,
+                           const void* w, int want_norm, Reducer red, const int* done, int Q,
+                           hipStream_t st) {
+  unsigned gx = 0;
+  if (Q <= 2) multidot_g<VR, 2>(b0, q0, b1, q1, N, w, want_norm, red, done, Q, st, &gx);
+  else if (Q <= 4) multidot_g<VR, 4>(b0, q0, b1, q1, N, w, want_norm, red, done, Q, st, &gx);
+  else if (Q <= 8) multidot_g<VR, 8>(b0, q0, b1, q1, N, w, want_norm, red, done, Q, st, &gx);
+  else multidot_g<VR, 16>(b0, q0, b1, q1, N, w, want_norm, red, done, Q, st, &gx);
+  return gx;
 }
 
 void launch_multidot(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
@@ -1632,32 +1717,31 @@ void launch_multidot(Prec p, const void* b0, int q0, const void* b1, int q1, siz
                      hipStream_t st) {
   const int Q = q0 + q1 + (want_norm ? 1 : 0);
   if (Q == 0) return;
-  const int gy = (Q + kQG - 1) / kQG;
-  const dim3 grid(dot_blocks(N, gy), unsigned(gy)), block(256);
-  if (p == P64)
-    hipLaunchKernelGGL(k_multidot<double>, grid, block, 0, st, static_cast<const z64*>(b0), q0,
-                       static_cast<const z64*>(b1), q1, N, static_cast<const z64*>(w), want_norm,
-                       red, result, done);
-  else
-    hipLaunchKernelGGL(k_multidot<float>, grid, block, 0, st, static_cast<const z32*>(b0), q0,
-                       static_cast<const z32*>(b1), q1, N, static_cast<const z32*>(w), want_norm,
-                       red, result, done);
+  const unsigned gx = p == P64 ? multidot_t<double>(b0, q0, b1, q1, N, w, want_norm, red, done, Q, st)
+                               : multidot_t<float>(b0, q0, b1, q1, N, w, want_norm, red, done, Q, st);
   DC_HIP(hipGetLastError());
+  // value v of the launch is result v (value = group * 2G + 2*(q - g0) + re/im = 2q + re/im)
+  finalize(red.partials, 2 * Q, int(gx), result, done, st);
 }
 
 void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, int q1, size_t N,
                       const double* coef, int want_norm, Reducer red, double* result,
                       const int* done, hipStream_t st) {
-  const dim3 grid(grid_for(N, 256, kMaxRedBlocks)), block(256);
+  if (q0 + q1 == 0 && !want_norm) return;
+  size_t nb = (N + 256 * kDotE - 1) / (256 * kDotE);
+  if (nb > 2048) nb = 2048;
+  if (nb < 1) nb = 1;
+  const dim3 grid{static_cast<unsigned>(nb)}, block{256};
   if (p == P64)
     hipLaunchKernelGGL(k_multiaxpy<double>, grid, block, 0, st, static_cast<z64*>(w),
                        static_cast<const z64*>(b0), q0, static_cast<const z64*>(b1), q1, N, coef,
-                       want_norm, red, result, done);
+                       want_norm, red, done);
   else
     hipLaunchKernelGGL(k_multiaxpy<float>, grid, block, 0, st, static_cast<z32*>(w),
                        static_cast<const z32*>(b0), q0, static_cast<const z32*>(b1), q1, N, coef,
-                       want_norm, red, result, done);
+                       want_norm, red, done);
   DC_HIP(hipGetLastError());
+  if (want_norm) finalize(red.partials, 1, int(nb), result, done, st);
 }
 
 void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
@@ -1732,15 +1816,23 @@ void launch_axpy(Prec p, z64 a, const void* x, void* y, size_t N, hipStream_t st
   DC_HIP(hipGetLastError());
 }
 
-void launch_norm2(Prec p, const void* x, size_t N, Reducer red, double* result, hipStream_t st) {
-  const dim3 grid(grid_for(N, 256, kMaxRedBlocks)), block(256);
+void launch_colnorm2(Prec p, const void* x, int q, size_t N, Reducer red, double* result,
+                     hipStream_t st) {
+  if (q <= 0) return;
+  unsigned nb = red_blocks(N);
+  const unsigned cap = unsigned(size_t(kRedCap) / size_t(q));
+  if (nb > cap) nb = cap;
+  const dim3 grid(nb, unsigned(q)), block(256);
   if (p == P64)
-    hipLaunchKernelGGL(k_norm2<double>, grid, block, 0, st, static_cast<const z64*>(x), N, red,
-                       result);
+    hipLaunchKernelGGL(k_norm2<double>, grid, block, 0, st, static_cast<const z64*>(x), N, red);
   else
-    hipLaunchKernelGGL(k_norm2<float>, grid, block, 0, st, static_cast<const z32*>(x), N, red,
-                       result);
+    hipLaunchKernelGGL(k_norm2<float>, grid, block, 0, st, static_cast<const z32*>(x), N, red);
   DC_HIP(hipGetLastError());
+  finalize(red.partials, q, int(nb), result, nullptr, st);
+}
+
+void launch_norm2(Prec p, const void* x, size_t N, Reducer red, double* result, hipStream_t st) {
+  launch_colnorm2(p, x, 1, N, red, result, st);
 }
 
 void launch_gamma5(Prec p, const void* in, void* out, int V, int n, hipStream_t st) {

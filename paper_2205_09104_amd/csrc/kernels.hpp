@@ -7,14 +7,13 @@
 
 namespace dc {
 
-// Deterministic grid reduction scratch: per-block partial sums plus a counter
-// that the last block to finish uses to sum the partials in block order.
+// Deterministic two-stage reduction scratch: each block of a reduction kernel
+// stores its partial sums value-major, a one-wave-per-value finalize kernel
+// sums them in a fixed order (results do not depend on block scheduling).
 struct Reducer {
-  double* partials = nullptr;   // capacity: kMaxRedBlocks * kRedWidth doubles
-  unsigned* counter = nullptr;  // zero between launches
+  double* partials = nullptr;   // capacity: kRedCap doubles
 };
-constexpr int kMaxRedBlocks = 1024;
-constexpr int kRedWidth = 32;  // doubles per block (16 complex dots)
+constexpr int kRedCap = 65536;
 
 // ---------------------------------------------------------------- operator
 // Re-lay out FP64 input blocks (self [V][n][n] + hops [V][4][n][n], device,
@@ -113,6 +112,9 @@ void launch_zero(Prec p, void* x, size_t N, hipStream_t st);
 void launch_axpy(Prec p, z64 a, const void* x, void* y, size_t N, hipStream_t st);
 // result[0] = ||x||^2
 void launch_norm2(Prec p, const void* x, size_t N, Reducer red, double* result, hipStream_t st);
+// result[i] = ||x_i||^2 for the q vectors x_i = x + i*N (q <= kRedCap)
+void launch_colnorm2(Prec p, const void* x, int q, size_t N, Reducer red, double* result,
+                     hipStream_t st);
 // out = Gamma5 in (per-site sign); in == out allowed
 void launch_gamma5(Prec p, const void* in, void* out, int V, int n, hipStream_t st);
 // precision conversions (with optional Gamma5): out = g5? * in

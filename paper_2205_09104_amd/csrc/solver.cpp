@@ -105,9 +105,7 @@ void op_build(Op& op, const int dims[4], int n_tv, int store, double mu, const v
   }
   op.gbuf64.alloc(size_t(op.V) * 9 * op.n * sizeof(z64));
   if (op.store & 6) op.gbuf32.alloc(size_t(op.V) * 9 * op.n * sizeof(z32));
-  op.redpart.alloc(size_t(kMaxRedBlocks) * kRedWidth * sizeof(double));
-  op.redcnt.alloc(256);
-  DC_HIP(hipMemsetAsync(op.redcnt.p, 0, 256, st));
+  op.redpart.alloc(size_t(kRedCap) * sizeof(double));
   op.scal.alloc(256);
   copy_blocks_in(op, self_blocks, hop_blocks, on_device, st);
 }
@@ -454,7 +452,12 @@ struct Krylov {
 
   void refresh_unorm() {
     var.unorm.assign(var.kcur, 1.0);
-    for (int i = 0; i < var.kcur; ++i) var.unorm[i] = norm(Uv() + size_t(i) * N);
+    if (var.kcur == 0) return;
+    launch_colnorm2(p, Uv(), var.kcur, N, op.red(), res1, st);  // res1 holds >= kmax doubles
+    DC_HIP(hipMemcpyAsync(var.unorm.data(), res1, sizeof(double) * size_t(var.kcur),
+                          hipMemcpyDeviceToHost, st));
+    DC_HIP(hipStreamSynchronize(st));
+    for (double& u : var.unorm) u = std::sqrt(std::max(u, 0.0));
   }
 
   // New recycle space from an (unpreconditioned-residual) GMRES cycle:

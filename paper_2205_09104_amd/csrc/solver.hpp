@@ -79,13 +79,13 @@ struct Op {
   } bj[2];
   const BJ& ensure_bj(int sign, hipStream_t st);
   DevBuf gbuf64, gbuf32;
-  DevBuf redpart, redcnt;   // reducer scratch
+  DevBuf redpart;           // reducer scratch
   DevBuf scal;              // a few device doubles
   DevBuf t64a, t64b, t32a, t32b, zouter;  // per-solve vector scratch, kept across calls
   DevBuf ptrs;              // device pointer arrays of the multi-RHS apply
   std::vector<DevBuf> bws, bsm;            // per right-hand-side workspaces of batched solves
   DevBuf bx64, bb64, b32, x32, r64;        // batched-solve vectors
-  Reducer red() const { return Reducer{redpart.as<double>(), redcnt.as<unsigned>()}; }
+  Reducer red() const { return Reducer{redpart.as<double>()}; }
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<Variant>> variants;
   size_t N() const { return size_t(V) * n; }
   Variant& variant(Prec p, int sign, int bj, int d);
