@@ -1,14 +1,16 @@
 """Benchmark: coarse solves/s to relative residual 1e-8 on one MI355X.
 
 Workload: the synthetic 8^4 coarse operator with N_tv = 24 (196,608 unknowns,
-clover-Wilson type, min Re(eig) = 1e-4 * max|eig|), seeded right-hand sides.
+clover-Wilson type, m0 from the limiting spectral disk with min Re / max|.| =
+1e-4), seeded right-hand sides.
 A step is one complete coarse solve of a fresh right-hand side with the
 method's solver: polynomial preconditioning (d Leja-ordered harmonic Ritz
 values) + GCRO-DR deflation/recycling (k vectors), reduced-precision inner
 solve inside an FP64 flexible-GMRES outer loop; the FP64 true residual of
-every solve is checked.  Plain FP64 GMRES(30) is timed on the same operator
-and right-hand sides for comparison.  The D_c apply roofline is measured with
-HIP events around back-to-back applies on the library's stream.
+every solve is checked.  Plain FP64 GMRES(30) is run on the same operator and
+right-hand sides for comparison (capped: on this operator it can stagnate).
+The roofline entry is the apply's block kernel timed live in the timed solves
+with HIP events on the library's launch stream.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -30,20 +32,24 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=4)
+    p.add_argument("--steps", type=int, default=10)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="c2")
     p.add_argument("--tol", type=float, default=1e-8)
     p.add_argument("--inner", default="f16s", choices=["f32", "f16s"])
-    p.add_argument("--d", type=int, default=8)
+    p.add_argument("--d", type=int, default=24)
     p.add_argument("--k", type=int, default=32)
     p.add_argument("--m", type=int, default=30, help="new Arnoldi vectors per cycle")
-    p.add_argument("--inner-tol", type=float, default=1e-4)
+    p.add_argument("--inner-tol", type=float, default=1e-1)
     p.add_argument("--plain-steps", type=int, default=1)
-    p.add_argument("--plain-max-cycles", type=int, default=100000)
+    p.add_argument("--plain-max-cycles", type=int, default=400,
+                   help="restart cycles of the plain GMRES(30) comparison (it may stagnate)")
     p.add_argument("--apply-reps", type=int, default=50)
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=20.0)
+    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
+                   help="only run a plain elementwise copy of this many MiB (read + write), "
+                        "the reference for scaling HBM byte counters")
     return p.parse_args()
 
 
@@ -52,10 +58,54 @@ def log(*a):
 
 
 def apply_bytes(V, n, prec):
+    """Algorithmic bytes of one D_c apply: the 5 stored blocks per site (plus
+    their FP16 scales), one read of the input and one write of the output."""
     sb = {"f64": 16, "f32": 8, "f16s": 4}[prec]
     sv = 16 if prec == "f64" else 8
     extra = 5 * 4 if prec == "f16s" else 0
     return V * (5 * n * n * sb + 2 * n * sv + extra)
+
+
+def stage1_bytes(V, n, prec):
+    """Algorithmic bytes of the apply's block kernel: the stored blocks (and
+    scales) plus one read of the input vector; its per-coupling partial
+    products are an intermediate of this design, not counted."""
+    sb = {"f64": 16, "f32": 8, "f16s": 4}[prec]
+    sv = 16 if prec == "f64" else 8
+    extra = 5 * 4 if prec == "f16s" else 0
+    return V * (5 * n * n * sb + n * sv + extra)
+
+
+# HBM traffic of one launch of the f16s block kernel on the 8^4, N_tv = 24
+# workload: rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch,
+# median over the launches that did work), each scaled by the ratio of true
+# bytes to counter reading for a plain 1 GiB elementwise copy (--copy-probe
+# 1024: FETCH_SIZE 524300 KiB for 1 GiB read, WRITE_SIZE 1048576 KiB for 1 GiB
+# written).  Valid only for the apply source it was taken on.
+TRAFFIC = {"workload": "c2", "prec": "f16s",
+           "fetch_kib": 94006.06, "fetch_scale": 1048576.0 / 524300.0,
+           "write_kib": 13824.0, "write_scale": 1048576.0 / 1048576.0,
+           "apply_source_sha256": "4ad78bf68862fbf112a58afb3ce8cb7b738d2824c562da0e9a33f8c64732a804"}
+
+
+def apply_source_digest():
+    """sha256 of the apply section (block and gather kernels) of the HIP source."""
+    import hashlib
+    import re
+    src = open(os.path.join(ROOT, "paper_2205_09104_amd", "csrc", "kernels.hip")).read()
+    a = re.search(r"^// -+ apply$", src, re.M).start()
+    b = re.search(r"^// -+ block Jacobi$", src, re.M).start()
+    return hashlib.sha256(src[a:b].encode()).hexdigest()
+
+
+def measured_traffic(workload, prec):
+    t = TRAFFIC
+    if workload != t["workload"] or prec != t["prec"] or apply_source_digest() != t["apply_source_sha256"]:
+        return None, None
+    fetch = t["fetch_kib"] * 1024 * t["fetch_scale"]
+    write = t["write_kib"] * 1024 * t["write_scale"]
+    return fetch + write, {"fetch_bytes": fetch, "write_bytes": write,
+                           "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"]}
 
 
 def main():
@@ -64,8 +114,11 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU sharding is a design only)"}))
         sys.exit(2)
-    import numpy as np
     import torch
+
+    if a.copy_probe:
+        copy_probe(a.copy_probe)
+        return
 
     import synth
     from paper_2205_09104_amd import CoarseOp, Opts
@@ -80,9 +133,16 @@ def main():
     del A, B
     torch.cuda.synchronize()
     log(f"operator built in {time.time() - t0:.1f}s")
+    # the library launches on torch's current stream (the HIP null stream here)
     stream = torch.cuda.current_stream()
+    # HIP events around every launch of the apply's block kernel, from here on
+    op.profile_apply(True)
 
-    # ---------------------------------------------------------------- roofline
+    def prof_totals():
+        return {p: (op.profile_apply_read(p), op.profile_apply_read(p, include_noops=True))
+                for p in ("f64", "f32", "f16s")}
+
+    # ------------------------------------------------ back-to-back apply rates
     def apply_rate(prec):
         x = synth.rhs(w.dims, w.n_tv, 999, device="cuda")
         x = x if prec == "f64" else x.to(torch.complex64)
@@ -98,14 +158,13 @@ def main():
         ev1.record(stream)
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / a.apply_reps
-        gbs = apply_bytes(V, n, prec) / (ms * 1e-3) / 1e9
-        return ms, gbs
+        return ms, apply_bytes(V, n, prec) / (ms * 1e-3) / 1e9
 
     rates = {p: apply_rate(p) for p in ("f64", "f32", "f16s")}
     for p, (ms, gbs) in rates.items():
-        log(f"apply {p}: {ms * 1e3:.1f} us, {gbs:.0f} GB/s algorithmic")
+        log(f"apply {p} (both stages, back to back): {ms * 1e3:.1f} us, {gbs:.0f} GB/s algorithmic")
 
-    # ---------------------------------------------------------------- method solve
+    # ------------------------------------------------ method solve (timed)
     opts = Opts(m=a.m + a.k, k=a.k, d=a.d, u=10, prec=a.inner, outer=1, m_outer=10,
                 max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000)
 
@@ -118,47 +177,73 @@ def main():
     for r in range(a.warmup):
         x, st, rc = one_solve(r, opts)
         setup_ms += st["t_setup_ms"]
-        log(f"warmup solve {r}: rc {rc} {st}")
+        log(f"warmup solve {r}: rc {rc} relres {st['rel_res_true']:.2e} iters {st['iters']} "
+            f"matvecs {st['matvecs']} setup {st['t_setup_ms']:.0f} ms")
+    rhs = [synth.rhs(w.dims, w.n_tv, r, device="cuda") for r in range(a.warmup, a.warmup + a.steps)]
     torch.cuda.synchronize()
+    pre = prof_totals()
     t0 = time.perf_counter()
     stats = []
-    for r in range(a.warmup, a.warmup + a.steps):
-        x, st, rc = one_solve(r, opts)
-        stats.append(st)
-        log(f"timed solve {r}: rc {rc} relres {st['rel_res_true']:.2e} iters {st['iters']} "
-            f"matvecs {st['matvecs']} outer {st['outer_iters']} {st['t_solve_ms']:.0f} ms")
+    for b in rhs:
+        x, st, rc = op.solve(b, a.tol, opts)
+        stats.append(st[0])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    x_last = x
+    post = prof_totals()
+    # timed-region block-kernel launches that did work: (count, ms) per precision
+    prof = {p: (post[p][0][0] - pre[p][0][0], post[p][0][1] - pre[p][0][1]) for p in post}
+    for i, st in enumerate(stats):
+        log(f"timed solve {i}: status {st['status']} relres {st['rel_res_true']:.2e} "
+            f"iters {st['iters']} matvecs {st['matvecs']} outer {st['outer_iters']} "
+            f"{st['t_solve_ms']:.0f} ms")
     ok = all(s["status"] == 0 and s["rel_res_true"] <= a.tol for s in stats)
     value = a.steps / dt if ok else 0.0
 
-    # ---------------------------------------------------------------- plain FP64 GMRES(30)
-    plain = {"solves_per_s": None}
+    # ------------------------------------------------ FP64 comparisons (one RHS each)
+    # GMRES(30) plain, with the polynomial preconditioner (d = 4, 8, 16), and
+    # with polynomial + deflation; each capped near 12000 matvecs since the
+    # plain and polynomial-only variants can stagnate on this operator.
+    comp = {}
     if a.plain_steps > 0:
-        po = Opts(m=30, prec="f64", max_cycles=a.plain_max_cycles)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        pst = []
-        for r in range(a.warmup, a.warmup + a.plain_steps):
-            x, st, rc = one_solve(r, po)
-            pst.append(st)
-            log(f"plain solve {r}: rc {rc} relres {st['rel_res_true']:.2e} iters {st['iters']} "
-                f"{st['t_solve_ms']:.0f} ms")
-        torch.cuda.synchronize()
-        pdt = time.perf_counter() - t1
-        pok = all(s["status"] == 0 for s in pst)
-        plain = {"solves_per_s": (a.plain_steps / pdt) if pok else None,
-                 "converged": pok, "iters": [s["iters"] for s in pst],
-                 "rel_res_true": [s["rel_res_true"] for s in pst],
-                 "ms_per_solve": 1e3 * pdt / a.plain_steps}
+        cases = [("gmres30", Opts(m=30, prec="f64", max_cycles=a.plain_max_cycles))]
+        for d in (4, 8, 16):
+            cases.append((f"gmres30_poly_d{d}",
+                          Opts(m=30, d=d, prec="f64", seed=1,
+                               max_cycles=max(1, 12000 // (30 * d)))))
+        cases.append(("gmres_poly_d16_defl_k32",
+                      Opts(m=62, k=32, d=16, prec="f64", seed=1, max_cycles=400)))
+        r = a.warmup
+        for name, o in cases:
+            if o.k > 0:
+                one_solve(r + 1, o)           # setup solve: builds the recycle space
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, st, rc = one_solve(r, o)
+            torch.cuda.synchronize()
+            pdt = time.perf_counter() - t1
+            conv = st["status"] == 0
+            comp[name] = {"solves_per_s": (1.0 / pdt) if conv else 0.0, "converged": conv,
+                          "iters": st["iters"], "matvecs": st["matvecs"],
+                          "rel_res_true": st["rel_res_true"], "ms": 1e3 * pdt}
+            log(f"fp64 {name}: status {st['status']} relres {st['rel_res_true']:.2e} "
+                f"iters {st['iters']} matvecs {st['matvecs']} {1e3 * pdt:.0f} ms")
+    plain = comp.get("gmres30", {"solves_per_s": None})
 
-    # ---------------------------------------------------------------- CPU oracle baseline
+    whole = prof_totals()     # the whole run so far, for comparison with a kernel tracer
+    op.profile_apply(False)
+
+    # ------------------------------------------------ CPU oracle baseline
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(w, a, plain)
+        cpu = cpu_baseline(w, a, stats, x_check=(x_last, rhs[-1]))
 
     inner = a.inner
-    ms_ap, gbs = rates[inner]
+    launches, tot_ms = prof[inner]
+    avg_us = 1e3 * tot_ms / max(launches, 1)
+    s1b = stage1_bytes(V, n, inner)
+    achieved = s1b / (avg_us * 1e-6) / 1e9 if launches else None
+    traffic, traffic_detail = measured_traffic(w.name, inner)
     line = {
         "metric": METRIC,
         "value": value,
@@ -173,7 +258,7 @@ def main():
         "dtype": f"{inner} blocks, f32 inner / f64 outer",
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {'x'.join(map(str, w.dims))} lattice, N_tv={w.n_tv} "
-                               f"({w.N} unknowns), mu={w.mu}, min Re/max|eig|={w.rho}",
+                               f"({w.N} unknowns), mu={w.mu}, m0={w.m0():.6f}",
                    "solver": f"FGMRES(10) fp64 outer; inner {inner} GCRO-DR(m={a.m + a.k},k={a.k}) "
                              f"+ poly d={a.d}, inner_tol={a.inner_tol}",
                    "tol": a.tol, "parallelism": "single GPU"},
@@ -182,39 +267,67 @@ def main():
         "matvecs_per_solve": [s["matvecs"] for s in stats],
         "rel_res_true": [s["rel_res_true"] for s in stats],
         "plain_fp64_gmres30": plain,
-        "apply": {p: {"us": r[0] * 1e3, "GB/s": r[1]} for p, r in rates.items()},
-        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"D_c apply ({inner} blocks; block stage + gather)",
-                     "bytes_per_launch": apply_bytes(V, n, inner)},
+        "fp64_comparison": comp,
+        "apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]} for p, r in rates.items()},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
+                     "traffic_detail": traffic_detail,
+                     "kernel": f"k_apply_blocks ({inner} blocks), timed in the solves",
+                     "launches": launches, "avg_us": avg_us, "bytes_per_launch": s1b,
+                     "f64_block_kernel": {"launches": prof["f64"][0],
+                                          "avg_us": 1e3 * prof["f64"][1] / max(prof["f64"][0], 1)},
+                     "whole_run_all_launches": {
+                         p: {"launches": whole[p][1][0],
+                             "avg_us": 1e3 * whole[p][1][1] / max(whole[p][1][0], 1)}
+                         for p in whole}},
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(w, a, plain):
-    """The oracle (FP64 NumPy) on the host: one GMRES(30) restart cycle on the
-    same operator, extrapolated to a full solve with the iteration count the
-    GPU plain FP64 solve needed."""
+def copy_probe(mib):
+    """y = 1.0 * x over mib MiB of float32, 5 launches: each reads and writes
+    exactly mib MiB of HBM-resident data."""
+    import torch
+    torch.cuda.set_device(0)
+    x = torch.ones(mib * (1 << 18), dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(5):
+        torch.mul(x, 1.0, out=y)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_MiB": mib, "launches": 5}), flush=True)
+
+
+def cpu_baseline(w, a, stats, x_check=None):
+    """The FP64 oracle on the host.  Sample: oracle D_c applies for about
+    a.cpu_seconds; the oracle's solves/s is bounded above by one over (time per
+    apply x matvecs the GPU method needed per solve), its orthogonalisation and
+    setup not counted.  Also checks the last GPU solution's FP64 residual with
+    the oracle apply."""
     import numpy as np
 
     import synth
     from oracle import operator as dop
-    from oracle.krylov import gmres
     A, B = synth.operator(w)
     oop = dop.build(w.dims, A.numpy(), B.numpy(), w.mu)
-    b = synth.rhs(w.dims, w.n_tv, 0).numpy().reshape(-1)
-    f = lambda v: dop.apply(oop, v.reshape(oop.V, oop.n)).reshape(-1)
-    t0 = time.perf_counter()
-    x, info = gmres(f, b, a.tol, 30, 1)
-    dt = time.perf_counter() - t0
-    per_iter = dt / max(info.iters, 1)
-    iters = (plain.get("iters") or [None])[0]
-    value = 1.0 / (per_iter * iters) if iters else None
-    return {"value": value, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"one GMRES(30) cycle ({info.iters} iterations, {dt:.1f} s) of the FP64 "
-                      f"oracle on the same operator, extrapolated to {iters} iterations "
-                      f"(the GPU plain FP64 solve's count); single-threaded numpy einsum"}
+    del A, B
+    v = synth.rhs(w.dims, w.n_tv, 0).numpy()
+    dop.apply(oop, v)
+    reps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < a.cpu_seconds:
+        dop.apply(oop, v)
+        reps += 1
+    per_apply = (time.perf_counter() - t0) / reps
+    mv = float(np.mean([s["matvecs"] for s in stats]))
+    out = {"value": 1.0 / (per_apply * mv), "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": f"{reps} FP64 oracle D_c applies ({per_apply:.3f} s each, numpy einsum, one "
+                     f"thread) x {mv:.0f} matvecs per solve of the GPU method; an upper bound "
+                     f"(orthogonalisation and setup not counted)"}
+    if x_check is not None:
+        x, b = (t.cpu().numpy() for t in x_check)
+        r = b - dop.apply(oop, x)
+        out["oracle_relres_last_solve"] = float(np.linalg.norm(r) / np.linalg.norm(b))
+    return out
 
 
 if __name__ == "__main__":

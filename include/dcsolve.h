@@ -233,9 +233,28 @@ int dc_export_f16(dc_op_t op, uint16_t* codes, float* scales);
 
 /* Copy the current recycle space of the solver variant (opts->prec,
  * opts->block_jacobi, opts->d, adjoint) to device complex128 [k][V][n]
- * arrays U and C (either may be NULL); *k_out = its dimension (0 if none). */
+ * arrays U and C with k = opts->k (either may be NULL); *k_out = its
+ * dimension (<= opts->k; 0 if the variant holds no space built for this k
+ * and the current operator). */
 int dc_export_recycle(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint,
                       void* U, void* C, int32_t* k_out, void* stream);
+
+/* Timing of the D_c apply's block kernel (diagnostics, not part of the
+ * method).  enable != 0 clears the totals and records a pair of HIP events on
+ * the launch stream around every later launch of the block kernel (the stage
+ * that streams the stored blocks); enable = 0 stops recording.  Launches that
+ * a finished Arnoldi cycle turned into no-ops are not counted.  Adds two event
+ * records per apply to the stream. */
+int dc_profile_apply(dc_op_t op, int32_t enable);
+
+/* Totals since the last dc_profile_apply(op, 1) for the blocks used in
+ * precision prec (DC_PREC_F64 / DC_PREC_F32 / DC_PREC_F16S): *launches =
+ * launches that did work, *total_ms = their summed event-to-event duration;
+ * *launches_all, *total_ms_all = the same over every recorded launch, no-op
+ * launches of finished cycles included (what a kernel tracer sees).  Any
+ * output pointer may be NULL.  Waits for the recorded events to complete. */
+int dc_profile_apply_read(dc_op_t op, int32_t prec, int64_t* launches, double* total_ms,
+                          int64_t* launches_all, double* total_ms_all);
 
 /* Message of the last error on this thread ("" if none). */
 const char* dc_last_error(void);

@@ -218,6 +218,21 @@ class CoarseOp:
                                              int(x0 is not None), _stream_ptr(stream), stats))
         return x, [stats[i].as_dict() for i in range(R)], rc
 
+    # -- diagnostics
+    def profile_apply(self, enable: bool = True):
+        """Start (clearing the totals) or stop HIP-event timing of the apply's
+        block kernel."""
+        check(load().dc_profile_apply(self._h, int(bool(enable))))
+
+    def profile_apply_read(self, prec: str, include_noops: bool = False):
+        """(launches, total ms) of the block kernel in precision prec since
+        the last profile_apply(True): launches that did work, or with
+        include_noops every launch (no-op launches of finished cycles too)."""
+        n, ms, na, msa = C.c_int64(), C.c_double(), C.c_int64(), C.c_double()
+        check(load().dc_profile_apply_read(self._h, PREC[prec], C.byref(n), C.byref(ms),
+                                           C.byref(na), C.byref(msa)))
+        return (na.value, msa.value) if include_noops else (n.value, ms.value)
+
     def export_recycle(self, opts: Opts, adjoint=False, stream=None):
         k = max(opts.k, 1)
         U = torch.zeros((k, self.V, self.n), dtype=torch.complex128, device="cuda")

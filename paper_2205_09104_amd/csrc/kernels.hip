@@ -1378,7 +1378,10 @@ __global__ void k_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const d
   *a.est = est;
   *a.jdone = j + 1;
   if (breakdown) *a.brk_flag = 1;
-  if (breakdown || est <= target || j + 1 >= steps) *a.done = 1;
+  if (breakdown || est <= target || j + 1 >= steps) {
+    *a.done = 1;
+    if (a.hdone) *a.hdone = 1;
+  }
 }
 
 // ------------------------------------------------------------------ gradient

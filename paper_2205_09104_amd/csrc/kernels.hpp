@@ -139,6 +139,7 @@ struct ArnoldiDev {
   int* done;        // cycle flag
   int* jdone;       // steps completed
   int* brk_flag;    // 1 if the cycle ended by breakdown
+  int* hdone = nullptr;  // optional host-mapped copy of the done flag (set to 1 with it)
 };
 void launch_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const double* c1,
                            const double* c2, const double* nrm2, double target, double brk,

@@ -117,6 +117,114 @@ void op_update(Op& op, const void* self_blocks, const void* hop_blocks, bool on_
   op.version += 1;  // block Jacobi, polynomial and recycle space become stale
 }
 
+// ------------------------------------------------------------------ apply profile
+static int prec_slot(Prec p) { return p == P64 ? 0 : (p == P32 ? 1 : 2); }
+
+void ApplyProfile::reset() {
+  flush();
+  for (int i = 0; i < 3; ++i) {
+    ms[i] = ms_all[i] = 0.0;
+    count[i] = count_all[i] = 0;
+  }
+  missed = 0;
+  tag = -1;
+}
+
+bool ApplyProfile::take(hipEvent_t* a, hipEvent_t* b) {
+  while (idle.size() < 2 && owned.size() + 2 <= kMaxEvents) {
+    hipEvent_t e;
+    DC_HIP(hipEventCreate(&e));
+    owned.push_back(e);
+    idle.push_back(e);
+  }
+  if (idle.size() < 2) return false;
+  *a = idle.back(); idle.pop_back();
+  *b = idle.back(); idle.pop_back();
+  return true;
+}
+
+void ApplyProfile::end_cycle(int steps_done) {
+  for (Rec& r : recs)
+    if (r.tag >= 0) {
+      if (r.tag >= steps_done) r.noop = true;
+      r.tag = -1;
+    }
+  tag = -1;
+}
+
+void ApplyProfile::flush() {
+  for (Rec& r : recs) {
+    DC_HIP(hipEventSynchronize(r.b));
+    float t = 0.f;
+    DC_HIP(hipEventElapsedTime(&t, r.a, r.b));
+    ms_all[r.prec] += t;
+    ++count_all[r.prec];
+    if (!r.noop) {
+      ms[r.prec] += t;
+      ++count[r.prec];
+    }
+    idle.push_back(r.a);
+    idle.push_back(r.b);
+  }
+  recs.clear();
+}
+
+ApplyProfile::~ApplyProfile() {
+  for (hipEvent_t e : owned) (void)hipEventDestroy(e);
+}
+
+void CycleSignal::ensure() {
+  if (host) return;
+  void* h = nullptr;
+  DC_HIP(hipHostMalloc(&h, 64, hipHostMallocMapped | hipHostMallocCoherent));
+  host = static_cast<int*>(h);
+  *host = 0;
+  void* d = nullptr;
+  DC_HIP(hipHostGetDevicePointer(&d, h, 0));
+  dev = static_cast<int*>(d);
+  for (auto& e : ev) DC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+}
+
+CycleSignal::~CycleSignal() {
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (host) (void)hipHostFree(host);
+}
+
+// Stage 1 of the apply, timed when profiling is on.  Records are flushed
+// outside cycles once many have accumulated, so the event pool stays small.
+static void stage1(Op& op, Prec p, int n, int V, const void* blocks, const float* scales,
+                   const void* in, void* gbuf, const int* nbr, double tm, const int* done,
+                   hipStream_t st) {
+  ApplyProfile& pr = op.prof;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (pr.on) {
+    if (pr.tag < 0 && pr.recs.size() >= 2048) pr.flush();
+    if (pr.take(&a, &b)) DC_HIP(hipEventRecord(a, st));
+    else ++pr.missed;
+  }
+  launch_apply_blocks(p, n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
+  if (a) {
+    DC_HIP(hipEventRecord(b, st));
+    pr.recs.push_back({a, b, prec_slot(p), done ? pr.tag : -1, false});
+  }
+}
+
+void op_profile(Op& op, int enable) {
+  op.prof.reset();
+  op.prof.on = enable != 0;
+}
+
+void op_profile_read(Op& op, Prec p, long* launches, double* total_ms, long* launches_all,
+                     double* total_ms_all) {
+  op.prof.flush();
+  const int i = prec_slot(p);
+  if (launches) *launches = op.prof.count[i];
+  if (total_ms) *total_ms = op.prof.ms[i];
+  if (launches_all) *launches_all = op.prof.count_all[i];
+  if (total_ms_all) *total_ms_all = op.prof.ms_all[i];
+}
+
 static void check_prec(const Op& op, Prec p) {
   if (p == P32 && !(op.store & 2)) throw InvalidArg("FP32 blocks were not stored (desc.store)");
   if (p == P16S && !(op.store & 4)) throw InvalidArg("FP16 blocks were not stored (desc.store)");
@@ -130,13 +238,13 @@ void op_apply(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_
   if (!in || !out) throw InvalidArg("null vector pointer");
   if (in == out) throw InvalidArg("in and out must not overlap");
   if (!adjoint) {
-    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
+    stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
                         op.mu, nullptr, st);
     launch_gather_store(p, op.n, op.V, op.gbuf(p), out, nullptr, st);
   } else {
     // D(mu)^H = Gamma5 D(-mu) Gamma5
     launch_gamma5(p, in, out, op.V, op.n, st);
-    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), out, op.gbuf(p),
+    stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), out, op.gbuf(p),
                         op.nbr.as<int>(), -op.mu, nullptr, st);
     launch_gather_store(p, op.n, op.V, op.gbuf(p), out, nullptr, st);
     launch_gamma5(p, out, out, op.V, op.n, st);
@@ -287,7 +395,7 @@ struct Krylov {
 
   // A~ in = (B^{-1}) D in (one matvec)
   void A(const Z* in, Z* out, const int* done) {
-    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
+    stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
                         tm, done, st);
     if (bjinv) launch_bj_gather_store(p, op.n, op.V, bjinv, bjsc, op.gbuf(p), out, done, st);
     else launch_gather_store(p, op.n, op.V, op.gbuf(p), out, done, st);
@@ -313,7 +421,7 @@ struct Krylov {
       return;
     }
     // i = 1: prod = v - A v / theta_0;  y = v / theta_0 + prod / theta_1
-    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
+    stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
                         tm, done, st);
     if (bjinv)
       launch_bj_gather_poly_first(p, op.n, op.V, bjinv, bjsc, op.gbuf(p), in, prod, out, inv(th[0]),
@@ -323,7 +431,7 @@ struct Krylov {
                                inv(th[1]), done, st);
     ++matvecs;
     for (int i = 2; i < d; ++i) {
-      launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), prod, op.gbuf(p),
+      stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), prod, op.gbuf(p),
                           op.nbr.as<int>(), tm, done, st);
       if (bjinv)
         launch_bj_gather_poly(p, op.n, op.V, bjinv, bjsc, op.gbuf(p), prod, out, inv(th[i - 1]),
@@ -346,7 +454,7 @@ struct Krylov {
 
   // r = b - D x (true residual in the variant's precision); returns ||r||
   double true_resid(const Z* x, const Z* b, Z* r) {
-    launch_apply_blocks(p, op.n, op.V, op.blocks(p), op.scales(p), x, op.gbuf(p), op.nbr.as<int>(),
+    stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), x, op.gbuf(p), op.nbr.as<int>(),
                         tm, nullptr, st);
     launch_gather_resid(p, op.n, op.V, op.gbuf(p), b, r, op.red(), nrm, st);
     ++matvecs;
@@ -392,10 +500,32 @@ struct Krylov {
   CycleOut cycle(const Z* rv, double beta, int steps, int kC, double target, int min_steps) {
     launch_scale(p, rv, V(0), N, nullptr, 1.0 / beta, nullptr, st);
     launch_arnoldi_init(ad, beta, st);
+    // The host enqueues the cycle in chunks of about a millisecond of device
+    // work and stays at most two chunks ahead; once the device has set the stop
+    // flag no further chunks are enqueued (the steps already queued past the
+    // stopping one exit at entry).
+    const double per_step = double(N) * (has_poly() ? double(var.theta.size()) : 1.0);
+    const int chunk = std::max(1, std::min(steps, int(std::ceil(1.0e6 / per_step))));
+    op.sig.ensure();
+    *op.sig.host = 0;
+    ad.hdone = op.sig.dev;
+    int nchunk = 0, enqueued = 0;
     for (int j = 0; j < steps; ++j) {
+      op.prof.tag = j;
       Ahat(V(j), V(j + 1), ad.done);
       orth_step(j, kC, steps, (j + 1 < min_steps) ? -1.0 : target);
+      enqueued = j + 1;
+      if ((j + 1) % chunk == 0 && j + 1 < steps) {
+        DC_HIP(hipEventRecord(op.sig.ev[nchunk & 1], st));
+        if (nchunk >= 1) {
+          DC_HIP(hipEventSynchronize(op.sig.ev[(nchunk - 1) & 1]));
+          if (__atomic_load_n(op.sig.host, __ATOMIC_ACQUIRE)) break;
+        }
+        ++nchunk;
+      }
     }
+    ad.hdone = nullptr;
+    op.prof.tag = -1;
     CycleOut c;
     int flags[3];
     DC_HIP(hipMemcpyAsync(flags, ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -408,6 +538,9 @@ struct Krylov {
     DC_HIP(hipStreamSynchronize(st));
     c.jd = flags[1];
     c.breakdown = flags[2] != 0;
+    op.prof.end_cycle(c.jd);
+    // steps past the stopping one were enqueued but exited at entry
+    matvecs -= long(enqueued - c.jd) * (has_poly() ? long(var.theta.size()) : 1L);
     c.est = est;
     c.H = Mat(c.jd + 1, c.jd);
     for (int jj = 0; jj < c.jd; ++jj)
@@ -488,6 +621,7 @@ struct Krylov {
     upload_coef(cu);
     launch_combine(p, nullptr, 0, V(0), jd, N, coef, kk, Uv(), 0, st);
     var.kcur = kk;
+    var.k_built = kmax;
     var.updates = 1;
     var.recycle_version = op.version;
     refresh_unorm();
@@ -505,7 +639,8 @@ struct Krylov {
       relres = 0.0;
       return true;
     }
-    if (var.recycle_version != op.version) {  // matrix changed: rebuild lazily
+    // matrix changed, or a different recycle dimension requested: rebuild lazily
+    if (var.recycle_version != op.version || var.k_built != kmax) {
       var.kcur = 0;
       var.updates = 0;
     }
@@ -792,7 +927,7 @@ static double fp64_relres(Op& op, const z64* x, const z64* b, int adjoint, hipSt
   double* d = op.scal.as<double>();
   launch_norm2(P64, b, N, op.red(), d, st);
   if (!adjoint) {
-    launch_apply_blocks(P64, op.n, op.V, op.blocks(P64), nullptr, x, op.gbuf(P64),
+    stage1(op, P64, op.n, op.V, op.blocks(P64), nullptr, x, op.gbuf(P64),
                         op.nbr.as<int>(), op.mu, nullptr, st);
     launch_gather_resid(P64, op.n, op.V, op.gbuf(P64), b, op.t64a.p, op.red(), d + 1, st);
   } else {
@@ -1224,7 +1359,7 @@ int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b
   Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d);
   const auto ts = std::chrono::steady_clock::now();
   ensure_poly(op, var, o, st, &stt[0]);
-  if (var.recycle_version != op.version) var.kcur = 0;
+  if (var.recycle_version != op.version || var.k_built != o.k) var.kcur = 0;
   const double t_setup = ms_since(ts);
   const int kC = (o.k > 0) ? var.kcur : 0;
   const int kc_saved = var.kcur;
@@ -1362,7 +1497,8 @@ int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C,
   const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
   Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d);
   const size_t N = op.N();
-  if (var.kcur == 0) return 0;
+  // only a space built for this k fits the caller's [k][V][n] arrays
+  if (var.kcur == 0 || var.k_built != o.k || var.recycle_version != op.version) return 0;
   if (var.prec == P64) {
     if (U) DC_HIP(hipMemcpyAsync(U, var.U.p, size_t(var.kcur) * N * sizeof(z64), hipMemcpyDeviceToDevice, st));
     if (C) DC_HIP(hipMemcpyAsync(C, var.C.p, size_t(var.kcur) * N * sizeof(z64), hipMemcpyDeviceToDevice, st));

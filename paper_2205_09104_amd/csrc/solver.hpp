@@ -60,10 +60,42 @@ struct Variant {
   // recycle space (vectors of the variant's precision)
   DevBuf U, C;
   int kcur = 0;
+  int k_built = 0;   // recycle dimension requested when the space was built
   int updates = 0;
   long recycle_version = -1;
   std::vector<double> unorm;   // ||u_i||
   DevBuf ws, sm;               // Krylov workspace: vectors and small device arrays
+};
+
+// Optional timing of the apply's block kernel (stage 1) with HIP events on its
+// launch stream.  Launches inside an Arnoldi cycle carry the cycle step they
+// belong to; steps past the one where the cycle stopped ran as no-ops (device
+// done flag) and are dropped once the cycle's step count is known.
+struct ApplyProfile {
+  struct Rec { hipEvent_t a, b; int prec; int tag; bool noop; };
+  bool on = false;
+  int tag = -1;                   // step of the pending cycle (-1: outside a cycle)
+  std::vector<hipEvent_t> idle, owned;
+  std::vector<Rec> recs;
+  double ms[3] = {0, 0, 0}, ms_all[3] = {0, 0, 0};
+  long count[3] = {0, 0, 0}, count_all[3] = {0, 0, 0};   // *_all: no-op launches included
+  long missed = 0;                // launches not recorded (event cap reached)
+  static constexpr size_t kMaxEvents = 16384;
+  void reset();
+  bool take(hipEvent_t* a, hipEvent_t* b);
+  void end_cycle(int steps_done);
+  void flush();
+  ~ApplyProfile();
+};
+
+// Host-mapped stop flag of the pending Arnoldi cycle and two events that
+// pace the host's enqueueing a bounded distance ahead of the device.
+struct CycleSignal {
+  int* host = nullptr;    // pinned, mapped
+  int* dev = nullptr;     // its device address
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  void ensure();
+  ~CycleSignal();
 };
 
 struct Op {
@@ -85,6 +117,8 @@ struct Op {
   DevBuf ptrs;              // device pointer arrays of the multi-RHS apply
   std::vector<DevBuf> bws, bsm;            // per right-hand-side workspaces of batched solves
   DevBuf bx64, bb64, b32, x32, r64;        // batched-solve vectors
+  ApplyProfile prof;
+  CycleSignal sig;
   Reducer red() const { return Reducer{redpart.as<double>()}; }
   std::map<std::tuple<int, int, int, int>, std::unique_ptr<Variant>> variants;
   size_t N() const { return size_t(V) * n; }
@@ -110,6 +144,9 @@ int op_arnoldi(Op& op, const SolveOpts& o, const void* v, int steps, hipStream_t
 int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, void* x,
              const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
 int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st);
+void op_profile(Op& op, int enable);
+void op_profile_read(Op& op, Prec p, long* launches, double* total_ms, long* launches_all,
+                     double* total_ms_all);
 int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b, void* x,
                    const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
 

@@ -294,3 +294,50 @@ def test_batched_adjoint():
     assert rc == 0
     for r in range(3):
         assert oracle_relres(oop, X[r].cpu().numpy(), B[r].numpy(), adjoint=True) <= 1e-11
+
+
+def test_apply_profile_counts_executed_launches(c1):
+    """The event profiler counts every apply it brackets, and inside a solve
+    exactly the block-kernel launches that did work: one per matvec plus the
+    closing FP64 true-residual check."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, b, xref = c1
+    log("apply profile")
+    x = b.cuda()
+    out = torch.empty_like(x)
+    gop.profile_apply(True)
+    for _ in range(7):
+        gop.apply(x, prec="f64", out=out)
+    n64, ms64 = gop.profile_apply_read("f64")
+    assert n64 == 7 and ms64 > 0.0
+    assert gop.profile_apply_read("f32") == (0, 0.0)
+    for o in (Opts(m=30), Opts(m=20, d=4, seed=1), Opts(m=24, k=8, d=4, seed=1)):
+        gop.profile_apply(True)
+        _, st, rc = gop.solve(x, 1e-10, o)
+        n, ms = gop.profile_apply_read("f64")
+        log(f"  opts m={o.m} k={o.k} d={o.d}: launches {n} matvecs {st[0]['matvecs']}")
+        assert rc == 0 and n == st[0]["matvecs"] + 1 and ms > 0.0
+    n_before = gop.profile_apply_read("f64")[0]
+    gop.profile_apply(False)
+    gop.apply(x, prec="f64", out=out)
+    assert gop.profile_apply_read("f64")[0] <= n_before
+
+
+def test_changing_recycle_dimension_rebuilds_the_space(c1):
+    """A solve with a different k on the same solver variant starts a new
+    recycle space instead of reusing one of another dimension."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, b, xref = c1
+    log("recycle dimension change")
+    x = b.cuda()
+    for k in (8, 4, 12, 4):
+        o = Opts(m=20 + k, k=k, d=4, seed=1)
+        xs, st, rc = gop.solve(x, 1e-10, o)
+        assert rc == 0 and st[0]["rel_res_true"] <= 1e-10
+        assert oracle_relres(oop, xs.cpu().numpy(), b.numpy()) <= 1e-10
+        U, Cm = gop.export_recycle(o)
+        kk = U.shape[0]
+        assert 0 < kk <= k
+        # C = D U with orthonormal C (the GCRO-DR invariants of the exported space)
+        Cn = Cm[:kk].cpu().numpy().reshape(kk, -1)
+        assert np.abs(Cn.conj() @ Cn.T - np.eye(kk)).max() < 1e-8
