@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=10)
+    p.add_argument("--steps", type=int, default=16)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="c2")
     p.add_argument("--tol", type=float, default=1e-8)
@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--plain-max-cycles", type=int, default=400,
                    help="restart cycles of the plain GMRES(30) comparison (it may stagnate)")
     p.add_argument("--apply-reps", type=int, default=50)
+    p.add_argument("--profile-every", type=int, default=8,
+                   help="time one in this many launches of the apply's block kernel (0: off)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
     p.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
@@ -135,8 +137,8 @@ def main():
     log(f"operator built in {time.time() - t0:.1f}s")
     # the library launches on torch's current stream (the HIP null stream here)
     stream = torch.cuda.current_stream()
-    # HIP events around every launch of the apply's block kernel, from here on
-    op.profile_apply(True)
+    # HIP events on one in a.profile_every launches of the apply's block kernel
+    op.profile_apply(a.profile_every)
 
     def prof_totals():
         return {p: (op.profile_apply_read(p), op.profile_apply_read(p, include_noops=True))
@@ -230,8 +232,16 @@ def main():
                 f"iters {st['iters']} matvecs {st['matvecs']} {1e3 * pdt:.0f} ms")
     plain = comp.get("gmres30", {"solves_per_s": None})
 
+    # forward error of the last timed solve against an FP64 solve to 1e-12
+    # (polynomial + deflation, FP64 throughout), outside the timed region
+    ref_opts = Opts(m=62, k=32, d=16, prec="f64", seed=1, max_cycles=2000)
+    xr, sr, _ = op.solve(rhs[-1], 1e-12, ref_opts)
+    err_vs_fp64 = float(torch.linalg.vector_norm(x_last - xr) / torch.linalg.vector_norm(xr))
+    log(f"forward error of the last solve vs FP64 (rel.res {sr[0]['rel_res_true']:.1e}): "
+        f"{err_vs_fp64:.2e}")
+
     whole = prof_totals()     # the whole run so far, for comparison with a kernel tracer
-    op.profile_apply(False)
+    op.profile_apply(0)
 
     # ------------------------------------------------ CPU oracle baseline
     cpu = None
@@ -266,6 +276,7 @@ def main():
         "iters_per_solve": [s["iters"] for s in stats],
         "matvecs_per_solve": [s["matvecs"] for s in stats],
         "rel_res_true": [s["rel_res_true"] for s in stats],
+        "err_vs_fp64_last_solve": err_vs_fp64,
         "plain_fp64_gmres30": plain,
         "fp64_comparison": comp,
         "apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]} for p, r in rates.items()},
@@ -273,11 +284,13 @@ def main():
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "traffic_detail": traffic_detail,
                      "kernel": f"k_apply_blocks ({inner} blocks), timed in the solves",
-                     "launches": launches, "avg_us": avg_us, "bytes_per_launch": s1b,
+                     "traffic_GBs": (traffic / (avg_us * 1e-6) / 1e9) if (traffic and launches) else None,
+                     "timed_launches": launches, "sampling": f"1 in {a.profile_every}",
+                     "avg_us": avg_us, "bytes_per_launch": s1b,
                      "f64_block_kernel": {"launches": prof["f64"][0],
                                           "avg_us": 1e3 * prof["f64"][1] / max(prof["f64"][0], 1)},
                      "whole_run_all_launches": {
-                         p: {"launches": whole[p][1][0],
+                         p: {"timed_launches": whole[p][1][0],
                              "avg_us": 1e3 * whole[p][1][1] / max(whole[p][1][0], 1)}
                          for p in whole}},
         "cpu_baseline": cpu,
@@ -319,7 +332,13 @@ def cpu_baseline(w, a, stats, x_check=None):
         reps += 1
     per_apply = (time.perf_counter() - t0) / reps
     mv = float(np.mean([s["matvecs"] for s in stats]))
+    try:
+        from threadpoolctl import threadpool_info
+        blas = [{k: i.get(k) for k in ("internal_api", "num_threads")} for i in threadpool_info()]
+    except Exception:  # noqa: BLE001
+        blas = None
     out = {"value": 1.0 / (per_apply * mv), "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "host_cpus": os.cpu_count(), "blas_pools": blas,
            "sample": f"{reps} FP64 oracle D_c applies ({per_apply:.3f} s each, numpy einsum, one "
                      f"thread) x {mv:.0f} matvecs per solve of the GPU method; an upper bound "
                      f"(orthogonalisation and setup not counted)"}

@@ -240,12 +240,13 @@ int dc_export_recycle(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint,
                       void* U, void* C, int32_t* k_out, void* stream);
 
 /* Timing of the D_c apply's block kernel (diagnostics, not part of the
- * method).  enable != 0 clears the totals and records a pair of HIP events on
- * the launch stream around every later launch of the block kernel (the stage
- * that streams the stored blocks); enable = 0 stops recording.  Launches that
- * a finished Arnoldi cycle turned into no-ops are not counted.  Adds two event
- * records per apply to the stream. */
-int dc_profile_apply(dc_op_t op, int32_t enable);
+ * method).  every >= 1 clears the totals and has one in `every` later
+ * dispatches of the block kernel (the stage that streams the stored blocks)
+ * record a start and an end HIP event on its launch stream (events passed to
+ * hipExtLaunchKernel); every = 0 stops recording; every < 0 is
+ * DC_ERR_INVALID.  Launches that a finished Arnoldi cycle turned into no-ops
+ * are counted separately. */
+int dc_profile_apply(dc_op_t op, int32_t every);
 
 /* Totals since the last dc_profile_apply(op, 1) for the blocks used in
  * precision prec (DC_PREC_F64 / DC_PREC_F32 / DC_PREC_F16S): *launches =

@@ -219,10 +219,10 @@ class CoarseOp:
         return x, [stats[i].as_dict() for i in range(R)], rc
 
     # -- diagnostics
-    def profile_apply(self, enable: bool = True):
-        """Start (clearing the totals) or stop HIP-event timing of the apply's
-        block kernel."""
-        check(load().dc_profile_apply(self._h, int(bool(enable))))
+    def profile_apply(self, every: int = 1):
+        """Start (clearing the totals) HIP-event timing of one in `every`
+        launches of the apply's block kernel; every = 0 (or False) stops."""
+        check(load().dc_profile_apply(self._h, int(every)))
 
     def profile_apply_read(self, prec: str, include_noops: bool = False):
         """(launches, total ms) of the block kernel in precision prec since

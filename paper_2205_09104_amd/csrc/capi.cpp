@@ -302,10 +302,10 @@ int dc_export_recycle(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, vo
   });
 }
 
-int dc_profile_apply(dc_op_t op, int32_t enable) {
+int dc_profile_apply(dc_op_t op, int32_t every) {
   return guarded([&] {
     if (!op) throw dc::InvalidArg("null handle");
-    dc::op_profile(op->op, enable);
+    dc::op_profile(op->op, every);
     return DC_OK;
   });
 }

@@ -2,6 +2,8 @@
 // reductions, tall-skinny combinations, conversions and the gradient kernel.
 #include "kernels.hpp"
 
+#include <hip/hip_ext.h>
+
 #include <hip/hip_fp16.h>
 
 namespace dc {
@@ -1315,41 +1317,65 @@ __global__ void k_arnoldi_init(ArnoldiDev a, double beta) {
 
 // Givens storage in a.giv: g[0..ldh] (complex), then c[0..ldh) (real, stored
 // in the even slots of complex entries), then s[0..ldh) (complex).
-__global__ void k_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const double* c1,
-                                 const double* c2, const double* nrm2, double target,
-                                 double brk) {
+constexpr int kFinishLds = 512;  // Hessenberg column length staged in LDS
+
+// One workgroup of 64 lanes: the lanes combine the two Gram-Schmidt passes'
+// coefficients in parallel and stage the new column and the stored rotations in
+// LDS; lane 0 then runs the (inherently serial) Givens update from LDS.
+__global__ __launch_bounds__(64) void k_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j,
+                                                       const double* c1, const double* c2,
+                                                       const double* nrm2, double target,
+                                                       double brk) {
   if (*a.done) return;
-  if (threadIdx.x != 0) return;
+  __shared__ double hcol[2 * (kFinishLds + 2)], csl[kFinishLds], snl[2 * kFinishLds];
+  const bool staged = j + 2 <= kFinishLds;
   double* Hc = a.H + 2 * size_t(j) * a.ldh;
-  for (int i = 0; i < kC; ++i) {
-    a.Bk[2 * (size_t(j) * a.ldb + i)] = c1[2 * i] + c2[2 * i];
-    a.Bk[2 * (size_t(j) * a.ldb + i) + 1] = c1[2 * i + 1] + c2[2 * i + 1];
-  }
-  for (int i = 0; i <= j; ++i) {
-    Hc[2 * i] = c1[2 * (kC + i)] + c2[2 * (kC + i)];
-    Hc[2 * i + 1] = c1[2 * (kC + i) + 1] + c2[2 * (kC + i) + 1];
-  }
-  const double wn0 = sqrt(fmax(c1[2 * (kC + j + 1)], 0.0));  // ||A v_j|| before orthogonalisation
-  const double h = sqrt(fmax(*nrm2, 0.0));
-  const bool breakdown = !(h > brk * wn0);
-  Hc[2 * (j + 1)] = breakdown ? 0.0 : h;
-  Hc[2 * (j + 1) + 1] = 0.0;
-  *a.inv_h = breakdown ? 0.0 : 1.0 / h;
   double* g = a.giv;
   double* cs = a.giv + 2 * (a.ldh + 1);
   double* sn = cs + 2 * a.ldh;
+  for (int i = threadIdx.x; i < kC; i += 64) {
+    a.Bk[2 * (size_t(j) * a.ldb + i)] = c1[2 * i] + c2[2 * i];
+    a.Bk[2 * (size_t(j) * a.ldb + i) + 1] = c1[2 * i + 1] + c2[2 * i + 1];
+  }
+  for (int i = threadIdx.x; i <= j; i += 64) {
+    const double hr = c1[2 * (kC + i)] + c2[2 * (kC + i)];
+    const double hi = c1[2 * (kC + i) + 1] + c2[2 * (kC + i) + 1];
+    Hc[2 * i] = hr;
+    Hc[2 * i + 1] = hi;
+    if (staged) {
+      hcol[2 * i] = hr;
+      hcol[2 * i + 1] = hi;
+    }
+  }
+  if (staged)
+    for (int i = threadIdx.x; i < j; i += 64) {
+      csl[i] = cs[2 * i];
+      snl[2 * i] = sn[2 * i];
+      snl[2 * i + 1] = sn[2 * i + 1];
+    }
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double* hsrc = staged ? hcol : Hc;
+  const double wn0 = sqrt(fmax(c1[2 * (kC + j + 1)], 0.0));  // ||A v_j|| before orthogonalisation
+  const double h = sqrt(fmax(*nrm2, 0.0));
+  const bool breakdown = !(h > brk * wn0);
+  const double hh = breakdown ? 0.0 : h;
+  Hc[2 * (j + 1)] = hh;
+  Hc[2 * (j + 1) + 1] = 0.0;
+  *a.inv_h = breakdown ? 0.0 : 1.0 / h;
   // carry the running entry through the previous rotations:
   // [h_i; h_{i+1}] <- [[c_i, s_i], [-conj(s_i), c_i]] [h_i; h_{i+1}]
-  double xr = Hc[0], xi = Hc[1];
+  double xr = hsrc[0], xi = hsrc[1];
   for (int i = 0; i < j; ++i) {
-    const double c = cs[2 * i], sr = sn[2 * i], si = sn[2 * i + 1];
-    const double yr = Hc[2 * (i + 1)], yi = Hc[2 * (i + 1) + 1];
+    const double c = staged ? csl[i] : cs[2 * i];
+    const double sr = staged ? snl[2 * i] : sn[2 * i];
+    const double si = staged ? snl[2 * i + 1] : sn[2 * i + 1];
+    const double yr = hsrc[2 * (i + 1)], yi = hsrc[2 * (i + 1) + 1];
     const double nyr = -(sr * xr + si * xi) + c * yr;
     const double nyi = -(sr * xi - si * xr) + c * yi;
     xr = nyr;
     xi = nyi;
   }
-  const double hh = Hc[2 * (j + 1)];
   const double ax = sqrt(xr * xr + xi * xi);
   double c, sr, si;
   if (hh == 0.0) {
@@ -1439,7 +1465,8 @@ void launch_neighbours(int* nbr, int L0, int L1, int L2, int L3, hipStream_t st)
 
 template <int P>
 static void apply_T(int n, int V, const void* blocks, const float* scales, const void* in,
-                    void* gbuf, const int* nbr, double tm, const int* done, hipStream_t st) {
+                    void* gbuf, const int* nbr, double tm, const int* done, hipStream_t st,
+                    hipEvent_t ev0, hipEvent_t ev1) {
   using VR = typename VecOf<P>::R;
   const int chunk = (5 * V + 7) / 8;
   const dim3 grid(unsigned(chunk) * 8u), block(64);
@@ -1447,14 +1474,15 @@ static void apply_T(int n, int V, const void* blocks, const float* scales, const
   auto* pg = static_cast<cx<VR>*>(gbuf);
   const bool full = (n % 8) == 0;
   switch (tile_T(n)) {
-#define DC_CASE(TV)                                                                          \
-  case TV:                                                                                   \
-    if (full)                                                                                \
-      hipLaunchKernelGGL((k_apply_blocks<TV, P, true>), grid, block, 0, st, blocks, scales,  \
-                         pin, pg, nbr, V, n, chunk, tm, done);                               \
-    else                                                                                     \
-      hipLaunchKernelGGL((k_apply_blocks<TV, P, false>), grid, block, 0, st, blocks, scales, \
-                         pin, pg, nbr, V, n, chunk, tm, done);                               \
+  // with events: the dispatch itself records its start and end (no marker packets)
+#define DC_CASE(TV)                                                                           \
+  case TV:                                                                                    \
+    if (full)                                                                                 \
+      hipExtLaunchKernelGGL((k_apply_blocks<TV, P, true>), grid, block, 0, st, ev0, ev1, 0,   \
+                            blocks, scales, pin, pg, nbr, V, n, chunk, tm, done);            \
+    else                                                                                      \
+      hipExtLaunchKernelGGL((k_apply_blocks<TV, P, false>), grid, block, 0, st, ev0, ev1, 0,  \
+                            blocks, scales, pin, pg, nbr, V, n, chunk, tm, done);            \
     break;
     DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
 #undef DC_CASE
@@ -1466,10 +1494,10 @@ static void apply_T(int n, int V, const void* blocks, const float* scales, const
 
 void launch_apply_blocks(Prec p, int n, int V, const void* blocks, const float* scales,
                          const void* in, void* gbuf, const int* nbr, double tm, const int* done,
-                         hipStream_t st) {
-  if (p == P64) apply_T<P64>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
-  else if (p == P32) apply_T<P32>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
-  else apply_T<P16S>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
+                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (p == P64) apply_T<P64>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st, ev0, ev1);
+  else if (p == P32) apply_T<P32>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st, ev0, ev1);
+  else apply_T<P16S>(n, V, blocks, scales, in, gbuf, nbr, tm, done, st, ev0, ev1);
 }
 
 void launch_invert_blocks(const void* tiled64, int V, int n, double tm, void* out64, void* out32,

@@ -30,9 +30,11 @@ void launch_neighbours(int* nbr, int L0, int L1, int L2, int L3, hipStream_t st)
 // writes B psi_{x+mu} into slot 5+mu of gbuf[x] and the backward contribution
 // Gamma5 B^H Gamma5 psi_x into slot mu of gbuf[x+mu].  gbuf: [V][9][n] in the
 // vector precision.
+// ev0/ev1 (optional): events that the dispatch records at its start and end.
 void launch_apply_blocks(Prec p, int n, int V, const void* blocks, const float* scales,
                          const void* in, void* gbuf, const int* nbr, double tm,
-                         const int* done, hipStream_t st);
+                         const int* done, hipStream_t st, hipEvent_t ev0 = nullptr,
+                         hipEvent_t ev1 = nullptr);
 
 // Apply, stage 2 (sum of the 9 slots in a fixed order) with an epilogue.
 //   store : out = s

@@ -198,21 +198,20 @@ static void stage1(Op& op, Prec p, int n, int V, const void* blocks, const float
                    hipStream_t st) {
   ApplyProfile& pr = op.prof;
   hipEvent_t a = nullptr, b = nullptr;
-  if (pr.on) {
+  if (pr.on && (pr.seen++ % pr.every) == 0) {
     if (pr.tag < 0 && pr.recs.size() >= 2048) pr.flush();
-    if (pr.take(&a, &b)) DC_HIP(hipEventRecord(a, st));
-    else ++pr.missed;
+    if (!pr.take(&a, &b)) ++pr.missed;
   }
-  launch_apply_blocks(p, n, V, blocks, scales, in, gbuf, nbr, tm, done, st);
-  if (a) {
-    DC_HIP(hipEventRecord(b, st));
-    pr.recs.push_back({a, b, prec_slot(p), done ? pr.tag : -1, false});
-  }
+  launch_apply_blocks(p, n, V, blocks, scales, in, gbuf, nbr, tm, done, st, a, b);
+  if (a) pr.recs.push_back({a, b, prec_slot(p), done ? pr.tag : -1, false});
 }
 
-void op_profile(Op& op, int enable) {
+void op_profile(Op& op, int every) {
+  if (every < 0) throw InvalidArg("sampling period must be >= 0");
   op.prof.reset();
-  op.prof.on = enable != 0;
+  op.prof.on = every != 0;
+  op.prof.every = every > 0 ? every : 1;
+  op.prof.seen = 0;
 }
 
 void op_profile_read(Op& op, Prec p, long* launches, double* total_ms, long* launches_all,

@@ -67,13 +67,15 @@ struct Variant {
   DevBuf ws, sm;               // Krylov workspace: vectors and small device arrays
 };
 
-// Optional timing of the apply's block kernel (stage 1) with HIP events on its
-// launch stream.  Launches inside an Arnoldi cycle carry the cycle step they
+// Optional timing of the apply's block kernel (stage 1) with HIP events that
+// its dispatch records on the launch stream.  Launches inside an Arnoldi cycle carry the cycle step they
 // belong to; steps past the one where the cycle stopped ran as no-ops (device
 // done flag) and are dropped once the cycle's step count is known.
 struct ApplyProfile {
   struct Rec { hipEvent_t a, b; int prec; int tag; bool noop; };
   bool on = false;
+  int every = 1;                  // time one launch in `every`
+  long seen = 0;                  // launches since enabling
   int tag = -1;                   // step of the pending cycle (-1: outside a cycle)
   std::vector<hipEvent_t> idle, owned;
   std::vector<Rec> recs;
@@ -144,7 +146,7 @@ int op_arnoldi(Op& op, const SolveOpts& o, const void* v, int steps, hipStream_t
 int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, void* x,
              const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
 int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st);
-void op_profile(Op& op, int enable);
+void op_profile(Op& op, int every);
 void op_profile_read(Op& op, Prec p, long* launches, double* total_ms, long* launches_all,
                      double* total_ms_all);
 int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b, void* x,
