@@ -209,6 +209,21 @@ int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, i
                        const void* b, void* x, const double* tol, int32_t use_x0, void* stream,
                        dc_solve_stats* stats);
 
+/* Mixed batch of lattices: the batched solve of solve_coarse_batch over
+ * n_ops operators at once (every operator with the same n = 2 n_tv and the
+ * precision opts->prec stored; no operator twice).  Operator o solves n_rhs[o]
+ * systems: b[o], x[o] device complex128 [n_rhs[o]][V_o][n], tol[o] host
+ * [n_rhs[o]], stats[o] host [n_rhs[o]] (NULL entries allowed).  Each step
+ * runs one multi-right-hand-side apply launch over a work list of the sites of
+ * every operator (up to 8 operators per launch); polynomial, block Jacobi and
+ * frozen recycle space are each operator's own.  Returns DC_OK if every
+ * system converged, else DC_NOT_CONVERGED; DC_ERR_INVALID for mismatched n,
+ * repeated or null handles, or bad tolerances. */
+int solve_coarse_multi(const dc_op_t* ops, int32_t n_ops, const dc_solve_opts* opts,
+                       int32_t adjoint, const int32_t* n_rhs, const void* const* b,
+                       void* const* x, const double* const* tol, int32_t use_x0, void* stream,
+                       dc_solve_stats* const* stats);
+
 /* Gradient of a real loss with respect to the hop blocks, given lambda =
  * D^{-H} dL/dx and x (device complex128 [V][n]).
  *   tied = 0: grad device complex128 [V][8][n][n]; direction mu < 4 is the

@@ -218,6 +218,33 @@ class CoarseOp:
                                              int(x0 is not None), _stream_ptr(stream), stats))
         return x, [stats[i].as_dict() for i in range(R)], rc
 
+    @staticmethod
+    def solve_multi(ops, bs, tols, opts: "Opts | None" = None, adjoint=False, stream=None):
+        """Mixed batch of lattices: ops[i] solves bs[i] ([R_i, V_i, n] complex128)
+        to tolerances tols[i] (scalar or [R_i]), all in lockstep with one
+        multi-apply launch per step over every operator's sites.
+        Returns ([x_i], [[stats per right-hand side] per operator], rc)."""
+        opts = opts or Opts()
+        G = len(ops)
+        assert G == len(bs) == len(tols) and G >= 1
+        bb = [b.contiguous() for b in bs]
+        xs = [torch.empty_like(b) for b in bb]
+        R = [b.shape[0] for b in bb]
+        for op, b in zip(ops, bb):
+            assert b.dtype == torch.complex128 and b.shape[1:] == (op.V, op.n)
+        tl = [np.broadcast_to(np.asarray(t, dtype=np.float64), (r,)).copy() for t, r in zip(tols, R)]
+        stats = [(_lib.SolveStats * max(r, 1))() for r in R]
+        hs = (C.c_void_p * G)(*[op._h for op in ops])
+        nr = (C.c_int32 * G)(*R)
+        bp = (C.c_void_p * G)(*[b.data_ptr() for b in bb])
+        xp = (C.c_void_p * G)(*[x.data_ptr() for x in xs])
+        tp = (C.POINTER(C.c_double) * G)(*[t.ctypes.data_as(C.POINTER(C.c_double)) for t in tl])
+        sp = (C.POINTER(_lib.SolveStats) * G)(*[C.cast(s, C.POINTER(_lib.SolveStats)) for s in stats])
+        o = opts.to_c()
+        rc = check(load().solve_coarse_multi(hs, G, C.byref(o), int(adjoint), nr, bp, xp, tp, 0,
+                                             _stream_ptr(stream), sp))
+        return xs, [[stats[g][i].as_dict() for i in range(R[g])] for g in range(G)], rc
+
     # -- diagnostics
     def profile_apply(self, every: int = 1):
         """Start (clearing the totals) HIP-event timing of one in `every`

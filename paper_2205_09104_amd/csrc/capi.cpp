@@ -248,6 +248,41 @@ int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, i
   });
 }
 
+int solve_coarse_multi(const dc_op_t* ops, int32_t n_ops, const dc_solve_opts* opts,
+                       int32_t adjoint, const int32_t* n_rhs, const void* const* b,
+                       void* const* x, const double* const* tol, int32_t use_x0, void* stream,
+                       dc_solve_stats* const* stats) {
+  return guarded([&] {
+    if (!ops || !opts || !n_rhs || !b || !x || !tol || n_ops < 1)
+      throw dc::InvalidArg("null argument or n_ops < 1");
+    std::vector<dc::Op*> o(n_ops);
+    std::vector<int> R(n_ops);
+    std::vector<const void*> bb(n_ops);
+    std::vector<void*> xx(n_ops);
+    std::vector<const double*> tt(n_ops);
+    std::vector<std::vector<dc::SolveStats>> st(n_ops);
+    std::vector<dc::SolveStats*> sp(n_ops);
+    for (int i = 0; i < n_ops; ++i) {
+      if (!ops[i]) throw dc::InvalidArg("null operator handle");
+      o[i] = &ops[i]->op;
+      R[i] = n_rhs[i];
+      if (R[i] < 0) throw dc::InvalidArg("negative n_rhs");
+      bb[i] = b[i];
+      xx[i] = x[i];
+      tt[i] = tol[i];
+      st[i].resize(R[i]);
+      sp[i] = st[i].data();
+    }
+    const int rc = dc::op_solve_multi(o, convert(opts), adjoint, R, bb, xx, tt, use_x0,
+                                      as_stream(stream), sp);
+    if (stats)
+      for (int i = 0; i < n_ops; ++i)
+        if (stats[i])
+          for (int r = 0; r < R[i]; ++r) copy_stats(st[i][r], stats[i] + r);
+    return rc == 0 ? DC_OK : DC_NOT_CONVERGED;
+  });
+}
+
 int dc_grad_hops(dc_op_t op, const void* lambda, const void* x, void* grad, int32_t tied,
                  void* stream) {
   return guarded([&] {

@@ -784,19 +784,51 @@ struct Mfma<double> {
 // waves; each tile keeps a real and an imaginary accumulator.
 constexpr int kMultiMaxTiles = 4;
 
+// The grid runs over a work list of the sites of up to kMaxMultiOps operators
+// (a mixed batch of lattices with one block size n): workgroup x belongs to the
+// operator whose site range [site0, site0 + V) contains it; grid.y tiles the
+// right-hand sides of the operator with the most, tiles past an operator's own
+// count exit at entry.
 template <int NP, int P, typename VT>
-__global__ __launch_bounds__(256) void k_apply_multi(
-    const void* __restrict__ blocks, const float* __restrict__ scales,
-    const cx<VT>* const* __restrict__ xin, cx<VT>* const* __restrict__ yout, int R,
-    const int* __restrict__ nbr, int V, int n, double tm, int g5io) {
+__global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
   using acc_t = typename Mfma<VT>::acc_t;
+  // select this workgroup's operator (uniform; fields copied by select so the
+  // kernel-argument array is never indexed dynamically)
+  int o = 0;
+#pragma unroll
+  for (int i = 1; i < kMaxMultiOps; ++i)
+    if (i < ops.n_ops && int(blockIdx.x) >= ops.op[i].site0) o = i;
+  const void* blocks = ops.op[0].blocks;
+  const float* scales = ops.op[0].scales;
+  const int* nbr = ops.op[0].nbr;
+  const void* const* xin_v = ops.op[0].xin;
+  void* const* yout_v = ops.op[0].yout;
+  int V = ops.op[0].V, R = ops.op[0].R, site0 = ops.op[0].site0;
+  double tm = ops.op[0].tm;
+#pragma unroll
+  for (int i = 1; i < kMaxMultiOps; ++i)
+    if (i == o) {
+      blocks = ops.op[i].blocks;
+      scales = ops.op[i].scales;
+      nbr = ops.op[i].nbr;
+      xin_v = ops.op[i].xin;
+      yout_v = ops.op[i].yout;
+      V = ops.op[i].V;
+      R = ops.op[i].R;
+      site0 = ops.op[i].site0;
+      tm = ops.op[i].tm;
+    }
+  const int n = ops.n, g5io = ops.g5io;
+  const auto* const* xin = reinterpret_cast<const cx<VT>* const*>(xin_v);
+  auto* const* yout = reinterpret_cast<cx<VT>* const*>(yout_v);
+  if (int(blockIdx.y) * 64 >= R) return;
   constexpr int LD = NP + 1;                  // padded row stride of every LDS plane
   extern __shared__ unsigned char smem[];
   VT* Mr = reinterpret_cast<VT*>(smem);       // [NP][LD] coupling matrix, real part
   VT* Mi = Mr + NP * LD;                      // imaginary part
   VT* Pr = Mi + NP * LD;                      // [64][LD] panel: row r = x_r at the source
   VT* Pi = Pr + 64 * LD;
-  const int site = blockIdx.x;
+  const int site = int(blockIdx.x) - site0;
   const int r0 = blockIdx.y * 64;
   const int Rc = min(64, R - r0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1602,38 +1634,61 @@ size_t multi_lds_bytes(int n, bool dbl) {
 }
 
 template <int NP, int P, typename VT>
-static void multi_launch(int n, int V, const void* blocks, const float* scales,
-                         const void* const* xin, void* const* yout, int R, const int* nbr,
-                         double tm, int g5io, hipStream_t st) {
-  const size_t lds = multi_lds_bytes(n, sizeof(VT) == 8);
+static void multi_launch(const MultiOps& ops, unsigned sites, unsigned rtiles, hipStream_t st) {
+  const size_t lds = multi_lds_bytes(ops.n, sizeof(VT) == 8);
   DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<NP, P, VT>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  const dim3 grid(unsigned(V), unsigned((R + 63) / 64)), block(256);
-  hipLaunchKernelGGL((k_apply_multi<NP, P, VT>), grid, block, lds, st, blocks, scales,
-                     reinterpret_cast<const cx<VT>* const*>(xin),
-                     reinterpret_cast<cx<VT>* const*>(yout), R, nbr, V, n, tm, g5io);
+  hipLaunchKernelGGL((k_apply_multi<NP, P, VT>), dim3(sites, rtiles), dim3(256), lds, st, ops);
   DC_HIP(hipGetLastError());
 }
 
 template <int NP>
-static void multi_np_launch(Prec p, int n, int V, const void* blocks, const float* scales,
-                            const void* const* xin, void* const* yout, int R, const int* nbr,
-                            double tm, int g5io, hipStream_t st) {
-  if (p == P64) multi_launch<NP, P64, double>(n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st);
-  else if (p == P32) multi_launch<NP, P32, float>(n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st);
-  else multi_launch<NP, P16S, float>(n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st);
+static void multi_np_launch(Prec p, const MultiOps& ops, unsigned sites, unsigned rtiles,
+                            hipStream_t st) {
+  if (p == P64) multi_launch<NP, P64, double>(ops, sites, rtiles, st);
+  else if (p == P32) multi_launch<NP, P32, float>(ops, sites, rtiles, st);
+  else multi_launch<NP, P16S, float>(ops, sites, rtiles, st);
+}
+
+void launch_apply_multi_ops(Prec p, int n, const MultiOpDesc* desc, int n_ops, int g5io,
+                            hipStream_t st) {
+  if (n_ops < 1 || n_ops > kMaxMultiOps) throw InvalidArg("1..8 operators per multi-apply");
+  MultiOps ops{};
+  ops.n_ops = n_ops;
+  ops.n = n;
+  ops.g5io = g5io;
+  unsigned sites = 0;
+  int rmax = 0;
+  for (int i = 0; i < n_ops; ++i) {
+    ops.op[i] = desc[i];
+    ops.op[i].site0 = int(sites);
+    sites += unsigned(desc[i].V);
+    rmax = std::max(rmax, desc[i].R);
+  }
+  if (rmax <= 0 || sites == 0) return;
+  const unsigned rtiles = unsigned((rmax + 63) / 64);
+  switch (multi_np(n)) {
+    case 16: multi_np_launch<16>(p, ops, sites, rtiles, st); break;
+    case 32: multi_np_launch<32>(p, ops, sites, rtiles, st); break;
+    case 48: multi_np_launch<48>(p, ops, sites, rtiles, st); break;
+    case 64: multi_np_launch<64>(p, ops, sites, rtiles, st); break;
+    default: throw InvalidArg("block size n > 64 is not supported");
+  }
 }
 
 void launch_apply_multi(Prec p, int n, int V, const void* blocks, const float* scales,
                         const void* const* xin, void* const* yout, int R, const int* nbr, double tm,
                         int g5io, hipStream_t st) {
-  switch (multi_np(n)) {
-    case 16: multi_np_launch<16>(p, n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st); break;
-    case 32: multi_np_launch<32>(p, n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st); break;
-    case 48: multi_np_launch<48>(p, n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st); break;
-    case 64: multi_np_launch<64>(p, n, V, blocks, scales, xin, yout, R, nbr, tm, g5io, st); break;
-    default: throw InvalidArg("block size n > 64 is not supported");
-  }
+  MultiOpDesc d{};
+  d.blocks = blocks;
+  d.scales = scales;
+  d.nbr = nbr;
+  d.xin = xin;
+  d.yout = yout;
+  d.V = V;
+  d.R = R;
+  d.tm = tm;
+  launch_apply_multi_ops(p, n, &d, 1, g5io, st);
 }
 
 void launch_gather_store(Prec p, int n, int V, const void* gbuf, void* out, const int* done,

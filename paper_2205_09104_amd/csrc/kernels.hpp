@@ -78,6 +78,25 @@ void launch_apply_multi(Prec p, int n, int V, const void* blocks, const float* s
                         const void* const* xin, void* const* yout, int R, const int* nbr, double tm,
                         int g5io, hipStream_t st);
 size_t multi_lds_bytes(int n, bool dbl);
+// The same over a work list of several operators with one block size n (a
+// mixed batch of lattices): operator i contributes V sites and R right-hand
+// sides (its own pointer arrays xin/yout, twisted mass tm); one launch.
+constexpr int kMaxMultiOps = 8;
+struct MultiOpDesc {
+  const void* blocks = nullptr;
+  const float* scales = nullptr;
+  const int* nbr = nullptr;
+  const void* const* xin = nullptr;
+  void* const* yout = nullptr;
+  int V = 0, R = 0, site0 = 0;   // site0: set by the launcher
+  double tm = 0.0;
+};
+struct MultiOps {
+  MultiOpDesc op[kMaxMultiOps];
+  int n_ops, n, g5io;
+};
+void launch_apply_multi_ops(Prec p, int n, const MultiOpDesc* desc, int n_ops, int g5io,
+                            hipStream_t st);
 // batched polynomial-chain step over R vectors (device pointer arrays):
 //   first:  prod = v - ca t;  y = c0 v + cb prod;   else: prod -= ca t;  y += cb prod
 void launch_chain_multi(Prec p, const void* const* t, const void* const* v, void* const* prod,

@@ -1062,69 +1062,107 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
 }
 
 // ============================================================================ batched
-// R right-hand sides solved in lockstep (independent Krylov spaces, one MFMA
-// multi-apply per step for all active right-hand sides): restarted GMRES(m)
-// with the variant's polynomial and block-Jacobi preconditioners and, when the
-// variant already holds a recycle space, deflation against it (frozen: the
-// shared space is not refreshed by the batch).  Converged right-hand sides
-// drop out of the active set at cycle ends.
+// Right-hand sides solved in lockstep (independent Krylov spaces, one MFMA
+// multi-apply per step for all active right-hand sides of all operators):
+// restarted GMRES(m) with each operator's polynomial and block-Jacobi
+// preconditioners and, when its variant already holds a recycle space,
+// deflation against it (frozen: the shared space is not refreshed by the
+// batch).  A batch holds one group per operator (a mixed batch of lattices
+// with one block size); converged right-hand sides drop out of the active set
+// at cycle ends.
 
 namespace {
 
 template <typename VR>
 struct Batch {
   using Z = cx<VR>;
-  Op& op;
-  Variant& var;
+  struct Group {
+    Op* op;
+    Variant* var;
+    size_t N;
+    int R;                                          // columns of this operator
+    SolveOpts ko;                                   // options of its Krylov objects
+    std::vector<std::unique_ptr<Krylov<VR>>> K;     // per column
+    std::vector<int> act;                           // active columns
+    size_t toff = 0;                                // offset of its tables (pointers)
+    std::vector<const Z*> b;
+    std::vector<Z*> x;
+  };
   const SolveOpts& o;
   Prec p;
   hipStream_t st;
-  size_t N;
-  int R;
-  std::vector<std::unique_ptr<Krylov<VR>>> K;
-  std::vector<int> act;           // active right-hand sides
-  DevBuf tab;                     // device pointer tables for the active set
+  std::vector<Group> g;
+  DevBuf& tab;                    // device pointer tables of the active sets
+  std::vector<void*> htab;        // host copy
   int ldh;
   long matvecs = 0;
-  // table layout (pointers): [slot][Ra]
+  // per group, table layout (pointers): [slot][Ra_g]
   enum { T_PROD, T_Y, T_TA, T_TB, T_TMP, T_TMP2, T_X, T_B, T_RT, T_NFIX };
 
-  Batch(Op& op_, Variant& v, const SolveOpts& o_, int R_, hipStream_t st_,
-        std::vector<DevBuf>& ws, std::vector<DevBuf>& sm)
-      : op(op_), var(v), o(o_), p(v.prec), st(st_), N(op_.N()), R(R_) {
-    SolveOpts ko = o;
-    ko.k = var.kcur;  // dot-product arrays sized for the (frozen) deflation space
-    for (int r = 0; r < R; ++r)
-      K.emplace_back(std::make_unique<Krylov<VR>>(op, var, ko, ws[r], sm[r], o.m, st, false));
-    ldh = K[0]->ldh;
+  Batch(const std::vector<Op*>& ops, const std::vector<Variant*>& vars, const SolveOpts& o_,
+        const std::vector<int>& R, hipStream_t st_, DevBuf& tab_)
+      : o(o_), p(vars[0]->prec), st(st_), tab(tab_) {
+    g.resize(ops.size());
+    for (size_t i = 0; i < ops.size(); ++i) {
+      Group& gr = g[i];
+      gr.op = ops[i];
+      gr.var = vars[i];
+      gr.N = ops[i]->N();
+      gr.R = R[i];
+      gr.ko = o;
+      gr.ko.k = vars[i]->kcur;  // dot-product arrays sized for the (frozen) deflation space
+      Op& op = *ops[i];
+      op.bws.resize(std::max<size_t>(op.bws.size(), size_t(R[i])));
+      op.bsm.resize(std::max<size_t>(op.bsm.size(), size_t(R[i])));
+      for (int r = 0; r < R[i]; ++r)
+        gr.K.emplace_back(std::make_unique<Krylov<VR>>(op, *vars[i], gr.ko, op.bws[r], op.bsm[r],
+                                                       o.m, st, false));
+    }
+    ldh = std::max(o.m, std::max(o.d, 1)) + 2;  // as every Krylov object of the batch
+    for (const Group& gr : g)
+      if (!gr.K.empty() && gr.K[0]->ldh != ldh) throw BadState("batched Krylov size mismatch");
   }
 
-  // pointer tables of the current active set: fixed slots, then basis V_j
-  const Z* const* fixed(int slot) const {
-    return reinterpret_cast<const Z* const*>(tab.as<void*>() + size_t(slot) * act.size());
+  // device pointer array of slot s of group gi (T_NFIX + j: basis vector j)
+  Z* const* slot(int gi, int s) const {
+    return reinterpret_cast<Z* const*>(static_cast<void**>(tab.p) + g[gi].toff + size_t(s) * g[gi].act.size());
   }
-  Z* const* fixedw(int slot) const {
-    return reinterpret_cast<Z* const*>(tab.as<void*>() + size_t(slot) * act.size());
+  std::vector<Z*> host_slot(int gi, int s) const {
+    const size_t Ra = g[gi].act.size(), off = g[gi].toff + size_t(s) * Ra;
+    std::vector<Z*> out(Ra);
+    for (size_t a = 0; a < Ra; ++a) out[a] = static_cast<Z*>(htab[off + a]);
+    return out;
   }
-  Z* const* basis(int j) const {
-    return reinterpret_cast<Z* const*>(tab.as<void*>() + size_t(T_NFIX + j) * act.size());
+  bool any_active() const {
+    for (const Group& gr : g)
+      if (!gr.act.empty()) return true;
+    return false;
   }
 
-  void upload_tables(const std::vector<Z*>& x, const std::vector<const Z*>& b) {
-    const size_t Ra = act.size();
-    std::vector<void*> h((T_NFIX + ldh + 1) * Ra);
-    for (size_t a = 0; a < Ra; ++a) {
-      Krylov<VR>& k = *K[act[a]];
-      h[T_PROD * Ra + a] = k.prod;
-      h[T_Y * Ra + a] = k.ybuf;
-      h[T_TA * Ra + a] = k.ta;
-      h[T_TB * Ra + a] = k.tb;
-      h[T_TMP * Ra + a] = k.tmp;
-      h[T_TMP2 * Ra + a] = k.tmp2;
-      h[T_X * Ra + a] = x[act[a]];
-      h[T_B * Ra + a] = const_cast<Z*>(b[act[a]]);
-      h[T_RT * Ra + a] = k.rtrue;
-      for (int j = 0; j <= ldh; ++j) h[(T_NFIX + j) * Ra + a] = k.V(j);
+  void upload_tables() {
+    const int ns = T_NFIX + ldh + 1;
+    size_t total = 0;
+    for (Group& gr : g) {
+      gr.toff = total;
+      total += size_t(ns) * gr.act.size();
+    }
+    std::vector<void*> h(std::max<size_t>(total, 1));
+    for (Group& gr : g) {
+      const size_t Ra = gr.act.size();
+      for (size_t a = 0; a < Ra; ++a) {
+        Krylov<VR>& k = *gr.K[gr.act[a]];
+        void** t = h.data() + gr.toff;
+        t[T_PROD * Ra + a] = k.prod;
+        t[T_Y * Ra + a] = k.ybuf;
+        t[T_TA * Ra + a] = k.ta;
+        t[T_TB * Ra + a] = k.tb;
+        t[T_TMP * Ra + a] = k.tmp;
+        t[T_TMP2 * Ra + a] = k.tmp2;
+        t[T_X * Ra + a] = gr.x[gr.act[a]];
+        t[T_B * Ra + a] = const_cast<Z*>(gr.b[gr.act[a]]);
+        t[T_RT * Ra + a] = k.rtrue;
+        for (int j = 0; j <= ldh; ++j) t[(T_NFIX + j) * Ra + a] = k.V(j);
+      }
     }
     tab.ensure(h.size() * sizeof(void*));
     DC_HIP(hipMemcpyAsync(tab.p, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice, st));
@@ -1132,364 +1170,518 @@ struct Batch {
     htab = std::move(h);
   }
 
-  std::vector<void*> htab;  // host copy of the device pointer tables
-
-  // host copy of the Ra pointers of a device table slot
-  template <typename PT>
-  std::vector<Z*> host_of(PT dev) const {
-    const size_t off = size_t(reinterpret_cast<const char*>(dev) - static_cast<const char*>(tab.p)) / sizeof(void*);
-    std::vector<Z*> out(act.size());
-    for (size_t a = 0; a < act.size(); ++a) out[a] = static_cast<Z*>(htab[off + a]);
-    return out;
+  // one multi-apply over every group with active columns: slot `out` = D slot `in`
+  void multi_apply(Prec pa, int in, int out) {
+    std::vector<MultiOpDesc> d;
+    int n = 0;
+    for (size_t gi = 0; gi < g.size(); ++gi) {
+      const Group& gr = g[gi];
+      if (gr.act.empty()) continue;
+      MultiOpDesc e{};
+      e.blocks = gr.op->blocks(pa);
+      e.scales = gr.op->scales(pa);
+      e.nbr = static_cast<const int*>(gr.op->nbr.p);
+      e.xin = reinterpret_cast<const void* const*>(slot(int(gi), in));
+      e.yout = reinterpret_cast<void* const*>(slot(int(gi), out));
+      e.V = gr.op->V;
+      e.R = int(gr.act.size());
+      e.tm = gr.var->sign * gr.op->mu;
+      d.push_back(e);
+      n = gr.op->n;
+    }
+    for (size_t i = 0; i < d.size(); i += kMaxMultiOps)
+      launch_apply_multi_ops(pa, n, d.data() + i, int(std::min<size_t>(kMaxMultiOps, d.size() - i)),
+                             0, st);
   }
 
-  // out_a = A~ in_a for the active set (A~ = B^{-1} D with block Jacobi)
-  void A(const Z* const* in, Z* const* out) {
-    const int Ra = int(act.size());
-    const bool bj = K[0]->bjinv != nullptr;
-    launch_apply_multi(p, op.n, op.V, op.blocks(p), op.scales(p),
-                       reinterpret_cast<const void* const*>(in),
-                       reinterpret_cast<void* const*>(bj ? fixedw(T_TB) : out), Ra,
-                       op.nbr.as<int>(), var.sign * op.mu, 0, st);
-    if (bj) {
-      const std::vector<Z*> ho = host_of(out);
-      for (int a = 0; a < Ra; ++a)
-        launch_bj_vec(p, op.n, op.V, K[0]->bjinv, K[0]->bjsc, K[act[a]]->tb, ho[a], st);
-    }
+  // slot out = A~ slot in for the active set (A~ = B^{-1} D with block Jacobi)
+  void A(int in, int out) {
+    bool bj = false;
+    for (const Group& gr : g) bj = bj || (!gr.act.empty() && gr.K[0]->bjinv);
+    multi_apply(p, in, bj ? T_TB : out);
+    if (bj)
+      for (size_t gi = 0; gi < g.size(); ++gi) {
+        Group& gr = g[gi];
+        const std::vector<Z*> ho = host_slot(int(gi), out);
+        for (size_t a = 0; a < gr.act.size(); ++a) {
+          Krylov<VR>& k = *gr.K[gr.act[a]];
+          launch_bj_vec(p, gr.op->n, gr.op->V, k.bjinv, k.bjsc, k.tb, ho[a], st);
+        }
+      }
     matvecs += 1;
   }
 
-  // out_a = q(A~) in_a (Newton-like chain), out distinct from in
-  void Q(const Z* const* in, Z* const* out) {
-    const auto& th = var.theta;
-    const int d = int(th.size());
+  static bool has_poly(const Variant& v) { return v.d > 1 && int(v.theta.size()) > 1; }
+
+  // slot out = q(A~) slot in (Newton-like chain per operator), out distinct from in.
+  // Every operator of a batch shares d (same options), each has its own theta.
+  void Q(int in, int out) {
     auto inv = [](cd t) { const cd r = 1.0 / t; return mk(r.real(), r.imag()); };
-    const int Ra = int(act.size());
+    const int d = int(g[0].var->theta.size());
     if (d <= 1) {
-      const std::vector<Z*> ho = host_of(out);
-      const std::vector<Z*> hi = host_of(in);
-      const z64 c = (d == 1) ? inv(th[0]) : mk(1.0, 0.0);
-      for (int a = 0; a < Ra; ++a) launch_cscale(p, hi[a], ho[a], N, c, nullptr, st);
+      for (size_t gi = 0; gi < g.size(); ++gi) {
+        Group& gr = g[gi];
+        const std::vector<Z*> ho = host_slot(int(gi), out), hi = host_slot(int(gi), in);
+        const auto& th = gr.var->theta;
+        const z64 c = (int(th.size()) == 1) ? inv(th[0]) : mk(1.0, 0.0);
+        for (size_t a = 0; a < gr.act.size(); ++a) launch_cscale(p, hi[a], ho[a], gr.N, c, nullptr, st);
+      }
       return;
     }
-    A(in, fixedw(T_TA));
-    launch_chain_multi(p, reinterpret_cast<const void* const*>(fixed(T_TA)),
-                       reinterpret_cast<const void* const*>(in),
-                       reinterpret_cast<void* const*>(fixedw(T_PROD)),
-                       reinterpret_cast<void* const*>(out), Ra, N, inv(th[0]), inv(th[0]),
-                       inv(th[1]), 1, st);
+    A(in, T_TA);
+    for (size_t gi = 0; gi < g.size(); ++gi) {
+      const Group& gr = g[gi];
+      if (gr.act.empty()) continue;
+      const auto& th = gr.var->theta;
+      launch_chain_multi(p, reinterpret_cast<const void* const*>(slot(int(gi), T_TA)),
+                         reinterpret_cast<const void* const*>(slot(int(gi), in)),
+                         reinterpret_cast<void* const*>(slot(int(gi), T_PROD)),
+                         reinterpret_cast<void* const*>(slot(int(gi), out)), int(gr.act.size()),
+                         gr.N, inv(th[0]), inv(th[0]), inv(th[1]), 1, st);
+    }
     for (int i = 2; i < d; ++i) {
-      A(fixed(T_PROD), fixedw(T_TA));
-      launch_chain_multi(p, reinterpret_cast<const void* const*>(fixed(T_TA)), nullptr,
-                         reinterpret_cast<void* const*>(fixedw(T_PROD)),
-                         reinterpret_cast<void* const*>(out), Ra, N, mk(0.0, 0.0), inv(th[i - 1]),
-                         inv(th[i]), 0, st);
+      A(T_PROD, T_TA);
+      for (size_t gi = 0; gi < g.size(); ++gi) {
+        const Group& gr = g[gi];
+        if (gr.act.empty()) continue;
+        const auto& th = gr.var->theta;
+        launch_chain_multi(p, reinterpret_cast<const void* const*>(slot(int(gi), T_TA)), nullptr,
+                           reinterpret_cast<void* const*>(slot(int(gi), T_PROD)),
+                           reinterpret_cast<void* const*>(slot(int(gi), out)), int(gr.act.size()),
+                           gr.N, mk(0.0, 0.0), inv(th[i - 1]), inv(th[i]), 0, st);
+      }
     }
   }
 
-  void Ahat(const Z* const* in, Z* const* out) {
-    if (var.d > 1 && int(var.theta.size()) > 1) {
-      Q(in, fixedw(T_Y));
-      A(fixed(T_Y), out);
+  void Ahat(int in, int out) {
+    if (has_poly(*g[0].var)) {
+      Q(in, T_Y);
+      A(T_Y, out);
     } else {
       A(in, out);
     }
   }
 
-  // true residuals r_a = b_a - D x_a (in the batch precision); returns ||r_a||
-  std::vector<double> true_resid() {
-    const int Ra = int(act.size());
-    launch_apply_multi(p, op.n, op.V, op.blocks(p), op.scales(p),
-                       reinterpret_cast<const void* const*>(fixed(T_X)),
-                       reinterpret_cast<void* const*>(fixedw(T_TA)), Ra, op.nbr.as<int>(),
-                       var.sign * op.mu, 0, st);
+  // true residuals r = b - D x (in the batch precision) for every active column
+  std::vector<std::vector<double>> true_resid() {
+    multi_apply(p, T_X, T_TA);
     matvecs += 1;
-    std::vector<double> rn(Ra);
-    for (int a = 0; a < Ra; ++a) {
-      Krylov<VR>& k = *K[act[a]];
-      launch_scale(p, k.ta, k.rtrue, N, nullptr, -1.0, nullptr, st);
-      launch_axpy(p, mk(1.0, 0.0), bptr[act[a]], k.rtrue, N, st);
-      launch_norm2(p, k.rtrue, N, op.red(), k.nrm, st);
+    std::vector<std::vector<double>> rn(g.size());
+    for (Group& gr : g) {
+      for (int c : gr.act) {
+        Krylov<VR>& k = *gr.K[c];
+        launch_scale(p, k.ta, k.rtrue, gr.N, nullptr, -1.0, nullptr, st);
+        launch_axpy(p, mk(1.0, 0.0), gr.b[c], k.rtrue, gr.N, st);
+        launch_norm2(p, k.rtrue, gr.N, gr.op->red(), k.nrm, st);
+      }
     }
-    for (int a = 0; a < Ra; ++a) {
-      DC_HIP(hipMemcpyAsync(&rn[a], K[act[a]]->nrm, sizeof(double), hipMemcpyDeviceToHost, st));
-      DC_HIP(hipStreamSynchronize(st));
-      rn[a] = std::sqrt(std::max(rn[a], 0.0));
+    for (size_t gi = 0; gi < g.size(); ++gi) {
+      Group& gr = g[gi];
+      rn[gi].resize(gr.act.size());
+      for (size_t a = 0; a < gr.act.size(); ++a) {
+        DC_HIP(hipMemcpyAsync(&rn[gi][a], gr.K[gr.act[a]]->nrm, sizeof(double),
+                              hipMemcpyDeviceToHost, st));
+        DC_HIP(hipStreamSynchronize(st));
+        rn[gi][a] = std::sqrt(std::max(rn[gi][a], 0.0));
+      }
     }
     return rn;
   }
 
-  std::vector<const Z*> bptr;
-
-  // Solve D x_r = b_r for all r to tolerances tol[r]; returns converged flags.
-  std::vector<int> solve(const std::vector<const Z*>& b, const std::vector<Z*>& x,
-                         const std::vector<double>& tol, bool use_x0, int max_cycles,
-                         std::vector<SolveStats>& stt, std::vector<double>& relres) {
-    bptr = b;
-    std::vector<int> conv(R, 0);
-    std::vector<double> bn(R);
-    for (int r = 0; r < R; ++r) {
-      if (!use_x0) launch_zero(p, x[r], N, st);
-      bn[r] = K[r]->norm(b[r]);
-      if (bn[r] == 0.0) {
-        launch_zero(p, x[r], N, st);
-        conv[r] = 1;
-        relres[r] = 0.0;
+  // Solve D_g x_{g,r} = b_{g,r} to tolerances tol[g][r]; stt, relres likewise indexed.
+  void solve(bool use_x0, int max_cycles, const std::vector<std::vector<double>>& tol,
+             std::vector<std::vector<SolveStats>>& stt, std::vector<std::vector<double>>& relres) {
+    const int steps_req = o.m;
+    std::vector<std::vector<int>> conv(g.size()), cycles(g.size());
+    std::vector<std::vector<double>> bn(g.size());
+    for (size_t gi = 0; gi < g.size(); ++gi) {
+      Group& gr = g[gi];
+      conv[gi].assign(gr.R, 0);
+      cycles[gi].assign(gr.R, 0);
+      bn[gi].assign(gr.R, 0.0);
+      for (int r = 0; r < gr.R; ++r) {
+        if (!use_x0) launch_zero(p, gr.x[r], gr.N, st);
+        bn[gi][r] = gr.K[r]->norm(gr.b[r]);
+        if (bn[gi][r] == 0.0) {
+          launch_zero(p, gr.x[r], gr.N, st);
+          conv[gi][r] = 1;
+          relres[gi][r] = 0.0;
+        }
       }
+      if (gr.R > 0 && std::min(steps_req - gr.var->kcur, ldh - 2) < 1)
+        throw InvalidArg("batched solve needs m > k");
     }
-    const int kC = var.kcur;
-    const bool poly = var.d > 1 && int(var.theta.size()) > 1;
-    const int steps = std::min(o.m - kC, ldh - 2);
-    if (steps < 1) throw InvalidArg("batched solve needs m > k");
-    std::vector<int> cycles(R, 0);
+    const bool poly = has_poly(*g[0].var);
     for (int cyc = 0;; ++cyc) {
-      act.clear();
-      for (int r = 0; r < R; ++r)
-        if (!conv[r] && cycles[r] <= max_cycles) act.push_back(r);
-      if (act.empty()) break;
-      upload_tables(x, b);
+      for (size_t gi = 0; gi < g.size(); ++gi) {
+        Group& gr = g[gi];
+        gr.act.clear();
+        for (int r = 0; r < gr.R; ++r)
+          if (!conv[gi][r] && cycles[gi][r] <= max_cycles) gr.act.push_back(r);
+      }
+      if (!any_active()) break;
+      upload_tables();
       const long mv0 = matvecs;
-      const std::vector<double> rn = true_resid();
-      std::vector<int> keep;
-      for (size_t a = 0; a < act.size(); ++a) {
-        const int r = act[a];
-        relres[r] = rn[a] / bn[r];
-        stt[r].matvecs += int(matvecs - mv0);
-        if (relres[r] <= tol[r]) conv[r] = 1;
-        else if (cycles[r] < max_cycles) keep.push_back(r);
+      const auto rn = true_resid();
+      bool any = false, changed = false;
+      for (size_t gi = 0; gi < g.size(); ++gi) {
+        Group& gr = g[gi];
+        std::vector<int> keep;
+        for (size_t a = 0; a < gr.act.size(); ++a) {
+          const int r = gr.act[a];
+          relres[gi][r] = rn[gi][a] / bn[gi][r];
+          stt[gi][r].matvecs += int(matvecs - mv0);
+          if (relres[gi][r] <= tol[gi][r]) conv[gi][r] = 1;
+          else if (cycles[gi][r] < max_cycles) keep.push_back(r);
+        }
+        if (keep.size() != gr.act.size()) changed = true;
+        gr.act = keep;
+        any = any || !keep.empty();
       }
-      if (keep.empty()) break;
-      if (keep.size() != act.size()) {
-        act = keep;
-        upload_tables(x, b);
-      }
-      const int Ra = int(act.size());
+      if (!any) break;
+      if (changed) upload_tables();
       // start vectors: rhat = B^{-1} r, deflated against C (x += q U C^H rhat)
-      std::vector<double> beta(Ra), target(Ra);
-      for (int a = 0; a < Ra; ++a) {
-        Krylov<VR>& k = *K[act[a]];
-        k.left_precondition(k.rtrue, k.rhat);
-        const double b0 = k.bjinv ? k.norm(k.rhat) : rn[a];
-        target[a] = tol[act[a]] * bn[act[a]] * (b0 / std::max(relres[act[a]] * bn[act[a]], 1e-300));
-        if (kC > 0) {
-          launch_multidot(p, k.Cv(), kC, nullptr, 0, N, k.rhat, 0, op.red(), k.res1, nullptr, st);
-          launch_multiaxpy(p, k.rhat, k.Cv(), kC, nullptr, 0, N, k.res1, 0, op.red(), k.nrm,
-                           nullptr, st);
-          launch_combine(p, k.Uv(), kC, nullptr, 0, N, k.res1, 1, k.tmp, 0, st);
+      std::vector<std::vector<double>> beta(g.size()), target(g.size());
+      bool defl = false;
+      for (size_t gi = 0; gi < g.size(); ++gi) {
+        Group& gr = g[gi];
+        const int kC = gr.var->kcur;
+        beta[gi].resize(gr.act.size());
+        target[gi].resize(gr.act.size());
+        for (size_t a = 0; a < gr.act.size(); ++a) {
+          const int r = gr.act[a];
+          Krylov<VR>& k = *gr.K[r];
+          k.left_precondition(k.rtrue, k.rhat);
+          const double rr = relres[gi][r] * bn[gi][r];
+          const double b0 = k.bjinv ? k.norm(k.rhat) : rr;
+          target[gi][a] = tol[gi][r] * bn[gi][r] * (b0 / std::max(rr, 1e-300));
+          if (kC > 0) {
+            launch_multidot(p, k.Cv(), kC, nullptr, 0, gr.N, k.rhat, 0, gr.op->red(), k.res1,
+                            nullptr, st);
+            launch_multiaxpy(p, k.rhat, k.Cv(), kC, nullptr, 0, gr.N, k.res1, 0, gr.op->red(),
+                             k.nrm, nullptr, st);
+            launch_combine(p, k.Uv(), kC, nullptr, 0, gr.N, k.res1, 1, k.tmp, 0, st);
+            defl = true;
+          }
+          beta[gi][a] = (kC > 0) ? k.norm(k.rhat) : b0;
         }
-        beta[a] = (kC > 0) ? k.norm(k.rhat) : b0;
       }
-      if (kC > 0) {  // x += q(A~) U c for all active right-hand sides
-        if (poly) Q(fixed(T_TMP), fixedw(T_TMP2));
-        for (int a = 0; a < Ra; ++a) {
-          Krylov<VR>& k = *K[act[a]];
-          launch_axpy(p, mk(1.0, 0.0), poly ? k.tmp2 : k.tmp, x[act[a]], N, st);
+      if (defl) {  // x += q(A~) U c for the active columns of deflated groups
+        if (poly) Q(T_TMP, T_TMP2);
+        for (Group& gr : g) {
+          if (gr.var->kcur == 0) continue;
+          for (int r : gr.act) {
+            Krylov<VR>& k = *gr.K[r];
+            launch_axpy(p, mk(1.0, 0.0), poly ? k.tmp2 : k.tmp, gr.x[r], gr.N, st);
+          }
         }
       }
-      for (int a = 0; a < Ra; ++a) {
-        Krylov<VR>& k = *K[act[a]];
-        launch_scale(p, k.rhat, k.V(0), N, nullptr, 1.0 / beta[a], nullptr, st);
-        launch_arnoldi_init(k.ad, beta[a], st);
+      for (size_t gi = 0; gi < g.size(); ++gi) {
+        Group& gr = g[gi];
+        for (size_t a = 0; a < gr.act.size(); ++a) {
+          Krylov<VR>& k = *gr.K[gr.act[a]];
+          launch_scale(p, k.rhat, k.V(0), gr.N, nullptr, 1.0 / beta[gi][a], nullptr, st);
+          launch_arnoldi_init(k.ad, beta[gi][a], st);
+        }
       }
       const long mv1 = matvecs;
+      int steps = ldh - 2;
+      for (const Group& gr : g)
+        if (!gr.act.empty()) steps = std::min(steps, steps_req - gr.var->kcur);
       for (int j = 0; j < steps; ++j) {
-        Ahat(basis(j), basis(j + 1));
-        for (int a = 0; a < Ra; ++a) K[act[a]]->orth_step(j, kC, steps, target[a]);
+        Ahat(T_NFIX + j, T_NFIX + j + 1);
+        for (size_t gi = 0; gi < g.size(); ++gi) {
+          Group& gr = g[gi];
+          for (size_t a = 0; a < gr.act.size(); ++a)
+            gr.K[gr.act[a]]->orth_step(j, gr.var->kcur, steps, target[gi][a]);
+        }
       }
       // per right-hand side: least squares and the update of x
-      for (int a = 0; a < Ra; ++a) {
-        const int r = act[a];
-        Krylov<VR>& k = *K[r];
-        int flags[3];
-        DC_HIP(hipMemcpyAsync(flags, k.ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-        std::vector<double> Hh(2 * size_t(k.ldh) * k.ldh), Bh(2 * size_t(k.ad.ldb) * k.ldh);
-        DC_HIP(hipMemcpyAsync(Hh.data(), k.ad.H, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        if (kC) DC_HIP(hipMemcpyAsync(Bh.data(), k.ad.Bk, Bh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        DC_HIP(hipStreamSynchronize(st));
-        const int jd = flags[1];
-        stt[r].iters += jd;
-        stt[r].matvecs += int(matvecs - mv1);
-        cycles[r] += 1;
-        stt[r].cycles += 1;
-        Mat G(kC + jd + 1, kC + jd);
-        for (int i = 0; i < kC; ++i) G(i, i) = 1.0 / var.unorm[i];
-        for (int jj = 0; jj < jd; ++jj) {
-          for (int i = 0; i < kC; ++i)
-            G(i, kC + jj) = cd(Bh[2 * (size_t(jj) * k.ad.ldb + i)], Bh[2 * (size_t(jj) * k.ad.ldb + i) + 1]);
-          for (int i = 0; i <= jj + 1; ++i)
-            G(kC + i, kC + jj) = cd(Hh[2 * (size_t(jj) * k.ldh + i)], Hh[2 * (size_t(jj) * k.ldh + i) + 1]);
+      for (size_t gi = 0; gi < g.size(); ++gi) {
+        Group& gr = g[gi];
+        const int kC = gr.var->kcur;
+        for (size_t a = 0; a < gr.act.size(); ++a) {
+          const int r = gr.act[a];
+          Krylov<VR>& k = *gr.K[r];
+          int flags[3];
+          DC_HIP(hipMemcpyAsync(flags, k.ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+          std::vector<double> Hh(2 * size_t(k.ldh) * k.ldh), Bh(2 * size_t(k.ad.ldb) * k.ldh);
+          DC_HIP(hipMemcpyAsync(Hh.data(), k.ad.H, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+          if (kC) DC_HIP(hipMemcpyAsync(Bh.data(), k.ad.Bk, Bh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+          DC_HIP(hipStreamSynchronize(st));
+          const int jd = flags[1];
+          stt[gi][r].iters += jd;
+          stt[gi][r].matvecs += int(matvecs - mv1);
+          cycles[gi][r] += 1;
+          stt[gi][r].cycles += 1;
+          Mat G(kC + jd + 1, kC + jd);
+          for (int i = 0; i < kC; ++i) G(i, i) = 1.0 / gr.var->unorm[i];
+          for (int jj = 0; jj < jd; ++jj) {
+            for (int i = 0; i < kC; ++i)
+              G(i, kC + jj) = cd(Bh[2 * (size_t(jj) * k.ad.ldb + i)], Bh[2 * (size_t(jj) * k.ad.ldb + i) + 1]);
+            for (int i = 0; i <= jj + 1; ++i)
+              G(kC + i, kC + jj) = cd(Hh[2 * (size_t(jj) * k.ldh + i)], Hh[2 * (size_t(jj) * k.ldh + i) + 1]);
+          }
+          std::vector<cd> rhs(kC + jd + 1, cd(0.0));
+          rhs[kC] = beta[gi][a];
+          double lsres = 0.0;
+          const auto y = lstsq(G, rhs, &lsres);
+          stt[gi][r].rel_res_est = lsres / bn[gi][r];
+          std::vector<cd> cy(kC + jd);
+          for (int i = 0; i < kC; ++i) cy[i] = y[i] / gr.var->unorm[i];
+          for (int i = 0; i < jd; ++i) cy[kC + i] = y[kC + i];
+          k.upload_coef(cy);
+          launch_combine(p, kC ? k.Uv() : nullptr, kC, k.V(0), jd, gr.N, k.coef, 1,
+                         poly ? k.tmp : gr.x[r], poly ? 0 : 1, st);
         }
-        std::vector<cd> rhs(kC + jd + 1, cd(0.0));
-        rhs[kC] = beta[a];
-        double lsres = 0.0;
-        const auto y = lstsq(G, rhs, &lsres);
-        stt[r].rel_res_est = lsres / bn[r];
-        std::vector<cd> cy(kC + jd);
-        for (int i = 0; i < kC; ++i) cy[i] = y[i] / var.unorm[i];
-        for (int i = 0; i < jd; ++i) cy[kC + i] = y[kC + i];
-        k.upload_coef(cy);
-        launch_combine(p, kC ? k.Uv() : nullptr, kC, k.V(0), jd, N, k.coef, 1,
-                       poly ? k.tmp : x[r], poly ? 0 : 1, st);
       }
       if (poly) {
-        Q(fixed(T_TMP), fixedw(T_TMP2));
-        for (int a = 0; a < Ra; ++a)
-          launch_axpy(p, mk(1.0, 0.0), K[act[a]]->tmp2, x[act[a]], N, st);
+        Q(T_TMP, T_TMP2);
+        for (Group& gr : g)
+          for (int r : gr.act) launch_axpy(p, mk(1.0, 0.0), gr.K[r]->tmp2, gr.x[r], gr.N, st);
       }
     }
-    return conv;
   }
 };
 
 }  // namespace
 
-int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b, void* x,
-                   const double* tol, int use_x0, hipStream_t st, SolveStats* stats) {
-  check_prec(op, o.prec);
-  if (!b || !x || !tol || R < 0) throw InvalidArg("null pointer or negative n_rhs");
+// Batched solve over one or more operators (same block size, precision
+// stored, options); b[g], x[g]: device complex128 [R[g]][V_g][n]; tol[g][r].
+static int solve_groups(const std::vector<Op*>& ops, const SolveOpts& o, int adjoint,
+                        const std::vector<int>& R, const std::vector<const void*>& b,
+                        const std::vector<void*>& x, const std::vector<const double*>& tol,
+                        int use_x0, hipStream_t st, const std::vector<SolveStats*>& stats) {
+  const size_t G = ops.size();
+  if (G == 0) return 0;
   if (o.m < 1 || o.max_cycles < 0) throw InvalidArg("bad solver options");
-  for (int r = 0; r < R; ++r)
-    if (!(tol[r] > 0.0)) throw InvalidArg("tolerances must be positive");
-  if (R == 0) return 0;
-  const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
-  const size_t N = op.N();
+  for (size_t gi = 0; gi < G; ++gi) {
+    if (!ops[gi]) throw InvalidArg("null operator handle");
+    check_prec(*ops[gi], o.prec);
+    if (ops[gi]->n != ops[0]->n) throw InvalidArg("every operator of a batch needs the same n");
+    if (R[gi] < 0 || (R[gi] > 0 && (!b[gi] || !x[gi] || !tol[gi])))
+      throw InvalidArg("null pointer or negative n_rhs");
+    for (int r = 0; r < R[gi]; ++r)
+      if (!(tol[gi][r] > 0.0)) throw InvalidArg("tolerances must be positive");
+    for (size_t gj = 0; gj < gi; ++gj)
+      if (ops[gj] == ops[gi]) throw InvalidArg("an operator appears twice in a batch");
+  }
   const auto t0 = std::chrono::steady_clock::now();
-  std::vector<SolveStats> stt(R);
-  Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d);
-  const auto ts = std::chrono::steady_clock::now();
-  ensure_poly(op, var, o, st, &stt[0]);
-  if (var.recycle_version != op.version || var.k_built != o.k) var.kcur = 0;
-  const double t_setup = ms_since(ts);
-  const int kC = (o.k > 0) ? var.kcur : 0;
-  const int kc_saved = var.kcur;
-  var.kcur = kC;
-  op.bws.resize(std::max<size_t>(op.bws.size(), size_t(R)));
-  op.bsm.resize(std::max<size_t>(op.bsm.size(), size_t(R)));
+  std::vector<std::vector<SolveStats>> stt(G);
+  std::vector<Variant*> vars(G);
+  std::vector<int> kc_saved(G);
+  std::vector<double> t_setup(G, 0.0);
+  for (size_t gi = 0; gi < G; ++gi) {
+    Op& op = *ops[gi];
+    stt[gi].resize(std::max(R[gi], 1));
+    const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
+    Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d);
+    const auto ts = std::chrono::steady_clock::now();
+    ensure_poly(op, var, o, st, &stt[gi][0]);
+    if (var.recycle_version != op.version || var.k_built != o.k) var.kcur = 0;
+    t_setup[gi] = ms_since(ts);
+    kc_saved[gi] = var.kcur;
+    if (o.k <= 0) var.kcur = 0;
+    vars[gi] = &var;
+  }
   // caller vectors (complex128); adjoint through Gamma5 on copies
-  op.bx64.ensure(size_t(R) * N * sizeof(z64));
-  op.bb64.ensure(size_t(R) * N * sizeof(z64));
-  z64* B64 = op.bb64.as<z64>();
-  z64* X64 = op.bx64.as<z64>();
-  for (int r = 0; r < R; ++r) {
-    const z64* br = static_cast<const z64*>(b) + size_t(r) * N;
-    z64* xr = static_cast<z64*>(x) + size_t(r) * N;
-    if (adjoint) {
-      launch_gamma5(P64, br, B64 + size_t(r) * N, op.V, op.n, st);
-      if (use_x0) launch_gamma5(P64, xr, X64 + size_t(r) * N, op.V, op.n, st);
-    } else {
-      DC_HIP(hipMemcpyAsync(B64 + size_t(r) * N, br, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
-      if (use_x0) DC_HIP(hipMemcpyAsync(X64 + size_t(r) * N, xr, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+  std::vector<z64*> B64(G), X64(G);
+  for (size_t gi = 0; gi < G; ++gi) {
+    Op& op = *ops[gi];
+    const size_t N = op.N();
+    op.bx64.ensure(size_t(std::max(R[gi], 1)) * N * sizeof(z64));
+    op.bb64.ensure(size_t(std::max(R[gi], 1)) * N * sizeof(z64));
+    B64[gi] = op.bb64.as<z64>();
+    X64[gi] = op.bx64.as<z64>();
+    for (int r = 0; r < R[gi]; ++r) {
+      const z64* br = static_cast<const z64*>(b[gi]) + size_t(r) * N;
+      const z64* xr = static_cast<const z64*>(x[gi]) + size_t(r) * N;
+      if (adjoint) {
+        launch_gamma5(P64, br, B64[gi] + size_t(r) * N, op.V, op.n, st);
+        if (use_x0) launch_gamma5(P64, xr, X64[gi] + size_t(r) * N, op.V, op.n, st);
+      } else {
+        DC_HIP(hipMemcpyAsync(B64[gi] + size_t(r) * N, br, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+        if (use_x0) DC_HIP(hipMemcpyAsync(X64[gi] + size_t(r) * N, xr, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+      }
     }
   }
-  std::vector<double> tl(tol, tol + R), rel(R, 0.0);
+  std::vector<std::vector<double>> tl(G), rel(G);
+  for (size_t gi = 0; gi < G; ++gi) {
+    tl[gi].assign(tol[gi], tol[gi] + R[gi]);
+    rel[gi].assign(R[gi], 0.0);
+  }
+  DevBuf& tab = ops[0]->ptrs;
   if (o.prec == P64) {
-    Batch<double> Bt(op, var, o, R, st, op.bws, op.bsm);
-    std::vector<const z64*> bp(R);
-    std::vector<z64*> xp(R);
-    for (int r = 0; r < R; ++r) {
-      bp[r] = B64 + size_t(r) * N;
-      xp[r] = X64 + size_t(r) * N;
+    Batch<double> Bt(ops, vars, o, R, st, tab);
+    for (size_t gi = 0; gi < G; ++gi) {
+      const size_t N = ops[gi]->N();
+      for (int r = 0; r < R[gi]; ++r) {
+        Bt.g[gi].b.push_back(B64[gi] + size_t(r) * N);
+        Bt.g[gi].x.push_back(X64[gi] + size_t(r) * N);
+      }
     }
-    Bt.solve(bp, xp, tl, use_x0 != 0, o.max_cycles, stt, rel);
+    Bt.solve(use_x0 != 0, o.max_cycles, tl, stt, rel);
   } else {
     // FP64 iterative refinement around the batched reduced-precision solve:
     // x += ||r|| solve32(D, r / ||r||) until the FP64 residual meets tol
-    if (!use_x0) for (int r = 0; r < R; ++r) launch_zero(P64, X64 + size_t(r) * N, N, st);
-    op.b32.ensure(size_t(R) * N * sizeof(z32));
-    op.x32.ensure(size_t(R) * N * sizeof(z32));
-    op.r64.ensure(size_t(R) * N * sizeof(z64));
-    z32* B32 = op.b32.as<z32>();
-    z32* X32 = op.x32.as<z32>();
-    z64* R64 = op.r64.as<z64>();
-    std::vector<int> done(R, 0);
-    std::vector<double> bn(R);
-    for (int r = 0; r < R; ++r) {
-      launch_norm2(P64, B64 + size_t(r) * N, N, op.red(), op.scal.as<double>(), st);
-      DC_HIP(hipMemcpyAsync(&bn[r], op.scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
-      DC_HIP(hipStreamSynchronize(st));
-      bn[r] = std::sqrt(bn[r]);
-      if (bn[r] == 0.0) done[r] = 1;
+    std::vector<z32*> B32(G), X32(G);
+    std::vector<z64*> R64(G);
+    std::vector<std::vector<int>> done(G);
+    std::vector<std::vector<double>> bn(G);
+    for (size_t gi = 0; gi < G; ++gi) {
+      Op& op = *ops[gi];
+      const size_t N = op.N(), Rg = size_t(std::max(R[gi], 1));
+      if (!use_x0) for (int r = 0; r < R[gi]; ++r) launch_zero(P64, X64[gi] + size_t(r) * N, N, st);
+      op.b32.ensure(Rg * N * sizeof(z32));
+      op.x32.ensure(Rg * N * sizeof(z32));
+      op.r64.ensure(Rg * N * sizeof(z64));
+      B32[gi] = op.b32.as<z32>();
+      X32[gi] = op.x32.as<z32>();
+      R64[gi] = op.r64.as<z64>();
+      done[gi].assign(R[gi], 0);
+      bn[gi].assign(R[gi], 0.0);
+      for (int r = 0; r < R[gi]; ++r) {
+        launch_norm2(P64, B64[gi] + size_t(r) * N, N, op.red(), op.scal.as<double>(), st);
+        DC_HIP(hipMemcpyAsync(&bn[gi][r], op.scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        DC_HIP(hipStreamSynchronize(st));
+        bn[gi][r] = std::sqrt(bn[gi][r]);
+        if (bn[gi][r] == 0.0) done[gi][r] = 1;
+      }
     }
     for (int outer = 0; outer <= o.max_outer; ++outer) {
-      std::vector<int> act;
-      for (int r = 0; r < R; ++r)
-        if (!done[r]) act.push_back(r);
-      if (act.empty()) break;
-      std::vector<const void*> hx, hy;
-      for (int r : act) {
-        hx.push_back(X64 + size_t(r) * N);
-        hy.push_back(R64 + size_t(r) * N);
+      // FP64 residuals of every active column: one multi-apply over all operators
+      std::vector<std::vector<int>> act(G);
+      std::vector<void*> h;
+      std::vector<size_t> off(G);
+      bool any = false;
+      for (size_t gi = 0; gi < G; ++gi) {
+        for (int r = 0; r < R[gi]; ++r)
+          if (!done[gi][r]) act[gi].push_back(r);
+        any = any || !act[gi].empty();
       }
-      std::vector<const void*> h(hx);
-      h.insert(h.end(), hy.begin(), hy.end());
-      op.ptrs.ensure(h.size() * sizeof(void*));
-      DC_HIP(hipMemcpyAsync(op.ptrs.p, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+      if (!any) break;
+      for (size_t gi = 0; gi < G; ++gi) {
+        const size_t N = ops[gi]->N();
+        off[gi] = h.size();
+        for (int r : act[gi]) h.push_back(X64[gi] + size_t(r) * N);
+        for (int r : act[gi]) h.push_back(R64[gi] + size_t(r) * N);
+      }
+      tab.ensure(h.size() * sizeof(void*));
+      DC_HIP(hipMemcpyAsync(tab.p, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice, st));
       DC_HIP(hipStreamSynchronize(st));
-      void** tbl = op.ptrs.as<void*>();
-      launch_apply_multi(P64, op.n, op.V, op.blocks(P64), nullptr, const_cast<const void* const*>(tbl),
-                         tbl + act.size(), int(act.size()), op.nbr.as<int>(), sign * op.mu, 0, st);
-      std::vector<int> inner_r;
-      std::vector<double> scale;
-      for (size_t a = 0; a < act.size(); ++a) {
-        const int r = act[a];
-        z64* rr = R64 + size_t(r) * N;
-        launch_scale(P64, rr, rr, N, nullptr, -1.0, nullptr, st);
-        launch_axpy(P64, mk(1.0, 0.0), B64 + size_t(r) * N, rr, N, st);
-        launch_norm2(P64, rr, N, op.red(), op.scal.as<double>(), st);
-        double h2;
-        DC_HIP(hipMemcpyAsync(&h2, op.scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
-        DC_HIP(hipStreamSynchronize(st));
-        const double rn = std::sqrt(std::max(h2, 0.0));
-        rel[r] = rn / bn[r];
-        if (rel[r] <= tl[r] || outer == o.max_outer) {
-          done[r] = 1;
-          continue;
+      std::vector<MultiOpDesc> d;
+      for (size_t gi = 0; gi < G; ++gi) {
+        if (act[gi].empty()) continue;
+        MultiOpDesc e{};
+        e.blocks = ops[gi]->blocks(P64);
+        e.nbr = ops[gi]->nbr.as<int>();
+        e.xin = const_cast<const void* const*>(tab.as<void*>() + off[gi]);
+        e.yout = tab.as<void*>() + off[gi] + act[gi].size();
+        e.V = ops[gi]->V;
+        e.R = int(act[gi].size());
+        e.tm = vars[gi]->sign * ops[gi]->mu;
+        d.push_back(e);
+      }
+      for (size_t i = 0; i < d.size(); i += kMaxMultiOps)
+        launch_apply_multi_ops(P64, ops[0]->n, d.data() + i,
+                               int(std::min<size_t>(kMaxMultiOps, d.size() - i)), 0, st);
+      std::vector<std::vector<int>> inner_r(G);
+      std::vector<std::vector<double>> scale(G);
+      bool any_inner = false;
+      for (size_t gi = 0; gi < G; ++gi) {
+        Op& op = *ops[gi];
+        const size_t N = op.N();
+        for (int r : act[gi]) {
+          z64* rr = R64[gi] + size_t(r) * N;
+          launch_scale(P64, rr, rr, N, nullptr, -1.0, nullptr, st);
+          launch_axpy(P64, mk(1.0, 0.0), B64[gi] + size_t(r) * N, rr, N, st);
+          launch_norm2(P64, rr, N, op.red(), op.scal.as<double>(), st);
+          double h2;
+          DC_HIP(hipMemcpyAsync(&h2, op.scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
+          DC_HIP(hipStreamSynchronize(st));
+          const double rn = std::sqrt(std::max(h2, 0.0));
+          rel[gi][r] = rn / bn[gi][r];
+          if (rel[gi][r] <= tl[gi][r] || outer == o.max_outer) {
+            done[gi][r] = 1;
+            continue;
+          }
+          stt[gi][r].outer_iters += 1;
+          inner_r[gi].push_back(r);
+          scale[gi].push_back(rn);
+          launch_convert_64to32(rr, B32[gi] + size_t(r) * N, N, op.n, 0, st);
+          launch_cscale(P32, B32[gi] + size_t(r) * N, B32[gi] + size_t(r) * N, N, mk(1.0 / rn, 0.0),
+                        nullptr, st);
+          any_inner = true;
         }
-        stt[r].outer_iters += 1;
-        inner_r.push_back(r);
-        scale.push_back(rn);
-        launch_convert_64to32(rr, B32 + size_t(r) * N, N, op.n, 0, st);
-        launch_cscale(P32, B32 + size_t(r) * N, B32 + size_t(r) * N, N, mk(1.0 / rn, 0.0), nullptr, st);
       }
-      if (inner_r.empty()) break;
-      // inner batched solve on the still-active right-hand sides
-      std::vector<const z32*> bp;
-      std::vector<z32*> xp;
-      std::vector<double> itol;
-      std::vector<SolveStats> ist(inner_r.size());
-      std::vector<double> irel(inner_r.size());
-      for (int r : inner_r) {
-        bp.push_back(B32 + size_t(r) * N);
-        xp.push_back(X32 + size_t(r) * N);
-        itol.push_back(o.inner_tol);
+      if (!any_inner) break;
+      // inner batched solve on the still-active right-hand sides of every operator
+      std::vector<int> Ri(G);
+      std::vector<std::vector<double>> itol(G), irel(G);
+      std::vector<std::vector<SolveStats>> ist(G);
+      for (size_t gi = 0; gi < G; ++gi) {
+        Ri[gi] = int(inner_r[gi].size());
+        itol[gi].assign(Ri[gi], o.inner_tol);
+        irel[gi].assign(Ri[gi], 0.0);
+        ist[gi].resize(Ri[gi]);
       }
-      Batch<float> Bi(op, var, o, int(inner_r.size()), st, op.bws, op.bsm);
-      Bi.solve(bp, xp, itol, false, o.max_cycles, ist, irel);
-      for (size_t i = 0; i < inner_r.size(); ++i) {
-        const int r = inner_r[i];
-        stt[r].iters += ist[i].iters;
-        stt[r].cycles += ist[i].cycles;
-        stt[r].matvecs += ist[i].matvecs + 1;
-        launch_convert_32to64(X32 + size_t(r) * N, R64 + size_t(r) * N, N, op.n, 0, st);
-        launch_axpy(P64, mk(scale[i], 0.0), R64 + size_t(r) * N, X64 + size_t(r) * N, N, st);
+      Batch<float> Bi(ops, vars, o, Ri, st, tab);
+      for (size_t gi = 0; gi < G; ++gi) {
+        const size_t N = ops[gi]->N();
+        for (int r : inner_r[gi]) {
+          Bi.g[gi].b.push_back(B32[gi] + size_t(r) * N);
+          Bi.g[gi].x.push_back(X32[gi] + size_t(r) * N);
+        }
+      }
+      Bi.solve(false, o.max_cycles, itol, ist, irel);
+      for (size_t gi = 0; gi < G; ++gi) {
+        const size_t N = ops[gi]->N();
+        for (size_t i = 0; i < inner_r[gi].size(); ++i) {
+          const int r = inner_r[gi][i];
+          stt[gi][r].iters += ist[gi][i].iters;
+          stt[gi][r].cycles += ist[gi][i].cycles;
+          stt[gi][r].matvecs += ist[gi][i].matvecs + 1;
+          launch_convert_32to64(X32[gi] + size_t(r) * N, R64[gi] + size_t(r) * N, N, ops[gi]->n, 0, st);
+          launch_axpy(P64, mk(scale[gi][i], 0.0), R64[gi] + size_t(r) * N, X64[gi] + size_t(r) * N, N, st);
+        }
       }
     }
   }
-  var.kcur = kc_saved;
   int all_ok = 1;
-  for (int r = 0; r < R; ++r) {
-    const z64* br = static_cast<const z64*>(b) + size_t(r) * N;
-    z64* xr = static_cast<z64*>(x) + size_t(r) * N;
-    if (adjoint) launch_gamma5(P64, X64 + size_t(r) * N, xr, op.V, op.n, st);
-    else DC_HIP(hipMemcpyAsync(xr, X64 + size_t(r) * N, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
-    stt[r].rel_res_true = fp64_relres(op, xr, br, adjoint, st);
-    stt[r].status = stt[r].rel_res_true <= tol[r] ? 0 : 1;
-    if (stt[r].status) all_ok = 0;
-    stt[r].t_setup_ms = (r == 0) ? t_setup : 0.0;
-    stt[r].t_solve_ms = ms_since(t0);
-    if (stats) stats[r] = stt[r];
+  for (size_t gi = 0; gi < G; ++gi) {
+    Op& op = *ops[gi];
+    vars[gi]->kcur = kc_saved[gi];
+    const size_t N = op.N();
+    for (int r = 0; r < R[gi]; ++r) {
+      const z64* br = static_cast<const z64*>(b[gi]) + size_t(r) * N;
+      z64* xr = static_cast<z64*>(x[gi]) + size_t(r) * N;
+      if (adjoint) launch_gamma5(P64, X64[gi] + size_t(r) * N, xr, op.V, op.n, st);
+      else DC_HIP(hipMemcpyAsync(xr, X64[gi] + size_t(r) * N, N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+      stt[gi][r].rel_res_true = fp64_relres(op, xr, br, adjoint, st);
+      stt[gi][r].status = stt[gi][r].rel_res_true <= tol[gi][r] ? 0 : 1;
+      if (stt[gi][r].status) all_ok = 0;
+      stt[gi][r].t_setup_ms = (r == 0) ? t_setup[gi] : 0.0;
+      stt[gi][r].t_solve_ms = ms_since(t0);
+      if (gi < stats.size() && stats[gi]) stats[gi][r] = stt[gi][r];
+    }
   }
   return all_ok ? 0 : 1;
+}
+
+int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b, void* x,
+                   const double* tol, int use_x0, hipStream_t st, SolveStats* stats) {
+  if (R < 0) throw InvalidArg("negative n_rhs");
+  if (R == 0) return 0;
+  return solve_groups({&op}, o, adjoint, {R}, {b}, {x}, {tol}, use_x0, st, {stats});
+}
+
+int op_solve_multi(const std::vector<Op*>& ops, const SolveOpts& o, int adjoint,
+                   const std::vector<int>& R, const std::vector<const void*>& b,
+                   const std::vector<void*>& x, const std::vector<const double*>& tol, int use_x0,
+                   hipStream_t st, const std::vector<SolveStats*>& stats) {
+  if (ops.empty()) throw InvalidArg("no operators");
+  if (ops.size() > size_t(kMaxMultiOps) * 64) throw InvalidArg("too many operators");
+  return solve_groups(ops, o, adjoint, R, b, x, tol, use_x0, st, stats);
 }
 
 int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st) {

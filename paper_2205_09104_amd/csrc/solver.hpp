@@ -149,6 +149,10 @@ int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C,
 void op_profile(Op& op, int every);
 void op_profile_read(Op& op, Prec p, long* launches, double* total_ms, long* launches_all,
                      double* total_ms_all);
+int op_solve_multi(const std::vector<Op*>& ops, const SolveOpts& o, int adjoint,
+                   const std::vector<int>& R, const std::vector<const void*>& b,
+                   const std::vector<void*>& x, const std::vector<const double*>& tol, int use_x0,
+                   hipStream_t st, const std::vector<SolveStats*>& stats);
 int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b, void* x,
                    const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
 

@@ -341,3 +341,50 @@ def test_changing_recycle_dimension_rebuilds_the_space(c1):
         # C = D U with orthonormal C (the GCRO-DR invariants of the exported space)
         Cn = Cm[:kk].cpu().numpy().reshape(kk, -1)
         assert np.abs(Cn.conj() @ Cn.T - np.eye(kk)).max() < 1e-8
+
+
+@pytest.mark.parametrize("cfg", ["gmres", "poly", "f32", "f16s", "bj"])
+def test_mixed_lattice_batch(cfg):
+    """Several lattices (same n) solved in one lockstep batch: every system
+    reaches its own tolerance by the oracle's apply."""
+    from paper_2205_09104_amd import CoarseOp, Opts
+    log("mixed batch", cfg)
+    store = ("f64", "f32", "f16s")
+    pairs = [make_pair((2, 2, 2, 2), 4, 3.2, store=store),
+             make_pair((3, 2, 2, 2), 4, 3.1, mu=0.05, store=store),
+             make_pair((4, 3, 2, 2), 4, 3.0, store=store)]
+    R = [2, 3, 1]
+    bs, tols = [], []
+    for i, ((gop, oop), r) in enumerate(zip(pairs, R)):
+        bs.append(torch.stack([rand_vec(oop.V, oop.n, 300 + 10 * i, j) for j in range(r)]).cuda())
+        tols.append(synth.tolerances_loguniform(r, 1e-10, 1e-7, seed=7 + i))
+    opts = {"gmres": Opts(m=24),
+            "poly": Opts(m=20, d=4, seed=3),
+            "f32": Opts(m=20, d=4, prec="f32", outer=1, inner_tol=1e-3, seed=3),
+            "f16s": Opts(m=20, d=4, prec="f16s", outer=1, inner_tol=1e-3, seed=3),
+            "bj": Opts(m=20, d=4, block_jacobi=1, seed=3)}[cfg]
+    xs, st, rc = CoarseOp.solve_multi([p[0] for p in pairs], bs, tols, opts)
+    assert rc == 0, st
+    for (gop, oop), x, b, t, s in zip(pairs, xs, bs, tols, st):
+        for j in range(b.shape[0]):
+            assert oracle_relres(oop, x[j].cpu().numpy(), b[j].cpu().numpy()) <= t[j]
+            assert s[j]["rel_res_true"] <= t[j] and s[j]["status"] == 0
+    if cfg in ("gmres", "poly"):
+        # lockstep over lattices does not change a system's iteration count much
+        gop, oop = pairs[1]
+        x1, s1, _ = gop.solve(bs[1][0], tols[1][0], opts)
+        assert abs(s1[0]["iters"] - st[1][0]["iters"]) <= opts.m
+
+
+def test_mixed_lattice_batch_rejects_bad_input():
+    from paper_2205_09104_amd import CoarseOp, Opts
+    from paper_2205_09104_amd._lib import DcError
+    log("mixed batch errors")
+    a, oa = make_pair((2, 2, 2, 2), 4, 3.2)
+    c, oc = make_pair((2, 2, 2, 2), 3, 3.2)
+    ba = rand_vec(oa.V, oa.n, 400, 0)[None].cuda()
+    bc = rand_vec(oc.V, oc.n, 401, 0)[None].cuda()
+    with pytest.raises(DcError):
+        CoarseOp.solve_multi([a, c], [ba, bc], [1e-8, 1e-8], Opts(m=10))
+    with pytest.raises(DcError):
+        CoarseOp.solve_multi([a, a], [ba, ba], [1e-8, 1e-8], Opts(m=10))
