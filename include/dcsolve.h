@@ -272,6 +272,18 @@ int dc_profile_apply(dc_op_t op, int32_t every);
 int dc_profile_apply_read(dc_op_t op, int32_t prec, int64_t* launches, double* total_ms,
                           int64_t* launches_all, double* total_ms_all);
 
+/* Right-hand-side tile (right-hand sides per workgroup: 16, 32 or 64) of the
+ * multi-right-hand-side apply.  The first launch of a shape class (block size
+ * n, precision, n_rhs bucket <=16 / <=32 / <=64 / more, floor(log2(sites)))
+ * times the candidate tiles on its operands with HIP events and keeps the
+ * fastest for the process.  dc_multi_tile returns the tile chosen for a shape
+ * (0 if not tuned yet); dc_set_multi_tile_mode(0) returns to autotuning and
+ * forgets the table, 16 / 32 / 64 forces that tile; other values are
+ * DC_ERR_INVALID.  Results do not depend on the tile (same arithmetic per
+ * output entry). */
+int dc_multi_tile(int32_t prec, int32_t n, int32_t n_rhs, int32_t sites);
+int dc_set_multi_tile_mode(int32_t mode);
+
 /* Message of the last error on this thread ("" if none). */
 const char* dc_last_error(void);
 

@@ -299,6 +299,16 @@ class CoarseSolve(torch.autograd.Function):
 
 
 # host-only dense helpers (no device needed)
+def multi_tile(prec: str, n: int, n_rhs: int, sites: int) -> int:
+    """Right-hand-side tile the multi-apply autotuner chose for a shape (0: not yet)."""
+    return int(load().dc_multi_tile(PREC[prec], n, n_rhs, sites))
+
+
+def set_multi_tile_mode(mode: int):
+    """0: autotune (and forget earlier choices); 16 / 32 / 64: force that tile."""
+    check(load().dc_set_multi_tile_mode(int(mode)))
+
+
 def dense_eig(A: np.ndarray, vectors=False):
     lib = load()
     n = A.shape[0]

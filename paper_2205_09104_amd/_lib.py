@@ -82,6 +82,8 @@ SIGNATURES = {
     "dc_export_f16": (C.c_int, [C.c_void_p, C.POINTER(C.c_uint16), C.POINTER(C.c_float)]),
     "dc_export_recycle": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p,
                                     C.c_void_p, C.POINTER(C.c_int32), C.c_void_p]),
+    "dc_multi_tile": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
+    "dc_set_multi_tile_mode": (C.c_int, [C.c_int32]),
     "dc_profile_apply": (C.c_int, [C.c_void_p, C.c_int32]),
     "dc_profile_apply_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double), C.POINTER(C.c_int64),

@@ -337,6 +337,18 @@ int dc_export_recycle(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, vo
   });
 }
 
+int dc_multi_tile(int32_t prec, int32_t n, int32_t n_rhs, int32_t sites) {
+  if (prec < 0 || prec > 2 || n < 1 || n_rhs < 1 || sites < 1) return 0;
+  return dc::multi_tile_for(dc::Prec(prec), n, n_rhs, unsigned(sites));
+}
+
+int dc_set_multi_tile_mode(int32_t mode) {
+  return guarded([&] {
+    dc::set_multi_tile_mode(mode);
+    return DC_OK;
+  });
+}
+
 int dc_profile_apply(dc_op_t op, int32_t every) {
   return guarded([&] {
     if (!op) throw dc::InvalidArg("null handle");

@@ -4,6 +4,10 @@
 
 #include <hip/hip_ext.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include <hip/hip_fp16.h>
 
 namespace dc {
@@ -789,8 +793,9 @@ constexpr int kMultiMaxTiles = 4;
 // operator whose site range [site0, site0 + V) contains it; grid.y tiles the
 // right-hand sides of the operator with the most, tiles past an operator's own
 // count exit at entry.
-template <int NP, int P, typename VT>
+template <int NP, int P, typename VT, int RB>
 __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
+  static_assert(RB % 16 == 0 && RB <= 64, "right-hand-side tile of 16, 32 or 64");
   using acc_t = typename Mfma<VT>::acc_t;
   // select this workgroup's operator (uniform; fields copied by select so the
   // kernel-argument array is never indexed dynamically)
@@ -821,16 +826,16 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
   const int n = ops.n, g5io = ops.g5io;
   const auto* const* xin = reinterpret_cast<const cx<VT>* const*>(xin_v);
   auto* const* yout = reinterpret_cast<cx<VT>* const*>(yout_v);
-  if (int(blockIdx.y) * 64 >= R) return;
+  if (int(blockIdx.y) * RB >= R) return;
   constexpr int LD = NP + 1;                  // padded row stride of every LDS plane
   extern __shared__ unsigned char smem[];
   VT* Mr = reinterpret_cast<VT*>(smem);       // [NP][LD] coupling matrix, real part
   VT* Mi = Mr + NP * LD;                      // imaginary part
-  VT* Pr = Mi + NP * LD;                      // [64][LD] panel: row r = x_r at the source
-  VT* Pi = Pr + 64 * LD;
+  VT* Pr = Mi + NP * LD;                      // [RB][LD] panel: row r = x_r at the source
+  VT* Pi = Pr + RB * LD;
   const int site = int(blockIdx.x) - site0;
-  const int r0 = blockIdx.y * 64;
-  const int Rc = min(64, R - r0);
+  const int r0 = blockIdx.y * RB;
+  const int Rc = min(RB, R - r0);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lk = lane >> 4;
   const int T = (n + 7) / 8, TT = T * T;
@@ -893,7 +898,7 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
       Mr[i * LD + j] = re;
       Mi[i * LD + j] = im;
     }
-    for (int t = threadIdx.x; t < 64 * NP; t += blockDim.x) {
+    for (int t = threadIdx.x; t < RB * NP; t += blockDim.x) {
       const int r = t / NP, k = t % NP;
       cx<VT> z = mk(VT(0), VT(0));
       if (k < n && r < Rc) {
@@ -1628,31 +1633,90 @@ void launch_chain_multi(Prec p, const void* const* t, const void* const* v, void
   DC_HIP(hipGetLastError());
 }
 
-size_t multi_lds_bytes(int n, bool dbl) {
+size_t multi_lds_bytes(int n, bool dbl, int rb) {
   const int np = multi_np(n);
-  return size_t(2) * (size_t(np) + 64) * (np + 1) * (dbl ? sizeof(double) : sizeof(float));
+  return size_t(2) * (size_t(np) + rb) * (np + 1) * (dbl ? sizeof(double) : sizeof(float));
 }
 
-template <int NP, int P, typename VT>
-static void multi_launch(const MultiOps& ops, unsigned sites, unsigned rtiles, hipStream_t st) {
-  const size_t lds = multi_lds_bytes(ops.n, sizeof(VT) == 8);
-  DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<NP, P, VT>),
+template <int NP, int P, typename VT, int RB>
+static void multi_launch(const MultiOps& ops, unsigned sites, int rmax, hipStream_t st) {
+  const size_t lds = multi_lds_bytes(ops.n, sizeof(VT) == 8, RB);
+  DC_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_apply_multi<NP, P, VT, RB>),
                              hipFuncAttributeMaxDynamicSharedMemorySize, int(lds)));
-  hipLaunchKernelGGL((k_apply_multi<NP, P, VT>), dim3(sites, rtiles), dim3(256), lds, st, ops);
+  const unsigned rtiles = unsigned((rmax + RB - 1) / RB);
+  hipLaunchKernelGGL((k_apply_multi<NP, P, VT, RB>), dim3(sites, rtiles), dim3(256), lds, st, ops);
   DC_HIP(hipGetLastError());
 }
 
+template <int NP, typename VT, int P>
+static void multi_rb_launch(int rb, const MultiOps& ops, unsigned sites, int rmax, hipStream_t st) {
+  if (rb == 16) multi_launch<NP, P, VT, 16>(ops, sites, rmax, st);
+  else if (rb == 32) multi_launch<NP, P, VT, 32>(ops, sites, rmax, st);
+  else multi_launch<NP, P, VT, 64>(ops, sites, rmax, st);
+}
+
 template <int NP>
-static void multi_np_launch(Prec p, const MultiOps& ops, unsigned sites, unsigned rtiles,
+static void multi_np_launch(Prec p, int rb, const MultiOps& ops, unsigned sites, int rmax,
                             hipStream_t st) {
-  if (p == P64) multi_launch<NP, P64, double>(ops, sites, rtiles, st);
-  else if (p == P32) multi_launch<NP, P32, float>(ops, sites, rtiles, st);
-  else multi_launch<NP, P16S, float>(ops, sites, rtiles, st);
+  if (p == P64) multi_rb_launch<NP, double, P64>(rb, ops, sites, rmax, st);
+  else if (p == P32) multi_rb_launch<NP, float, P32>(rb, ops, sites, rmax, st);
+  else multi_rb_launch<NP, float, P16S>(rb, ops, sites, rmax, st);
+}
+
+static void multi_dispatch(Prec p, int rb, const MultiOps& ops, unsigned sites, int rmax,
+                           hipStream_t st) {
+  switch (multi_np(ops.n)) {
+    case 16: multi_np_launch<16>(p, rb, ops, sites, rmax, st); break;
+    case 32: multi_np_launch<32>(p, rb, ops, sites, rmax, st); break;
+    case 48: multi_np_launch<48>(p, rb, ops, sites, rmax, st); break;
+    case 64: multi_np_launch<64>(p, rb, ops, sites, rmax, st); break;
+    default: throw InvalidArg("block size n > 64 is not supported");
+  }
+}
+
+// Autotuned right-hand-side tile (16, 32 or 64 per workgroup): the first launch
+// of a shape class (block size, precision, right-hand-side and site-count
+// buckets) times each candidate on the actual operands with HIP events and
+// keeps the fastest; later launches of the class use it.
+namespace {
+struct TuneKey {
+  int np, prec, rbucket, vbucket;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(np, prec, rbucket, vbucket) < std::tie(o.np, o.prec, o.rbucket, o.vbucket);
+  }
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, int> g_tune;
+int g_tune_mode = 0;  // 0: autotune; 16/32/64: forced tile
+
+TuneKey tune_key(Prec p, int n, int rmax, unsigned sites) {
+  int rbk = 0;
+  while ((16 << rbk) < rmax && rbk < 3) ++rbk;   // <=16, <=32, <=64, >64
+  int vb = 0;
+  while ((1u << (vb + 1)) <= sites && vb < 30) ++vb;  // floor(log2(sites))
+  return TuneKey{multi_np(n), int(p), rbk, vb};
+}
+}  // namespace
+
+int multi_tile_for(Prec p, int n, int rmax, unsigned sites) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tune_mode) return g_tune_mode;
+  const auto it = g_tune.find(tune_key(p, n, rmax, sites));
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+void set_multi_tile_mode(int mode) {
+  if (mode != 0 && mode != 16 && mode != 32 && mode != 64)
+    throw InvalidArg("tile mode must be 0 (autotune), 16, 32 or 64");
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_mode = mode;
+  if (mode == 0) g_tune.clear();
 }
 
 void launch_apply_multi_ops(Prec p, int n, const MultiOpDesc* desc, int n_ops, int g5io,
                             hipStream_t st) {
   if (n_ops < 1 || n_ops > kMaxMultiOps) throw InvalidArg("1..8 operators per multi-apply");
+  if (multi_np(n) > 64) throw InvalidArg("block size n > 64 is not supported");
   MultiOps ops{};
   ops.n_ops = n_ops;
   ops.n = n;
@@ -1666,14 +1730,34 @@ void launch_apply_multi_ops(Prec p, int n, const MultiOpDesc* desc, int n_ops, i
     rmax = std::max(rmax, desc[i].R);
   }
   if (rmax <= 0 || sites == 0) return;
-  const unsigned rtiles = unsigned((rmax + 63) / 64);
-  switch (multi_np(n)) {
-    case 16: multi_np_launch<16>(p, ops, sites, rtiles, st); break;
-    case 32: multi_np_launch<32>(p, ops, sites, rtiles, st); break;
-    case 48: multi_np_launch<48>(p, ops, sites, rtiles, st); break;
-    case 64: multi_np_launch<64>(p, ops, sites, rtiles, st); break;
-    default: throw InvalidArg("block size n > 64 is not supported");
+  int rb = multi_tile_for(p, n, rmax, sites);
+  if (rb == 0) {
+    // time every candidate (each fully overwrites the outputs with the same result)
+    hipEvent_t e0, e1;
+    DC_HIP(hipEventCreate(&e0));
+    DC_HIP(hipEventCreate(&e1));
+    float best = 1e30f;
+    for (int cand : {16, 32, 64}) {
+      if (cand > 16 && (cand / 2) >= rmax) break;   // wider tiles than the batch
+      multi_dispatch(p, cand, ops, sites, rmax, st);   // warm
+      DC_HIP(hipEventRecord(e0, st));
+      for (int rep = 0; rep < 3; ++rep) multi_dispatch(p, cand, ops, sites, rmax, st);
+      DC_HIP(hipEventRecord(e1, st));
+      DC_HIP(hipEventSynchronize(e1));
+      float ms = 0.f;
+      DC_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        rb = cand;
+      }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(p, n, rmax, sites)] = rb;
+    return;   // the last candidate's launches already wrote the outputs
   }
+  multi_dispatch(p, rb, ops, sites, rmax, st);
 }
 
 void launch_apply_multi(Prec p, int n, int V, const void* blocks, const float* scales,

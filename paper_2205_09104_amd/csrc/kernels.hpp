@@ -77,7 +77,11 @@ void launch_bj_gather_poly(Prec p, int n, int V, const void* inv, const float* s
 void launch_apply_multi(Prec p, int n, int V, const void* blocks, const float* scales,
                         const void* const* xin, void* const* yout, int R, const int* nbr, double tm,
                         int g5io, hipStream_t st);
-size_t multi_lds_bytes(int n, bool dbl);
+size_t multi_lds_bytes(int n, bool dbl, int rb);
+// right-hand-side tile chosen for a multi-apply shape (0: not tuned yet), and
+// the tuning mode (0: autotune, 16/32/64: force that tile; 0 clears the table)
+int multi_tile_for(Prec p, int n, int rmax, unsigned sites);
+void set_multi_tile_mode(int mode);
 // The same over a work list of several operators with one block size n (a
 // mixed batch of lattices): operator i contributes V sites and R right-hand
 // sides (its own pointer arrays xin/yout, twisted mass tm); one launch.

@@ -287,8 +287,14 @@ void op_apply_multi(Op& op, Prec p, int adjoint, int R, const void* in, void* ou
   check_prec(op, p);
   if (R < 0) throw InvalidArg("n_rhs must be >= 0");
   if (R == 0) return;
-  if (!in || !out || in == out) throw InvalidArg("bad vector pointers");
+  if (!in || !out) throw InvalidArg("bad vector pointers");
   const size_t vb = op.N() * vec_bytes(p);
+  {
+    const char* a = static_cast<const char*>(in);
+    const char* b = static_cast<const char*>(out);
+    const size_t span = size_t(R) * vb;
+    if (a < b + span && b < a + span) throw InvalidArg("in and out overlap");
+  }
   std::vector<const void*> h(2 * size_t(R));
   for (int r = 0; r < R; ++r) {
     h[r] = static_cast<const char*>(in) + size_t(r) * vb;

@@ -134,3 +134,30 @@ def test_apply_multi_matches_oracle(dims, ntv, R, mu):
     # same result as R single applies through the other kernel
     single = torch.stack([gop.apply(X32[r], prec="f32") for r in range(R)])
     assert rel(gop.apply_multi(X32, prec="f32").cpu().numpy(), single.cpu().numpy()) <= 2e-6
+
+
+def test_apply_multi_tiles_agree_bitwise():
+    """Every right-hand-side tile of the multi-apply does the same arithmetic
+    per output entry; the autotuner picks one of them."""
+    import paper_2205_09104_amd as dc
+    log("apply multi tiles")
+    gop, oop = make_pair((3, 2, 2, 2), 24, 2.5, mu=0.1, store=("f64", "f32"))
+    R = 40
+    X = torch.stack([rand_vec(oop.V, oop.n, 81, r) for r in range(R)]).cuda()
+    X32 = X.to(torch.complex64)
+    outs = {}
+    try:
+        for mode in (16, 32, 64):
+            dc.set_multi_tile_mode(mode)
+            outs[mode] = (gop.apply_multi(X).cpu(), gop.apply_multi(X32, prec="f32").cpu())
+        dc.set_multi_tile_mode(0)
+        auto = (gop.apply_multi(X).cpu(), gop.apply_multi(X32, prec="f32").cpu())
+    finally:
+        dc.set_multi_tile_mode(0)
+    for mode in (32, 64):
+        assert torch.equal(outs[mode][0], outs[16][0]) and torch.equal(outs[mode][1], outs[16][1])
+    assert torch.equal(auto[0], outs[16][0]) and torch.equal(auto[1], outs[16][1])
+    assert dc.multi_tile("f64", oop.n, R, oop.V) in (16, 32, 64)
+    assert dc.multi_tile("f32", oop.n, R, oop.V) in (16, 32, 64)
+    with pytest.raises(Exception):
+        dc.set_multi_tile_mode(48)
