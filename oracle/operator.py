@@ -89,6 +89,20 @@ def apply(op: CoarseOp, psi: np.ndarray) -> np.ndarray:
     return out
 
 
+def apply_site(A_x, B_x, B_back, psi_x, psi_fwd, psi_bwd, mu: float = 0.0) -> np.ndarray:
+    """(D psi)_x at one site from the blocks it touches (for sampled checks of
+    lattices too large to hold on the host): A_x [n, n] (without the twisted
+    mass), B_x [4, n, n] = B[x, mu], B_back [4, n, n] = B[x - mu, mu],
+    psi_x [n], psi_fwd [4, n] = psi_{x+mu}, psi_bwd [4, n] = psi_{x-mu}."""
+    n = A_x.shape[0]
+    g5 = gamma5(n)
+    out = A_x @ psi_x + 1j * mu * g5 * psi_x
+    for m in range(4):
+        out = out + B_x[m] @ psi_fwd[m]
+        out = out + g5 * (np.conj(B_back[m]).T @ (g5 * psi_bwd[m]))
+    return out
+
+
 def apply_adjoint(op: CoarseOp, psi: np.ndarray) -> np.ndarray:
     """(D^H psi), written from the definition D^H[y, x] = D[x, y]^H:
     (D^H psi)_x = A'_x^H psi_x + sum_mu Gamma5 B[x,mu] Gamma5 psi_{x+mu}

@@ -1,0 +1,198 @@
+"""Parity at full configuration sizes (GPU): sampled outputs that the oracle
+computes one site at a time, and properties that hold at any size.
+
+c3: 16^3 x 32, N_tv = 24, twisted mass 1e-3 (6.29M unknowns) - apply in three
+precisions at sampled sites; mixed-precision solve to 1e-8 with its residual
+re-checked at sampled sites.  c4: 16^4, N_tv = 24 - batched solve of 12
+right-hand sides with log-uniform tolerances.  c5: 8^4, N_tv = 16, twisted
+mass 1e-2 - autograd gradient of L = Re(c^H x) against central differences.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import mixed
+from oracle import operator as dop
+from oracle.lattice import neighbours
+
+from .helpers import log
+
+pytestmark = pytest.mark.gpu
+
+
+def sample_sites(V, k, seed):
+    rng = np.random.default_rng(seed)
+    s = set(rng.choice(V, size=k - 2, replace=False).tolist())
+    return sorted(s | {0, V - 1})
+
+
+def site_blocks(w, m0, s, bwd, store="f64"):
+    """Blocks that the stencil at site s touches, regenerated on the host, in
+    the storage precision store (decoded to complex128)."""
+    A = synth.self_blocks(w.dims, w.n_tv, m0, w.seed, sites=[s]).numpy()[0]
+    B = synth.hop_blocks(w.dims, w.n_tv, w.seed, sites=[s]).numpy()[0]
+    Bb = synth.hop_blocks(w.dims, w.n_tv, w.seed, sites=bwd[:, s].tolist()).numpy()
+    Bb = np.stack([Bb[m, m] for m in range(4)])
+    if store == "f32":
+        A, B, Bb = (mixed.round_fp32(t).astype(np.complex128) for t in (A, B, Bb))
+    elif store == "f16s":
+        A, B, Bb = (mixed.dequantize_fp16(*mixed.quantize_fp16(t)).astype(np.complex128)
+                    for t in (A, B, Bb))
+    return A, B, Bb
+
+
+def oracle_rows(w, m0, x, sites, store="f64"):
+    fwd, bwd = neighbours(w.dims)
+    out = []
+    for s in sites:
+        A, B, Bb = site_blocks(w, m0, s, bwd, store)
+        out.append(dop.apply_site(A, B, Bb, x[s], x[fwd[:, s]], x[bwd[:, s]], w.mu))
+    return np.stack(out)
+
+
+def build(name, store):
+    from paper_2205_09104_amd import CoarseOp
+    w = synth.WORKLOADS[name]
+    A, B = synth.operator(w, device="cuda")
+    op = CoarseOp(A, B, w.dims, mu=w.mu, store=store)
+    del A, B
+    torch.cuda.empty_cache()
+    return op, w
+
+
+@pytest.fixture(scope="module")
+def c3():
+    log("build c3 (16^3 x 32, n = 48)")
+    op, w = build("c3", ("f64", "f32", "f16s"))
+    yield op, w
+    del op
+    torch.cuda.empty_cache()
+
+
+def test_c3_apply_sampled_sites(c3):
+    op, w = c3
+    m0 = w.m0()
+    x = synth.vector(w.dims, w.n_tv, synth.STREAM_AUX, 11, device="cuda")
+    sites = sample_sites(w.V, 24, 3)
+    xh = x.cpu().numpy()
+    y = op.apply(x).cpu().numpy()
+    ref = oracle_rows(w, m0, xh, sites)
+    err = np.abs(y[sites] - ref).max() / np.abs(ref).max()
+    log(f"c3 f64 sampled apply: {err:.2e}")
+    assert err <= 1e-13
+    x32 = x.to(torch.complex64)
+    xh32 = x32.cpu().numpy().astype(np.complex128)
+    for prec in ("f32", "f16s"):
+        y = op.apply(x32, prec=prec).cpu().numpy()
+        ref = oracle_rows(w, m0, xh32, sites, store=prec)
+        err = np.abs(y[sites] - ref).max() / np.abs(ref).max()
+        log(f"c3 {prec} sampled apply: {err:.2e}")
+        assert err <= 2e-6
+
+
+def test_c3_mixed_solve(c3):
+    from paper_2205_09104_amd import Opts
+    op, w = c3
+    m0 = w.m0()
+    opts = Opts(m=62, k=32, d=16, prec="f16s", outer=1, m_outer=10, max_outer=60,
+                inner_tol=1e-1, seed=1, max_cycles=3000)
+    b = synth.rhs(w.dims, w.n_tv, 0, device="cuda")
+    x, st, rc = op.solve(b, 1e-8, opts)
+    s = st[0]
+    log(f"c3 mixed solve: rc {rc} rel {s['rel_res_true']:.2e} matvecs {s['matvecs']} "
+        f"outer {s['outer_iters']} {s['t_solve_ms']:.0f} ms")
+    assert rc == 0 and s["rel_res_true"] <= 1e-8
+    # the residual the library measured, re-derived: FP64 apply checked at
+    # sampled sites by the oracle, norm from the FP64 apply
+    r = b - op.apply(x)
+    assert float(torch.linalg.vector_norm(r) / torch.linalg.vector_norm(b)) <= 1e-8
+    sites = sample_sites(w.V, 12, 4)
+    xh = x.cpu().numpy()
+    rs = b.cpu().numpy()[sites] - oracle_rows(w, m0, xh, sites)
+    assert np.abs(rs - r.cpu().numpy()[sites]).max() <= 1e-12 * np.abs(b.cpu().numpy()).max()
+
+
+def test_c4_batched_solve():
+    from paper_2205_09104_amd import Opts
+    log("build c4 (16^4, n = 48)")
+    op, w = build("c4", ("f64", "f32", "f16s"))
+    m0 = w.m0()
+    opts = Opts(m=62, k=32, d=16, prec="f16s", outer=1, m_outer=10, max_outer=60,
+                inner_tol=1e-1, seed=1, max_cycles=3000)
+    b0 = synth.rhs(w.dims, w.n_tv, 100, device="cuda")
+    _, st0, rc0 = op.solve(b0, 1e-8, opts)         # builds the polynomial and recycle space
+    log(f"c4 setup solve: rc {rc0} matvecs {st0[0]['matvecs']} {st0[0]['t_solve_ms']:.0f} ms")
+    R = 12
+    B = torch.stack([synth.rhs(w.dims, w.n_tv, r, device="cuda") for r in range(R)])
+    tols = synth.tolerances_loguniform(R, 1e-10, 1e-6, seed=4)
+    X, st, rc = op.solve_batch(B, tols, opts)
+    log(f"c4 batch: rc {rc} max cycles {max(s['cycles'] for s in st)} "
+        f"{max(s['t_solve_ms'] for s in st):.0f} ms")
+    assert rc == 0
+    for r in range(R):
+        assert st[r]["rel_res_true"] <= tols[r]
+        res = B[r] - op.apply(X[r])
+        assert float(torch.linalg.vector_norm(res) / torch.linalg.vector_norm(B[r])) <= tols[r]
+    sites = sample_sites(w.V, 8, 5)
+    for r in (0, R - 1):
+        xh = X[r].cpu().numpy()
+        rs = B[r].cpu().numpy()[sites] - oracle_rows(w, m0, xh, sites)
+        ref = (B[r] - op.apply(X[r])).cpu().numpy()[sites]
+        assert np.abs(rs - ref).max() <= 1e-12 * np.abs(B[r].cpu().numpy()).max()
+    del op, X, B
+    torch.cuda.empty_cache()
+
+
+def test_c5_gradient_against_central_differences():
+    """dL/dB for L = Re(c^H x), x = D^{-1} b, through the autograd Function
+    (adjoint solve + gradient kernel), against central differences of L over
+    32 seeded forward-hop entries (real and imaginary directions: 64
+    derivatives), each difference from two solves warm-started at x to 1e-13."""
+    from paper_2205_09104_amd import CoarseOp, CoarseSolve, Opts
+    log("build c5 (8^4, n = 32, mu = 1e-2)")
+    w = synth.WORKLOADS["c5"]
+    A, B = synth.operator(w, device="cuda")
+    op = CoarseOp(A, B, w.dims, mu=w.mu)
+    b = synth.rhs(w.dims, w.n_tv, 0, device="cuda")
+    c = synth.vector(w.dims, w.n_tv, synth.STREAM_AUX, 3, device="cuda")
+    opts = Opts(m=40, d=8, seed=1, max_cycles=200)
+    tol = 1e-13
+    Bp = B.clone().requires_grad_(True)
+    bp = b.clone().requires_grad_(True)
+    x = CoarseSolve.apply(bp, Bp, op, opts, tol)
+    L = torch.real(torch.vdot(c.reshape(-1), x.reshape(-1)))
+    L.backward()
+    g = Bp.grad
+    # grad_b = lambda with D^H lambda = c
+    lam = bp.grad
+    res = c - op.apply(lam, adjoint=True)
+    assert float(torch.linalg.vector_norm(res) / torch.linalg.vector_norm(c)) <= 1e-12
+    x = x.detach()
+    rng = np.random.default_rng(12)
+    idx = [(int(rng.integers(w.V)), int(rng.integers(4)), int(rng.integers(w.n)),
+            int(rng.integers(w.n))) for _ in range(32)]
+    h = 1e-4
+    fd, an = [], []
+    for (s, mu, i, j) in idx:
+        for part, unit in (("re", 1.0), ("im", 1j)):
+            Ls = []
+            for sgn in (1.0, -1.0):
+                Bq = B.clone()
+                Bq[s, mu, i, j] += sgn * h * unit
+                op.update(A, Bq)
+                xq, st, rc = op.solve(b, tol, opts, x0=x)
+                assert rc == 0, st
+                Ls.append(float(torch.real(torch.vdot(c.reshape(-1), xq.reshape(-1)))))
+            fd.append((Ls[0] - Ls[1]) / (2 * h))
+            gv = g[s, mu, i, j].item()
+            an.append(gv.real if part == "re" else gv.imag)
+    op.update(A, B)
+    fd, an = np.array(fd), np.array(an)
+    err = np.abs(fd - an).max() / np.abs(an).max()
+    log(f"c5 gradient vs central differences: max rel err {err:.2e} "
+        f"(|grad| up to {np.abs(an).max():.3f})")
+    # step 1e-4: truncation O(h^2); solve noise ~ tol-level error of L / h
+    assert err <= 1e-4
+    del op, A, B
+    torch.cuda.empty_cache()
