@@ -150,14 +150,14 @@ def test_apply_multi_tiles_agree_bitwise():
         for mode in (16, 32, 64):
             dc.set_multi_tile_mode(mode)
             outs[mode] = (gop.apply_multi(X).cpu(), gop.apply_multi(X32, prec="f32").cpu())
-        dc.set_multi_tile_mode(0)
+        dc.set_multi_tile_mode(0)       # back to autotuning, table cleared
         auto = (gop.apply_multi(X).cpu(), gop.apply_multi(X32, prec="f32").cpu())
+        tiles = (dc.multi_tile("f64", oop.n, R, oop.V), dc.multi_tile("f32", oop.n, R, oop.V))
+        with pytest.raises(Exception):
+            dc.set_multi_tile_mode(48)
     finally:
         dc.set_multi_tile_mode(0)
     for mode in (32, 64):
         assert torch.equal(outs[mode][0], outs[16][0]) and torch.equal(outs[mode][1], outs[16][1])
     assert torch.equal(auto[0], outs[16][0]) and torch.equal(auto[1], outs[16][1])
-    assert dc.multi_tile("f64", oop.n, R, oop.V) in (16, 32, 64)
-    assert dc.multi_tile("f32", oop.n, R, oop.V) in (16, 32, 64)
-    with pytest.raises(Exception):
-        dc.set_multi_tile_mode(48)
+    assert tiles[0] in (16, 32, 64) and tiles[1] in (16, 32, 64)
