@@ -49,6 +49,10 @@ def parse():
                    help="time one in this many launches of the apply's block kernel (0: off)")
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--summarize-trace", default=None, metavar="CSV",
+                   help="only summarise a rocprofv3 kernel_trace.csv: per-kernel launches and "
+                        "mean duration over launches longer than --min-us (launches that did work)")
+    p.add_argument("--min-us", type=float, default=8.0)
     p.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                    help="only run a plain elementwise copy of this many MiB (read + write), "
                         "the reference for scaling HBM byte counters")
@@ -112,6 +116,9 @@ def measured_traffic(workload, prec):
 
 def main():
     a = parse()
+    if a.summarize_trace:
+        summarize_trace(a.summarize_trace, a.min_us)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                                    "(the multi-GPU sharding is a design only)"}))
@@ -296,6 +303,26 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def summarize_trace(path, min_us):
+    """Per kernel of a rocprofv3 kernel trace: all launches and their mean
+    duration, and the same over launches longer than min_us (a finished
+    Arnoldi cycle turns its remaining launches into near-empty ones)."""
+    import csv
+    import statistics
+    d = {}
+    with open(path) as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"].replace("(anonymous namespace)::", "").split("(")[0]
+            d.setdefault(name[:90], []).append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    rows = sorted(d.items(), key=lambda kv: -sum(kv[1]))[:20]
+    print(f"{'kernel':90s} {'launches':>9s} {'mean_us':>8s} {'work':>9s} {'mean_us':>8s} {'median':>8s}")
+    for k, v in rows:
+        w = [x for x in v if x > min_us]
+        print(f"{k:90s} {len(v):9d} {statistics.mean(v):8.2f} {len(w):9d} "
+              f"{(statistics.mean(w) if w else 0):8.2f} {(statistics.median(w) if w else 0):8.2f}")
 
 
 def copy_probe(mib):
