@@ -45,6 +45,8 @@ def parse():
     p.add_argument("--plain-max-cycles", type=int, default=400,
                    help="restart cycles of the plain GMRES(30) comparison (it may stagnate)")
     p.add_argument("--apply-reps", type=int, default=50)
+    p.add_argument("--multi-rhs", type=int, default=64,
+                   help="right-hand sides of the multi-RHS (MFMA) apply measurement (0: skip)")
     p.add_argument("--profile-every", type=int, default=8,
                    help="time one in this many launches of the apply's block kernel (0: off)")
     p.add_argument("--no-cpu", action="store_true")
@@ -173,6 +175,33 @@ def main():
     for p, (ms, gbs) in rates.items():
         log(f"apply {p} (both stages, back to back): {ms * 1e3:.1f} us, {gbs:.0f} GB/s algorithmic")
 
+    # ------------------------------------------------ multi-RHS (MFMA) apply
+    multi = {}
+    if a.multi_rhs > 0:
+        R = a.multi_rhs
+        flops = 72.0 * V * n * n * R           # complex n x n times n x R per coupling, 9 couplings
+        for p, peak in (("f64", 78.6), ("f32", 157.3), ("f16s", 157.3)):
+            X = torch.stack([synth.rhs(w.dims, w.n_tv, 500 + r, device="cuda") for r in range(R)])
+            X = X if p == "f64" else X.to(torch.complex64)
+            Y = torch.empty_like(X)
+            for _ in range(2):
+                op.apply_multi(X, prec=p, out=Y)
+            times = []
+            for _ in range(5):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                op.apply_multi(X, prec=p, out=Y)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                times.append(e0.elapsed_time(e1))
+            ms = sorted(times)[2]
+            tf = flops / (ms * 1e-3) / 1e12
+            multi[p] = {"n_rhs": R, "ms": ms, "TFLOP/s": tf, "peak": peak, "frac": tf / peak,
+                        "mfma": "f64 16x16x4" if p == "f64" else "f32 16x16x4"}
+            log(f"multi-RHS apply {p} R={R}: {ms:.3f} ms, {tf:.1f} TFLOP/s ({100 * tf / peak:.1f}% of {peak})")
+            del X, Y
+
     # ------------------------------------------------ method solve (timed)
     opts = Opts(m=a.m + a.k, k=a.k, d=a.d, u=10, prec=a.inner, outer=1, m_outer=10,
                 max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000)
@@ -287,6 +316,7 @@ def main():
         "plain_fp64_gmres30": plain,
         "fp64_comparison": comp,
         "apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]} for p, r in rates.items()},
+        "multi_rhs_apply": multi,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "traffic_detail": traffic_detail,

@@ -5,7 +5,7 @@ c3: 16^3 x 32, N_tv = 24, twisted mass 1e-3 (6.29M unknowns) - apply in three
 precisions at sampled sites; a mixed-precision solve whose residual is
 re-checked at sampled sites (to 1e-4 here: a solve to 1e-8 takes ~110 s on
 this operator and is measured, not tested).  c4: 16^4, N_tv = 24 - batched
-solve of 12 right-hand sides with log-uniform tolerances (in [1e-6, 1e-4] here;
+solve of 12 right-hand sides with log-uniform tolerances (in [1e-5, 1e-3] here;
 the [1e-10, 1e-6] range is tested on the 4^4 lattice).  c5: 8^4, N_tv = 16,
 twisted mass 1e-2 - autograd gradient of L = Re(c^H x) against central
 differences.
@@ -129,7 +129,7 @@ def test_c4_batched_solve():
     log(f"c4 setup solve: rc {rc0} matvecs {st0[0]['matvecs']} {st0[0]['t_solve_ms']:.0f} ms")
     R = 12
     B = torch.stack([synth.rhs(w.dims, w.n_tv, r, device="cuda") for r in range(R)])
-    tols = synth.tolerances_loguniform(R, 1e-6, 1e-4, seed=4)
+    tols = synth.tolerances_loguniform(R, 1e-5, 1e-3, seed=4)
     X, st, rc = op.solve_batch(B, tols, opts)
     log(f"c4 batch: rc {rc} max cycles {max(s['cycles'] for s in st)} "
         f"{max(s['t_solve_ms'] for s in st):.0f} ms")
