@@ -278,8 +278,8 @@ int dc_profile_apply_read(dc_op_t op, int32_t prec, int64_t* launches, double* t
  * times the candidate tiles on its operands with HIP events and keeps the
  * fastest for the process.  dc_multi_tile returns the tile chosen for a shape
  * (0 if not tuned yet); dc_set_multi_tile_mode(0) returns to autotuning and
- * forgets the table, 16 / 32 / 64 forces that tile; other values are
- * DC_ERR_INVALID.  Results do not depend on the tile (same arithmetic per
+ * forgets the table, 16 / 32 / 64 forces that tile (FP64 uses 32 for 64);
+ * other values are DC_ERR_INVALID.  Results do not depend on the tile (same arithmetic per
  * output entry). */
 int dc_multi_tile(int32_t prec, int32_t n, int32_t n_rhs, int32_t sites);
 int dc_set_multi_tile_mode(int32_t mode);

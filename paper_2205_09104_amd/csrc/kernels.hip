@@ -784,9 +784,6 @@ struct Mfma<double> {
   __device__ static int row(int lk, int q) { return lk + 4 * q; }
 };
 
-// Output tiles per wave: (NP/16) row tiles x ceil(R/16) column tiles over 4
-// waves; each tile keeps a real and an imaginary accumulator.
-constexpr int kMultiMaxTiles = 4;
 
 // The grid runs over a work list of the sites of up to kMaxMultiOps operators
 // (a mixed batch of lattices with one block size n): workgroup x belongs to the
@@ -839,21 +836,78 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int l16 = lane & 15, lk = lane >> 4;
   const int T = (n + 7) / 8, TT = T * T;
-  const int epl = (P == P64) ? 1 : (P == P32 ? 2 : 4);
-  const int tte = (TT + epl - 1) / epl * epl;
+  constexpr int epl = (P == P64) ? 1 : (P == P32 ? 2 : 4);   // block entries per 16-byte unit
+  const int upl = (TT + epl - 1) / epl;                      // units per lane of a block
+  const int nunits = 64 * upl;
+  const int half = n >> 1;
+  // output tiles (16 x 16): RT row tiles x RB/16 column tiles, spread over the
+  // 4 waves (tile t = wave + 4 it); a partial right-hand-side tile computes on
+  // zero padding and stores only its Rc columns
   constexpr int RT = NP / 16;
-  const int CT = (Rc + 15) / 16;
-  const int ntiles = RT * CT;
-  acc_t cre[kMultiMaxTiles], cim[kMultiMaxTiles];
+  constexpr int NT = RT * (RB / 16);
+  constexpr int TPW = (NT + 3) / 4;     // tiles per wave
+  // Staging with 16-byte loads.  Blocks: thread t takes units u = t + 256 s of
+  // the tiled block (lane u % 64, unit u / 64 of that lane), each holding epl
+  // entries whose (row, column) are fixed per thread and computed once.
+  // Panel: thread t takes 16-byte chunks c = t + 256 s (right-hand side c / CPR,
+  // chunk c % CPR of its n entries at the source site).
+  constexpr int TMAX = NP / 8;
+  constexpr int MU = (64 * ((TMAX * TMAX + epl - 1) / epl) + 255) / 256;
+  constexpr int VPC = 16 / int(sizeof(cx<VT>));             // vector entries per chunk
+  constexpr int CPRMAX = NP / VPC;
+  constexpr int PU = (RB * CPRMAX + 255) / 256;
+  const int cpr = n / VPC;                                   // chunks per right-hand side
+  int uoff[MU];                  // unit offset in the block (in 16-byte units), -1 if none
+  int ij[MU][epl];               // packed (row, column) of each entry, -1 if padding
 #pragma unroll
-  for (int t = 0; t < kMultiMaxTiles; ++t) {
-    cre[t] = acc_t{0, 0, 0, 0};
-    cim[t] = acc_t{0, 0, 0, 0};
+  for (int s2 = 0; s2 < MU; ++s2) {
+    const int u = threadIdx.x + 256 * s2;
+    uoff[s2] = -1;
+#pragma unroll
+    for (int q = 0; q < epl; ++q) ij[s2][q] = -1;
+    if (u < nunits) {
+      const int l = u % 64, k = u / 64;
+      uoff[s2] = k * 64 + l;
+#pragma unroll
+      for (int q = 0; q < epl; ++q) {
+        const int e = k * epl + q;
+        if (e < TT) {
+          const int i = (l / 8) * T + e / T, j = (l % 8) * T + e % T;
+          if (i < n && j < n) ij[s2][q] = (i << 8) | j;
+        }
+      }
+    }
   }
-  for (int c = 0; c < 9; ++c) {
+  const cx<VT>* prow[PU];        // this thread's panel chunk sources (right-hand-side base)
+  int pr_[PU], pk_[PU];          // right-hand side and first component of each chunk
+#pragma unroll
+  for (int s2 = 0; s2 < PU; ++s2) {
+    const int c = threadIdx.x + 256 * s2;
+    const int r = c / cpr, k = (c % cpr) * VPC;
+    pr_[s2] = -1;
+    pk_[s2] = k;
+    prow[s2] = nullptr;
+    if (c < RB * cpr && r < Rc) {
+      pr_[s2] = r;
+      prow[s2] = xin[r0 + r];
+    }
+  }
+  // zero both planes once: padding rows / columns are never written again
+  for (int t = threadIdx.x; t < 2 * (NP + RB) * LD; t += blockDim.x) Mr[t] = VT(0);
+  __syncthreads();   // the zero fill must land before any staged value
+  acc_t crr[TPW], cii[TPW], cri[TPW], cir[TPW];
+#pragma unroll
+  for (int t = 0; t < TPW; ++t) {
+    crr[t] = acc_t{0, 0, 0, 0};
+    cii[t] = acc_t{0, 0, 0, 0};
+    cri[t] = acc_t{0, 0, 0, 0};
+    cir[t] = acc_t{0, 0, 0, 0};
+  }
+  uint4 mreg[MU], preg[PU];      // the next coupling's raw 16-byte units
+  int cblk = 0, csrc = 0;
+  float csc = 1.0f;
+  auto fetch = [&](int c, int& blk, int& src, float& sc) {
     // coupling c: 0 self, 1..4 forward hop mu = c-1, 5..8 backward hop mu = c-5
-    int src, blk;
-    bool trans = false;
     if (c == 0) {
       src = site;
       blk = site * 5;
@@ -863,97 +917,125 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
     } else {
       src = nbr[(4 + c - 5) * V + site];       // x - mu
       blk = src * 5 + (c - 4);                 // B[x-mu, mu]
-      trans = true;
     }
-    const float sc = (P == P16S) ? scales[blk] : 1.0f;
-    // stage the coupling matrix M as two planes (for a backward hop
-    // Gamma5 B^H Gamma5: M[i][j] = g_i g_j conj(B[j][i])); zero padding
-    for (int t = threadIdx.x; t < NP * NP; t += blockDim.x) {
-      const int i = t / NP, j = t % NP;
-      VT re = VT(0), im = VT(0);
-      if (i < n && j < n) {
-        const int bi = trans ? j : i, bj = trans ? i : j;   // entry of the stored block
-        const int l = (bi / T) * 8 + bj / T, e = (bi % T) * T + (bj % T);
-        const size_t off = size_t(blk) * tte * 64 + (size_t(e / epl) * 64 + l) * epl + (e % epl);
+    sc = (P == P16S) ? scales[blk] : 1.0f;
+    const uint4* bu = reinterpret_cast<const uint4*>(blocks) + size_t(blk) * size_t(upl) * 64;
+#pragma unroll
+    for (int s2 = 0; s2 < MU; ++s2)
+      mreg[s2] = uoff[s2] >= 0 ? bu[uoff[s2]] : make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int s2 = 0; s2 < PU; ++s2)
+      preg[s2] = pr_[s2] >= 0
+                     ? *reinterpret_cast<const uint4*>(prow[s2] + size_t(src) * n + pk_[s2])
+                     : make_uint4(0, 0, 0, 0);
+  };
+  fetch(0, cblk, csrc, csc);
+  for (int c = 0; c < 9; ++c) {
+    const bool trans = c >= 5;
+    const float sc = csc;
+    // raw units -> LDS planes (the previous coupling's products are done)
+#pragma unroll
+    for (int s2 = 0; s2 < MU; ++s2) {
+      const uint32_t w[4] = {mreg[s2].x, mreg[s2].y, mreg[s2].z, mreg[s2].w};
+#pragma unroll
+      for (int q = 0; q < epl; ++q) {
+        const int pij = ij[s2][q];
+        if (pij < 0) continue;
+        const int bi = pij >> 8, bj = pij & 255;
+        VT re, im;
         if (P == P64) {
-          const z64 v = static_cast<const z64*>(blocks)[off];
-          re = VT(v.re);
-          im = VT(v.im);
+          re = VT(__builtin_bit_cast(double, (uint64_t(w[1]) << 32) | w[0]));
+          im = VT(__builtin_bit_cast(double, (uint64_t(w[3]) << 32) | w[2]));
         } else if (P == P32) {
-          const z32 v = static_cast<const z32*>(blocks)[off];
-          re = VT(v.re);
-          im = VT(v.im);
+          re = VT(__builtin_bit_cast(float, w[2 * q]));
+          im = VT(__builtin_bit_cast(float, w[2 * q + 1]));
         } else {
-          const uint32_t w = static_cast<const uint32_t*>(blocks)[off];
-          re = VT(lo_h(w) * sc);
-          im = VT(hi_h(w) * sc);
+          re = VT(lo_h(w[q]) * sc);
+          im = VT(hi_h(w[q]) * sc);
         }
+        int i = bi, j = bj;
         if (trans) {
-          const VT sg = ((i < (n >> 1)) == (j < (n >> 1))) ? VT(1) : VT(-1);
+          // backward hop Gamma5 B^H Gamma5: M[i][j] = g_i g_j conj(B[j][i])
+          i = bj;
+          j = bi;
+          const VT sg = ((i < half) == (j < half)) ? VT(1) : VT(-1);
           re = sg * re;
           im = -sg * im;
         }
-        if (c == 0 && i == j) im += VT(i < (n >> 1) ? tm : -tm);  // i * tm * Gamma5
+        if (c == 0 && i == j) im += VT(i < half ? tm : -tm);  // i * tm * Gamma5
+        Mr[i * LD + j] = re;
+        Mi[i * LD + j] = im;
       }
-      Mr[i * LD + j] = re;
-      Mi[i * LD + j] = im;
     }
-    for (int t = threadIdx.x; t < RB * NP; t += blockDim.x) {
-      const int r = t / NP, k = t % NP;
-      cx<VT> z = mk(VT(0), VT(0));
-      if (k < n && r < Rc) {
-        z = xin[r0 + r][size_t(src) * n + k];
-        if ((g5io & 1) && k >= (n >> 1)) z = mk(VT(-z.re), VT(-z.im));
+#pragma unroll
+    for (int s2 = 0; s2 < PU; ++s2) {
+      if (pr_[s2] < 0) continue;
+      const uint32_t w[4] = {preg[s2].x, preg[s2].y, preg[s2].z, preg[s2].w};
+      const int r = pr_[s2];
+#pragma unroll
+      for (int q = 0; q < VPC; ++q) {
+        const int k = pk_[s2] + q;
+        VT re, im;
+        if (sizeof(VT) == 8) {
+          re = VT(__builtin_bit_cast(double, (uint64_t(w[1]) << 32) | w[0]));
+          im = VT(__builtin_bit_cast(double, (uint64_t(w[3]) << 32) | w[2]));
+        } else {
+          re = VT(__builtin_bit_cast(float, w[2 * q]));
+          im = VT(__builtin_bit_cast(float, w[2 * q + 1]));
+        }
+        if ((g5io & 1) && k >= half) {
+          re = -re;
+          im = -im;
+        }
+        Pr[r * LD + k] = re;
+        Pi[r * LD + k] = im;
       }
-      Pr[r * LD + k] = z.re;
-      Pi[r * LD + k] = z.im;
     }
     __syncthreads();
-    // C += M P:  Re C += Mr Pr - Mi Pi,  Im C += Mr Pi + Mi Pr  (16x16x4 tiles)
+    // the next coupling's loads are in flight while this one multiplies
+    if (c + 1 < 9) fetch(c + 1, cblk, csrc, csc);
+    // C += M P:  Re C += Mr Pr - Mi Pi,  Im C += Mr Pi + Mi Pr  (16x16x4 tiles),
+    // k outermost so the wave's tiles interleave their MFMA chains
 #pragma unroll
-    for (int it = 0; it < kMultiMaxTiles; ++it) {
-      const int t = wave + 4 * it;
-      if (t >= ntiles) break;
-      const int rt = t % RT, ct = t / RT;
-      const VT* ar = Mr + (rt * 16 + l16) * LD + lk;
-      const VT* ai = Mi + (rt * 16 + l16) * LD + lk;
-      const VT* br = Pr + (ct * 16 + l16) * LD + lk;
-      const VT* bi = Pi + (ct * 16 + l16) * LD + lk;
-      acc_t xr = cre[it], xi = cim[it];
+    for (int k = 0; k < NP; k += 4) {
 #pragma unroll
-      for (int k = 0; k < NP; k += 4) {
-        const VT a_r = ar[k], a_i = ai[k], b_r = br[k], b_i = bi[k];
-        xr = Mfma<VT>::mma(a_r, b_r, xr);
-        xr = Mfma<VT>::mma(a_i, -b_i, xr);
-        xi = Mfma<VT>::mma(a_r, b_i, xi);
-        xi = Mfma<VT>::mma(a_i, b_r, xi);
+      for (int it = 0; it < TPW; ++it) {
+        const int t = wave + 4 * it;
+        if (t < NT) {
+          const int rt = t % RT, ct = t / RT;
+          const int ao = (rt * 16 + l16) * LD + lk + k, bo = (ct * 16 + l16) * LD + lk + k;
+          const VT a_r = Mr[ao], a_i = Mi[ao], b_r = Pr[bo], b_i = Pi[bo];
+          crr[it] = Mfma<VT>::mma(a_r, b_r, crr[it]);
+          cii[it] = Mfma<VT>::mma(a_i, b_i, cii[it]);
+          cri[it] = Mfma<VT>::mma(a_r, b_i, cri[it]);
+          cir[it] = Mfma<VT>::mma(a_i, b_r, cir[it]);
+        }
       }
-      cre[it] = xr;
-      cim[it] = xi;
     }
     __syncthreads();
   }
   // accumulators -> LDS panel planes (row r = right-hand side) -> coalesced stores
 #pragma unroll
-  for (int it = 0; it < kMultiMaxTiles; ++it) {
+  for (int it = 0; it < TPW; ++it) {
     const int t = wave + 4 * it;
-    if (t >= ntiles) break;
-    const int rt = t % RT, ct = t / RT;
-    const int col = ct * 16 + l16;
+    if (t < NT) {
+      const int rt = t % RT, ct = t / RT;
+      const int col = ct * 16 + l16;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      // accumulator value q of a lane: row 4*(lane/16)+q for the FP32 16x16x4
-      // MFMA, row lane/16 + 4*q for the FP64 one
-      const int row = rt * 16 + Mfma<VT>::row(lk, q);
-      Pr[col * LD + row] = cre[it][q];
-      Pi[col * LD + row] = cim[it][q];
+      for (int q = 0; q < 4; ++q) {
+        // accumulator value q of a lane: row 4*(lane/16)+q for the FP32 16x16x4
+        // MFMA, row lane/16 + 4*q for the FP64 one
+        const int row = rt * 16 + Mfma<VT>::row(lk, q);
+        Pr[col * LD + row] = crr[it][q] - cii[it][q];
+        Pi[col * LD + row] = cri[it][q] + cir[it][q];
+      }
     }
   }
   __syncthreads();
   for (int t = threadIdx.x; t < Rc * n; t += blockDim.x) {
     const int r = t / n, i = t % n;
     cx<VT> z = mk(Pr[r * LD + i], Pi[r * LD + i]);
-    if ((g5io & 2) && i >= (n >> 1)) z = mk(VT(-z.re), VT(-z.im));
+    if ((g5io & 2) && i >= half) z = mk(VT(-z.re), VT(-z.im));
     yout[r0 + r][size_t(site) * n + i] = z;
   }
 }
@@ -1651,8 +1733,8 @@ static void multi_launch(const MultiOps& ops, unsigned sites, int rmax, hipStrea
 template <int NP, typename VT, int P>
 static void multi_rb_launch(int rb, const MultiOps& ops, unsigned sites, int rmax, hipStream_t st) {
   if (rb == 16) multi_launch<NP, P, VT, 16>(ops, sites, rmax, st);
-  else if (rb == 32) multi_launch<NP, P, VT, 32>(ops, sites, rmax, st);
-  else multi_launch<NP, P, VT, 64>(ops, sites, rmax, st);
+  else if (rb == 32 || sizeof(VT) == 8) multi_launch<NP, P, VT, 32>(ops, sites, rmax, st);
+  else multi_launch<NP, P, VT, (sizeof(VT) == 8 ? 32 : 64)>(ops, sites, rmax, st);
 }
 
 template <int NP>
@@ -1739,6 +1821,7 @@ void launch_apply_multi_ops(Prec p, int n, const MultiOpDesc* desc, int n_ops, i
     float best = 1e30f;
     for (int cand : {16, 32, 64}) {
       if (cand > 16 && (cand / 2) >= rmax) break;   // wider tiles than the batch
+      if (cand == 64 && p == P64) break;            // FP64 accumulators of 64 would spill
       multi_dispatch(p, cand, ops, sites, rmax, st);   // warm
       DC_HIP(hipEventRecord(e0, st));
       for (int rep = 0; rep < 3; ++rep) multi_dispatch(p, cand, ops, sites, rmax, st);
