@@ -91,7 +91,16 @@ typedef struct {
   double inner_tol;     /* relative residual asked of each inner solve          */
   uint64_t seed;        /* seed of the polynomial's random start vector         */
   const void* v0;       /* optional start vector of the polynomial construction,
-                           device complex128 [V][n]; NULL = seeded Gaussian      */
+                           device complex128 [V][n] ([V/2][n] with schur);
+                           NULL = seeded Gaussian                               */
+  int32_t schur;        /* 1: solve the odd-even reduced system (Sec. 2.2):
+                           S = D_ee - D_eo D_oo^{-1} D_oe on the even sites in
+                           factored form, then x_o = D_oo^{-1}(b_o - D_oe x_e);
+                           needs every extent even, excludes block_jacobi and
+                           the batched solves.  b, x stay full-lattice; the
+                           polynomial, recycle space and Arnoldi vectors of a
+                           reduced variant are even-site compressed [V/2][n]
+                           (site x at row x / 2).                               */
 } dc_solve_opts;
 
 typedef struct {
@@ -109,7 +118,7 @@ typedef struct {
 
 /* Fill `o` with defaults: m=30, k=0, d=0, u=10, max_cycles=100000,
  * block_jacobi=0, prec=F64, outer=0, m_outer=10, max_outer=50,
- * inner_tol=1e-4, seed=0, v0=NULL. */
+ * inner_tol=1e-4, seed=0, v0=NULL, schur=0. */
 int dc_default_opts(dc_solve_opts* o);
 
 /* Build a handle for D_c (Sec. 2.2; twisted mass Sec. 2.1).
@@ -139,6 +148,16 @@ void destroy_coarse_op(dc_op_t op);
  * D^H = Gamma5 D(-mu) Gamma5.  DC_ERR_INVALID if the precision is not stored. */
 int dc_apply(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* out,
              void* stream);
+
+/* The odd-even reduced operator (Sec. 2.2, factored form):
+ * out = (D_ee - D_eo D_oo^{-1} D_oe) in (adjoint = 1: its adjoint, through
+ * Gamma5 with -mu) on compressed even-site vectors, device [V/2][n] (site x at
+ * row x / 2; complex128 for DC_PREC_F64, complex64 otherwise), in and out must
+ * not overlap.  D_oo^{-1} are the odd sites' self-block inverses in the same
+ * precision (built on first use).  DC_ERR_INVALID if an extent is odd or the
+ * precision is not stored. */
+int dc_apply_reduced(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* out,
+                     void* stream);
 
 /* Multi-right-hand-side apply (MFMA): out_r = D_c in_r (adjoint = 0) or
  * D_c^H in_r (adjoint = 1) for r < n_rhs; in, out device [n_rhs][V][n],

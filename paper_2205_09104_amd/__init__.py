@@ -51,6 +51,7 @@ class Opts:
     inner_tol: float = 1e-4
     seed: int = 0
     v0: torch.Tensor | None = field(default=None, repr=False)
+    schur: int = 0      # 1: odd-even reduced system (even extents only)
 
     def to_c(self) -> _lib.SolveOpts:
         o = _lib.SolveOpts()
@@ -59,6 +60,7 @@ class Opts:
         o.prec = PREC[self.prec]
         o.outer, o.m_outer, o.max_outer = self.outer, self.m_outer, self.max_outer
         o.inner_tol, o.seed = float(self.inner_tol), int(self.seed)
+        o.schur = int(self.schur)
         if self.v0 is not None:
             assert self.v0.dtype == torch.complex128 and self.v0.is_cuda
             o.v0 = self.v0.data_ptr()
@@ -122,6 +124,15 @@ class CoarseOp:
         out = self.empty(prec) if out is None else out
         check(load().dc_apply(self._h, PREC[prec], int(adjoint), _ptr(x), _ptr(out),
                               _stream_ptr(stream)))
+        return out
+
+    def apply_reduced(self, x: torch.Tensor, prec="f64", adjoint=False, out=None, stream=None):
+        """Odd-even reduced operator on a compressed even-site vector [V/2, n]."""
+        x = x.contiguous()
+        assert x.dtype == _vec_dtype(prec) and x.shape == (self.V // 2, self.n)
+        out = torch.empty_like(x) if out is None else out
+        check(load().dc_apply_reduced(self._h, PREC[prec], int(adjoint), _ptr(x), _ptr(out),
+                                      _stream_ptr(stream)))
         return out
 
     def apply_multi(self, X: torch.Tensor, prec="f64", adjoint=False, out=None, stream=None):
@@ -262,7 +273,8 @@ class CoarseOp:
 
     def export_recycle(self, opts: Opts, adjoint=False, stream=None):
         k = max(opts.k, 1)
-        U = torch.zeros((k, self.V, self.n), dtype=torch.complex128, device="cuda")
+        rows = self.V // 2 if opts.schur else self.V
+        U = torch.zeros((k, rows, self.n), dtype=torch.complex128, device="cuda")
         Cm = torch.zeros_like(U)
         kk = C.c_int32()
         o = opts.to_c()

@@ -32,7 +32,8 @@ class SolveOpts(C.Structure):
     _fields_ = [("m", C.c_int32), ("k", C.c_int32), ("d", C.c_int32), ("u", C.c_int32),
                 ("max_cycles", C.c_int32), ("block_jacobi", C.c_int32), ("prec", C.c_int32),
                 ("outer", C.c_int32), ("m_outer", C.c_int32), ("max_outer", C.c_int32),
-                ("inner_tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p)]
+                ("inner_tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p),
+                ("schur", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -54,6 +55,8 @@ SIGNATURES = {
     "destroy_coarse_op": (None, [C.c_void_p]),
     "dc_apply": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
                            C.c_void_p]),
+    "dc_apply_reduced": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_void_p, C.c_void_p,
+                                   C.c_void_p]),
     "dc_apply_multi": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                  C.c_void_p, C.c_void_p]),
     "dc_apply_block_jacobi": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -59,6 +59,8 @@ dc::SolveOpts convert(const dc_solve_opts* o) {
   s.inner_tol = o->inner_tol;
   s.seed = o->seed;
   s.v0 = o->v0;
+  if (o->schur != 0 && o->schur != 1) throw dc::InvalidArg("schur must be 0 or 1");
+  s.schur = o->schur;
   return s;
 }
 
@@ -99,6 +101,7 @@ int dc_default_opts(dc_solve_opts* o) {
   o->inner_tol = 1e-4;
   o->seed = 0;
   o->v0 = nullptr;
+  o->schur = 0;
   return DC_OK;
 }
 
@@ -148,6 +151,16 @@ int dc_apply(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* ou
     if (!op) throw dc::InvalidArg("null handle");
     if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
     dc::op_apply(op->op, dc::Prec(prec), adjoint, in, out, as_stream(stream));
+    return DC_OK;
+  });
+}
+
+int dc_apply_reduced(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* out,
+                     void* stream) {
+  return guarded([&] {
+    if (!op) throw dc::InvalidArg("null handle");
+    if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
+    dc::op_apply_reduced(op->op, dc::Prec(prec), adjoint, in, out, as_stream(stream));
     return DC_OK;
   });
 }

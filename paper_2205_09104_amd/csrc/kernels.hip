@@ -362,7 +362,9 @@ __device__ inline float hi_h(uint32_t w) {
 // Accumulate one lane's sub-tile: f_a += z_ac pc_c and (hop blocks)
 // g_c += conj(z_ac) pr_a.  npc_im = -Im(pc), npr_re = -Re(pr) avoid sign flips
 // per element.
-template <int T, int P, bool HOP, typename A>
+// f += M pc (row products, DOF) and g += M^T pr (column products, DOG) over one
+// lane's T x T sub-tile.
+template <int T, int P, bool DOF, bool DOG, typename A>
 __device__ inline void tile_products(const TileRegs<T, P>& R, const cx<A> (&pc)[T],
                                      const A (&npc_im)[T], const cx<A> (&pr)[T],
                                      const A (&npr_re)[T], cx<A> (&f)[T], cx<A> (&g)[T]) {
@@ -378,11 +380,13 @@ __device__ inline void tile_products(const TileRegs<T, P>& R, const cx<A> (&pc)[
         zr = R.m[a * T + c].re;
         zi = R.m[a * T + c].im;
       }
-      f[a].re = fma(zr, pc[c].re, f[a].re);
-      f[a].re = fma(zi, npc_im[c], f[a].re);
-      f[a].im = fma(zr, pc[c].im, f[a].im);
-      f[a].im = fma(zi, pc[c].re, f[a].im);
-      if constexpr (HOP) {
+      if constexpr (DOF) {
+        f[a].re = fma(zr, pc[c].re, f[a].re);
+        f[a].re = fma(zi, npc_im[c], f[a].re);
+        f[a].im = fma(zr, pc[c].im, f[a].im);
+        f[a].im = fma(zi, pc[c].re, f[a].im);
+      }
+      if constexpr (DOG) {
         g[c].re = fma(zr, pr[a].re, g[c].re);
         g[c].re = fma(zi, pr[a].im, g[c].re);
         g[c].im = fma(zr, pr[a].im, g[c].im);
@@ -391,16 +395,24 @@ __device__ inline void tile_products(const TileRegs<T, P>& R, const cx<A> (&pc)[
     }
 }
 
-// One stored block of one site, processed by one wave.
-template <int T, int P, bool FULL, bool HOP>
+// One stored block of one site, processed by one wave.  Full lattice (the
+// default): the self block writes slot 4 of gbuf[x]; a hop block B[x,mu]
+// writes B psi_{x+mu} into slot 5+mu of gbuf[x] and Gamma5 B^H Gamma5 psi_x
+// into slot mu of gbuf[x+mu].  The odd-even reduction selects one direction
+// (DIRS: 1 forward only, 2 backward only), addresses vectors and gbuf by the
+// compressed index x / 2 of one parity (COMP) and may negate the products (NEG).
+template <int T, int P, bool FULL, bool HOP, int DIRS = 3, bool COMP = false, bool NEG = false>
 __device__ __forceinline__ void apply_one_block(
     const uint4* __restrict__ bp, const float* __restrict__ scales,
     const cx<typename VecOf<P>::R>* __restrict__ psi, cx<typename VecOf<P>::R>* __restrict__ gbuf,
     int item, int site, int slot, int src, int n, double tm) {
   using A = typename Tile<T, P>::A;
   using VR = typename VecOf<P>::R;
+  constexpr bool DOF = !HOP || (DIRS & 1);
+  constexpr bool DOG = HOP && (DIRS & 2);
   const int lane = threadIdx.x;
   const int lr = lane >> 3, lc = lane & 7;
+  const int vsite = COMP ? (site >> 1) : site, vsrc = COMP ? (src >> 1) : src;
   TileRegs<T, P> R;
   R.load(bp, lane);
   cx<A> pc[T], pr[T];
@@ -409,16 +421,16 @@ __device__ __forceinline__ void apply_one_block(
   for (int q = 0; q < T; ++q) {
     const int col = lc * T + q;
     pc[q] = mk(A(0), A(0));
-    if (FULL || col < n) {
-      const cx<VR> z = psi[size_t(src) * n + col];
+    if (DOF && (FULL || col < n)) {
+      const cx<VR> z = psi[size_t(HOP ? vsrc : vsite) * n + col];
       pc[q] = mk(A(z.re), A(z.im));
     }
     npc_im[q] = -pc[q].im;
     pr[q] = mk(A(0), A(0));
-    if (HOP) {
+    if (DOG) {
       const int row = lr * T + q;
       if (FULL || row < n) {
-        const cx<VR> z = psi[size_t(site) * n + row];
+        const cx<VR> z = psi[size_t(vsite) * n + row];
         pr[q] = (row < (n >> 1)) ? mk(A(z.re), A(z.im)) : mk(A(-z.re), A(-z.im));
       }
     }
@@ -430,39 +442,42 @@ __device__ __forceinline__ void apply_one_block(
     f[q] = mk(A(0), A(0));
     g[q] = mk(A(0), A(0));
   }
-  tile_products<T, P, HOP>(R, pc, npc_im, pr, npr_re, f, g);
+  tile_products<T, P, DOF, DOG>(R, pc, npc_im, pr, npr_re, f, g);
   A s = A(1);
   if (P == P16S) s = A(scales[item]);
-#pragma unroll
-  for (int q = 0; q < T; ++q) {
-    f[q].re = sum_row8(f[q].re) * s;
-    f[q].im = sum_row8(f[q].im) * s;
-  }
-  if (lc == 0) {
-    cx<VR>* dst = gbuf + (size_t(site) * kSlots + (HOP ? 4 + slot : 4)) * n;
+  if (NEG) s = -s;
+  if constexpr (DOF) {
 #pragma unroll
     for (int q = 0; q < T; ++q) {
-      const int row = lr * T + q;
-      if (FULL || row < n) {
-        cx<A> v = f[q];
-        if (!HOP && tm != 0.0) {  // i * tm * Gamma5 psi_x in the accumulation precision
-          const A t = A(row < (n >> 1) ? tm : -tm);
-          const cx<VR> z = psi[size_t(site) * n + row];
-          v.re -= t * A(z.im);
-          v.im += t * A(z.re);
+      f[q].re = sum_row8(f[q].re) * s;
+      f[q].im = sum_row8(f[q].im) * s;
+    }
+    if (lc == 0) {
+      cx<VR>* dst = gbuf + (size_t(vsite) * kSlots + (HOP ? 4 + slot : 4)) * n;
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        const int row = lr * T + q;
+        if (FULL || row < n) {
+          cx<A> v = f[q];
+          if (!HOP && tm != 0.0) {  // i * tm * Gamma5 psi_x in the accumulation precision
+            const A t = A(row < (n >> 1) ? tm : -tm);
+            const cx<VR> z = psi[size_t(vsite) * n + row];
+            v.re -= t * A(z.im);
+            v.im += t * A(z.re);
+          }
+          dst[row] = mk(VR(v.re), VR(v.im));
         }
-        dst[row] = mk(VR(v.re), VR(v.im));
       }
     }
   }
-  if constexpr (HOP) {
+  if constexpr (DOG) {
 #pragma unroll
     for (int q = 0; q < T; ++q) {
       g[q].re = sum_col8(g[q].re) * s;
       g[q].im = sum_col8(g[q].im) * s;
     }
     if (lr == 0) {
-      cx<VR>* dst = gbuf + (size_t(src) * kSlots + (slot - 1)) * n;  // x + mu receives it
+      cx<VR>* dst = gbuf + (size_t(vsrc) * kSlots + (slot - 1)) * n;  // x + mu receives it
 #pragma unroll
       for (int q = 0; q < T; ++q) {
         const int col = lc * T + q;
@@ -500,6 +515,62 @@ __global__ __launch_bounds__(64) void k_apply_blocks(
   } else {
     const int src = nbr[(slot - 1) * V + site];
     apply_one_block<T, P, FULL, true>(bp, scales, psi, gbuf, item, site, slot, src, n, tm);
+  }
+}
+
+// Odd-even reduction, stage 1 over compressed vectors (site x of parity p at
+// position x / 2).  Every stored block is read once per launch and yields one
+// product:
+//   MODE 1 (t_o = D_oe x_e, odd rows): hop blocks of odd sites forward (source
+//     x+mu even), hop blocks of even sites backward (row x+mu odd, source x);
+//     the self slot of every odd row is zeroed.
+//   MODE 2 (y_e = A_e x_e - D_eo t_o, even rows): self blocks of even sites on
+//     x_e (zero slot if x_e is null), hop blocks of even sites forward and of
+//     odd sites backward on t_o, both negated.
+// Items and their XCD-aware order as in k_apply_blocks; items of the other
+// parity exit at entry.
+template <int T, int P, bool FULL, int MODE>
+__global__ __launch_bounds__(64) void k_apply_oddeven(
+    const void* __restrict__ blocks, const float* __restrict__ scales,
+    const cx<typename VecOf<P>::R>* __restrict__ x_e, const cx<typename VecOf<P>::R>* __restrict__ t_o,
+    cx<typename VecOf<P>::R>* __restrict__ gbuf, const int* __restrict__ nbr,
+    const unsigned char* __restrict__ par, int V, int n, int chunk, double tm,
+    const int* __restrict__ done) {
+  using VR = typename VecOf<P>::R;
+  if (done && *done) return;
+  const int b = blockIdx.x;
+  const int item = (b & 7) * chunk + (b >> 3);
+  if (item >= 5 * V) return;
+  const int site = item / 5, slot = item - 5 * site;
+  const int odd = par[site];
+  const size_t blk_units = size_t(Tile<T, P>::UNITS) * 64;
+  const uint4* bp = static_cast<const uint4*>(blocks) + size_t(item) * blk_units;
+  if (slot == 0) {
+    const bool zero_slot = (MODE == 1) ? (odd != 0) : (odd == 0 && x_e == nullptr);
+    if (zero_slot) {
+      cx<VR>* dst = gbuf + (size_t(site >> 1) * kSlots + 4) * n;
+      for (int i = threadIdx.x; i < n; i += 64) dst[i] = mk(VR(0), VR(0));
+    } else if (MODE == 2 && odd == 0) {
+      apply_one_block<T, P, FULL, false, 3, true, false>(bp, scales, x_e, gbuf, item, site, 0,
+                                                         site, n, tm);
+    }
+    return;
+  }
+  const int src = nbr[(slot - 1) * V + site];
+  if (MODE == 1) {
+    if (odd)
+      apply_one_block<T, P, FULL, true, 1, true, false>(bp, scales, x_e, gbuf, item, site, slot,
+                                                        src, n, tm);
+    else
+      apply_one_block<T, P, FULL, true, 2, true, false>(bp, scales, x_e, gbuf, item, site, slot,
+                                                        src, n, tm);
+  } else {
+    if (!odd)
+      apply_one_block<T, P, FULL, true, 1, true, true>(bp, scales, t_o, gbuf, item, site, slot,
+                                                       src, n, tm);
+    else
+      apply_one_block<T, P, FULL, true, 2, true, true>(bp, scales, t_o, gbuf, item, site, slot,
+                                                       src, n, tm);
   }
 }
 
@@ -661,17 +732,18 @@ __global__ __launch_bounds__(64) void k_block_jacobi(
     const void* __restrict__ blocks, const float* __restrict__ scales,
     const cx<typename VecOf<P>::R>* __restrict__ tin, cx<typename VecOf<P>::R>* out,
     const cx<typename VecOf<P>::R>* vin, cx<typename VecOf<P>::R>* y, int V, int n, int chunk,
-    z64 c0, z64 ca, z64 cb, const int* __restrict__ done) {
+    z64 c0, z64 ca, z64 cb, const int* __restrict__ done, const int* __restrict__ rowsite) {
   using A = typename Tile<T, P>::A;
   using VR = typename VecOf<P>::R;
   if (done && *done) return;
   const int b = blockIdx.x;
-  const int site = (b & 7) * chunk + (b >> 3);
+  const int site = (b & 7) * chunk + (b >> 3);   // row of the vectors
   if (site >= V) return;
+  const int blk = rowsite ? rowsite[site] : site;  // block of that row's lattice site
   const int lane = threadIdx.x, lr = lane >> 3, lc = lane & 7;
   const size_t blk_units = size_t(Tile<T, P>::UNITS) * 64;
   TileRegs<T, P> R;
-  R.load(static_cast<const uint4*>(blocks) + size_t(site) * blk_units, lane);
+  R.load(static_cast<const uint4*>(blocks) + size_t(blk) * blk_units, lane);
   cx<A> pc[T], pr[T], f[T], g[T];
   A npc_im[T], npr_re[T];
 #pragma unroll
@@ -694,9 +766,9 @@ __global__ __launch_bounds__(64) void k_block_jacobi(
     f[q] = mk(A(0), A(0));
     g[q] = mk(A(0), A(0));
   }
-  tile_products<T, P, false>(R, pc, npc_im, pr, npr_re, f, g);
+  tile_products<T, P, true, false>(R, pc, npc_im, pr, npr_re, f, g);
   A s = A(1);
-  if (P == P16S) s = A(scales[site]);
+  if (P == P16S) s = A(scales[blk]);
 #pragma unroll
   for (int q = 0; q < T; ++q) {
     f[q].re = sum_row8(f[q].re) * s;
@@ -1421,6 +1493,24 @@ __global__ void k_gaussian(z64* out, size_t N, uint64_t seed, uint32_t stream_id
   }
 }
 
+// ------------------------------------------------------------------ odd-even split
+template <typename VR>
+__global__ void k_oddeven_split(int n, int H, const int* __restrict__ esite,
+                                const int* __restrict__ osite, cx<VR>* full, cx<VR>* ve,
+                                cx<VR>* vo, int dir) {
+  const size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= size_t(H) * n) return;
+  const int r = int(i / n), c = int(i % n);
+  const size_t fe = size_t(esite[r]) * n + c, fo = size_t(osite[r]) * n + c;
+  if (dir == 0) {
+    if (ve) ve[i] = full[fe];
+    if (vo) vo[i] = full[fo];
+  } else {
+    full[fe] = ve ? ve[i] : mk(VR(0), VR(0));
+    full[fo] = vo ? vo[i] : mk(VR(0), VR(0));
+  }
+}
+
 // ------------------------------------------------------------------ Arnoldi
 __global__ void k_arnoldi_init(ArnoldiDev a, double beta) {
   if (threadIdx.x == 0) {
@@ -1634,7 +1724,7 @@ void launch_invert_blocks(const void* tiled64, int V, int n, double tm, void* ou
 template <int P, bool FROMBUF, int EPI>
 static void bj_T(int n, int V, const void* blocks, const float* scales, const void* tin, void* out,
                  const void* vin, void* y, z64 c0, z64 ca, z64 cb, const int* done,
-                 hipStream_t st) {
+                 hipStream_t st, const int* rowsite = nullptr) {
   using VR = typename VecOf<P>::R;
   const int chunk = (V + 7) / 8;
   const dim3 grid(unsigned(chunk) * 8u), block(64);
@@ -1648,10 +1738,10 @@ static void bj_T(int n, int V, const void* blocks, const float* scales, const vo
   case TV:                                                                                       \
     if (full)                                                                                    \
       hipLaunchKernelGGL((k_block_jacobi<TV, P, true, FROMBUF, EPI>), grid, block, 0, st, blocks, \
-                         scales, ti, o, vi, yy, V, n, chunk, c0, ca, cb, done);                  \
+                         scales, ti, o, vi, yy, V, n, chunk, c0, ca, cb, done, rowsite);         \
     else                                                                                         \
       hipLaunchKernelGGL((k_block_jacobi<TV, P, false, FROMBUF, EPI>), grid, block, 0, st,       \
-                         blocks, scales, ti, o, vi, yy, V, n, chunk, c0, ca, cb, done);          \
+                         blocks, scales, ti, o, vi, yy, V, n, chunk, c0, ca, cb, done, rowsite); \
     break;
     DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
 #undef DC_CASE
@@ -1664,10 +1754,10 @@ static void bj_T(int n, int V, const void* blocks, const float* scales, const vo
 template <bool FROMBUF, int EPI>
 static void bj_P(Prec p, int n, int V, const void* blocks, const float* scales, const void* tin,
                  void* out, const void* vin, void* y, z64 c0, z64 ca, z64 cb, const int* done,
-                 hipStream_t st) {
-  if (p == P64) bj_T<P64, FROMBUF, EPI>(n, V, blocks, scales, tin, out, vin, y, c0, ca, cb, done, st);
-  else if (p == P32) bj_T<P32, FROMBUF, EPI>(n, V, blocks, scales, tin, out, vin, y, c0, ca, cb, done, st);
-  else bj_T<P16S, FROMBUF, EPI>(n, V, blocks, scales, tin, out, vin, y, c0, ca, cb, done, st);
+                 hipStream_t st, const int* rowsite = nullptr) {
+  if (p == P64) bj_T<P64, FROMBUF, EPI>(n, V, blocks, scales, tin, out, vin, y, c0, ca, cb, done, st, rowsite);
+  else if (p == P32) bj_T<P32, FROMBUF, EPI>(n, V, blocks, scales, tin, out, vin, y, c0, ca, cb, done, st, rowsite);
+  else bj_T<P16S, FROMBUF, EPI>(n, V, blocks, scales, tin, out, vin, y, c0, ca, cb, done, st, rowsite);
 }
 
 void launch_bj_vec(Prec p, int n, int V, const void* inv, const float* scales, const void* in,
@@ -1680,6 +1770,74 @@ void launch_bj_gather_store(Prec p, int n, int V, const void* inv, const float* 
                             const void* gbuf, void* out, const int* done, hipStream_t st) {
   const z64 z = mk(0.0, 0.0);
   bj_P<true, 0>(p, n, V, inv, scales, gbuf, out, nullptr, nullptr, z, z, z, done, st);
+}
+
+void launch_bj_rows(Prec p, int n, int rows, const int* rowsite, const void* inv,
+                    const float* scales, const void* in, int from_gbuf, void* out,
+                    const int* done, hipStream_t st) {
+  const z64 z = mk(0.0, 0.0);
+  if (from_gbuf)
+    bj_P<true, 0>(p, n, rows, inv, scales, in, out, nullptr, nullptr, z, z, z, done, st, rowsite);
+  else
+    bj_P<false, 0>(p, n, rows, inv, scales, in, out, nullptr, nullptr, z, z, z, done, st, rowsite);
+}
+
+template <int P, int MODE>
+static void oddeven_T(int n, int V, const void* blocks, const float* scales, const void* x_e,
+                      const void* t_o, void* gbuf, const int* nbr, const unsigned char* par,
+                      double tm, const int* done, hipStream_t st) {
+  using VR = typename VecOf<P>::R;
+  const int chunk = (5 * V + 7) / 8;
+  const dim3 grid(unsigned(chunk) * 8u), block(64);
+  const auto* xe = static_cast<const cx<VR>*>(x_e);
+  const auto* to = static_cast<const cx<VR>*>(t_o);
+  auto* pg = static_cast<cx<VR>*>(gbuf);
+  const bool full = (n % 8) == 0;
+  switch (tile_T(n)) {
+#define DC_CASE(TV)                                                                            \
+  case TV:                                                                                     \
+    if (full)                                                                                  \
+      hipLaunchKernelGGL((k_apply_oddeven<TV, P, true, MODE>), grid, block, 0, st, blocks,     \
+                         scales, xe, to, pg, nbr, par, V, n, chunk, tm, done);                 \
+    else                                                                                       \
+      hipLaunchKernelGGL((k_apply_oddeven<TV, P, false, MODE>), grid, block, 0, st, blocks,    \
+                         scales, xe, to, pg, nbr, par, V, n, chunk, tm, done);                 \
+    break;
+    DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
+#undef DC_CASE
+    default:
+      throw InvalidArg("block size n > 64 is not supported");
+  }
+  DC_HIP(hipGetLastError());
+}
+
+void launch_apply_oddeven(Prec p, int mode, int n, int V, const void* blocks, const float* scales,
+                          const void* x_e, const void* t_o, void* gbuf, const int* nbr,
+                          const unsigned char* par, double tm, const int* done, hipStream_t st) {
+  if (mode != 1 && mode != 2) throw InvalidArg("odd-even stage mode must be 1 or 2");
+  if (mode == 1) {
+    if (p == P64) oddeven_T<P64, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
+    else if (p == P32) oddeven_T<P32, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
+    else oddeven_T<P16S, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
+  } else {
+    if (p == P64) oddeven_T<P64, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
+    else if (p == P32) oddeven_T<P32, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
+    else oddeven_T<P16S, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
+  }
+}
+
+void launch_oddeven_split(Prec p, int n, int half_sites, const int* esite, const int* osite,
+                          void* full, void* ve, void* vo, int dir, hipStream_t st) {
+  const size_t N = size_t(half_sites) * n;
+  if (N == 0) return;
+  const dim3 grid(unsigned((N + 255) / 256)), block(256);
+  if (p == P64)
+    hipLaunchKernelGGL(k_oddeven_split<double>, grid, block, 0, st, n, half_sites, esite, osite,
+                       static_cast<z64*>(full), static_cast<z64*>(ve), static_cast<z64*>(vo), dir);
+  else
+    hipLaunchKernelGGL(k_oddeven_split<float>, grid, block, 0, st, n, half_sites, esite, osite,
+                       static_cast<z32*>(full), static_cast<z32*>(ve), static_cast<z32*>(vo), dir);
+  DC_HIP(hipGetLastError());
 }
 
 void launch_bj_gather_poly_first(Prec p, int n, int V, const void* inv, const float* scales,

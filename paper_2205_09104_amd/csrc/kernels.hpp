@@ -70,6 +70,26 @@ void launch_bj_gather_poly(Prec p, int n, int V, const void* inv, const float* s
                            const void* gbuf, void* prod, void* y, z64 ca, z64 cb, const int* done,
                            hipStream_t st);
 
+// out_r = B_{site(r)}^{-1} in_r for rows r < rows of a compressed vector, where
+// rowsite[r] is the lattice site of row r (null: row r is site r); in is a
+// plain vector or (from_gbuf) a gbuf whose 9 slots are summed first.
+void launch_bj_rows(Prec p, int n, int rows, const int* rowsite, const void* inv,
+                    const float* scales, const void* in, int from_gbuf, void* out,
+                    const int* done, hipStream_t st);
+
+// ---------------------------------------------------------------- odd-even reduction
+// Stage 1 of D_oe (mode 1: odd rows of gbuf from x_e) or of A_e x_e - D_eo t_o
+// (mode 2: even rows from x_e, t_o; x_e null gives -D_eo t_o) over compressed
+// vectors (site x of a parity at row x / 2, every extent even); gbuf: [V/2][9][n]
+// summed by the ordinary gathers over V/2 rows.  par: uint8 [V] site parity.
+void launch_apply_oddeven(Prec p, int mode, int n, int V, const void* blocks, const float* scales,
+                          const void* x_e, const void* t_o, void* gbuf, const int* nbr,
+                          const unsigned char* par, double tm, const int* done, hipStream_t st);
+// split a full-lattice vector into its compressed even and odd halves, or merge
+// them back (dir 0: split, 1: merge); esite/osite: int32 [V/2] row -> site
+void launch_oddeven_split(Prec p, int n, int half_sites, const int* esite, const int* osite,
+                          void* full, void* ve, void* vo, int dir, hipStream_t st);
+
 // ---------------------------------------------------------------- multi-RHS apply
 // yout[r] = D xin[r] for r < R (device arrays of R vector pointers, vectors in
 // the precision's vector type), MFMA based; g5io bit 0 multiplies inputs and

@@ -38,14 +38,34 @@ static size_t block_units(int n, Prec p) {
   return size_t(tile_elems(n, epl) / epl) * 64;  // 16-byte units per block
 }
 
+void* Op::gbuf_s(Prec p) {
+  const size_t rows = size_t(V / 2) * 9 * n;
+  if (p == P64) {
+    gbs64.ensure(rows * sizeof(z64));
+    return gbs64.p;
+  }
+  gbs32.ensure(rows * sizeof(z32));
+  return gbs32.p;
+}
+
+void* Op::tmp_s(Prec p) {
+  const size_t len = size_t(V / 2) * n;
+  if (p == P64) {
+    ts64.ensure(len * sizeof(z64));
+    return ts64.p;
+  }
+  ts32.ensure(len * sizeof(z32));
+  return ts32.p;
+}
+
 const void* Op::blocks(Prec p) const {
   if (p == P64) return blk64.p;
   if (p == P32) return blk32.p;
   return blk16.p;
 }
 
-Variant& Op::variant(Prec p, int sign, int bj, int d) {
-  auto key = std::make_tuple(int(p), sign, bj, d);
+Variant& Op::variant(Prec p, int sign, int bj, int d, int schur) {
+  auto key = std::make_tuple(int(p), sign, bj, d, schur);
   auto it = variants.find(key);
   if (it != variants.end()) return *it->second;
   auto v = std::make_unique<Variant>();
@@ -53,6 +73,7 @@ Variant& Op::variant(Prec p, int sign, int bj, int d) {
   v->sign = sign;
   v->bj = bj;
   v->d = d;
+  v->schur = schur;
   Variant& ref = *v;
   variants.emplace(key, std::move(v));
   return ref;
@@ -107,6 +128,30 @@ void op_build(Op& op, const int dims[4], int n_tv, int store, double mu, const v
   if (op.store & 6) op.gbuf32.alloc(size_t(op.V) * 9 * op.n * sizeof(z32));
   op.redpart.alloc(size_t(kRedCap) * sizeof(double));
   op.scal.alloc(256);
+  // checkerboard tables for the odd-even reduction (every extent even): site
+  // parity and the sites of each parity in increasing order (row r of a
+  // compressed vector is site esite[r] / osite[r]; for even L0 that is 2r or 2r+1)
+  op.oddeven = (dims[0] % 2 == 0) && (dims[1] % 2 == 0) && (dims[2] % 2 == 0) &&
+               (dims[3] % 2 == 0);
+  if (op.oddeven) {
+    std::vector<unsigned char> par(op.V);
+    std::vector<int> es, os;
+    es.reserve(op.V / 2);
+    os.reserve(op.V / 2);
+    for (int x = 0; x < op.V; ++x) {
+      const int x0 = x % dims[0], x1 = (x / dims[0]) % dims[1];
+      const int x2 = (x / (dims[0] * dims[1])) % dims[2], x3 = x / (dims[0] * dims[1] * dims[2]);
+      par[x] = static_cast<unsigned char>((x0 + x1 + x2 + x3) & 1);
+      (par[x] ? os : es).push_back(x);
+    }
+    op.par.alloc(par.size());
+    op.esite.alloc(es.size() * sizeof(int));
+    op.osite.alloc(os.size() * sizeof(int));
+    DC_HIP(hipMemcpyAsync(op.par.p, par.data(), par.size(), hipMemcpyHostToDevice, st));
+    DC_HIP(hipMemcpyAsync(op.esite.p, es.data(), es.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    DC_HIP(hipMemcpyAsync(op.osite.p, os.data(), os.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    DC_HIP(hipStreamSynchronize(st));  // host tables must outlive the copies
+  }
   copy_blocks_in(op, self_blocks, hop_blocks, on_device, st);
 }
 
@@ -277,6 +322,41 @@ static const void* bj_blocks(const Op::BJ& b, Prec p) {
   return p == P64 ? b.b64.p : (p == P32 ? b.b32.p : b.b16.p);
 }
 
+void op_apply_reduced(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_t st) {
+  check_prec(op, p);
+  if (!op.oddeven) throw InvalidArg("the odd-even reduction needs every lattice extent even");
+  if (!in || !out) throw InvalidArg("null vector pointer");
+  const int half = op.V / 2;
+  const size_t N = size_t(half) * op.n;
+  {
+    const char* a = static_cast<const char*>(in);
+    const char* b = static_cast<const char*>(out);
+    const size_t span = N * vec_bytes(p);
+    if (a < b + span && b < a + span) throw InvalidArg("in and out overlap");
+  }
+  // S(mu)^H = Gamma5 S(-mu) Gamma5, as for the full operator
+  const int sign = adjoint ? -1 : +1;
+  const double tm = sign * op.mu;
+  const Op::BJ& bj = op.ensure_bj(sign, st);
+  const void* inv = bj_blocks(bj, p);
+  const float* invsc = (p == P16S) ? bj.sc16.as<float>() : nullptr;
+  const auto* par = static_cast<const unsigned char*>(op.par.p);
+  void* gb = op.gbuf_s(p);
+  void* ts = op.tmp_s(p);
+  const void* src = in;
+  if (adjoint) {
+    launch_gamma5(p, in, out, half, op.n, st);
+    src = out;
+  }
+  launch_apply_oddeven(p, 1, op.n, op.V, op.blocks(p), op.scales(p), src, nullptr, gb,
+                       op.nbr.as<int>(), par, tm, nullptr, st);
+  launch_bj_rows(p, op.n, half, op.osite.as<int>(), inv, invsc, gb, 1, ts, nullptr, st);
+  launch_apply_oddeven(p, 2, op.n, op.V, op.blocks(p), op.scales(p), src, ts, gb,
+                       op.nbr.as<int>(), par, tm, nullptr, st);
+  launch_gather_store(p, op.n, half, gb, out, nullptr, st);
+  if (adjoint) launch_gamma5(p, out, out, half, op.n, st);
+}
+
 void op_apply_bj(Op& op, const void* in, void* out, hipStream_t st) {
   if (!in || !out || in == out) throw InvalidArg("bad vector pointers");
   const Op::BJ& b = op.ensure_bj(+1, st);
@@ -336,13 +416,30 @@ struct Krylov {
   double brk;
   const void* bjinv = nullptr;   // block-Jacobi inverses of this precision, if used
   const float* bjsc = nullptr;
+  int rows = 0;                   // rows of the vectors (sites, or half of them when reduced)
+  void* gb = nullptr;             // gbuf of the apply's stage 1
+  const void* oinv = nullptr;     // odd-even reduction: D_oo^{-1} blocks, odd-site temporary
+  const float* oinvsc = nullptr;
+  Z* ts = nullptr;
 
   // recycle_tmp = false: no U/C refresh buffers (members of a batched solve)
   Krylov(Op& op_, Variant& v, const SolveOpts& o_, DevBuf& ws_, DevBuf& sm_, int steps_max,
          hipStream_t st_, bool recycle_tmp = true)
-      : op(op_), var(v), o(o_), p(v.prec), tm(v.sign * op_.mu), st(st_), N(op_.N()), ws(ws_),
-        sm(sm_) {
+      : op(op_), var(v), o(o_), p(v.prec), tm(v.sign * op_.mu), st(st_),
+        N(v.schur ? op_.N() / 2 : op_.N()), ws(ws_), sm(sm_) {
     brk = (p == P64) ? 1e-14 : 1e-6;
+    rows = v.schur ? op.V / 2 : op.V;
+    if (v.schur) {
+      if (!op.oddeven) throw InvalidArg("the odd-even reduction needs every lattice extent even");
+      if (v.bj) throw InvalidArg("block Jacobi and the odd-even reduction are exclusive");
+      const Op::BJ& b = op.ensure_bj(v.sign, st);   // D_oo^{-1}: inverses of the odd self blocks
+      oinv = bj_blocks(b, p);
+      oinvsc = (p == P16S) ? b.sc16.as<float>() : nullptr;
+      gb = op.gbuf_s(p);
+      ts = static_cast<Z*>(op.tmp_s(p));
+    } else {
+      gb = op.gbuf(p);
+    }
     if (v.bj) {
       const Op::BJ& b = op.ensure_bj(v.sign, st);
       bjinv = bj_blocks(b, p);
@@ -398,18 +495,34 @@ struct Krylov {
   Z* Uv() const { return var.U.as<Z>(); }
   Z* Cv() const { return var.C.as<Z>(); }
 
+  // Stage 1 of one apply into gb: D in on the full lattice, or the reduced
+  // operator A_e in - D_eo D_oo^{-1} D_oe in on compressed even vectors
+  // (Sec. 2.2, factored form: D_oe, the odd self-block inverses, D_eo).
+  void stage(const Z* in, const int* done) {
+    if (!var.schur) {
+      stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), in, gb, op.nbr.as<int>(), tm, done,
+             st);
+      return;
+    }
+    const auto* par = static_cast<const unsigned char*>(op.par.p);
+    launch_apply_oddeven(p, 1, op.n, op.V, op.blocks(p), op.scales(p), in, nullptr, gb,
+                         op.nbr.as<int>(), par, tm, done, st);
+    launch_bj_rows(p, op.n, rows, op.osite.as<int>(), oinv, oinvsc, gb, 1, ts, done, st);
+    launch_apply_oddeven(p, 2, op.n, op.V, op.blocks(p), op.scales(p), in, ts, gb,
+                         op.nbr.as<int>(), par, tm, done, st);
+  }
+
   // A~ in = (B^{-1}) D in (one matvec)
   void A(const Z* in, Z* out, const int* done) {
-    stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
-                        tm, done, st);
-    if (bjinv) launch_bj_gather_store(p, op.n, op.V, bjinv, bjsc, op.gbuf(p), out, done, st);
-    else launch_gather_store(p, op.n, op.V, op.gbuf(p), out, done, st);
+    stage(in, done);
+    if (bjinv) launch_bj_gather_store(p, op.n, rows, bjinv, bjsc, gb, out, done, st);
+    else launch_gather_store(p, op.n, rows, gb, out, done, st);
     ++matvecs;
   }
 
   // rhat = B^{-1} r (or a copy without block Jacobi)
   void left_precondition(const Z* r, Z* out) {
-    if (bjinv) launch_bj_vec(p, op.n, op.V, bjinv, bjsc, r, out, st);
+    if (bjinv) launch_bj_vec(p, op.n, rows, bjinv, bjsc, r, out, st);
     else DC_HIP(hipMemcpyAsync(out, r, N * sizeof(Z), hipMemcpyDeviceToDevice, st));
   }
 
@@ -426,23 +539,21 @@ struct Krylov {
       return;
     }
     // i = 1: prod = v - A v / theta_0;  y = v / theta_0 + prod / theta_1
-    stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), in, op.gbuf(p), op.nbr.as<int>(),
-                        tm, done, st);
+    stage(in, done);
     if (bjinv)
-      launch_bj_gather_poly_first(p, op.n, op.V, bjinv, bjsc, op.gbuf(p), in, prod, out, inv(th[0]),
+      launch_bj_gather_poly_first(p, op.n, rows, bjinv, bjsc, gb, in, prod, out, inv(th[0]),
                                   inv(th[0]), inv(th[1]), done, st);
     else
-      launch_gather_poly_first(p, op.n, op.V, op.gbuf(p), in, prod, out, inv(th[0]), inv(th[0]),
+      launch_gather_poly_first(p, op.n, rows, gb, in, prod, out, inv(th[0]), inv(th[0]),
                                inv(th[1]), done, st);
     ++matvecs;
     for (int i = 2; i < d; ++i) {
-      stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), prod, op.gbuf(p),
-                          op.nbr.as<int>(), tm, done, st);
+      stage(prod, done);
       if (bjinv)
-        launch_bj_gather_poly(p, op.n, op.V, bjinv, bjsc, op.gbuf(p), prod, out, inv(th[i - 1]),
+        launch_bj_gather_poly(p, op.n, rows, bjinv, bjsc, gb, prod, out, inv(th[i - 1]),
                               inv(th[i]), done, st);
       else
-        launch_gather_poly(p, op.n, op.V, op.gbuf(p), prod, out, inv(th[i - 1]), inv(th[i]), done, st);
+        launch_gather_poly(p, op.n, rows, gb, prod, out, inv(th[i - 1]), inv(th[i]), done, st);
       ++matvecs;
     }
   }
@@ -459,9 +570,8 @@ struct Krylov {
 
   // r = b - D x (true residual in the variant's precision); returns ||r||
   double true_resid(const Z* x, const Z* b, Z* r) {
-    stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), x, op.gbuf(p), op.nbr.as<int>(),
-                        tm, nullptr, st);
-    launch_gather_resid(p, op.n, op.V, op.gbuf(p), b, r, op.red(), nrm, st);
+    stage(x, nullptr);
+    launch_gather_resid(p, op.n, rows, gb, b, r, op.red(), nrm, st);
     ++matvecs;
     double h;
     DC_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -827,7 +937,7 @@ void build_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st) {
   po.k = 0;
   Krylov<VR> K(op, var, po, var.ws, var.sm, std::max(o.d, o.m), st);
   var.theta.clear();  // build with A~ itself (no polynomial yet)
-  const size_t N = op.N();
+  const size_t N = K.N;
   // start vector: caller's v0 (complex128) or a seeded Gaussian
   DevBuf v64;
   const z64* src = static_cast<const z64*>(o.v0);
@@ -879,7 +989,7 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta) {
   check_prec(op, o.prec);
   if (o.d < 1) throw InvalidArg("d must be >= 1");
-  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d);
+  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d, o.schur);
   var.poly_version = -1;
   if (var.prec == P64) build_poly<double>(op, var, o, st);
   else build_poly<float>(op, var, o, st);
@@ -890,7 +1000,7 @@ int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& t
 void op_poly_apply(Op& op, const SolveOpts& o, const void* in, void* out, hipStream_t st) {
   check_prec(op, o.prec);
   if (!in || !out || in == out) throw InvalidArg("bad vector pointers");
-  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d);
+  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d, o.schur);
   if (var.poly_version != op.version) throw BadState("polynomial not built for this operator");
   if (var.prec == P64) {
     Krylov<double> K(op, var, o, var.ws, var.sm, std::max(o.m, o.d), st);
@@ -905,14 +1015,14 @@ int op_arnoldi(Op& op, const SolveOpts& o, const void* v, int steps, hipStream_t
                std::vector<cd>& hbar) {
   check_prec(op, o.prec);
   if (!v || steps < 1) throw InvalidArg("bad Arnoldi arguments");
-  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d);
+  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d, o.schur);
   ensure_poly(op, var, o, st, nullptr);
   auto run = [&](auto tag) -> int {
     using VR = decltype(tag);
     Krylov<VR> K(op, var, o, var.ws, var.sm, std::max(steps, o.d), st);
     const z64* src = static_cast<const z64*>(v);
-    if (var.prec == P64) DC_HIP(hipMemcpyAsync(K.tmp, src, op.N() * sizeof(z64), hipMemcpyDeviceToDevice, st));
-    else launch_convert_64to32(src, reinterpret_cast<z32*>(K.tmp), op.N(), op.n, 0, st);
+    if (var.prec == P64) DC_HIP(hipMemcpyAsync(K.tmp, src, K.N * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    else launch_convert_64to32(src, reinterpret_cast<z32*>(K.tmp), K.N, op.n, 0, st);
     const double beta = K.norm(K.tmp);
     auto c = K.cycle(K.tmp, beta, steps, 0, -1.0, 0);
     hbar.assign(size_t(steps + 1) * steps, cd(0.0));
@@ -959,15 +1069,20 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
     throw InvalidArg("bad outer-loop options");
   for (int r = 0; r < n_rhs; ++r)
     if (!(tol[r] > 0.0)) throw InvalidArg("tolerances must be positive");
+  if (o.schur && !op.oddeven) throw InvalidArg("the odd-even reduction needs every lattice extent even");
+  if (o.schur && o.block_jacobi) throw InvalidArg("block Jacobi and the odd-even reduction are exclusive");
   const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
-  const size_t N = op.N();
+  const size_t Nfull = op.N();
+  // system size: the full lattice, or the even sites of the reduced system
+  const size_t N = o.schur ? Nfull / 2 : Nfull;
+  const int half = op.V / 2;
   int all_ok = 1;
   for (int r = 0; r < n_rhs; ++r) {
     const auto t0 = std::chrono::steady_clock::now();
     SolveStats s;
-    const z64* br = static_cast<const z64*>(b) + size_t(r) * N;
-    z64* xr = static_cast<z64*>(x) + size_t(r) * N;
-    Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d);
+    const z64* br = static_cast<const z64*>(b) + size_t(r) * Nfull;
+    z64* xr = static_cast<z64*>(x) + size_t(r) * Nfull;
+    Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d, o.schur);
     const auto ts = std::chrono::steady_clock::now();
     ensure_poly(op, var, o, st, &s);
     s.t_setup_ms = ms_since(ts);
@@ -975,17 +1090,51 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
     const z64* bb = br;
     z64* xx = xr;
     if (adjoint) {
-      op.t64a.ensure(N * sizeof(z64));
-      op.t64b.ensure(N * sizeof(z64));
+      op.t64a.ensure(Nfull * sizeof(z64));
+      op.t64b.ensure(Nfull * sizeof(z64));
       launch_gamma5(P64, br, op.t64a.p, op.V, op.n, st);
       if (use_x0) launch_gamma5(P64, xr, op.t64b.p, op.V, op.n, st);
       bb = op.t64a.as<z64>();
       xx = op.t64b.as<z64>();
     }
+    // odd-even reduction (Sec. 2.2): solve S x_e = b_e - D_eo D_oo^{-1} b_o on
+    // compressed even vectors to tol ||b|| / ||b^_e|| (the odd rows of the full
+    // residual vanish), then x_o = D_oo^{-1} (b_o - D_oe x_e)
+    const z64* bfull = bb;
+    z64* xfull = xx;
+    double tol_r = tol[r];
+    DevBuf be, bo, xe, to;
+    const int* esite = op.esite.as<int>();
+    const int* osite = op.osite.as<int>();
+    const double tm = sign * op.mu;
+    const void* oinv = nullptr;
+    if (o.schur) {
+      oinv = op.ensure_bj(sign, st).b64.p;
+      be.alloc(N * sizeof(z64));
+      bo.alloc(N * sizeof(z64));
+      xe.alloc(N * sizeof(z64));
+      to.alloc(N * sizeof(z64));
+      const auto* par = static_cast<const unsigned char*>(op.par.p);
+      launch_oddeven_split(P64, op.n, half, esite, osite, const_cast<z64*>(bfull), be.p, bo.p, 0, st);
+      if (use_x0) launch_oddeven_split(P64, op.n, half, esite, osite, xfull, xe.p, nullptr, 0, st);
+      launch_bj_rows(P64, op.n, half, osite, oinv, nullptr, bo.p, 0, to.p, nullptr, st);
+      launch_apply_oddeven(P64, 2, op.n, op.V, op.blocks(P64), nullptr, nullptr, to.p,
+                           op.gbuf_s(P64), op.nbr.as<int>(), par, tm, nullptr, st);
+      launch_gather_store(P64, op.n, half, op.gbuf_s(P64), op.tmp_s(P64), nullptr, st);
+      launch_axpy(P64, mk(1.0, 0.0), op.tmp_s(P64), be.p, N, st);   // be := b^_e
+      double nb[2];
+      launch_norm2(P64, bfull, Nfull, op.red(), op.scal.as<double>(), st);
+      launch_norm2(P64, be.p, N, op.red(), op.scal.as<double>() + 1, st);
+      DC_HIP(hipMemcpyAsync(nb, op.scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      DC_HIP(hipStreamSynchronize(st));
+      if (nb[1] > 0.0) tol_r = tol[r] * std::sqrt(nb[0] / nb[1]);
+      bb = be.as<z64>();
+      xx = xe.as<z64>();
+    }
     double rel = 0.0;
     if (o.prec == P64) {
       Krylov<double> K(op, var, o, var.ws, var.sm, o.m, st);
-      K.solve(bb, xx, tol[r], use_x0 != 0, o.max_cycles, s, rel);
+      K.solve(bb, xx, tol_r, use_x0 != 0, o.max_cycles, s, rel);
     } else if (!o.outer) {
       Krylov<float> K(op, var, o, var.ws, var.sm, o.m, st);
       op.t32a.ensure(N * sizeof(z32));
@@ -994,7 +1143,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       z32* x32 = op.t32b.as<z32>();
       launch_convert_64to32(bb, b32, N, op.n, 0, st);
       if (use_x0) launch_convert_64to32(xx, x32, N, op.n, 0, st);
-      K.solve(b32, x32, tol[r], use_x0 != 0, o.max_cycles, s, rel);
+      K.solve(b32, x32, tol_r, use_x0 != 0, o.max_cycles, s, rel);
       launch_convert_32to64(x32, xx, N, op.n, 0, st);
     } else {
       // FP64 flexible GMRES outer loop; its preconditioner is the
@@ -1003,7 +1152,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       oo.k = 0;
       oo.d = 0;
       oo.m = o.m_outer;
-      Variant& vo = op.variant(P64, sign, 0, -1);  // holds the outer workspace
+      Variant& vo = op.variant(P64, sign, 0, -1, o.schur);  // holds the outer workspace
       Krylov<double> KO(op, vo, oo, vo.ws, vo.sm, o.m_outer, st);
       op.zouter.ensure(size_t(o.m_outer) * N * sizeof(z64));
       z64* Zb = op.zouter.as<z64>();
@@ -1018,7 +1167,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       while (bn > 0.0) {
         const double rn = KO.true_resid(xx, bb, KO.rtrue);
         rel = rn / bn;
-        if (rel <= tol[r] || outer_done >= o.max_outer) break;
+        if (rel <= tol_r || outer_done >= o.max_outer) break;
         launch_scale(P64, KO.rtrue, KO.V(0), N, nullptr, 1.0 / rn, nullptr, st);
         launch_arnoldi_init(KO.ad, rn, st);
         int jd = 0;
@@ -1028,7 +1177,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
           KI.solve(b32, x32, o.inner_tol, false, o.max_cycles, s, irel);
           launch_convert_32to64(x32, Zb + size_t(j) * N, N, op.n, 0, st);
           KO.A(Zb + size_t(j) * N, KO.V(j + 1), nullptr);
-          KO.orth_step(j, 0, o.m_outer, tol[r] * bn);
+          KO.orth_step(j, 0, o.m_outer, tol_r * bn);
           ++outer_done;
           int flags[3];
           DC_HIP(hipMemcpyAsync(flags, KO.ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1054,6 +1203,18 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       }
       s.outer_iters = outer_done;
       s.matvecs += int(KO.matvecs);
+    }
+    if (o.schur) {
+      const auto* par = static_cast<const unsigned char*>(op.par.p);
+      launch_apply_oddeven(P64, 1, op.n, op.V, op.blocks(P64), nullptr, xe.p, nullptr,
+                           op.gbuf_s(P64), op.nbr.as<int>(), par, tm, nullptr, st);
+      launch_gather_store(P64, op.n, half, op.gbuf_s(P64), to.p, nullptr, st);   // D_oe x_e
+      launch_scale(P64, to.p, to.p, N, nullptr, -1.0, nullptr, st);
+      launch_axpy(P64, mk(1.0, 0.0), bo.p, to.p, N, st);                          // b_o - D_oe x_e
+      launch_bj_rows(P64, op.n, half, osite, oinv, nullptr, to.p, 0, bo.p, nullptr, st);
+      launch_oddeven_split(P64, op.n, half, esite, osite, xfull, xe.p, bo.p, 1, st);
+      DC_HIP(hipStreamSynchronize(st));   // the scratch vectors are freed at scope end
+      xx = xfull;
     }
     if (adjoint) launch_gamma5(P64, xx, xr, op.V, op.n, st);
     (void)rel;
@@ -1461,6 +1622,7 @@ static int solve_groups(const std::vector<Op*>& ops, const SolveOpts& o, int adj
   const size_t G = ops.size();
   if (G == 0) return 0;
   if (o.m < 1 || o.max_cycles < 0) throw InvalidArg("bad solver options");
+  if (o.schur) throw InvalidArg("the batched solve works on the full lattice (schur = 0)");
   for (size_t gi = 0; gi < G; ++gi) {
     if (!ops[gi]) throw InvalidArg("null operator handle");
     check_prec(*ops[gi], o.prec);
@@ -1692,8 +1854,8 @@ int op_solve_multi(const std::vector<Op*>& ops, const SolveOpts& o, int adjoint,
 
 int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st) {
   const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
-  Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d);
-  const size_t N = op.N();
+  Variant& var = op.variant(o.prec, sign, o.block_jacobi ? 1 : 0, o.d, o.schur);
+  const size_t N = o.schur ? op.N() / 2 : op.N();
   // only a space built for this k fits the caller's [k][V][n] arrays
   if (var.kcur == 0 || var.k_built != o.k || var.recycle_version != op.version) return 0;
   if (var.prec == P64) {

@@ -37,6 +37,7 @@ struct SolveOpts {
   Prec prec = P64;
   int outer = 0, m_outer = 10, max_outer = 50;
   double inner_tol = 1e-4;
+  int schur = 0;   // solve the odd-even reduced system (Sec. 2.2)
   uint64_t seed = 0;
   const void* v0 = nullptr;  // device complex128 [V][n]
 };
@@ -54,6 +55,7 @@ struct Variant {
   int sign;        // +1: D(mu); -1: D(-mu) (adjoint through Gamma5)
   int bj;
   int d;
+  int schur = 0;   // works on the odd-even reduced operator (compressed even vectors)
   // polynomial
   std::vector<cd> theta;
   long poly_version = -1;
@@ -113,6 +115,13 @@ struct Op {
   } bj[2];
   const BJ& ensure_bj(int sign, hipStream_t st);
   DevBuf gbuf64, gbuf32;
+  // odd-even reduction: site parity, compressed row -> site maps, the reduced
+  // apply's gbuf [V/2][9][n] and odd-site temporary, per vector precision
+  bool oddeven = false;              // every extent even
+  DevBuf par, esite, osite;
+  DevBuf gbs64, gbs32, ts64, ts32;
+  void* gbuf_s(Prec p);
+  void* tmp_s(Prec p);
   DevBuf redpart;           // reducer scratch
   DevBuf scal;              // a few device doubles
   DevBuf t64a, t64b, t32a, t32b, zouter;  // per-solve vector scratch, kept across calls
@@ -122,9 +131,9 @@ struct Op {
   ApplyProfile prof;
   CycleSignal sig;
   Reducer red() const { return Reducer{redpart.as<double>()}; }
-  std::map<std::tuple<int, int, int, int>, std::unique_ptr<Variant>> variants;
+  std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Variant>> variants;
   size_t N() const { return size_t(V) * n; }
-  Variant& variant(Prec p, int sign, int bj, int d);
+  Variant& variant(Prec p, int sign, int bj, int d, int schur = 0);
   const void* blocks(Prec p) const;
   const float* scales(Prec p) const { return p == P16S ? sc16.as<float>() : nullptr; }
   void* gbuf(Prec p) const { return p == P64 ? gbuf64.p : gbuf32.p; }
@@ -138,6 +147,7 @@ void op_update(Op& op, const void* self_blocks, const void* hop_blocks, bool on_
 // Precision-level entry points used by the C ABI.
 void op_apply(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_t st);
 void op_apply_bj(Op& op, const void* in, void* out, hipStream_t st);
+void op_apply_reduced(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_t st);
 void op_apply_multi(Op& op, Prec p, int adjoint, int R, const void* in, void* out, hipStream_t st);
 int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta);
 void op_poly_apply(Op& op, const SolveOpts& o, const void* in, void* out, hipStream_t st);

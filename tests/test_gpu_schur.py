@@ -1,0 +1,109 @@
+"""Odd-even reduced system (Sec. 2.2) on the GPU against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import operator as dop
+from oracle import schur
+from oracle.krylov import arnoldi as o_arnoldi
+
+from .helpers import log, make_pair, oracle_relres, rand_vec, rel, workload_pair
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("dims,ntv,mu", [((2, 2, 2, 2), 4, 0.0), ((4, 2, 2, 4), 6, 0.2),
+                                         ((4, 4, 4, 4), 24, 0.0)])
+def test_reduced_apply_matches_oracle(dims, ntv, mu):
+    log("reduced apply", dims, ntv, mu)
+    gop, oop = make_pair(dims, ntv, 2.8, mu=mu, store=("f64", "f32", "f16s"))
+    ne = oop.V // 2
+    x = rand_vec(ne, oop.n, 70, 0)
+    ref = schur.apply(oop, x.numpy())
+    y = gop.apply_reduced(x.cuda()).cpu().numpy()
+    assert rel(y, ref) <= 1e-13
+    # adjoint: <S^H z, x> = <z, S x>
+    z = rand_vec(ne, oop.n, 71, 0)
+    yh = gop.apply_reduced(z.cuda(), adjoint=True).cpu().numpy()
+    lhs = np.vdot(yh.reshape(-1), x.numpy().reshape(-1))
+    rhs = np.vdot(z.numpy().reshape(-1), ref.reshape(-1))
+    assert abs(lhs - rhs) <= 1e-12 * abs(rhs)
+    x32 = x.to(torch.complex64).cuda()
+    y32 = gop.apply_reduced(x32, prec="f32").cpu().numpy()
+    assert rel(y32, ref) <= 1e-5
+    y16 = gop.apply_reduced(x32, prec="f16s").cpu().numpy()
+    assert rel(y16, ref) <= 5e-3          # FP16 blocks and inverse blocks, 2^-11 per entry
+
+
+def test_reduced_arnoldi_matches_oracle():
+    from paper_2205_09104_amd import Opts
+    log("reduced arnoldi")
+    gop, oop = make_pair((4, 2, 2, 2), 4, 3.0, mu=0.1)
+    ne = oop.V // 2
+    v = rand_vec(ne, oop.n, 72, 0)
+    H, s = gop.arnoldi(v.cuda(), 12, Opts(m=12, schur=1))
+    f = lambda u: schur.apply(oop, u.reshape(ne, oop.n)).reshape(-1)
+    ref = o_arnoldi(f, v.numpy().reshape(-1), 12, "mgs")
+    assert s == 12
+    assert np.abs(H - ref.Hbar).max() <= 1e-10 * np.abs(ref.Hbar).max()
+
+
+@pytest.fixture(scope="module")
+def c1():
+    gop, oop, w = workload_pair("c1", store=("f64", "f32", "f16s"))
+    b = synth.rhs(w.dims, w.n_tv, 0)
+    xref = np.linalg.solve(dop.dense(oop), b.numpy().reshape(-1)).reshape(oop.V, oop.n)
+    return gop, oop, w, b, xref
+
+
+@pytest.mark.parametrize("cfg", ["gmres", "poly", "gcrodr", "f32", "f16s"])
+def test_reduced_solves(c1, cfg):
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, b, xref = c1
+    log("reduced solve", cfg)
+    opts = {"gmres": Opts(m=30, schur=1),
+            "poly": Opts(m=20, d=4, seed=1, schur=1),
+            "gcrodr": Opts(m=28, k=8, d=4, seed=1, schur=1),
+            "f32": Opts(m=20, d=4, prec="f32", outer=1, inner_tol=1e-3, seed=1, schur=1),
+            "f16s": Opts(m=20, d=4, prec="f16s", outer=1, inner_tol=1e-3, seed=1, schur=1)}[cfg]
+    for rep in range(2):       # second solve reuses polynomial and recycle space
+        x, st, rc = gop.solve(b.cuda(), 1e-10, opts)
+        assert rc == 0 and st[0]["rel_res_true"] <= 1e-10, st
+        xh = x.cpu().numpy()
+        assert oracle_relres(oop, xh, b.numpy()) <= 1e-10
+        assert rel(xh, xref) <= 1e-6
+    if cfg == "gmres":
+        # the reduced system needs fewer iterations than the full one
+        _, sf, _ = gop.solve(b.cuda(), 1e-10, Opts(m=30))
+        log(f"  iterations: reduced {st[0]['iters']}, full {sf[0]['iters']}")
+        assert st[0]["iters"] < sf[0]["iters"]
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.07])
+def test_reduced_adjoint_solve(mu):
+    from paper_2205_09104_amd import Opts
+    log("reduced adjoint", mu)
+    gop, oop = make_pair((4, 2, 2, 2), 4, 3.2, mu=mu)
+    b = rand_vec(oop.V, oop.n, 73, 0)
+    x, st, rc = gop.solve(b.cuda(), 1e-11, Opts(m=20, d=4, seed=2, schur=1), adjoint=True)
+    assert rc == 0
+    assert oracle_relres(oop, x.cpu().numpy(), b.numpy(), adjoint=True) <= 1e-11
+
+
+def test_reduced_rejects_bad_input():
+    from paper_2205_09104_amd import Opts
+    from paper_2205_09104_amd._lib import DcError
+    log("reduced errors")
+    gop, oop = make_pair((3, 2, 2, 2), 2, 3.0)
+    b = rand_vec(oop.V, oop.n, 74, 0).cuda()
+    with pytest.raises(DcError):
+        gop.solve(b, 1e-8, Opts(m=10, schur=1))          # odd extent
+    with pytest.raises(DcError):
+        gop.apply_reduced(torch.zeros(oop.V // 2, oop.n, dtype=torch.complex128, device="cuda"))
+    gop2, oop2 = make_pair((2, 2, 2, 2), 2, 3.0)
+    b2 = rand_vec(oop2.V, oop2.n, 75, 0).cuda()
+    with pytest.raises(DcError):
+        gop2.solve(b2, 1e-8, Opts(m=10, schur=1, block_jacobi=1))
+    with pytest.raises(DcError):
+        gop2.solve_batch(b2[None], 1e-8, Opts(m=10, schur=1))
