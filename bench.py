@@ -37,8 +37,12 @@ def parse():
     p.add_argument("--workload", default="c2")
     p.add_argument("--tol", type=float, default=1e-8)
     p.add_argument("--inner", default="f16s", choices=["f32", "f16s"])
-    p.add_argument("--d", type=int, default=24)
-    p.add_argument("--k", type=int, default=32)
+    p.add_argument("--d", type=int, default=16)
+    p.add_argument("--k", type=int, default=64)
+    p.add_argument("--schur", type=int, default=1, choices=[0, 1],
+                   help="solve the odd-even reduced system (1) or the full lattice (0)")
+    p.add_argument("--full-steps", type=int, default=4,
+                   help="timed solves of the same method on the full lattice, for comparison")
     p.add_argument("--m", type=int, default=30, help="new Arnoldi vectors per cycle")
     p.add_argument("--inner-tol", type=float, default=1e-1)
     p.add_argument("--plain-steps", type=int, default=1)
@@ -90,7 +94,7 @@ def stage1_bytes(V, n, prec):
 # bytes to counter reading for a plain 1 GiB elementwise copy (--copy-probe
 # 1024: FETCH_SIZE 524300 KiB for 1 GiB read, WRITE_SIZE 1048576 KiB for 1 GiB
 # written).  Valid only for the apply source it was taken on.
-TRAFFIC = {"workload": "c2", "prec": "f16s",
+TRAFFIC = {"workload": "c2", "prec": "f16s", "kernel": 0,
            "fetch_kib": 94006.06, "fetch_scale": 1048576.0 / 524300.0,
            "write_kib": 13824.0, "write_scale": 1048576.0 / 1048576.0,
            "apply_source_sha256": "4ad78bf68862fbf112a58afb3ce8cb7b738d2824c562da0e9a33f8c64732a804"}
@@ -106,9 +110,21 @@ def apply_source_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def measured_traffic(workload, prec):
+def reduced_eo_bytes(V, n, prec):
+    """Algorithmic bytes of the odd-even reduction's D_eo stage kernel: all
+    4V hop blocks and the V/2 even self blocks (and scales), one read of t_o
+    and one of x_e (compressed half-lattice vectors)."""
+    sb = {"f64": 16, "f32": 8, "f16s": 4}[prec]
+    sv = 16 if prec == "f64" else 8
+    nblk = 4 * V + V // 2
+    extra = nblk * 4 if prec == "f16s" else 0
+    return nblk * n * n * sb + extra + 2 * (V // 2) * n * sv
+
+
+def measured_traffic(workload, prec, kernel):
     t = TRAFFIC
-    if workload != t["workload"] or prec != t["prec"] or apply_source_digest() != t["apply_source_sha256"]:
+    if (workload != t["workload"] or prec != t["prec"] or kernel != t["kernel"]
+            or apply_source_digest() != t["apply_source_sha256"]):
         return None, None
     fetch = t["fetch_kib"] * 1024 * t["fetch_scale"]
     write = t["write_kib"] * 1024 * t["write_scale"]
@@ -149,8 +165,12 @@ def main():
     # HIP events on one in a.profile_every launches of the apply's block kernel
     op.profile_apply(a.profile_every)
 
-    def prof_totals():
-        return {p: (op.profile_apply_read(p), op.profile_apply_read(p, include_noops=True))
+    kern = 2 if a.schur else 0     # the roofline kernel: D_eo stage, or the full block kernel
+
+    def prof_totals(kernel=None):
+        kk = kern if kernel is None else kernel
+        return {p: (op.profile_apply_read(p, kernel=kk),
+                    op.profile_apply_read(p, include_noops=True, kernel=kk))
                 for p in ("f64", "f32", "f16s")}
 
     # ------------------------------------------------ back-to-back apply rates
@@ -204,7 +224,7 @@ def main():
 
     # ------------------------------------------------ method solve (timed)
     opts = Opts(m=a.m + a.k, k=a.k, d=a.d, u=10, prec=a.inner, outer=1, m_outer=10,
-                max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000)
+                max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000, schur=a.schur)
 
     def one_solve(r, o):
         b = synth.rhs(w.dims, w.n_tv, r, device="cuda")
@@ -237,6 +257,22 @@ def main():
             f"{st['t_solve_ms']:.0f} ms")
     ok = all(s["status"] == 0 and s["rel_res_true"] <= a.tol for s in stats)
     value = a.steps / dt if ok else 0.0
+
+    # ------------------------------------------------ same method, full lattice
+    full_cmp = None
+    if a.schur and a.full_steps > 0:
+        fo = Opts(m=a.m + a.k, k=a.k, d=a.d, u=10, prec=a.inner, outer=1, m_outer=10,
+                  max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000, schur=0)
+        one_solve(0, fo)                       # setup: polynomial and recycle space
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fst = [one_solve(r, fo)[1] for r in range(a.warmup, a.warmup + a.full_steps)]
+        torch.cuda.synchronize()
+        fdt = time.perf_counter() - t1
+        full_cmp = {"solves_per_s": a.full_steps / fdt, "steps": a.full_steps,
+                    "matvecs_per_solve": [s["matvecs"] for s in fst],
+                    "converged": all(s["status"] == 0 for s in fst)}
+        log(f"same method on the full lattice: {a.full_steps / fdt:.2f} solves/s")
 
     # ------------------------------------------------ FP64 comparisons (one RHS each)
     # GMRES(30) plain, with the polynomial preconditioner (d = 4, 8, 16), and
@@ -287,9 +323,11 @@ def main():
     inner = a.inner
     launches, tot_ms = prof[inner]
     avg_us = 1e3 * tot_ms / max(launches, 1)
-    s1b = stage1_bytes(V, n, inner)
+    s1b = reduced_eo_bytes(V, n, inner) if a.schur else stage1_bytes(V, n, inner)
     achieved = s1b / (avg_us * 1e-6) / 1e9 if launches else None
-    traffic, traffic_detail = measured_traffic(w.name, inner)
+    traffic, traffic_detail = measured_traffic(w.name, inner, kern)
+    kname = (f"k_apply_oddeven<.., {inner}, mode 2> (D_eo stage of the odd-even reduction)"
+             if a.schur else f"k_apply_blocks ({inner} blocks)")
     line = {
         "metric": METRIC,
         "value": value,
@@ -305,8 +343,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {'x'.join(map(str, w.dims))} lattice, N_tv={w.n_tv} "
                                f"({w.N} unknowns), mu={w.mu}, m0={w.m0():.6f}",
-                   "solver": f"FGMRES(10) fp64 outer; inner {inner} GCRO-DR(m={a.m + a.k},k={a.k}) "
-                             f"+ poly d={a.d}, inner_tol={a.inner_tol}",
+                   "solver": f"{'odd-even reduced system; ' if a.schur else ''}FGMRES(10) fp64 "
+                             f"outer; inner {inner} GCRO-DR(m={a.m + a.k},k={a.k}) + poly "
+                             f"d={a.d}, inner_tol={a.inner_tol}",
                    "tol": a.tol, "parallelism": "single GPU"},
         "setup_ms": setup_ms,
         "iters_per_solve": [s["iters"] for s in stats],
@@ -314,13 +353,14 @@ def main():
         "rel_res_true": [s["rel_res_true"] for s in stats],
         "err_vs_fp64_last_solve": err_vs_fp64,
         "plain_fp64_gmres30": plain,
+        "same_method_full_lattice": full_cmp,
         "fp64_comparison": comp,
         "apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]} for p, r in rates.items()},
         "multi_rhs_apply": multi,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
                      "traffic_detail": traffic_detail,
-                     "kernel": f"k_apply_blocks ({inner} blocks), timed in the solves",
+                     "kernel": f"{kname}, timed in the solves",
                      "traffic_GBs": (traffic / (avg_us * 1e-6) / 1e9) if (traffic and launches) else None,
                      "timed_launches": launches, "sampling": f"1 in {a.profile_every}",
                      "avg_us": avg_us, "bytes_per_launch": s1b,

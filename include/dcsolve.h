@@ -275,21 +275,24 @@ int dc_export_recycle(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint,
 
 /* Timing of the D_c apply's block kernel (diagnostics, not part of the
  * method).  every >= 1 clears the totals and has one in `every` later
- * dispatches of the block kernel (the stage that streams the stored blocks)
- * record a start and an end HIP event on its launch stream (events passed to
+ * dispatches of the block kernels (the stages that stream the stored blocks,
+ * full lattice or odd-even reduction) record a start and an end HIP event on
+ * their launch stream (events passed to
  * hipExtLaunchKernel); every = 0 stops recording; every < 0 is
  * DC_ERR_INVALID.  Launches that a finished Arnoldi cycle turned into no-ops
  * are counted separately. */
 int dc_profile_apply(dc_op_t op, int32_t every);
 
-/* Totals since the last dc_profile_apply(op, 1) for the blocks used in
- * precision prec (DC_PREC_F64 / DC_PREC_F32 / DC_PREC_F16S): *launches =
- * launches that did work, *total_ms = their summed event-to-event duration;
- * *launches_all, *total_ms_all = the same over every recorded launch, no-op
- * launches of finished cycles included (what a kernel tracer sees).  Any
- * output pointer may be NULL.  Waits for the recorded events to complete. */
-int dc_profile_apply_read(dc_op_t op, int32_t prec, int64_t* launches, double* total_ms,
-                          int64_t* launches_all, double* total_ms_all);
+/* Totals since the last dc_profile_apply for the blocks used in precision
+ * prec (DC_PREC_F64 / DC_PREC_F32 / DC_PREC_F16S) and kernel 0 (the full
+ * lattice's block kernel), 1 (the odd-even reduction's D_oe stage) or 2 (its
+ * D_eo stage): *launches = launches that did work, *total_ms = their summed
+ * event-to-event duration; *launches_all, *total_ms_all = the same over every
+ * recorded launch, no-op launches of finished cycles included (what a kernel
+ * tracer sees).  Any output pointer may be NULL.  Waits for the recorded events
+ * to complete. */
+int dc_profile_apply_read(dc_op_t op, int32_t prec, int32_t kernel, int64_t* launches,
+                          double* total_ms, int64_t* launches_all, double* total_ms_all);
 
 /* Right-hand-side tile (right-hand sides per workgroup: 16, 32 or 64) of the
  * multi-right-hand-side apply.  The first launch of a shape class (block size

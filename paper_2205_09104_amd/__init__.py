@@ -262,13 +262,14 @@ class CoarseOp:
         launches of the apply's block kernel; every = 0 (or False) stops."""
         check(load().dc_profile_apply(self._h, int(every)))
 
-    def profile_apply_read(self, prec: str, include_noops: bool = False):
-        """(launches, total ms) of the block kernel in precision prec since
-        the last profile_apply(True): launches that did work, or with
+    def profile_apply_read(self, prec: str, include_noops: bool = False, kernel: int = 0):
+        """(launches, total ms) of a block kernel in precision prec since the
+        last profile_apply: kernel 0 the full lattice's, 1 / 2 the odd-even
+        reduction's D_oe / D_eo stage; launches that did work, or with
         include_noops every launch (no-op launches of finished cycles too)."""
         n, ms, na, msa = C.c_int64(), C.c_double(), C.c_int64(), C.c_double()
-        check(load().dc_profile_apply_read(self._h, PREC[prec], C.byref(n), C.byref(ms),
-                                           C.byref(na), C.byref(msa)))
+        check(load().dc_profile_apply_read(self._h, PREC[prec], int(kernel), C.byref(n),
+                                           C.byref(ms), C.byref(na), C.byref(msa)))
         return (na.value, msa.value) if include_noops else (n.value, ms.value)
 
     def export_recycle(self, opts: Opts, adjoint=False, stream=None):

@@ -88,7 +88,7 @@ SIGNATURES = {
     "dc_multi_tile": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "dc_set_multi_tile_mode": (C.c_int, [C.c_int32]),
     "dc_profile_apply": (C.c_int, [C.c_void_p, C.c_int32]),
-    "dc_profile_apply_read": (C.c_int, [C.c_void_p, C.c_int32, C.POINTER(C.c_int64),
+    "dc_profile_apply_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double)]),
     "dc_last_error": (C.c_char_p, []),

@@ -370,14 +370,14 @@ int dc_profile_apply(dc_op_t op, int32_t every) {
   });
 }
 
-int dc_profile_apply_read(dc_op_t op, int32_t prec, int64_t* launches, double* total_ms,
-                          int64_t* launches_all, double* total_ms_all) {
+int dc_profile_apply_read(dc_op_t op, int32_t prec, int32_t kernel, int64_t* launches,
+                          double* total_ms, int64_t* launches_all, double* total_ms_all) {
   return guarded([&] {
     if (!op) throw dc::InvalidArg("null handle");
     if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
     long n = 0, na = 0;
     double ms = 0.0, msa = 0.0;
-    dc::op_profile_read(op->op, dc::Prec(prec), &n, &ms, &na, &msa);
+    dc::op_profile_read(op->op, dc::Prec(prec), kernel, &n, &ms, &na, &msa);
     if (launches) *launches = n;
     if (total_ms) *total_ms = ms;
     if (launches_all) *launches_all = na;

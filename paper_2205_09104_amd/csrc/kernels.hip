@@ -1785,7 +1785,7 @@ void launch_bj_rows(Prec p, int n, int rows, const int* rowsite, const void* inv
 template <int P, int MODE>
 static void oddeven_T(int n, int V, const void* blocks, const float* scales, const void* x_e,
                       const void* t_o, void* gbuf, const int* nbr, const unsigned char* par,
-                      double tm, const int* done, hipStream_t st) {
+                      double tm, const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
   using VR = typename VecOf<P>::R;
   const int chunk = (5 * V + 7) / 8;
   const dim3 grid(unsigned(chunk) * 8u), block(64);
@@ -1797,11 +1797,13 @@ static void oddeven_T(int n, int V, const void* blocks, const float* scales, con
 #define DC_CASE(TV)                                                                            \
   case TV:                                                                                     \
     if (full)                                                                                  \
-      hipLaunchKernelGGL((k_apply_oddeven<TV, P, true, MODE>), grid, block, 0, st, blocks,     \
-                         scales, xe, to, pg, nbr, par, V, n, chunk, tm, done);                 \
+      hipExtLaunchKernelGGL((k_apply_oddeven<TV, P, true, MODE>), grid, block, 0, st, ev0,     \
+                            ev1, 0, blocks, scales, xe, to, pg, nbr, par, V, n, chunk, tm,    \
+                            done);                                                             \
     else                                                                                       \
-      hipLaunchKernelGGL((k_apply_oddeven<TV, P, false, MODE>), grid, block, 0, st, blocks,    \
-                         scales, xe, to, pg, nbr, par, V, n, chunk, tm, done);                 \
+      hipExtLaunchKernelGGL((k_apply_oddeven<TV, P, false, MODE>), grid, block, 0, st, ev0,    \
+                            ev1, 0, blocks, scales, xe, to, pg, nbr, par, V, n, chunk, tm,    \
+                            done);                                                             \
     break;
     DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
 #undef DC_CASE
@@ -1813,16 +1815,17 @@ static void oddeven_T(int n, int V, const void* blocks, const float* scales, con
 
 void launch_apply_oddeven(Prec p, int mode, int n, int V, const void* blocks, const float* scales,
                           const void* x_e, const void* t_o, void* gbuf, const int* nbr,
-                          const unsigned char* par, double tm, const int* done, hipStream_t st) {
+                          const unsigned char* par, double tm, const int* done, hipStream_t st,
+                          hipEvent_t ev0, hipEvent_t ev1) {
   if (mode != 1 && mode != 2) throw InvalidArg("odd-even stage mode must be 1 or 2");
   if (mode == 1) {
-    if (p == P64) oddeven_T<P64, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
-    else if (p == P32) oddeven_T<P32, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
-    else oddeven_T<P16S, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
+    if (p == P64) oddeven_T<P64, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
+    else if (p == P32) oddeven_T<P32, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
+    else oddeven_T<P16S, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
   } else {
-    if (p == P64) oddeven_T<P64, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
-    else if (p == P32) oddeven_T<P32, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
-    else oddeven_T<P16S, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st);
+    if (p == P64) oddeven_T<P64, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
+    else if (p == P32) oddeven_T<P32, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
+    else oddeven_T<P16S, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
   }
 }
 

@@ -84,7 +84,8 @@ void launch_bj_rows(Prec p, int n, int rows, const int* rowsite, const void* inv
 // summed by the ordinary gathers over V/2 rows.  par: uint8 [V] site parity.
 void launch_apply_oddeven(Prec p, int mode, int n, int V, const void* blocks, const float* scales,
                           const void* x_e, const void* t_o, void* gbuf, const int* nbr,
-                          const unsigned char* par, double tm, const int* done, hipStream_t st);
+                          const unsigned char* par, double tm, const int* done, hipStream_t st,
+                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // split a full-lattice vector into its compressed even and odd halves, or merge
 // them back (dir 0: split, 1: merge); esite/osite: int32 [V/2] row -> site
 void launch_oddeven_split(Prec p, int n, int half_sites, const int* esite, const int* osite,

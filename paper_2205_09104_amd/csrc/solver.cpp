@@ -167,7 +167,7 @@ static int prec_slot(Prec p) { return p == P64 ? 0 : (p == P32 ? 1 : 2); }
 
 void ApplyProfile::reset() {
   flush();
-  for (int i = 0; i < 3; ++i) {
+  for (int i = 0; i < kSlotsP; ++i) {
     ms[i] = ms_all[i] = 0.0;
     count[i] = count_all[i] = 0;
   }
@@ -251,6 +251,21 @@ static void stage1(Op& op, Prec p, int n, int V, const void* blocks, const float
   if (a) pr.recs.push_back({a, b, prec_slot(p), done ? pr.tag : -1, false});
 }
 
+// Stage kernels of the odd-even reduction (mode 1: D_oe, 2: D_eo), timed like stage1.
+static void stage_oddeven(Op& op, Prec p, int mode, const void* x_e, const void* t_o, void* gbuf,
+                          double tm, const int* done, hipStream_t st) {
+  ApplyProfile& pr = op.prof;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (pr.on && (pr.seen++ % pr.every) == 0) {
+    if (pr.tag < 0 && pr.recs.size() >= 2048) pr.flush();
+    if (!pr.take(&a, &b)) ++pr.missed;
+  }
+  launch_apply_oddeven(p, mode, op.n, op.V, op.blocks(p), op.scales(p), x_e, t_o, gbuf,
+                       op.nbr.as<int>(), static_cast<const unsigned char*>(op.par.p), tm, done,
+                       st, a, b);
+  if (a) pr.recs.push_back({a, b, 3 * mode + prec_slot(p), done ? pr.tag : -1, false});
+}
+
 void op_profile(Op& op, int every) {
   if (every < 0) throw InvalidArg("sampling period must be >= 0");
   op.prof.reset();
@@ -259,10 +274,11 @@ void op_profile(Op& op, int every) {
   op.prof.seen = 0;
 }
 
-void op_profile_read(Op& op, Prec p, long* launches, double* total_ms, long* launches_all,
-                     double* total_ms_all) {
+void op_profile_read(Op& op, Prec p, int kernel, long* launches, double* total_ms,
+                     long* launches_all, double* total_ms_all) {
+  if (kernel < 0 || kernel > 2) throw InvalidArg("kernel must be 0, 1 or 2");
   op.prof.flush();
-  const int i = prec_slot(p);
+  const int i = 3 * kernel + prec_slot(p);
   if (launches) *launches = op.prof.count[i];
   if (total_ms) *total_ms = op.prof.ms[i];
   if (launches_all) *launches_all = op.prof.count_all[i];
@@ -504,12 +520,9 @@ struct Krylov {
              st);
       return;
     }
-    const auto* par = static_cast<const unsigned char*>(op.par.p);
-    launch_apply_oddeven(p, 1, op.n, op.V, op.blocks(p), op.scales(p), in, nullptr, gb,
-                         op.nbr.as<int>(), par, tm, done, st);
+    stage_oddeven(op, p, 1, in, nullptr, gb, tm, done, st);
     launch_bj_rows(p, op.n, rows, op.osite.as<int>(), oinv, oinvsc, gb, 1, ts, done, st);
-    launch_apply_oddeven(p, 2, op.n, op.V, op.blocks(p), op.scales(p), in, ts, gb,
-                         op.nbr.as<int>(), par, tm, done, st);
+    stage_oddeven(op, p, 2, in, ts, gb, tm, done, st);
   }
 
   // A~ in = (B^{-1}) D in (one matvec)

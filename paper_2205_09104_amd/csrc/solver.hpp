@@ -81,8 +81,11 @@ struct ApplyProfile {
   int tag = -1;                   // step of the pending cycle (-1: outside a cycle)
   std::vector<hipEvent_t> idle, owned;
   std::vector<Rec> recs;
-  double ms[3] = {0, 0, 0}, ms_all[3] = {0, 0, 0};
-  long count[3] = {0, 0, 0}, count_all[3] = {0, 0, 0};   // *_all: no-op launches included
+  // slot = kernel * 3 + precision; kernel 0: full-lattice block kernel,
+  // 1 / 2: the odd-even reduction's D_oe / D_eo stage kernels
+  static constexpr int kSlotsP = 9;
+  double ms[kSlotsP] = {}, ms_all[kSlotsP] = {};
+  long count[kSlotsP] = {}, count_all[kSlotsP] = {};   // *_all: no-op launches included
   long missed = 0;                // launches not recorded (event cap reached)
   static constexpr size_t kMaxEvents = 16384;
   void reset();
@@ -157,8 +160,8 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
              const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
 int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st);
 void op_profile(Op& op, int every);
-void op_profile_read(Op& op, Prec p, long* launches, double* total_ms, long* launches_all,
-                     double* total_ms_all);
+void op_profile_read(Op& op, Prec p, int kernel, long* launches, double* total_ms,
+                     long* launches_all, double* total_ms_all);
 int op_solve_multi(const std::vector<Op*>& ops, const SolveOpts& o, int adjoint,
                    const std::vector<int>& R, const std::vector<const void*>& b,
                    const std::vector<void*>& x, const std::vector<const double*>& tol, int use_x0,

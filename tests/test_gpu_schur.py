@@ -107,3 +107,20 @@ def test_reduced_rejects_bad_input():
         gop2.solve(b2, 1e-8, Opts(m=10, schur=1, block_jacobi=1))
     with pytest.raises(DcError):
         gop2.solve_batch(b2[None], 1e-8, Opts(m=10, schur=1))
+
+
+def test_reduced_profile_counts_stage_launches(c1):
+    """Each reduced matvec runs one D_oe and one D_eo stage launch; the
+    profiler counts exactly those that did work."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, b, xref = c1
+    log("reduced profile")
+    for o in (Opts(m=30, schur=1), Opts(m=20, d=4, seed=1, schur=1)):
+        gop.profile_apply(1)
+        _, st, rc = gop.solve(b.cuda(), 1e-10, o)
+        n1, _ = gop.profile_apply_read("f64", kernel=1)
+        n2, ms2 = gop.profile_apply_read("f64", kernel=2)
+        n0, _ = gop.profile_apply_read("f64", kernel=0)
+        assert rc == 0 and n1 == n2 == st[0]["matvecs"] and ms2 > 0.0
+        assert n0 == 1          # the closing FP64 residual check on the full lattice
+    gop.profile_apply(0)
