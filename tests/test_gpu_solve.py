@@ -312,6 +312,7 @@ def test_apply_profile_counts_executed_launches(c1):
     assert n64 == 7 and ms64 > 0.0
     assert gop.profile_apply_read("f32") == (0, 0.0)
     for o in (Opts(m=30), Opts(m=20, d=4, seed=1), Opts(m=24, k=8, d=4, seed=1)):
+        gop.solve(x, 1e-10, o)            # builds the polynomial (its applies are not matvecs)
         gop.profile_apply(True)
         _, st, rc = gop.solve(x, 1e-10, o)
         n, ms = gop.profile_apply_read("f64")
