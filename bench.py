@@ -88,16 +88,18 @@ def stage1_bytes(V, n, prec):
     return V * (5 * n * n * sb + n * sv + extra)
 
 
-# HBM traffic of one launch of the f16s block kernel on the 8^4, N_tv = 24
-# workload: rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch,
-# median over the launches that did work), each scaled by the ratio of true
-# bytes to counter reading for a plain 1 GiB elementwise copy (--copy-probe
-# 1024: FETCH_SIZE 524300 KiB for 1 GiB read, WRITE_SIZE 1048576 KiB for 1 GiB
-# written).  Valid only for the apply source it was taken on.
-TRAFFIC = {"workload": "c2", "prec": "f16s", "kernel": 0,
-           "fetch_kib": 94006.06, "fetch_scale": 1048576.0 / 524300.0,
-           "write_kib": 13824.0, "write_scale": 1048576.0 / 1048576.0,
-           "apply_source_sha256": "4ad78bf68862fbf112a58afb3ce8cb7b738d2824c562da0e9a33f8c64732a804"}
+# HBM traffic of one launch of the roofline kernel on the 8^4, N_tv = 24
+# workload with FP16 blocks (kernel 2: the D_eo stage of the odd-even
+# reduction): rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per
+# dispatch, median over the launches that did work), each scaled by the ratio
+# of true bytes to counter reading for a plain 1 GiB elementwise copy
+# (--copy-probe 1024: FETCH_SIZE 524300 KiB for 1 GiB read, WRITE_SIZE
+# 1048576 KiB for 1 GiB written).  Valid only for the apply source it was
+# taken on.
+TRAFFIC = {"workload": "c2", "prec": "f16s", "kernel": 2,
+           "fetch_kib": 84372.6875, "fetch_scale": 1048576.0 / 524300.0,
+           "write_kib": 6917.59375, "write_scale": 1048576.0 / 1048576.0,
+           "apply_source_sha256": "aa845142f41ba2aee930494f67d760c3736beb9094fd475796ce9ae50fa77352"}
 
 
 def apply_source_digest():
