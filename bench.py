@@ -9,8 +9,9 @@ values) + GCRO-DR deflation/recycling (k vectors), reduced-precision inner
 solve inside an FP64 flexible-GMRES outer loop; the FP64 true residual of
 every solve is checked.  Plain FP64 GMRES(30) is run on the same operator and
 right-hand sides for comparison (capped: on this operator it can stagnate).
-The roofline entry is the apply's block kernel timed live in the timed solves
-with HIP events on the library's launch stream.
+The roofline entry is the kernel that streams the stored blocks in the method's
+applies (on the odd-even reduced system, the A_e - D_eo kernel), timed live in
+the timed solves with HIP events on the library's launch stream.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 """
@@ -112,15 +113,26 @@ def apply_source_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def reduced_eo_bytes(V, n, prec):
-    """Algorithmic bytes of the odd-even reduction's D_eo stage kernel: all
-    4V hop blocks and the V/2 even self blocks (and scales), one read of t_o
-    and one of x_e (compressed half-lattice vectors)."""
+def reduced_block_bytes(V, n, prec):
+    """Block bytes of one launch of either kernel of the reduced operator: per
+    row (V/2 of them) nine blocks and their FP16 scales -- the A_o^{-1} D_oe
+    kernel reads the 8 hop blocks of an odd site and its self-block inverse,
+    the A_e - D_eo kernel the 8 hop blocks of an even site and its self block."""
     sb = {"f64": 16, "f32": 8, "f16s": 4}[prec]
-    sv = 16 if prec == "f64" else 8
-    nblk = 4 * V + V // 2
-    extra = nblk * 4 if prec == "f16s" else 0
-    return nblk * n * n * sb + extra + 2 * (V // 2) * n * sv
+    extra = 9 * 4 if prec == "f16s" else 0
+    return (V // 2) * (9 * n * n * sb + extra)
+
+
+def reduced_vec_bytes(V, n, prec):
+    """Bytes of one vector pass over the V/2 rows of a compressed vector."""
+    return (V // 2) * n * (16 if prec == "f64" else 8)
+
+
+def reduced_apply_bytes(V, n, prec):
+    """Algorithmic bytes of one apply of the reduced operator: both kernels'
+    blocks, one read of the input and one write of the output (the odd-row
+    temporary between the kernels is this design's)."""
+    return 2 * reduced_block_bytes(V, n, prec) + 2 * reduced_vec_bytes(V, n, prec)
 
 
 def measured_traffic(workload, prec, kernel):
@@ -197,6 +209,30 @@ def main():
     for p, (ms, gbs) in rates.items():
         log(f"apply {p} (both stages, back to back): {ms * 1e3:.1f} us, {gbs:.0f} GB/s algorithmic")
 
+    def reduced_rate(prec):
+        x = synth.rhs(w.dims, w.n_tv, 998, device="cuda")[: V // 2]
+        x = x if prec == "f64" else x.to(torch.complex64)
+        out = torch.empty_like(x)
+        for _ in range(3):
+            op.apply_reduced(x, prec=prec, out=out)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(a.apply_reps):
+            op.apply_reduced(x, prec=prec, out=out)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / a.apply_reps
+        return ms, reduced_apply_bytes(V, n, prec) / (ms * 1e-3) / 1e9
+
+    rrates = {}
+    if a.schur:
+        rrates = {p: reduced_rate(p) for p in ("f64", "f32", "f16s")}
+        for p, (ms, gbs) in rrates.items():
+            log(f"reduced apply {p} (both kernels, back to back): {ms * 1e3:.1f} us, "
+                f"{gbs:.0f} GB/s algorithmic")
+
     # ------------------------------------------------ multi-RHS (MFMA) apply
     multi = {}
     if a.multi_rhs > 0:
@@ -242,6 +278,9 @@ def main():
     rhs = [synth.rhs(w.dims, w.n_tv, r, device="cuda") for r in range(a.warmup, a.warmup + a.steps)]
     torch.cuda.synchronize()
     pre = prof_totals()
+    pre_oe = prof_totals(1)
+    pre_pass = {p: (op.profile_apply_passes(p, kern), op.profile_apply_passes(p, 1))
+                for p in ("f64", "f32", "f16s")}
     t0 = time.perf_counter()
     stats = []
     for b in rhs:
@@ -251,8 +290,14 @@ def main():
     dt = time.perf_counter() - t0
     x_last = x
     post = prof_totals()
-    # timed-region block-kernel launches that did work: (count, ms) per precision
+    post_oe = prof_totals(1)
+    # timed-region block-kernel launches that did work: (count, ms) per
+    # precision, and their vector passes
     prof = {p: (post[p][0][0] - pre[p][0][0], post[p][0][1] - pre[p][0][1]) for p in post}
+    prof_oe = {p: (post_oe[p][0][0] - pre_oe[p][0][0], post_oe[p][0][1] - pre_oe[p][0][1])
+               for p in post_oe}
+    passes = {p: op.profile_apply_passes(p, kern) - pre_pass[p][0] for p in pre_pass}
+    passes_oe = {p: op.profile_apply_passes(p, 1) - pre_pass[p][1] for p in pre_pass}
     for i, st in enumerate(stats):
         log(f"timed solve {i}: status {st['status']} relres {st['rel_res_true']:.2e} "
             f"iters {st['iters']} matvecs {st['matvecs']} outer {st['outer_iters']} "
@@ -325,11 +370,26 @@ def main():
     inner = a.inner
     launches, tot_ms = prof[inner]
     avg_us = 1e3 * tot_ms / max(launches, 1)
-    s1b = reduced_eo_bytes(V, n, inner) if a.schur else stage1_bytes(V, n, inner)
+    if a.schur:
+        # per launch: the nine blocks per row, plus the vector passes of its
+        # epilogue (2 to 5; summed over the timed launches by the library)
+        s1b = (launches * reduced_block_bytes(V, n, inner) +
+               passes[inner] * reduced_vec_bytes(V, n, inner)) / max(launches, 1)
+    else:
+        s1b = stage1_bytes(V, n, inner)
     achieved = s1b / (avg_us * 1e-6) / 1e9 if launches else None
     traffic, traffic_detail = measured_traffic(w.name, inner, kern)
-    kname = (f"k_apply_oddeven<.., {inner}, mode 2> (D_eo stage of the odd-even reduction)"
+    kname = (f"k_reduced_eo ({inner} blocks; A_e x_e - D_eo t_o with the chain epilogue)"
              if a.schur else f"k_apply_blocks ({inner} blocks)")
+    oe = None
+    if a.schur:
+        l1, m1 = prof_oe[inner]
+        if l1:
+            b1 = (l1 * reduced_block_bytes(V, n, inner) +
+                  passes_oe[inner] * reduced_vec_bytes(V, n, inner)) / l1
+            oe = {"kernel": f"k_reduced_oe ({inner} blocks; t_o = A_o^-1 D_oe x_e)",
+                  "timed_launches": l1, "avg_us": 1e3 * m1 / l1, "bytes_per_launch": b1,
+                  "GB/s": b1 / (1e-3 * m1 / l1) / 1e9}
     line = {
         "metric": METRIC,
         "value": value,
@@ -358,6 +418,8 @@ def main():
         "same_method_full_lattice": full_cmp,
         "fp64_comparison": comp,
         "apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]} for p, r in rates.items()},
+        "reduced_apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]}
+                                       for p, r in rrates.items()},
         "multi_rhs_apply": multi,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBS) if achieved else None, "traffic": traffic,
@@ -366,6 +428,7 @@ def main():
                      "traffic_GBs": (traffic / (avg_us * 1e-6) / 1e9) if (traffic and launches) else None,
                      "timed_launches": launches, "sampling": f"1 in {a.profile_every}",
                      "avg_us": avg_us, "bytes_per_launch": s1b,
+                     "other_reduced_kernel": oe,
                      "f64_block_kernel": {"launches": prof["f64"][0],
                                           "avg_us": 1e3 * prof["f64"][1] / max(prof["f64"][0], 1)},
                      "whole_run_all_launches": {

@@ -273,11 +273,11 @@ int dc_export_f16(dc_op_t op, uint16_t* codes, float* scales);
 int dc_export_recycle(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint,
                       void* U, void* C, int32_t* k_out, void* stream);
 
-/* Timing of the D_c apply's block kernel (diagnostics, not part of the
- * method).  every >= 1 clears the totals and has one in `every` later
- * dispatches of the block kernels (the stages that stream the stored blocks,
- * full lattice or odd-even reduction) record a start and an end HIP event on
- * their launch stream (events passed to
+/* Timing of the kernels that stream the stored blocks (diagnostics, not part
+ * of the method): the full lattice's block kernel and the two kernels of the
+ * odd-even reduced operator (Sec. 2.2).  every >= 1 clears the totals and has
+ * one in `every` later dispatches of each of these kernels record a start and
+ * an end HIP event on their launch stream (events passed to
  * hipExtLaunchKernel); every = 0 stops recording; every < 0 is
  * DC_ERR_INVALID.  Launches that a finished Arnoldi cycle turned into no-ops
  * are counted separately. */
@@ -285,14 +285,22 @@ int dc_profile_apply(dc_op_t op, int32_t every);
 
 /* Totals since the last dc_profile_apply for the blocks used in precision
  * prec (DC_PREC_F64 / DC_PREC_F32 / DC_PREC_F16S) and kernel 0 (the full
- * lattice's block kernel), 1 (the odd-even reduction's D_oe stage) or 2 (its
- * D_eo stage): *launches = launches that did work, *total_ms = their summed
+ * lattice's block kernel), 1 (the reduced operator's t_o = A_o^{-1} D_oe x_e
+ * kernel) or 2 (its A_e x_e - D_eo t_o kernel with the chain epilogue): *launches = launches that did work, *total_ms = their summed
  * event-to-event duration; *launches_all, *total_ms_all = the same over every
  * recorded launch, no-op launches of finished cycles included (what a kernel
  * tracer sees).  Any output pointer may be NULL.  Waits for the recorded events
  * to complete. */
 int dc_profile_apply_read(dc_op_t op, int32_t prec, int32_t kernel, int64_t* launches,
                           double* total_ms, int64_t* launches_all, double* total_ms_all);
+
+/* Vector passes of the launches that dc_profile_apply_read counts as having
+ * done work (same prec and kernel): per launch, the distinct vectors it reads
+ * plus the vectors it writes, each spanning the kernel's rows (V for kernel 0,
+ * V/2 for kernels 1 and 2).  Kernel 0: 1 (its input); kernel 1: 2 (x_e,
+ * t_o); kernel 2: 2-5 by epilogue.  Together with the blocks a launch streams
+ * this gives the algorithmic bytes of the timed launches.  passes may be NULL. */
+int dc_profile_apply_passes(dc_op_t op, int32_t prec, int32_t kernel, int64_t* passes);
 
 /* Right-hand-side tile (right-hand sides per workgroup: 16, 32 or 64) of the
  * multi-right-hand-side apply.  The first launch of a shape class (block size

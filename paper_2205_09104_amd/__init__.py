@@ -264,13 +264,21 @@ class CoarseOp:
 
     def profile_apply_read(self, prec: str, include_noops: bool = False, kernel: int = 0):
         """(launches, total ms) of a block kernel in precision prec since the
-        last profile_apply: kernel 0 the full lattice's, 1 / 2 the odd-even
-        reduction's D_oe / D_eo stage; launches that did work, or with
+        last profile_apply: kernel 0 the full lattice's, 1 / 2 the reduced
+        operator's A_o^{-1} D_oe / A_e - D_eo kernel; launches that did work, or with
         include_noops every launch (no-op launches of finished cycles too)."""
         n, ms, na, msa = C.c_int64(), C.c_double(), C.c_int64(), C.c_double()
         check(load().dc_profile_apply_read(self._h, PREC[prec], int(kernel), C.byref(n),
                                            C.byref(ms), C.byref(na), C.byref(msa)))
         return (na.value, msa.value) if include_noops else (n.value, ms.value)
+
+    def profile_apply_passes(self, prec: str, kernel: int = 0) -> int:
+        """Vector passes (distinct vectors read plus vectors written, each over
+        the kernel's rows) summed over the launches profile_apply_read counts
+        as having done work."""
+        v = C.c_int64()
+        check(load().dc_profile_apply_passes(self._h, PREC[prec], int(kernel), C.byref(v)))
+        return v.value
 
     def export_recycle(self, opts: Opts, adjoint=False, stream=None):
         k = max(opts.k, 1)

@@ -91,6 +91,7 @@ SIGNATURES = {
     "dc_profile_apply_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double), C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double)]),
+    "dc_profile_apply_passes": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64)]),
     "dc_last_error": (C.c_char_p, []),
     # host-only dense linear algebra
     "dc_dense_eig": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),

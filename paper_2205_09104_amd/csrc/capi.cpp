@@ -377,11 +377,22 @@ int dc_profile_apply_read(dc_op_t op, int32_t prec, int32_t kernel, int64_t* lau
     if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
     long n = 0, na = 0;
     double ms = 0.0, msa = 0.0;
-    dc::op_profile_read(op->op, dc::Prec(prec), kernel, &n, &ms, &na, &msa);
+    dc::op_profile_read(op->op, dc::Prec(prec), kernel, &n, &ms, nullptr, &na, &msa);
     if (launches) *launches = n;
     if (total_ms) *total_ms = ms;
     if (launches_all) *launches_all = na;
     if (total_ms_all) *total_ms_all = msa;
+    return DC_OK;
+  });
+}
+
+int dc_profile_apply_passes(dc_op_t op, int32_t prec, int32_t kernel, int64_t* passes) {
+  return guarded([&] {
+    if (!op) throw dc::InvalidArg("null handle");
+    if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
+    long v = 0;
+    dc::op_profile_read(op->op, dc::Prec(prec), kernel, nullptr, nullptr, &v, nullptr, nullptr);
+    if (passes) *passes = v;
     return DC_OK;
   });
 }

@@ -518,59 +518,264 @@ __global__ __launch_bounds__(64) void k_apply_blocks(
   }
 }
 
-// Odd-even reduction, stage 1 over compressed vectors (site x of parity p at
-// position x / 2).  Every stored block is read once per launch and yields one
-// product:
-//   MODE 1 (t_o = D_oe x_e, odd rows): hop blocks of odd sites forward (source
-//     x+mu even), hop blocks of even sites backward (row x+mu odd, source x);
-//     the self slot of every odd row is zeroed.
-//   MODE 2 (y_e = A_e x_e - D_eo t_o, even rows): self blocks of even sites on
-//     x_e (zero slot if x_e is null), hop blocks of even sites forward and of
-//     odd sites backward on t_o, both negated.
-// Items and their XCD-aware order as in k_apply_blocks; items of the other
-// parity exit at entry.
-template <int T, int P, bool FULL, int MODE>
-__global__ __launch_bounds__(64) void k_apply_oddeven(
-    const void* __restrict__ blocks, const float* __restrict__ scales,
-    const cx<typename VecOf<P>::R>* __restrict__ x_e, const cx<typename VecOf<P>::R>* __restrict__ t_o,
-    cx<typename VecOf<P>::R>* __restrict__ gbuf, const int* __restrict__ nbr,
-    const unsigned char* __restrict__ par, int V, int n, int chunk, double tm,
-    const int* __restrict__ done) {
+// ------------------------------------------------------------------ odd-even reduction
+// S = A_e - D_eo A_o^{-1} D_oe (Sec. 2.2) in factored form over compressed
+// vectors (the site x of either parity sits at row x / 2).  A hop block
+// B[x,mu] couples an even and an odd site, and each factor needs it in one
+// direction only, so both kernels are site-centric: one workgroup per row, one
+// wave per block of that row (every block is read once per launch), each
+// wave's n-vector product into LDS, then a fixed-order sum (deterministic).
+
+// One wave's product of a stored block (registers R, scale s) with the
+// n-vector v, into dst (LDS): DIR 1 forward B v (row sums), DIR 2 backward
+// Gamma5 B^H Gamma5 v (column sums), DIR 0 self block B v + i tm Gamma5 v.
+template <int T, int P, bool FULL, int DIR>
+__device__ __forceinline__ void wave_product(const TileRegs<T, P>& R, typename Tile<T, P>::A s,
+                                             const cx<typename VecOf<P>::R>* __restrict__ v,
+                                             cx<typename VecOf<P>::R>* dst, int n, double tm,
+                                             int lane) {
+  using A = typename Tile<T, P>::A;
   using VR = typename VecOf<P>::R;
+  constexpr bool DOF = DIR != 2, DOG = DIR == 2;
+  const int lr = lane >> 3, lc = lane & 7;
+  cx<A> pc[T], pr[T], f[T], g[T];
+  A npc_im[T], npr_re[T];
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+    pc[q] = mk(A(0), A(0));
+    pr[q] = mk(A(0), A(0));
+    if (DOF) {
+      const int col = lc * T + q;
+      if (FULL || col < n) {
+        const cx<VR> z = v[col];
+        pc[q] = mk(A(z.re), A(z.im));
+      }
+    }
+    if (DOG) {
+      const int row = lr * T + q;
+      if (FULL || row < n) {
+        const cx<VR> z = v[row];
+        pr[q] = (row < (n >> 1)) ? mk(A(z.re), A(z.im)) : mk(A(-z.re), A(-z.im));
+      }
+    }
+    npc_im[q] = -pc[q].im;
+    npr_re[q] = -pr[q].re;
+    f[q] = mk(A(0), A(0));
+    g[q] = mk(A(0), A(0));
+  }
+  tile_products<T, P, DOF, DOG>(R, pc, npc_im, pr, npr_re, f, g);
+  if constexpr (DOF) {
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      f[q].re = sum_row8(f[q].re) * s;
+      f[q].im = sum_row8(f[q].im) * s;
+    }
+    if (lc == 0) {
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        const int row = lr * T + q;
+        if (FULL || row < n) {
+          cx<A> w = f[q];
+          if (DIR == 0 && tm != 0.0) {  // i * tm * Gamma5 v in the accumulation precision
+            const A t = A(row < (n >> 1) ? tm : -tm);
+            const cx<VR> z = v[row];
+            w.re -= t * A(z.im);
+            w.im += t * A(z.re);
+          }
+          dst[row] = mk(VR(w.re), VR(w.im));
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      g[q].re = sum_col8(g[q].re) * s;
+      g[q].im = sum_col8(g[q].im) * s;
+    }
+    if (lr == 0) {
+#pragma unroll
+      for (int q = 0; q < T; ++q) {
+        const int col = lc * T + q;
+        if (FULL || col < n) {
+          const A gg = (col < (n >> 1)) ? A(1) : A(-1);
+          dst[col] = mk(VR(gg * g[q].re), VR(gg * g[q].im));
+        }
+      }
+    }
+  }
+}
+
+constexpr int kRedWaves = 9;   // waves per workgroup of the reduced kernels
+
+template <int T, int P>
+__device__ __forceinline__ const uint4* block_ptr(const void* blocks, size_t item) {
+  return static_cast<const uint4*>(blocks) + item * (size_t(Tile<T, P>::UNITS) * 64);
+}
+
+// t_o = A_o^{-1} D_oe x_e.  Workgroup per odd row r (site x = osite[r]):
+// waves 0-3 the forward hops B[x,mu] x_e(x+mu), waves 4-7 the backward hops
+// Gamma5 B[x-mu,mu]^H Gamma5 x_e(x-mu), then wave 8 applies the inverse of
+// x's self block to the sum of the eight products.
+// Rows are ordered XCD-aware as in k_apply_blocks (contiguous rows per XCD).
+template <int T, int P, bool FULL>
+__global__ __launch_bounds__(64 * kRedWaves) void k_reduced_oe(
+    const void* __restrict__ blocks, const float* __restrict__ scales,
+    const void* __restrict__ inv, const float* __restrict__ invsc,
+    const cx<typename VecOf<P>::R>* __restrict__ x_e, cx<typename VecOf<P>::R>* __restrict__ t_o,
+    const int* __restrict__ nbr, const int* __restrict__ osite, int V, int n, int chunk,
+    const int* __restrict__ done) {
+  using A = typename Tile<T, P>::A;
+  using VR = typename VecOf<P>::R;
+  __shared__ cx<VR> part[8][64];
   if (done && *done) return;
   const int b = blockIdx.x;
-  const int item = (b & 7) * chunk + (b >> 3);
-  if (item >= 5 * V) return;
-  const int site = item / 5, slot = item - 5 * site;
-  const int odd = par[site];
-  const size_t blk_units = size_t(Tile<T, P>::UNITS) * 64;
-  const uint4* bp = static_cast<const uint4*>(blocks) + size_t(item) * blk_units;
-  if (slot == 0) {
-    const bool zero_slot = (MODE == 1) ? (odd != 0) : (odd == 0 && x_e == nullptr);
-    if (zero_slot) {
-      cx<VR>* dst = gbuf + (size_t(site >> 1) * kSlots + 4) * n;
-      for (int i = threadIdx.x; i < n; i += 64) dst[i] = mk(VR(0), VR(0));
-    } else if (MODE == 2 && odd == 0) {
-      apply_one_block<T, P, FULL, false, 3, true, false>(bp, scales, x_e, gbuf, item, site, 0,
-                                                         site, n, tm);
-    }
-    return;
+  const int r = (b & 7) * chunk + (b >> 3);
+  if (r >= (V >> 1)) return;
+  const int x = osite[r];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  TileRegs<T, P> R;
+  if (w < 4) {
+    const int item = 5 * x + 1 + w;
+    R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+    const A s = (P == P16S) ? A(scales[item]) : A(1);
+    const int src = nbr[w * V + x];
+    wave_product<T, P, FULL, 1>(R, s, x_e + size_t(src >> 1) * n, part[w], n, 0.0, lane);
+  } else if (w < 8) {
+    const int mu = w - 4;
+    const int y = nbr[(4 + mu) * V + x];
+    const int item = 5 * y + 1 + mu;
+    R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+    const A s = (P == P16S) ? A(scales[item]) : A(1);
+    wave_product<T, P, FULL, 2>(R, s, x_e + size_t(y >> 1) * n, part[w], n, 0.0, lane);
   }
-  const int src = nbr[(slot - 1) * V + site];
-  if (MODE == 1) {
-    if (odd)
-      apply_one_block<T, P, FULL, true, 1, true, false>(bp, scales, x_e, gbuf, item, site, slot,
-                                                        src, n, tm);
-    else
-      apply_one_block<T, P, FULL, true, 2, true, false>(bp, scales, x_e, gbuf, item, site, slot,
-                                                        src, n, tm);
+  __syncthreads();
+  if (w != 8) return;
+  // loaded after the barrier: holding the tile across it would raise the
+  // kernel's register count past what three 9-wave workgroups per CU allow
+  R.load(block_ptr<T, P>(inv, size_t(x)), lane);
+  const int lr = lane >> 3, lc = lane & 7;
+  cx<A> pc[T], pr[T], f[T], g[T];
+  A npc_im[T], npr_re[T];
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+    const int col = lc * T + q;
+    cx<VR> t = mk(VR(0), VR(0));
+    if (FULL || col < n) {
+      t = part[0][col];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        t.re += part[k][col].re;
+        t.im += part[k][col].im;
+      }
+    }
+    pc[q] = mk(A(t.re), A(t.im));
+    npc_im[q] = -pc[q].im;
+    pr[q] = mk(A(0), A(0));
+    npr_re[q] = A(0);
+    f[q] = mk(A(0), A(0));
+    g[q] = mk(A(0), A(0));
+  }
+  tile_products<T, P, true, false>(R, pc, npc_im, pr, npr_re, f, g);
+  const A s = (P == P16S) ? A(invsc[x]) : A(1);
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+    f[q].re = sum_row8(f[q].re) * s;
+    f[q].im = sum_row8(f[q].im) * s;
+  }
+  if (lc != 0) return;
+#pragma unroll
+  for (int q = 0; q < T; ++q) {
+    const int row = lr * T + q;
+    if (FULL || row < n) t_o[size_t(r) * n + row] = mk(VR(f[q].re), VR(f[q].im));
+  }
+}
+
+// s = A_e x_e - D_eo t_o (A_e x_e omitted when x_e is null), workgroup per
+// even row r (site x = esite[r]): wave 0 the self block, waves 1-4 the forward
+// hops B[x,mu] t_o(x+mu), waves 5-8 the backward hops Gamma5 B[x-mu,mu]^H
+// Gamma5 t_o(x-mu), both negated; summed in that order.  Epilogue on row r
+// (e = v, the apply's chain input, where it is read):
+//   EPI 0: out = s
+//   EPI 1: p = e - ca s; out = p; y = c0 e + cb p       (first chain step)
+//   EPI 2: p = out - ca s; out = p; y += cb p            (later chain steps)
+//   EPI 3: out = e - s                                    (residual, e = b)
+template <int T, int P, bool FULL, int EPI>
+__global__ __launch_bounds__(64 * kRedWaves) void k_reduced_eo(
+    const void* __restrict__ blocks, const float* __restrict__ scales,
+    const cx<typename VecOf<P>::R>* x_e, const cx<typename VecOf<P>::R>* __restrict__ t_o,
+    const int* __restrict__ nbr, const int* __restrict__ esite, int V, int n, int chunk, double tm,
+    cx<typename VecOf<P>::R>* out, const cx<typename VecOf<P>::R>* e, cx<typename VecOf<P>::R>* y,
+    z64 c0, z64 ca, z64 cb, const int* __restrict__ done) {
+  using A = typename Tile<T, P>::A;
+  using VR = typename VecOf<P>::R;
+  __shared__ cx<VR> part[kRedWaves][64];
+  if (done && *done) return;
+  const int b = blockIdx.x;
+  const int r = (b & 7) * chunk + (b >> 3);
+  if (r >= (V >> 1)) return;
+  const int x = esite[r];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  if (w == 0) {
+    if (x_e) {
+      TileRegs<T, P> R;
+      const int item = 5 * x;
+      R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+      const A s = (P == P16S) ? A(scales[item]) : A(1);
+      wave_product<T, P, FULL, 0>(R, s, x_e + size_t(r) * n, part[0], n, tm, lane);
+    } else {
+      for (int i = lane; i < n; i += 64) part[0][i] = mk(VR(0), VR(0));
+    }
+  } else if (w < 5) {
+    const int mu = w - 1;
+    const int item = 5 * x + 1 + mu;
+    TileRegs<T, P> R;
+    R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+    const A s = (P == P16S) ? A(scales[item]) : A(1);
+    const int src = nbr[mu * V + x];
+    wave_product<T, P, FULL, 1>(R, -s, t_o + size_t(src >> 1) * n, part[w], n, 0.0, lane);
   } else {
-    if (!odd)
-      apply_one_block<T, P, FULL, true, 1, true, true>(bp, scales, t_o, gbuf, item, site, slot,
-                                                       src, n, tm);
-    else
-      apply_one_block<T, P, FULL, true, 2, true, true>(bp, scales, t_o, gbuf, item, site, slot,
-                                                       src, n, tm);
+    const int mu = w - 5;
+    const int yy = nbr[(4 + mu) * V + x];
+    const int item = 5 * yy + 1 + mu;
+    TileRegs<T, P> R;
+    R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+    const A s = (P == P16S) ? A(scales[item]) : A(1);
+    wave_product<T, P, FULL, 2>(R, -s, t_o + size_t(yy >> 1) * n, part[w], n, 0.0, lane);
+  }
+  __syncthreads();
+  if (w != 0) return;
+  const VR ar = VR(ca.re), ai = VR(ca.im), br = VR(cb.re), bi = VR(cb.im);
+  for (int c = lane; c < n; c += 64) {
+    cx<VR> t = part[0][c];
+#pragma unroll
+    for (int k = 1; k < kRedWaves; ++k) {
+      t.re += part[k][c].re;
+      t.im += part[k][c].im;
+    }
+    const size_t i = size_t(r) * n + c;
+    if (EPI == 0) {
+      out[i] = t;
+    } else if (EPI == 3) {
+      const cx<VR> bb = e[i];
+      out[i] = mk(VR(bb.re - t.re), VR(bb.im - t.im));
+    } else {
+      const cx<VR> base = (EPI == 1) ? e[i] : out[i];
+      cx<VR> p = base;
+      p.re -= ar * t.re - ai * t.im;
+      p.im -= ar * t.im + ai * t.re;
+      out[i] = p;
+      cx<VR> yv;
+      if (EPI == 1) {
+        const VR zr = VR(c0.re), zi = VR(c0.im);
+        yv.re = zr * base.re - zi * base.im + (br * p.re - bi * p.im);
+        yv.im = zr * base.im + zi * base.re + (br * p.im + bi * p.re);
+      } else {
+        yv = y[i];
+        yv.re += br * p.re - bi * p.im;
+        yv.im += br * p.im + bi * p.re;
+      }
+      y[i] = yv;
+    }
   }
 }
 
@@ -1773,37 +1978,32 @@ void launch_bj_gather_store(Prec p, int n, int V, const void* inv, const float* 
 }
 
 void launch_bj_rows(Prec p, int n, int rows, const int* rowsite, const void* inv,
-                    const float* scales, const void* in, int from_gbuf, void* out,
-                    const int* done, hipStream_t st) {
+                    const float* scales, const void* in, void* out, hipStream_t st) {
   const z64 z = mk(0.0, 0.0);
-  if (from_gbuf)
-    bj_P<true, 0>(p, n, rows, inv, scales, in, out, nullptr, nullptr, z, z, z, done, st, rowsite);
-  else
-    bj_P<false, 0>(p, n, rows, inv, scales, in, out, nullptr, nullptr, z, z, z, done, st, rowsite);
+  bj_P<false, 0>(p, n, rows, inv, scales, in, out, nullptr, nullptr, z, z, z, nullptr, st, rowsite);
 }
 
-template <int P, int MODE>
-static void oddeven_T(int n, int V, const void* blocks, const float* scales, const void* x_e,
-                      const void* t_o, void* gbuf, const int* nbr, const unsigned char* par,
-                      double tm, const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+template <int P>
+static void reduced_oe_T(int n, int V, const void* blocks, const float* scales, const void* inv,
+                         const float* invsc, const void* x_e, void* t_o, const int* nbr,
+                         const int* osite, const int* done, hipStream_t st, hipEvent_t ev0,
+                         hipEvent_t ev1) {
   using VR = typename VecOf<P>::R;
-  const int chunk = (5 * V + 7) / 8;
-  const dim3 grid(unsigned(chunk) * 8u), block(64);
+  const int rows = V / 2;
+  const int chunk = (rows + 7) / 8;
+  const dim3 grid(unsigned(chunk) * 8u), block(64 * kRedWaves);
   const auto* xe = static_cast<const cx<VR>*>(x_e);
-  const auto* to = static_cast<const cx<VR>*>(t_o);
-  auto* pg = static_cast<cx<VR>*>(gbuf);
+  auto* to = static_cast<cx<VR>*>(t_o);
   const bool full = (n % 8) == 0;
   switch (tile_T(n)) {
-#define DC_CASE(TV)                                                                            \
-  case TV:                                                                                     \
-    if (full)                                                                                  \
-      hipExtLaunchKernelGGL((k_apply_oddeven<TV, P, true, MODE>), grid, block, 0, st, ev0,     \
-                            ev1, 0, blocks, scales, xe, to, pg, nbr, par, V, n, chunk, tm,    \
-                            done);                                                             \
-    else                                                                                       \
-      hipExtLaunchKernelGGL((k_apply_oddeven<TV, P, false, MODE>), grid, block, 0, st, ev0,    \
-                            ev1, 0, blocks, scales, xe, to, pg, nbr, par, V, n, chunk, tm,    \
-                            done);                                                             \
+#define DC_CASE(TV)                                                                           \
+  case TV:                                                                                    \
+    if (full)                                                                                 \
+      hipExtLaunchKernelGGL((k_reduced_oe<TV, P, true>), grid, block, 0, st, ev0, ev1, 0,     \
+                            blocks, scales, inv, invsc, xe, to, nbr, osite, V, n, chunk, done); \
+    else                                                                                      \
+      hipExtLaunchKernelGGL((k_reduced_oe<TV, P, false>), grid, block, 0, st, ev0, ev1, 0,    \
+                            blocks, scales, inv, invsc, xe, to, nbr, osite, V, n, chunk, done); \
     break;
     DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
 #undef DC_CASE
@@ -1813,20 +2013,76 @@ static void oddeven_T(int n, int V, const void* blocks, const float* scales, con
   DC_HIP(hipGetLastError());
 }
 
-void launch_apply_oddeven(Prec p, int mode, int n, int V, const void* blocks, const float* scales,
-                          const void* x_e, const void* t_o, void* gbuf, const int* nbr,
-                          const unsigned char* par, double tm, const int* done, hipStream_t st,
-                          hipEvent_t ev0, hipEvent_t ev1) {
-  if (mode != 1 && mode != 2) throw InvalidArg("odd-even stage mode must be 1 or 2");
-  if (mode == 1) {
-    if (p == P64) oddeven_T<P64, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
-    else if (p == P32) oddeven_T<P32, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
-    else oddeven_T<P16S, 1>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
-  } else {
-    if (p == P64) oddeven_T<P64, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
-    else if (p == P32) oddeven_T<P32, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
-    else oddeven_T<P16S, 2>(n, V, blocks, scales, x_e, t_o, gbuf, nbr, par, tm, done, st, ev0, ev1);
+void launch_reduced_oe(Prec p, int n, int V, const void* blocks, const float* scales,
+                       const void* inv, const float* invsc, const void* x_e, void* t_o,
+                       const int* nbr, const int* osite, const int* done, hipStream_t st,
+                       hipEvent_t ev0, hipEvent_t ev1) {
+  if (V < 2 || V % 2) throw InvalidArg("the reduced operator needs an even number of sites");
+  if (p == P64) reduced_oe_T<P64>(n, V, blocks, scales, inv, invsc, x_e, t_o, nbr, osite, done, st, ev0, ev1);
+  else if (p == P32) reduced_oe_T<P32>(n, V, blocks, scales, inv, invsc, x_e, t_o, nbr, osite, done, st, ev0, ev1);
+  else reduced_oe_T<P16S>(n, V, blocks, scales, inv, invsc, x_e, t_o, nbr, osite, done, st, ev0, ev1);
+}
+
+template <int P, int EPI>
+static void reduced_eo_T(int n, int V, const void* blocks, const float* scales, const void* x_e,
+                         const void* t_o, const int* nbr, const int* esite, double tm, void* out,
+                         const void* e, void* y, z64 c0, z64 ca, z64 cb, const int* done,
+                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  using VR = typename VecOf<P>::R;
+  const int rows = V / 2;
+  const int chunk = (rows + 7) / 8;
+  const dim3 grid(unsigned(chunk) * 8u), block(64 * kRedWaves);
+  const auto* xe = static_cast<const cx<VR>*>(x_e);
+  const auto* to = static_cast<const cx<VR>*>(t_o);
+  auto* o = static_cast<cx<VR>*>(out);
+  const auto* ee = static_cast<const cx<VR>*>(e);
+  auto* yy = static_cast<cx<VR>*>(y);
+  const bool full = (n % 8) == 0;
+  switch (tile_T(n)) {
+#define DC_CASE(TV)                                                                              \
+  case TV:                                                                                       \
+    if (full)                                                                                    \
+      hipExtLaunchKernelGGL((k_reduced_eo<TV, P, true, EPI>), grid, block, 0, st, ev0, ev1, 0,   \
+                            blocks, scales, xe, to, nbr, esite, V, n, chunk, tm, o, ee, yy, c0,  \
+                            ca, cb, done);                                                       \
+    else                                                                                         \
+      hipExtLaunchKernelGGL((k_reduced_eo<TV, P, false, EPI>), grid, block, 0, st, ev0, ev1, 0,  \
+                            blocks, scales, xe, to, nbr, esite, V, n, chunk, tm, o, ee, yy, c0,  \
+                            ca, cb, done);                                                       \
+    break;
+    DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
+#undef DC_CASE
+    default:
+      throw InvalidArg("block size n > 64 is not supported");
   }
+  DC_HIP(hipGetLastError());
+}
+
+template <int P>
+static void reduced_eo_P(int epi, int n, int V, const void* blocks, const float* scales,
+                         const void* x_e, const void* t_o, const int* nbr, const int* esite,
+                         double tm, void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
+                         const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  switch (epi) {
+    case 0: reduced_eo_T<P, 0>(n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1); break;
+    case 1: reduced_eo_T<P, 1>(n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1); break;
+    case 2: reduced_eo_T<P, 2>(n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1); break;
+    default: reduced_eo_T<P, 3>(n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1); break;
+  }
+}
+
+void launch_reduced_eo(Prec p, int epi, int n, int V, const void* blocks, const float* scales,
+                       const void* x_e, const void* t_o, const int* nbr, const int* esite,
+                       double tm, void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
+                       const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (epi < 0 || epi > 3) throw InvalidArg("reduced epilogue must be 0..3");
+  if (V < 2 || V % 2) throw InvalidArg("the reduced operator needs an even number of sites");
+  if (!t_o || !out) throw InvalidArg("null vector pointer");
+  if ((epi == 1 || epi == 3) && !e) throw InvalidArg("null epilogue input");
+  if ((epi == 1 || epi == 2) && !y) throw InvalidArg("null chain output");
+  if (p == P64) reduced_eo_P<P64>(epi, n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1);
+  else if (p == P32) reduced_eo_P<P32>(epi, n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1);
+  else reduced_eo_P<P16S>(epi, n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1);
 }
 
 void launch_oddeven_split(Prec p, int n, int half_sites, const int* esite, const int* osite,

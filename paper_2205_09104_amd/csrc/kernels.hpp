@@ -71,21 +71,28 @@ void launch_bj_gather_poly(Prec p, int n, int V, const void* inv, const float* s
                            hipStream_t st);
 
 // out_r = B_{site(r)}^{-1} in_r for rows r < rows of a compressed vector, where
-// rowsite[r] is the lattice site of row r (null: row r is site r); in is a
-// plain vector or (from_gbuf) a gbuf whose 9 slots are summed first.
+// rowsite[r] is the lattice site of row r (null: row r is site r).
 void launch_bj_rows(Prec p, int n, int rows, const int* rowsite, const void* inv,
-                    const float* scales, const void* in, int from_gbuf, void* out,
-                    const int* done, hipStream_t st);
+                    const float* scales, const void* in, void* out, hipStream_t st);
 
 // ---------------------------------------------------------------- odd-even reduction
-// Stage 1 of D_oe (mode 1: odd rows of gbuf from x_e) or of A_e x_e - D_eo t_o
-// (mode 2: even rows from x_e, t_o; x_e null gives -D_eo t_o) over compressed
-// vectors (site x of a parity at row x / 2, every extent even); gbuf: [V/2][9][n]
-// summed by the ordinary gathers over V/2 rows.  par: uint8 [V] site parity.
-void launch_apply_oddeven(Prec p, int mode, int n, int V, const void* blocks, const float* scales,
-                          const void* x_e, const void* t_o, void* gbuf, const int* nbr,
-                          const unsigned char* par, double tm, const int* done, hipStream_t st,
-                          hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// The reduced operator S = A_e - D_eo A_o^{-1} D_oe over compressed vectors
+// (site x of a parity at row x / 2, every extent even), two site-centric kernels.
+// launch_reduced_oe: t_o = A_o^{-1} D_oe x_e, with inv / invsc the self-block
+// inverses of every site (tiled, indexed by site) and osite: int32 [V/2] odd
+// row -> site.
+void launch_reduced_oe(Prec p, int n, int V, const void* blocks, const float* scales,
+                       const void* inv, const float* invsc, const void* x_e, void* t_o,
+                       const int* nbr, const int* osite, const int* done, hipStream_t st,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// launch_reduced_eo: s = A_e x_e - D_eo t_o (x_e null: -D_eo t_o) with the
+// epilogue epi: 0 out = s; 1 p = e - ca s, out = p, y = c0 e + cb p; 2 p = out -
+// ca s, out = p, y += cb p; 3 out = e - s.  esite: int32 [V/2] even row -> site.
+void launch_reduced_eo(Prec p, int epi, int n, int V, const void* blocks, const float* scales,
+                       const void* x_e, const void* t_o, const int* nbr, const int* esite,
+                       double tm, void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
+                       const int* done, hipStream_t st, hipEvent_t ev0 = nullptr,
+                       hipEvent_t ev1 = nullptr);
 // split a full-lattice vector into its compressed even and odd halves, or merge
 // them back (dir 0: split, 1: merge); esite/osite: int32 [V/2] row -> site
 void launch_oddeven_split(Prec p, int n, int half_sites, const int* esite, const int* osite,

@@ -38,16 +38,6 @@ static size_t block_units(int n, Prec p) {
   return size_t(tile_elems(n, epl) / epl) * 64;  // 16-byte units per block
 }
 
-void* Op::gbuf_s(Prec p) {
-  const size_t rows = size_t(V / 2) * 9 * n;
-  if (p == P64) {
-    gbs64.ensure(rows * sizeof(z64));
-    return gbs64.p;
-  }
-  gbs32.ensure(rows * sizeof(z32));
-  return gbs32.p;
-}
-
 void* Op::tmp_s(Prec p) {
   const size_t len = size_t(V / 2) * n;
   if (p == P64) {
@@ -134,20 +124,16 @@ void op_build(Op& op, const int dims[4], int n_tv, int store, double mu, const v
   op.oddeven = (dims[0] % 2 == 0) && (dims[1] % 2 == 0) && (dims[2] % 2 == 0) &&
                (dims[3] % 2 == 0);
   if (op.oddeven) {
-    std::vector<unsigned char> par(op.V);
     std::vector<int> es, os;
     es.reserve(op.V / 2);
     os.reserve(op.V / 2);
     for (int x = 0; x < op.V; ++x) {
       const int x0 = x % dims[0], x1 = (x / dims[0]) % dims[1];
       const int x2 = (x / (dims[0] * dims[1])) % dims[2], x3 = x / (dims[0] * dims[1] * dims[2]);
-      par[x] = static_cast<unsigned char>((x0 + x1 + x2 + x3) & 1);
-      (par[x] ? os : es).push_back(x);
+      (((x0 + x1 + x2 + x3) & 1) ? os : es).push_back(x);
     }
-    op.par.alloc(par.size());
     op.esite.alloc(es.size() * sizeof(int));
     op.osite.alloc(os.size() * sizeof(int));
-    DC_HIP(hipMemcpyAsync(op.par.p, par.data(), par.size(), hipMemcpyHostToDevice, st));
     DC_HIP(hipMemcpyAsync(op.esite.p, es.data(), es.size() * sizeof(int), hipMemcpyHostToDevice, st));
     DC_HIP(hipMemcpyAsync(op.osite.p, os.data(), os.size() * sizeof(int), hipMemcpyHostToDevice, st));
     DC_HIP(hipStreamSynchronize(st));  // host tables must outlive the copies
@@ -170,6 +156,8 @@ void ApplyProfile::reset() {
   for (int i = 0; i < kSlotsP; ++i) {
     ms[i] = ms_all[i] = 0.0;
     count[i] = count_all[i] = 0;
+    passes[i] = 0;
+    seen[i] = 0;
   }
   missed = 0;
   tag = -1;
@@ -207,6 +195,7 @@ void ApplyProfile::flush() {
     if (!r.noop) {
       ms[r.prec] += t;
       ++count[r.prec];
+      passes[r.prec] += r.passes;
     }
     idle.push_back(r.a);
     idle.push_back(r.b);
@@ -236,34 +225,59 @@ CycleSignal::~CycleSignal() {
   if (host) (void)hipHostFree(host);
 }
 
-// Stage 1 of the apply, timed when profiling is on.  Records are flushed
-// outside cycles once many have accumulated, so the event pool stays small.
+// Stage 1 of the apply, timed when profiling is on (one in `every` launches
+// of each kernel).  Records are flushed outside cycles once many have
+// accumulated, so the event pool stays small.
 static void stage1(Op& op, Prec p, int n, int V, const void* blocks, const float* scales,
                    const void* in, void* gbuf, const int* nbr, double tm, const int* done,
                    hipStream_t st) {
   ApplyProfile& pr = op.prof;
   hipEvent_t a = nullptr, b = nullptr;
-  if (pr.on && (pr.seen++ % pr.every) == 0) {
+  const int slot = prec_slot(p);
+  if (pr.sample(slot)) {
     if (pr.tag < 0 && pr.recs.size() >= 2048) pr.flush();
     if (!pr.take(&a, &b)) ++pr.missed;
   }
   launch_apply_blocks(p, n, V, blocks, scales, in, gbuf, nbr, tm, done, st, a, b);
-  if (a) pr.recs.push_back({a, b, prec_slot(p), done ? pr.tag : -1, false});
+  if (a) pr.recs.push_back({a, b, slot, done ? pr.tag : -1, false, 1});
 }
 
-// Stage kernels of the odd-even reduction (mode 1: D_oe, 2: D_eo), timed like stage1.
-static void stage_oddeven(Op& op, Prec p, int mode, const void* x_e, const void* t_o, void* gbuf,
-                          double tm, const int* done, hipStream_t st) {
+// The reduced operator's kernels (Sec. 2.2, factored form), timed like stage1:
+// t_o = A_o^{-1} D_oe x_e, then A_e x_e - D_eo t_o with an epilogue.
+static void reduced_oe(Op& op, Prec p, const void* inv, const float* invsc, const void* x_e,
+                       void* t_o, const int* done, hipStream_t st) {
   ApplyProfile& pr = op.prof;
   hipEvent_t a = nullptr, b = nullptr;
-  if (pr.on && (pr.seen++ % pr.every) == 0) {
+  const int slot = 3 + prec_slot(p);
+  if (pr.sample(slot)) {
     if (pr.tag < 0 && pr.recs.size() >= 2048) pr.flush();
     if (!pr.take(&a, &b)) ++pr.missed;
   }
-  launch_apply_oddeven(p, mode, op.n, op.V, op.blocks(p), op.scales(p), x_e, t_o, gbuf,
-                       op.nbr.as<int>(), static_cast<const unsigned char*>(op.par.p), tm, done,
-                       st, a, b);
-  if (a) pr.recs.push_back({a, b, 3 * mode + prec_slot(p), done ? pr.tag : -1, false});
+  launch_reduced_oe(p, op.n, op.V, op.blocks(p), op.scales(p), inv, invsc, x_e, t_o,
+                    op.nbr.as<int>(), op.osite.as<int>(), done, st, a, b);
+  if (a) pr.recs.push_back({a, b, slot, done ? pr.tag : -1, false, 2});
+}
+
+static void reduced_eo(Op& op, Prec p, int epi, const void* x_e, const void* t_o, double tm,
+                       void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
+                       const int* done, hipStream_t st) {
+  ApplyProfile& pr = op.prof;
+  hipEvent_t a = nullptr, b = nullptr;
+  const int slot = 6 + prec_slot(p);
+  if (pr.sample(slot)) {
+    if (pr.tag < 0 && pr.recs.size() >= 2048) pr.flush();
+    if (!pr.take(&a, &b)) ++pr.missed;
+  }
+  launch_reduced_eo(p, epi, op.n, op.V, op.blocks(p), op.scales(p), x_e, t_o, op.nbr.as<int>(),
+                    op.esite.as<int>(), tm, out, e, y, c0, ca, cb, done, st, a, b);
+  if (a) {
+    // distinct vectors read (x_e, t_o and the epilogue's inputs) plus writes
+    int passes = 1 + (x_e ? 1 : 0);
+    if ((epi == 1 || epi == 3) && e != x_e) ++passes;
+    if (epi == 2) passes += (out != x_e ? 1 : 0) + 1;
+    passes += (epi == 1 || epi == 2) ? 2 : 1;
+    pr.recs.push_back({a, b, slot, done ? pr.tag : -1, false, passes});
+  }
 }
 
 void op_profile(Op& op, int every) {
@@ -271,16 +285,16 @@ void op_profile(Op& op, int every) {
   op.prof.reset();
   op.prof.on = every != 0;
   op.prof.every = every > 0 ? every : 1;
-  op.prof.seen = 0;
 }
 
-void op_profile_read(Op& op, Prec p, int kernel, long* launches, double* total_ms,
+void op_profile_read(Op& op, Prec p, int kernel, long* launches, double* total_ms, long* passes,
                      long* launches_all, double* total_ms_all) {
   if (kernel < 0 || kernel > 2) throw InvalidArg("kernel must be 0, 1 or 2");
   op.prof.flush();
   const int i = 3 * kernel + prec_slot(p);
   if (launches) *launches = op.prof.count[i];
   if (total_ms) *total_ms = op.prof.ms[i];
+  if (passes) *passes = op.prof.passes[i];
   if (launches_all) *launches_all = op.prof.count_all[i];
   if (total_ms_all) *total_ms_all = op.prof.ms_all[i];
 }
@@ -356,20 +370,16 @@ void op_apply_reduced(Op& op, Prec p, int adjoint, const void* in, void* out, hi
   const Op::BJ& bj = op.ensure_bj(sign, st);
   const void* inv = bj_blocks(bj, p);
   const float* invsc = (p == P16S) ? bj.sc16.as<float>() : nullptr;
-  const auto* par = static_cast<const unsigned char*>(op.par.p);
-  void* gb = op.gbuf_s(p);
   void* ts = op.tmp_s(p);
   const void* src = in;
   if (adjoint) {
     launch_gamma5(p, in, out, half, op.n, st);
     src = out;
   }
-  launch_apply_oddeven(p, 1, op.n, op.V, op.blocks(p), op.scales(p), src, nullptr, gb,
-                       op.nbr.as<int>(), par, tm, nullptr, st);
-  launch_bj_rows(p, op.n, half, op.osite.as<int>(), inv, invsc, gb, 1, ts, nullptr, st);
-  launch_apply_oddeven(p, 2, op.n, op.V, op.blocks(p), op.scales(p), src, ts, gb,
-                       op.nbr.as<int>(), par, tm, nullptr, st);
-  launch_gather_store(p, op.n, half, gb, out, nullptr, st);
+  const z64 z = mk(0.0, 0.0);
+  reduced_oe(op, p, inv, invsc, src, ts, nullptr, st);
+  // the D_eo kernel reads src only on its own row before writing that row of out
+  reduced_eo(op, p, 0, src, ts, tm, out, nullptr, nullptr, z, z, z, nullptr, st);
   if (adjoint) launch_gamma5(p, out, out, half, op.n, st);
 }
 
@@ -433,8 +443,8 @@ struct Krylov {
   const void* bjinv = nullptr;   // block-Jacobi inverses of this precision, if used
   const float* bjsc = nullptr;
   int rows = 0;                   // rows of the vectors (sites, or half of them when reduced)
-  void* gb = nullptr;             // gbuf of the apply's stage 1
-  const void* oinv = nullptr;     // odd-even reduction: D_oo^{-1} blocks, odd-site temporary
+  void* gb = nullptr;             // gbuf of the full lattice's stage 1
+  const void* oinv = nullptr;     // odd-even reduction: A_o^{-1} blocks, odd-row temporary
   const float* oinvsc = nullptr;
   Z* ts = nullptr;
 
@@ -451,7 +461,6 @@ struct Krylov {
       const Op::BJ& b = op.ensure_bj(v.sign, st);   // D_oo^{-1}: inverses of the odd self blocks
       oinv = bj_blocks(b, p);
       oinvsc = (p == P16S) ? b.sc16.as<float>() : nullptr;
-      gb = op.gbuf_s(p);
       ts = static_cast<Z*>(op.tmp_s(p));
     } else {
       gb = op.gbuf(p);
@@ -511,22 +520,29 @@ struct Krylov {
   Z* Uv() const { return var.U.as<Z>(); }
   Z* Cv() const { return var.C.as<Z>(); }
 
-  // Stage 1 of one apply into gb: D in on the full lattice, or the reduced
-  // operator A_e in - D_eo D_oo^{-1} D_oe in on compressed even vectors
-  // (Sec. 2.2, factored form: D_oe, the odd self-block inverses, D_eo).
+  // Stage 1 of one full-lattice apply into gb.
   void stage(const Z* in, const int* done) {
-    if (!var.schur) {
-      stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), in, gb, op.nbr.as<int>(), tm, done,
-             st);
-      return;
-    }
-    stage_oddeven(op, p, 1, in, nullptr, gb, tm, done, st);
-    launch_bj_rows(p, op.n, rows, op.osite.as<int>(), oinv, oinvsc, gb, 1, ts, done, st);
-    stage_oddeven(op, p, 2, in, ts, gb, tm, done, st);
+    stage1(op, p, op.n, op.V, op.blocks(p), op.scales(p), in, gb, op.nbr.as<int>(), tm, done, st);
+  }
+
+  // One apply of the reduced operator S = A_e - D_eo A_o^{-1} D_oe on compressed
+  // even vectors (Sec. 2.2, factored form) with the D_eo kernel's epilogue
+  // (0 store, 1 first chain step, 2 later chain step, 3 residual).  Its
+  // epilogue reads and writes only the row it computes, so out may alias in.
+  void reduced(const Z* in, int epi, Z* out, const Z* e, Z* y, z64 c0, z64 ca, z64 cb,
+               const int* done) {
+    reduced_oe(op, p, oinv, oinvsc, in, ts, done, st);
+    reduced_eo(op, p, epi, in, ts, tm, out, e, y, c0, ca, cb, done, st);
   }
 
   // A~ in = (B^{-1}) D in (one matvec)
   void A(const Z* in, Z* out, const int* done) {
+    if (var.schur) {
+      const z64 z = mk(0.0, 0.0);
+      reduced(in, 0, out, nullptr, nullptr, z, z, z, done);
+      ++matvecs;
+      return;
+    }
     stage(in, done);
     if (bjinv) launch_bj_gather_store(p, op.n, rows, bjinv, bjsc, gb, out, done, st);
     else launch_gather_store(p, op.n, rows, gb, out, done, st);
@@ -552,6 +568,15 @@ struct Krylov {
       return;
     }
     // i = 1: prod = v - A v / theta_0;  y = v / theta_0 + prod / theta_1
+    if (var.schur) {
+      reduced(in, 1, prod, in, out, inv(th[0]), inv(th[0]), inv(th[1]), done);
+      ++matvecs;
+      for (int i = 2; i < d; ++i) {
+        reduced(prod, 2, prod, nullptr, out, mk(0.0, 0.0), inv(th[i - 1]), inv(th[i]), done);
+        ++matvecs;
+      }
+      return;
+    }
     stage(in, done);
     if (bjinv)
       launch_bj_gather_poly_first(p, op.n, rows, bjinv, bjsc, gb, in, prod, out, inv(th[0]),
@@ -583,8 +608,14 @@ struct Krylov {
 
   // r = b - D x (true residual in the variant's precision); returns ||r||
   double true_resid(const Z* x, const Z* b, Z* r) {
-    stage(x, nullptr);
-    launch_gather_resid(p, op.n, rows, gb, b, r, op.red(), nrm, st);
+    if (var.schur) {
+      const z64 z = mk(0.0, 0.0);
+      reduced(x, 3, r, b, nullptr, z, z, z, nullptr);
+      launch_norm2(p, r, N, op.red(), nrm, st);
+    } else {
+      stage(x, nullptr);
+      launch_gather_resid(p, op.n, rows, gb, b, r, op.red(), nrm, st);
+    }
     ++matvecs;
     double h;
     DC_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1110,9 +1141,9 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       bb = op.t64a.as<z64>();
       xx = op.t64b.as<z64>();
     }
-    // odd-even reduction (Sec. 2.2): solve S x_e = b_e - D_eo D_oo^{-1} b_o on
+    // odd-even reduction (Sec. 2.2): solve S x_e = b_e - D_eo A_o^{-1} b_o on
     // compressed even vectors to tol ||b|| / ||b^_e|| (the odd rows of the full
-    // residual vanish), then x_o = D_oo^{-1} (b_o - D_oe x_e)
+    // residual vanish), then x_o = A_o^{-1} b_o - A_o^{-1} D_oe x_e
     const z64* bfull = bb;
     z64* xfull = xx;
     double tol_r = tol[r];
@@ -1121,19 +1152,20 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
     const int* osite = op.osite.as<int>();
     const double tm = sign * op.mu;
     const void* oinv = nullptr;
+    const z64 z0 = mk(0.0, 0.0);
     if (o.schur) {
       oinv = op.ensure_bj(sign, st).b64.p;
       be.alloc(N * sizeof(z64));
       bo.alloc(N * sizeof(z64));
       xe.alloc(N * sizeof(z64));
       to.alloc(N * sizeof(z64));
-      const auto* par = static_cast<const unsigned char*>(op.par.p);
       launch_oddeven_split(P64, op.n, half, esite, osite, const_cast<z64*>(bfull), be.p, bo.p, 0, st);
       if (use_x0) launch_oddeven_split(P64, op.n, half, esite, osite, xfull, xe.p, nullptr, 0, st);
-      launch_bj_rows(P64, op.n, half, osite, oinv, nullptr, bo.p, 0, to.p, nullptr, st);
-      launch_apply_oddeven(P64, 2, op.n, op.V, op.blocks(P64), nullptr, nullptr, to.p,
-                           op.gbuf_s(P64), op.nbr.as<int>(), par, tm, nullptr, st);
-      launch_gather_store(P64, op.n, half, op.gbuf_s(P64), op.tmp_s(P64), nullptr, st);
+      launch_bj_rows(P64, op.n, half, osite, oinv, nullptr, bo.p, to.p, st);   // A_o^{-1} b_o
+      // -D_eo A_o^{-1} b_o (set-up and recovery launches are not profiled)
+      launch_reduced_eo(P64, 0, op.n, op.V, op.blocks(P64), nullptr, nullptr, to.p,
+                        op.nbr.as<int>(), esite, tm, op.tmp_s(P64), nullptr, nullptr, z0, z0, z0,
+                        nullptr, st);
       launch_axpy(P64, mk(1.0, 0.0), op.tmp_s(P64), be.p, N, st);   // be := b^_e
       double nb[2];
       launch_norm2(P64, bfull, Nfull, op.red(), op.scal.as<double>(), st);
@@ -1218,14 +1250,10 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       s.matvecs += int(KO.matvecs);
     }
     if (o.schur) {
-      const auto* par = static_cast<const unsigned char*>(op.par.p);
-      launch_apply_oddeven(P64, 1, op.n, op.V, op.blocks(P64), nullptr, xe.p, nullptr,
-                           op.gbuf_s(P64), op.nbr.as<int>(), par, tm, nullptr, st);
-      launch_gather_store(P64, op.n, half, op.gbuf_s(P64), to.p, nullptr, st);   // D_oe x_e
-      launch_scale(P64, to.p, to.p, N, nullptr, -1.0, nullptr, st);
-      launch_axpy(P64, mk(1.0, 0.0), bo.p, to.p, N, st);                          // b_o - D_oe x_e
-      launch_bj_rows(P64, op.n, half, osite, oinv, nullptr, to.p, 0, bo.p, nullptr, st);
-      launch_oddeven_split(P64, op.n, half, esite, osite, xfull, xe.p, bo.p, 1, st);
+      launch_reduced_oe(P64, op.n, op.V, op.blocks(P64), nullptr, oinv, nullptr, xe.p, bo.p,
+                        op.nbr.as<int>(), osite, nullptr, st);       // A_o^{-1} D_oe x_e
+      launch_axpy(P64, mk(-1.0, 0.0), bo.p, to.p, N, st);           // x_o = A_o^{-1} b_o - that
+      launch_oddeven_split(P64, op.n, half, esite, osite, xfull, xe.p, to.p, 1, st);
       DC_HIP(hipStreamSynchronize(st));   // the scratch vectors are freed at scope end
       xx = xfull;
     }

@@ -74,18 +74,22 @@ struct Variant {
 // belong to; steps past the one where the cycle stopped ran as no-ops (device
 // done flag) and are dropped once the cycle's step count is known.
 struct ApplyProfile {
-  struct Rec { hipEvent_t a, b; int prec; int tag; bool noop; };
+  // passes: algorithmic vector passes of the launch (reads of distinct input
+  // vectors plus output writes, each over the kernel's rows)
+  struct Rec { hipEvent_t a, b; int prec; int tag; bool noop; int passes; };
   bool on = false;
-  int every = 1;                  // time one launch in `every`
-  long seen = 0;                  // launches since enabling
+  int every = 1;                  // time one launch in `every` of each kernel
   int tag = -1;                   // step of the pending cycle (-1: outside a cycle)
   std::vector<hipEvent_t> idle, owned;
   std::vector<Rec> recs;
   // slot = kernel * 3 + precision; kernel 0: full-lattice block kernel,
-  // 1 / 2: the odd-even reduction's D_oe / D_eo stage kernels
+  // 1: the reduced operator's A_o^{-1} D_oe kernel, 2: its A_e - D_eo kernel
   static constexpr int kSlotsP = 9;
+  long seen[kSlotsP] = {};        // launches since enabling
   double ms[kSlotsP] = {}, ms_all[kSlotsP] = {};
   long count[kSlotsP] = {}, count_all[kSlotsP] = {};   // *_all: no-op launches included
+  long passes[kSlotsP] = {};      // vector passes of the counted work launches
+  bool sample(int slot) { return on && (seen[slot]++ % every) == 0; }
   long missed = 0;                // launches not recorded (event cap reached)
   static constexpr size_t kMaxEvents = 16384;
   void reset();
@@ -118,12 +122,11 @@ struct Op {
   } bj[2];
   const BJ& ensure_bj(int sign, hipStream_t st);
   DevBuf gbuf64, gbuf32;
-  // odd-even reduction: site parity, compressed row -> site maps, the reduced
-  // apply's gbuf [V/2][9][n] and odd-site temporary, per vector precision
+  // odd-even reduction: compressed row -> site maps and the odd-row temporary
+  // t_o = A_o^{-1} D_oe x_e, per vector precision
   bool oddeven = false;              // every extent even
-  DevBuf par, esite, osite;
-  DevBuf gbs64, gbs32, ts64, ts32;
-  void* gbuf_s(Prec p);
+  DevBuf esite, osite;
+  DevBuf ts64, ts32;
   void* tmp_s(Prec p);
   DevBuf redpart;           // reducer scratch
   DevBuf scal;              // a few device doubles
@@ -160,7 +163,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
              const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
 int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st);
 void op_profile(Op& op, int every);
-void op_profile_read(Op& op, Prec p, int kernel, long* launches, double* total_ms,
+void op_profile_read(Op& op, Prec p, int kernel, long* launches, double* total_ms, long* passes,
                      long* launches_all, double* total_ms_all);
 int op_solve_multi(const std::vector<Op*>& ops, const SolveOpts& o, int adjoint,
                    const std::vector<int>& R, const std::vector<const void*>& b,

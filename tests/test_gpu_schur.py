@@ -5,6 +5,7 @@ import torch
 
 import synth
 from oracle import operator as dop
+from oracle import poly as opoly
 from oracle import schur
 from oracle.krylov import arnoldi as o_arnoldi
 
@@ -14,7 +15,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("dims,ntv,mu", [((2, 2, 2, 2), 4, 0.0), ((4, 2, 2, 4), 6, 0.2),
-                                         ((4, 4, 4, 4), 24, 0.0)])
+                                         ((4, 4, 4, 4), 24, 0.0), ((2, 4, 2, 2), 32, 0.1),
+                                         ((2, 2, 2, 2), 1, 0.3)])
 def test_reduced_apply_matches_oracle(dims, ntv, mu):
     log("reduced apply", dims, ntv, mu)
     gop, oop = make_pair(dims, ntv, 2.8, mu=mu, store=("f64", "f32", "f16s"))
@@ -124,4 +126,73 @@ def test_reduced_profile_counts_stage_launches(c1):
         n0, _ = gop.profile_apply_read("f64", kernel=0)
         assert rc == 0 and n1 == n2 == st[0]["matvecs"] and ms2 > 0.0
         assert n0 == 1          # the closing FP64 residual check on the full lattice
+    gop.profile_apply(0)
+
+
+def s_flat(oop):
+    ne = oop.V // 2
+    return lambda u: schur.apply(oop, u.reshape(ne, oop.n)).reshape(-1)
+
+
+@pytest.mark.parametrize("d", [2, 5])
+def test_reduced_polynomial_chain(c1, d):
+    """The reduced apply's chain epilogues (first and later steps of q(S))
+    against the oracle's chain on its own S, with its own harmonic Ritz
+    values and Leja order."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, b, xref = c1
+    log("reduced poly chain", d)
+    ne = oop.V // 2
+    v0 = rand_vec(ne, oop.n, 73)
+    opts = Opts(d=d, v0=v0.cuda(), schur=1)
+    th = gop.poly_setup(opts)
+    th_ref, _ = opoly.build_polynomial(s_flat(oop), v0.numpy().reshape(-1), d)
+    assert len(th) == d
+    assert np.max(np.abs(th - th_ref)) <= 1e-8 * np.abs(th_ref).max()
+    x = rand_vec(ne, oop.n, 74)
+    got = gop.poly_apply(x.cuda(), opts).cpu().numpy()
+    want = opoly.q_apply(s_flat(oop), th_ref, x.numpy().reshape(-1)).reshape(ne, oop.n)
+    assert rel(got, want) <= 1e-8
+
+
+def test_reduced_recycle_invariants(c1):
+    """GCRO-DR on S: C^H C = I and C = S q(S) U with the oracle's S."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, b, xref = c1
+    log("reduced recycle invariants")
+    k, d = 6, 3
+    opts = Opts(m=24 + k, k=k, d=d, u=10, seed=3, schur=1)
+    for r in range(2):
+        x, st, rc = gop.solve(synth.rhs(w.dims, w.n_tv, 10 + r).cuda(), 1e-10, opts)
+        assert rc == 0
+    U, Cm = gop.export_recycle(opts)
+    assert U.shape[0] == k and U.shape[1] == oop.V // 2
+    Ch = Cm.cpu().numpy().reshape(k, -1)
+    assert np.allclose(Ch.conj() @ Ch.T, np.eye(k), atol=1e-10)
+    Uq = [gop.poly_apply(U[i], opts).cpu().numpy().reshape(-1) for i in range(k)]
+    SU = np.stack([s_flat(oop)(u) for u in Uq])
+    assert np.max(np.abs(SU - Ch)) <= 1e-8 * np.abs(Ch).max()
+
+
+def test_reduced_profile_vector_passes(c1):
+    """The reduced kernels report their algorithmic vector passes: 2 for the
+    A_o^{-1} D_oe kernel; for the A_e - D_eo kernel 3 when storing, 4 / 5 in
+    the first / later chain steps and 4 for the residual."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, b, xref = c1
+    log("reduced profile passes")
+    gop.profile_apply(1)
+    ne = oop.V // 2
+    x = rand_vec(ne, oop.n, 75).cuda()
+    gop.apply_reduced(x)
+    assert gop.profile_apply_read("f64", kernel=1)[0] == 1
+    assert gop.profile_apply_passes("f64", 1) == 2
+    assert gop.profile_apply_passes("f64", 2) == 3
+    o = Opts(d=4, v0=rand_vec(ne, oop.n, 76).cuda(), schur=1)
+    gop.poly_setup(o)
+    gop.profile_apply(1)
+    gop.poly_apply(x, o)                    # q of degree 3: one first and two later steps
+    assert gop.profile_apply_read("f64", kernel=2)[0] == 3
+    assert gop.profile_apply_passes("f64", 2) == 4 + 5 + 5
+    assert gop.profile_apply_passes("f64", 1) == 2 * 3
     gop.profile_apply(0)
