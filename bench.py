@@ -38,7 +38,7 @@ def parse():
     p.add_argument("--workload", default="c2")
     p.add_argument("--tol", type=float, default=1e-8)
     p.add_argument("--inner", default="f16s", choices=["f32", "f16s"])
-    p.add_argument("--d", type=int, default=16)
+    p.add_argument("--d", type=int, default=24)
     p.add_argument("--k", type=int, default=64)
     p.add_argument("--schur", type=int, default=1, choices=[0, 1],
                    help="solve the odd-even reduced system (1) or the full lattice (0)")
