@@ -90,17 +90,17 @@ def stage1_bytes(V, n, prec):
 
 
 # HBM traffic of one launch of the roofline kernel on the 8^4, N_tv = 24
-# workload with FP16 blocks (kernel 2: the D_eo stage of the odd-even
-# reduction): rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per
-# dispatch, median over the launches that did work), each scaled by the ratio
-# of true bytes to counter reading for a plain 1 GiB elementwise copy
-# (--copy-probe 1024: FETCH_SIZE 524300 KiB for 1 GiB read, WRITE_SIZE
-# 1048576 KiB for 1 GiB written).  Valid only for the apply source it was
-# taken on.
+# workload with FP16 blocks (kernel 2: the reduced operator's A_e - D_eo
+# kernel): rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch,
+# median over the 3439 launches that did work, almost all later chain steps),
+# each scaled by the ratio of true bytes to counter reading for a plain 1 GiB
+# elementwise copy (--copy-probe 1024: FETCH_SIZE 524300 KiB for 1 GiB read,
+# WRITE_SIZE 1048576 KiB for 1 GiB written).  Valid only for the apply source
+# it was taken on.
 TRAFFIC = {"workload": "c2", "prec": "f16s", "kernel": 2,
-           "fetch_kib": 84372.6875, "fetch_scale": 1048576.0 / 524300.0,
-           "write_kib": 6917.59375, "write_scale": 1048576.0 / 1048576.0,
-           "apply_source_sha256": "aa845142f41ba2aee930494f67d760c3736beb9094fd475796ce9ae50fa77352"}
+           "fetch_kib": 85536.4375, "fetch_scale": 1048576.0 / 524300.0,
+           "write_kib": 1536.0, "write_scale": 1048576.0 / 1048576.0,
+           "apply_source_sha256": "5c0bd7055b182519b7fa68ec2d705e971feff8dffbdb3ffb1659f6be9aa48858"}
 
 
 def apply_source_digest():
