@@ -28,6 +28,8 @@ def orthogonalise(w, basis, ortho: str):
     'cgs'  : classical Gram-Schmidt, all coefficients from the same w (Alg. 1).
     'mgs'  : modified Gram-Schmidt, each coefficient from the updated w.
     'cgs2' : classical Gram-Schmidt applied twice, coefficients summed.
+    'ss'   : classical Gram-Schmidt once (the coefficients of the single-sync
+             process; its norm is formed in `arnoldi`).
     """
     h = np.zeros(len(basis), dtype=np.complex128)
     if ortho == "mgs":
@@ -35,7 +37,7 @@ def orthogonalise(w, basis, ortho: str):
             h[i] = dot(w, v)
             w = w - h[i] * v
         return w, h
-    passes = 2 if ortho == "cgs2" else 1
+    passes = 2 if ortho == "cgs2" else 1   # 'cgs' and 'ss': one pass
     for _ in range(passes):
         hp = np.array([dot(w, v) for v in basis], dtype=np.complex128)
         for i, v in enumerate(basis):
@@ -65,7 +67,20 @@ def arnoldi(A, v1, m: int, ortho: str = "mgs", C=None, rhs_norm=None,
     min_steps steps.
     Breakdown: stop when h_{j+1,j} <= breakdown_rel * ||A v_j|| (the exact-zero
     test of Alg. 1 with a rounding threshold).
+
+    ortho='ss' is the single-sync process of Sec. 3.5 without the lag: the
+    coefficients of one classical Gram-Schmidt pass and ||A v_j||^2 come from
+    the same reduction, h_{j+1,j}^2 = ||A v_j||^2 - sum |h|^2 - sum |b|^2
+    (breakdown when that is <= (breakdown_rel ||A v_j||)^2), and the new
+    vector is the orthogonalised one divided by that h.  ortho='p1' runs the
+    latency-1 pipelined process of Alg. 4 / Alg. 5 (pipelined.p1_arnoldi).
     """
+    if ortho == "p1":
+        from .pipelined import p1_arnoldi
+        V, Hb, Bk, steps, brk, _ = p1_arnoldi(A, v1, m, C=C, rhs_norm=rhs_norm,
+                                              est_target=est_target, min_steps=min_steps,
+                                              breakdown_rel=breakdown_rel)
+        return ArnoldiResult(V, Hb, Bk if C is not None else None, steps, brk)
     beta = np.linalg.norm(v1)
     V = [v1 / beta]
     H = np.zeros((m + 1, m), dtype=np.complex128)
@@ -81,7 +96,11 @@ def arnoldi(A, v1, m: int, ortho: str = "mgs", C=None, rhs_norm=None,
             Bk[:, j] = b
         w, h = orthogonalise(w, V, ortho)
         H[:j + 1, j] = h
-        hn = np.linalg.norm(w)
+        if ortho == "ss":
+            t = wnorm0 ** 2 - np.sum(np.abs(h) ** 2) - (np.sum(np.abs(Bk[:, j]) ** 2) if k else 0.0)
+            hn = np.sqrt(t) if t > (breakdown_rel * wnorm0) ** 2 else 0.0
+        else:
+            hn = np.linalg.norm(w)
         H[j + 1, j] = hn
         steps = j + 1
         if hn <= breakdown_rel * wnorm0:
