@@ -45,6 +45,10 @@ def parse():
     p.add_argument("--full-steps", type=int, default=4,
                    help="timed solves of the same method on the full lattice, for comparison")
     p.add_argument("--m", type=int, default=30, help="new Arnoldi vectors per cycle")
+    p.add_argument("--ortho", type=int, default=0, choices=[0, 1],
+                   help="Arnoldi: 0 Gram-Schmidt twice, 1 single-sync (one reduction per step)")
+    p.add_argument("--ss-steps", type=int, default=4,
+                   help="timed solves of the same method with the other --ortho choice")
     p.add_argument("--inner-tol", type=float, default=1e-1)
     p.add_argument("--plain-steps", type=int, default=1)
     p.add_argument("--plain-max-cycles", type=int, default=400,
@@ -262,7 +266,8 @@ def main():
 
     # ------------------------------------------------ method solve (timed)
     opts = Opts(m=a.m + a.k, k=a.k, d=a.d, u=10, prec=a.inner, outer=1, m_outer=10,
-                max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000, schur=a.schur)
+                max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000, schur=a.schur,
+                ortho=a.ortho)
 
     def one_solve(r, o):
         b = synth.rhs(w.dims, w.n_tv, r, device="cuda")
@@ -320,6 +325,24 @@ def main():
                     "matvecs_per_solve": [s["matvecs"] for s in fst],
                     "converged": all(s["status"] == 0 for s in fst)}
         log(f"same method on the full lattice: {a.full_steps / fdt:.2f} solves/s")
+
+    # ------------------------------------------------ same method, single-sync Arnoldi
+    ss_cmp = None
+    if a.ss_steps > 0:
+        so = Opts(m=a.m + a.k, k=a.k, d=a.d, u=10, prec=a.inner, outer=1, m_outer=10,
+                  max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000,
+                  schur=a.schur, ortho=1 - a.ortho)
+        one_solve(0, so)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        sst = [one_solve(r, so)[1] for r in range(a.warmup, a.warmup + a.ss_steps)]
+        torch.cuda.synchronize()
+        sdt = time.perf_counter() - t1
+        ss_cmp = {"ortho": 1 - a.ortho, "solves_per_s": a.ss_steps / sdt, "steps": a.ss_steps,
+                  "matvecs_per_solve": [s["matvecs"] for s in sst],
+                  "iters_per_solve": [s["iters"] for s in sst],
+                  "converged": all(s["status"] == 0 for s in sst)}
+        log(f"same method with ortho={1 - a.ortho}: {a.ss_steps / sdt:.2f} solves/s")
 
     # ------------------------------------------------ FP64 comparisons (one RHS each)
     # GMRES(30) plain, with the polynomial preconditioner (d = 4, 8, 16), and
@@ -407,7 +430,8 @@ def main():
                                f"({w.N} unknowns), mu={w.mu}, m0={w.m0():.6f}",
                    "solver": f"{'odd-even reduced system; ' if a.schur else ''}FGMRES(10) fp64 "
                              f"outer; inner {inner} GCRO-DR(m={a.m + a.k},k={a.k}) + poly "
-                             f"d={a.d}, inner_tol={a.inner_tol}",
+                             f"d={a.d}, inner_tol={a.inner_tol}"
+                             f"{', single-sync Arnoldi' if a.ortho else ''}",
                    "tol": a.tol, "parallelism": "single GPU"},
         "setup_ms": setup_ms,
         "iters_per_solve": [s["iters"] for s in stats],
@@ -416,6 +440,7 @@ def main():
         "err_vs_fp64_last_solve": err_vs_fp64,
         "plain_fp64_gmres30": plain,
         "same_method_full_lattice": full_cmp,
+        "same_method_other_ortho": ss_cmp,
         "fp64_comparison": comp,
         "apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]} for p, r in rates.items()},
         "reduced_apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]}

@@ -101,6 +101,14 @@ typedef struct {
                            polynomial, recycle space and Arnoldi vectors of a
                            reduced variant are even-site compressed [V/2][n]
                            (site x at row x / 2).                               */
+  int32_t ortho;        /* Arnoldi orthogonalisation of the single-RHS solves:
+                           0 classical Gram-Schmidt applied twice; 1 the
+                           single-sync process of Sec. 3.5 (one pass whose
+                           reduction also yields ||A v_j||^2, h_{j+1,j}^2 =
+                           ||A v_j||^2 - sum |h|^2, normalisation fused into
+                           the update; less stable on long cycles, breakdown
+                           when that difference is not positive).  The
+                           batched solves take 0 only.                          */
 } dc_solve_opts;
 
 typedef struct {
@@ -118,7 +126,7 @@ typedef struct {
 
 /* Fill `o` with defaults: m=30, k=0, d=0, u=10, max_cycles=100000,
  * block_jacobi=0, prec=F64, outer=0, m_outer=10, max_outer=50,
- * inner_tol=1e-4, seed=0, v0=NULL, schur=0. */
+ * inner_tol=1e-4, seed=0, v0=NULL, schur=0, ortho=0. */
 int dc_default_opts(dc_solve_opts* o);
 
 /* Build a handle for D_c (Sec. 2.2; twisted mass Sec. 2.1).

@@ -52,6 +52,7 @@ class Opts:
     seed: int = 0
     v0: torch.Tensor | None = field(default=None, repr=False)
     schur: int = 0      # 1: odd-even reduced system (even extents only)
+    ortho: int = 0      # 1: single-sync Arnoldi (one reduction per step)
 
     def to_c(self) -> _lib.SolveOpts:
         o = _lib.SolveOpts()
@@ -61,6 +62,7 @@ class Opts:
         o.outer, o.m_outer, o.max_outer = self.outer, self.m_outer, self.max_outer
         o.inner_tol, o.seed = float(self.inner_tol), int(self.seed)
         o.schur = int(self.schur)
+        o.ortho = int(self.ortho)
         if self.v0 is not None:
             assert self.v0.dtype == torch.complex128 and self.v0.is_cuda
             o.v0 = self.v0.data_ptr()

@@ -33,7 +33,7 @@ class SolveOpts(C.Structure):
                 ("max_cycles", C.c_int32), ("block_jacobi", C.c_int32), ("prec", C.c_int32),
                 ("outer", C.c_int32), ("m_outer", C.c_int32), ("max_outer", C.c_int32),
                 ("inner_tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p),
-                ("schur", C.c_int32)]
+                ("schur", C.c_int32), ("ortho", C.c_int32)]
 
 
 class SolveStats(C.Structure):

@@ -61,6 +61,8 @@ dc::SolveOpts convert(const dc_solve_opts* o) {
   s.v0 = o->v0;
   if (o->schur != 0 && o->schur != 1) throw dc::InvalidArg("schur must be 0 or 1");
   s.schur = o->schur;
+  if (o->ortho != 0 && o->ortho != 1) throw dc::InvalidArg("ortho must be 0 or 1");
+  s.ortho = o->ortho;
   return s;
 }
 
@@ -102,6 +104,7 @@ int dc_default_opts(dc_solve_opts* o) {
   o->seed = 0;
   o->v0 = nullptr;
   o->schur = 0;
+  o->ortho = 0;
   return DC_OK;
 }
 

@@ -1467,14 +1467,24 @@ __global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0,
   }
 }
 
+// out = (w - sum_q coef_q basis_q) (times *scale when scale is given; then the
+// launch belongs to Arnoldi step j and runs only if that step's bookkeeping
+// ran, *jdone == j + 1, instead of checking the stop flag).  out may be w.
 template <typename VR>
-__global__ __launch_bounds__(256) void k_multiaxpy(cx<VR>* __restrict__ w,
+__global__ __launch_bounds__(256) void k_multiaxpy(const cx<VR>* w, cx<VR>* out,
                                                    const cx<VR>* __restrict__ b0, int q0,
                                                    const cx<VR>* __restrict__ b1, int q1,
                                                    size_t N, const double* __restrict__ coef,
                                                    int want_norm, Reducer red,
-                                                   const int* __restrict__ done) {
-  if (done && *done) return;
+                                                   const int* __restrict__ done,
+                                                   const double* __restrict__ scale,
+                                                   const int* __restrict__ jdone, int j) {
+  if (scale) {
+    if (*jdone != j + 1) return;
+  } else if (done && *done) {
+    return;
+  }
+  const double sc = scale ? *scale : 1.0;
   const int Q = q0 + q1;
   double nacc[1] = {0.0};
   const size_t chunk = size_t(blockDim.x) * kDotE;
@@ -1515,8 +1525,8 @@ __global__ __launch_bounds__(256) void k_multiaxpy(cx<VR>* __restrict__ w,
 #pragma unroll
     for (int e = 0; e < kDotE; ++e) {
       if (base + size_t(e) * blockDim.x < N) {
-        const cx<VR> o = mk(VR(sr[e]), VR(si[e]));
-        w[idx[e]] = o;
+        const cx<VR> o = mk(VR(sr[e] * sc), VR(si[e] * sc));
+        out[idx[e]] = o;
         nacc[0] += double(o.re) * double(o.re) + double(o.im) * double(o.im);
       }
     }
@@ -1736,6 +1746,9 @@ constexpr int kFinishLds = 512;  // Hessenberg column length staged in LDS
 // One workgroup of 64 lanes: the lanes combine the two Gram-Schmidt passes'
 // coefficients in parallel and stage the new column and the stored rotations in
 // LDS; lane 0 then runs the (inherently serial) Givens update from LDS.
+// Single-sync process (c2 null, Sec. 3.5): the coefficients come from one pass
+// and h_{j+1,j}^2 = ||A v_j||^2 - sum |coefficients|^2 (nrm2 unused); a value
+// at or below (brk ||A v_j||)^2 is a breakdown.
 __global__ __launch_bounds__(64) void k_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j,
                                                        const double* c1, const double* c2,
                                                        const double* nrm2, double target,
@@ -1747,13 +1760,19 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(ArnoldiDev a, int steps, 
   double* g = a.giv;
   double* cs = a.giv + 2 * (a.ldh + 1);
   double* sn = cs + 2 * a.ldh;
+  const bool ss = (c2 == nullptr);
+  double sq = 0.0;   // single-sync: this lane's share of sum |coefficients|^2
   for (int i = threadIdx.x; i < kC; i += 64) {
-    a.Bk[2 * (size_t(j) * a.ldb + i)] = c1[2 * i] + c2[2 * i];
-    a.Bk[2 * (size_t(j) * a.ldb + i) + 1] = c1[2 * i + 1] + c2[2 * i + 1];
+    const double br = c1[2 * i] + (ss ? 0.0 : c2[2 * i]);
+    const double bi = c1[2 * i + 1] + (ss ? 0.0 : c2[2 * i + 1]);
+    a.Bk[2 * (size_t(j) * a.ldb + i)] = br;
+    a.Bk[2 * (size_t(j) * a.ldb + i) + 1] = bi;
+    sq += br * br + bi * bi;
   }
   for (int i = threadIdx.x; i <= j; i += 64) {
-    const double hr = c1[2 * (kC + i)] + c2[2 * (kC + i)];
-    const double hi = c1[2 * (kC + i) + 1] + c2[2 * (kC + i) + 1];
+    const double hr = c1[2 * (kC + i)] + (ss ? 0.0 : c2[2 * (kC + i)]);
+    const double hi = c1[2 * (kC + i) + 1] + (ss ? 0.0 : c2[2 * (kC + i) + 1]);
+    sq += hr * hr + hi * hi;
     Hc[2 * i] = hr;
     Hc[2 * i + 1] = hi;
     if (staged) {
@@ -1767,12 +1786,23 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(ArnoldiDev a, int steps, 
       snl[2 * i] = sn[2 * i];
       snl[2 * i + 1] = sn[2 * i + 1];
     }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) sq += shfl_xor(sq, o);
   __syncthreads();
   if (threadIdx.x != 0) return;
   const double* hsrc = staged ? hcol : Hc;
-  const double wn0 = sqrt(fmax(c1[2 * (kC + j + 1)], 0.0));  // ||A v_j|| before orthogonalisation
-  const double h = sqrt(fmax(*nrm2, 0.0));
-  const bool breakdown = !(h > brk * wn0);
+  const double wn2 = c1[2 * (kC + j + 1)];   // ||A v_j||^2 before orthogonalisation
+  const double wn0 = sqrt(fmax(wn2, 0.0));
+  double h;
+  bool breakdown;
+  if (ss) {
+    const double t = wn2 - sq;
+    breakdown = !(t > brk * brk * wn2);
+    h = breakdown ? 0.0 : sqrt(t);
+  } else {
+    h = sqrt(fmax(*nrm2, 0.0));
+    breakdown = !(h > brk * wn0);
+  }
   const double hh = breakdown ? 0.0 : h;
   Hc[2 * (j + 1)] = hh;
   Hc[2 * (j + 1) + 1] = 0.0;
@@ -2403,15 +2433,36 @@ void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, i
   if (nb < 1) nb = 1;
   const dim3 grid{static_cast<unsigned>(nb)}, block{256};
   if (p == P64)
-    hipLaunchKernelGGL(k_multiaxpy<double>, grid, block, 0, st, static_cast<z64*>(w),
-                       static_cast<const z64*>(b0), q0, static_cast<const z64*>(b1), q1, N, coef,
-                       want_norm, red, done);
+    hipLaunchKernelGGL(k_multiaxpy<double>, grid, block, 0, st, static_cast<const z64*>(w),
+                       static_cast<z64*>(w), static_cast<const z64*>(b0), q0,
+                       static_cast<const z64*>(b1), q1, N, coef, want_norm, red, done, nullptr,
+                       nullptr, 0);
   else
-    hipLaunchKernelGGL(k_multiaxpy<float>, grid, block, 0, st, static_cast<z32*>(w),
-                       static_cast<const z32*>(b0), q0, static_cast<const z32*>(b1), q1, N, coef,
-                       want_norm, red, done);
+    hipLaunchKernelGGL(k_multiaxpy<float>, grid, block, 0, st, static_cast<const z32*>(w),
+                       static_cast<z32*>(w), static_cast<const z32*>(b0), q0,
+                       static_cast<const z32*>(b1), q1, N, coef, want_norm, red, done, nullptr,
+                       nullptr, 0);
   DC_HIP(hipGetLastError());
   if (want_norm) finalize(red.partials, 1, int(nb), result, done, st);
+}
+
+void launch_multiaxpy_scaled(Prec p, void* w, const void* b0, int q0, const void* b1, int q1,
+                             size_t N, const double* coef, const double* scale, const int* jdone,
+                             int j, hipStream_t st) {
+  size_t nb = (N + 256 * kDotE - 1) / (256 * kDotE);
+  if (nb > 2048) nb = 2048;
+  if (nb < 1) nb = 1;
+  const dim3 grid{static_cast<unsigned>(nb)}, block{256};
+  const Reducer none{};
+  if (p == P64)
+    hipLaunchKernelGGL(k_multiaxpy<double>, grid, block, 0, st, static_cast<const z64*>(w),
+                       static_cast<z64*>(w), static_cast<const z64*>(b0), q0,
+                       static_cast<const z64*>(b1), q1, N, coef, 0, none, nullptr, scale, jdone, j);
+  else
+    hipLaunchKernelGGL(k_multiaxpy<float>, grid, block, 0, st, static_cast<const z32*>(w),
+                       static_cast<z32*>(w), static_cast<const z32*>(b0), q0,
+                       static_cast<const z32*>(b1), q1, N, coef, 0, none, nullptr, scale, jdone, j);
+  DC_HIP(hipGetLastError());
 }
 
 void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,

@@ -146,6 +146,11 @@ void launch_multidot(Prec p, const void* b0, int q0, const void* b1, int q1, siz
 void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, int q1,
                       size_t N, const double* coef, int want_norm, Reducer red,
                       double* result, const int* done, hipStream_t st);
+// w = (w - sum_q coef_q basis_q) * (*scale) for Arnoldi step j: runs only if
+// that step's bookkeeping ran (*jdone == j + 1); no norm.
+void launch_multiaxpy_scaled(Prec p, void* w, const void* b0, int q0, const void* b1, int q1,
+                             size_t N, const double* coef, const double* scale, const int* jdone,
+                             int j, hipStream_t st);
 // out_r (= or +=) sum_q coef[r*Q + q] basis_q for r < R, Q = q0 + q1; coef
 // device complex; outputs are R vectors with stride N.
 void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
@@ -194,6 +199,8 @@ struct ArnoldiDev {
   int* brk_flag;    // 1 if the cycle ended by breakdown
   int* hdone = nullptr;  // optional host-mapped copy of the done flag (set to 1 with it)
 };
+// c2 null: the single-sync process (one pass of coefficients c1, whose entry
+// kC + j + 1 is ||A v_j||^2; h_{j+1,j}^2 = ||A v_j||^2 - sum |c1|^2; nrm2 unused).
 void launch_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const double* c1,
                            const double* c2, const double* nrm2, double target, double brk,
                            hipStream_t st);

@@ -207,6 +207,68 @@ ApplyProfile::~ApplyProfile() {
   for (hipEvent_t e : owned) (void)hipEventDestroy(e);
 }
 
+void stream_wait(hipStream_t st) {
+  for (;;) {
+    const hipError_t e = hipStreamQuery(st);
+    if (e == hipSuccess) return;
+    if (e != hipErrorNotReady) DC_HIP(e);
+  }
+}
+
+void HostStage::read(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  const size_t off = (rd_used + 15) & ~size_t(15);
+  if (off + bytes > rd_cap) {
+    wait(st);                    // no read may be in flight while the area is replaced
+    size_t cap = std::max<size_t>(size_t(1) << 16, 2 * rd_cap);
+    while (cap < bytes) cap *= 2;
+    if (rd) DC_HIP(hipHostFree(rd));
+    void* h = nullptr;
+    DC_HIP(hipHostMalloc(&h, cap, hipHostMallocDefault));
+    rd = static_cast<char*>(h);
+    rd_cap = cap;
+    read(dst, src, bytes, st);
+    return;
+  }
+  DC_HIP(hipMemcpyAsync(rd + off, src, bytes, hipMemcpyDeviceToHost, st));
+  pending.push_back({dst, off, bytes});
+  rd_used = off + bytes;
+}
+
+void HostStage::wait(hipStream_t st) {
+  stream_wait(st);
+  for (const Pending& q : pending) std::memcpy(q.dst, rd + q.off, q.bytes);
+  pending.clear();
+  rd_used = 0;
+}
+
+void HostStage::write(void* dst, const void* src, size_t bytes, hipStream_t st) {
+  if (bytes > kSlotBytes) {      // large uploads (rare): through the read path's wait
+    DC_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+    wait(st);
+    return;
+  }
+  if (!up) {
+    void* h = nullptr;
+    DC_HIP(hipHostMalloc(&h, kSlots * kSlotBytes, hipHostMallocDefault));
+    up = static_cast<char*>(h);
+    for (auto& e : ev) DC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
+  const int s = next;
+  next = (next + 1) % kSlots;
+  if (ev_live[s]) DC_HIP(hipEventSynchronize(ev[s]));   // its previous copy has run
+  std::memcpy(up + size_t(s) * kSlotBytes, src, bytes);
+  DC_HIP(hipMemcpyAsync(dst, up + size_t(s) * kSlotBytes, bytes, hipMemcpyHostToDevice, st));
+  DC_HIP(hipEventRecord(ev[s], st));
+  ev_live[s] = true;
+}
+
+HostStage::~HostStage() {
+  for (auto& e : ev)
+    if (e) (void)hipEventDestroy(e);
+  if (rd) (void)hipHostFree(rd);
+  if (up) (void)hipHostFree(up);
+}
+
 void CycleSignal::ensure() {
   if (host) return;
   void* h = nullptr;
@@ -341,8 +403,8 @@ const Op::BJ& Op::ensure_bj(int sign, hipStream_t st) {
                        (store & 4) ? b.b16.p : nullptr, (store & 4) ? b.sc16.as<float>() : nullptr,
                        flag, st);
   int h = 0;
-  DC_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, st));
-  DC_HIP(hipStreamSynchronize(st));
+  hs.read(&h, flag, sizeof(int), st);
+  hs.wait(st);
   if (h) throw BadState("a self block is singular: block-Jacobi preconditioning is not defined");
   b.version = version;
   return b;
@@ -407,18 +469,42 @@ void op_apply_multi(Op& op, Prec p, int adjoint, int R, const void* in, void* ou
     h[R + r] = static_cast<char*>(out) + size_t(r) * vb;
   }
   op.ptrs.ensure(h.size() * sizeof(void*));
-  DC_HIP(hipMemcpyAsync(op.ptrs.p, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice, st));
+  op.hs.write(op.ptrs.p, h.data(), h.size() * sizeof(void*), st);
   void** table = op.ptrs.as<void*>();
   const void* const* xin = const_cast<const void* const*>(table);
   void* const* yout = table + R;
   launch_apply_multi(p, op.n, op.V, op.blocks(p), op.scales(p), xin, yout, R, op.nbr.as<int>(),
                      adjoint ? -op.mu : op.mu, adjoint ? 3 : 0, st);
-  DC_HIP(hipStreamSynchronize(st));  // the host pointer table must outlive the copy
 }
 
 // ============================================================================ Krylov
 
 namespace {
+
+
+// min || beta e_{k+1} - G y || for the GCRO-DR matrix G = [[D_k, B_k], [0, Hbar]]
+// (D_k = diag(1 / unorm)): the first k rows are met exactly by
+// y_1 = -D_k^{-1} B_k y_2, so only the (j+1) x j Hessenberg part is a least-
+// squares problem.  O(j^2 + k j) instead of a dense QR of the whole G.
+static std::vector<cd> gcrodr_lstsq(const Mat& Hbar, const Mat& Bk,
+                                    const std::vector<double>& unorm, double beta, double* res) {
+  const int k = Bk.r, j = Hbar.c;
+  std::vector<cd> y(size_t(k) + j, cd(0.0));
+  if (j == 0) {
+    if (res) *res = beta;
+    return y;
+  }
+  std::vector<cd> e1(j + 1, cd(0.0));
+  e1[0] = beta;
+  const auto y2 = lstsq(Hbar, e1, res);
+  for (int i = 0; i < k; ++i) {
+    cd acc(0.0);
+    for (int q = 0; q < j; ++q) acc += Bk(i, q) * y2[q];
+    y[i] = -acc * unorm[i];
+  }
+  for (int q = 0; q < j; ++q) y[size_t(k) + q] = y2[q];
+  return y;
+}
 
 template <typename VR>
 struct Krylov {
@@ -618,16 +704,16 @@ struct Krylov {
     }
     ++matvecs;
     double h;
-    DC_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
-    DC_HIP(hipStreamSynchronize(st));
+    op.hs.read(&h, nrm, sizeof(double), st);
+    op.hs.wait(st);
     return std::sqrt(std::max(h, 0.0));
   }
 
   double norm(const Z* x) {
     launch_norm2(p, x, N, op.red(), nrm, st);
     double h;
-    DC_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
-    DC_HIP(hipStreamSynchronize(st));
+    op.hs.read(&h, nrm, sizeof(double), st);
+    op.hs.wait(st);
     return std::sqrt(std::max(h, 0.0));
   }
 
@@ -636,6 +722,15 @@ struct Krylov {
   void orth_step(int j, int kC, int steps, double target) {
     Z* w = V(j + 1);
     const Z* Cb = kC ? Cv() : nullptr;
+    if (o.ortho == 1) {
+      // single-sync process (Sec. 3.5): one reduction yields the coefficients
+      // and ||A v_j||^2, h_{j+1,j} follows from their difference, and the
+      // update and normalisation are one pass
+      launch_multidot(p, Cb, kC, V(0), j + 1, N, w, 1, op.red(), res1, ad.done, st);
+      launch_arnoldi_finish(ad, steps, kC, j, res1, nullptr, nullptr, target, brk, st);
+      launch_multiaxpy_scaled(p, w, Cb, kC, V(0), j + 1, N, res1, ad.inv_h, ad.jdone, j, st);
+      return;
+    }
     launch_multidot(p, Cb, kC, V(0), j + 1, N, w, 1, op.red(), res1, ad.done, st);
     launch_multiaxpy(p, w, Cb, kC, V(0), j + 1, N, res1, 0, op.red(), nrm, ad.done, st);
     launch_multidot(p, Cb, kC, V(0), j + 1, N, w, 0, op.red(), res2, ad.done, st);
@@ -687,14 +782,14 @@ struct Krylov {
     op.prof.tag = -1;
     CycleOut c;
     int flags[3];
-    DC_HIP(hipMemcpyAsync(flags, ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+    op.hs.read(flags, ad.done, 3 * sizeof(int), st);
     double est;
-    DC_HIP(hipMemcpyAsync(&est, ad.est, sizeof(double), hipMemcpyDeviceToHost, st));
+    op.hs.read(&est, ad.est, sizeof(double), st);
     std::vector<double> Hh(2 * size_t(ldh) * ldh);
-    DC_HIP(hipMemcpyAsync(Hh.data(), ad.H, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    op.hs.read(Hh.data(), ad.H, Hh.size() * sizeof(double), st);
     std::vector<double> Bh(2 * size_t(ad.ldb) * ldh);
-    if (kC) DC_HIP(hipMemcpyAsync(Bh.data(), ad.Bk, Bh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    DC_HIP(hipStreamSynchronize(st));
+    if (kC) op.hs.read(Bh.data(), ad.Bk, Bh.size() * sizeof(double), st);
+    op.hs.wait(st);
     c.jd = flags[1];
     c.breakdown = flags[2] != 0;
     op.prof.end_cycle(c.jd);
@@ -718,9 +813,7 @@ struct Krylov {
       h[2 * i] = c[i].real();
       h[2 * i + 1] = c[i].imag();
     }
-    DC_HIP(hipMemcpyAsync(coef, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice, st));
-    // the host vector must stay alive until the copy has run
-    DC_HIP(hipStreamSynchronize(st));
+    op.hs.write(coef, h.data(), h.size() * sizeof(double), st);
   }
 
   // x += q(A~) (sum_q c_q basis_q)
@@ -746,9 +839,8 @@ struct Krylov {
     var.unorm.assign(var.kcur, 1.0);
     if (var.kcur == 0) return;
     launch_colnorm2(p, Uv(), var.kcur, N, op.red(), res1, st);  // res1 holds >= kmax doubles
-    DC_HIP(hipMemcpyAsync(var.unorm.data(), res1, sizeof(double) * size_t(var.kcur),
-                          hipMemcpyDeviceToHost, st));
-    DC_HIP(hipStreamSynchronize(st));
+    op.hs.read(var.unorm.data(), res1, sizeof(double) * size_t(var.kcur), st);
+    op.hs.wait(st);
     for (double& u : var.unorm) u = std::sqrt(std::max(u, 0.0));
   }
 
@@ -805,7 +897,9 @@ struct Krylov {
     }
     const int k = kmax;
     const int m = o.m;
-    double rn = true_resid(x, b, rtrue);
+    double rn = bn;                  // x = 0: the residual is b itself
+    if (use_x0) rn = true_resid(x, b, rtrue);
+    else DC_HIP(hipMemcpyAsync(rtrue, b, N * sizeof(Z), hipMemcpyDeviceToDevice, st));
     relres = rn / bn;
     if (relres <= tol) {
       stt.matvecs += int(matvecs - mv0);
@@ -896,10 +990,8 @@ struct Krylov {
         for (int i = 0; i < kk; ++i) G(i, kk + jj) = c.Bk(i, jj);
         for (int i = 0; i <= jj + 1; ++i) G(kk + i, kk + jj) = c.H(i, jj);
       }
-      std::vector<cd> rhs(kk + jd + 1, cd(0.0));
-      rhs[kk] = beta;
       double lsres;
-      const auto y = lstsq(G, rhs, &lsres);
+      const auto y = gcrodr_lstsq(c.H, c.Bk, var.unorm, beta, &lsres);
       stt.rel_res_est = lsres / bn;
       // x += q(A~) Vhat y, Vhat = [U D_k, V_jd]
       std::vector<cd> cy(kk + jd);
@@ -915,8 +1007,8 @@ struct Krylov {
       upload_coef(gy);
       launch_multiaxpy(p, rhat, Cv(), kk, V(0), jd + 1, N, coef, 1, op.red(), nrm, nullptr, st);
       double h;
-      DC_HIP(hipMemcpyAsync(&h, nrm, sizeof(double), hipMemcpyDeviceToHost, st));
-      DC_HIP(hipStreamSynchronize(st));
+      op.hs.read(&h, nrm, sizeof(double), st);
+      op.hs.wait(st);
       beta = std::sqrt(std::max(h, 0.0));
       if (var.updates < o.u && jd > 0) refresh_recycle(c, G);
       if (jd == 0) break;
@@ -937,8 +1029,8 @@ struct Krylov {
       launch_multidot(p, Cv(), kk, V(0), jd + 1, N, Uv() + size_t(i) * N, 0, op.red(), res1,
                       nullptr, st);
       std::vector<double> h(2 * size_t(nr));
-      DC_HIP(hipMemcpyAsync(h.data(), res1, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-      DC_HIP(hipStreamSynchronize(st));
+      op.hs.read(h.data(), res1, h.size() * sizeof(double), st);
+      op.hs.wait(st);
       for (int r = 0; r < nr; ++r) WV(r, i) = cd(h[2 * r], h[2 * r + 1]) / var.unorm[i];
     }
     for (int jj = 0; jj < jd; ++jj) WV(kk + jj, kk + jj) = 1.0;
@@ -979,6 +1071,7 @@ void build_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st) {
   using Z = cx<VR>;
   SolveOpts po = o;
   po.k = 0;
+  po.ortho = 0;   // harmonic Ritz values from the Gram-Schmidt-twice Hessenberg
   Krylov<VR> K(op, var, po, var.ws, var.sm, std::max(o.d, o.m), st);
   var.theta.clear();  // build with A~ itself (no polynomial yet)
   const size_t N = K.N;
@@ -1096,8 +1189,8 @@ static double fp64_relres(Op& op, const z64* x, const z64* b, int adjoint, hipSt
     launch_norm2(P64, op.t64b.p, N, op.red(), d + 1, st);
   }
   double h[2];
-  DC_HIP(hipMemcpyAsync(h, d, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  DC_HIP(hipStreamSynchronize(st));
+  op.hs.read(h, d, 2 * sizeof(double), st);
+  op.hs.wait(st);
   const double bn = std::sqrt(std::max(h[0], 0.0)), rn = std::sqrt(std::max(h[1], 0.0));
   return bn > 0 ? rn / bn : 0.0;
 }
@@ -1147,7 +1240,10 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
     const z64* bfull = bb;
     z64* xfull = xx;
     double tol_r = tol[r];
-    DevBuf be, bo, xe, to;
+    DevBuf& be = op.rbe;
+    DevBuf& bo = op.rbo;
+    DevBuf& xe = op.rxe;
+    DevBuf& to = op.rto;
     const int* esite = op.esite.as<int>();
     const int* osite = op.osite.as<int>();
     const double tm = sign * op.mu;
@@ -1155,10 +1251,10 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
     const z64 z0 = mk(0.0, 0.0);
     if (o.schur) {
       oinv = op.ensure_bj(sign, st).b64.p;
-      be.alloc(N * sizeof(z64));
-      bo.alloc(N * sizeof(z64));
-      xe.alloc(N * sizeof(z64));
-      to.alloc(N * sizeof(z64));
+      be.ensure(N * sizeof(z64));
+      bo.ensure(N * sizeof(z64));
+      xe.ensure(N * sizeof(z64));
+      to.ensure(N * sizeof(z64));
       launch_oddeven_split(P64, op.n, half, esite, osite, const_cast<z64*>(bfull), be.p, bo.p, 0, st);
       if (use_x0) launch_oddeven_split(P64, op.n, half, esite, osite, xfull, xe.p, nullptr, 0, st);
       launch_bj_rows(P64, op.n, half, osite, oinv, nullptr, bo.p, to.p, st);   // A_o^{-1} b_o
@@ -1170,8 +1266,8 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       double nb[2];
       launch_norm2(P64, bfull, Nfull, op.red(), op.scal.as<double>(), st);
       launch_norm2(P64, be.p, N, op.red(), op.scal.as<double>() + 1, st);
-      DC_HIP(hipMemcpyAsync(nb, op.scal.p, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      DC_HIP(hipStreamSynchronize(st));
+      op.hs.read(nb, op.scal.p, 2 * sizeof(double), st);
+      op.hs.wait(st);
       if (nb[1] > 0.0) tol_r = tol[r] * std::sqrt(nb[0] / nb[1]);
       bb = be.as<z64>();
       xx = xe.as<z64>();
@@ -1197,6 +1293,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       oo.k = 0;
       oo.d = 0;
       oo.m = o.m_outer;
+      oo.ortho = 0;   // the FP64 outer loop keeps Gram-Schmidt twice
       Variant& vo = op.variant(P64, sign, 0, -1, o.schur);  // holds the outer workspace
       Krylov<double> KO(op, vo, oo, vo.ws, vo.sm, o.m_outer, st);
       op.zouter.ensure(size_t(o.m_outer) * N * sizeof(z64));
@@ -1225,14 +1322,14 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
           KO.orth_step(j, 0, o.m_outer, tol_r * bn);
           ++outer_done;
           int flags[3];
-          DC_HIP(hipMemcpyAsync(flags, KO.ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
-          DC_HIP(hipStreamSynchronize(st));
+          op.hs.read(flags, KO.ad.done, 3 * sizeof(int), st);
+          op.hs.wait(st);
           jd = flags[1];
           if (flags[0]) break;
         }
         std::vector<double> Hh(2 * size_t(KO.ldh) * KO.ldh);
-        DC_HIP(hipMemcpyAsync(Hh.data(), KO.ad.H, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-        DC_HIP(hipStreamSynchronize(st));
+        op.hs.read(Hh.data(), KO.ad.H, Hh.size() * sizeof(double), st);
+        op.hs.wait(st);
         Mat H(jd + 1, jd);
         for (int jj = 0; jj < jd; ++jj)
           for (int i = 0; i <= jj + 1; ++i)
@@ -1254,7 +1351,6 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
                         op.nbr.as<int>(), osite, nullptr, st);       // A_o^{-1} D_oe x_e
       launch_axpy(P64, mk(-1.0, 0.0), bo.p, to.p, N, st);           // x_o = A_o^{-1} b_o - that
       launch_oddeven_split(P64, op.n, half, esite, osite, xfull, xe.p, to.p, 1, st);
-      DC_HIP(hipStreamSynchronize(st));   // the scratch vectors are freed at scope end
       xx = xfull;
     }
     if (adjoint) launch_gamma5(P64, xx, xr, op.V, op.n, st);
@@ -1373,8 +1469,7 @@ struct Batch {
       }
     }
     tab.ensure(h.size() * sizeof(void*));
-    DC_HIP(hipMemcpyAsync(tab.p, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice, st));
-    DC_HIP(hipStreamSynchronize(st));
+    g[0].op->hs.write(tab.p, h.data(), h.size() * sizeof(void*), st);
     htab = std::move(h);
   }
 
@@ -1486,13 +1581,12 @@ struct Batch {
     for (size_t gi = 0; gi < g.size(); ++gi) {
       Group& gr = g[gi];
       rn[gi].resize(gr.act.size());
-      for (size_t a = 0; a < gr.act.size(); ++a) {
-        DC_HIP(hipMemcpyAsync(&rn[gi][a], gr.K[gr.act[a]]->nrm, sizeof(double),
-                              hipMemcpyDeviceToHost, st));
-        DC_HIP(hipStreamSynchronize(st));
-        rn[gi][a] = std::sqrt(std::max(rn[gi][a], 0.0));
-      }
+      for (size_t a = 0; a < gr.act.size(); ++a)
+        g[0].op->hs.read(&rn[gi][a], gr.K[gr.act[a]]->nrm, sizeof(double), st);
     }
+    g[0].op->hs.wait(st);
+    for (auto& v : rn)
+      for (double& x : v) x = std::sqrt(std::max(x, 0.0));
     return rn;
   }
 
@@ -1612,28 +1706,27 @@ struct Batch {
           const int r = gr.act[a];
           Krylov<VR>& k = *gr.K[r];
           int flags[3];
-          DC_HIP(hipMemcpyAsync(flags, k.ad.done, 3 * sizeof(int), hipMemcpyDeviceToHost, st));
+          HostStage& hst = g[0].op->hs;
+          hst.read(flags, k.ad.done, 3 * sizeof(int), st);
           std::vector<double> Hh(2 * size_t(k.ldh) * k.ldh), Bh(2 * size_t(k.ad.ldb) * k.ldh);
-          DC_HIP(hipMemcpyAsync(Hh.data(), k.ad.H, Hh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-          if (kC) DC_HIP(hipMemcpyAsync(Bh.data(), k.ad.Bk, Bh.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-          DC_HIP(hipStreamSynchronize(st));
+          hst.read(Hh.data(), k.ad.H, Hh.size() * sizeof(double), st);
+          if (kC) hst.read(Bh.data(), k.ad.Bk, Bh.size() * sizeof(double), st);
+          hst.wait(st);
           const int jd = flags[1];
           stt[gi][r].iters += jd;
           stt[gi][r].matvecs += int(matvecs - mv1);
           cycles[gi][r] += 1;
           stt[gi][r].cycles += 1;
-          Mat G(kC + jd + 1, kC + jd);
-          for (int i = 0; i < kC; ++i) G(i, i) = 1.0 / gr.var->unorm[i];
+          // G = [[D_k, B_k], [0, Hbar]] with D_k = diag(1 / unorm)
+          Mat Hb(jd + 1, jd), Bk(kC, jd);
           for (int jj = 0; jj < jd; ++jj) {
             for (int i = 0; i < kC; ++i)
-              G(i, kC + jj) = cd(Bh[2 * (size_t(jj) * k.ad.ldb + i)], Bh[2 * (size_t(jj) * k.ad.ldb + i) + 1]);
+              Bk(i, jj) = cd(Bh[2 * (size_t(jj) * k.ad.ldb + i)], Bh[2 * (size_t(jj) * k.ad.ldb + i) + 1]);
             for (int i = 0; i <= jj + 1; ++i)
-              G(kC + i, kC + jj) = cd(Hh[2 * (size_t(jj) * k.ldh + i)], Hh[2 * (size_t(jj) * k.ldh + i) + 1]);
+              Hb(i, jj) = cd(Hh[2 * (size_t(jj) * k.ldh + i)], Hh[2 * (size_t(jj) * k.ldh + i) + 1]);
           }
-          std::vector<cd> rhs(kC + jd + 1, cd(0.0));
-          rhs[kC] = beta[gi][a];
           double lsres = 0.0;
-          const auto y = lstsq(G, rhs, &lsres);
+          const auto y = gcrodr_lstsq(Hb, Bk, gr.var->unorm, beta[gi][a], &lsres);
           stt[gi][r].rel_res_est = lsres / bn[gi][r];
           std::vector<cd> cy(kC + jd);
           for (int i = 0; i < kC; ++i) cy[i] = y[i] / gr.var->unorm[i];
@@ -1664,6 +1757,7 @@ static int solve_groups(const std::vector<Op*>& ops, const SolveOpts& o, int adj
   if (G == 0) return 0;
   if (o.m < 1 || o.max_cycles < 0) throw InvalidArg("bad solver options");
   if (o.schur) throw InvalidArg("the batched solve works on the full lattice (schur = 0)");
+  if (o.ortho) throw InvalidArg("the batched solve orthogonalises with Gram-Schmidt twice (ortho = 0)");
   for (size_t gi = 0; gi < G; ++gi) {
     if (!ops[gi]) throw InvalidArg("null operator handle");
     check_prec(*ops[gi], o.prec);
@@ -1751,8 +1845,8 @@ static int solve_groups(const std::vector<Op*>& ops, const SolveOpts& o, int adj
       bn[gi].assign(R[gi], 0.0);
       for (int r = 0; r < R[gi]; ++r) {
         launch_norm2(P64, B64[gi] + size_t(r) * N, N, op.red(), op.scal.as<double>(), st);
-        DC_HIP(hipMemcpyAsync(&bn[gi][r], op.scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
-        DC_HIP(hipStreamSynchronize(st));
+        op.hs.read(&bn[gi][r], op.scal.p, sizeof(double), st);
+        op.hs.wait(st);
         bn[gi][r] = std::sqrt(bn[gi][r]);
         if (bn[gi][r] == 0.0) done[gi][r] = 1;
       }
@@ -1776,8 +1870,7 @@ static int solve_groups(const std::vector<Op*>& ops, const SolveOpts& o, int adj
         for (int r : act[gi]) h.push_back(R64[gi] + size_t(r) * N);
       }
       tab.ensure(h.size() * sizeof(void*));
-      DC_HIP(hipMemcpyAsync(tab.p, h.data(), h.size() * sizeof(void*), hipMemcpyHostToDevice, st));
-      DC_HIP(hipStreamSynchronize(st));
+      ops[0]->hs.write(tab.p, h.data(), h.size() * sizeof(void*), st);
       std::vector<MultiOpDesc> d;
       for (size_t gi = 0; gi < G; ++gi) {
         if (act[gi].empty()) continue;
@@ -1806,8 +1899,8 @@ static int solve_groups(const std::vector<Op*>& ops, const SolveOpts& o, int adj
           launch_axpy(P64, mk(1.0, 0.0), B64[gi] + size_t(r) * N, rr, N, st);
           launch_norm2(P64, rr, N, op.red(), op.scal.as<double>(), st);
           double h2;
-          DC_HIP(hipMemcpyAsync(&h2, op.scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
-          DC_HIP(hipStreamSynchronize(st));
+          op.hs.read(&h2, op.scal.p, sizeof(double), st);
+          op.hs.wait(st);
           const double rn = std::sqrt(std::max(h2, 0.0));
           rel[gi][r] = rn / bn[gi][r];
           if (rel[gi][r] <= tl[gi][r] || outer == o.max_outer) {

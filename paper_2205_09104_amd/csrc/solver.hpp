@@ -38,6 +38,7 @@ struct SolveOpts {
   int outer = 0, m_outer = 10, max_outer = 50;
   double inner_tol = 1e-4;
   int schur = 0;   // solve the odd-even reduced system (Sec. 2.2)
+  int ortho = 0;   // 0: CGS applied twice; 1: single-sync process (Sec. 3.5)
   uint64_t seed = 0;
   const void* v0 = nullptr;  // device complex128 [V][n]
 };
@@ -99,6 +100,34 @@ struct ApplyProfile {
   ~ApplyProfile();
 };
 
+// Pinned host staging for the solver's small transfers.  A copy between the
+// device and pageable host memory makes the runtime drain the stream before
+// it issues the copy, so every such read or upload leaves the GPU idle for a
+// host round trip; copies from and to pinned memory queue behind the kernels.
+// Reads are queued (read) and land in their destinations at the next wait();
+// uploads go through a ring of pinned slots, each reused only after the event
+// recorded behind its previous copy has completed.
+struct HostStage {
+  struct Pending { void* dst; size_t off, bytes; };
+  char* rd = nullptr;            // read area
+  size_t rd_cap = 0, rd_used = 0;
+  std::vector<Pending> pending;
+  static constexpr int kSlots = 8;
+  static constexpr size_t kSlotBytes = size_t(1) << 18;
+  char* up = nullptr;            // kSlots upload slots
+  hipEvent_t ev[kSlots] = {};
+  bool ev_live[kSlots] = {};
+  int next = 0;
+  void read(void* dst, const void* src, size_t bytes, hipStream_t st);
+  void wait(hipStream_t st);     // completes the stream's work, then scatters the reads
+  void write(void* dst, const void* src, size_t bytes, hipStream_t st);
+  ~HostStage();
+};
+
+// Waits for the stream by polling it (lower wake-up latency than a blocking
+// wait; the solver's host thread has nothing else to do meanwhile).
+void stream_wait(hipStream_t st);
+
 // Host-mapped stop flag of the pending Arnoldi cycle and two events that
 // pace the host's enqueueing a bounded distance ahead of the device.
 struct CycleSignal {
@@ -127,6 +156,7 @@ struct Op {
   bool oddeven = false;              // every extent even
   DevBuf esite, osite;
   DevBuf ts64, ts32;
+  DevBuf rbe, rbo, rxe, rto;         // FP64 half vectors of the reduced solve's wrapper
   void* tmp_s(Prec p);
   DevBuf redpart;           // reducer scratch
   DevBuf scal;              // a few device doubles
@@ -136,6 +166,7 @@ struct Op {
   DevBuf bx64, bb64, b32, x32, r64;        // batched-solve vectors
   ApplyProfile prof;
   CycleSignal sig;
+  HostStage hs;
   Reducer red() const { return Reducer{redpart.as<double>()}; }
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Variant>> variants;
   size_t N() const { return size_t(V) * n; }
