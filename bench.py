@@ -45,7 +45,7 @@ def parse():
     p.add_argument("--full-steps", type=int, default=4,
                    help="timed solves of the same method on the full lattice, for comparison")
     p.add_argument("--m", type=int, default=30, help="new Arnoldi vectors per cycle")
-    p.add_argument("--ortho", type=int, default=0, choices=[0, 1],
+    p.add_argument("--ortho", type=int, default=1, choices=[0, 1],
                    help="Arnoldi: 0 Gram-Schmidt twice, 1 single-sync (one reduction per step)")
     p.add_argument("--ss-steps", type=int, default=4,
                    help="timed solves of the same method with the other --ortho choice")

@@ -520,6 +520,9 @@ struct Krylov {
   // device workspace (owned by the variant so it persists across calls)
   DevBuf& ws;
   DevBuf& sm;
+  // Zb: z_j = q(A~) v_j of the cycle's steps (flexible-GMRES storage, with a
+  // polynomial and a recycle-capable workspace); MUtmp: q(A~) U during refresh
+  Z *Zb = nullptr, *MUtmp = nullptr;
   Z *Vb = nullptr, *Ctmp = nullptr, *Utmp = nullptr, *prod = nullptr, *ybuf = nullptr,
     *tmp = nullptr, *tmp2 = nullptr, *rhat = nullptr, *rtrue = nullptr, *ta = nullptr, *tb = nullptr;
   double *res1 = nullptr, *res2 = nullptr, *nrm = nullptr, *coef = nullptr, *scal = nullptr;
@@ -561,13 +564,21 @@ struct Krylov {
     nbasis = ldh + 1;
     const size_t vb = N * sizeof(Z);
     const int ktmp = recycle_tmp ? kmax : 0;
-    const size_t nvec = size_t(nbasis) + 2 * size_t(ktmp) + 8;
+    const int nz = (recycle_tmp && o.d > 1) ? nbasis : 0;
+    const int kz = nz ? ktmp : 0;
+    const size_t nvec = size_t(nbasis) + 2 * size_t(ktmp) + size_t(nz) + size_t(kz) + 8;
     ws.ensure(nvec * vb);
     Z* base = ws.as<Z>();
     Vb = base;
     Ctmp = Vb + size_t(nbasis) * N;
     Utmp = Ctmp + size_t(ktmp) * N;
-    prod = Utmp + size_t(ktmp) * N;
+    Z* after = Utmp + size_t(ktmp) * N;
+    if (nz) {
+      Zb = after;
+      MUtmp = Zb + size_t(nz) * N;
+      after = MUtmp + size_t(kz) * N;
+    }
+    prod = after;
     ybuf = prod + N;
     tmp = ybuf + N;
     tmp2 = tmp + N;
@@ -605,6 +616,9 @@ struct Krylov {
   Z* V(int j) const { return Vb + size_t(j) * N; }
   Z* Uv() const { return var.U.as<Z>(); }
   Z* Cv() const { return var.C.as<Z>(); }
+  Z* MUv() const { return var.MU.as<Z>(); }
+  Z* Zj(int j) const { return Zb + size_t(j) * N; }
+  bool zstore() const { return Zb != nullptr && has_poly(); }
 
   // Stage 1 of one full-lattice apply into gb.
   void stage(const Z* in, const int* done) {
@@ -766,7 +780,12 @@ struct Krylov {
     int nchunk = 0, enqueued = 0;
     for (int j = 0; j < steps; ++j) {
       op.prof.tag = j;
-      Ahat(V(j), V(j + 1), ad.done);
+      if (zstore()) {            // keep z_j = q(A~) v_j for the update of x
+        Q(V(j), Zj(j), ad.done);
+        A(Zj(j), V(j + 1), ad.done);
+      } else {
+        Ahat(V(j), V(j + 1), ad.done);
+      }
       orth_step(j, kC, steps, (j + 1 < min_steps) ? -1.0 : target);
       enqueued = j + 1;
       if ((j + 1) % chunk == 0 && j + 1 < steps) {
@@ -833,6 +852,18 @@ struct Krylov {
     const size_t vb = N * sizeof(Z) * size_t(std::max(kmax, 1));
     var.U.ensure(vb);
     var.C.ensure(vb);
+    if (zstore()) var.MU.ensure(vb);
+  }
+
+  // x += q(A~) ([U] c_U + V_jd c_V) after a cycle: from the stored z_j (and
+  // MU = q(A~) U) when available, else by applying q to the combination
+  void update_x(Z* x, int kk, int jd, const std::vector<cd>& c) {
+    if (zstore() && (kk == 0 || var.mu_ok)) {
+      upload_coef(c);
+      launch_combine(p, kk ? MUv() : nullptr, kk, Zj(0), jd, N, coef, 1, x, 1, st);
+      return;
+    }
+    add_preconditioned(x, kk ? Uv() : nullptr, kk, V(0), jd, c);
   }
 
   void refresh_unorm() {
@@ -871,6 +902,9 @@ struct Krylov {
     launch_combine(p, nullptr, 0, V(0), jd + 1, N, coef, kk, Cv(), 0, st);
     upload_coef(cu);
     launch_combine(p, nullptr, 0, V(0), jd, N, coef, kk, Uv(), 0, st);
+    // q(A~) U by the same combination of the z_j
+    if (zstore()) launch_combine(p, nullptr, 0, Zj(0), jd, N, coef, kk, MUv(), 0, st);
+    var.mu_ok = zstore();
     var.kcur = kk;
     var.k_built = kmax;
     var.updates = 1;
@@ -919,6 +953,8 @@ struct Krylov {
       launch_multiaxpy(p, rhat, Cv(), var.kcur, nullptr, 0, N, res1, 1, op.red(), nrm, nullptr, st);
       if (!has_poly()) {
         launch_combine(p, Uv(), var.kcur, nullptr, 0, N, res1, 1, x, 1, st);
+      } else if (zstore() && var.mu_ok) {
+        launch_combine(p, MUv(), var.kcur, nullptr, 0, N, res1, 1, x, 1, st);
       } else {
         launch_combine(p, Uv(), var.kcur, nullptr, 0, N, res1, 1, tmp, 0, st);
         Q(tmp, tmp2, nullptr);
@@ -935,7 +971,7 @@ struct Krylov {
       e1[0] = beta;
       double lsres;
       const auto y = lstsq(c.H, e1, &lsres);
-      add_preconditioned(x, nullptr, 0, V(0), c.jd, y);
+      update_x(x, 0, c.jd, y);
       // rhat = V_{jd+1} (beta e1 - H y)
       std::vector<cd> rr(c.jd + 1);
       const auto Hy = matmul(c.H, [&] { Mat t(c.jd, 1); for (int i = 0; i < c.jd; ++i) t(i, 0) = y[i]; return t; }());
@@ -971,7 +1007,7 @@ struct Krylov {
         double lsres;
         const auto y = lstsq(c.H, e1, &lsres);
         stt.rel_res_est = lsres / bn;
-        add_preconditioned(x, nullptr, 0, V(0), c.jd, y);
+        update_x(x, 0, c.jd, y);
         if (c.jd == 0) break;  // immediate breakdown: nothing more to gain
         continue;
       }
@@ -997,7 +1033,7 @@ struct Krylov {
       std::vector<cd> cy(kk + jd);
       for (int i = 0; i < kk; ++i) cy[i] = y[i] / var.unorm[i];
       for (int i = 0; i < jd; ++i) cy[kk + i] = y[kk + i];
-      add_preconditioned(x, Uv(), kk, V(0), jd, cy);
+      update_x(x, kk, jd, cy);
       // rhat -= What (G y), What = [C, V_{jd+1}]
       Mat ym(kk + jd, 1);
       for (int i = 0; i < kk + jd; ++i) ym(i, 0) = y[i];
@@ -1059,8 +1095,12 @@ struct Krylov {
     launch_combine(p, Cv(), kk, V(0), jd + 1, N, coef, kk, Ctmp, 0, st);
     upload_coef(cu);
     launch_combine(p, Uv(), kk, V(0), jd, N, coef, kk, Utmp, 0, st);
+    const bool mu = zstore() && var.mu_ok;
+    if (mu) launch_combine(p, MUv(), kk, Zj(0), jd, N, coef, kk, MUtmp, 0, st);
     DC_HIP(hipMemcpyAsync(Cv(), Ctmp, size_t(kk) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
     DC_HIP(hipMemcpyAsync(Uv(), Utmp, size_t(kk) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    if (mu) DC_HIP(hipMemcpyAsync(MUv(), MUtmp, size_t(kk) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    var.mu_ok = mu;
     var.updates += 1;
     refresh_unorm();
   }

@@ -67,6 +67,11 @@ struct Variant {
   int updates = 0;
   long recycle_version = -1;
   std::vector<double> unorm;   // ||u_i||
+  // q(A~) U, kept in step with U by the same linear combinations (the single-
+  // RHS solver's recycle updates), so that x += q(A~) U c needs no polynomial
+  // application; mu_ok: MU matches the current U and polynomial
+  DevBuf MU;
+  bool mu_ok = false;
   DevBuf ws, sm;               // Krylov workspace: vectors and small device arrays
 };
 
