@@ -523,6 +523,12 @@ struct Krylov {
   // Zb: z_j = q(A~) v_j of the cycle's steps (flexible-GMRES storage, with a
   // polynomial and a recycle-capable workspace); MUtmp: q(A~) U during refresh
   Z *Zb = nullptr, *MUtmp = nullptr;
+  // orthogonalisation of the next cycle (see use_ortho); ss_off: a single-sync
+  // cycle broke down (||A v||^2 - sum |h|^2 not positive, which loss of
+  // orthogonality can cause as well as an invariant subspace) and the rest of
+  // the solve uses Gram-Schmidt twice, whose breakdown test is reliable
+  int ortho_now = 0;
+  bool ss_off = false;
   Z *Vb = nullptr, *Ctmp = nullptr, *Utmp = nullptr, *prod = nullptr, *ybuf = nullptr,
     *tmp = nullptr, *tmp2 = nullptr, *rhat = nullptr, *rtrue = nullptr, *ta = nullptr, *tb = nullptr;
   double *res1 = nullptr, *res2 = nullptr, *nrm = nullptr, *coef = nullptr, *scal = nullptr;
@@ -543,6 +549,7 @@ struct Krylov {
       : op(op_), var(v), o(o_), p(v.prec), tm(v.sign * op_.mu), st(st_),
         N(v.schur ? op_.N() / 2 : op_.N()), ws(ws_), sm(sm_) {
     brk = (p == P64) ? 1e-14 : 1e-6;
+    ortho_now = o.ortho;   // entry points that run cycles directly (Arnoldi)
     rows = v.schur ? op.V / 2 : op.V;
     if (v.schur) {
       if (!op.oddeven) throw InvalidArg("the odd-even reduction needs every lattice extent even");
@@ -736,7 +743,7 @@ struct Krylov {
   void orth_step(int j, int kC, int steps, double target) {
     Z* w = V(j + 1);
     const Z* Cb = kC ? Cv() : nullptr;
-    if (o.ortho == 1) {
+    if (ortho_now == 1) {
       // single-sync process (Sec. 3.5): one reduction yields the coefficients
       // and ||A v_j||^2, h_{j+1,j} follows from their difference, and the
       // update and normalisation are one pass
@@ -811,6 +818,7 @@ struct Krylov {
     op.hs.wait(st);
     c.jd = flags[1];
     c.breakdown = flags[2] != 0;
+    if (c.breakdown && ortho_now == 1) ss_off = true;
     op.prof.end_cycle(c.jd);
     // steps past the stopping one were enqueued but exited at entry
     matvecs -= long(enqueued - c.jd) * (has_poly() ? long(var.theta.size()) : 1L);
@@ -912,6 +920,31 @@ struct Krylov {
     refresh_unorm();
   }
 
+  // The single-sync process for the next cycle only where its Hessenberg does
+  // not define the recycle space: the construction cycle and the cycles that
+  // still refresh U, C (fewer than u updates) use Gram-Schmidt twice, since
+  // the single-sync basis loses orthogonality over long cycles and a recycle
+  // space built from it would stay inaccurate once frozen.
+  void use_ortho(bool defines_recycle) {
+    ortho_now = (o.ortho == 1 && !ss_off && !defines_recycle) ? 1 : 0;
+  }
+
+  // New right-hand side with a recycle space: x += q(A~) U C^H rhat;
+  // rhat -= C C^H rhat.
+  void deflate_start(Z* x) {
+    launch_multidot(p, Cv(), var.kcur, nullptr, 0, N, rhat, 0, op.red(), res1, nullptr, st);
+    launch_multiaxpy(p, rhat, Cv(), var.kcur, nullptr, 0, N, res1, 1, op.red(), nrm, nullptr, st);
+    if (!has_poly()) {
+      launch_combine(p, Uv(), var.kcur, nullptr, 0, N, res1, 1, x, 1, st);
+    } else if (zstore() && var.mu_ok) {
+      launch_combine(p, MUv(), var.kcur, nullptr, 0, N, res1, 1, x, 1, st);
+    } else {
+      launch_combine(p, Uv(), var.kcur, nullptr, 0, N, res1, 1, tmp, 0, st);
+      Q(tmp, tmp2, nullptr);
+      launch_axpy(p, mk(1.0, 0.0), tmp2, x, N, st);
+    }
+  }
+
   // Solve D x = b to relative true residual tol; b, x device vectors of this
   // precision.  Returns true if converged.
   bool solve(const Z* b, Z* x, double tol, bool use_x0, int max_cycles, SolveStats& stt,
@@ -948,22 +981,12 @@ struct Krylov {
     int cycles = 0;
     bool converged = false;
     if (k > 0 && var.kcur > 0) {
-      // new right-hand side: x += q(A~) U C^H r; r -= C C^H r
-      launch_multidot(p, Cv(), var.kcur, nullptr, 0, N, rhat, 0, op.red(), res1, nullptr, st);
-      launch_multiaxpy(p, rhat, Cv(), var.kcur, nullptr, 0, N, res1, 1, op.red(), nrm, nullptr, st);
-      if (!has_poly()) {
-        launch_combine(p, Uv(), var.kcur, nullptr, 0, N, res1, 1, x, 1, st);
-      } else if (zstore() && var.mu_ok) {
-        launch_combine(p, MUv(), var.kcur, nullptr, 0, N, res1, 1, x, 1, st);
-      } else {
-        launch_combine(p, Uv(), var.kcur, nullptr, 0, N, res1, 1, tmp, 0, st);
-        Q(tmp, tmp2, nullptr);
-        launch_axpy(p, mk(1.0, 0.0), tmp2, x, N, st);
-      }
+      deflate_start(x);
       beta = norm(rhat);
     } else if (k > 0) {
       // construction cycle: GMRES(m) of at least k steps
       const int steps = std::min(m, ldh - 2);
+      use_ortho(true);
       CycleOut c = cycle(rhat, beta, steps, 0, target_abs, k);
       ++cycles;
       stt.iters += c.jd;
@@ -983,6 +1006,8 @@ struct Krylov {
       construct_recycle(c);
       beta = norm(rhat);
     }
+    double best = rn;
+    int stall = 0;
     while (true) {
       rn = true_resid(x, b, rtrue);
       relres = rn / bn;
@@ -991,6 +1016,19 @@ struct Krylov {
         break;
       }
       if (cycles >= max_cycles) break;
+      if (rn < 0.99 * best) {
+        best = rn;
+        stall = 0;
+      } else if (++stall >= 10 && o.ortho == 1 && k > 0 && var.kcur > 0) {
+        // single-sync solves: the recursively updated residual no longer tracks
+        // the true one (loss of orthogonality); restart from the true
+        // residual, deflated, with Gram-Schmidt twice
+        stall = 0;
+        ss_off = true;
+        left_precondition(rtrue, rhat);
+        deflate_start(x);
+        beta = norm(rhat);
+      }
       if (k == 0 || var.kcur == 0) {
         // plain GMRES(m) cycle from the (left-preconditioned) true residual
         const int steps = std::min(m, ldh - 2);
@@ -999,6 +1037,7 @@ struct Krylov {
           left_precondition(rtrue, rhat);
           b0 = norm(rhat);
         }
+        use_ortho(false);
         CycleOut c = cycle(bjinv ? rhat : rtrue, b0, steps, 0, target_abs, 0);
         ++cycles;
         stt.iters += c.jd;
@@ -1015,6 +1054,7 @@ struct Krylov {
       const int kk = var.kcur;
       const int steps = std::min(m - kk, ldh - 2);
       if (steps < 1) throw InvalidArg("GCRO-DR needs m > k");
+      use_ortho(var.updates < o.u);
       CycleOut c = cycle(rhat, beta, steps, kk, target_abs, 0);
       ++cycles;
       stt.iters += c.jd;

@@ -81,3 +81,24 @@ def test_single_sync_rejected_where_unsupported(c1):
         gop.solve_batch(b[None].cuda(), 1e-8, Opts(m=10, ortho=1))
     with pytest.raises(DcError):
         gop.solve(b.cuda(), 1e-8, Opts(m=10, ortho=2))
+
+
+def test_single_sync_recycle_space_from_gram_schmidt_twice(c1):
+    """The recycle space is built and refreshed from Gram-Schmidt-twice cycles
+    even when the solve asks for the single-sync process, so C stays
+    orthonormal and C = A~ q(A~) U holds with the oracle's operator."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, b, xref = c1
+    log("single-sync recycle space")
+    k, d = 40, 6
+    o = Opts(m=30 + k, k=k, d=d, u=3, seed=2, ortho=1)
+    for r in range(3):
+        x, st, rc = gop.solve(synth.rhs(w.dims, w.n_tv, 20 + r).cuda(), 1e-10, o)
+        assert rc == 0, st
+    U, Cm = gop.export_recycle(o)
+    assert U.shape[0] == k
+    Ch = Cm.cpu().numpy().reshape(k, -1)
+    assert np.abs(Ch.conj() @ Ch.T - np.eye(k)).max() <= 1e-10
+    Uq = [gop.poly_apply(U[i], o).cpu().numpy().reshape(-1) for i in range(k)]
+    AU = np.stack([dop.apply(oop, u.reshape(oop.V, oop.n)).reshape(-1) for u in Uq])
+    assert np.abs(AU - Ch).max() <= 1e-8 * np.abs(Ch).max()
