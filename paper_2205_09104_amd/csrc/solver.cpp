@@ -1101,14 +1101,17 @@ struct Krylov {
     const int nr = kk + jd + 1, nc = kk + jd;
     // What^H Vhat = [[C^H U D_k, 0], [V^H U D_k, I]]
     Mat WV(nr, nc);
-    for (int i = 0; i < kk; ++i) {
-      launch_multidot(p, Cv(), kk, V(0), jd + 1, N, Uv() + size_t(i) * N, 0, op.red(), res1,
-                      nullptr, st);
-      std::vector<double> h(2 * size_t(nr));
-      op.hs.read(h.data(), res1, h.size() * sizeof(double), st);
-      op.hs.wait(st);
-      for (int r = 0; r < nr; ++r) WV(r, i) = cd(h[2 * r], h[2 * r + 1]) / var.unorm[i];
-    }
+    op.wvbuf.ensure(size_t(kk) * nr * 2 * sizeof(double));
+    double* wv = op.wvbuf.as<double>();
+    for (int i = 0; i < kk; ++i)   // all columns queued, then one read
+      launch_multidot(p, Cv(), kk, V(0), jd + 1, N, Uv() + size_t(i) * N, 0, op.red(),
+                      wv + size_t(i) * nr * 2, nullptr, st);
+    std::vector<double> h(size_t(kk) * nr * 2);
+    op.hs.read(h.data(), wv, h.size() * sizeof(double), st);
+    op.hs.wait(st);
+    for (int i = 0; i < kk; ++i)
+      for (int r = 0; r < nr; ++r)
+        WV(r, i) = cd(h[(size_t(i) * nr + r) * 2], h[(size_t(i) * nr + r) * 2 + 1]) / var.unorm[i];
     for (int jj = 0; jj < jd; ++jj) WV(kk + jj, kk + jj) = 1.0;
     const Mat GH = adjoint(G);
     Mat Bm = matmul(GH, WV);

@@ -162,6 +162,7 @@ struct Op {
   DevBuf esite, osite;
   DevBuf ts64, ts32;
   DevBuf rbe, rbo, rxe, rto;         // FP64 half vectors of the reduced solve's wrapper
+  DevBuf wvbuf;                      // recycle refresh: What^H U, one column per recycled vector
   void* tmp_s(Prec p);
   DevBuf redpart;           // reducer scratch
   DevBuf scal;              // a few device doubles
