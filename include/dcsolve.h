@@ -236,6 +236,30 @@ int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, i
                        const void* b, void* x, const double* tol, int32_t use_x0, void* stream,
                        dc_solve_stats* stats);
 
+/* Block GMRES over n_rhs right-hand sides with one shared Krylov space (the
+ * batching configuration's block GMRES; solve_coarse_batch keeps a space per
+ * right-hand side).  Each restart cycle builds block Arnoldi vectors from the
+ * block of current residuals of the columns not yet converged (block
+ * classical Gram-Schmidt twice, Cholesky QR twice of each new block), with
+ * the polynomial of opts->d as right preconditioner on every block and the
+ * MFMA multi-right-hand-side apply (dc_apply_multi) as block matvec; every
+ * column takes its minimal-residual correction in the whole block space and
+ * leaves the block when its true residual meets tol[r].  A cycle ends after
+ * opts->m block steps, when all columns' least-squares residuals meet their
+ * targets, or when a new block is rank deficient.  Full lattice, no block
+ * Jacobi, no recycling (schur, block_jacobi must be 0; k is ignored).
+ * opts->prec F64: the block solve in FP64; F32 / F16S: an FP64
+ * iterative-refinement loop (r = b - D x in FP64, block solve of D e = r to
+ * opts->inner_tol per column in the reduced precision, x += e; at most
+ * opts->max_outer times).  b, x: device complex128 [n_rhs][V][n] (x is
+ * overwritten, starting from zero); tol host [n_rhs]; stats host [n_rhs] or
+ * NULL (iters: block steps the column took part in; matvecs: single-vector
+ * applications divided by n_rhs).  Device memory: about (2 m + 7) n_rhs
+ * vectors of the precision.  Returns DC_OK if all converged, else
+ * DC_NOT_CONVERGED; DC_ERR_INVALID for bad options or tolerances. */
+int solve_coarse_block(dc_op_t op, const dc_solve_opts* opts, int32_t n_rhs, const void* b,
+                       void* x, const double* tol, void* stream, dc_solve_stats* stats);
+
 /* Mixed batch of lattices: the batched solve of solve_coarse_batch over
  * n_ops operators at once (every operator with the same n = 2 n_tv and the
  * precision opts->prec stored; no operator twice).  Operator o solves n_rhs[o]

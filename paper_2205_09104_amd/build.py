@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdcsolve.so")
 
-SOURCES = ["kernels.hip", "dense.cpp", "solver.cpp", "capi.cpp"]
+SOURCES = ["kernels.hip", "dense.cpp", "solver.cpp", "block.cpp", "capi.cpp"]
 ARCH = os.environ.get("DCSOLVE_ARCH", "gfx950")
 
 # -packed-fp32-ops: keep hipcc from forming v_pk_*_f32 instructions
@@ -46,7 +46,9 @@ def build(verbose: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    rocm_lib = os.path.join(os.path.dirname(os.path.dirname(_hipcc())), "lib")
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           f"-L{rocm_lib}", "-lrocblas", f"-Wl,-rpath,{rocm_lib}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

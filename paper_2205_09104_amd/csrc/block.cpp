@@ -1,0 +1,586 @@
+// Block GMRES over many right-hand sides of one operator with one shared
+// Krylov space (the batching configuration's block GMRES; the lockstep batched
+// solver keeps one space per right-hand side).  The block matvec is the MFMA
+// multi-right-hand-side apply, the polynomial preconditioner of Sec. 3.3 runs
+// on whole blocks, block Gram-Schmidt (classical, twice) and the Cholesky QR
+// of each new block are tall-skinny complex GEMMs (rocBLAS), and the block
+// Hessenberg matrix is reduced by Householder transformations on the host as
+// it grows, which gives every column's least-squares residual after every
+// block step.  Reduced-precision blocks (FP32, FP16 + scale) run inside an
+// FP64 iterative-refinement loop.
+#include "solver.hpp"
+
+#include <rocblas/rocblas.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <vector>
+
+namespace dc {
+namespace {
+
+void blas_check(rocblas_status s) {
+  if (s != rocblas_status_success) throw BadState("rocBLAS call failed");
+}
+
+rocblas_handle blas_handle(Op& op, hipStream_t st) {
+  if (!op.blas) {
+    rocblas_handle h = nullptr;
+    blas_check(rocblas_create_handle(&h));
+    op.blas = std::shared_ptr<void>(static_cast<void*>(h), [](void* q) {
+      (void)rocblas_destroy_handle(static_cast<rocblas_handle>(q));
+    });
+  }
+  auto h = static_cast<rocblas_handle>(op.blas.get());
+  blas_check(rocblas_set_stream(h, st));
+  return h;
+}
+
+template <typename VR>
+struct Blas;
+template <>
+struct Blas<double> {
+  static void gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n,
+                   int k, cd al, const z64* A, int lda, const z64* B, int ldb, cd be, z64* C,
+                   int ldc) {
+    const rocblas_double_complex a(al.real(), al.imag()), b(be.real(), be.imag());
+    blas_check(rocblas_zgemm(h, ta, tb, m, n, k, &a,
+                             reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                             reinterpret_cast<const rocblas_double_complex*>(B), ldb, &b,
+                             reinterpret_cast<rocblas_double_complex*>(C), ldc));
+  }
+};
+template <>
+struct Blas<float> {
+  static void gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n,
+                   int k, cd al, const z32* A, int lda, const z32* B, int ldb, cd be, z32* C,
+                   int ldc) {
+    const rocblas_float_complex a(float(al.real()), float(al.imag()));
+    const rocblas_float_complex b(float(be.real()), float(be.imag()));
+    blas_check(rocblas_cgemm(h, ta, tb, m, n, k, &a,
+                             reinterpret_cast<const rocblas_float_complex*>(A), lda,
+                             reinterpret_cast<const rocblas_float_complex*>(B), ldb, &b,
+                             reinterpret_cast<rocblas_float_complex*>(C), ldc));
+  }
+};
+
+// Cholesky factor of a Hermitian r x r matrix after diagonal scaling:
+// G = D Gs D with D = diag(sqrt(G_ii)), Gs = L L^H; returns R = L^H D (upper,
+// G = R^H R) or false when a pivot of Gs falls to rel_pivot (a rank-deficient
+// block: its columns span fewer than r directions).
+bool scaled_cholesky(const Mat& G, double rel_pivot, Mat& R) {
+  const int r = G.r;
+  std::vector<double> d(r);
+  for (int i = 0; i < r; ++i) {
+    const double g = G(i, i).real();
+    if (!(g > 0.0)) return false;
+    d[i] = std::sqrt(g);
+  }
+  Mat L(r, r);
+  for (int j = 0; j < r; ++j) {
+    cd s = G(j, j) / (d[j] * d[j]);
+    for (int k = 0; k < j; ++k) s -= L(j, k) * std::conj(L(j, k));
+    if (!(s.real() > rel_pivot)) return false;
+    const double ljj = std::sqrt(s.real());
+    L(j, j) = ljj;
+    for (int i = j + 1; i < r; ++i) {
+      cd t = G(i, j) / (d[i] * d[j]);
+      for (int k = 0; k < j; ++k) t -= L(i, k) * std::conj(L(j, k));
+      L(i, j) = t / ljj;
+    }
+  }
+  R = Mat(r, r);
+  for (int i = 0; i < r; ++i)
+    for (int j = i; j < r; ++j) R(i, j) = std::conj(L(j, i)) * d[j];
+  return true;
+}
+
+// Householder reduction of a (2r x r) block to upper-triangular form:
+// returns Q^H (2r x 2r) with Q^H A = [R; 0]; A is overwritten with [R; 0].
+Mat householder_qh(Mat& A) {
+  const int m = A.r, n = A.c;
+  Mat QH = Mat::eye(m);
+  std::vector<cd> v(m);
+  for (int k = 0; k < n; ++k) {
+    double nx = 0.0;
+    for (int i = k; i < m; ++i) nx += std::norm(A(i, k));
+    nx = std::sqrt(nx);
+    if (nx == 0.0) continue;
+    const cd x0 = A(k, k);
+    const cd ph = (std::abs(x0) > 0.0) ? x0 / std::abs(x0) : cd(1.0);
+    const cd alpha = -ph * nx;
+    for (int i = k; i < m; ++i) v[i] = A(i, k);
+    v[k] -= alpha;
+    double nv = 0.0;
+    for (int i = k; i < m; ++i) nv += std::norm(v[i]);
+    nv = std::sqrt(nv);
+    if (nv == 0.0) continue;
+    for (int i = k; i < m; ++i) v[i] /= nv;
+    // A <- (I - 2 v v^H) A on rows k.., QH likewise
+    for (int j = k; j < n; ++j) {
+      cd s(0.0);
+      for (int i = k; i < m; ++i) s += std::conj(v[i]) * A(i, j);
+      for (int i = k; i < m; ++i) A(i, j) -= 2.0 * v[i] * s;
+    }
+    for (int j = 0; j < m; ++j) {
+      cd s(0.0);
+      for (int i = k; i < m; ++i) s += std::conj(v[i]) * QH(i, j);
+      for (int i = k; i < m; ++i) QH(i, j) -= 2.0 * v[i] * s;
+    }
+    for (int i = k + 1; i < m; ++i) A(i, k) = 0.0;
+  }
+  return QH;
+}
+
+template <typename VR>
+struct BlockGmres {
+  using Z = cx<VR>;
+  Op& op;
+  const Variant& var;
+  const SolveOpts& o;
+  Prec p;
+  hipStream_t st;
+  size_t N;
+  int m, Rmax;
+  rocblas_handle h;
+  Z *V = nullptr, *Zb = nullptr, *W = nullptr, *T1 = nullptr, *TA = nullptr, *PROD = nullptr,
+    *U = nullptr;
+  Z *Hd = nullptr, *Gd = nullptr, *Rd = nullptr, *Yd = nullptr;
+  void** tabs = nullptr;
+  long applies = 0;   // operator applications to single vectors
+
+  // apply_only: just the multi-apply (and its pointer tables), no Krylov workspace
+  BlockGmres(Op& op_, const Variant& v, const SolveOpts& o_, Prec p_, int R, hipStream_t st_,
+             bool apply_only = false)
+      : op(op_), var(v), o(o_), p(p_), st(st_), N(op_.N()), m(std::max(o_.m, 1)), Rmax(R) {
+    h = blas_handle(op, st);
+    const size_t vb = N * sizeof(Z) * size_t(R);
+    const bool poly = has_poly();
+    Op::BlockWS& b = (sizeof(VR) == 8) ? op.bk64 : op.bk32;
+    b.tab.ensure(size_t(8) * R * sizeof(void*));
+    tabs = b.tab.as<void*>();
+    b.small.ensure(std::max<size_t>(size_t(R), 32) * sizeof(double));
+    Gd = b.small.as<Z>();
+    if (apply_only) return;
+    b.V.ensure(vb * size_t(m + 1));
+    if (poly) b.Z.ensure(vb * size_t(m));
+    b.W.ensure(vb);
+    b.T1.ensure(vb);
+    b.TA.ensure(vb);
+    b.PROD.ensure(vb);
+    b.U.ensure(vb);
+    const size_t ns = size_t(m + 1) * R * R + 2 * size_t(R) * R + size_t(m) * R * R;
+    b.small.ensure(ns * sizeof(Z));
+    V = b.V.as<Z>();
+    Zb = poly ? b.Z.as<Z>() : nullptr;
+    W = b.W.as<Z>();
+    T1 = b.T1.as<Z>();
+    TA = b.TA.as<Z>();
+    PROD = b.PROD.as<Z>();
+    U = b.U.as<Z>();
+    Hd = b.small.as<Z>();
+    Gd = Hd + size_t(m + 1) * R * R;
+    Rd = Gd + size_t(R) * R;
+    Yd = Rd + size_t(R) * R;
+  }
+
+  // ||x_a||^2 for r contiguous vectors, read to the host
+  std::vector<double> colnorms(const Z* x, int r) {
+    std::vector<double> out(r);
+    double* d = reinterpret_cast<double*>(Gd);   // >= max(R, 32) doubles
+    for (int c0 = 0; c0 < r; c0 += 32) {
+      const int k = std::min(32, r - c0);
+      launch_colnorm2(p, x + size_t(c0) * N, k, N, op.red(), d, st);
+      op.hs.read(out.data() + c0, d, sizeof(double) * size_t(k), st);
+      op.hs.wait(st);
+    }
+    return out;
+  }
+
+  bool has_poly() const { return var.d > 1 && int(var.theta.size()) > 1; }
+
+  // out[a] = D in[a] for a < r (one multi-right-hand-side launch)
+  void apply(const std::vector<const Z*>& in, const std::vector<Z*>& out) {
+    const int r = int(in.size());
+    std::vector<void*> t(2 * size_t(r));
+    for (int a = 0; a < r; ++a) {
+      t[a] = const_cast<Z*>(in[a]);
+      t[r + a] = out[a];
+    }
+    op.hs.write(tabs, t.data(), t.size() * sizeof(void*), st);
+    MultiOpDesc e{};
+    e.blocks = op.blocks(p);
+    e.scales = op.scales(p);
+    e.nbr = op.nbr.as<int>();
+    e.xin = const_cast<const void* const*>(tabs);
+    e.yout = tabs + r;
+    e.V = op.V;
+    e.R = r;
+    e.tm = op.mu;
+    launch_apply_multi_ops(p, op.n, &e, 1, 0, st);
+    applies += r;
+  }
+  std::vector<const Z*> cols(const Z* base, int r) const {
+    std::vector<const Z*> v(r);
+    for (int a = 0; a < r; ++a) v[a] = base + size_t(a) * N;
+    return v;
+  }
+  std::vector<Z*> cols(Z* base, int r) const {
+    std::vector<Z*> v(r);
+    for (int a = 0; a < r; ++a) v[a] = base + size_t(a) * N;
+    return v;
+  }
+  void apply_block(const Z* in, Z* out, int r) { apply(cols(in, r), cols(out, r)); }
+
+  // out = q(A) in on a block of r vectors (Newton-like chain, d - 1 applies);
+  // the chain updates are elementwise, so the block is one vector of r N entries
+  void Q(const Z* in, Z* out, int r) {
+    auto inv = [](cd t) { const cd q = 1.0 / t; return mk(q.real(), q.imag()); };
+    const auto& th = var.theta;
+    const int d = int(th.size());
+    const size_t L = size_t(r) * N;
+    const void* tt = TA;
+    const void* vv = in;
+    void* pp = PROD;
+    void* yy = out;
+    void** ct = tabs + 2 * size_t(Rmax);   // four one-entry tables after the apply tables
+    void* h4[4] = {const_cast<void*>(tt), const_cast<void*>(vv), pp, yy};
+    op.hs.write(ct, h4, sizeof(h4), st);
+    apply_block(in, TA, r);
+    launch_chain_multi(p, const_cast<const void* const*>(ct), const_cast<const void* const*>(ct + 1),
+                       ct + 2, ct + 3, 1, L, inv(th[0]), inv(th[0]), inv(th[1]), 1, st);
+    for (int i = 2; i < d; ++i) {
+      apply_block(PROD, TA, r);
+      launch_chain_multi(p, const_cast<const void* const*>(ct), nullptr, ct + 2, ct + 3, 1, L,
+                         mk(0.0, 0.0), inv(th[i - 1]), inv(th[i]), 0, st);
+    }
+  }
+
+  void gemm(rocblas_operation ta, rocblas_operation tb, int mm, int nn, int kk, cd al,
+            const Z* A, int lda, const Z* B, int ldb, cd be, Z* C, int ldc) {
+    Blas<VR>::gemm(h, ta, tb, mm, nn, kk, al, A, lda, B, ldb, be, C, ldc);
+  }
+
+  Mat read_mat(const Z* d, int rows, int colsn) {
+    std::vector<Z> hbuf(size_t(rows) * colsn);
+    op.hs.read(hbuf.data(), d, hbuf.size() * sizeof(Z), st);
+    op.hs.wait(st);
+    Mat M(rows, colsn);
+    for (int j = 0; j < colsn; ++j)
+      for (int i = 0; i < rows; ++i) {
+        const Z z = hbuf[size_t(j) * rows + i];
+        M(i, j) = cd(double(z.re), double(z.im));
+      }
+    return M;
+  }
+  void write_mat(Z* d, const Mat& M) {
+    std::vector<Z> hbuf(size_t(M.r) * M.c);
+    for (int j = 0; j < M.c; ++j)
+      for (int i = 0; i < M.r; ++i) {
+        const cd z = M(i, j);
+        hbuf[size_t(j) * M.r + i] = mk(VR(z.real()), VR(z.imag()));
+      }
+    op.hs.write(d, hbuf.data(), hbuf.size() * sizeof(Z), st);
+  }
+
+  // Cholesky QR, twice: dst = src R^{-1} with src = dst R; false on rank deficiency
+  bool cholqr2(Z* src, Z* dst, int r, Mat& Rtot) {
+    const double piv = (sizeof(VR) == 8) ? 1e-24 : 1e-10;
+    Rtot = Mat::eye(r);
+    Z* a = src;
+    Z* b = T1;
+    for (int pass = 0; pass < 2; ++pass) {
+      if (pass == 1) {
+        a = T1;
+        b = dst;
+      }
+      gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, r, r, int(N), 1.0, a,
+           int(N), a, int(N), 0.0, Gd, r);
+      const Mat G = read_mat(Gd, r, r);
+      Mat R;
+      if (!scaled_cholesky(G, piv, R)) return false;
+      write_mat(Rd, tri_inverse(R));
+      gemm(rocblas_operation_none, rocblas_operation_none, int(N), r, r, 1.0, a, int(N), Rd, r,
+           0.0, b, int(N));
+      Rtot = matmul(R, Rtot);
+    }
+    return true;
+  }
+
+  struct Cycle {
+    int steps = 0;
+    Mat Y;          // (steps r) x r coefficients
+    std::vector<double> est;
+  };
+
+  // One cycle from the orthonormal block V_0 (r columns) with R_0 = V_0 S0; the
+  // cycle ends when every column's least-squares residual is at or below its
+  // target, after m steps, or when a new block is rank deficient.
+  Cycle cycle(int r, const Mat& S0, const std::vector<double>& target) {
+    Cycle c;
+    const int nr = r;
+    Mat Rf((m + 1) * nr, m * nr);
+    Mat G((m + 1) * nr, nr);
+    for (int j = 0; j < nr; ++j)
+      for (int i = 0; i < nr; ++i) G(i, j) = S0(i, j);
+    std::vector<Mat> qhs;
+    c.est.assign(nr, 0.0);
+    for (int a = 0; a < nr; ++a) {
+      double s = 0.0;
+      for (int i = 0; i < nr; ++i) s += std::norm(S0(i, a));
+      c.est[a] = std::sqrt(s);
+    }
+    for (int j = 0; j < m; ++j) {
+      Z* Vj = V + size_t(j) * nr * N;
+      const Z* src = Vj;
+      if (has_poly()) {
+        Q(Vj, Zb + size_t(j) * nr * N, nr);
+        src = Zb + size_t(j) * nr * N;
+      }
+      apply_block(src, W, nr);
+      const int q = (j + 1) * nr;
+      Mat hcol(q, nr);
+      for (int pass = 0; pass < 2; ++pass) {
+        gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, q, nr, int(N), 1.0, V,
+             int(N), W, int(N), 0.0, Hd, q);
+        gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, q, -1.0, V, int(N), Hd, q,
+             1.0, W, int(N));
+        const Mat hp = read_mat(Hd, q, nr);
+        for (int b = 0; b < nr; ++b)
+          for (int i = 0; i < q; ++i) hcol(i, b) += hp(i, b);
+      }
+      Mat Hsub;
+      const bool full = cholqr2(W, V + size_t(j + 1) * nr * N, nr, Hsub);
+      // the new block column of Hbar, reduced by the earlier reflections
+      Mat col((j + 2) * nr, nr);
+      for (int b = 0; b < nr; ++b) {
+        for (int i = 0; i < q; ++i) col(i, b) = hcol(i, b);
+        for (int i = 0; i < nr; ++i) col(q + i, b) = full ? Hsub(i, b) : cd(0.0);
+      }
+      for (int i = 0; i < j; ++i) {
+        Mat sub(2 * nr, nr);
+        for (int b = 0; b < nr; ++b)
+          for (int t = 0; t < 2 * nr; ++t) sub(t, b) = col(i * nr + t, b);
+        const Mat rs = matmul(qhs[size_t(i)], sub);
+        for (int b = 0; b < nr; ++b)
+          for (int t = 0; t < 2 * nr; ++t) col(i * nr + t, b) = rs(t, b);
+      }
+      Mat blk(2 * nr, nr);
+      for (int b = 0; b < nr; ++b)
+        for (int t = 0; t < 2 * nr; ++t) blk(t, b) = col(j * nr + t, b);
+      const Mat qh = householder_qh(blk);
+      for (int b = 0; b < nr; ++b) {
+        for (int i = 0; i < j * nr; ++i) Rf(i, j * nr + b) = col(i, b);
+        for (int t = 0; t < nr; ++t) Rf(j * nr + t, j * nr + b) = blk(t, b);
+      }
+      qhs.push_back(qh);
+      {
+        Mat gs(2 * nr, nr);
+        for (int b = 0; b < nr; ++b)
+          for (int t = 0; t < 2 * nr; ++t) gs(t, b) = G(j * nr + t, b);
+        const Mat gr = matmul(qh, gs);
+        for (int b = 0; b < nr; ++b)
+          for (int t = 0; t < 2 * nr; ++t) G(j * nr + t, b) = gr(t, b);
+      }
+      c.steps = j + 1;
+      bool done = true;
+      for (int a = 0; a < nr; ++a) {
+        double s = 0.0;
+        for (int t = 0; t < nr; ++t) s += std::norm(G((j + 1) * nr + t, a));
+        c.est[a] = std::sqrt(s);
+        if (c.est[a] > target[size_t(a)]) done = false;
+      }
+      if (done || !full) break;
+    }
+    // back substitution: Rf(0:s, 0:s) Y = G(0:s, :)
+    const int s = c.steps * nr;
+    c.Y = Mat(s, nr);
+    for (int b = 0; b < nr; ++b)
+      for (int i = s - 1; i >= 0; --i) {
+        cd t = G(i, b);
+        for (int k = i + 1; k < s; ++k) t -= Rf(i, k) * c.Y(k, b);
+        c.Y(i, b) = (std::abs(Rf(i, i)) > 0.0) ? t / Rf(i, i) : cd(0.0);
+      }
+    return c;
+  }
+
+  // Solve D X = B for R columns (this precision) to relative tolerances tol,
+  // X starting at zero; per-column statistics accumulate into stats.
+  void solve(const Z* B, Z* X, int R, const std::vector<double>& tol, int max_cycles,
+             std::vector<SolveStats>& stats, std::vector<double>& rel) {
+    launch_zero(p, X, size_t(R) * N, st);
+    std::vector<double> bn = colnorms(B, R);
+    for (double& x : bn) x = std::sqrt(std::max(x, 0.0));
+    rel.assign(R, 0.0);
+    std::vector<int> act;
+    for (int c = 0; c < R; ++c)
+      if (bn[c] > 0.0) act.push_back(c);
+    bool first = true;
+    bool single = false;   // dependent residual columns: one column per cycle
+    for (int cyc = 0;; ++cyc) {
+      const int r = int(act.size());
+      if (r == 0) break;
+      // residual block of the active columns in V_0
+      if (first) {
+        for (int a = 0; a < r; ++a)
+          DC_HIP(hipMemcpyAsync(V + size_t(a) * N, B + size_t(act[a]) * N, N * sizeof(Z),
+                                hipMemcpyDeviceToDevice, st));
+      } else {
+        std::vector<const Z*> in(r);
+        for (int a = 0; a < r; ++a) in[a] = X + size_t(act[a]) * N;
+        apply(in, cols(V, r));
+        for (int a = 0; a < r; ++a) {
+          Z* v = V + size_t(a) * N;
+          launch_scale(p, v, v, N, nullptr, -1.0, nullptr, st);
+          launch_axpy(p, mk(1.0, 0.0), B + size_t(act[a]) * N, v, N, st);
+        }
+      }
+      first = false;
+      const std::vector<double> rn = colnorms(V, r);
+      std::vector<int> keep;
+      for (int a = 0; a < r; ++a) {
+        const int c = act[a];
+        rel[c] = std::sqrt(std::max(rn[a], 0.0)) / bn[c];
+        if (rel[c] > tol[c] && cyc < max_cycles) keep.push_back(a);
+      }
+      if (keep.empty()) break;
+      // compact the residual block to the columns still active
+      for (size_t t = 0; t < keep.size(); ++t)
+        if (int(t) != keep[t])
+          DC_HIP(hipMemcpyAsync(V + t * N, V + size_t(keep[t]) * N, N * sizeof(Z),
+                                hipMemcpyDeviceToDevice, st));
+      std::vector<int> act2(keep.size());
+      for (size_t t = 0; t < keep.size(); ++t) act2[t] = act[size_t(keep[t])];
+      act = act2;
+      const int nr = single ? 1 : int(act.size());
+      Mat S0;
+      if (!cholqr2(V, V, nr, S0)) {
+        if (nr == 1) break;   // a zero residual column cannot occur here (rel > tol)
+        single = true;        // dependent columns: solve them one at a time
+        continue;
+      }
+      std::vector<double> target(nr);
+      for (int a = 0; a < nr; ++a) target[a] = tol[act[a]] * bn[act[a]];
+      const Cycle c = cycle(nr, S0, target);
+      for (int a = 0; a < nr; ++a) {
+        stats[act[a]].iters += c.steps;
+        stats[act[a]].cycles += 1;
+      }
+      const int s = c.steps * nr;
+      if (s == 0) break;
+      write_mat(Yd, c.Y);
+      gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, s, 1.0,
+           has_poly() ? Zb : V, int(N), Yd, s, 0.0, U, int(N));
+      for (int a = 0; a < nr; ++a)
+        launch_axpy(p, mk(1.0, 0.0), U + size_t(a) * N, X + size_t(act[a]) * N, N, st);
+    }
+  }
+};
+
+}  // namespace
+
+int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, const double* tol,
+                   hipStream_t st, SolveStats* stats) {
+  if (R < 1) throw InvalidArg("n_rhs must be >= 1");
+  if (!b || !x || !tol) throw InvalidArg("null pointer");
+  if (o.schur) throw InvalidArg("the block solver works on the full lattice (schur = 0)");
+  if (o.block_jacobi) throw InvalidArg("the block solver has no block-Jacobi preconditioning");
+  if (o.m < 1 || o.max_cycles < 0) throw InvalidArg("bad solver options");
+  if (o.prec != P64 && (o.max_outer < 1 || !(o.inner_tol > 0.0)))
+    throw InvalidArg("bad outer-loop options");
+  check_prec(op, o.prec);
+  for (int r = 0; r < R; ++r)
+    if (!(tol[r] > 0.0)) throw InvalidArg("tolerances must be positive");
+  const auto t0 = std::chrono::steady_clock::now();
+  std::vector<SolveStats> stt(R);
+  Variant& var = op.variant(o.prec, +1, 0, o.d, 0);
+  const auto ts = std::chrono::steady_clock::now();
+  ensure_poly(op, var, o, st, &stt[0]);
+  const double t_setup = ms_since(ts);
+  const size_t N = op.N();
+  const z64* B64 = static_cast<const z64*>(b);
+  z64* X64 = static_cast<z64*>(x);
+  std::vector<double> tl(tol, tol + R), rel(R, 0.0);
+  long applies = 0;
+  if (o.prec == P64) {
+    BlockGmres<double> K(op, var, o, P64, R, st);
+    K.solve(B64, X64, R, tl, o.max_cycles, stt, rel);
+    applies = K.applies;
+  } else {
+    // FP64 iterative refinement: r = b - D x in FP64, the block solve of
+    // D e = r in the reduced precision to inner_tol, x += e
+    BlockGmres<double> K64(op, var, o, P64, R, st, true);
+    BlockGmres<float> K(op, var, o, o.prec, R, st);
+    op.bk64.R.ensure(N * sizeof(z64) * size_t(R));
+    op.bk32.R.ensure(N * sizeof(z32) * size_t(R));
+    op.bk32.X.ensure(N * sizeof(z32) * size_t(R));
+    z64* Rr = op.bk64.R.as<z64>();
+    z32* Rin = op.bk32.R.as<z32>();
+    z32* E = op.bk32.X.as<z32>();
+    launch_zero(P64, X64, size_t(R) * N, st);
+    std::vector<double> bn = K64.colnorms(B64, R);
+    for (double& v : bn) v = std::sqrt(std::max(v, 0.0));
+    std::vector<int> act;
+    for (int c = 0; c < R; ++c)
+      if (bn[c] > 0.0) act.push_back(c);
+    for (int outer = 0; !act.empty(); ++outer) {
+      const int r = int(act.size());
+      // residuals of the active columns (FP64)
+      std::vector<const z64*> in(r);
+      std::vector<z64*> out(r);
+      for (int a = 0; a < r; ++a) {
+        in[a] = X64 + size_t(act[a]) * N;
+        out[a] = Rr + size_t(a) * N;
+      }
+      K64.apply(in, out);
+      for (int a = 0; a < r; ++a) {
+        launch_scale(P64, out[a], out[a], N, nullptr, -1.0, nullptr, st);
+        launch_axpy(P64, mk(1.0, 0.0), B64 + size_t(act[a]) * N, out[a], N, st);
+      }
+      const std::vector<double> rn = K64.colnorms(Rr, r);
+      std::vector<int> keep;
+      for (int a = 0; a < r; ++a) {
+        const int c = act[a];
+        rel[c] = std::sqrt(std::max(rn[a], 0.0)) / bn[c];
+        if (rel[c] > tl[c] && outer < o.max_outer) keep.push_back(a);
+      }
+      if (keep.empty()) break;
+      const int nr = int(keep.size());
+      for (int t = 0; t < nr; ++t)
+        launch_convert_64to32(Rr + size_t(keep[t]) * N, Rin + size_t(t) * N, N, op.n, 0, st);
+      std::vector<double> itol(nr, o.inner_tol), irel;
+      std::vector<SolveStats> ist(nr);
+      K.solve(Rin, E, nr, itol, o.max_cycles, ist, irel);
+      std::vector<int> act2(nr);
+      for (int t = 0; t < nr; ++t) {
+        const int c = act[size_t(keep[t])];
+        act2[t] = c;
+        stt[c].iters += ist[t].iters;
+        stt[c].cycles += ist[t].cycles;
+        stt[c].outer_iters += 1;
+        // x += e (through the FP64 residual buffer as staging)
+        launch_convert_32to64(E + size_t(t) * N, Rr + size_t(t) * N, N, op.n, 0, st);
+        launch_axpy(P64, mk(1.0, 0.0), Rr + size_t(t) * N, X64 + size_t(c) * N, N, st);
+      }
+      act = act2;
+    }
+    applies = K.applies + K64.applies;
+  }
+  int all_ok = 1;
+  const double t_solve = ms_since(t0);
+  for (int r = 0; r < R; ++r) {
+    SolveStats& s = stt[r];
+    s.rel_res_true = rel[r];
+    s.status = rel[r] <= tl[r] ? 0 : 1;
+    if (s.status) all_ok = 0;
+    s.matvecs = int(applies / R);
+    s.t_setup_ms = t_setup;
+    s.t_solve_ms = t_solve;
+    if (stats) stats[r] = s;
+  }
+  return all_ok ? 0 : 1;
+}
+
+}  // namespace dc

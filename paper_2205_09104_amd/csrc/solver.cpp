@@ -361,7 +361,7 @@ void op_profile_read(Op& op, Prec p, int kernel, long* launches, double* total_m
   if (total_ms_all) *total_ms_all = op.prof.ms_all[i];
 }
 
-static void check_prec(const Op& op, Prec p) {
+void check_prec(const Op& op, Prec p) {
   if (p == P32 && !(op.store & 2)) throw InvalidArg("FP32 blocks were not stored (desc.store)");
   if (p == P16S && !(op.store & 4)) throw InvalidArg("FP16 blocks were not stored (desc.store)");
   if (p != P64 && p != P32 && p != P16S) throw InvalidArg("unknown precision");
@@ -1189,6 +1189,8 @@ void build_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st) {
   (void)sizeof(Z);
 }
 
+}  // namespace
+
 void ensure_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st, SolveStats* stt) {
   if (o.d <= 1) {
     var.theta.clear();
@@ -1203,8 +1205,6 @@ void ensure_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st, Solve
 double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
-
-}  // namespace
 
 int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta) {
   check_prec(op, o.prec);

@@ -1,6 +1,7 @@
 // Coarse operator handle and the Krylov solvers driving the HIP kernels.
 #pragma once
 
+#include <chrono>
 #include <map>
 #include <memory>
 #include <tuple>
@@ -163,6 +164,12 @@ struct Op {
   DevBuf ts64, ts32;
   DevBuf rbe, rbo, rxe, rto;         // FP64 half vectors of the reduced solve's wrapper
   DevBuf wvbuf;                      // recycle refresh: What^H U, one column per recycled vector
+  // block GMRES workspaces (FP64 and reduced-precision vectors) and the
+  // rocBLAS handle of its tall-skinny GEMMs (created on first use)
+  struct BlockWS {
+    DevBuf V, Z, W, T1, TA, PROD, U, small, tab, R, X;
+  } bk64, bk32;
+  std::shared_ptr<void> blas;
   void* tmp_s(Prec p);
   DevBuf redpart;           // reducer scratch
   DevBuf scal;              // a few device doubles
@@ -208,5 +215,12 @@ int op_solve_multi(const std::vector<Op*>& ops, const SolveOpts& o, int adjoint,
                    hipStream_t st, const std::vector<SolveStats*>& stats);
 int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b, void* x,
                    const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
+// block GMRES with one shared Krylov space over R right-hand sides
+int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, const double* tol,
+                   hipStream_t st, SolveStats* stats);
+// shared helpers of the solvers
+void check_prec(const Op& op, Prec p);
+void ensure_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st, SolveStats* stt);
+double ms_since(std::chrono::steady_clock::time_point t0);
 
 }  // namespace dc

@@ -1,0 +1,91 @@
+"""Block GMRES with one shared Krylov space (solve_coarse_block) against the
+oracle's block GMRES and dense LU."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import operator as dop
+from oracle.block import block_gmres
+
+from .helpers import log, make_pair, oracle_relres, rel, workload_pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _rhs(dims, ntv, R, seed0):
+    return torch.stack([synth.rhs(dims, ntv, seed0 + r) for r in range(R)])
+
+
+def test_first_cycle_matches_oracle():
+    """One cycle of m block steps from zero, no early stop: every column is the
+    least-squares minimiser over the same block space as the oracle's."""
+    from paper_2205_09104_amd import Opts
+    log("block gmres one cycle")
+    gop, oop = make_pair((4, 2, 2, 4), 6, 3.0, mu=0.1)
+    R, m = 3, 6
+    B = _rhs(oop.dims, 6, R, 40)
+    X, st, rc = gop.solve_block(B.cuda(), 1e-30, Opts(m=m, max_cycles=1))
+    assert rc != 0 and all(s["iters"] == m for s in st)
+    N = oop.V * oop.n
+    f = lambda v: dop.apply(oop, v.reshape(oop.V, oop.n)).reshape(-1)
+    Bn = B.numpy().reshape(R, N).T
+    Xr, info = block_gmres(f, Bn, [1e-30] * R, m, 1)
+    Xg = X.cpu().numpy().reshape(R, N).T
+    assert rel(Xg, Xr) <= 1e-10
+    for c in range(R):
+        assert abs(st[c]["rel_res_true"] - info["relres"][c]) <= 1e-8 * info["relres"][c]
+
+
+@pytest.fixture(scope="module")
+def c1():
+    gop, oop, w = workload_pair("c1", store=("f64", "f32", "f16s"))
+    D = dop.dense(oop)
+    return gop, oop, w, D
+
+
+@pytest.mark.parametrize("cfg", ["f64", "f64_poly", "f32", "f16s"])
+def test_block_solve_per_column_tolerances(c1, cfg):
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, D = c1
+    log("block gmres solve", cfg)
+    R = 6
+    B = _rhs(w.dims, w.n_tv, R, 50)
+    tols = np.array(synth.tolerances_loguniform(R, 1e-10, 1e-6, seed=3))
+    o = {"f64": Opts(m=20),
+         "f64_poly": Opts(m=12, d=4, seed=1),
+         "f32": Opts(m=12, d=4, seed=1, prec="f32", inner_tol=1e-3, max_outer=40),
+         "f16s": Opts(m=12, d=4, seed=1, prec="f16s", inner_tol=1e-2, max_outer=40)}[cfg]
+    X, st, rc = gop.solve_block(B.cuda(), tols, o)
+    assert rc == 0, st
+    Xh = X.cpu().numpy()
+    for c in range(R):
+        assert st[c]["rel_res_true"] <= tols[c]
+        assert oracle_relres(oop, Xh[c], B[c].numpy()) <= tols[c] * 1.0001
+    xr = np.linalg.solve(D, B[int(np.argmin(tols))].numpy().reshape(-1))
+    assert rel(Xh[int(np.argmin(tols))].reshape(-1), xr) <= 1e-6
+
+
+def test_single_column_is_gmres(c1):
+    """With one right-hand side the block process is GMRES(m): the same number
+    of Arnoldi steps as the single-RHS solver (to a step or two of rounding)."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, D = c1
+    log("block with one column")
+    b = synth.rhs(w.dims, w.n_tv, 60)
+    _, s1, rc1 = gop.solve_block(b[None].cuda(), 1e-9, Opts(m=12, d=4, seed=1))
+    _, sg, rcg = gop.solve(b.cuda(), 1e-9, Opts(m=12, d=4, seed=1))
+    assert rc1 == 0 and rcg == 0
+    assert abs(s1[0]["iters"] - sg[0]["iters"]) <= 2
+
+
+def test_block_solver_rejects_bad_options(c1):
+    from paper_2205_09104_amd import Opts
+    from paper_2205_09104_amd._lib import DcError
+    gop, oop, w, D = c1
+    B = _rhs(w.dims, w.n_tv, 2, 70).cuda()
+    for o in (Opts(m=10, schur=1), Opts(m=10, block_jacobi=1), Opts(m=0)):
+        with pytest.raises(DcError):
+            gop.solve_block(B, 1e-8, o)
+    with pytest.raises(DcError):
+        gop.solve_block(B, [1e-8, 0.0], Opts(m=10))
