@@ -246,8 +246,13 @@ int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, i
  * column takes its minimal-residual correction in the whole block space and
  * leaves the block when its true residual meets tol[r].  A cycle ends after
  * opts->m block steps, when all columns' least-squares residuals meet their
- * targets, or when a new block is rank deficient.  Full lattice, no block
- * Jacobi, no recycling (schur, block_jacobi must be 0; k is ignored).
+ * targets, or when a new block is rank deficient.  If opts->k > 0 and
+ * solve_coarse built a recycle space for the same variant (prec, d, full
+ * lattice), every cycle is deflated against it without refreshing it (Sec.
+ * 3.4): new residual blocks start with x += q(A) U C^H r, r -= C C^H r, the
+ * block Arnoldi runs on (I - C C^H) A, and each column's correction has the
+ * recycled part -q(A) U B_k y.  Full lattice, no block Jacobi (schur,
+ * block_jacobi must be 0).
  * opts->prec F64: the block solve in FP64; F32 / F16S: an FP64
  * iterative-refinement loop (r = b - D x in FP64, block solve of D e = r to
  * opts->inner_tol per column in the reduced precision, x += e; at most

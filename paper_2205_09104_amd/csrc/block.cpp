@@ -148,8 +148,14 @@ struct BlockGmres {
   Z *V = nullptr, *Zb = nullptr, *W = nullptr, *T1 = nullptr, *TA = nullptr, *PROD = nullptr,
     *U = nullptr;
   Z *Hd = nullptr, *Gd = nullptr, *Rd = nullptr, *Yd = nullptr;
+  double* Dd = nullptr;   // complex-double results of the reductions over N
   void** tabs = nullptr;
   long applies = 0;   // operator applications to single vectors
+  // frozen recycle space of the single-RHS solver's variant (GCRO-DR, Sec. 3.4):
+  // the cycles run on (I - C C^H) A; kc = 0 without one
+  int kc = 0;
+  const Z *Cr = nullptr, *Ur = nullptr, *MUr = nullptr;
+  Z* Bd = nullptr;   // device C^H W, kc x r
 
   // apply_only: just the multi-apply (and its pointer tables), no Krylov workspace
   BlockGmres(Op& op_, const Variant& v, const SolveOpts& o_, Prec p_, int R, hipStream_t st_,
@@ -172,7 +178,9 @@ struct BlockGmres {
     b.PROD.ensure(vb);
     b.U.ensure(vb);
     const size_t ns = size_t(m + 1) * R * R + 2 * size_t(R) * R + size_t(m) * R * R;
-    b.small.ensure(ns * sizeof(Z));
+    const int kmax = std::max(o.k, 0);
+    const size_t nd = 2 * std::max(size_t(m + 1) * R * R, size_t(kmax) * R);
+    b.small.ensure(ns * sizeof(Z) + nd * sizeof(double));
     V = b.V.as<Z>();
     Zb = poly ? b.Z.as<Z>() : nullptr;
     W = b.W.as<Z>();
@@ -184,6 +192,31 @@ struct BlockGmres {
     Gd = Hd + size_t(m + 1) * R * R;
     Rd = Gd + size_t(R) * R;
     Yd = Rd + size_t(R) * R;
+    Dd = reinterpret_cast<double*>(Yd + size_t(m) * R * R);
+    if (o.k > 0 && v.kcur > 0 && v.recycle_version == op.version && v.k_built == o.k) {
+      kc = v.kcur;
+      Cr = v.C.as<Z>();
+      Ur = v.U.as<Z>();
+      MUr = (v.mu_ok && poly) ? v.MU.as<Z>() : nullptr;
+      b.Bc.ensure(size_t(kc) * R * sizeof(Z) + size_t(kc) * R * sizeof(Z));
+      Bd = b.Bc.as<Z>();
+    }
+  }
+
+  // X[cols] += q(A) U c for the columns' coefficients c (kc x r, device,
+  // leading dimension kc): through MU = q(A) U when it is kept, else by
+  // applying the polynomial to U c
+  void add_recycled(const Z* cdev, int r, const std::vector<Z*>& xcols) {
+    if (has_poly() && !MUr) {
+      gemm(rocblas_operation_none, rocblas_operation_none, int(N), r, kc, 1.0, Ur, int(N), cdev, kc,
+           0.0, U, int(N));
+      Q(U, W, r);
+      for (int a = 0; a < r; ++a) launch_axpy(p, mk(1.0, 0.0), W + size_t(a) * N, xcols[a], N, st);
+      return;
+    }
+    gemm(rocblas_operation_none, rocblas_operation_none, int(N), r, kc, 1.0, has_poly() ? MUr : Ur,
+         int(N), cdev, kc, 0.0, U, int(N));
+    for (int a = 0; a < r; ++a) launch_axpy(p, mk(1.0, 0.0), U + size_t(a) * N, xcols[a], N, st);
   }
 
   // ||x_a||^2 for r contiguous vectors, read to the host
@@ -263,6 +296,24 @@ struct BlockGmres {
     Blas<VR>::gemm(h, ta, tb, mm, nn, kk, al, A, lda, B, ldb, be, C, ldc);
   }
 
+  // A^H B for qa contiguous vectors A and rb contiguous vectors B, read to the
+  // host: one multidot launch per column of B (grid-wide partial sums, double
+  // accumulation).  A GEMM here has a q x r output and an inner dimension of N,
+  // too few output tiles to spread the reduction over the chip.
+  Mat tn(const Z* A, int qa, const Z* B, int rb) {
+    for (int b = 0; b < rb; ++b)
+      launch_multidot(p, A, qa, nullptr, 0, N, B + size_t(b) * N, 0, op.red(),
+                      Dd + 2 * size_t(qa) * b, nullptr, st);
+    std::vector<double> hbuf(2 * size_t(qa) * rb);
+    op.hs.read(hbuf.data(), Dd, hbuf.size() * sizeof(double), st);
+    op.hs.wait(st);
+    Mat M(qa, rb);
+    for (int b = 0; b < rb; ++b)
+      for (int i = 0; i < qa; ++i)
+        M(i, b) = cd(hbuf[2 * (size_t(b) * qa + i)], hbuf[2 * (size_t(b) * qa + i) + 1]);
+    return M;
+  }
+
   Mat read_mat(const Z* d, int rows, int colsn) {
     std::vector<Z> hbuf(size_t(rows) * colsn);
     op.hs.read(hbuf.data(), d, hbuf.size() * sizeof(Z), st);
@@ -296,9 +347,7 @@ struct BlockGmres {
         a = T1;
         b = dst;
       }
-      gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, r, r, int(N), 1.0, a,
-           int(N), a, int(N), 0.0, Gd, r);
-      const Mat G = read_mat(Gd, r, r);
+      const Mat G = tn(a, r, a, r);
       Mat R;
       if (!scaled_cholesky(G, piv, R)) return false;
       write_mat(Rd, tri_inverse(R));
@@ -312,6 +361,7 @@ struct BlockGmres {
   struct Cycle {
     int steps = 0;
     Mat Y;          // (steps r) x r coefficients
+    Mat Bk;         // kc x (m r): C^H A V of the deflated process
     std::vector<double> est;
   };
 
@@ -321,6 +371,7 @@ struct BlockGmres {
   Cycle cycle(int r, const Mat& S0, const std::vector<double>& target) {
     Cycle c;
     const int nr = r;
+    c.Bk = Mat(std::max(kc, 1), m * nr);
     Mat Rf((m + 1) * nr, m * nr);
     Mat G((m + 1) * nr, nr);
     for (int j = 0; j < nr; ++j)
@@ -343,11 +394,18 @@ struct BlockGmres {
       const int q = (j + 1) * nr;
       Mat hcol(q, nr);
       for (int pass = 0; pass < 2; ++pass) {
-        gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, q, nr, int(N), 1.0, V,
-             int(N), W, int(N), 0.0, Hd, q);
+        if (kc) {   // deflation: W -= C (C^H W), coefficients B_k
+          const Mat bp = tn(Cr, kc, W, nr);
+          write_mat(Bd, bp);
+          gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, kc, -1.0, Cr, int(N), Bd,
+               kc, 1.0, W, int(N));
+          for (int b = 0; b < nr; ++b)
+            for (int i = 0; i < kc; ++i) c.Bk(i, j * nr + b) += bp(i, b);
+        }
+        const Mat hp = tn(V, q, W, nr);
+        write_mat(Hd, hp);
         gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, q, -1.0, V, int(N), Hd, q,
              1.0, W, int(N));
-        const Mat hp = read_mat(Hd, q, nr);
         for (int b = 0; b < nr; ++b)
           for (int i = 0; i < q; ++i) hcol(i, b) += hp(i, b);
       }
@@ -455,6 +513,14 @@ struct BlockGmres {
       for (size_t t = 0; t < keep.size(); ++t) act2[t] = act[size_t(keep[t])];
       act = act2;
       const int nr = single ? 1 : int(act.size());
+      if (kc) {   // new residuals with a recycle space: x += q(A) U C^H r; r -= C C^H r
+        write_mat(Bd, tn(Cr, kc, V, nr));
+        gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, kc, -1.0, Cr, int(N), Bd, kc,
+             1.0, V, int(N));
+        std::vector<Z*> xc(nr);
+        for (int a = 0; a < nr; ++a) xc[a] = X + size_t(act[a]) * N;
+        add_recycled(Bd, nr, xc);
+      }
       Mat S0;
       if (!cholqr2(V, V, nr, S0)) {
         if (nr == 1) break;   // a zero residual column cannot occur here (rel > tol)
@@ -473,8 +539,24 @@ struct BlockGmres {
       write_mat(Yd, c.Y);
       gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, s, 1.0,
            has_poly() ? Zb : V, int(N), Yd, s, 0.0, U, int(N));
-      for (int a = 0; a < nr; ++a)
-        launch_axpy(p, mk(1.0, 0.0), U + size_t(a) * N, X + size_t(act[a]) * N, N, st);
+      std::vector<Z*> xc(nr);
+      for (int a = 0; a < nr; ++a) {
+        xc[a] = X + size_t(act[a]) * N;
+        launch_axpy(p, mk(1.0, 0.0), U + size_t(a) * N, xc[a], N, st);
+      }
+      if (kc) {
+        // the recycled part of the least-squares solution: the rows of C are met
+        // exactly by -B_k y (the block form of the GCRO-DR problem)
+        Mat By(kc, nr);
+        for (int b = 0; b < nr; ++b)
+          for (int i = 0; i < kc; ++i) {
+            cd t(0.0);
+            for (int q2 = 0; q2 < s; ++q2) t += c.Bk(i, q2) * c.Y(q2, b);
+            By(i, b) = -t;
+          }
+        write_mat(Bd, By);
+        add_recycled(Bd, nr, xc);
+      }
     }
   }
 };

@@ -167,7 +167,7 @@ struct Op {
   // block GMRES workspaces (FP64 and reduced-precision vectors) and the
   // rocBLAS handle of its tall-skinny GEMMs (created on first use)
   struct BlockWS {
-    DevBuf V, Z, W, T1, TA, PROD, U, small, tab, R, X;
+    DevBuf V, Z, W, T1, TA, PROD, U, small, tab, R, X, Bc;
   } bk64, bk32;
   std::shared_ptr<void> blas;
   void* tmp_s(Prec p);
