@@ -256,14 +256,17 @@ int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, i
  * opts->prec F64: the block solve in FP64; F32 / F16S: an FP64
  * iterative-refinement loop (r = b - D x in FP64, block solve of D e = r to
  * opts->inner_tol per column in the reduced precision, x += e; at most
- * opts->max_outer times).  b, x: device complex128 [n_rhs][V][n] (x is
- * overwritten, starting from zero); tol host [n_rhs]; stats host [n_rhs] or
+ * opts->max_outer times).  b, x: device complex128 [n_rhs][V][n]; use_x0 = 1
+ * starts from the x passed in (the solve is then D e = b - D x to
+ * tol ||b|| / ||b - D x|| and x += e, so a solve can be continued), else from
+ * zero; tol host [n_rhs]; stats host [n_rhs] or
  * NULL (iters: block steps the column took part in; matvecs: single-vector
  * applications divided by n_rhs).  Device memory: about (2 m + 7) n_rhs
  * vectors of the precision.  Returns DC_OK if all converged, else
  * DC_NOT_CONVERGED; DC_ERR_INVALID for bad options or tolerances. */
 int solve_coarse_block(dc_op_t op, const dc_solve_opts* opts, int32_t n_rhs, const void* b,
-                       void* x, const double* tol, void* stream, dc_solve_stats* stats);
+                       void* x, const double* tol, int32_t use_x0, void* stream,
+                       dc_solve_stats* stats);
 
 /* Mixed batch of lattices: the batched solve of solve_coarse_batch over
  * n_ops operators at once (every operator with the same n = 2 n_tv and the

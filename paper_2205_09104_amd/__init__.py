@@ -231,20 +231,20 @@ class CoarseOp:
                                              int(x0 is not None), _stream_ptr(stream), stats))
         return x, [stats[i].as_dict() for i in range(R)], rc
 
-    def solve_block(self, b: torch.Tensor, tol, opts: Opts | None = None, stream=None):
+    def solve_block(self, b: torch.Tensor, tol, opts: Opts | None = None, x0=None, stream=None):
         """Block GMRES with one shared Krylov space over R systems, b: [R, V, n]
-        complex128; tol scalar or [R]."""
+        complex128; tol scalar or [R]; x0 an optional start ([R, V, n])."""
         opts = opts or Opts()
         bb = b.contiguous()
         R = bb.shape[0]
         assert bb.dtype == torch.complex128 and bb.shape[1:] == (self.V, self.n)
-        x = torch.empty_like(bb)
+        x = x0.clone().contiguous() if x0 is not None else torch.empty_like(bb)
         tols = np.broadcast_to(np.asarray(tol, dtype=np.float64), (R,)).copy()
         stats = (_lib.SolveStats * R)()
         o = opts.to_c()
         rc = check(load().solve_coarse_block(self._h, C.byref(o), R, _ptr(bb), _ptr(x),
                                              tols.ctypes.data_as(C.POINTER(C.c_double)),
-                                             _stream_ptr(stream), stats))
+                                             int(x0 is not None), _stream_ptr(stream), stats))
         return x, [stats[i].as_dict() for i in range(R)], rc
 
     @staticmethod

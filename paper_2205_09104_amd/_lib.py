@@ -76,7 +76,7 @@ SIGNATURES = {
                                      C.c_void_p, C.c_void_p, C.POINTER(C.c_double), C.c_int32,
                                      C.c_void_p, C.POINTER(SolveStats)]),
     "solve_coarse_block": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_int32, C.c_void_p,
-                                     C.c_void_p, C.POINTER(C.c_double), C.c_void_p,
+                                     C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_void_p,
                                      C.POINTER(SolveStats)]),
     "solve_coarse_multi": (C.c_int, [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(SolveOpts),
                                      C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_void_p),

@@ -51,6 +51,26 @@ struct Blas<double> {
                              reinterpret_cast<const rocblas_double_complex*>(B), ldb, &b,
                              reinterpret_cast<rocblas_double_complex*>(C), ldc));
   }
+  // C_p = A_p^H B_p for P chunks (strided)
+  static void gemm_cn_batched(rocblas_handle h, int m, int n, int k, const z64* A, int lda,
+                              long sa, const z64* B, int ldb, long sb, z64* C, int ldc, long sc,
+                              int P) {
+    const rocblas_double_complex a(1.0, 0.0), b(0.0, 0.0);
+    blas_check(rocblas_zgemm_strided_batched(
+        h, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n, k, &a,
+        reinterpret_cast<const rocblas_double_complex*>(A), lda, sa,
+        reinterpret_cast<const rocblas_double_complex*>(B), ldb, sb, &b,
+        reinterpret_cast<rocblas_double_complex*>(C), ldc, sc, P));
+  }
+  // y = A x (A: rows x cols, column-major)
+  static void gemv(rocblas_handle h, int rows, int cols, const z64* A, int lda, const z64* x,
+                   z64* y) {
+    const rocblas_double_complex a(1.0, 0.0), b(0.0, 0.0);
+    blas_check(rocblas_zgemv(h, rocblas_operation_none, rows, cols, &a,
+                             reinterpret_cast<const rocblas_double_complex*>(A), lda,
+                             reinterpret_cast<const rocblas_double_complex*>(x), 1, &b,
+                             reinterpret_cast<rocblas_double_complex*>(y), 1));
+  }
 };
 template <>
 struct Blas<float> {
@@ -63,6 +83,24 @@ struct Blas<float> {
                              reinterpret_cast<const rocblas_float_complex*>(A), lda,
                              reinterpret_cast<const rocblas_float_complex*>(B), ldb, &b,
                              reinterpret_cast<rocblas_float_complex*>(C), ldc));
+  }
+  static void gemm_cn_batched(rocblas_handle h, int m, int n, int k, const z32* A, int lda,
+                              long sa, const z32* B, int ldb, long sb, z32* C, int ldc, long sc,
+                              int P) {
+    const rocblas_float_complex a(1.0f, 0.0f), b(0.0f, 0.0f);
+    blas_check(rocblas_cgemm_strided_batched(
+        h, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n, k, &a,
+        reinterpret_cast<const rocblas_float_complex*>(A), lda, sa,
+        reinterpret_cast<const rocblas_float_complex*>(B), ldb, sb, &b,
+        reinterpret_cast<rocblas_float_complex*>(C), ldc, sc, P));
+  }
+  static void gemv(rocblas_handle h, int rows, int cols, const z32* A, int lda, const z32* x,
+                   z32* y) {
+    const rocblas_float_complex a(1.0f, 0.0f), b(0.0f, 0.0f);
+    blas_check(rocblas_cgemv(h, rocblas_operation_none, rows, cols, &a,
+                             reinterpret_cast<const rocblas_float_complex*>(A), lda,
+                             reinterpret_cast<const rocblas_float_complex*>(x), 1, &b,
+                             reinterpret_cast<rocblas_float_complex*>(y), 1));
   }
 };
 
@@ -148,7 +186,7 @@ struct BlockGmres {
   Z *V = nullptr, *Zb = nullptr, *W = nullptr, *T1 = nullptr, *TA = nullptr, *PROD = nullptr,
     *U = nullptr;
   Z *Hd = nullptr, *Gd = nullptr, *Rd = nullptr, *Yd = nullptr;
-  double* Dd = nullptr;   // complex-double results of the reductions over N
+  Z *Pt = nullptr, *Ones = nullptr, *Sum = nullptr;   // split-K partials, ones, their sum
   void** tabs = nullptr;
   long applies = 0;   // operator applications to single vectors
   // frozen recycle space of the single-RHS solver's variant (GCRO-DR, Sec. 3.4):
@@ -179,8 +217,9 @@ struct BlockGmres {
     b.U.ensure(vb);
     const size_t ns = size_t(m + 1) * R * R + 2 * size_t(R) * R + size_t(m) * R * R;
     const int kmax = std::max(o.k, 0);
-    const size_t nd = 2 * std::max(size_t(m + 1) * R * R, size_t(kmax) * R);
-    b.small.ensure(ns * sizeof(Z) + nd * sizeof(double));
+    const size_t qrmax = std::max(size_t(m + 1) * R * R, size_t(kmax) * R);
+    b.small.ensure(ns * sizeof(Z));
+    b.part.ensure((size_t(kChunks + 1) * qrmax + (kChunks + 1) + qrmax) * sizeof(Z));
     V = b.V.as<Z>();
     Zb = poly ? b.Z.as<Z>() : nullptr;
     W = b.W.as<Z>();
@@ -192,7 +231,13 @@ struct BlockGmres {
     Gd = Hd + size_t(m + 1) * R * R;
     Rd = Gd + size_t(R) * R;
     Yd = Rd + size_t(R) * R;
-    Dd = reinterpret_cast<double*>(Yd + size_t(m) * R * R);
+    Pt = b.part.as<Z>();
+    Ones = Pt + size_t(kChunks + 1) * qrmax;
+    Sum = Ones + (kChunks + 1);
+    {
+      std::vector<Z> ones(kChunks + 1, mk(VR(1), VR(0)));
+      op.hs.write(Ones, ones.data(), ones.size() * sizeof(Z), st);
+    }
     if (o.k > 0 && v.kcur > 0 && v.recycle_version == op.version && v.k_built == o.k) {
       kc = v.kcur;
       Cr = v.C.as<Z>();
@@ -297,20 +342,52 @@ struct BlockGmres {
   }
 
   // A^H B for qa contiguous vectors A and rb contiguous vectors B, read to the
-  // host: one multidot launch per column of B (grid-wide partial sums, double
-  // accumulation).  A GEMM here has a q x r output and an inner dimension of N,
-  // too few output tiles to spread the reduction over the chip.
+  // host.  One GEMM has a q x r output and an inner dimension of N, too few
+  // output tiles to spread the reduction over the chip, so N is split into
+  // kChunks row ranges: a strided-batched GEMM forms the chunks' partial
+  // products side by side and a GEMV with a ones vector sums them (a remainder
+  // of fewer rows than a chunk adds one more partial).
+  // Narrow blocks (rb <= 16) take one multidot launch per column of B instead
+  // (grid-wide partials, double accumulation): faster there than the batched
+  // GEMM.
+  static constexpr int kChunks = 256;
   Mat tn(const Z* A, int qa, const Z* B, int rb) {
-    for (int b = 0; b < rb; ++b)
-      launch_multidot(p, A, qa, nullptr, 0, N, B + size_t(b) * N, 0, op.red(),
-                      Dd + 2 * size_t(qa) * b, nullptr, st);
-    std::vector<double> hbuf(2 * size_t(qa) * rb);
-    op.hs.read(hbuf.data(), Dd, hbuf.size() * sizeof(double), st);
+    if (rb <= 16) {
+      double* dd = reinterpret_cast<double*>(Pt);
+      for (int b = 0; b < rb; ++b)
+        launch_multidot(p, A, qa, nullptr, 0, N, B + size_t(b) * N, 0, op.red(),
+                        dd + 2 * size_t(qa) * b, nullptr, st);
+      std::vector<double> hb(2 * size_t(qa) * rb);
+      op.hs.read(hb.data(), dd, hb.size() * sizeof(double), st);
+      op.hs.wait(st);
+      Mat M(qa, rb);
+      for (int b = 0; b < rb; ++b)
+        for (int i = 0; i < qa; ++i)
+          M(i, b) = cd(hb[2 * (size_t(b) * qa + i)], hb[2 * (size_t(b) * qa + i) + 1]);
+      return M;
+    }
+    const size_t qr = size_t(qa) * rb;
+    const size_t L = N / kChunks;             // rows per chunk (0 for tiny N)
+    const int P = L ? kChunks : 0;
+    const size_t rem = N - size_t(P) * L;
+    const int parts = P + (rem ? 1 : 0);
+    Z* part = Pt;
+    if (P)
+      Blas<VR>::gemm_cn_batched(h, qa, rb, int(L), A, int(N), long(L), B, int(N), long(L), part,
+                                qa, long(qr), P);
+    if (rem)
+      gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, qa, rb, int(rem), 1.0,
+           A + size_t(P) * L, int(N), B + size_t(P) * L, int(N), 0.0, part + size_t(P) * qr, qa);
+    Blas<VR>::gemv(h, int(qr), parts, part, int(qr), Ones, Sum);
+    std::vector<Z> hbuf(qr);
+    op.hs.read(hbuf.data(), Sum, qr * sizeof(Z), st);
     op.hs.wait(st);
     Mat M(qa, rb);
     for (int b = 0; b < rb; ++b)
-      for (int i = 0; i < qa; ++i)
-        M(i, b) = cd(hbuf[2 * (size_t(b) * qa + i)], hbuf[2 * (size_t(b) * qa + i) + 1]);
+      for (int i = 0; i < qa; ++i) {
+        const Z z = hbuf[size_t(b) * qa + i];
+        M(i, b) = cd(double(z.re), double(z.im));
+      }
     return M;
   }
 
@@ -564,7 +641,7 @@ struct BlockGmres {
 }  // namespace
 
 int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, const double* tol,
-                   hipStream_t st, SolveStats* stats) {
+                   int use_x0, hipStream_t st, SolveStats* stats) {
   if (R < 1) throw InvalidArg("n_rhs must be >= 1");
   if (!b || !x || !tol) throw InvalidArg("null pointer");
   if (o.schur) throw InvalidArg("the block solver works on the full lattice (schur = 0)");
@@ -581,45 +658,69 @@ int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, co
   const auto ts = std::chrono::steady_clock::now();
   ensure_poly(op, var, o, st, &stt[0]);
   const double t_setup = ms_since(ts);
-  const size_t N = op.N();
+  const size_t N = op.N(), NR = N * size_t(R);
   const z64* B64 = static_cast<const z64*>(b);
   z64* X64 = static_cast<z64*>(x);
   std::vector<double> tl(tol, tol + R), rel(R, 0.0);
   long applies = 0;
+  // FP64 applies and norms; in the FP64 path it is not used once the full
+  // solver below has (re)sized the shared FP64 workspace
+  BlockGmres<double> K64(op, var, o, P64, R, st, true);
+  const std::vector<double> bn0 = K64.colnorms(B64, R);
+  // With a start vector the solve is D e = b - D x0, to tol ||b|| / ||b - D x0||,
+  // and x = x0 + e; its right-hand side is kept in bk64.E0, e in bk64.E.
+  const z64* rhs = B64;
+  z64* sol = X64;
+  if (use_x0) {
+    op.bk64.X0.ensure(NR * sizeof(z64));
+    op.bk64.E0.ensure(NR * sizeof(z64));
+    op.bk64.E.ensure(NR * sizeof(z64));
+    z64* X0 = op.bk64.X0.as<z64>();
+    z64* Rb = op.bk64.E0.as<z64>();
+    DC_HIP(hipMemcpyAsync(X0, X64, NR * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    K64.apply(K64.cols(static_cast<const z64*>(X0), R), K64.cols(Rb, R));
+    launch_scale(P64, Rb, Rb, NR, nullptr, -1.0, nullptr, st);
+    launch_axpy(P64, mk(1.0, 0.0), B64, Rb, NR, st);
+    const std::vector<double> rn2 = K64.colnorms(Rb, R);
+    for (int c = 0; c < R; ++c) {
+      const double rn = std::sqrt(std::max(rn2[c], 0.0)), bnc = std::sqrt(std::max(bn0[c], 0.0));
+      tl[c] = rn > 0.0 ? tol[c] * bnc / rn : 1.0;
+    }
+    rhs = Rb;
+    sol = op.bk64.E.as<z64>();
+  }
   if (o.prec == P64) {
     BlockGmres<double> K(op, var, o, P64, R, st);
-    K.solve(B64, X64, R, tl, o.max_cycles, stt, rel);
-    applies = K.applies;
+    K.solve(rhs, sol, R, tl, o.max_cycles, stt, rel);
+    applies += K.applies;
   } else {
-    // FP64 iterative refinement: r = b - D x in FP64, the block solve of
-    // D e = r in the reduced precision to inner_tol, x += e
-    BlockGmres<double> K64(op, var, o, P64, R, st, true);
+    // FP64 iterative refinement: r = rhs - D sol in FP64, the block solve of
+    // D e = r in the reduced precision to inner_tol, sol += e
     BlockGmres<float> K(op, var, o, o.prec, R, st);
-    op.bk64.R.ensure(N * sizeof(z64) * size_t(R));
+    op.bk64.R.ensure(NR * sizeof(z64));
     op.bk32.R.ensure(N * sizeof(z32) * size_t(R));
     op.bk32.X.ensure(N * sizeof(z32) * size_t(R));
     z64* Rr = op.bk64.R.as<z64>();
     z32* Rin = op.bk32.R.as<z32>();
     z32* E = op.bk32.X.as<z32>();
-    launch_zero(P64, X64, size_t(R) * N, st);
-    std::vector<double> bn = K64.colnorms(B64, R);
+    launch_zero(P64, sol, NR, st);
+    std::vector<double> bn = K64.colnorms(rhs, R);
     for (double& v : bn) v = std::sqrt(std::max(v, 0.0));
     std::vector<int> act;
     for (int c = 0; c < R; ++c)
       if (bn[c] > 0.0) act.push_back(c);
     for (int outer = 0; !act.empty(); ++outer) {
       const int r = int(act.size());
-      // residuals of the active columns (FP64)
       std::vector<const z64*> in(r);
       std::vector<z64*> out(r);
       for (int a = 0; a < r; ++a) {
-        in[a] = X64 + size_t(act[a]) * N;
+        in[a] = sol + size_t(act[a]) * N;
         out[a] = Rr + size_t(a) * N;
       }
       K64.apply(in, out);
       for (int a = 0; a < r; ++a) {
         launch_scale(P64, out[a], out[a], N, nullptr, -1.0, nullptr, st);
-        launch_axpy(P64, mk(1.0, 0.0), B64 + size_t(act[a]) * N, out[a], N, st);
+        launch_axpy(P64, mk(1.0, 0.0), rhs + size_t(act[a]) * N, out[a], N, st);
       }
       const std::vector<double> rn = K64.colnorms(Rr, r);
       std::vector<int> keep;
@@ -642,20 +743,27 @@ int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, co
         stt[c].iters += ist[t].iters;
         stt[c].cycles += ist[t].cycles;
         stt[c].outer_iters += 1;
-        // x += e (through the FP64 residual buffer as staging)
+        // sol += e (through the FP64 residual buffer as staging)
         launch_convert_32to64(E + size_t(t) * N, Rr + size_t(t) * N, N, op.n, 0, st);
-        launch_axpy(P64, mk(1.0, 0.0), Rr + size_t(t) * N, X64 + size_t(c) * N, N, st);
+        launch_axpy(P64, mk(1.0, 0.0), Rr + size_t(t) * N, sol + size_t(c) * N, N, st);
       }
       act = act2;
     }
-    applies = K.applies + K64.applies;
+    applies += K.applies;
+  }
+  applies += K64.applies;
+  if (use_x0) {
+    // x = x0 + e, and the residuals relative to b
+    DC_HIP(hipMemcpyAsync(X64, op.bk64.X0.p, NR * sizeof(z64), hipMemcpyDeviceToDevice, st));
+    launch_axpy(P64, mk(1.0, 0.0), sol, X64, NR, st);
+    for (int c = 0; c < R; ++c) rel[c] = tl[c] > 0.0 ? rel[c] * tol[c] / tl[c] : rel[c];
   }
   int all_ok = 1;
   const double t_solve = ms_since(t0);
   for (int r = 0; r < R; ++r) {
     SolveStats& s = stt[r];
     s.rel_res_true = rel[r];
-    s.status = rel[r] <= tl[r] ? 0 : 1;
+    s.status = rel[r] <= tol[r] * (1.0 + 1e-12) ? 0 : 1;
     if (s.status) all_ok = 0;
     s.matvecs = int(applies / R);
     s.t_setup_ms = t_setup;

@@ -265,12 +265,13 @@ int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, i
 }
 
 int solve_coarse_block(dc_op_t op, const dc_solve_opts* opts, int32_t n_rhs, const void* b,
-                       void* x, const double* tol, void* stream, dc_solve_stats* stats) {
+                       void* x, const double* tol, int32_t use_x0, void* stream,
+                       dc_solve_stats* stats) {
   return guarded([&] {
     if (!op || !opts) throw dc::InvalidArg("null handle or options");
     std::vector<dc::SolveStats> st(n_rhs > 0 ? n_rhs : 0);
-    const int rc = dc::op_solve_block(op->op, convert(opts), n_rhs, b, x, tol, as_stream(stream),
-                                      st.data());
+    const int rc = dc::op_solve_block(op->op, convert(opts), n_rhs, b, x, tol, use_x0,
+                                      as_stream(stream), st.data());
     if (stats)
       for (int r = 0; r < n_rhs; ++r) copy_stats(st[r], stats + r);
     return rc == 0 ? DC_OK : DC_NOT_CONVERGED;

@@ -167,7 +167,7 @@ struct Op {
   // block GMRES workspaces (FP64 and reduced-precision vectors) and the
   // rocBLAS handle of its tall-skinny GEMMs (created on first use)
   struct BlockWS {
-    DevBuf V, Z, W, T1, TA, PROD, U, small, tab, R, X, Bc;
+    DevBuf V, Z, W, T1, TA, PROD, U, small, tab, R, X, Bc, part, X0, E0, E;
   } bk64, bk32;
   std::shared_ptr<void> blas;
   void* tmp_s(Prec p);
@@ -217,7 +217,7 @@ int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b
                    const double* tol, int use_x0, hipStream_t st, SolveStats* stats);
 // block GMRES with one shared Krylov space over R right-hand sides
 int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, const double* tol,
-                   hipStream_t st, SolveStats* stats);
+                   int use_x0, hipStream_t st, SolveStats* stats);
 // shared helpers of the solvers
 void check_prec(const Op& op, Prec p);
 void ensure_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st, SolveStats* stt);

@@ -88,6 +88,31 @@ def test_block_solve_deflated_by_recycle_space(c1):
     assert max(s["iters"] for s in sd) < max(s["iters"] for s in s0)
 
 
+@pytest.mark.parametrize("prec", ["f64", "f16s"])
+def test_block_solve_continues_from_start_vector(c1, prec):
+    """A solve stopped early (bounded refinement / cycles) continues from its x:
+    the second call meets the tolerances relative to b."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, D = c1
+    log("block gmres continued", prec)
+    R = 3
+    B = _rhs(w.dims, w.n_tv, R, 100).cuda()
+    tols = np.array([1e-10, 1e-9, 1e-8])
+    if prec == "f64":
+        o1, o2 = Opts(m=8, max_cycles=2), Opts(m=12)
+    else:
+        o1 = Opts(m=8, d=4, seed=1, prec="f16s", inner_tol=1e-2, max_outer=2)
+        o2 = Opts(m=8, d=4, seed=1, prec="f16s", inner_tol=1e-2, max_outer=40)
+    X1, s1, rc1 = gop.solve_block(B, tols, o1)
+    assert rc1 != 0
+    X2, s2, rc2 = gop.solve_block(B, tols, o2, x0=X1)
+    assert rc2 == 0
+    Xh = X2.cpu().numpy()
+    for c in range(R):
+        assert s2[c]["rel_res_true"] <= tols[c]
+        assert oracle_relres(oop, Xh[c], B[c].cpu().numpy()) <= tols[c] * 1.0001
+
+
 def test_single_column_is_gmres(c1):
     """With one right-hand side the block process is GMRES(m): the same number
     of Arnoldi steps as the single-RHS solver (to a step or two of rounding)."""
