@@ -1396,6 +1396,37 @@ __device__ inline const cx<VR>* basis_ptr(const cx<VR>* b0, int q0, const cx<VR>
   return q < q0 ? b0 + size_t(q) * N : b1 + size_t(q - q0) * N;
 }
 
+// Wave sums of V per-lane values (V a power of two, at most 64) by halving
+// exchanges: at each step a lane keeps one half of its values, sends the other
+// half to its partner and adds what it receives, so after log2(V) steps lane l
+// holds one value, index l / (64 / V), summed over V lanes; the remaining
+// steps are a plain butterfly.  V - 1 + 6 - log2(V) exchanges instead of 6 V,
+// in a fixed order.
+template <int V, int S = 0>
+__device__ inline void halving_steps(double (&acc)[V], int lane) {
+  if constexpr ((V >> S) > 1) {
+    constexpr int half = V >> (S + 1);
+    constexpr int o = 32 >> S;
+    const bool upper = (lane & o) != 0;
+#pragma unroll
+    for (int i = 0; i < half; ++i) {
+      const double send = upper ? acc[i] : acc[i + half];
+      const double keep = upper ? acc[i + half] : acc[i];
+      acc[i] = keep + shfl_xor(send, o);
+    }
+    halving_steps<V, S + 1>(acc, lane);
+  }
+}
+
+template <int V>
+__device__ inline double wave_sum_many(double (&acc)[V], int lane) {
+  halving_steps<V>(acc, lane);
+  double v = acc[0];
+#pragma unroll
+  for (int o = 32 / V; o > 0; o >>= 1) v += shfl_xor(v, o);
+  return v;
+}
+
 // result value v = blockIdx.y * 2G + t of the group; t = 2*(q - g0) + re/im
 template <typename VR, int G>
 __global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0, int q0,
@@ -1451,13 +1482,9 @@ __global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0,
   (void)want_norm;
   __shared__ double sh[4][2 * G];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-  for (int t = 0; t < 2 * G; ++t) {
-    double s = acc[t];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) s += shfl_xor(s, o);
-    if (lane == 0) sh[wave][t] = s;
-  }
+  const double s = wave_sum_many<2 * G>(acc, lane);
+  constexpr int kSpan = 64 / (2 * G);   // lanes holding the same value
+  if (lane % kSpan == 0) sh[wave][lane / kSpan] = s;
   __syncthreads();
   const int gx = gridDim.x;
   if (threadIdx.x < 2 * G) {
@@ -1571,6 +1598,63 @@ __global__ __launch_bounds__(256) void k_combine(const cx<VR>* __restrict__ b0, 
           *o = mk(VR(double(old.re) + ar[t]), VR(double(old.im) + ai[t]));
         } else {
           *o = mk(VR(ar[t]), VR(ai[t]));
+        }
+      }
+    }
+  }
+}
+
+// One output (R = 1): out (+)= sum_q coef_q basis_q, with the loads of a
+// chunk of kAxpyG basis vectors issued before their arithmetic, as in the
+// update kernel (the general kernel above walks the basis one load at a time).
+template <typename VR>
+__global__ __launch_bounds__(256) void k_combine1(const cx<VR>* __restrict__ b0, int q0,
+                                                  const cx<VR>* __restrict__ b1, int q1,
+                                                  size_t N, const double* __restrict__ coef,
+                                                  cx<VR>* __restrict__ out, int accumulate) {
+  const int Q = q0 + q1;
+  const size_t chunk = size_t(blockDim.x) * kDotE;
+  const size_t stride = size_t(gridDim.x) * chunk;
+  for (size_t base = size_t(blockIdx.x) * chunk + threadIdx.x; base < N; base += stride) {
+    size_t idx[kDotE];
+    double sr[kDotE], si[kDotE];
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+      const size_t i = base + size_t(e) * blockDim.x;
+      idx[e] = i < N ? i : N - 1;
+      sr[e] = si[e] = 0.0;
+    }
+    for (int qc = 0; qc < Q; qc += kAxpyG) {
+      cx<VR> v[kAxpyG][kDotE];
+#pragma unroll
+      for (int t = 0; t < kAxpyG; ++t) {
+        const int q = min(qc + t, Q - 1);
+        const cx<VR>* p = basis_ptr(b0, q0, b1, N, q);
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) v[t][e] = p[idx[e]];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < kAxpyG; ++t) {
+        const int q = qc + t;
+        const double cr = q < Q ? coef[2 * q] : 0.0, ci = q < Q ? coef[2 * q + 1] : 0.0;
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) {
+          const double vr = v[t][e].re, vi = v[t][e].im;
+          sr[e] = fma(cr, vr, fma(-ci, vi, sr[e]));
+          si[e] = fma(cr, vi, fma(ci, vr, si[e]));
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+      if (base + size_t(e) * blockDim.x < N) {
+        cx<VR>* o = out + idx[e];
+        if (accumulate) {
+          const cx<VR> old = *o;
+          *o = mk(VR(double(old.re) + sr[e]), VR(double(old.im) + si[e]));
+        } else {
+          *o = mk(VR(sr[e]), VR(si[e]));
         }
       }
     }
@@ -1846,6 +1930,7 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(ArnoldiDev a, int steps, 
   g[2 * (j + 1) + 1] = -(sr * gi - si * gr);
   const double est = sqrt(g[2 * (j + 1)] * g[2 * (j + 1)] + g[2 * (j + 1) + 1] * g[2 * (j + 1) + 1]);
   *a.est = est;
+  if (a.hest) a.hest[j] = est;
   *a.jdone = j + 1;
   if (breakdown) *a.brk_flag = 1;
   if (breakdown || est <= target || j + 1 >= steps) {
@@ -2468,6 +2553,26 @@ void launch_multiaxpy_scaled(Prec p, void* w, const void* b0, int q0, const void
 void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
                     const double* coef, int R, void* out, int accumulate, hipStream_t st) {
   if (R <= 0) return;
+  if (R == 1) {
+    size_t nb = (N + 256 * kDotE - 1) / (256 * kDotE);
+    if (nb > 2048) nb = 2048;
+    if (nb < 1) nb = 1;
+    const dim3 grid{static_cast<unsigned>(nb)}, block{256};
+    if (q0 + q1 == 0) {
+      if (!accumulate) launch_zero(p, out, N, st);
+      return;
+    }
+    if (p == P64)
+      hipLaunchKernelGGL(k_combine1<double>, grid, block, 0, st, static_cast<const z64*>(b0), q0,
+                         static_cast<const z64*>(b1), q1, N, coef, static_cast<z64*>(out),
+                         accumulate);
+    else
+      hipLaunchKernelGGL(k_combine1<float>, grid, block, 0, st, static_cast<const z32*>(b0), q0,
+                         static_cast<const z32*>(b1), q1, N, coef, static_cast<z32*>(out),
+                         accumulate);
+    DC_HIP(hipGetLastError());
+    return;
+  }
   const int gy = (R + kCombR - 1) / kCombR;
   const dim3 grid(grid_for(N, 256, 2048), unsigned(gy)), block(256);
   if (p == P64)
@@ -2514,6 +2619,28 @@ void launch_scale_step(Prec p, void* v, size_t N, const double* inv_h, const int
   else
     hipLaunchKernelGGL(k_scale_step<float>, grid, block, 0, st, static_cast<z32*>(v), N, inv_h,
                        jdone, j);
+  DC_HIP(hipGetLastError());
+}
+
+// 4-byte words from src to dst; one side is host-mapped pinned memory (the
+// staged transfers between the solver's host logic and the device, which as
+// kernels queue without the host-side cost of a copy call).
+__global__ void k_copy_words(const uint32_t* __restrict__ src, uint32_t* __restrict__ dst,
+                             size_t n) {
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = src[i];
+}
+
+void launch_copy_words(const void* src, void* dst, size_t bytes, hipStream_t st) {
+  if (bytes == 0) return;
+  if (bytes % 4 != 0 || reinterpret_cast<uintptr_t>(src) % 4 != 0 ||
+      reinterpret_cast<uintptr_t>(dst) % 4 != 0)
+    throw std::invalid_argument("staged copies move aligned 4-byte words");
+  const size_t n = bytes / 4;
+  const dim3 grid(grid_for(n, 256, 2048)), block(256);
+  hipLaunchKernelGGL(k_copy_words, grid, block, 0, st, static_cast<const uint32_t*>(src),
+                     static_cast<uint32_t*>(dst), n);
   DC_HIP(hipGetLastError());
 }
 

@@ -166,6 +166,9 @@ void launch_scale_step(Prec p, void* v, size_t N, const double* inv_h, const int
                        hipStream_t st);
 // x = 0
 void launch_zero(Prec p, void* x, size_t N, hipStream_t st);
+// bytes (a multiple of 4, both pointers 4-byte aligned) from src to dst, one of
+// them host-mapped pinned memory given by its device address
+void launch_copy_words(const void* src, void* dst, size_t bytes, hipStream_t st);
 // y = a*x + y (complex a)
 void launch_axpy(Prec p, z64 a, const void* x, void* y, size_t N, hipStream_t st);
 // result[0] = ||x||^2
@@ -198,6 +201,7 @@ struct ArnoldiDev {
   int* jdone;       // steps completed
   int* brk_flag;    // 1 if the cycle ended by breakdown
   int* hdone = nullptr;  // optional host-mapped copy of the done flag (set to 1 with it)
+  double* hest = nullptr;  // optional host-mapped per-step estimates: hest[j] after step j
 };
 // c2 null: the single-sync process (one pass of coefficients c1, whose entry
 // kC + j + 1 is ||A v_j||^2; h_{j+1,j}^2 = ||A v_j||^2 - sum |c1|^2; nrm2 unused).

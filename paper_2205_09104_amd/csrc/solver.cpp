@@ -215,21 +215,28 @@ void stream_wait(hipStream_t st) {
   }
 }
 
+static char* mapped_alloc(size_t bytes, char** dev) {
+  void* h = nullptr;
+  DC_HIP(hipHostMalloc(&h, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+  void* d = nullptr;
+  DC_HIP(hipHostGetDevicePointer(&d, h, 0));
+  *dev = static_cast<char*>(d);
+  return static_cast<char*>(h);
+}
+
 void HostStage::read(void* dst, const void* src, size_t bytes, hipStream_t st) {
   const size_t off = (rd_used + 15) & ~size_t(15);
   if (off + bytes > rd_cap) {
     wait(st);                    // no read may be in flight while the area is replaced
-    size_t cap = std::max<size_t>(size_t(1) << 16, 2 * rd_cap);
+    size_t cap = std::max<size_t>(size_t(1) << 20, 2 * rd_cap);
     while (cap < bytes) cap *= 2;
-    if (rd) DC_HIP(hipHostFree(rd));
-    void* h = nullptr;
-    DC_HIP(hipHostMalloc(&h, cap, hipHostMallocDefault));
-    rd = static_cast<char*>(h);
+    if (rd) retired.push_back(rd);
+    rd = mapped_alloc(cap, &rd_dev);
     rd_cap = cap;
     read(dst, src, bytes, st);
     return;
   }
-  DC_HIP(hipMemcpyAsync(rd + off, src, bytes, hipMemcpyDeviceToHost, st));
+  launch_copy_words(src, rd_dev + off, bytes, st);
   pending.push_back({dst, off, bytes});
   rd_used = off + bytes;
 }
@@ -248,16 +255,14 @@ void HostStage::write(void* dst, const void* src, size_t bytes, hipStream_t st) 
     return;
   }
   if (!up) {
-    void* h = nullptr;
-    DC_HIP(hipHostMalloc(&h, kSlots * kSlotBytes, hipHostMallocDefault));
-    up = static_cast<char*>(h);
+    up = mapped_alloc(kSlots * kSlotBytes, &up_dev);
     for (auto& e : ev) DC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   }
   const int s = next;
   next = (next + 1) % kSlots;
   if (ev_live[s]) DC_HIP(hipEventSynchronize(ev[s]));   // its previous copy has run
   std::memcpy(up + size_t(s) * kSlotBytes, src, bytes);
-  DC_HIP(hipMemcpyAsync(dst, up + size_t(s) * kSlotBytes, bytes, hipMemcpyHostToDevice, st));
+  launch_copy_words(up_dev + size_t(s) * kSlotBytes, dst, bytes, st);
   DC_HIP(hipEventRecord(ev[s], st));
   ev_live[s] = true;
 }
@@ -266,6 +271,7 @@ HostStage::~HostStage() {
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
   if (rd) (void)hipHostFree(rd);
+  for (void* r : retired) (void)hipHostFree(r);
   if (up) (void)hipHostFree(up);
 }
 
@@ -281,10 +287,28 @@ void CycleSignal::ensure() {
   for (auto& e : ev) DC_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
 }
 
+void CycleSignal::ensure_est(int steps) {
+  if (est_host && est_cap >= steps) return;
+  if (est_host) retired.push_back(est_host);   // kernels wrote it: released with the signal
+  est_host = nullptr;
+  est_dev = nullptr;
+  est_cap = 0;
+  const int cap = std::max(steps, 256);
+  void* h = nullptr;
+  DC_HIP(hipHostMalloc(&h, size_t(cap) * sizeof(double), hipHostMallocMapped | hipHostMallocCoherent));
+  est_host = static_cast<double*>(h);
+  void* d = nullptr;
+  DC_HIP(hipHostGetDevicePointer(&d, h, 0));
+  est_dev = static_cast<double*>(d);
+  est_cap = cap;
+}
+
 CycleSignal::~CycleSignal() {
   for (auto& e : ev)
     if (e) (void)hipEventDestroy(e);
   if (host) (void)hipHostFree(host);
+  if (est_host) (void)hipHostFree(est_host);
+  for (void* r : retired) (void)hipHostFree(r);
 }
 
 // Stage 1 of the apply, timed when profiling is on (one in `every` launches
@@ -529,6 +553,11 @@ struct Krylov {
   // the solve uses Gram-Schmidt twice, whose breakdown test is reliable
   int ortho_now = 0;
   bool ss_off = false;
+  // inner solves of the FP64 flexible outer loop stop on the recursively
+  // updated residual of the deflated GCRO-DR cycles (rhat, which without a
+  // left preconditioner is the residual of this precision's operator) instead
+  // of re-applying the operator: the outer loop's FP64 residual decides
+  bool inner_est = false;
   Z *Vb = nullptr, *Ctmp = nullptr, *Utmp = nullptr, *prod = nullptr, *ybuf = nullptr,
     *tmp = nullptr, *tmp2 = nullptr, *rhat = nullptr, *rtrue = nullptr, *ta = nullptr, *tb = nullptr;
   double *res1 = nullptr, *res2 = nullptr, *nrm = nullptr, *coef = nullptr, *scal = nullptr;
@@ -659,7 +688,7 @@ struct Krylov {
   // rhat = B^{-1} r (or a copy without block Jacobi)
   void left_precondition(const Z* r, Z* out) {
     if (bjinv) launch_bj_vec(p, op.n, rows, bjinv, bjsc, r, out, st);
-    else DC_HIP(hipMemcpyAsync(out, r, N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    else launch_copy_words(r, out, N * sizeof(Z), st);
   }
 
   bool has_poly() const { return var.d > 1 && int(var.theta.size()) > 1; }
@@ -778,12 +807,18 @@ struct Krylov {
     // The host enqueues the cycle in chunks of about a millisecond of device
     // work and stays at most two chunks ahead; once the device has set the stop
     // flag no further chunks are enqueued (the steps already queued past the
-    // stopping one exit at entry).
+    // stopping one exit at entry).  With one step per chunk, when the estimate
+    // of the finished step extrapolated geometrically reaches the target, the
+    // host waits for the running step before enqueueing the next, which then
+    // is not enqueued at all if that step converged.
     const double per_step = double(N) * (has_poly() ? double(var.theta.size()) : 1.0);
     const int chunk = std::max(1, std::min(steps, int(std::ceil(1.0e6 / per_step))));
     op.sig.ensure();
+    op.sig.ensure_est(steps);
     *op.sig.host = 0;
     ad.hdone = op.sig.dev;
+    ad.hest = op.sig.est_dev;
+    double last_est = beta;
     int nchunk = 0, enqueued = 0;
     for (int j = 0; j < steps; ++j) {
       op.prof.tag = j;
@@ -800,11 +835,22 @@ struct Krylov {
         if (nchunk >= 1) {
           DC_HIP(hipEventSynchronize(op.sig.ev[(nchunk - 1) & 1]));
           if (__atomic_load_n(op.sig.host, __ATOMIC_ACQUIRE)) break;
+          if (chunk == 1 && target >= 0.0 && j + 1 >= min_steps) {
+            // step j - 1 has finished: its estimate is final
+            const double e = static_cast<volatile const double*>(op.sig.est_host)[j - 1];
+            const double ratio = last_est > 0.0 ? std::min(1.0, e / last_est) : 1.0;
+            last_est = e;
+            if (e * ratio <= target) {
+              DC_HIP(hipEventSynchronize(op.sig.ev[nchunk & 1]));
+              if (__atomic_load_n(op.sig.host, __ATOMIC_ACQUIRE)) break;
+            }
+          }
         }
         ++nchunk;
       }
     }
     ad.hdone = nullptr;
+    ad.hest = nullptr;
     op.prof.tag = -1;
     CycleOut c;
     int flags[3];
@@ -966,7 +1012,7 @@ struct Krylov {
     const int m = o.m;
     double rn = bn;                  // x = 0: the residual is b itself
     if (use_x0) rn = true_resid(x, b, rtrue);
-    else DC_HIP(hipMemcpyAsync(rtrue, b, N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    else launch_copy_words(b, rtrue, N * sizeof(Z), st);
     relres = rn / bn;
     if (relres <= tol) {
       stt.matvecs += int(matvecs - mv0);
@@ -1009,7 +1055,8 @@ struct Krylov {
     double best = rn;
     int stall = 0;
     while (true) {
-      rn = true_resid(x, b, rtrue);
+      const bool by_est = inner_est && !bjinv && k > 0 && var.kcur > 0;
+      rn = by_est ? beta : true_resid(x, b, rtrue);
       relres = rn / bn;
       if (relres <= tol) {
         converged = true;
@@ -1025,6 +1072,7 @@ struct Krylov {
         // residual, deflated, with Gram-Schmidt twice
         stall = 0;
         ss_off = true;
+        if (by_est) rn = true_resid(x, b, rtrue);
         left_precondition(rtrue, rhat);
         deflate_start(x);
         beta = norm(rhat);
@@ -1382,6 +1430,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       op.zouter.ensure(size_t(o.m_outer) * N * sizeof(z64));
       z64* Zb = op.zouter.as<z64>();
       Krylov<float> KI(op, var, o, var.ws, var.sm, o.m, st);
+      KI.inner_est = true;
       op.t32a.ensure(N * sizeof(z32));
       op.t32b.ensure(N * sizeof(z32));
       z32* b32 = op.t32a.as<z32>();
@@ -1389,11 +1438,17 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       if (!use_x0) launch_zero(P64, xx, N, st);
       const double bn = KO.norm(bb);
       int outer_done = 0;
+      // residual of the current x: b itself for a zero start; after a cycle
+      // whose FP64 least-squares residual is below half the target the cycle's
+      // estimate (the Arnoldi relation of FP64 applies holds to rounding)
+      double rknown = use_x0 ? -1.0 : bn;
       while (bn > 0.0) {
-        const double rn = KO.true_resid(xx, bb, KO.rtrue);
+        const bool known = rknown >= 0.0;
+        const double rn = known ? rknown : KO.true_resid(xx, bb, KO.rtrue);
+        rknown = -1.0;
         rel = rn / bn;
         if (rel <= tol_r || outer_done >= o.max_outer) break;
-        launch_scale(P64, KO.rtrue, KO.V(0), N, nullptr, 1.0 / rn, nullptr, st);
+        launch_scale(P64, known ? bb : KO.rtrue, KO.V(0), N, nullptr, 1.0 / rn, nullptr, st);
         launch_arnoldi_init(KO.ad, rn, st);
         int jd = 0;
         for (int j = 0; j < o.m_outer && outer_done < o.max_outer; ++j) {
@@ -1425,6 +1480,10 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
         KO.upload_coef(y);
         launch_combine(P64, nullptr, 0, Zb, jd, N, KO.coef, 1, xx, 1, st);
         if (jd == 0) break;
+        if (lsres <= 0.5 * tol_r * bn) {
+          rel = lsres / bn;
+          break;
+        }
       }
       s.outer_iters = outer_done;
       s.matvecs += int(KO.matvecs);

@@ -113,14 +113,21 @@ struct ApplyProfile {
 // Reads are queued (read) and land in their destinations at the next wait();
 // uploads go through a ring of pinned slots, each reused only after the event
 // recorded behind its previous copy has completed.
+// Small transfers between the host logic and the device, in host-mapped
+// pinned memory moved by copy kernels on the stream (queued in order with the
+// kernels around them).  Areas that kernels have touched are released only
+// with the stage.
 struct HostStage {
   struct Pending { void* dst; size_t off, bytes; };
-  char* rd = nullptr;            // read area
+  char* rd = nullptr;            // read area (host address)
+  char* rd_dev = nullptr;        // its device address
   size_t rd_cap = 0, rd_used = 0;
   std::vector<Pending> pending;
+  std::vector<void*> retired;    // outgrown read areas
   static constexpr int kSlots = 8;
   static constexpr size_t kSlotBytes = size_t(1) << 18;
-  char* up = nullptr;            // kSlots upload slots
+  char* up = nullptr;            // kSlots upload slots (host address)
+  char* up_dev = nullptr;
   hipEvent_t ev[kSlots] = {};
   bool ev_live[kSlots] = {};
   int next = 0;
@@ -134,13 +141,19 @@ struct HostStage {
 // wait; the solver's host thread has nothing else to do meanwhile).
 void stream_wait(hipStream_t st);
 
-// Host-mapped stop flag of the pending Arnoldi cycle and two events that
-// pace the host's enqueueing a bounded distance ahead of the device.
+// Host-mapped stop flag of the pending Arnoldi cycle, its per-step residual
+// estimates, and two events that pace the host's enqueueing a bounded
+// distance ahead of the device.
 struct CycleSignal {
   int* host = nullptr;    // pinned, mapped
   int* dev = nullptr;     // its device address
+  double* est_host = nullptr;  // pinned, mapped: estimate after each step
+  double* est_dev = nullptr;
+  int est_cap = 0;
+  std::vector<void*> retired;  // outgrown estimate areas
   hipEvent_t ev[2] = {nullptr, nullptr};
   void ensure();
+  void ensure_est(int steps);
   ~CycleSignal();
 };
 
