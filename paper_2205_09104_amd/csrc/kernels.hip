@@ -1811,8 +1811,9 @@ __global__ void k_oddeven_split(int n, int H, const int* __restrict__ esite,
 }
 
 // ------------------------------------------------------------------ Arnoldi
-__global__ void k_arnoldi_init(ArnoldiDev a, double beta) {
+__global__ void k_arnoldi_init(ArnoldiDev a, double beta, const double* __restrict__ beta_dev) {
   if (threadIdx.x == 0) {
+    if (beta_dev) beta = *beta_dev;
     *a.done = 0;
     *a.jdone = 0;
     *a.brk_flag = 0;
@@ -2719,8 +2720,22 @@ void launch_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const double*
   DC_HIP(hipGetLastError());
 }
 
-void launch_arnoldi_init(ArnoldiDev a, double beta, hipStream_t st) {
-  hipLaunchKernelGGL(k_arnoldi_init, dim3(1), dim3(64), 0, st, a, beta);
+void launch_arnoldi_init(ArnoldiDev a, double beta, hipStream_t st, const double* beta_dev) {
+  hipLaunchKernelGGL(k_arnoldi_init, dim3(1), dim3(64), 0, st, a, beta, beta_dev);
+  DC_HIP(hipGetLastError());
+}
+
+// out[0] = sqrt(max(*nrm2, 0)), out[1] = 1 / out[0] (0 for a zero norm)
+__global__ void k_norm_root(const double* __restrict__ nrm2, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    const double b = sqrt(fmax(*nrm2, 0.0));
+    out[0] = b;
+    out[1] = b > 0.0 ? 1.0 / b : 0.0;
+  }
+}
+
+void launch_norm_root(const double* nrm2, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_norm_root, dim3(1), dim3(64), 0, st, nrm2, out);
   DC_HIP(hipGetLastError());
 }
 

@@ -208,7 +208,11 @@ struct ArnoldiDev {
 void launch_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const double* c1,
                            const double* c2, const double* nrm2, double target, double brk,
                            hipStream_t st);
-void launch_arnoldi_init(ArnoldiDev a, double beta, hipStream_t st);
+// beta_dev: take beta from device memory instead
+void launch_arnoldi_init(ArnoldiDev a, double beta, hipStream_t st,
+                         const double* beta_dev = nullptr);
+// out[0] = sqrt(*nrm2), out[1] = its reciprocal (0 for a zero norm); device pointers
+void launch_norm_root(const double* nrm2, double* out, hipStream_t st);
 
 // ---------------------------------------------------------------- gradient
 void launch_grad_hops(const z64* lam, const z64* x, z64* grad, const int* nbr, int V, int n,

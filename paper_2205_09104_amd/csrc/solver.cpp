@@ -558,6 +558,8 @@ struct Krylov {
   // left preconditioner is the residual of this precision's operator) instead
   // of re-applying the operator: the outer loop's FP64 residual decides
   bool inner_est = false;
+  double bn_hint = -1.0;   // ||b|| when the caller knows it (inner solves: unit vectors)
+  std::vector<double> Hh_, Bh_;   // host copies of the cycle's Hessenberg and B_k columns
   Z *Vb = nullptr, *Ctmp = nullptr, *Utmp = nullptr, *prod = nullptr, *ybuf = nullptr,
     *tmp = nullptr, *tmp2 = nullptr, *rhat = nullptr, *rtrue = nullptr, *ta = nullptr, *tb = nullptr;
   double *res1 = nullptr, *res2 = nullptr, *nrm = nullptr, *coef = nullptr, *scal = nullptr;
@@ -793,6 +795,7 @@ struct Krylov {
     int jd = 0;
     bool breakdown = false;
     double est = 0;
+    double beta = 0;  // norm of the start vector
     Mat H;   // (jd+1) x jd
     Mat Bk;  // kC x jd
   };
@@ -800,10 +803,17 @@ struct Krylov {
   // One Arnoldi cycle of up to `steps` steps of A^ from rv (norm beta), with
   // deflation against the first kC columns of C.  The device stops the cycle
   // when the least-squares residual estimate reaches `target` (not before
-  // min_steps steps) or on breakdown.
+  // min_steps steps) or on breakdown.  beta < 0: the norm is on the device
+  // (nrm[2], its reciprocal nrm[3]) and is read back with the cycle's results.
   CycleOut cycle(const Z* rv, double beta, int steps, int kC, double target, int min_steps) {
-    launch_scale(p, rv, V(0), N, nullptr, 1.0 / beta, nullptr, st);
-    launch_arnoldi_init(ad, beta, st);
+    const bool dev_beta = beta < 0.0;
+    if (dev_beta) {
+      launch_scale(p, rv, V(0), N, nrm + 3, 0.0, nullptr, st);
+      launch_arnoldi_init(ad, 0.0, st, nrm + 2);
+    } else {
+      launch_scale(p, rv, V(0), N, nullptr, 1.0 / beta, nullptr, st);
+      launch_arnoldi_init(ad, beta, st);
+    }
     // The host enqueues the cycle in chunks of about a millisecond of device
     // work and stays at most two chunks ahead; once the device has set the stop
     // flag no further chunks are enqueued (the steps already queued past the
@@ -857,10 +867,17 @@ struct Krylov {
     op.hs.read(flags, ad.done, 3 * sizeof(int), st);
     double est;
     op.hs.read(&est, ad.est, sizeof(double), st);
-    std::vector<double> Hh(2 * size_t(ldh) * ldh);
-    op.hs.read(Hh.data(), ad.H, Hh.size() * sizeof(double), st);
-    std::vector<double> Bh(2 * size_t(ad.ldb) * ldh);
-    if (kC) op.hs.read(Bh.data(), ad.Bk, Bh.size() * sizeof(double), st);
+    if (dev_beta) op.hs.read(&beta, nrm + 2, sizeof(double), st);
+    // columns 0 .. enqueued-1 hold every step that can have run
+    std::vector<double>& Hh = Hh_;
+    std::vector<double>& Bh = Bh_;
+    const size_t hcols = size_t(std::max(enqueued, 1));
+    if (Hh.size() < 2 * size_t(ldh) * hcols) Hh.resize(2 * size_t(ldh) * hcols);
+    op.hs.read(Hh.data(), ad.H, 2 * size_t(ldh) * hcols * sizeof(double), st);
+    if (kC) {
+      if (Bh.size() < 2 * size_t(ad.ldb) * hcols) Bh.resize(2 * size_t(ad.ldb) * hcols);
+      op.hs.read(Bh.data(), ad.Bk, 2 * size_t(ad.ldb) * hcols * sizeof(double), st);
+    }
     op.hs.wait(st);
     c.jd = flags[1];
     c.breakdown = flags[2] != 0;
@@ -869,6 +886,7 @@ struct Krylov {
     // steps past the stopping one were enqueued but exited at entry
     matvecs -= long(enqueued - c.jd) * (has_poly() ? long(var.theta.size()) : 1L);
     c.est = est;
+    c.beta = beta;
     c.H = Mat(c.jd + 1, c.jd);
     for (int jj = 0; jj < c.jd; ++jj)
       for (int i = 0; i <= jj + 1; ++i)
@@ -997,7 +1015,7 @@ struct Krylov {
              double& relres) {
     const long mv0 = matvecs;
     if (!use_x0) launch_zero(p, x, N, st);
-    const double bn = norm(b);
+    const double bn = bn_hint > 0.0 ? bn_hint : norm(b);
     if (bn == 0.0) {
       launch_zero(p, x, N, st);
       relres = 0.0;
@@ -1028,7 +1046,12 @@ struct Krylov {
     bool converged = false;
     if (k > 0 && var.kcur > 0) {
       deflate_start(x);
-      beta = norm(rhat);
+      if (inner_est && !bjinv) {
+        launch_norm_root(nrm, nrm + 2, st);   // ||rhat|| stays on the device
+        beta = -1.0;
+      } else {
+        beta = norm(rhat);
+      }
     } else if (k > 0) {
       // construction cycle: GMRES(m) of at least k steps
       const int steps = std::min(m, ldh - 2);
@@ -1056,26 +1079,31 @@ struct Krylov {
     int stall = 0;
     while (true) {
       const bool by_est = inner_est && !bjinv && k > 0 && var.kcur > 0;
-      rn = by_est ? beta : true_resid(x, b, rtrue);
-      relres = rn / bn;
-      if (relres <= tol) {
-        converged = true;
-        break;
-      }
-      if (cycles >= max_cycles) break;
-      if (rn < 0.99 * best) {
-        best = rn;
-        stall = 0;
-      } else if (++stall >= 10 && o.ortho == 1 && k > 0 && var.kcur > 0) {
-        // single-sync solves: the recursively updated residual no longer tracks
-        // the true one (loss of orthogonality); restart from the true
-        // residual, deflated, with Gram-Schmidt twice
-        stall = 0;
-        ss_off = true;
-        if (by_est) rn = true_resid(x, b, rtrue);
-        left_precondition(rtrue, rhat);
-        deflate_start(x);
-        beta = norm(rhat);
+      if (by_est && beta < 0.0) {
+        // the deflated start's norm is on the device: straight to a cycle
+        if (cycles >= max_cycles) break;
+      } else {
+        rn = by_est ? beta : true_resid(x, b, rtrue);
+        relres = rn / bn;
+        if (relres <= tol) {
+          converged = true;
+          break;
+        }
+        if (cycles >= max_cycles) break;
+        if (rn < 0.99 * best) {
+          best = rn;
+          stall = 0;
+        } else if (++stall >= 10 && o.ortho == 1 && k > 0 && var.kcur > 0) {
+          // single-sync solves: the recursively updated residual no longer tracks
+          // the true one (loss of orthogonality); restart from the true
+          // residual, deflated, with Gram-Schmidt twice
+          stall = 0;
+          ss_off = true;
+          if (by_est) rn = true_resid(x, b, rtrue);
+          left_precondition(rtrue, rhat);
+          deflate_start(x);
+          beta = norm(rhat);
+        }
       }
       if (k == 0 || var.kcur == 0) {
         // plain GMRES(m) cycle from the (left-preconditioned) true residual
@@ -1115,26 +1143,36 @@ struct Krylov {
         for (int i = 0; i <= jj + 1; ++i) G(kk + i, kk + jj) = c.H(i, jj);
       }
       double lsres;
-      const auto y = gcrodr_lstsq(c.H, c.Bk, var.unorm, beta, &lsres);
+      const auto y = gcrodr_lstsq(c.H, c.Bk, var.unorm, c.beta, &lsres);
       stt.rel_res_est = lsres / bn;
       // x += q(A~) Vhat y, Vhat = [U D_k, V_jd]
       std::vector<cd> cy(kk + jd);
       for (int i = 0; i < kk; ++i) cy[i] = y[i] / var.unorm[i];
       for (int i = 0; i < jd; ++i) cy[kk + i] = y[kk + i];
       update_x(x, kk, jd, cy);
-      // rhat -= What (G y), What = [C, V_{jd+1}]
-      Mat ym(kk + jd, 1);
-      for (int i = 0; i < kk + jd; ++i) ym(i, 0) = y[i];
-      const Mat Gy = matmul(G, ym);
-      std::vector<cd> gy(kk + jd + 1);
-      for (int i = 0; i < kk + jd + 1; ++i) gy[i] = Gy(i, 0);
-      upload_coef(gy);
-      launch_multiaxpy(p, rhat, Cv(), kk, V(0), jd + 1, N, coef, 1, op.red(), nrm, nullptr, st);
-      double h;
-      op.hs.read(&h, nrm, sizeof(double), st);
-      op.hs.wait(st);
-      beta = std::sqrt(std::max(h, 0.0));
+      // inner solves: the least-squares residual is the norm the update of
+      // rhat would give, so a converged cycle skips that update
+      const bool est_conv = by_est && lsres <= tol * bn;
+      if (!est_conv) {
+        // rhat -= What (G y), What = [C, V_{jd+1}]
+        Mat ym(kk + jd, 1);
+        for (int i = 0; i < kk + jd; ++i) ym(i, 0) = y[i];
+        const Mat Gy = matmul(G, ym);
+        std::vector<cd> gy(kk + jd + 1);
+        for (int i = 0; i < kk + jd + 1; ++i) gy[i] = Gy(i, 0);
+        upload_coef(gy);
+        launch_multiaxpy(p, rhat, Cv(), kk, V(0), jd + 1, N, coef, 1, op.red(), nrm, nullptr, st);
+        double h;
+        op.hs.read(&h, nrm, sizeof(double), st);
+        op.hs.wait(st);
+        beta = std::sqrt(std::max(h, 0.0));
+      }
       if (var.updates < o.u && jd > 0) refresh_recycle(c, G);
+      if (est_conv) {
+        converged = true;
+        relres = lsres / bn;
+        break;
+      }
       if (jd == 0) break;
     }
     stt.cycles += cycles;
@@ -1431,6 +1469,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       z64* Zb = op.zouter.as<z64>();
       Krylov<float> KI(op, var, o, var.ws, var.sm, o.m, st);
       KI.inner_est = true;
+      KI.bn_hint = 1.0;   // the right-hand sides are the outer basis vectors
       op.t32a.ensure(N * sizeof(z32));
       op.t32b.ensure(N * sizeof(z32));
       z32* b32 = op.t32a.as<z32>();
