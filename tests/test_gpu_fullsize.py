@@ -1,6 +1,8 @@
 """Parity at full configuration sizes (GPU): sampled outputs that the oracle
 computes one site at a time, and properties that hold at any size.
 
+c2: 8^4, N_tv = 24 - the odd-even reduced apply of the benchmark at sampled
+rows, in three precisions.
 c3: 16^3 x 32, N_tv = 24, twisted mass 1e-3 (6.29M unknowns) - apply in three
 precisions at sampled sites; a mixed-precision solve whose residual is
 re-checked at sampled sites (to 1e-4 here: a solve to 1e-8 takes ~110 s on
@@ -17,6 +19,7 @@ import torch
 import synth
 from oracle import mixed
 from oracle import operator as dop
+from oracle import schur
 from oracle.lattice import neighbours
 
 from .helpers import log
@@ -115,6 +118,73 @@ def test_c3_mixed_solve(c3):
     xh = x.cpu().numpy()
     rs = b.cpu().numpy()[sites] - oracle_rows(w, m0, xh, sites)
     assert np.abs(rs - r.cpu().numpy()[sites]).max() <= 1e-12 * np.abs(b.cpu().numpy()).max()
+
+
+def _coded(M, store):
+    """M in the storage precision (decoded to complex128)."""
+    if store == "f32":
+        return mixed.round_fp32(M).astype(np.complex128)
+    if store == "f16s":
+        return mixed.dequantize_fp16(*mixed.quantize_fp16(M)).astype(np.complex128)
+    return M
+
+
+def reduced_rows(w, m0, xe, rows, store="f64"):
+    """(S x_e) at compressed even rows (Sec. 2.2, factored form) from the blocks
+    each row touches: at the 8 odd neighbours y of the row's site s,
+    t_y = (A_y + i mu Gamma5)^{-1} (D_oe x_e)_y with the inverse formed in FP64
+    and then held in the storage precision; then
+    (A_s + i mu Gamma5) x_s - (D_eo t)_s."""
+    fwd, bwd = neighbours(w.dims)
+    even, odd = schur.sites(w.dims, 0), schur.sites(w.dims, 1)
+    row = np.empty(w.V, dtype=np.int64)
+    row[even] = np.arange(even.size)
+    row[odd] = np.arange(odd.size)
+    n = 2 * w.n_tv
+    tm = 1j * w.mu * np.diag(dop.gamma5(n))
+    zero = np.zeros((n, n), dtype=np.complex128)
+    out = []
+    for r in rows:
+        s = int(even[r])
+        t = {}
+        for y in sorted(set(fwd[:, s].tolist()) | set(bwd[:, s].tolist())):
+            _, B, Bb = site_blocks(w, m0, y, bwd, store)
+            u = dop.apply_site(zero, B, Bb, np.zeros(n, dtype=np.complex128),
+                               xe[row[fwd[:, y]]], xe[row[bwd[:, y]]], 0.0)
+            A64 = synth.self_blocks(w.dims, w.n_tv, m0, w.seed, sites=[y]).numpy()[0]
+            t[y] = _coded(np.linalg.inv(A64 + tm), store) @ u
+        A, B, Bb = site_blocks(w, m0, s, bwd, store)
+        tf = -np.stack([t[int(y)] for y in fwd[:, s]])
+        tb = -np.stack([t[int(y)] for y in bwd[:, s]])
+        out.append(dop.apply_site(A, B, Bb, xe[r], tf, tb, w.mu))
+    return np.stack(out)
+
+
+def test_c2_reduced_apply_sampled_rows():
+    """The benchmark's operator and kernels at full size (c2, odd-even reduced,
+    2,048 rows per launch): S x_e at sampled rows against the oracle's factored
+    form evaluated row by row, in each storage precision."""
+    log("build c2 (8^4, n = 48), reduced apply at sampled rows")
+    op, w = build("c2", ("f64", "f32", "f16s"))
+    m0 = w.m0()
+    ne = w.V // 2
+    xe = synth.vector(w.dims, w.n_tv, synth.STREAM_AUX, 12, device="cuda")[:ne].contiguous()
+    rows = sample_sites(ne, 16, 5)
+    xh = xe.cpu().numpy()
+    y = op.apply_reduced(xe).cpu().numpy()
+    ref = reduced_rows(w, m0, xh, rows)
+    err = np.abs(y[rows] - ref).max() / np.abs(ref).max()
+    log(f"c2 f64 reduced sampled rows: {err:.2e}")
+    assert err <= 1e-13
+    x32 = xe.to(torch.complex64)
+    xh32 = x32.cpu().numpy().astype(np.complex128)
+    for prec in ("f32", "f16s"):
+        y = op.apply_reduced(x32, prec=prec).cpu().numpy()
+        ref = reduced_rows(w, m0, xh32, rows, store=prec)
+        err = np.abs(y[rows] - ref).max() / np.abs(ref).max()
+        log(f"c2 {prec} reduced sampled rows: {err:.2e}")
+        assert err <= 2e-5
+    op.close()
 
 
 def test_c4_batched_solve():
