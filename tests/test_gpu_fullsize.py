@@ -187,6 +187,43 @@ def test_c2_reduced_apply_sampled_rows():
     op.close()
 
 
+def test_c2_benchmark_method_solves():
+    """The benchmark's method and launch configuration on c2 (odd-even reduced
+    system, FP64 flexible outer loop, FP16-stored inner GCRO-DR(126, 96) with a
+    degree-32 polynomial and single-sync Arnoldi, recycle space frozen after two
+    solves): every solve meets 1e-8 on the full-lattice residual computed by the
+    oracle's FP64 apply, and the first and a later right-hand side agree with a
+    plain FP64 solve to the accuracy the residual allows."""
+    from paper_2205_09104_amd import Opts
+    log("build c2 (8^4, n = 48), benchmark method solves")
+    w = synth.WORKLOADS["c2"]
+    A, B = synth.operator(w)
+    from paper_2205_09104_amd import CoarseOp
+    op = CoarseOp(A.cuda(), B.cuda(), w.dims, mu=w.mu, store=("f64", "f32", "f16s"))
+    oop = dop.build(w.dims, A.numpy(), B.numpy(), w.mu)
+    del A, B
+    o = Opts(m=126, k=96, d=32, u=10, prec="f16s", outer=1, m_outer=10, max_outer=50,
+             inner_tol=0.1, seed=1, max_cycles=100000, schur=1, ortho=1)
+    tol = 1e-8
+    for r in range(5):
+        b = synth.rhs(w.dims, w.n_tv, r, device="cuda")
+        x, st, rc = op.solve(b, tol, o)
+        bh = b.cpu().numpy()
+        rel = np.linalg.norm(bh - dop.apply(oop, x.cpu().numpy())) / np.linalg.norm(bh)
+        log(f"c2 solve {r}: rc {rc} oracle rel {rel:.2e} matvecs {st[0]['matvecs']} "
+            f"outer {st[0]['outer_iters']}")
+        assert rc == 0 and rel <= tol
+        assert abs(rel - st[0]["rel_res_true"]) <= 1e-3 * rel + 1e-15
+        if r in (0, 4):
+            x64, s64, rc64 = op.solve(b, 1e-12, Opts(m=126, k=96, d=32, u=10, seed=1,
+                                                     max_cycles=100000, schur=1))
+            assert rc64 == 0
+            err = float(torch.linalg.vector_norm(x - x64) / torch.linalg.vector_norm(x64))
+            log(f"c2 solve {r}: forward error against FP64 {err:.2e}")
+            assert err <= 1e-5
+    op.close()
+
+
 def test_c4_batched_solve():
     from paper_2205_09104_amd import Opts
     log("build c4 (16^4, n = 48)")
