@@ -2645,6 +2645,26 @@ void launch_copy_words(const void* src, void* dst, size_t bytes, hipStream_t st)
   DC_HIP(hipGetLastError());
 }
 
+// Several segments of 4-byte words in one launch (blockIdx.y = segment).
+__global__ void k_copy_segments(CopySegments s) {
+  const int g = blockIdx.y;
+  const uint32_t* __restrict__ src = s.src[g];
+  uint32_t* __restrict__ dst = s.dst[g];
+  const size_t n = s.words[g];
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
+void launch_copy_segments(const CopySegments& s, hipStream_t st) {
+  if (s.count <= 0) return;
+  if (s.count > kCopySegMax) throw std::invalid_argument("too many copy segments");
+  size_t most = 0;
+  for (int g = 0; g < s.count; ++g) most = std::max(most, s.words[g]);
+  const dim3 grid(grid_for(most, 256, 256), unsigned(s.count)), block(256);
+  hipLaunchKernelGGL(k_copy_segments, grid, block, 0, st, s);
+  DC_HIP(hipGetLastError());
+}
+
 void launch_zero(Prec p, void* x, size_t N, hipStream_t st) {
   const dim3 grid(grid_for(N, 256)), block(256);
   if (p == P64)

@@ -169,6 +169,15 @@ void launch_zero(Prec p, void* x, size_t N, hipStream_t st);
 // bytes (a multiple of 4, both pointers 4-byte aligned) from src to dst, one of
 // them host-mapped pinned memory given by its device address
 void launch_copy_words(const void* src, void* dst, size_t bytes, hipStream_t st);
+// up to kCopySegMax independent copies of 4-byte words in one launch
+constexpr int kCopySegMax = 8;
+struct CopySegments {
+  const uint32_t* src[kCopySegMax];
+  uint32_t* dst[kCopySegMax];
+  size_t words[kCopySegMax];
+  int count = 0;
+};
+void launch_copy_segments(const CopySegments& s, hipStream_t st);
 // y = a*x + y (complex a)
 void launch_axpy(Prec p, z64 a, const void* x, void* y, size_t N, hipStream_t st);
 // result[0] = ||x||^2

@@ -227,7 +227,7 @@ static char* mapped_alloc(size_t bytes, char** dev) {
 void HostStage::read(void* dst, const void* src, size_t bytes, hipStream_t st) {
   const size_t off = (rd_used + 15) & ~size_t(15);
   if (off + bytes > rd_cap) {
-    wait(st);                    // no read may be in flight while the area is replaced
+    wait(st);                    // no read may be pending while the area is replaced
     size_t cap = std::max<size_t>(size_t(1) << 20, 2 * rd_cap);
     while (cap < bytes) cap *= 2;
     if (rd) retired.push_back(rd);
@@ -236,12 +236,26 @@ void HostStage::read(void* dst, const void* src, size_t bytes, hipStream_t st) {
     read(dst, src, bytes, st);
     return;
   }
-  launch_copy_words(src, rd_dev + off, bytes, st);
-  pending.push_back({dst, off, bytes});
+  if (bytes % 4 != 0 || reinterpret_cast<uintptr_t>(src) % 4 != 0)
+    throw InvalidArg("staged reads move aligned 4-byte words");
+  pending.push_back({dst, src, off, bytes});
   rd_used = off + bytes;
 }
 
 void HostStage::wait(hipStream_t st) {
+  CopySegments seg;
+  for (const Pending& q : pending) {
+    if (q.bytes == 0) continue;
+    if (seg.count == kCopySegMax) {
+      launch_copy_segments(seg, st);
+      seg.count = 0;
+    }
+    seg.src[seg.count] = static_cast<const uint32_t*>(q.src);
+    seg.dst[seg.count] = reinterpret_cast<uint32_t*>(rd_dev + q.off);
+    seg.words[seg.count] = q.bytes / 4;
+    ++seg.count;
+  }
+  launch_copy_segments(seg, st);
   stream_wait(st);
   for (const Pending& q : pending) std::memcpy(q.dst, rd + q.off, q.bytes);
   pending.clear();
@@ -1135,13 +1149,22 @@ struct Krylov {
       ++cycles;
       stt.iters += c.jd;
       const int jd = c.jd;
-      // G = [[D_k, B_k], [0, Hbar]]
-      Mat G(kk + jd + 1, kk + jd);
-      for (int i = 0; i < kk; ++i) G(i, i) = 1.0 / var.unorm[i];
-      for (int jj = 0; jj < jd; ++jj) {
-        for (int i = 0; i < kk; ++i) G(i, kk + jj) = c.Bk(i, jj);
-        for (int i = 0; i <= jj + 1; ++i) G(kk + i, kk + jj) = c.H(i, jj);
-      }
+      // G = [[D_k, B_k], [0, Hbar]], formed only when the residual update or
+      // a refresh needs it
+      Mat G;
+      bool have_G = false;
+      auto get_G = [&]() -> const Mat& {
+        if (!have_G) {
+          G = Mat(kk + jd + 1, kk + jd);
+          for (int i = 0; i < kk; ++i) G(i, i) = 1.0 / var.unorm[i];
+          for (int jj = 0; jj < jd; ++jj) {
+            for (int i = 0; i < kk; ++i) G(i, kk + jj) = c.Bk(i, jj);
+            for (int i = 0; i <= jj + 1; ++i) G(kk + i, kk + jj) = c.H(i, jj);
+          }
+          have_G = true;
+        }
+        return G;
+      };
       double lsres;
       const auto y = gcrodr_lstsq(c.H, c.Bk, var.unorm, c.beta, &lsres);
       stt.rel_res_est = lsres / bn;
@@ -1157,7 +1180,7 @@ struct Krylov {
         // rhat -= What (G y), What = [C, V_{jd+1}]
         Mat ym(kk + jd, 1);
         for (int i = 0; i < kk + jd; ++i) ym(i, 0) = y[i];
-        const Mat Gy = matmul(G, ym);
+        const Mat Gy = matmul(get_G(), ym);
         std::vector<cd> gy(kk + jd + 1);
         for (int i = 0; i < kk + jd + 1; ++i) gy[i] = Gy(i, 0);
         upload_coef(gy);
@@ -1167,7 +1190,7 @@ struct Krylov {
         op.hs.wait(st);
         beta = std::sqrt(std::max(h, 0.0));
       }
-      if (var.updates < o.u && jd > 0) refresh_recycle(c, G);
+      if (var.updates < o.u && jd > 0) refresh_recycle(c, get_G());
       if (est_conv) {
         converged = true;
         relres = lsres / bn;

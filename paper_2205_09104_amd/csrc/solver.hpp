@@ -114,11 +114,13 @@ struct ApplyProfile {
 // uploads go through a ring of pinned slots, each reused only after the event
 // recorded behind its previous copy has completed.
 // Small transfers between the host logic and the device, in host-mapped
-// pinned memory moved by copy kernels on the stream (queued in order with the
-// kernels around them).  Areas that kernels have touched are released only
-// with the stage.
+// pinned memory moved by copy kernels on the stream.  Uploads are queued in
+// order with the kernels around them.  Reads are gathered: the copies run, in
+// as few launches as possible, when wait() is called, so work queued between
+// read() and wait() must not change what is read.  Areas that kernels have
+// touched are released only with the stage.
 struct HostStage {
-  struct Pending { void* dst; size_t off, bytes; };
+  struct Pending { void* dst; const void* src; size_t off, bytes; };
   char* rd = nullptr;            // read area (host address)
   char* rd_dev = nullptr;        // its device address
   size_t rd_cap = 0, rd_used = 0;
