@@ -435,6 +435,61 @@ struct BlockGmres {
     return true;
   }
 
+  // Residual columns R (nr of them, in V) that are numerically dependent: the
+  // block that generates the Krylov space is the orthonormalised subset of
+  // columns picked by a pivoted Cholesky factorisation of their scaled Gram
+  // matrix (each pick keeps at least sel_piv of its squared norm outside the
+  // span of the earlier picks).  On return V holds that basis V_0 (the count is
+  // returned), S0 = V_0^H R (nb x nr) and drop[a] = ||R_a - V_0 S0_a||; R is
+  // kept in U.  0 if not even the first pick orthonormalises.
+  int select_block(int nr, Mat& S0, std::vector<double>& drop) {
+    const Mat G = tn(V, nr, V, nr);
+    std::vector<double> d(nr);
+    for (int i = 0; i < nr; ++i) d[i] = std::sqrt(std::max(G(i, i).real(), 0.0));
+    // pivoted Cholesky of Gs = D^{-1} G D^{-1}: Schur-complement diagonal
+    const double sel_piv = (sizeof(VR) == 8) ? 1e-12 : 1e-6;
+    std::vector<double> rest(nr);
+    for (int i = 0; i < nr; ++i) rest[i] = d[i] > 0.0 ? 1.0 : 0.0;
+    Mat L(nr, nr);
+    std::vector<int> pick;
+    for (int k = 0; k < nr; ++k) {
+      int best = -1;
+      for (int i = 0; i < nr; ++i)
+        if (std::find(pick.begin(), pick.end(), i) == pick.end() &&
+            (best < 0 || rest[i] > rest[best]))
+          best = i;
+      if (best < 0 || !(rest[best] > sel_piv)) break;
+      const double lkk = std::sqrt(rest[best]);
+      for (int i = 0; i < nr; ++i) {
+        if (std::find(pick.begin(), pick.end(), i) != pick.end() || i == best) continue;
+        if (!(d[i] > 0.0)) continue;
+        cd t = G(i, best) / (d[i] * d[best]);
+        for (int q = 0; q < k; ++q) t -= L(i, q) * std::conj(L(best, q));
+        L(i, k) = t / lkk;
+        rest[i] -= std::norm(L(i, k));
+      }
+      L(best, k) = lkk;
+      pick.push_back(best);
+    }
+    const int nb = int(pick.size());
+    if (nb == 0) return 0;
+    DC_HIP(hipMemcpyAsync(U, V, size_t(nr) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    for (int t = 0; t < nb; ++t)
+      DC_HIP(hipMemcpyAsync(T1 + size_t(t) * N, U + size_t(pick[size_t(t)]) * N, N * sizeof(Z),
+                            hipMemcpyDeviceToDevice, st));
+    Mat Rsel;
+    DC_HIP(hipMemcpyAsync(V, T1, size_t(nb) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    if (!cholqr2(V, V, nb, Rsel)) return 0;
+    S0 = tn(V, nb, U, nr);
+    drop.assign(nr, 0.0);
+    for (int a = 0; a < nr; ++a) {
+      double s = 0.0;
+      for (int i = 0; i < nb; ++i) s += std::norm(S0(i, a));
+      drop[a] = std::sqrt(std::max(G(a, a).real() - s, 0.0));
+    }
+    return nb;
+  }
+
   struct Cycle {
     int steps = 0;
     Mat Y;          // (steps r) x r coefficients
@@ -442,21 +497,24 @@ struct BlockGmres {
     std::vector<double> est;
   };
 
-  // One cycle from the orthonormal block V_0 (r columns) with R_0 = V_0 S0; the
-  // cycle ends when every column's least-squares residual is at or below its
-  // target, after m steps, or when a new block is rank deficient.
-  Cycle cycle(int r, const Mat& S0, const std::vector<double>& target) {
+  // One cycle from the orthonormal block V_0 (nr columns) for nc residual
+  // columns R_0 = V_0 S0 + E (S0 nr x nc; E orthogonal to V_0, column norms
+  // drop, zero when V_0 spans R_0); every column takes its least-squares
+  // minimiser over the block space.  The cycle ends when every column's
+  // residual is at or below its target, after m steps, or when a new block is
+  // rank deficient.
+  Cycle cycle(int nr, int nc, const Mat& S0, const std::vector<double>& target,
+              const std::vector<double>& drop) {
     Cycle c;
-    const int nr = r;
     c.Bk = Mat(std::max(kc, 1), m * nr);
     Mat Rf((m + 1) * nr, m * nr);
-    Mat G((m + 1) * nr, nr);
-    for (int j = 0; j < nr; ++j)
+    Mat G((m + 1) * nr, nc);
+    for (int j = 0; j < nc; ++j)
       for (int i = 0; i < nr; ++i) G(i, j) = S0(i, j);
     std::vector<Mat> qhs;
-    c.est.assign(nr, 0.0);
-    for (int a = 0; a < nr; ++a) {
-      double s = 0.0;
+    c.est.assign(nc, 0.0);
+    for (int a = 0; a < nc; ++a) {
+      double s = drop[size_t(a)] * drop[size_t(a)];
       for (int i = 0; i < nr; ++i) s += std::norm(S0(i, a));
       c.est[a] = std::sqrt(s);
     }
@@ -512,17 +570,17 @@ struct BlockGmres {
       }
       qhs.push_back(qh);
       {
-        Mat gs(2 * nr, nr);
-        for (int b = 0; b < nr; ++b)
+        Mat gs(2 * nr, nc);
+        for (int b = 0; b < nc; ++b)
           for (int t = 0; t < 2 * nr; ++t) gs(t, b) = G(j * nr + t, b);
         const Mat gr = matmul(qh, gs);
-        for (int b = 0; b < nr; ++b)
+        for (int b = 0; b < nc; ++b)
           for (int t = 0; t < 2 * nr; ++t) G(j * nr + t, b) = gr(t, b);
       }
       c.steps = j + 1;
       bool done = true;
-      for (int a = 0; a < nr; ++a) {
-        double s = 0.0;
+      for (int a = 0; a < nc; ++a) {
+        double s = drop[size_t(a)] * drop[size_t(a)];
         for (int t = 0; t < nr; ++t) s += std::norm(G((j + 1) * nr + t, a));
         c.est[a] = std::sqrt(s);
         if (c.est[a] > target[size_t(a)]) done = false;
@@ -531,8 +589,8 @@ struct BlockGmres {
     }
     // back substitution: Rf(0:s, 0:s) Y = G(0:s, :)
     const int s = c.steps * nr;
-    c.Y = Mat(s, nr);
-    for (int b = 0; b < nr; ++b)
+    c.Y = Mat(s, nc);
+    for (int b = 0; b < nc; ++b)
       for (int i = s - 1; i >= 0; --i) {
         cd t = G(i, b);
         for (int k = i + 1; k < s; ++k) t -= Rf(i, k) * c.Y(k, b);
@@ -553,7 +611,6 @@ struct BlockGmres {
     for (int c = 0; c < R; ++c)
       if (bn[c] > 0.0) act.push_back(c);
     bool first = true;
-    bool single = false;   // dependent residual columns: one column per cycle
     for (int cyc = 0;; ++cyc) {
       const int r = int(act.size());
       if (r == 0) break;
@@ -589,7 +646,7 @@ struct BlockGmres {
       std::vector<int> act2(keep.size());
       for (size_t t = 0; t < keep.size(); ++t) act2[t] = act[size_t(keep[t])];
       act = act2;
-      const int nr = single ? 1 : int(act.size());
+      const int nr = int(act.size());
       if (kc) {   // new residuals with a recycle space: x += q(A) U C^H r; r -= C C^H r
         write_mat(Bd, tn(Cr, kc, V, nr));
         gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, kc, -1.0, Cr, int(N), Bd, kc,
@@ -598,20 +655,23 @@ struct BlockGmres {
         for (int a = 0; a < nr; ++a) xc[a] = X + size_t(act[a]) * N;
         add_recycled(Bd, nr, xc);
       }
+      // the block that generates the space: every residual column, or a
+      // well-conditioned subset of them when they are numerically dependent
       Mat S0;
+      std::vector<double> drop(nr, 0.0);
+      int nb = nr;
       if (!cholqr2(V, V, nr, S0)) {
-        if (nr == 1) break;   // a zero residual column cannot occur here (rel > tol)
-        single = true;        // dependent columns: solve them one at a time
-        continue;
+        nb = select_block(nr, S0, drop);
+        if (nb == 0) break;
       }
       std::vector<double> target(nr);
       for (int a = 0; a < nr; ++a) target[a] = tol[act[a]] * bn[act[a]];
-      const Cycle c = cycle(nr, S0, target);
+      const Cycle c = cycle(nb, nr, S0, target, drop);
       for (int a = 0; a < nr; ++a) {
         stats[act[a]].iters += c.steps;
         stats[act[a]].cycles += 1;
       }
-      const int s = c.steps * nr;
+      const int s = c.steps * nb;
       if (s == 0) break;
       write_mat(Yd, c.Y);
       gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, s, 1.0,

@@ -113,6 +113,27 @@ def test_block_solve_continues_from_start_vector(c1, prec):
         assert oracle_relres(oop, Xh[c], B[c].cpu().numpy()) <= tols[c] * 1.0001
 
 
+@pytest.mark.parametrize("prec,eps", [("f64", 1e-13), ("f16s", 1e-7)])
+def test_block_solve_with_dependent_columns(c1, prec, eps):
+    """Right-hand sides that are numerically dependent (two columns within eps
+    of two others): the space grows from a well-conditioned subset of the
+    residual columns and every column still meets its tolerance."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, D = c1
+    log("block gmres dependent columns", prec)
+    b = [synth.rhs(w.dims, w.n_tv, 110 + r) for r in range(4)]
+    B = torch.stack([b[0], b[1], b[0] + eps * b[2], b[1] - eps * b[3]]).cuda()
+    tols = np.array([1e-10, 1e-9, 1e-10, 1e-8])
+    o = (Opts(m=12) if prec == "f64" else
+         Opts(m=8, d=4, seed=1, prec="f16s", inner_tol=1e-2, max_outer=40))
+    X, st, rc = gop.solve_block(B, tols, o)
+    assert rc == 0, st
+    Xh = X.cpu().numpy()
+    Bh = B.cpu().numpy()
+    for c in range(4):
+        assert oracle_relres(oop, Xh[c], Bh[c]) <= tols[c] * 1.0001
+
+
 def test_single_column_is_gmres(c1):
     """With one right-hand side the block process is GMRES(m): the same number
     of Arnoldi steps as the single-RHS solver (to a step or two of rounding)."""
