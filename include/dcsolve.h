@@ -246,7 +246,10 @@ int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, i
  * column takes its minimal-residual correction in the whole block space and
  * leaves the block when its true residual meets tol[r].  A cycle ends after
  * opts->m block steps, when all columns' least-squares residuals meet their
- * targets, or when a new block is rank deficient.  If opts->k > 0 and
+ * targets, or when a new block is rank deficient.  Numerically dependent
+ * residual columns: the space grows from a well-conditioned subset of them
+ * (pivoted Cholesky of their scaled Gram matrix) and every column takes its
+ * minimiser over it.  If opts->k > 0 and
  * solve_coarse built a recycle space for the same variant (prec, d, full
  * lattice), every cycle is deflated against it without refreshing it (Sec.
  * 3.4): new residual blocks start with x += q(A) U C^H r, r -= C C^H r, the
