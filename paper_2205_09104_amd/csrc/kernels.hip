@@ -1494,6 +1494,50 @@ __global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0,
   }
 }
 
+// The update kernels split the basis between the kSplitWaves waves of a
+// workgroup: each wave takes every kSplitWaves-th chunk of kAxpyG vectors (the
+// loads of a chunk issued before their arithmetic) for the same 64 kDotE
+// elements, so a wave waits on a quarter of the chunks; the partial sums are
+// then combined through LDS in a fixed order.  Elements of a pass:
+// base + e 64 + lane.
+constexpr int kSplitWaves = 4;   // waves per workgroup (256 threads)
+
+template <typename VR>
+__device__ inline void split_sums(const cx<VR>* __restrict__ b0, int q0,
+                                  const cx<VR>* __restrict__ b1, size_t N, int Q,
+                                  const double* __restrict__ coef, size_t base, int lane,
+                                  int wave, size_t (&idx)[kDotE], double (&sr)[kDotE],
+                                  double (&si)[kDotE]) {
+#pragma unroll
+  for (int e = 0; e < kDotE; ++e) {
+    const size_t i = base + size_t(e) * 64 + lane;
+    idx[e] = i < N ? i : N - 1;
+    sr[e] = si[e] = 0.0;
+  }
+  for (int qc = wave * kAxpyG; qc < Q; qc += kSplitWaves * kAxpyG) {
+    cx<VR> v[kAxpyG][kDotE];
+#pragma unroll
+    for (int t = 0; t < kAxpyG; ++t) {
+      const int q = min(qc + t, Q - 1);
+      const cx<VR>* p = basis_ptr(b0, q0, b1, N, q);
+#pragma unroll
+      for (int e = 0; e < kDotE; ++e) v[t][e] = p[idx[e]];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int t = 0; t < kAxpyG; ++t) {
+      const int q = qc + t;
+      const double cr = q < Q ? coef[2 * q] : 0.0, ci = q < Q ? coef[2 * q + 1] : 0.0;
+#pragma unroll
+      for (int e = 0; e < kDotE; ++e) {
+        const double vr = v[t][e].re, vi = v[t][e].im;
+        sr[e] = fma(cr, vr, fma(-ci, vi, sr[e]));
+        si[e] = fma(cr, vi, fma(ci, vr, si[e]));
+      }
+    }
+  }
+}
+
 // out = (w - sum_q coef_q basis_q) (times *scale when scale is given; then the
 // launch belongs to Arnoldi step j and runs only if that step's bookkeeping
 // ran, *jdone == j + 1, instead of checking the stop flag).  out may be w.
@@ -1513,50 +1557,38 @@ __global__ __launch_bounds__(256) void k_multiaxpy(const cx<VR>* w, cx<VR>* out,
   }
   const double sc = scale ? *scale : 1.0;
   const int Q = q0 + q1;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double part[kSplitWaves][kDotE][2][64];
   double nacc[1] = {0.0};
-  const size_t chunk = size_t(blockDim.x) * kDotE;
-  const size_t stride = size_t(gridDim.x) * chunk;
-  for (size_t base = size_t(blockIdx.x) * chunk + threadIdx.x; base < N; base += stride) {
+  const size_t span = size_t(64) * kDotE;
+  for (size_t base = size_t(blockIdx.x) * span; base < N; base += size_t(gridDim.x) * span) {
     size_t idx[kDotE];
     double sr[kDotE], si[kDotE];
+    split_sums<VR>(b0, q0, b1, N, Q, coef, base, lane, wave, idx, sr, si);
 #pragma unroll
     for (int e = 0; e < kDotE; ++e) {
-      const size_t i = base + size_t(e) * blockDim.x;
-      idx[e] = i < N ? i : N - 1;
-      const cx<VR> wv = w[idx[e]];
-      sr[e] = wv.re;
-      si[e] = wv.im;
+      part[wave][e][0][lane] = sr[e];
+      part[wave][e][1][lane] = si[e];
     }
-    for (int qc = 0; qc < Q; qc += kAxpyG) {
-      cx<VR> v[kAxpyG][kDotE];
+    __syncthreads();
+    if (wave == 0) {
 #pragma unroll
-      for (int t = 0; t < kAxpyG; ++t) {
-        const int q = min(qc + t, Q - 1);
-        const cx<VR>* p = basis_ptr(b0, q0, b1, N, q);
+      for (int e = 0; e < kDotE; ++e) {
+        if (base + size_t(e) * 64 + lane < N) {
+          const cx<VR> wv = w[idx[e]];
+          double r = wv.re, im = wv.im;
 #pragma unroll
-        for (int e = 0; e < kDotE; ++e) v[t][e] = p[idx[e]];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = 0; t < kAxpyG; ++t) {
-        const int q = qc + t;
-        const double cr = q < Q ? coef[2 * q] : 0.0, ci = q < Q ? coef[2 * q + 1] : 0.0;
-#pragma unroll
-        for (int e = 0; e < kDotE; ++e) {
-          const double vr = v[t][e].re, vi = v[t][e].im;
-          sr[e] = fma(-cr, vr, fma(ci, vi, sr[e]));
-          si[e] = fma(-cr, vi, fma(-ci, vr, si[e]));
+          for (int v2 = 0; v2 < kSplitWaves; ++v2) {
+            r -= part[v2][e][0][lane];
+            im -= part[v2][e][1][lane];
+          }
+          const cx<VR> o = mk(VR(r * sc), VR(im * sc));
+          out[idx[e]] = o;
+          nacc[0] += double(o.re) * double(o.re) + double(o.im) * double(o.im);
         }
       }
     }
-#pragma unroll
-    for (int e = 0; e < kDotE; ++e) {
-      if (base + size_t(e) * blockDim.x < N) {
-        const cx<VR> o = mk(VR(sr[e] * sc), VR(si[e] * sc));
-        out[idx[e]] = o;
-        nacc[0] += double(o.re) * double(o.re) + double(o.im) * double(o.im);
-      }
-    }
+    __syncthreads();
   }
   if (want_norm) block_partials<1>(nacc, red.partials);
 }
@@ -1604,60 +1636,48 @@ __global__ __launch_bounds__(256) void k_combine(const cx<VR>* __restrict__ b0, 
   }
 }
 
-// One output (R = 1): out (+)= sum_q coef_q basis_q, with the loads of a
-// chunk of kAxpyG basis vectors issued before their arithmetic, as in the
-// update kernel (the general kernel above walks the basis one load at a time).
+// One output (R = 1): out (+)= sum_q coef_q basis_q with the basis split
+// between the waves as in the update kernel (the general kernel above walks
+// the basis one load at a time).
 template <typename VR>
 __global__ __launch_bounds__(256) void k_combine1(const cx<VR>* __restrict__ b0, int q0,
                                                   const cx<VR>* __restrict__ b1, int q1,
                                                   size_t N, const double* __restrict__ coef,
                                                   cx<VR>* __restrict__ out, int accumulate) {
   const int Q = q0 + q1;
-  const size_t chunk = size_t(blockDim.x) * kDotE;
-  const size_t stride = size_t(gridDim.x) * chunk;
-  for (size_t base = size_t(blockIdx.x) * chunk + threadIdx.x; base < N; base += stride) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __shared__ double part[kSplitWaves][kDotE][2][64];
+  const size_t span = size_t(64) * kDotE;
+  for (size_t base = size_t(blockIdx.x) * span; base < N; base += size_t(gridDim.x) * span) {
     size_t idx[kDotE];
     double sr[kDotE], si[kDotE];
+    split_sums<VR>(b0, q0, b1, N, Q, coef, base, lane, wave, idx, sr, si);
 #pragma unroll
     for (int e = 0; e < kDotE; ++e) {
-      const size_t i = base + size_t(e) * blockDim.x;
-      idx[e] = i < N ? i : N - 1;
-      sr[e] = si[e] = 0.0;
+      part[wave][e][0][lane] = sr[e];
+      part[wave][e][1][lane] = si[e];
     }
-    for (int qc = 0; qc < Q; qc += kAxpyG) {
-      cx<VR> v[kAxpyG][kDotE];
+    __syncthreads();
+    if (wave == 0) {
 #pragma unroll
-      for (int t = 0; t < kAxpyG; ++t) {
-        const int q = min(qc + t, Q - 1);
-        const cx<VR>* p = basis_ptr(b0, q0, b1, N, q);
+      for (int e = 0; e < kDotE; ++e) {
+        if (base + size_t(e) * 64 + lane < N) {
+          double r = 0.0, im = 0.0;
+          if (accumulate) {
+            const cx<VR> old = out[idx[e]];
+            r = old.re;
+            im = old.im;
+          }
 #pragma unroll
-        for (int e = 0; e < kDotE; ++e) v[t][e] = p[idx[e]];
-      }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int t = 0; t < kAxpyG; ++t) {
-        const int q = qc + t;
-        const double cr = q < Q ? coef[2 * q] : 0.0, ci = q < Q ? coef[2 * q + 1] : 0.0;
-#pragma unroll
-        for (int e = 0; e < kDotE; ++e) {
-          const double vr = v[t][e].re, vi = v[t][e].im;
-          sr[e] = fma(cr, vr, fma(-ci, vi, sr[e]));
-          si[e] = fma(cr, vi, fma(ci, vr, si[e]));
+          for (int v2 = 0; v2 < kSplitWaves; ++v2) {
+            r += part[v2][e][0][lane];
+            im += part[v2][e][1][lane];
+          }
+          out[idx[e]] = mk(VR(r), VR(im));
         }
       }
     }
-#pragma unroll
-    for (int e = 0; e < kDotE; ++e) {
-      if (base + size_t(e) * blockDim.x < N) {
-        cx<VR>* o = out + idx[e];
-        if (accumulate) {
-          const cx<VR> old = *o;
-          *o = mk(VR(double(old.re) + sr[e]), VR(double(old.im) + si[e]));
-        } else {
-          *o = mk(VR(sr[e]), VR(si[e]));
-        }
-      }
-    }
+    __syncthreads();
   }
 }
 
@@ -2514,8 +2534,8 @@ void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, i
                       const double* coef, int want_norm, Reducer red, double* result,
                       const int* done, hipStream_t st) {
   if (q0 + q1 == 0 && !want_norm) return;
-  size_t nb = (N + 256 * kDotE - 1) / (256 * kDotE);
-  if (nb > 2048) nb = 2048;
+  size_t nb = (N + 64 * kDotE - 1) / (64 * kDotE);   // one pass of 64 kDotE elements per workgroup
+  if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
   const dim3 grid{static_cast<unsigned>(nb)}, block{256};
   if (p == P64)
@@ -2535,8 +2555,8 @@ void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, i
 void launch_multiaxpy_scaled(Prec p, void* w, const void* b0, int q0, const void* b1, int q1,
                              size_t N, const double* coef, const double* scale, const int* jdone,
                              int j, hipStream_t st) {
-  size_t nb = (N + 256 * kDotE - 1) / (256 * kDotE);
-  if (nb > 2048) nb = 2048;
+  size_t nb = (N + 64 * kDotE - 1) / (64 * kDotE);   // one pass of 64 kDotE elements per workgroup
+  if (nb > 4096) nb = 4096;
   if (nb < 1) nb = 1;
   const dim3 grid{static_cast<unsigned>(nb)}, block{256};
   const Reducer none{};
@@ -2555,8 +2575,8 @@ void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size
                     const double* coef, int R, void* out, int accumulate, hipStream_t st) {
   if (R <= 0) return;
   if (R == 1) {
-    size_t nb = (N + 256 * kDotE - 1) / (256 * kDotE);
-    if (nb > 2048) nb = 2048;
+    size_t nb = (N + 64 * kDotE - 1) / (64 * kDotE);
+    if (nb > 4096) nb = 4096;
     if (nb < 1) nb = 1;
     const dim3 grid{static_cast<unsigned>(nb)}, block{256};
     if (q0 + q1 == 0) {
