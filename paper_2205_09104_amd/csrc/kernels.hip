@@ -1593,6 +1593,72 @@ __global__ __launch_bounds__(256) void k_multiaxpy(const cx<VR>* w, cx<VR>* out,
   if (want_norm) block_partials<1>(nacc, red.partials);
 }
 
+// Bases of at most one chunk (kAxpyG vectors): nothing to split between the
+// waves, so each thread takes its own kDotE elements through the whole basis.
+template <typename VR>
+__global__ __launch_bounds__(256) void k_multiaxpy_flat(const cx<VR>* w, cx<VR>* out,
+                                                   const cx<VR>* __restrict__ b0, int q0,
+                                                   const cx<VR>* __restrict__ b1, int q1,
+                                                   size_t N, const double* __restrict__ coef,
+                                                   int want_norm, Reducer red,
+                                                   const int* __restrict__ done,
+                                                   const double* __restrict__ scale,
+                                                   const int* __restrict__ jdone, int j) {
+  if (scale) {
+    if (*jdone != j + 1) return;
+  } else if (done && *done) {
+    return;
+  }
+  const double sc = scale ? *scale : 1.0;
+  const int Q = q0 + q1;
+  double nacc[1] = {0.0};
+  const size_t chunk = size_t(blockDim.x) * kDotE;
+  const size_t stride = size_t(gridDim.x) * chunk;
+  for (size_t base = size_t(blockIdx.x) * chunk + threadIdx.x; base < N; base += stride) {
+    size_t idx[kDotE];
+    double sr[kDotE], si[kDotE];
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+      const size_t i = base + size_t(e) * blockDim.x;
+      idx[e] = i < N ? i : N - 1;
+      const cx<VR> wv = w[idx[e]];
+      sr[e] = wv.re;
+      si[e] = wv.im;
+    }
+    for (int qc = 0; qc < Q; qc += kAxpyG) {
+      cx<VR> v[kAxpyG][kDotE];
+#pragma unroll
+      for (int t = 0; t < kAxpyG; ++t) {
+        const int q = min(qc + t, Q - 1);
+        const cx<VR>* p = basis_ptr(b0, q0, b1, N, q);
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) v[t][e] = p[idx[e]];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int t = 0; t < kAxpyG; ++t) {
+        const int q = qc + t;
+        const double cr = q < Q ? coef[2 * q] : 0.0, ci = q < Q ? coef[2 * q + 1] : 0.0;
+#pragma unroll
+        for (int e = 0; e < kDotE; ++e) {
+          const double vr = v[t][e].re, vi = v[t][e].im;
+          sr[e] = fma(-cr, vr, fma(ci, vi, sr[e]));
+          si[e] = fma(-cr, vi, fma(-ci, vr, si[e]));
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < kDotE; ++e) {
+      if (base + size_t(e) * blockDim.x < N) {
+        const cx<VR> o = mk(VR(sr[e] * sc), VR(si[e] * sc));
+        out[idx[e]] = o;
+        nacc[0] += double(o.re) * double(o.re) + double(o.im) * double(o.im);
+      }
+    }
+  }
+  if (want_norm) block_partials<1>(nacc, red.partials);
+}
+
 constexpr int kCombR = 16;  // outputs per pass of the combine kernel
 
 template <typename VR>
@@ -2530,45 +2596,48 @@ void launch_multidot(Prec p, const void* b0, int q0, const void* b1, int q1, siz
   finalize(red.partials, 2 * Q, int(gx), result, done, st);
 }
 
+// The update over Q basis vectors: the wave-split kernel when the basis has
+// more than one chunk, else the flat one.  Returns the number of norm partials.
+static unsigned multiaxpy_any(Prec p, void* w, const void* b0, int q0, const void* b1, int q1,
+                              size_t N, const double* coef, int want_norm, Reducer red,
+                              const int* done, const double* scale, const int* jdone, int j,
+                              hipStream_t st) {
+  const bool split = q0 + q1 > kAxpyG;
+  const size_t per = split ? size_t(64) * kDotE : size_t(256) * kDotE;
+  size_t nb = (N + per - 1) / per;
+  const size_t cap = split ? 4096 : 2048;
+  if (nb > cap) nb = cap;
+  if (nb < 1) nb = 1;
+  const dim3 grid{static_cast<unsigned>(nb)}, block{256};
+  if (p == P64) {
+    auto k = split ? k_multiaxpy<double> : k_multiaxpy_flat<double>;
+    hipLaunchKernelGGL(k, grid, block, 0, st, static_cast<const z64*>(w), static_cast<z64*>(w),
+                       static_cast<const z64*>(b0), q0, static_cast<const z64*>(b1), q1, N, coef,
+                       want_norm, red, done, scale, jdone, j);
+  } else {
+    auto k = split ? k_multiaxpy<float> : k_multiaxpy_flat<float>;
+    hipLaunchKernelGGL(k, grid, block, 0, st, static_cast<const z32*>(w), static_cast<z32*>(w),
+                       static_cast<const z32*>(b0), q0, static_cast<const z32*>(b1), q1, N, coef,
+                       want_norm, red, done, scale, jdone, j);
+  }
+  DC_HIP(hipGetLastError());
+  return unsigned(nb);
+}
+
 void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, int q1, size_t N,
                       const double* coef, int want_norm, Reducer red, double* result,
                       const int* done, hipStream_t st) {
   if (q0 + q1 == 0 && !want_norm) return;
-  size_t nb = (N + 64 * kDotE - 1) / (64 * kDotE);   // one pass of 64 kDotE elements per workgroup
-  if (nb > 4096) nb = 4096;
-  if (nb < 1) nb = 1;
-  const dim3 grid{static_cast<unsigned>(nb)}, block{256};
-  if (p == P64)
-    hipLaunchKernelGGL(k_multiaxpy<double>, grid, block, 0, st, static_cast<const z64*>(w),
-                       static_cast<z64*>(w), static_cast<const z64*>(b0), q0,
-                       static_cast<const z64*>(b1), q1, N, coef, want_norm, red, done, nullptr,
-                       nullptr, 0);
-  else
-    hipLaunchKernelGGL(k_multiaxpy<float>, grid, block, 0, st, static_cast<const z32*>(w),
-                       static_cast<z32*>(w), static_cast<const z32*>(b0), q0,
-                       static_cast<const z32*>(b1), q1, N, coef, want_norm, red, done, nullptr,
-                       nullptr, 0);
-  DC_HIP(hipGetLastError());
+  const unsigned nb = multiaxpy_any(p, w, b0, q0, b1, q1, N, coef, want_norm, red, done, nullptr,
+                                    nullptr, 0, st);
   if (want_norm) finalize(red.partials, 1, int(nb), result, done, st);
 }
 
 void launch_multiaxpy_scaled(Prec p, void* w, const void* b0, int q0, const void* b1, int q1,
                              size_t N, const double* coef, const double* scale, const int* jdone,
                              int j, hipStream_t st) {
-  size_t nb = (N + 64 * kDotE - 1) / (64 * kDotE);   // one pass of 64 kDotE elements per workgroup
-  if (nb > 4096) nb = 4096;
-  if (nb < 1) nb = 1;
-  const dim3 grid{static_cast<unsigned>(nb)}, block{256};
   const Reducer none{};
-  if (p == P64)
-    hipLaunchKernelGGL(k_multiaxpy<double>, grid, block, 0, st, static_cast<const z64*>(w),
-                       static_cast<z64*>(w), static_cast<const z64*>(b0), q0,
-                       static_cast<const z64*>(b1), q1, N, coef, 0, none, nullptr, scale, jdone, j);
-  else
-    hipLaunchKernelGGL(k_multiaxpy<float>, grid, block, 0, st, static_cast<const z32*>(w),
-                       static_cast<z32*>(w), static_cast<const z32*>(b0), q0,
-                       static_cast<const z32*>(b1), q1, N, coef, 0, none, nullptr, scale, jdone, j);
-  DC_HIP(hipGetLastError());
+  multiaxpy_any(p, w, b0, q0, b1, q1, N, coef, 0, none, nullptr, scale, jdone, j, st);
 }
 
 void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
