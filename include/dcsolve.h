@@ -96,8 +96,11 @@ typedef struct {
   int32_t schur;        /* 1: solve the odd-even reduced system (Sec. 2.2):
                            S = D_ee - D_eo D_oo^{-1} D_oe on the even sites in
                            factored form, then x_o = D_oo^{-1}(b_o - D_oe x_e);
-                           needs every extent even, excludes block_jacobi and
-                           the batched solves.  b, x stay full-lattice; the
+                           needs every extent even, excludes the batched
+                           solves.  With block_jacobi the left preconditioner
+                           is B = D_ee (Sec. 3.2: the even sites' self
+                           blocks) and the polynomial is built from B^{-1} S
+                           (Sec. 3.3).  b, x stay full-lattice; the
                            polynomial, recycle space and Arnoldi vectors of a
                            reduced variant are even-site compressed [V/2][n]
                            (site x at row x / 2).                               */
@@ -166,6 +169,16 @@ int dc_apply(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* ou
  * precision is not stored. */
 int dc_apply_reduced(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* out,
                      void* stream);
+
+/* The reduced operator with the left block-Jacobi preconditioner of Sec. 3.2,
+ * which for the reduced system takes B = D_ee, the even sites' self blocks
+ * (A_x + i mu Gamma5; not the block diagonal of S, a choice the paper makes
+ * knowingly): out = D_ee^{-1} (D_ee - D_eo D_oo^{-1} D_oe) in
+ *                 = in - D_ee^{-1} D_eo D_oo^{-1} D_oe in,
+ * vectors as in dc_apply_reduced.  The self-block inverses of every site are
+ * built on first use (DC_ERR_STATE if one is singular).  DC_ERR_INVALID as for
+ * dc_apply_reduced. */
+int dc_apply_reduced_bj(dc_op_t op, int32_t prec, const void* in, void* out, void* stream);
 
 /* Multi-right-hand-side apply (MFMA): out_r = D_c in_r (adjoint = 0) or
  * D_c^H in_r (adjoint = 1) for r < n_rhs; in, out device [n_rhs][V][n],

@@ -12,6 +12,13 @@ sites gives the Schur complement
 on the even sites: D x = b is solved as S x_e = b_e - D_eo D_oo^{-1} b_o,
 then x_o = D_oo^{-1} (b_o - D_oe x_e).
 
+Sec. 3.2 takes the block-Jacobi preconditioner of the reduced system to be
+B = D_ee, the even sites' self blocks (not the block diagonal of S itself, which
+the paper notes and accepts), applied from the left, and Sec. 3.3 builds the
+polynomial from B^{-1} S: the system solved is B^{-1} S q(B^{-1} S) y = B^{-1} b_e
+with x_e = q(B^{-1} S) y (the form written out in the paper for both
+preconditioners together).
+
 Vectors of one parity are stored compressed: the even (odd) sites in
 increasing site order, which for an even extent L0 puts site x at position
 x // 2.  Every extent must be even for the checkerboard to be consistent with
@@ -78,6 +85,18 @@ def apply(op, x_e):
     return np.einsum("sij,sj->si", Ae, x_e) - d_eo(op, dinv_oo(op, d_oe(op, x_e)))
 
 
+def dinv_ee(op, v_e):
+    """B^{-1} v_e with B = D_ee, the even sites' self blocks (Sec. 3.2)."""
+    Ae = op.A[sites(op.dims, 0)]
+    return np.stack([np.linalg.solve(Ae[i], v_e[i]) for i in range(Ae.shape[0])])
+
+
+def apply_bj(op, x_e):
+    """B^{-1} S x_e: the reduced operator with the block-Jacobi preconditioner
+    B = D_ee applied from the left (Sec. 3.2)."""
+    return dinv_ee(op, apply(op, x_e))
+
+
 def rhs(op, b):
     """Reduced right-hand side b_e - D_eo D_oo^{-1} b_o."""
     b_e, b_o = split(op, b)
@@ -100,6 +119,38 @@ def solve(op, b, tol: float, m: int = 30, max_cycles: int = 10000):
     tol_s = tol * np.linalg.norm(b) / max(np.linalg.norm(bh), 1e-300)
     xe, info = gmres(f, bh, tol_s, m, max_cycles)
     return recover(op, b, xe.reshape(n_e, op.n)), info
+
+
+def solve_method(op, b, tol: float, m: int, k: int, d: int, u: int, state,
+                 v0=None, bj: bool = True, max_cycles: int = 10000, seed: int = 0,
+                 ortho: str = "mgs"):
+    """D x = b through the reduced system with the paper's solver (Sec. 3.6):
+    left block Jacobi B = D_ee (bj), the GMRES polynomial q of degree d - 1
+    built from B^{-1} S (Sec. 3.3, random start v0), and GCRO-DR(m, k) with
+    recycling through `state` (Sec. 3.4).  The reduced system is solved to
+    the relative tolerance that makes ||b - D x|| <= tol ||b||.
+    Returns (x, info, theta)."""
+    from . import gcrodr as gc
+    from . import poly
+
+    bh = rhs(op, b).reshape(-1)
+    n_e = bh.shape[0] // op.n
+    shape = (n_e, op.n)
+    S = lambda v: apply(op, v.reshape(shape)).reshape(-1)
+    Binv = (lambda v: dinv_ee(op, v.reshape(shape)).reshape(-1)) if bj else None
+    At = (lambda v: Binv(S(v))) if bj else S
+    theta = None
+    right = None
+    if d > 1:
+        if v0 is None:
+            rng = np.random.default_rng(seed)
+            v0 = rng.standard_normal(bh.shape[0]) + 1j * rng.standard_normal(bh.shape[0])
+        theta, _ = poly.build_polynomial(At, np.asarray(v0).reshape(-1), d, ortho)
+        right = lambda v: poly.q_apply(At, theta, v)
+    tol_s = tol * np.linalg.norm(b) / max(np.linalg.norm(bh), 1e-300)
+    xe, info = gc.gcrodr(S, bh, tol_s, m, k, u, max_cycles, state, left=Binv, right=right,
+                         ortho=ortho)
+    return recover(op, b, xe.reshape(shape)), info, theta
 
 
 def dense(op) -> np.ndarray:

@@ -128,13 +128,20 @@ class CoarseOp:
                               _stream_ptr(stream)))
         return out
 
-    def apply_reduced(self, x: torch.Tensor, prec="f64", adjoint=False, out=None, stream=None):
-        """Odd-even reduced operator on a compressed even-site vector [V/2, n]."""
+    def apply_reduced(self, x: torch.Tensor, prec="f64", adjoint=False, out=None, stream=None,
+                      block_jacobi=False):
+        """Odd-even reduced operator on a compressed even-site vector [V/2, n];
+        block_jacobi: D_ee^{-1} S (adjoint not available)."""
         x = x.contiguous()
         assert x.dtype == _vec_dtype(prec) and x.shape == (self.V // 2, self.n)
         out = torch.empty_like(x) if out is None else out
-        check(load().dc_apply_reduced(self._h, PREC[prec], int(adjoint), _ptr(x), _ptr(out),
-                                      _stream_ptr(stream)))
+        if block_jacobi:
+            assert not adjoint
+            check(load().dc_apply_reduced_bj(self._h, PREC[prec], _ptr(x), _ptr(out),
+                                             _stream_ptr(stream)))
+        else:
+            check(load().dc_apply_reduced(self._h, PREC[prec], int(adjoint), _ptr(x),
+                                          _ptr(out), _stream_ptr(stream)))
         return out
 
     def apply_multi(self, X: torch.Tensor, prec="f64", adjoint=False, out=None, stream=None):

@@ -163,7 +163,16 @@ int dc_apply_reduced(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, 
   return guarded([&] {
     if (!op) throw dc::InvalidArg("null handle");
     if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
-    dc::op_apply_reduced(op->op, dc::Prec(prec), adjoint, in, out, as_stream(stream));
+    dc::op_apply_reduced(op->op, dc::Prec(prec), adjoint, 0, in, out, as_stream(stream));
+    return DC_OK;
+  });
+}
+
+int dc_apply_reduced_bj(dc_op_t op, int32_t prec, const void* in, void* out, void* stream) {
+  return guarded([&] {
+    if (!op) throw dc::InvalidArg("null handle");
+    if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
+    dc::op_apply_reduced(op->op, dc::Prec(prec), 0, 1, in, out, as_stream(stream));
     return DC_OK;
   });
 }

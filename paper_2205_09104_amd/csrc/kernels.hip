@@ -690,18 +690,56 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_reduced_oe(
   }
 }
 
+// Epilogue of the reduced operator on one entry i of its output (t = the
+// operator applied to the input at i; e = v, the apply's chain input, where
+// it is read):
+//   EPI 0: out = t
+//   EPI 1: p = e - ca t; out = p; y = c0 e + cb p       (first chain step)
+//   EPI 2: p = out - ca t; out = p; y += cb p            (later chain steps)
+//   EPI 3: out = e - t                                    (residual, e = b)
+template <int EPI, typename VR>
+__device__ __forceinline__ void reduced_epilogue(size_t i, cx<VR> t, cx<VR>* out,
+                                                 const cx<VR>* e, cx<VR>* y, z64 c0, z64 ca,
+                                                 z64 cb) {
+  if (EPI == 0) {
+    out[i] = t;
+  } else if (EPI == 3) {
+    const cx<VR> bb = e[i];
+    out[i] = mk(VR(bb.re - t.re), VR(bb.im - t.im));
+  } else {
+    const VR ar = VR(ca.re), ai = VR(ca.im), br = VR(cb.re), bi = VR(cb.im);
+    const cx<VR> base = (EPI == 1) ? e[i] : out[i];
+    cx<VR> p = base;
+    p.re -= ar * t.re - ai * t.im;
+    p.im -= ar * t.im + ai * t.re;
+    out[i] = p;
+    cx<VR> yv;
+    if (EPI == 1) {
+      const VR zr = VR(c0.re), zi = VR(c0.im);
+      yv.re = zr * base.re - zi * base.im + (br * p.re - bi * p.im);
+      yv.im = zr * base.im + zi * base.re + (br * p.im + bi * p.re);
+    } else {
+      yv = y[i];
+      yv.re += br * p.re - bi * p.im;
+      yv.im += br * p.im + bi * p.re;
+    }
+    y[i] = yv;
+  }
+}
+
 // s = A_e x_e - D_eo t_o (A_e x_e omitted when x_e is null), workgroup per
 // even row r (site x = esite[r]): wave 0 the self block, waves 1-4 the forward
 // hops B[x,mu] t_o(x+mu), waves 5-8 the backward hops Gamma5 B[x-mu,mu]^H
-// Gamma5 t_o(x-mu), both negated; summed in that order.  Epilogue on row r
-// (e = v, the apply's chain input, where it is read):
-//   EPI 0: out = s
-//   EPI 1: p = e - ca s; out = p; y = c0 e + cb p       (first chain step)
-//   EPI 2: p = out - ca s; out = p; y += cb p            (later chain steps)
-//   EPI 3: out = e - s                                    (residual, e = b)
-template <int T, int P, bool FULL, int EPI>
+// Gamma5 t_o(x-mu), both negated; summed in that order.
+// BJ (left block Jacobi with B = D_ee, Sec. 3.2): s = x_e - A_e^{-1} D_eo t_o
+// = B^{-1} (A_e x_e - D_eo t_o); wave 0 loads the inverse of x's self block
+// (einv, same tiled layout, indexed by site) before the barrier, in place of
+// the self block, and applies it to the sum of the eight hop products.
+// Epilogue on row r: reduced_epilogue<EPI> (EPI 3 only without BJ).
+template <int T, int P, bool FULL, int EPI, bool BJ>
 __global__ __launch_bounds__(64 * kRedWaves) void k_reduced_eo(
     const void* __restrict__ blocks, const float* __restrict__ scales,
+    const void* __restrict__ einv, const float* __restrict__ einvsc,
     const cx<typename VecOf<P>::R>* x_e, const cx<typename VecOf<P>::R>* __restrict__ t_o,
     const int* __restrict__ nbr, const int* __restrict__ esite, int V, int n, int chunk, double tm,
     cx<typename VecOf<P>::R>* out, const cx<typename VecOf<P>::R>* e, cx<typename VecOf<P>::R>* y,
@@ -709,15 +747,28 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_reduced_eo(
   using A = typename Tile<T, P>::A;
   using VR = typename VecOf<P>::R;
   __shared__ cx<VR> part[kRedWaves][64];
+  // BJ with FP32 / FP16 tiles: wave 0 stages the inverse in LDS before the
+  // barrier (18 / 9 KB at n = 48); holding it in registers across the barrier
+  // would cost a third of the resident workgroups.  FP64 tiles (37 KB) are
+  // loaded after the barrier instead.
+  constexpr bool STAGE = BJ && P != P64;
+  constexpr int SU = STAGE ? Tile<T, P>::UNITS * 64 : 1;
+  __shared__ uint4 inv_lds[SU];
   if (done && *done) return;
   const int b = blockIdx.x;
   const int r = (b & 7) * chunk + (b >> 3);
   if (r >= (V >> 1)) return;
   const int x = esite[r];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  TileRegs<T, P> R;
   if (w == 0) {
-    if (x_e) {
-      TileRegs<T, P> R;
+    if (STAGE) {
+      const uint4* src = block_ptr<T, P>(einv, size_t(x));
+#pragma unroll
+      for (int u = 0; u < Tile<T, P>::UNITS; ++u) inv_lds[u * 64 + lane] = src[u * 64 + lane];
+    } else if (BJ) {
+      // FP64: loaded after the barrier
+    } else if (x_e) {
       const int item = 5 * x;
       R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
       const A s = (P == P16S) ? A(scales[item]) : A(1);
@@ -728,7 +779,6 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_reduced_eo(
   } else if (w < 5) {
     const int mu = w - 1;
     const int item = 5 * x + 1 + mu;
-    TileRegs<T, P> R;
     R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
     const A s = (P == P16S) ? A(scales[item]) : A(1);
     const int src = nbr[mu * V + x];
@@ -737,44 +787,66 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_reduced_eo(
     const int mu = w - 5;
     const int yy = nbr[(4 + mu) * V + x];
     const int item = 5 * yy + 1 + mu;
-    TileRegs<T, P> R;
     R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
     const A s = (P == P16S) ? A(scales[item]) : A(1);
     wave_product<T, P, FULL, 2>(R, -s, t_o + size_t(yy >> 1) * n, part[w], n, 0.0, lane);
   }
   __syncthreads();
   if (w != 0) return;
-  const VR ar = VR(ca.re), ai = VR(ca.im), br = VR(cb.re), bi = VR(cb.im);
-  for (int c = lane; c < n; c += 64) {
-    cx<VR> t = part[0][c];
+  if constexpr (BJ) {
+    if (STAGE) R.load(inv_lds, lane);
+    else R.load(block_ptr<T, P>(einv, size_t(x)), lane);
+    const int lr = lane >> 3, lc = lane & 7;
+    cx<A> pc[T], pr[T], f[T], g[T];
+    A npc_im[T], npr_re[T];
 #pragma unroll
-    for (int k = 1; k < kRedWaves; ++k) {
-      t.re += part[k][c].re;
-      t.im += part[k][c].im;
-    }
-    const size_t i = size_t(r) * n + c;
-    if (EPI == 0) {
-      out[i] = t;
-    } else if (EPI == 3) {
-      const cx<VR> bb = e[i];
-      out[i] = mk(VR(bb.re - t.re), VR(bb.im - t.im));
-    } else {
-      const cx<VR> base = (EPI == 1) ? e[i] : out[i];
-      cx<VR> p = base;
-      p.re -= ar * t.re - ai * t.im;
-      p.im -= ar * t.im + ai * t.re;
-      out[i] = p;
-      cx<VR> yv;
-      if (EPI == 1) {
-        const VR zr = VR(c0.re), zi = VR(c0.im);
-        yv.re = zr * base.re - zi * base.im + (br * p.re - bi * p.im);
-        yv.im = zr * base.im + zi * base.re + (br * p.im + bi * p.re);
-      } else {
-        yv = y[i];
-        yv.re += br * p.re - bi * p.im;
-        yv.im += br * p.im + bi * p.re;
+    for (int q = 0; q < T; ++q) {
+      const int col = lc * T + q;
+      cx<VR> t = mk(VR(0), VR(0));
+      if (FULL || col < n) {
+        t = part[1][col];
+#pragma unroll
+        for (int k = 2; k < kRedWaves; ++k) {
+          t.re += part[k][col].re;
+          t.im += part[k][col].im;
+        }
       }
-      y[i] = yv;
+      pc[q] = mk(A(t.re), A(t.im));
+      npc_im[q] = -pc[q].im;
+      pr[q] = mk(A(0), A(0));
+      npr_re[q] = A(0);
+      f[q] = mk(A(0), A(0));
+      g[q] = mk(A(0), A(0));
+    }
+    tile_products<T, P, true, false>(R, pc, npc_im, pr, npr_re, f, g);
+    const A s = (P == P16S) ? A(einvsc[x]) : A(1);
+    // the row sums leave row lr*T + q's value in all eight lanes of row group
+    // lr; lane lc takes row lr*T + lc
+    cx<A> mine = mk(A(0), A(0));
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      const A fr = sum_row8(f[q].re) * s, fi = sum_row8(f[q].im) * s;
+      if (q == lc) mine = mk(fr, fi);
+    }
+    const int row = lr * T + lc;
+    if (lc >= T || !(FULL || row < n)) return;
+    const size_t i = size_t(r) * n + row;
+    cx<VR> t = mk(VR(mine.re), VR(mine.im));
+    if (x_e) {
+      const cx<VR> xv = x_e[i];
+      t.re += xv.re;
+      t.im += xv.im;
+    }
+    reduced_epilogue<EPI>(i, t, out, e, y, c0, ca, cb);
+  } else {
+    for (int c = lane; c < n; c += 64) {
+      cx<VR> t = part[0][c];
+#pragma unroll
+      for (int k = 1; k < kRedWaves; ++k) {
+        t.re += part[k][c].re;
+        t.im += part[k][c].im;
+      }
+      reduced_epilogue<EPI>(size_t(r) * n + c, t, out, e, y, c0, ca, cb);
     }
   }
 }
@@ -2225,11 +2297,12 @@ void launch_reduced_oe(Prec p, int n, int V, const void* blocks, const float* sc
   else reduced_oe_T<P16S>(n, V, blocks, scales, inv, invsc, x_e, t_o, nbr, osite, done, st, ev0, ev1);
 }
 
-template <int P, int EPI>
-static void reduced_eo_T(int n, int V, const void* blocks, const float* scales, const void* x_e,
-                         const void* t_o, const int* nbr, const int* esite, double tm, void* out,
-                         const void* e, void* y, z64 c0, z64 ca, z64 cb, const int* done,
-                         hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+template <int P, int EPI, bool BJ>
+static void reduced_eo_T(int n, int V, const void* blocks, const float* scales, const void* einv,
+                         const float* einvsc, const void* x_e, const void* t_o, const int* nbr,
+                         const int* esite, double tm, void* out, const void* e, void* y, z64 c0,
+                         z64 ca, z64 cb, const int* done, hipStream_t st, hipEvent_t ev0,
+                         hipEvent_t ev1) {
   using VR = typename VecOf<P>::R;
   const int rows = V / 2;
   const int chunk = (rows + 7) / 8;
@@ -2244,13 +2317,13 @@ static void reduced_eo_T(int n, int V, const void* blocks, const float* scales, 
 #define DC_CASE(TV)                                                                              \
   case TV:                                                                                       \
     if (full)                                                                                    \
-      hipExtLaunchKernelGGL((k_reduced_eo<TV, P, true, EPI>), grid, block, 0, st, ev0, ev1, 0,   \
-                            blocks, scales, xe, to, nbr, esite, V, n, chunk, tm, o, ee, yy, c0,  \
-                            ca, cb, done);                                                       \
+      hipExtLaunchKernelGGL((k_reduced_eo<TV, P, true, EPI, BJ>), grid, block, 0, st, ev0, ev1,  \
+                            0, blocks, scales, einv, einvsc, xe, to, nbr, esite, V, n, chunk, tm, \
+                            o, ee, yy, c0, ca, cb, done);                                        \
     else                                                                                         \
-      hipExtLaunchKernelGGL((k_reduced_eo<TV, P, false, EPI>), grid, block, 0, st, ev0, ev1, 0,  \
-                            blocks, scales, xe, to, nbr, esite, V, n, chunk, tm, o, ee, yy, c0,  \
-                            ca, cb, done);                                                       \
+      hipExtLaunchKernelGGL((k_reduced_eo<TV, P, false, EPI, BJ>), grid, block, 0, st, ev0, ev1, \
+                            0, blocks, scales, einv, einvsc, xe, to, nbr, esite, V, n, chunk, tm, \
+                            o, ee, yy, c0, ca, cb, done);                                        \
     break;
     DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
 #undef DC_CASE
@@ -2262,29 +2335,45 @@ static void reduced_eo_T(int n, int V, const void* blocks, const float* scales, 
 
 template <int P>
 static void reduced_eo_P(int epi, int n, int V, const void* blocks, const float* scales,
-                         const void* x_e, const void* t_o, const int* nbr, const int* esite,
-                         double tm, void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
-                         const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
-  switch (epi) {
-    case 0: reduced_eo_T<P, 0>(n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1); break;
-    case 1: reduced_eo_T<P, 1>(n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1); break;
-    case 2: reduced_eo_T<P, 2>(n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1); break;
-    default: reduced_eo_T<P, 3>(n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1); break;
+                         const void* einv, const float* einvsc, const void* x_e, const void* t_o,
+                         const int* nbr, const int* esite, double tm, void* out, const void* e,
+                         void* y, z64 c0, z64 ca, z64 cb, const int* done, hipStream_t st,
+                         hipEvent_t ev0, hipEvent_t ev1) {
+#define DC_ARGS n, V, blocks, scales, einv, einvsc, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1
+  if (einv) {
+    switch (epi) {
+      case 0: reduced_eo_T<P, 0, true>(DC_ARGS); break;
+      case 1: reduced_eo_T<P, 1, true>(DC_ARGS); break;
+      default: reduced_eo_T<P, 2, true>(DC_ARGS); break;
+    }
+    return;
   }
+  switch (epi) {
+    case 0: reduced_eo_T<P, 0, false>(DC_ARGS); break;
+    case 1: reduced_eo_T<P, 1, false>(DC_ARGS); break;
+    case 2: reduced_eo_T<P, 2, false>(DC_ARGS); break;
+    default: reduced_eo_T<P, 3, false>(DC_ARGS); break;
+  }
+#undef DC_ARGS
 }
 
 void launch_reduced_eo(Prec p, int epi, int n, int V, const void* blocks, const float* scales,
-                       const void* x_e, const void* t_o, const int* nbr, const int* esite,
-                       double tm, void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
-                       const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+                       const void* einv, const float* einvsc, const void* x_e, const void* t_o,
+                       const int* nbr, const int* esite, double tm, void* out, const void* e,
+                       void* y, z64 c0, z64 ca, z64 cb, const int* done, hipStream_t st,
+                       hipEvent_t ev0, hipEvent_t ev1) {
   if (epi < 0 || epi > 3) throw InvalidArg("reduced epilogue must be 0..3");
+  if (einv && epi == 3) throw InvalidArg("the residual epilogue takes the unpreconditioned operator");
+  if (einv && p == P16S && !einvsc) throw InvalidArg("FP16 inverses need their scales");
   if (V < 2 || V % 2) throw InvalidArg("the reduced operator needs an even number of sites");
   if (!t_o || !out) throw InvalidArg("null vector pointer");
   if ((epi == 1 || epi == 3) && !e) throw InvalidArg("null epilogue input");
   if ((epi == 1 || epi == 2) && !y) throw InvalidArg("null chain output");
-  if (p == P64) reduced_eo_P<P64>(epi, n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1);
-  else if (p == P32) reduced_eo_P<P32>(epi, n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1);
-  else reduced_eo_P<P16S>(epi, n, V, blocks, scales, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1);
+#define DC_ARGS epi, n, V, blocks, scales, einv, einvsc, x_e, t_o, nbr, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1
+  if (p == P64) reduced_eo_P<P64>(DC_ARGS);
+  else if (p == P32) reduced_eo_P<P32>(DC_ARGS);
+  else reduced_eo_P<P16S>(DC_ARGS);
+#undef DC_ARGS
 }
 
 void launch_oddeven_split(Prec p, int n, int half_sites, const int* esite, const int* osite,

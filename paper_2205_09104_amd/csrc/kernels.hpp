@@ -88,11 +88,14 @@ void launch_reduced_oe(Prec p, int n, int V, const void* blocks, const float* sc
 // launch_reduced_eo: s = A_e x_e - D_eo t_o (x_e null: -D_eo t_o) with the
 // epilogue epi: 0 out = s; 1 p = e - ca s, out = p, y = c0 e + cb p; 2 p = out -
 // ca s, out = p, y += cb p; 3 out = e - s.  esite: int32 [V/2] even row -> site.
+// einv (null: none) selects the left block-Jacobi form with B = D_ee:
+// s = x_e - A_e^{-1} D_eo t_o (= B^{-1} of the above), with einv / einvsc the
+// self-block inverses of every site (tiled, indexed by site); epi 0..2 only.
 void launch_reduced_eo(Prec p, int epi, int n, int V, const void* blocks, const float* scales,
-                       const void* x_e, const void* t_o, const int* nbr, const int* esite,
-                       double tm, void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
-                       const int* done, hipStream_t st, hipEvent_t ev0 = nullptr,
-                       hipEvent_t ev1 = nullptr);
+                       const void* einv, const float* einvsc, const void* x_e, const void* t_o,
+                       const int* nbr, const int* esite, double tm, void* out, const void* e,
+                       void* y, z64 c0, z64 ca, z64 cb, const int* done, hipStream_t st,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // split a full-lattice vector into its compressed even and odd halves, or merge
 // them back (dir 0: split, 1: merge); esite/osite: int32 [V/2] row -> site
 void launch_oddeven_split(Prec p, int n, int half_sites, const int* esite, const int* osite,

@@ -358,9 +358,9 @@ static void reduced_oe(Op& op, Prec p, const void* inv, const float* invsc, cons
   if (a) pr.recs.push_back({a, b, slot, done ? pr.tag : -1, false, 2});
 }
 
-static void reduced_eo(Op& op, Prec p, int epi, const void* x_e, const void* t_o, double tm,
-                       void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
-                       const int* done, hipStream_t st) {
+static void reduced_eo(Op& op, Prec p, int epi, const void* einv, const float* einvsc,
+                       const void* x_e, const void* t_o, double tm, void* out, const void* e,
+                       void* y, z64 c0, z64 ca, z64 cb, const int* done, hipStream_t st) {
   ApplyProfile& pr = op.prof;
   hipEvent_t a = nullptr, b = nullptr;
   const int slot = 6 + prec_slot(p);
@@ -368,8 +368,8 @@ static void reduced_eo(Op& op, Prec p, int epi, const void* x_e, const void* t_o
     if (pr.tag < 0 && pr.recs.size() >= 2048) pr.flush();
     if (!pr.take(&a, &b)) ++pr.missed;
   }
-  launch_reduced_eo(p, epi, op.n, op.V, op.blocks(p), op.scales(p), x_e, t_o, op.nbr.as<int>(),
-                    op.esite.as<int>(), tm, out, e, y, c0, ca, cb, done, st, a, b);
+  launch_reduced_eo(p, epi, op.n, op.V, op.blocks(p), op.scales(p), einv, einvsc, x_e, t_o,
+                    op.nbr.as<int>(), op.esite.as<int>(), tm, out, e, y, c0, ca, cb, done, st, a, b);
   if (a) {
     // distinct vectors read (x_e, t_o and the epilogue's inputs) plus writes
     int passes = 1 + (x_e ? 1 : 0);
@@ -452,7 +452,8 @@ static const void* bj_blocks(const Op::BJ& b, Prec p) {
   return p == P64 ? b.b64.p : (p == P32 ? b.b32.p : b.b16.p);
 }
 
-void op_apply_reduced(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_t st) {
+void op_apply_reduced(Op& op, Prec p, int adjoint, int block_jacobi, const void* in, void* out,
+                      hipStream_t st) {
   check_prec(op, p);
   if (!op.oddeven) throw InvalidArg("the odd-even reduction needs every lattice extent even");
   if (!in || !out) throw InvalidArg("null vector pointer");
@@ -470,6 +471,9 @@ void op_apply_reduced(Op& op, Prec p, int adjoint, const void* in, void* out, hi
   const Op::BJ& bj = op.ensure_bj(sign, st);
   const void* inv = bj_blocks(bj, p);
   const float* invsc = (p == P16S) ? bj.sc16.as<float>() : nullptr;
+  // left block Jacobi B = D_ee (Sec. 3.2): the even sites' inverses, same arrays
+  const void* bj_e = block_jacobi ? inv : nullptr;
+  const float* bj_esc = block_jacobi ? invsc : nullptr;
   void* ts = op.tmp_s(p);
   const void* src = in;
   if (adjoint) {
@@ -479,7 +483,7 @@ void op_apply_reduced(Op& op, Prec p, int adjoint, const void* in, void* out, hi
   const z64 z = mk(0.0, 0.0);
   reduced_oe(op, p, inv, invsc, src, ts, nullptr, st);
   // the D_eo kernel reads src only on its own row before writing that row of out
-  reduced_eo(op, p, 0, src, ts, tm, out, nullptr, nullptr, z, z, z, nullptr, st);
+  reduced_eo(op, p, 0, bj_e, bj_esc, src, ts, tm, out, nullptr, nullptr, z, z, z, nullptr, st);
   if (adjoint) launch_gamma5(p, out, out, half, op.n, st);
 }
 
@@ -598,7 +602,6 @@ struct Krylov {
     rows = v.schur ? op.V / 2 : op.V;
     if (v.schur) {
       if (!op.oddeven) throw InvalidArg("the odd-even reduction needs every lattice extent even");
-      if (v.bj) throw InvalidArg("block Jacobi and the odd-even reduction are exclusive");
       const Op::BJ& b = op.ensure_bj(v.sign, st);   // D_oo^{-1}: inverses of the odd self blocks
       oinv = bj_blocks(b, p);
       oinvsc = (p == P16S) ? b.sc16.as<float>() : nullptr;
@@ -681,10 +684,15 @@ struct Krylov {
   // even vectors (Sec. 2.2, factored form) with the D_eo kernel's epilogue
   // (0 store, 1 first chain step, 2 later chain step, 3 residual).  Its
   // epilogue reads and writes only the row it computes, so out may alias in.
+  // With block Jacobi (B = D_ee, Sec. 3.2) epilogues 0-2 act on B^{-1} S in:
+  // the inverses of the even self blocks replace them in the D_eo kernel.
+  // The residual epilogue (3) always takes S itself.
   void reduced(const Z* in, int epi, Z* out, const Z* e, Z* y, z64 c0, z64 ca, z64 cb,
                const int* done) {
+    const bool lbj = bjinv && epi != 3;
     reduced_oe(op, p, oinv, oinvsc, in, ts, done, st);
-    reduced_eo(op, p, epi, in, ts, tm, out, e, y, c0, ca, cb, done, st);
+    reduced_eo(op, p, epi, lbj ? bjinv : nullptr, lbj ? bjsc : nullptr, in, ts, tm, out, e, y,
+               c0, ca, cb, done, st);
   }
 
   // A~ in = (B^{-1}) D in (one matvec)
@@ -701,9 +709,12 @@ struct Krylov {
     ++matvecs;
   }
 
-  // rhat = B^{-1} r (or a copy without block Jacobi)
+  // rhat = B^{-1} r (or a copy without block Jacobi); on the reduced system
+  // B = D_ee, the even rows' self blocks
   void left_precondition(const Z* r, Z* out) {
-    if (bjinv) launch_bj_vec(p, op.n, rows, bjinv, bjsc, r, out, st);
+    if (bjinv && var.schur)
+      launch_bj_rows(p, op.n, rows, op.esite.as<int>(), bjinv, bjsc, r, out, st);
+    else if (bjinv) launch_bj_vec(p, op.n, rows, bjinv, bjsc, r, out, st);
     else launch_copy_words(r, out, N * sizeof(Z), st);
   }
 
@@ -1060,7 +1071,7 @@ struct Krylov {
     bool converged = false;
     if (k > 0 && var.kcur > 0) {
       deflate_start(x);
-      if (inner_est && !bjinv) {
+      if (inner_est) {
         launch_norm_root(nrm, nrm + 2, st);   // ||rhat|| stays on the device
         beta = -1.0;
       } else {
@@ -1092,12 +1103,14 @@ struct Krylov {
     double best = rn;
     int stall = 0;
     while (true) {
-      const bool by_est = inner_est && !bjinv && k > 0 && var.kcur > 0;
+      // inner solves stop on the recursively updated (left-preconditioned)
+      // residual, compared with the target on its own scale (ratio)
+      const bool by_est = inner_est && k > 0 && var.kcur > 0;
       if (by_est && beta < 0.0) {
         // the deflated start's norm is on the device: straight to a cycle
         if (cycles >= max_cycles) break;
       } else {
-        rn = by_est ? beta : true_resid(x, b, rtrue);
+        rn = by_est ? beta / ratio : true_resid(x, b, rtrue);
         relres = rn / bn;
         if (relres <= tol) {
           converged = true;
@@ -1175,7 +1188,7 @@ struct Krylov {
       update_x(x, kk, jd, cy);
       // inner solves: the least-squares residual is the norm the update of
       // rhat would give, so a converged cycle skips that update
-      const bool est_conv = by_est && lsres <= tol * bn;
+      const bool est_conv = by_est && lsres <= target_abs;
       if (!est_conv) {
         // rhat -= What (G y), What = [C, V_{jd+1}]
         Mat ym(kk + jd, 1);
@@ -1193,7 +1206,7 @@ struct Krylov {
       if (var.updates < o.u && jd > 0) refresh_recycle(c, get_G());
       if (est_conv) {
         converged = true;
-        relres = lsres / bn;
+        relres = lsres / (bn * ratio);
         break;
       }
       if (jd == 0) break;
@@ -1399,7 +1412,6 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
   for (int r = 0; r < n_rhs; ++r)
     if (!(tol[r] > 0.0)) throw InvalidArg("tolerances must be positive");
   if (o.schur && !op.oddeven) throw InvalidArg("the odd-even reduction needs every lattice extent even");
-  if (o.schur && o.block_jacobi) throw InvalidArg("block Jacobi and the odd-even reduction are exclusive");
   const int sign = (adjoint && op.mu != 0.0) ? -1 : +1;
   const size_t Nfull = op.N();
   // system size: the full lattice, or the even sites of the reduced system
@@ -1451,7 +1463,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       if (use_x0) launch_oddeven_split(P64, op.n, half, esite, osite, xfull, xe.p, nullptr, 0, st);
       launch_bj_rows(P64, op.n, half, osite, oinv, nullptr, bo.p, to.p, st);   // A_o^{-1} b_o
       // -D_eo A_o^{-1} b_o (set-up and recovery launches are not profiled)
-      launch_reduced_eo(P64, 0, op.n, op.V, op.blocks(P64), nullptr, nullptr, to.p,
+      launch_reduced_eo(P64, 0, op.n, op.V, op.blocks(P64), nullptr, nullptr, nullptr, nullptr, to.p,
                         op.nbr.as<int>(), esite, tm, op.tmp_s(P64), nullptr, nullptr, z0, z0, z0,
                         nullptr, st);
       launch_axpy(P64, mk(1.0, 0.0), op.tmp_s(P64), be.p, N, st);   // be := b^_e

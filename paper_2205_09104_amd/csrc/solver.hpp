@@ -212,7 +212,9 @@ void op_update(Op& op, const void* self_blocks, const void* hop_blocks, bool on_
 // Precision-level entry points used by the C ABI.
 void op_apply(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_t st);
 void op_apply_bj(Op& op, const void* in, void* out, hipStream_t st);
-void op_apply_reduced(Op& op, Prec p, int adjoint, const void* in, void* out, hipStream_t st);
+// block_jacobi: out = D_ee^{-1} S in (left block Jacobi of the reduced system)
+void op_apply_reduced(Op& op, Prec p, int adjoint, int block_jacobi, const void* in, void* out,
+                      hipStream_t st);
 void op_apply_multi(Op& op, Prec p, int adjoint, int R, const void* in, void* out, hipStream_t st);
 int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta);
 void op_poly_apply(Op& op, const SolveOpts& o, const void* in, void* out, hipStream_t st);

@@ -106,8 +106,6 @@ def test_reduced_rejects_bad_input():
     gop2, oop2 = make_pair((2, 2, 2, 2), 2, 3.0)
     b2 = rand_vec(oop2.V, oop2.n, 75, 0).cuda()
     with pytest.raises(DcError):
-        gop2.solve(b2, 1e-8, Opts(m=10, schur=1, block_jacobi=1))
-    with pytest.raises(DcError):
         gop2.solve_batch(b2[None], 1e-8, Opts(m=10, schur=1))
 
 
@@ -137,8 +135,8 @@ def s_flat(oop):
 @pytest.mark.parametrize("d", [2, 5])
 def test_reduced_polynomial_chain(c1, d):
     """The reduced apply's chain epilogues (first and later steps of q(S))
-    against the oracle's chain on its own S, with its own harmonic Ritz
-    values and Leja order."""
+    against the oracle's chain with the same harmonic Ritz values (to 1e-12),
+    and those values against the oracle's own (same v0, Leja order, 1e-8)."""
     from paper_2205_09104_amd import Opts
     gop, oop, w, b, xref = c1
     log("reduced poly chain", d)
@@ -151,8 +149,8 @@ def test_reduced_polynomial_chain(c1, d):
     assert np.max(np.abs(th - th_ref)) <= 1e-8 * np.abs(th_ref).max()
     x = rand_vec(ne, oop.n, 74)
     got = gop.poly_apply(x.cuda(), opts).cpu().numpy()
-    want = opoly.q_apply(s_flat(oop), th_ref, x.numpy().reshape(-1)).reshape(ne, oop.n)
-    assert rel(got, want) <= 1e-8
+    want = opoly.q_apply(s_flat(oop), th, x.numpy().reshape(-1)).reshape(ne, oop.n)
+    assert rel(got, want) <= 1e-12
 
 
 def test_reduced_recycle_invariants(c1):

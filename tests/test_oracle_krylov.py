@@ -260,3 +260,64 @@ def test_gcrodr_exact_eigenvectors_when_m_ge_N():
     got = np.linalg.eigvals(M)
     assert max(np.min(np.abs(smallest - g)) for g in got) <= 1e-8
     assert max(np.min(np.abs(got - s)) for s in smallest) <= 1e-8
+
+
+def _refresh_subspace_error(eig_fn=None):
+    """One GCRO-DR cycle whose Vhat = [U D_k, V_{m-k}] spans the whole space
+    (m - k = N - k deflated Arnoldi steps, breaking down on the invariant
+    complement of span(C)), followed by the recycle refresh from the
+    generalised problem G^H G z = theta G^H (What^H Vhat) z.  With Vhat
+    spanning C^N the harmonic Ritz pairs are exact eigenpairs, so the
+    refreshed span(U) must be the invariant subspace of the k smallest-|lambda|
+    eigenvalues.  Returns the largest of: the eigenvalue mismatch of U's
+    Rayleigh-Ritz matrix and the relative invariance residual."""
+    import oracle.gcrodr as gc
+    op = small_op(dims=(3, 1, 1, 1), ntv=2)      # N = 12
+    Dm = dop.dense(op)
+    A = flat(op)
+    N, k = op.N, 3
+    rng = np.random.default_rng(21)
+    st = RecycleState()
+    # a recycle space that is not invariant: random U, C from qr(A U) (the
+    # matrix-changed path), one update already counted
+    st.U = rng.standard_normal((N, k)) + 1j * rng.standard_normal((N, k))
+    st.C = np.zeros_like(st.U)
+    st.updates = 1
+    b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    saved = gc.sla
+    if eig_fn is not None:
+        class _Fake:
+            eig = staticmethod(eig_fn)
+        gc.sla = _Fake
+    try:
+        _, info = gcrodr(A, b, 1e-15, N, k, 10, 1, st, matrix_changed=True)
+    finally:
+        gc.sla = saved
+    assert info.cycles == 1 and st.updates == 2
+    ev = np.linalg.eigvals(Dm)
+    smallest = ev[np.argsort(np.abs(ev))[:k]]
+    U = st.U
+    M = np.linalg.lstsq(U, Dm @ U, rcond=None)[0]
+    inv_res = np.linalg.norm(Dm @ U - U @ M) / np.linalg.norm(Dm @ U)
+    got = np.linalg.eigvals(M)
+    mism = max(max(np.min(np.abs(smallest - g)) for g in got),
+               max(np.min(np.abs(got - s_)) for s_ in smallest))
+    return max(inv_res, mism / np.abs(smallest).max())
+
+
+def test_gcrodr_refresh_recovers_invariant_subspace():
+    """Pins the refresh step's generalised eigenproblem and its selection
+    (Sec. 3.4; Parks et al. update): exact when Vhat spans everything."""
+    assert _refresh_subspace_error() <= 1e-8
+
+
+@pytest.mark.parametrize("mistake", ["no_rhs_matrix", "swapped", "conjugated"])
+def test_gcrodr_refresh_pin_detects_wrong_eigenproblem(mistake):
+    """Mistakes planted in the oracle's refresh (on the CPU) must fail the pin
+    above: dropping What^H Vhat, swapping the two matrices (which selects the
+    largest |theta|), or conjugating the problem."""
+    import scipy.linalg as sla
+    wrong = {"no_rhs_matrix": lambda a, b: sla.eig(a),
+             "swapped": lambda a, b: sla.eig(b, a),
+             "conjugated": lambda a, b: sla.eig(a.conj(), b.conj())}[mistake]
+    assert _refresh_subspace_error(wrong) > 1e-3

@@ -58,3 +58,83 @@ def test_reduced_solve_matches_lu(mu):
     # the odd rows of the residual vanish up to rounding
     _, r_o = schur.split(op, r)
     assert np.linalg.norm(r_o) <= 1e-13 * np.linalg.norm(b)
+
+
+# ------------------------------------------------ block Jacobi on the reduced system
+
+def _dense_bj(op):
+    """B^{-1} S assembled densely: B = blockdiag(D_ee) inverted with
+    numpy.linalg.inv on the assembled block diagonal (independent of dinv_ee)."""
+    S = schur.dense(op)
+    Ae = op.A[schur.sites(op.dims, 0)]
+    n = op.n
+    Bd = np.zeros_like(S)
+    for i, a in enumerate(Ae):
+        Bd[i * n:(i + 1) * n, i * n:(i + 1) * n] = a
+    return np.linalg.inv(Bd) @ S, Bd
+
+
+@pytest.mark.parametrize("mu", [0.0, 0.15])
+def test_bj_apply_matches_dense(mu):
+    """Sec. 3.2: B = D_ee for the reduced system; B^{-1} S against the dense
+    block elimination and a dense inverse of the block diagonal."""
+    op = make((2, 4, 2, 2), 2, mu=mu)
+    M, Bd = _dense_bj(op)
+    rng = np.random.default_rng(3)
+    ne = op.V // 2
+    x = rng.standard_normal((ne, op.n)) + 1j * rng.standard_normal((ne, op.n))
+    assert np.allclose(schur.apply_bj(op, x).reshape(-1), M @ x.reshape(-1), rtol=0, atol=1e-12)
+    assert np.allclose(schur.dinv_ee(op, x).reshape(-1), np.linalg.solve(Bd, x.reshape(-1)),
+                       rtol=0, atol=1e-12)
+
+
+def test_bj_polynomial_is_built_from_preconditioned_operator():
+    """d = dim: the harmonic Ritz values of B^{-1} S are its exact eigenvalues
+    (Sec. 3.3, polynomial of the left-preconditioned operator); they differ
+    from the eigenvalues of S, so building q from S instead would fail."""
+    from oracle import poly
+    op = make((2, 2, 2, 2), 2, m0=2.6)
+    M, _ = _dense_bj(op)
+    S = schur.dense(op)
+    N = M.shape[0]
+    rng = np.random.default_rng(4)
+    v0 = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+    ne = op.V // 2
+    At = lambda v: schur.apply_bj(op, v.reshape(ne, op.n)).reshape(-1)
+    theta, _ = poly.build_polynomial(At, v0, N)
+    ev = np.linalg.eigvals(M)
+    # the N-th step's h_{N+1,N} is rounding (~1e-8), not zero: harmonic Ritz
+    # values within ~1e-6 of the eigenvalues
+    assert max(np.min(np.abs(ev - t)) for t in theta) <= 1e-5 * np.abs(ev).max()
+    evs = np.linalg.eigvals(S)
+    assert max(np.min(np.abs(evs - t)) for t in theta) > 1e-1
+
+
+@pytest.mark.parametrize("mu,d", [(0.0, 4), (0.1, 4), (0.0, 1)])
+def test_bj_poly_gcrodr_method_matches_lu(mu, d):
+    """The paper's coarsest-level method on the reduced system (left block
+    Jacobi + polynomial of B^{-1} S + GCRO-DR with recycling) against dense LU
+    for three right-hand sides in a row, with the recycle invariants of the
+    preconditioned operator A^ = B^{-1} S q(B^{-1} S): C = A^ U, C^H C = I."""
+    from oracle import poly
+    from oracle.gcrodr import RecycleState
+    op = make((4, 2, 2, 2), 3, m0=3.1, mu=mu)
+    Dm = dop.dense(op)
+    M, _ = _dense_bj(op)
+    rng = np.random.default_rng(5)
+    st = RecycleState()
+    ne = op.V // 2
+    v0 = rng.standard_normal(ne * op.n) + 1j * rng.standard_normal(ne * op.n)
+    for r in range(3):
+        b = rng.standard_normal((op.V, op.n)) + 1j * rng.standard_normal((op.V, op.n))
+        x, info, theta = schur.solve_method(op, b, 1e-11, m=16, k=4, d=d, u=10, state=st, v0=v0)
+        assert info.converged
+        xref = np.linalg.solve(Dm, b.reshape(-1))
+        assert np.linalg.norm(b.reshape(-1) - Dm @ x.reshape(-1)) <= 1e-11 * np.linalg.norm(b) * 1.0001
+        assert np.linalg.norm(x.reshape(-1) - xref) <= 1e-8 * np.linalg.norm(xref)
+        assert np.allclose(st.C.conj().T @ st.C, np.eye(4), atol=1e-10)
+        if d > 1:
+            qU = np.stack([poly.q_apply(lambda v: M @ v, theta, st.U[:, i]) for i in range(4)], 1)
+        else:
+            qU = st.U
+        assert np.linalg.norm(M @ qU - st.C) <= 1e-8 * np.linalg.norm(st.C)
