@@ -30,9 +30,11 @@
  *   - Return value: DC_OK (0), a positive status (result written, see below)
  *     or a negative error; nothing is thrown across the ABI.  After a negative
  *     return, dc_last_error() gives a message (thread-local).
- *   - Ownership: the library copies what it keeps.  Handles own their device
- *     memory (allocated with hipMalloc at build time and on first use of a
- *     solver variant) and free it in destroy_coarse_op.
+ *   - Ownership: the library copies what it keeps.  A handle from
+ *     build_coarse_op owns its device memory (allocated with hipMalloc at
+ *     build time and on first use of a solver variant) and frees it in
+ *     destroy_coarse_op; a handle from build_coarse_op_ws takes all of it from
+ *     two caller-owned ranges (dc_workspace_bytes gives their sizes).
  *   - A handle is used by one host thread and one stream at a time.
  */
 #ifndef DCSOLVE_H
@@ -47,12 +49,17 @@ extern "C" {
 
 typedef struct dc_op_s* dc_op_t;
 
-/* status codes */
+/* status codes: > 0 the best iterate is written and the stats are valid,
+ * < 0 no result */
 enum {
   DC_OK = 0,
   DC_NOT_CONVERGED = 1,   /* cap reached: best iterate written, stats valid   */
+  DC_BREAKDOWN = 2,       /* stopped on h_{j+1,j} = 0 at the first step of a
+                             cycle (Alg. 1: the Krylov space cannot grow) with
+                             the tolerance not met; best iterate written      */
   DC_ERR_INVALID = -1,    /* bad argument (null pointer, size, option)        */
   DC_ERR_HIP = -2,        /* a HIP runtime call failed                        */
+  DC_ERR_WORKSPACE = -3,  /* a caller-provided workspace is too small         */
   DC_ERR_STATE = -4,      /* handle state does not allow the call             */
   DC_ERR_NOMEM = -5       /* device allocation failed                         */
 };
@@ -112,6 +119,10 @@ typedef struct {
                            the update; less stable on long cycles, breakdown
                            when that difference is not positive).  The
                            batched solves take 0 only.                          */
+  const void* x_ref;    /* optional reference solutions, device complex128
+                           [n_rhs][V][n]: each solve then reports
+                           ||x - x_ref|| / ||x_ref|| (FP64) in err_vs_ref;
+                           NULL = none                                          */
 } dc_solve_opts;
 
 typedef struct {
@@ -125,12 +136,62 @@ typedef struct {
   double rel_res_est;   /* last least-squares residual estimate (relative)        */
   double t_setup_ms;    /* polynomial / recycle construction time in this call    */
   double t_solve_ms;    /* wall time of the call                                  */
+  double err_vs_ref;    /* ||x - x_ref|| / ||x_ref|| if opts->x_ref, else -1      */
+  int32_t breakdowns;   /* Arnoldi cycles that ended on h_{j+1,j} = 0 (Alg. 1's
+                           happy breakdown: the least-squares solution is exact
+                           in the space built so far)                             */
+  int32_t refresh_failed; /* recycle refreshes whose dense generalised eigen-
+                           problem failed; the space is then kept as it is and
+                           frozen (no further refreshes)                          */
 } dc_solve_stats;
 
 /* Fill `o` with defaults: m=30, k=0, d=0, u=10, max_cycles=100000,
  * block_jacobi=0, prec=F64, outer=0, m_outer=10, max_outer=50,
- * inner_tol=1e-4, seed=0, v0=NULL, schur=0, ortho=0. */
+ * inner_tol=1e-4, seed=0, v0=NULL, schur=0, ortho=0, x_ref=NULL. */
 int dc_default_opts(dc_solve_opts* o);
+
+/* Device memory a handle needs when the caller provides it (build_coarse_op_ws):
+ *   *persistent_bytes: what the handle keeps for its lifetime -- the blocks
+ *     in every stored precision (desc->store), FP16 scales, neighbour and
+ *     parity tables, the self-block inverses that block Jacobi (Sec. 3.2) and
+ *     the odd-even reduction (Sec. 2.2) use, and the recycle spaces U, C and
+ *     q(A~) U of GCRO-DR (Sec. 3.4) for the variants `opts` selects (both
+ *     signs of mu when mu != 0, so that adjoint solves fit too);
+ *   *scratch_bytes: everything else -- apply partials, Krylov bases,
+ *     polynomial chains, outer-loop vectors and residual temporaries of the
+ *     single-right-hand-side calls (applies, dc_poly_*, dc_arnoldi with at
+ *     most opts->m steps, solve_coarse / solve_coarse_adjoint) with these
+ *     options, and dc_apply_multi with up to max_rhs right-hand sides.
+ * Both are upper bounds for those calls; other options may need more (the
+ * call then returns DC_ERR_WORKSPACE).  Pure host computation: no device is
+ * touched.  DC_ERR_INVALID for bad descriptors or options. */
+int dc_workspace_bytes(const dc_op_desc* desc, const dc_solve_opts* opts, int32_t max_rhs,
+                       size_t* persistent_bytes, size_t* scratch_bytes);
+
+/* build_coarse_op on caller-owned device memory: the handle carves every
+ * device buffer it uses from the two ranges (first fit, 256-byte aligned) and
+ * calls no hipMalloc of its own, so memory can come from a framework's
+ * allocator (e.g. two torch uint8 CUDA tensors).  persistent_ws must stay
+ * valid, and untouched by the caller, until destroy_coarse_op; scratch_ws
+ * likewise (the handle keeps its Krylov workspaces there between calls).
+ * Sizes come from dc_workspace_bytes.  Returns DC_ERR_WORKSPACE, before any
+ * device work, if either range cannot hold what the build itself needs, and
+ * from any later call whose buffers do not fit.  The batched and block
+ * solvers (solve_coarse_batch, solve_coarse_multi, solve_coarse_block) are
+ * not available on such a handle (DC_ERR_STATE).  Other arguments and errors
+ * as build_coarse_op. */
+int build_coarse_op_ws(const dc_op_desc* desc, const void* self_blocks, const void* hop_blocks,
+                       void* persistent_ws, size_t persistent_bytes, void* scratch_ws,
+                       size_t scratch_bytes, void* stream, dc_op_t* out);
+
+/* Peak bytes a handle built by build_coarse_op_ws has used of each range so
+ * far.  DC_ERR_STATE for a handle that allocates its own memory. */
+int dc_workspace_used(dc_op_t op, size_t* persistent_peak, size_t* scratch_peak);
+
+/* Process-wide count of device allocations (hipMalloc) the library has made,
+ * and the bytes they hold now (handles built on caller workspaces add
+ * nothing).  Either pointer may be NULL. */
+int dc_device_allocations(int64_t* count, int64_t* bytes_held);
 
 /* Build a handle for D_c (Sec. 2.2; twisted mass Sec. 2.1).
  *   self_blocks: complex128 [V][n][n], the self couplings A_x (without the

@@ -53,6 +53,7 @@ class Opts:
     v0: torch.Tensor | None = field(default=None, repr=False)
     schur: int = 0      # 1: odd-even reduced system (even extents only)
     ortho: int = 0      # 1: single-sync Arnoldi (one reduction per step)
+    x_ref: torch.Tensor | None = field(default=None, repr=False)   # [R, V, n] complex128
 
     def to_c(self) -> _lib.SolveOpts:
         o = _lib.SolveOpts()
@@ -66,14 +67,50 @@ class Opts:
         if self.v0 is not None:
             assert self.v0.dtype == torch.complex128 and self.v0.is_cuda
             o.v0 = self.v0.data_ptr()
+        if self.x_ref is not None:
+            assert self.x_ref.dtype == torch.complex128 and self.x_ref.is_cuda
+            assert self.x_ref.is_contiguous()
+            o.x_ref = self.x_ref.data_ptr()
         return o
+
+
+def _desc(dims, n_tv, store, mu, on_device):
+    desc = _lib.OpDesc()
+    for i in range(4):
+        desc.dims[i] = int(dims[i])
+    desc.n_tv = int(n_tv)
+    desc.store = sum(STORE[s] for s in set(store) | {"f64"})
+    desc.where = _lib.DC_WHERE_DEVICE if on_device else _lib.DC_WHERE_HOST
+    desc.mu = float(mu)
+    return desc
+
+
+def workspace_bytes(dims, n_tv, store=("f64",), mu=0.0, opts: "Opts | None" = None,
+                    max_rhs=0, on_device=True):
+    """(persistent, scratch) device bytes of a handle built on caller memory
+    (dc_workspace_bytes)."""
+    pb, sb = C.c_size_t(), C.c_size_t()
+    o = (opts or Opts()).to_c()
+    check(load().dc_workspace_bytes(C.byref(_desc(dims, n_tv, store, mu, on_device)), C.byref(o),
+                                    int(max_rhs), C.byref(pb), C.byref(sb)))
+    return pb.value, sb.value
+
+
+def device_allocations():
+    """(count, bytes held) of the library's own hipMalloc allocations."""
+    c, b = C.c_int64(), C.c_int64()
+    check(load().dc_device_allocations(C.byref(c), C.byref(b)))
+    return c.value, b.value
 
 
 class CoarseOp:
     """Handle of the coarse operator D_c (build_coarse_op)."""
 
     def __init__(self, self_blocks: torch.Tensor, hop_blocks: torch.Tensor, dims, mu=0.0,
-                 store=("f64",), stream=None):
+                 store=("f64",), stream=None, workspace=None):
+        """workspace: optional (persistent, scratch) pair of CUDA uint8 tensors
+        sized by workspace_bytes(); the handle then takes all its device
+        memory from them (build_coarse_op_ws) and keeps them alive."""
         lib = load()
         assert self_blocks.dtype == torch.complex128 and hop_blocks.dtype == torch.complex128
         V, n, n2 = self_blocks.shape
@@ -94,16 +131,30 @@ class CoarseOp:
         sb = self_blocks.contiguous()
         hb = hop_blocks.contiguous()
         h = C.c_void_p()
-        check(lib.build_coarse_op(C.byref(desc), _ptr(sb), _ptr(hb), _stream_ptr(stream)
-                                  if on_dev or torch.cuda.is_available() else None,
-                                  C.byref(h)))
+        st = _stream_ptr(stream) if on_dev or torch.cuda.is_available() else None
+        self._ws = workspace
+        if workspace is None:
+            check(lib.build_coarse_op(C.byref(desc), _ptr(sb), _ptr(hb), st, C.byref(h)))
+        else:
+            pw, sw = workspace
+            assert pw.dtype == torch.uint8 and sw.dtype == torch.uint8
+            assert pw.is_cuda and sw.is_cuda and pw.is_contiguous() and sw.is_contiguous()
+            check(lib.build_coarse_op_ws(C.byref(desc), _ptr(sb), _ptr(hb), _ptr(pw),
+                                         pw.numel(), _ptr(sw), sw.numel(), st, C.byref(h)))
         self._h = h
+
+    def workspace_used(self):
+        """Peak (persistent, scratch) bytes used of the caller's workspaces."""
+        pb, sb = C.c_size_t(), C.c_size_t()
+        check(load().dc_workspace_used(self._h, C.byref(pb), C.byref(sb)))
+        return pb.value, sb.value
 
     # -- lifetime
     def close(self):
         if getattr(self, "_h", None):
             load().destroy_coarse_op(self._h)
             self._h = None
+        self._ws = None
 
     def __del__(self):
         try:

@@ -13,8 +13,10 @@ LIB_PATH = os.path.join(HERE, "libdcsolve.so")
 
 DC_OK = 0
 DC_NOT_CONVERGED = 1
+DC_BREAKDOWN = 2
 DC_ERR_INVALID = -1
 DC_ERR_HIP = -2
+DC_ERR_WORKSPACE = -3
 DC_ERR_STATE = -4
 DC_ERR_NOMEM = -5
 
@@ -33,14 +35,16 @@ class SolveOpts(C.Structure):
                 ("max_cycles", C.c_int32), ("block_jacobi", C.c_int32), ("prec", C.c_int32),
                 ("outer", C.c_int32), ("m_outer", C.c_int32), ("max_outer", C.c_int32),
                 ("inner_tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p),
-                ("schur", C.c_int32), ("ortho", C.c_int32)]
+                ("schur", C.c_int32), ("ortho", C.c_int32), ("x_ref", C.c_void_p)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("status", C.c_int32), ("cycles", C.c_int32), ("iters", C.c_int32),
                 ("matvecs", C.c_int32), ("outer_iters", C.c_int32), ("rebuilt", C.c_int32),
                 ("rel_res_true", C.c_double), ("rel_res_est", C.c_double),
-                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double)]
+                ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
+                ("err_vs_ref", C.c_double), ("breakdowns", C.c_int32),
+                ("refresh_failed", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -49,6 +53,13 @@ class SolveStats(C.Structure):
 # name -> (restype, argtypes); every symbol declared in include/*.h
 SIGNATURES = {
     "dc_default_opts": (C.c_int, [C.POINTER(SolveOpts)]),
+    "dc_workspace_bytes": (C.c_int, [C.POINTER(OpDesc), C.POINTER(SolveOpts), C.c_int32,
+                                     C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "build_coarse_op_ws": (C.c_int, [C.POINTER(OpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_size_t, C.c_void_p, C.c_size_t, C.c_void_p,
+                                     C.POINTER(C.c_void_p)]),
+    "dc_workspace_used": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
+    "dc_device_allocations": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "build_coarse_op": (C.c_int, [C.POINTER(OpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.POINTER(C.c_void_p)]),
     "update_coarse_op": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

@@ -702,6 +702,9 @@ struct BlockGmres {
 
 int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, const double* tol,
                    int use_x0, hipStream_t st, SolveStats* stats) {
+  if (op.caller_ws())
+    throw BadState("block GMRES allocates device memory (rocBLAS): not available on a handle "
+                   "built on caller workspaces");
   if (R < 1) throw InvalidArg("n_rhs must be >= 1");
   if (!b || !x || !tol) throw InvalidArg("null pointer");
   if (o.schur) throw InvalidArg("the block solver works on the full lattice (schur = 0)");

@@ -2,6 +2,7 @@
 // checks, exception-to-status mapping, thread-local error messages.
 #include <cstring>
 #include <exception>
+#include <memory>
 #include <string>
 #include <vector>
 
@@ -33,6 +34,8 @@ int guarded(F&& f) {
     return fail(DC_ERR_NOMEM, e.what());
   } catch (const dc::BadState& e) {
     return fail(DC_ERR_STATE, e.what());
+  } catch (const dc::WorkspaceShort& e) {
+    return fail(DC_ERR_WORKSPACE, e.what());
   } catch (const dc::HipError& e) {
     return fail(DC_ERR_HIP, e.what());
   } catch (const std::bad_alloc&) {
@@ -59,6 +62,7 @@ dc::SolveOpts convert(const dc_solve_opts* o) {
   s.inner_tol = o->inner_tol;
   s.seed = o->seed;
   s.v0 = o->v0;
+  s.x_ref = o->x_ref;
   if (o->schur != 0 && o->schur != 1) throw dc::InvalidArg("schur must be 0 or 1");
   s.schur = o->schur;
   if (o->ortho != 0 && o->ortho != 1) throw dc::InvalidArg("ortho must be 0 or 1");
@@ -79,6 +83,9 @@ void copy_stats(const dc::SolveStats& a, dc_solve_stats* b) {
   b->rel_res_est = a.rel_res_est;
   b->t_setup_ms = a.t_setup_ms;
   b->t_solve_ms = a.t_solve_ms;
+  b->err_vs_ref = a.err_vs_ref;
+  b->breakdowns = a.breakdowns;
+  b->refresh_failed = a.refresh_failed;
 }
 
 }  // namespace
@@ -105,7 +112,78 @@ int dc_default_opts(dc_solve_opts* o) {
   o->v0 = nullptr;
   o->schur = 0;
   o->ortho = 0;
+  o->x_ref = nullptr;
   return DC_OK;
+}
+
+int dc_workspace_bytes(const dc_op_desc* desc, const dc_solve_opts* opts, int32_t max_rhs,
+                       size_t* persistent_bytes, size_t* scratch_bytes) {
+  return guarded([&] {
+    if (!desc || !persistent_bytes || !scratch_bytes) throw dc::InvalidArg("null pointer");
+    if (desc->where != DC_WHERE_HOST && desc->where != DC_WHERE_DEVICE)
+      throw dc::InvalidArg("desc.where must be DC_WHERE_HOST or DC_WHERE_DEVICE");
+    if (desc->store & ~7) throw dc::InvalidArg("unknown bits in desc.store");
+    const dc::SolveOpts o = convert(opts);
+    dc::workspace_bytes(desc->dims, desc->n_tv, desc->store, desc->mu,
+                        desc->where == DC_WHERE_HOST, o, max_rhs, persistent_bytes,
+                        scratch_bytes);
+    return DC_OK;
+  });
+}
+
+int build_coarse_op_ws(const dc_op_desc* desc, const void* self_blocks, const void* hop_blocks,
+                       void* persistent_ws, size_t persistent_bytes, void* scratch_ws,
+                       size_t scratch_bytes, void* stream, dc_op_t* out) {
+  return guarded([&] {
+    if (!desc || !out) throw dc::InvalidArg("null descriptor or output handle");
+    *out = nullptr;
+    if (!persistent_ws || !scratch_ws) throw dc::InvalidArg("null workspace pointer");
+    if (desc->where != DC_WHERE_HOST && desc->where != DC_WHERE_DEVICE)
+      throw dc::InvalidArg("desc.where must be DC_WHERE_HOST or DC_WHERE_DEVICE");
+    if (desc->store & ~7) throw dc::InvalidArg("unknown bits in desc.store");
+    // what the build itself takes, checked before any device work
+    dc::SolveOpts o0;
+    size_t p_all = 0, s_all = 0, p_build = 0, s_build = 0;
+    dc::workspace_bytes(desc->dims, desc->n_tv, desc->store, desc->mu,
+                        desc->where == DC_WHERE_HOST, o0, 0, &p_all, &s_all, &p_build, &s_build);
+    // each arena loses up to one granule to aligning the caller's pointer
+    const size_t g = dc::Arena::kArenaAlign;
+    if (persistent_bytes < p_build + g || scratch_bytes < s_build + g)
+      throw dc::WorkspaceShort("workspace too small to build the operator: persistent " +
+                               std::to_string(persistent_bytes) + " < " +
+                               std::to_string(p_build + g) + " or scratch " +
+                               std::to_string(scratch_bytes) + " < " +
+                               std::to_string(s_build + g) + " bytes");
+    auto h = new dc_op_s;
+    try {
+      h->op.persist = std::make_unique<dc::Arena>(persistent_ws, persistent_bytes);
+      h->op.scratch = std::make_unique<dc::Arena>(scratch_ws, scratch_bytes);
+      h->op.bind_arenas();
+      dc::op_build(h->op, desc->dims, desc->n_tv, desc->store, desc->mu, self_blocks, hop_blocks,
+                   desc->where == DC_WHERE_DEVICE, as_stream(stream));
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return DC_OK;
+  });
+}
+
+int dc_device_allocations(int64_t* count, int64_t* bytes_held) {
+  if (count) *count = dc::device_allocations();
+  if (bytes_held) *bytes_held = dc::device_bytes_held();
+  return DC_OK;
+}
+
+int dc_workspace_used(dc_op_t op, size_t* persistent_peak, size_t* scratch_peak) {
+  return guarded([&] {
+    if (!op) throw dc::InvalidArg("null handle");
+    if (!op->op.caller_ws()) throw dc::BadState("the handle was not built on caller workspaces");
+    if (persistent_peak) *persistent_peak = op->op.persist->peak;
+    if (scratch_peak) *scratch_peak = op->op.scratch->peak;
+    return DC_OK;
+  });
 }
 
 int build_coarse_op(const dc_op_desc* desc, const void* self_blocks, const void* hop_blocks,

@@ -41,6 +41,10 @@ struct NoMem : std::runtime_error {
 struct BadState : std::runtime_error {
   using std::runtime_error::runtime_error;
 };
+// A caller-provided workspace is too small for what the call needs.
+struct WorkspaceShort : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
 
 #define DC_HIP(call)                                                              \
   do {                                                                            \

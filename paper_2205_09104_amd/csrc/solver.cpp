@@ -11,26 +11,117 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <atomic>
 #include <cstring>
 
 namespace dc {
 
+static std::atomic<long long> g_allocs{0}, g_held{0};
+
+long long device_allocations() { return g_allocs.load(); }
+long long device_bytes_held() { return g_held.load(); }
+
+Arena::Arena(void* p, size_t bytes) : base(static_cast<char*>(p)) {
+  // use the granule-aligned part of the caller's range
+  const uintptr_t a = reinterpret_cast<uintptr_t>(base);
+  const uintptr_t a2 = (a + kArenaAlign - 1) / kArenaAlign * kArenaAlign;
+  const size_t skip = size_t(a2 - a);
+  cap = bytes > skip ? (bytes - skip) / kArenaAlign * kArenaAlign : 0;
+  base += skip;
+  if (cap) free_[0] = cap;
+}
+
+void* Arena::take(size_t bytes, const char* what) {
+  const size_t need = round(bytes);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < need) continue;
+    const size_t off = it->first, len = it->second;
+    free_.erase(it);
+    if (len > need) free_[off + need] = len - need;
+    used += need;
+    peak = std::max(peak, used);
+    return base + off;
+  }
+  throw WorkspaceShort(std::string("caller workspace too small for ") + what + " (" +
+                       std::to_string(need) + " bytes; " + std::to_string(cap - used) +
+                       " of " + std::to_string(cap) + " free, fragmented)");
+}
+
+void Arena::give(void* p, size_t bytes) {
+  size_t off = size_t(static_cast<char*>(p) - base);
+  size_t len = round(bytes);
+  used -= len;
+  auto next = free_.lower_bound(off);
+  if (next != free_.end() && off + len == next->first) {   // merge with the block after
+    len += next->second;
+    next = free_.erase(next);
+  }
+  if (next != free_.begin()) {                              // and the block before
+    auto prev = std::prev(next);
+    if (prev->first + prev->second == off) {
+      prev->second += len;
+      return;
+    }
+  }
+  free_[off] = len;
+}
+
 void DevBuf::alloc(size_t b) {
   release();
   if (b == 0) return;
+  if (ar) {
+    p = ar->take(b, what);
+    bytes = b;
+    return;
+  }
   const hipError_t e = hipMalloc(&p, b);
   if (e != hipSuccess) {
     p = nullptr;
     (void)hipGetLastError();
     throw NoMem("hipMalloc of " + std::to_string(b) + " bytes failed: " + hipGetErrorString(e));
   }
+  g_allocs += 1;
+  g_held += (long long)b;
   bytes = b;
 }
 
 void DevBuf::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (ar) {
+      ar->give(p, bytes);
+    } else {
+      (void)hipFree(p);
+      g_held -= (long long)bytes;
+    }
+  }
   p = nullptr;
   bytes = 0;
+}
+
+void Op::bind_arenas() {
+  Arena* P = persist.get();
+  Arena* S = scratch.get();
+  auto bind = [](DevBuf& b, Arena* a, const char* what) { b.ar = a; b.what = what; };
+  bind(nbr, P, "neighbour table");
+  bind(blk64, P, "FP64 blocks");
+  bind(blk32, P, "FP32 blocks");
+  bind(blk16, P, "FP16 blocks");
+  bind(sc16, P, "FP16 scales");
+  for (auto& b : bj) {
+    bind(b.b64, P, "block inverses");
+    bind(b.b32, P, "block inverses");
+    bind(b.b16, P, "block inverses");
+    bind(b.sc16, P, "block inverse scales");
+  }
+  bind(esite, P, "parity table");
+  bind(osite, P, "parity table");
+  for (DevBuf* b : {&gbuf64, &gbuf32, &ts64, &ts32, &rbe, &rbo, &rxe, &rto, &wvbuf, &redpart, &scal,
+                    &t64a, &t64b, &t32a, &t32b, &zouter, &ptrs, &bx64, &bb64, &b32, &x32, &r64})
+    bind(*b, S, "vector scratch");
+  for (BlockWS* w : {&bk64, &bk32})
+    for (DevBuf* b : {&w->V, &w->Z, &w->W, &w->T1, &w->TA, &w->PROD, &w->U, &w->small, &w->tab,
+                      &w->R, &w->X, &w->Bc, &w->part, &w->X0, &w->E0, &w->E})
+      bind(*b, S, "block-solver scratch");
 }
 
 static size_t block_units(int n, Prec p) {
@@ -59,6 +150,10 @@ Variant& Op::variant(Prec p, int sign, int bj, int d, int schur) {
   auto it = variants.find(key);
   if (it != variants.end()) return *it->second;
   auto v = std::make_unique<Variant>();
+  if (caller_ws()) {
+    for (DevBuf* b : {&v->U, &v->C, &v->MU}) { b->ar = persist.get(); b->what = "recycle space"; }
+    for (DevBuf* b : {&v->ws, &v->sm}) { b->ar = scratch.get(); b->what = "Krylov workspace"; }
+  }
   v->prec = p;
   v->sign = sign;
   v->bj = bj;
@@ -75,6 +170,8 @@ static void copy_blocks_in(Op& op, const void* self_blocks, const void* hop_bloc
   const z64* dself = static_cast<const z64*>(self_blocks);
   const z64* dhops = static_cast<const z64*>(hop_blocks);
   DevBuf stage;
+  stage.ar = op.scratch_arena();
+  stage.what = "host block staging";
   if (!on_device) {
     stage.alloc(size_t(op.V) * 5 * nn * sizeof(z64));
     z64* s = stage.as<z64>();
@@ -548,6 +645,33 @@ static std::vector<cd> gcrodr_lstsq(const Mat& Hbar, const Mat& Bk,
   return y;
 }
 
+// Device workspace of one Krylov solver instance: the basis (m + 2 vectors,
+// with a polynomial also the z_j), recycle refresh temporaries, 8 work
+// vectors, and the small arrays (coefficients, Hessenberg, B_k, Givens).
+struct KrylovSizes {
+  int kmax, ldh, nbasis, ktmp, nz, kz;
+  size_t ws_bytes, sm_bytes;
+};
+static KrylovSizes krylov_sizes(size_t N, size_t zbytes, int k, int d, int steps_max,
+                                bool recycle_tmp) {
+  KrylovSizes s;
+  s.kmax = std::max(k, 0);
+  s.ldh = std::max(steps_max, std::max(d, 1)) + 2;
+  s.nbasis = s.ldh + 1;
+  s.ktmp = recycle_tmp ? s.kmax : 0;
+  s.nz = (recycle_tmp && d > 1) ? s.nbasis : 0;
+  s.kz = s.nz ? s.ktmp : 0;
+  const size_t nvec = size_t(s.nbasis) + 2 * size_t(s.ktmp) + size_t(s.nz) + size_t(s.kz) + 8;
+  s.ws_bytes = nvec * N * zbytes;
+  const int kmax = s.kmax, ldh = s.ldh;
+  const size_t q = size_t(kmax + ldh + 4);
+  const size_t nd = 2 * q * 2 + 8 + 2 * size_t(std::max(kmax + ldh + 2, 1)) * std::max(kmax, 2) +
+                    2 * size_t(ldh) * ldh + 2 * size_t(std::max(kmax, 1)) * ldh +
+                    2 * 3 * size_t(ldh + 1) + 64;
+  s.sm_bytes = nd * sizeof(double) + 64 * sizeof(int);
+  return s;
+}
+
 template <typename VR>
 struct Krylov {
   using Z = cx<VR>;
@@ -583,6 +707,9 @@ struct Krylov {
   double *res1 = nullptr, *res2 = nullptr, *nrm = nullptr, *coef = nullptr, *scal = nullptr;
   ArnoldiDev ad{};
   long matvecs = 0;
+  int refresh_failed = 0;         // refreshes whose dense problem failed
+  int breakdowns = 0;             // cycles ended by a happy breakdown
+  bool stuck = false;             // the last cycle broke down at its first step
   double brk;
   const void* bjinv = nullptr;   // block-Jacobi inverses of this precision, if used
   const float* bjsc = nullptr;
@@ -614,15 +741,12 @@ struct Krylov {
       bjinv = bj_blocks(b, p);
       bjsc = (p == P16S) ? b.sc16.as<float>() : nullptr;
     }
-    kmax = std::max(o.k, 0);
-    ldh = std::max(steps_max, std::max(o.d, 1)) + 2;
-    nbasis = ldh + 1;
-    const size_t vb = N * sizeof(Z);
-    const int ktmp = recycle_tmp ? kmax : 0;
-    const int nz = (recycle_tmp && o.d > 1) ? nbasis : 0;
-    const int kz = nz ? ktmp : 0;
-    const size_t nvec = size_t(nbasis) + 2 * size_t(ktmp) + size_t(nz) + size_t(kz) + 8;
-    ws.ensure(nvec * vb);
+    const KrylovSizes ks = krylov_sizes(N, sizeof(Z), o.k, o.d, steps_max, recycle_tmp);
+    kmax = ks.kmax;
+    ldh = ks.ldh;
+    nbasis = ks.nbasis;
+    const int ktmp = ks.ktmp, nz = ks.nz, kz = ks.kz;
+    ws.ensure(ks.ws_bytes);
     Z* base = ws.as<Z>();
     Vb = base;
     Ctmp = Vb + size_t(nbasis) * N;
@@ -643,10 +767,7 @@ struct Krylov {
     tb = ta + N;
     // small area (doubles)
     const size_t q = size_t(kmax + ldh + 4);
-    const size_t nd = 2 * q * 2 + 8 + 2 * size_t(std::max(kmax + ldh + 2, 1)) * std::max(kmax, 2) +
-                      2 * size_t(ldh) * ldh + 2 * size_t(std::max(kmax, 1)) * ldh +
-                      2 * 3 * size_t(ldh + 1) + 64;
-    sm.ensure(nd * sizeof(double) + 64 * sizeof(int));
+    sm.ensure(ks.sm_bytes);
     double* d = sm.as<double>();
     res1 = d;
     res2 = res1 + 2 * q;
@@ -906,6 +1027,7 @@ struct Krylov {
     op.hs.wait(st);
     c.jd = flags[1];
     c.breakdown = flags[2] != 0;
+    if (c.breakdown) ++breakdowns;
     if (c.breakdown && ortho_now == 1) ss_off = true;
     op.prof.end_cycle(c.jd);
     // steps past the stopping one were enqueued but exited at entry
@@ -1150,7 +1272,10 @@ struct Krylov {
         const auto y = lstsq(c.H, e1, &lsres);
         stt.rel_res_est = lsres / bn;
         update_x(x, 0, c.jd, y);
-        if (c.jd == 0) break;  // immediate breakdown: nothing more to gain
+        if (c.jd == 0) {        // immediate breakdown: nothing more to gain
+          stuck = true;
+          break;
+        }
         continue;
       }
       // GCRO-DR cycle
@@ -1209,7 +1334,10 @@ struct Krylov {
         relres = lsres / (bn * ratio);
         break;
       }
-      if (jd == 0) break;
+      if (jd == 0) {
+        stuck = true;
+        break;
+      }
     }
     stt.cycles += cycles;
     stt.matvecs += int(matvecs - mv0);
@@ -1223,7 +1351,8 @@ struct Krylov {
     const int nr = kk + jd + 1, nc = kk + jd;
     // What^H Vhat = [[C^H U D_k, 0], [V^H U D_k, I]]
     Mat WV(nr, nc);
-    op.wvbuf.ensure(size_t(kk) * nr * 2 * sizeof(double));
+    // sized for the longest cycle (nr <= m + 1), so later refreshes reuse it
+    op.wvbuf.ensure(size_t(kk) * std::max(nr, o.m + 1) * 2 * sizeof(double));
     double* wv = op.wvbuf.as<double>();
     for (int i = 0; i < kk; ++i)   // all columns queued, then one read
       launch_multidot(p, Cv(), kk, V(0), jd + 1, N, Uv() + size_t(i) * N, 0, op.red(),
@@ -1238,10 +1367,20 @@ struct Krylov {
     const Mat GH = adjoint(G);
     Mat Bm = matmul(GH, WV);
     Mat Am = matmul(GH, G);
-    if (!lu_solve(Bm, Am)) return;  // Am <- Bm^{-1} Am
+    // a failed dense problem leaves U, C as they are and freezes them (no
+    // further refresh attempts in this or later solves)
+    if (!lu_solve(Bm, Am)) {  // Am <- Bm^{-1} Am
+      var.updates = o.u;
+      ++refresh_failed;
+      return;
+    }
     std::vector<cd> th;
     Mat Zv;
-    if (!eig(Am, th, &Zv)) return;
+    if (!eig(Am, th, &Zv)) {
+      var.updates = o.u;
+      ++refresh_failed;
+      return;
+    }
     const auto idx = smallest_k(th, kk);
     Mat P(nc, kk);
     for (int t = 0; t < kk; ++t)
@@ -1275,13 +1414,16 @@ template <typename VR>
 void build_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st) {
   using Z = cx<VR>;
   SolveOpts po = o;
-  po.k = 0;
   po.ortho = 0;   // harmonic Ritz values from the Gram-Schmidt-twice Hessenberg
+  // sized as the solve's workspace (po.k kept), so the solve reuses it; the
+  // construction cycle below runs without deflation
   Krylov<VR> K(op, var, po, var.ws, var.sm, std::max(o.d, o.m), st);
   var.theta.clear();  // build with A~ itself (no polynomial yet)
   const size_t N = K.N;
   // start vector: caller's v0 (complex128) or a seeded Gaussian
   DevBuf v64;
+  v64.ar = op.scratch_arena();
+  v64.what = "polynomial start vector";
   const z64* src = static_cast<const z64*>(o.v0);
   if (!src) {
     v64.alloc(N * sizeof(z64));
@@ -1400,6 +1542,21 @@ static double fp64_relres(Op& op, const z64* x, const z64* b, int adjoint, hipSt
   return bn > 0 ? rn / bn : 0.0;
 }
 
+// ||x - x_ref|| / ||x_ref|| in FP64 (full-lattice vectors), using the handle's scratch.
+static double fp64_relerr(Op& op, const z64* x, const z64* xref, hipStream_t st) {
+  const size_t N = op.N();
+  op.t64a.ensure(N * sizeof(z64));
+  double* d = op.scal.as<double>();
+  launch_copy_words(x, op.t64a.p, N * sizeof(z64), st);
+  launch_axpy(P64, mk(-1.0, 0.0), xref, op.t64a.p, N, st);
+  launch_norm2(P64, op.t64a.p, N, op.red(), d, st);
+  launch_norm2(P64, xref, N, op.red(), d + 1, st);
+  double h[2];
+  op.hs.read(h, d, 2 * sizeof(double), st);
+  op.hs.wait(st);
+  return h[1] > 0.0 ? std::sqrt(std::max(h[0], 0.0) / h[1]) : std::sqrt(std::max(h[0], 0.0));
+}
+
 int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, void* x,
              const double* tol, int use_x0, hipStream_t st, SolveStats* stats) {
   check_prec(op, o.prec);
@@ -1417,7 +1574,7 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
   // system size: the full lattice, or the even sites of the reduced system
   const size_t N = o.schur ? Nfull / 2 : Nfull;
   const int half = op.V / 2;
-  int all_ok = 1;
+  int all_ok = 1, worst = 1;
   for (int r = 0; r < n_rhs; ++r) {
     const auto t0 = std::chrono::steady_clock::now();
     SolveStats s;
@@ -1477,9 +1634,16 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       xx = xe.as<z64>();
     }
     double rel = 0.0;
+    bool stuck = false;   // stopped on a breakdown at the first step of a cycle
+    auto collect = [&](const auto& K) {
+      s.breakdowns += K.breakdowns;
+      s.refresh_failed += K.refresh_failed;
+    };
     if (o.prec == P64) {
       Krylov<double> K(op, var, o, var.ws, var.sm, o.m, st);
       K.solve(bb, xx, tol_r, use_x0 != 0, o.max_cycles, s, rel);
+      collect(K);
+      stuck = K.stuck;
     } else if (!o.outer) {
       Krylov<float> K(op, var, o, var.ws, var.sm, o.m, st);
       op.t32a.ensure(N * sizeof(z32));
@@ -1489,6 +1653,8 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       launch_convert_64to32(bb, b32, N, op.n, 0, st);
       if (use_x0) launch_convert_64to32(xx, x32, N, op.n, 0, st);
       K.solve(b32, x32, tol_r, use_x0 != 0, o.max_cycles, s, rel);
+      collect(K);
+      stuck = K.stuck;
       launch_convert_32to64(x32, xx, N, op.n, 0, st);
     } else {
       // FP64 flexible GMRES outer loop; its preconditioner is the
@@ -1553,7 +1719,10 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
         s.rel_res_est = lsres / bn;
         KO.upload_coef(y);
         launch_combine(P64, nullptr, 0, Zb, jd, N, KO.coef, 1, xx, 1, st);
-        if (jd == 0) break;
+        if (jd == 0) {
+          stuck = true;
+          break;
+        }
         if (lsres <= 0.5 * tol_r * bn) {
           rel = lsres / bn;
           break;
@@ -1561,6 +1730,8 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
       }
       s.outer_iters = outer_done;
       s.matvecs += int(KO.matvecs);
+      collect(KI);
+      s.breakdowns += KO.breakdowns;
     }
     if (o.schur) {
       launch_reduced_oe(P64, op.n, op.V, op.blocks(P64), nullptr, oinv, nullptr, xe.p, bo.p,
@@ -1572,13 +1743,19 @@ int op_solve(Op& op, const SolveOpts& o, int adjoint, int n_rhs, const void* b, 
     if (adjoint) launch_gamma5(P64, xx, xr, op.V, op.n, st);
     (void)rel;
     s.rel_res_true = fp64_relres(op, xr, br, adjoint, st);
+    if (o.x_ref)
+      s.err_vs_ref = fp64_relerr(op, xr, static_cast<const z64*>(o.x_ref) + size_t(r) * Nfull, st);
     const bool conv = s.rel_res_true <= tol[r];
-    s.status = conv ? 0 : 1;
-    if (!conv) all_ok = 0;
+    // positive statuses: the best iterate is written
+    s.status = conv ? 0 : (stuck ? 2 : 1);
+    if (!conv) {
+      all_ok = 0;
+      worst = std::max(worst, s.status);
+    }
     s.t_solve_ms = ms_since(t0);
     if (stats) stats[r] = s;
   }
-  return all_ok ? 0 : 1;
+  return all_ok ? 0 : worst;
 }
 
 // ============================================================================ batched
@@ -2188,6 +2365,9 @@ static int solve_groups(const std::vector<Op*>& ops, const SolveOpts& o, int adj
 
 int op_solve_batch(Op& op, const SolveOpts& o, int adjoint, int R, const void* b, void* x,
                    const double* tol, int use_x0, hipStream_t st, SolveStats* stats) {
+  if (op.caller_ws())
+    throw BadState("the batched solve allocates per-right-hand-side memory: not available on a "
+                   "handle built on caller workspaces");
   if (R < 0) throw InvalidArg("negative n_rhs");
   if (R == 0) return 0;
   return solve_groups({&op}, o, adjoint, {R}, {b}, {x}, {tol}, use_x0, st, {stats});
@@ -2197,9 +2377,74 @@ int op_solve_multi(const std::vector<Op*>& ops, const SolveOpts& o, int adjoint,
                    const std::vector<int>& R, const std::vector<const void*>& b,
                    const std::vector<void*>& x, const std::vector<const double*>& tol, int use_x0,
                    hipStream_t st, const std::vector<SolveStats*>& stats) {
+  for (const Op* q : ops)
+    if (q && q->caller_ws())
+      throw BadState("the batched solve allocates per-right-hand-side memory: not available on "
+                     "a handle built on caller workspaces");
   if (ops.empty()) throw InvalidArg("no operators");
   if (ops.size() > size_t(kMaxMultiOps) * 64) throw InvalidArg("too many operators");
   return solve_groups(ops, o, adjoint, R, b, x, tol, use_x0, st, stats);
+}
+
+void workspace_bytes(const int dims[4], int n_tv, int store, double mu, bool host_input,
+                     const SolveOpts& o, int max_rhs, size_t* persistent, size_t* scratch,
+                     size_t* build_persistent, size_t* build_scratch) {
+  for (int i = 0; i < 4; ++i)
+    if (dims[i] < 1) throw InvalidArg("lattice extents must be >= 1");
+  if (n_tv < 1 || n_tv > 32) throw InvalidArg("n_tv must be in 1..32");
+  if (o.m < 1 || o.k < 0 || (o.k > 0 && o.k >= o.m) || o.m_outer < 1 || max_rhs < 0)
+    throw InvalidArg("bad solver options");
+  store |= 1;
+  const long long Vll = 1LL * dims[0] * dims[1] * dims[2] * dims[3];
+  if (Vll > (1LL << 30)) throw InvalidArg("lattice too large");
+  const size_t V = size_t(Vll), n = size_t(2 * n_tv), half = V / 2;
+  const bool oddeven = dims[0] % 2 == 0 && dims[1] % 2 == 0 && dims[2] % 2 == 0 &&
+                       dims[3] % 2 == 0;
+  if (o.schur && !oddeven) throw InvalidArg("the odd-even reduction needs every lattice extent even");
+  const auto R = [](size_t b) { return Arena::round(b); };
+  const size_t z64b = sizeof(z64), z32b = sizeof(z32);
+  const size_t vsys = o.prec == P64 ? z64b : z32b;
+  const size_t Nfull = V * n, Nsys = o.schur ? half * n : Nfull;
+  const int nsign = mu != 0.0 ? 2 : 1;    // the adjoint's D(-mu) variant keeps its own state
+  // persistent: tables, blocks, inverses, recycle spaces
+  size_t P = R(8 * V * sizeof(int)) + R(5 * V * block_units(int(n), P64) * 16);
+  if (store & 2) P += R(5 * V * block_units(int(n), P32) * 16);
+  if (store & 4) P += R(5 * V * block_units(int(n), P16S) * 16) + R(5 * V * sizeof(float));
+  if (oddeven) P += 2 * R(half * sizeof(int));
+  if (build_persistent) *build_persistent = P;
+  if (o.block_jacobi || o.schur) {
+    size_t inv = R(V * block_units(int(n), P64) * 16);
+    if (store & 2) inv += R(V * block_units(int(n), P32) * 16);
+    if (store & 4) inv += R(V * block_units(int(n), P16S) * 16) + R(V * sizeof(float));
+    P += size_t(nsign) * inv;
+  }
+  if (o.k > 0) {
+    const size_t kv = R(size_t(o.k) * Nsys * vsys);
+    P += size_t(nsign) * (2 + (o.d > 1 ? 1 : 0)) * kv;
+  }
+  // scratch at build: apply partials, reduction partials, host staging
+  size_t gb = R(V * 9 * n * z64b) + ((store & 6) ? R(V * 9 * n * z32b) : 0);
+  const size_t fixed = gb + R(size_t(kRedCap) * sizeof(double)) + R(256);
+  const size_t build = fixed + (host_input ? R(V * 5 * n * n * z64b) : 0);
+  if (build_scratch) *build_scratch = build;
+  // scratch of the calls
+  size_t run = fixed;
+  run += 2 * R(Nfull * z64b);                                      // FP64 residual / adjoint
+  if (oddeven) run += R(half * n * z64b) + ((store & 6) ? R(half * n * z32b) : 0);  // t_o
+  if (o.schur) run += 4 * R(half * n * z64b);                      // reduced rhs / recovery
+  if (o.prec != P64) run += 2 * R(Nsys * z32b);
+  const KrylovSizes ki = krylov_sizes(Nsys, vsys, o.k, o.d, std::max(o.m, o.d), true);
+  run += size_t(nsign) * (R(ki.ws_bytes) + R(ki.sm_bytes));
+  if (o.outer) {
+    const KrylovSizes ko = krylov_sizes(Nsys, z64b, 0, 0, o.m_outer, true);
+    run += size_t(nsign) * (R(ko.ws_bytes) + R(ko.sm_bytes)) + R(size_t(o.m_outer) * Nsys * z64b);
+  }
+  if (o.k > 0) run += R(size_t(o.k) * (o.m + 1) * 2 * sizeof(double));
+  if (o.d > 1 && !o.v0) run += R(Nsys * z64b);                     // polynomial start vector
+  if (max_rhs > 0) run += R(2 * size_t(max_rhs) * sizeof(void*)); // multi-apply pointer table
+  const size_t slack = 64 * Arena::kArenaAlign;
+  *persistent = P + slack;
+  *scratch = std::max(build, run) + slack;
 }
 
 int op_export_recycle(Op& op, const SolveOpts& o, int adjoint, void* U, void* C, hipStream_t st) {

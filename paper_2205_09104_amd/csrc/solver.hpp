@@ -12,17 +12,47 @@
 
 namespace dc {
 
-// Owning device allocation.
+// Device memory that the caller owns, carved into a handle's buffers: first
+// fit over a free list, blocks of kArenaAlign-byte granules, neighbouring
+// free blocks merged on release.  take() throws WorkspaceShort when no free
+// block is large enough.
+struct Arena {
+  static constexpr size_t kArenaAlign = 256;
+  char* base = nullptr;
+  size_t cap = 0, used = 0, peak = 0;
+  std::map<size_t, size_t> free_;   // offset -> length (granule multiples)
+  Arena(void* p, size_t bytes);
+  void* take(size_t bytes, const char* what);
+  void give(void* p, size_t bytes);
+  static size_t round(size_t b) { return (b + kArenaAlign - 1) / kArenaAlign * kArenaAlign; }
+};
+
+// Number of device allocations (hipMalloc) the library has made in this
+// process, and the bytes they hold now.
+long long device_allocations();
+long long device_bytes_held();
+
+// Owning device allocation: hipMalloc, or a block of an Arena when `ar` is set
+// (a handle built on caller-owned workspaces).
 struct DevBuf {
   void* p = nullptr;
   size_t bytes = 0;
+  Arena* ar = nullptr;
+  const char* what = "buffer";   // named in workspace errors
   DevBuf() = default;
   explicit DevBuf(size_t b) { alloc(b); }
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
-  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes) { o.p = nullptr; o.bytes = 0; }
+  DevBuf(DevBuf&& o) noexcept : p(o.p), bytes(o.bytes), ar(o.ar), what(o.what) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
   DevBuf& operator=(DevBuf&& o) noexcept {
-    if (this != &o) { release(); p = o.p; bytes = o.bytes; o.p = nullptr; o.bytes = 0; }
+    if (this != &o) {
+      release();
+      p = o.p; bytes = o.bytes; ar = o.ar; what = o.what;
+      o.p = nullptr; o.bytes = 0;
+    }
     return *this;
   }
   ~DevBuf() { release(); }
@@ -41,12 +71,16 @@ struct SolveOpts {
   int schur = 0;   // solve the odd-even reduced system (Sec. 2.2)
   int ortho = 0;   // 0: CGS applied twice; 1: single-sync process (Sec. 3.5)
   uint64_t seed = 0;
-  const void* v0 = nullptr;  // device complex128 [V][n]
+  const void* v0 = nullptr;     // device complex128 [V][n]
+  const void* x_ref = nullptr;  // optional reference solutions, device complex128 [n_rhs][V][n]
 };
 
 struct SolveStats {
   int status = 0, cycles = 0, iters = 0, matvecs = 0, outer_iters = 0, rebuilt = 0;
   double rel_res_true = 0, rel_res_est = 0, t_setup_ms = 0, t_solve_ms = 0;
+  double err_vs_ref = -1.0;     // ||x - x_ref|| / ||x_ref|| in FP64 (-1: no reference)
+  int breakdowns = 0;           // cycles that ended on h_{j+1,j} = 0 (happy breakdown)
+  int refresh_failed = 0;       // recycle refreshes whose dense problem failed (space frozen)
 };
 
 struct Op;
@@ -160,6 +194,14 @@ struct CycleSignal {
 };
 
 struct Op {
+  // caller-owned device workspaces (build_coarse_op_ws): blocks, inverses,
+  // tables and recycle spaces come from `persist`, every other buffer from
+  // `scratch`; null: the handle allocates with hipMalloc.  Declared first so
+  // that they outlive every buffer carved from them.
+  std::unique_ptr<Arena> persist, scratch;
+  bool caller_ws() const { return persist != nullptr; }
+  void bind_arenas();             // point every buffer at its arena
+  Arena* scratch_arena() const { return scratch.get(); }
   int dims[4] = {0, 0, 0, 0};
   int V = 0, n = 0, store = 0;
   double mu = 0.0;
@@ -195,6 +237,7 @@ struct Op {
   ApplyProfile prof;
   CycleSignal sig;
   HostStage hs;
+
   Reducer red() const { return Reducer{redpart.as<double>()}; }
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Variant>> variants;
   size_t N() const { return size_t(V) * n; }
@@ -206,6 +249,17 @@ struct Op {
 
 void op_build(Op& op, const int dims[4], int n_tv, int store, double mu, const void* self_blocks,
               const void* hop_blocks, bool on_device, hipStream_t st);
+
+// Device bytes a handle needs when the caller provides its memory: the
+// persistent part (blocks in every stored precision, FP16 scales, neighbour
+// and parity tables, block-Jacobi / odd-site inverses for the signs of mu the
+// options can use, recycle spaces) and the scratch part (apply partials,
+// Krylov bases, vector temporaries), for the single-right-hand-side solves,
+// applies, polynomial and Arnoldi calls with options o and multi-RHS applies
+// of up to max_rhs vectors.  Each buffer is rounded up to the arena granule.
+void workspace_bytes(const int dims[4], int n_tv, int store, double mu, bool host_input,
+                     const SolveOpts& o, int max_rhs, size_t* persistent, size_t* scratch,
+                     size_t* build_persistent = nullptr, size_t* build_scratch = nullptr);
 void op_update(Op& op, const void* self_blocks, const void* hop_blocks, bool on_device,
                hipStream_t st);
 

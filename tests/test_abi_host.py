@@ -107,3 +107,46 @@ def test_harmonic_ritz_and_leja_match_oracle():
             theta = np.array([complex(t) for t in inp.split()])
             want = np.array([complex(t) for t in out.split()])
             assert np.array_equal(leja_order(theta), want), line
+
+
+def test_workspace_query_and_undersized_workspace(lib):
+    """dc_workspace_bytes is host-only and grows with what the options keep;
+    build_coarse_op_ws rejects a workspace too small for the build itself with
+    DC_ERR_WORKSPACE before touching the device (the pointers here are never
+    dereferenced)."""
+    import ctypes as C
+    from paper_2205_09104_amd import Opts, _lib, workspace_bytes
+    dims, ntv = (8, 8, 8, 8), 24
+    V, n = 8 ** 4, 48
+    p0, s0 = workspace_bytes(dims, ntv, ("f64",), opts=Opts(m=30))
+    # FP64 blocks alone: 5 tiled n x n complex blocks per site
+    assert p0 >= V * 5 * n * n * 16
+    p1, s1 = workspace_bytes(dims, ntv, ("f64", "f32", "f16s"),
+                             opts=Opts(m=126, k=96, d=32, prec="f16s", outer=1, schur=1,
+                                       block_jacobi=1))
+    assert p1 > p0 + V * 5 * n * n * (8 + 4)       # two more block copies, inverses, recycle
+    assert s1 > s0
+    # twisted mass: the adjoint variant keeps its own inverses and recycle space
+    p2, _ = workspace_bytes(dims, ntv, ("f64", "f32", "f16s"), mu=1e-3,
+                            opts=Opts(m=126, k=96, d=32, prec="f16s", outer=1, schur=1,
+                                      block_jacobi=1))
+    assert p2 > p1
+    desc = _lib.OpDesc()
+    for i in range(4):
+        desc.dims[i] = dims[i]
+    desc.n_tv, desc.store, desc.where, desc.mu = ntv, 1, _lib.DC_WHERE_DEVICE, 0.0
+    h = C.c_void_p()
+    fake = C.c_void_p(1 << 40)
+    rc = lib.build_coarse_op_ws(C.byref(desc), fake, fake, fake, p0 // 2, fake, s0, None,
+                                C.byref(h))
+    assert rc == _lib.DC_ERR_WORKSPACE and not h.value
+    assert "workspace" in lib.dc_last_error().decode()
+    rc = lib.build_coarse_op_ws(C.byref(desc), fake, fake, fake, p0, fake, 1024, None, C.byref(h))
+    assert rc == _lib.DC_ERR_WORKSPACE
+    assert lib.build_coarse_op_ws(C.byref(desc), fake, fake, None, p0, fake, s0, None,
+                                  C.byref(h)) == _lib.DC_ERR_INVALID
+    # bad options are rejected by the query
+    o = Opts(m=10, k=20).to_c()
+    pb, sb = C.c_size_t(), C.c_size_t()
+    assert lib.dc_workspace_bytes(C.byref(desc), C.byref(o), 0, C.byref(pb),
+                                  C.byref(sb)) == _lib.DC_ERR_INVALID
