@@ -231,6 +231,23 @@ int dc_apply(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* ou
 int dc_apply_reduced(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, void* out,
                      void* stream);
 
+/* dc_apply_reduced for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * kernels and result, with the odd-row temporary t_o = D_oo^{-1} D_oe in kept
+ * in a fixed device array of the library (64 MiB per GPU, held until the
+ * process ends) instead of the handle's memory.  It calls no allocating
+ * routine at all, so:
+ *   - V/2 * n * (16 for DC_PREC_F64, else 8) bytes must fit 64 MiB
+ *     (DC_ERR_INVALID otherwise; e.g. 16^3 x 32 sites with n = 48 fit in FP64);
+ *   - the odd self-block inverses for this adjoint flag must already exist:
+ *     call dc_apply_reduced (or a reduced solve) once first after building or
+ *     updating the handle (DC_ERR_STATE otherwise).
+ * Every call on one GPU shares the array: calls that overlap in time on the
+ * same GPU (different streams or threads) race and give wrong results; calls
+ * in one stream are ordered and safe.  Arguments as dc_apply_reduced. */
+int dc_apply_reduced_noalloc(dc_op_t op, int32_t prec, int32_t adjoint, const void* in,
+                             void* out, void* stream);
+
 /* The reduced operator with the left block-Jacobi preconditioner of Sec. 3.2,
  * which for the reduced system takes B = D_ee, the even sites' self blocks
  * (A_x + i mu Gamma5; not the block diagonal of S, a choice the paper makes

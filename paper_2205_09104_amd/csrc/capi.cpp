@@ -161,6 +161,7 @@ int build_coarse_op_ws(const dc_op_desc* desc, const void* self_blocks, const vo
       h->op.bind_arenas();
       dc::op_build(h->op, desc->dims, desc->n_tv, desc->store, desc->mu, self_blocks, hop_blocks,
                    desc->where == DC_WHERE_DEVICE, as_stream(stream));
+      dc::noalloc_scratch(true);   // set-up of dc_apply_reduced_noalloc on this device
     } catch (...) {
       delete h;
       throw;
@@ -198,6 +199,7 @@ int build_coarse_op(const dc_op_desc* desc, const void* self_blocks, const void*
     try {
       dc::op_build(h->op, desc->dims, desc->n_tv, desc->store, desc->mu, self_blocks, hop_blocks,
                    desc->where == DC_WHERE_DEVICE, as_stream(stream));
+      dc::noalloc_scratch(true);   // set-up of dc_apply_reduced_noalloc on this device
     } catch (...) {
       delete h;
       throw;
@@ -242,6 +244,16 @@ int dc_apply_reduced(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, 
     if (!op) throw dc::InvalidArg("null handle");
     if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
     dc::op_apply_reduced(op->op, dc::Prec(prec), adjoint, 0, in, out, as_stream(stream));
+    return DC_OK;
+  });
+}
+
+int dc_apply_reduced_noalloc(dc_op_t op, int32_t prec, int32_t adjoint, const void* in,
+                             void* out, void* stream) {
+  return guarded([&] {
+    if (!op) throw dc::InvalidArg("null handle");
+    if (prec < 0 || prec > 2) throw dc::InvalidArg("unknown precision");
+    dc::op_apply_reduced_noalloc(op->op, dc::Prec(prec), adjoint, in, out, as_stream(stream));
     return DC_OK;
   });
 }

@@ -10,7 +10,34 @@
 
 #include <hip/hip_fp16.h>
 
+// Scratch of the no-allocation reduced apply (dc_apply_reduced_noalloc): the
+// odd-row temporary t_o lives in this file-scope device array, one copy per
+// GPU, held until the process ends.  Host code never passes `scratch` itself
+// to a kernel (in host code it names a host-side stand-in): it passes the
+// device address that hipGetSymbolAddress returned for the current device.
+static __device__ __align__(256) unsigned char scratch[dc::kNoAllocScratchBytes];
+
 namespace dc {
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+void* noalloc_scratch(bool setup) {
+  int dev = 0;
+  DC_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw InvalidArg("device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    if (!setup) return nullptr;
+    void* p = nullptr;
+    DC_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw HipError("hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_dev[dev] = p;
+  }
+  return g_scratch_dev[dev];
+}
 
 namespace {
 

@@ -7,6 +7,16 @@
 
 namespace dc {
 
+// ---------------------------------------------------------------- fixed scratch
+// Size of the file-scope device array behind the no-allocation reduced apply
+// (the odd-row temporary: V/2 x n complex values of the vector precision).
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+// Device address of that array on the current device.  setup = true looks
+// it up (hipGetSymbolAddress) on the first call for the device and keeps it;
+// setup = false returns null if that has not happened yet.
+void* noalloc_scratch(bool setup);
+
 // Deterministic two-stage reduction scratch: each block of a reduction kernel
 // stores its partial sums value-major, a one-wave-per-value finalize kernel
 // sums them in a fixed order (results do not depend on block scheduling).

@@ -584,6 +584,47 @@ void op_apply_reduced(Op& op, Prec p, int adjoint, int block_jacobi, const void*
   if (adjoint) launch_gamma5(p, out, out, half, op.n, st);
 }
 
+void op_apply_reduced_noalloc(Op& op, Prec p, int adjoint, const void* in, void* out,
+                              hipStream_t st) {
+  check_prec(op, p);
+  if (!op.oddeven) throw InvalidArg("the odd-even reduction needs every lattice extent even");
+  if (!in || !out) throw InvalidArg("null vector pointer");
+  const int half = op.V / 2;
+  const size_t N = size_t(half) * op.n;
+  const size_t span = N * vec_bytes(p);
+  {
+    const char* a = static_cast<const char*>(in);
+    const char* b = static_cast<const char*>(out);
+    if (a < b + span && b < a + span) throw InvalidArg("in and out overlap");
+  }
+  // the odd-row temporary must fit the fixed scratch
+  if (span > kNoAllocScratchBytes)
+    throw InvalidArg("the odd-row temporary (" + std::to_string(span) +
+                     " bytes) exceeds the fixed scratch of " +
+                     std::to_string(kNoAllocScratchBytes) + " bytes");
+  const int sign = adjoint ? -1 : +1;
+  const Op::BJ& bj = op.bj[sign > 0 ? 0 : 1];
+  if (bj.version != op.version)
+    throw BadState("the odd self-block inverses of this operator are not built yet: call "
+                   "dc_apply_reduced (or a reduced solve) with the same adjoint flag first");
+  void* t = noalloc_scratch(true);   // looked up once per device (at build, normally)
+  const void* inv = bj_blocks(bj, p);
+  const float* invsc = (p == P16S) ? bj.sc16.as<float>() : nullptr;
+  const double tm = sign * op.mu;
+  const void* src = in;
+  if (adjoint) {
+    launch_gamma5(p, in, out, half, op.n, st);
+    src = out;
+  }
+  const z64 z = mk(0.0, 0.0);
+  launch_reduced_oe(p, op.n, op.V, op.blocks(p), op.scales(p), inv, invsc, src, t,
+                    op.nbr.as<int>(), op.osite.as<int>(), nullptr, st);
+  launch_reduced_eo(p, 0, op.n, op.V, op.blocks(p), op.scales(p), nullptr, nullptr, src, t,
+                    op.nbr.as<int>(), op.esite.as<int>(), tm, out, nullptr, nullptr, z, z, z,
+                    nullptr, st);
+  if (adjoint) launch_gamma5(p, out, out, half, op.n, st);
+}
+
 void op_apply_bj(Op& op, const void* in, void* out, hipStream_t st) {
   if (!in || !out || in == out) throw InvalidArg("bad vector pointers");
   const Op::BJ& b = op.ensure_bj(+1, st);

@@ -269,6 +269,10 @@ void op_apply_bj(Op& op, const void* in, void* out, hipStream_t st);
 // block_jacobi: out = D_ee^{-1} S in (left block Jacobi of the reduced system)
 void op_apply_reduced(Op& op, Prec p, int adjoint, int block_jacobi, const void* in, void* out,
                       hipStream_t st);
+// The reduced apply with its odd-row temporary in the fixed device scratch
+// (noalloc_scratch): no allocation of any kind; the inverses must exist.
+void op_apply_reduced_noalloc(Op& op, Prec p, int adjoint, const void* in, void* out,
+                              hipStream_t st);
 void op_apply_multi(Op& op, Prec p, int adjoint, int R, const void* in, void* out, hipStream_t st);
 int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta);
 void op_poly_apply(Op& op, const SolveOpts& o, const void* in, void* out, hipStream_t st);
