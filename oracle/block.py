@@ -17,6 +17,26 @@ Gram-Schmidt between blocks is classical, applied twice; the new block is
 orthonormalised by a QR factorisation (H_{j+1,j} its triangular factor).  A
 rank-deficient new block (an invariant subspace reached by some combination of
 columns) ends the cycle.
+
+Numerically dependent residual columns (restarts of many columns whose
+residuals have collapsed onto a few slow directions) cannot all generate the
+space: the generating block is the orthonormalised set of columns picked
+greedily, each having the largest part outside the span of the earlier picks
+(pivoting on the column-scaled block), while that part's squared relative
+size exceeds sel_piv.  Every column still takes its least-squares
+minimiser over the space those picks generate (the cycle then runs up to
+m c / (picks) block steps, so that its space keeps the dimension m c that c
+independent columns would give): with R_0 = [r_1 .. r_c] and
+orthonormal blocks V_0 .. V_{j+1}, column a minimises
+|| g_a - Hbar y || with g_a = [V_0^H r_a; V_1^H r_a; ...; V_{j+1}^H r_a] --
+the parts of r_a outside V_0 are not orthogonal to the later blocks -- and
+its residual norm is sqrt(|| g_a - Hbar y_a ||^2 + ||r_a||^2 - ||g_a||^2).
+
+Deflation against a recycled pair (U, C) with C = A M U orthonormal (the
+GCRO-DR space of Sec. 3.4, frozen): every new residual block starts with
+x += M U C^H r, r -= C C^H r, the block Arnoldi runs on (I - C C^H) A M with
+B_k = C^H A M V, and column a's correction M (V y_a - U B_k y_a) leaves the
+residual r_a - V Hbar y_a (the C components cancel).
 """
 from __future__ import annotations
 
@@ -60,17 +80,110 @@ def block_arnoldi(A, R0, m: int, targets=None, rank_tol: float = 1e-12):
     return V, H[:(steps + 1) * r, :steps * r], S0, steps, est
 
 
-def block_gmres(A, B, tols, m: int, max_cycles: int, right=None):
+def select_generators(R0, sel_piv: float):
+    """Indices of the residual columns that generate the space, in pick order
+    (greedy pivoting on the column-scaled block, written out as Gram-Schmidt
+    twice): each pick is the column with the largest squared part outside the
+    span of the earlier picks (the lowest index among parts equal to a relative
+    1e-10, so the unit columns' first pick is column 0), kept while that part
+    exceeds sel_piv."""
+    d = np.linalg.norm(R0, axis=0)
+    cols = [R0[:, i] / d[i] if d[i] > 0 else None for i in range(R0.shape[1])]
+    Q, picks = [], []
+    while True:
+        rests = {}
+        for i, c in enumerate(cols):
+            if c is None or i in picks:
+                continue
+            w = c.copy()
+            for _ in range(2):
+                for q in Q:
+                    w = w - np.vdot(q, w) * q
+            rests[i] = float(np.vdot(w, w).real)
+        if not rests:
+            break
+        top = max(rests.values())
+        # parts within a relative 1e-10 of the largest count as equal
+        best = min(i for i, r in rests.items() if r >= top * (1.0 - 1e-10))
+        if not rests[best] > sel_piv:
+            break
+        w = cols[best].copy()
+        for _ in range(2):
+            for q in Q:
+                w = w - np.vdot(q, w) * q
+        Q.append(w / np.linalg.norm(w))
+        picks.append(best)
+    return np.array(picks, dtype=np.int64)
+
+
+def ls_rhs(Vblocks, R):
+    """Right-hand sides of every column's least squares: the coefficients of
+    the residual columns R on each basis block, stacked (V_i^H R)."""
+    return np.concatenate([Vb.conj().T @ R for Vb in Vblocks], axis=0)
+
+
+def _cycle(Ablk, R, m, targets, sel_piv, C):
+    """One block cycle for the residual block R (N x c, already deflated when
+    C is given).  Returns (Vblocks, Hbar, Y, steps, est, Bk, picks)."""
+    N, c = R.shape
+    picks = select_generators(R, sel_piv)
+    if picks.size == 0:
+        return [], None, None, 0, np.linalg.norm(R, axis=0), None, picks
+    V0, _ = np.linalg.qr(R[:, picks])
+    nb = V0.shape[1]
+    V = [V0]
+    H = np.zeros(((m + 1) * nb, m * nb), dtype=np.complex128)
+    k = 0 if C is None else C.shape[1]
+    Bk = np.zeros((k, m * nb), dtype=np.complex128)
+    rn2 = np.linalg.norm(R, axis=0) ** 2
+    steps, Y = 0, None
+    est = np.sqrt(rn2)
+    for j in range(m):
+        W = Ablk(V[j])
+        hcol = np.zeros(((j + 1) * nb, nb), dtype=np.complex128)
+        for _ in range(2):
+            if k:
+                b = C.conj().T @ W
+                W = W - C @ b
+                Bk[:, j * nb:(j + 1) * nb] += b
+            for i in range(j + 1):
+                h = V[i].conj().T @ W
+                W = W - V[i] @ h
+                hcol[i * nb:(i + 1) * nb] += h
+        Q, Rj = np.linalg.qr(W)
+        H[:(j + 1) * nb, j * nb:(j + 1) * nb] = hcol
+        H[(j + 1) * nb:(j + 2) * nb, j * nb:(j + 1) * nb] = Rj
+        V.append(Q)
+        steps = j + 1
+        Hs = H[:(steps + 1) * nb, :steps * nb]
+        G = ls_rhs(V, R)
+        Y = np.linalg.lstsq(Hs, G, rcond=None)[0]
+        inside = np.linalg.norm(G - Hs @ Y, axis=0) ** 2
+        outside = np.maximum(rn2 - np.linalg.norm(G, axis=0) ** 2, 0.0)
+        est = np.sqrt(inside + outside)
+        if np.min(np.abs(np.diag(Rj))) <= 1e-12 * max(np.linalg.norm(R, axis=0).max(), 1e-300):
+            break
+        if targets is not None and np.all(est <= targets):
+            break
+    return V, H[:(steps + 1) * nb, :steps * nb], Y, steps, est, Bk[:, :steps * nb], picks
+
+
+def block_gmres(A, B, tols, m: int, max_cycles: int, right=None, U=None, C=None,
+                sel_piv: float = 1e-12):
     """Solve A X = B (N x R, per-column relative tolerances) with restarted
-    block GMRES(m).  A and right act on single vectors.  Returns (X, info)
-    with info = dict(cycles, steps, relres per column, converged)."""
+    block GMRES(m).  A and right act on single vectors.  U, C: an optional
+    frozen recycle space (C = A right(U), orthonormal columns) to deflate
+    against.  Returns (X, info) with info = dict(cycles, steps, relres per
+    column, converged, generators: the generating-block size of each cycle)."""
     N, R = B.shape
     M = right or (lambda v: v)
     apply_block = lambda Vb: np.stack([A(M(Vb[:, c])) for c in range(Vb.shape[1])], axis=1)
+    Mblk = lambda Vb: np.stack([M(Vb[:, c]) for c in range(Vb.shape[1])], axis=1)
     X = np.zeros_like(B)
     bn = np.linalg.norm(B, axis=0)
     tols = np.asarray(tols, dtype=np.float64)
     cycles = steps = 0
+    gens = []
     rel = np.ones(R)
     while True:
         Rm = B - np.stack([A(X[:, c]) for c in range(R)], axis=1)
@@ -79,16 +192,25 @@ def block_gmres(A, B, tols, m: int, max_cycles: int, right=None):
         if active.size == 0 or cycles >= max_cycles:
             break
         R0 = Rm[:, active]
-        V, Hs, S0, j, _ = block_arnoldi(apply_block, R0, m, targets=tols[active] * bn[active])
-        r = active.size
-        E = np.zeros(((j + 1) * r, r), dtype=np.complex128)
-        E[:r] = S0
-        Y = np.linalg.lstsq(Hs, E, rcond=None)[0]
-        Vm = np.concatenate(V[:j], axis=1)
-        U = Vm @ Y
-        for a, c in enumerate(active):
-            X[:, c] += M(U[:, a])
+        if C is not None:
+            coef = C.conj().T @ R0
+            X[:, active] += Mblk(U @ coef)
+            R0 = R0 - C @ coef
+        # a block with fewer generators than columns keeps the dimension of
+        # the cycle's space: up to m * (columns) / (generators) block steps
+        npick = select_generators(R0, sel_piv).size
+        m_eff = m if npick in (0, R0.shape[1]) else (m * R0.shape[1]) // npick
+        V, Hs, Y, j, _, Bk, picks = _cycle(apply_block, R0, m_eff, tols[active] * bn[active],
+                                           sel_piv, C)
+        gens.append(int(picks.size))
         cycles += 1
         steps += j
+        if j == 0:
+            break
+        Vm = np.concatenate(V[:j], axis=1)
+        corr = Vm @ Y
+        if C is not None:
+            corr = corr - U @ (Bk @ Y)
+        X[:, active] += Mblk(corr)
     return X, {"cycles": cycles, "steps": steps, "relres": rel,
-               "converged": bool(np.all(rel <= tols))}
+               "converged": bool(np.all(rel <= tols)), "generators": gens}

@@ -87,3 +87,136 @@ def test_per_column_tolerances_on_coarse_operator():
     assert np.all(rel <= tols)
     Xr = np.linalg.solve(D, B)
     assert np.linalg.norm(X[:, 0] - Xr[:, 0]) <= 1e-7 * np.linalg.norm(Xr[:, 0])
+
+
+def _krylov_min(A, K, r):
+    """min_y || r - A K y || by brute force (dense least squares)."""
+    AK = np.stack([A(K[:, i]) for i in range(K.shape[1])], axis=1)
+    y = np.linalg.lstsq(AK, r, rcond=None)[0]
+    return np.linalg.norm(r - AK @ y)
+
+
+def _dependent_block(N=60, seed=5):
+    M, rng = _matrix(N=N, seed=seed)
+    base = rng.standard_normal((N, 3)) + 1j * rng.standard_normal((N, 3))
+    mix = rng.standard_normal((3, 4)) + 1j * rng.standard_normal((3, 4))
+    # three independent columns and four combinations of them, each with a
+    # part outside their span of relative size 1e-7 (dependent at 1e-12)
+    noise = rng.standard_normal((N, 4)) + 1j * rng.standard_normal((N, 4))
+    dep = base @ mix + 1e-7 * np.linalg.norm(base @ mix, axis=0) * noise / np.linalg.norm(noise, axis=0)
+    return M, np.concatenate([base, dep], axis=1)
+
+
+def test_dependent_columns_select_generators():
+    from oracle.block import select_generators
+    M, B = _dependent_block()
+    picks = select_generators(B, 1e-12)
+    assert picks.size == 3
+    # the picks span the block to within the planted 1e-7 parts
+    Q, _ = np.linalg.qr(B[:, picks])
+    res = np.linalg.norm(B - Q @ (Q.conj().T @ B), axis=0) / np.linalg.norm(B, axis=0)
+    assert res.max() <= 2e-7
+    assert select_generators(B, 1e-16).size == 7       # a looser threshold keeps all
+
+
+def test_dependent_columns_minimise_over_generated_space():
+    """Residual columns that are numerically dependent generate the space from
+    3 picks (the cycle runs 4 x 7 / 3 = 9 block steps, keeping the space's
+    dimension); every one of the 7 columns gets its exact least-squares
+    minimum over A times that space, including the parts of its residual
+    outside the first block (brute-force least squares)."""
+    from oracle.block import select_generators
+    M, B = _dependent_block()
+    A = lambda v: M @ v
+    m = 4
+    X, info = block_gmres(A, B, [1e-30] * 7, m, 1)
+    assert info["generators"] == [3]
+    assert info["steps"] == m * 7 // 3        # the space keeps dimension m x 7
+    V0, _ = np.linalg.qr(B[:, select_generators(B, 1e-12)])
+    K = [V0]
+    for _ in range(info["steps"] - 1):
+        Q, _ = np.linalg.qr(M @ K[-1])
+        K.append(Q)
+    K = np.concatenate(K, axis=1)
+    for c in range(7):
+        got = np.linalg.norm(B[:, c] - M @ X[:, c])
+        best = _krylov_min(A, K, B[:, c])
+        assert abs(got - best) <= 1e-8 * best + 1e-13 * np.linalg.norm(B[:, c])
+
+
+def test_dropping_outside_parts_is_detected():
+    """A mistake planted in the oracle (least squares with only the first
+    block's coefficients V_0^H r, the parts of r outside V_0 dropped) leaves
+    the dependent columns short of their minimum: the pin above catches it."""
+    import oracle.block as ob
+    M, B = _dependent_block()
+    B = B.copy()
+    nz = np.random.default_rng(9).standard_normal((60, 4))
+    # parts of relative size 3e-2 outside the picks (dependent at sel_piv 1e-2)
+    B[:, 3:] += 3e-2 * np.linalg.norm(B[:, 3:], axis=0) * nz / np.linalg.norm(nz, axis=0)
+    A = lambda v: M @ v
+    saved = ob.ls_rhs
+    ob.ls_rhs = lambda V, R: np.concatenate(
+        [V[0].conj().T @ R] + [np.zeros((Vb.shape[1], R.shape[1]), complex) for Vb in V[1:]], 0)
+    try:
+        X, info = ob.block_gmres(A, B, [1e-30] * 7, 4, 1, sel_piv=1e-2)
+    finally:
+        ob.ls_rhs = saved
+    Xf, info_f = ob.block_gmres(A, B, [1e-30] * 7, 4, 1, sel_piv=1e-2)
+    assert info["generators"] == info_f["generators"] == [3]
+    worse = [np.linalg.norm(B[:, c] - M @ X[:, c]) / np.linalg.norm(B[:, c] - M @ Xf[:, c])
+             for c in range(3, 7)]
+    assert max(worse) > 1.2
+
+
+def test_deflated_block_cycle_is_minimal_over_recycled_and_krylov_space():
+    """Deflation against a recycled pair (U, C = A U orthonormal): after one
+    cycle every column's residual is orthogonal to C and minimal over
+    A span(U, K_m((I - C C^H) A, R_0 deflated)) (brute force)."""
+    M, rng = _matrix(N=50, seed=6)
+    A = lambda v: M @ v
+    Uu = rng.standard_normal((50, 4)) + 1j * rng.standard_normal((50, 4))
+    C, Rr = np.linalg.qr(M @ Uu)
+    U = Uu @ np.linalg.inv(Rr)                      # C = A U exactly
+    B = rng.standard_normal((50, 3)) + 1j * rng.standard_normal((50, 3))
+    m = 3
+    X, info = block_gmres(A, B, [1e-30] * 3, m, 1, U=U, C=C)
+    R0 = B - C @ (C.conj().T @ B)
+    P = lambda W: W - C @ (C.conj().T @ W)
+    V0, _ = np.linalg.qr(R0)
+    K = [V0]
+    for _ in range(m - 1):
+        K.append(P(M @ K[-1]))
+    K = np.concatenate([U] + K, axis=1)
+    for c in range(3):
+        r = B[:, c] - M @ X[:, c]
+        assert np.linalg.norm(C.conj().T @ r) <= 1e-12 * np.linalg.norm(B[:, c])
+        best = _krylov_min(A, K, B[:, c])
+        assert np.linalg.norm(r) <= best * (1 + 1e-8)
+
+
+def test_deflated_block_gmres_converges_on_coarse_operator():
+    """Recycle space from the oracle's GCRO-DR on a small coarse operator,
+    then block GMRES deflated against it: every column to its tolerance, in
+    fewer block steps than without deflation."""
+    from oracle.gcrodr import RecycleState, gcrodr
+    dims, ntv = (2, 2, 2, 2), 4
+    A0 = synth.self_blocks(dims, ntv, 3.5, 0).numpy()
+    Bh = synth.hop_blocks(dims, ntv, 0).numpy()
+    op = dop.build(dims, A0, Bh, 0.05)
+    f = lambda v: dop.apply(op, v.reshape(op.V, op.n)).reshape(-1)
+    D = dop.dense(op)
+    rng = np.random.default_rng(8)
+    N = op.V * op.n
+    st = RecycleState()
+    for r in range(2):
+        b = rng.standard_normal(N) + 1j * rng.standard_normal(N)
+        gcrodr(f, b, 1e-10, 24, 8, 10, 200, st)
+    B = rng.standard_normal((N, 4)) + 1j * rng.standard_normal((N, 4))
+    tols = np.array([1e-10, 1e-8, 1e-9, 1e-7])
+    X, info = block_gmres(f, B, tols, 6, 400, U=st.U, C=st.C)
+    X0, info0 = block_gmres(f, B, tols, 6, 400)
+    assert info["converged"] and info0["converged"]
+    rel = np.linalg.norm(B - D @ X, axis=0) / np.linalg.norm(B, axis=0)
+    assert np.all(rel <= tols)
+    assert info["steps"] < info0["steps"]
