@@ -1,19 +1,21 @@
 """Benchmark: coarse solves/s to relative residual 1e-8 on one MI355X.
 
-Workload: the synthetic 8^4 coarse operator with N_tv = 24 (196,608 unknowns,
-clover-Wilson type, m0 from the limiting spectral disk with min Re / max|.| =
-1e-4), seeded right-hand sides.
+Workload (default): the synthetic 16^3 x 32 twisted-mass coarse operator with
+N_tv = 24 (6,291,456 unknowns, mu = 1e-3, m0 from the limiting spectral disk
+with min Re / max|.| = 1e-4), seeded Gaussian right-hand sides.
 A step is one complete coarse solve of a fresh right-hand side with the
-method's solver: polynomial preconditioning (d Leja-ordered harmonic Ritz
-values) + GCRO-DR deflation/recycling (k vectors), reduced-precision inner
-solve inside an FP64 flexible-GMRES outer loop; the FP64 true residual of
-every solve is checked.  Plain FP64 GMRES(30) is run on the same operator and
-right-hand sides for comparison (capped: on this operator it can stagnate).
-The roofline entry is the kernel that streams the stored blocks in the method's
-applies (on the odd-even reduced system, the A_e - D_eo kernel), timed live in
-the timed solves with HIP events on the library's launch stream.
+paper's coarsest-level method on the odd-even reduced system: left block
+Jacobi with B = D_ee, polynomial preconditioning (d Leja-ordered harmonic Ritz
+values of B^{-1} S) and GCRO-DR deflation / recycling (k vectors), as a
+reduced-precision (FP16-stored blocks, FP32 arithmetic) inner solve inside an
+FP64 flexible-GMRES outer loop; the FP64 true residual of every solve is
+checked.  Plain FP64 GMRES(30) runs on the same operator and right-hand side
+for comparison (capped by wall time: on this operator it stagnates).  The
+roofline entry is the kernel that streams the stored blocks in the method's
+applies (the A_e - D_eo kernel, here with the even inverses of block Jacobi),
+timed live in the timed solves with HIP events on the library's launch stream.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3|c2]
 """
 from __future__ import annotations
 
@@ -34,39 +36,66 @@ def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=16)
-    p.add_argument("--warmup", type=int, default=2,
-                   help="untimed solves before the timed ones; two complete the recycle "
-                        "space's u = 10 refreshes (the setup phase), so the timed solves "
-                        "see it frozen")
-    p.add_argument("--workload", default="c2")
+    p.add_argument("--warmup", type=int, default=3,
+                   help="untimed solves before the timed ones; the first builds the polynomial "
+                        "and the recycle space, the first two complete its u = 10 refreshes "
+                        "(the setup phase), so the timed solves see it frozen")
+    p.add_argument("--workload", default="c3")
     p.add_argument("--tol", type=float, default=1e-8)
     p.add_argument("--inner", default="f16s", choices=["f32", "f16s"])
-    p.add_argument("--d", type=int, default=32)
-    p.add_argument("--k", type=int, default=96)
+    p.add_argument("--d", type=int, default=24)
+    p.add_argument("--k", type=int, default=384)
+    p.add_argument("--bj", type=int, default=1, choices=[0, 1],
+                   help="left block Jacobi (B = D_ee on the reduced system)")
+    p.add_argument("--u", type=int, default=30, help="recycle-space refreshes before freezing")
     p.add_argument("--schur", type=int, default=1, choices=[0, 1],
                    help="solve the odd-even reduced system (1) or the full lattice (0)")
-    p.add_argument("--full-steps", type=int, default=4,
-                   help="timed solves of the same method on the full lattice, for comparison")
+    p.add_argument("--full-steps", type=int, default=-1,
+                   help="timed solves of the same method on the full lattice, for comparison "
+                        "(-1: 4 on lattices up to 8^4, else 0)")
     p.add_argument("--m", type=int, default=30, help="new Arnoldi vectors per cycle")
     p.add_argument("--ortho", type=int, default=1, choices=[0, 1],
                    help="Arnoldi: 0 Gram-Schmidt twice, 1 single-sync (one reduction per step)")
-    p.add_argument("--ss-steps", type=int, default=4,
-                   help="timed solves of the same method with the other --ortho choice")
+    p.add_argument("--ss-steps", type=int, default=-1,
+                   help="timed solves of the same method with the other --ortho choice "
+                        "(-1: 4 on lattices up to 8^4, else 0)")
+    p.add_argument("--bj-steps", type=int, default=-1,
+                   help="timed solves of the same method with the other --bj choice "
+                        "(-1: 4 on lattices up to 8^4, else 0)")
+    p.add_argument("--c1-steps", type=int, default=40,
+                   help="solves of the 4^4 workload (launch-bound) with and without the "
+                        "Arnoldi cycles replayed as HIP graphs (0: skip)")
+    p.add_argument("--c2-steps", type=int, default=16,
+                   help="timed solves of the same method on the 8^4 workload after the "
+                        "headline (0: skip)")
     p.add_argument("--inner-tol", type=float, default=1e-1)
     p.add_argument("--plain-steps", type=int, default=1)
-    p.add_argument("--plain-max-cycles", type=int, default=400,
-                   help="restart cycles of the plain GMRES(30) comparison (it may stagnate)")
+    p.add_argument("--plain-seconds", type=float, default=15.0,
+                   help="wall-time cap of each FP64 comparison solve (they can stagnate); "
+                        "reported as not converged with the residual reached")
     p.add_argument("--apply-reps", type=int, default=50)
     p.add_argument("--multi-rhs", type=int, default=64,
                    help="right-hand sides of the multi-RHS (MFMA) apply measurement (0: skip)")
     p.add_argument("--profile-every", type=int, default=8,
                    help="time one in this many launches of the apply's block kernel (0: off)")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--cpu-seconds", type=float, default=10.0)
+    p.add_argument("--ref-tol", type=float, default=1e-11,
+                   help="tolerance of the reference solve for the forward error (same method, "
+                        "its FP64 outer loop carried further)")
     p.add_argument("--summarize-trace", default=None, metavar="CSV",
                    help="only summarise a rocprofv3 kernel_trace.csv: per-kernel launches and "
                         "mean duration over launches longer than --min-us (launches that did work)")
     p.add_argument("--min-us", type=float, default=8.0)
+    p.add_argument("--kernel-probe", type=int, default=0, metavar="CHAINS",
+                   help="only build the workload's operator and its polynomial and run this "
+                        "many polynomial chains q(A~) v of the method's reduced operator (the "
+                        "solves' A_o^-1 D_oe and A_e - D_eo launches, chain epilogues), for "
+                        "kernel traces and hardware counters")
+    p.add_argument("--multi-probe", type=int, default=0, metavar="REPS",
+                   help="only build the workload's operator and run this many multi-RHS (MFMA) "
+                        "applies of --multi-rhs right-hand sides in --inner precision, for "
+                        "kernel traces and hardware counters")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                    help="only run a plain elementwise copy of this many MiB (read + write), "
                         "the reference for scaling HBM byte counters")
@@ -183,6 +212,12 @@ def main():
     log(f"operator built in {time.time() - t0:.1f}s")
     # the library launches on torch's current stream (the HIP null stream here)
     stream = torch.cuda.current_stream()
+    if a.kernel_probe:
+        kernel_probe(op, w, a)
+        return
+    if a.multi_probe:
+        multi_probe(op, w, a)
+        return
     # HIP events on one in a.profile_every launches of the apply's block kernel
     op.profile_apply(a.profile_every)
 
@@ -268,21 +303,47 @@ def main():
             del X, Y
 
     # ------------------------------------------------ method solve (timed)
-    opts = Opts(m=a.m + a.k, k=a.k, d=a.d, u=10, prec=a.inner, outer=1, m_outer=10,
-                max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000, schur=a.schur,
-                ortho=a.ortho)
+    small = w.V <= 4096
+    full_steps = a.full_steps if a.full_steps >= 0 else (4 if small else 0)
+    ss_steps = a.ss_steps if a.ss_steps >= 0 else (4 if small else 0)
+    bj_steps = a.bj_steps if a.bj_steps >= 0 else (4 if small else 0)
 
-    def one_solve(r, o):
+    def method_opts(**kw):
+        base = dict(m=a.m + a.k, k=a.k, d=a.d, u=a.u, prec=a.inner, outer=1, m_outer=10,
+                    max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000,
+                    schur=a.schur, ortho=a.ortho, block_jacobi=a.bj)
+        base.update(kw)
+        return Opts(**base)
+
+    opts = method_opts()
+
+    def one_solve(r, o, tol=None):
         b = synth.rhs(w.dims, w.n_tv, r, device="cuda")
-        x, st, rc = op.solve(b, a.tol, o)
+        x, st, rc = op.solve(b, a.tol if tol is None else tol, o)
         return x, st[0], rc
+
+    def timed_solves(o, first, count, label):
+        """count solves of fresh right-hand sides first.. after setup, timed."""
+        rr = [synth.rhs(w.dims, w.n_tv, r, device="cuda") for r in range(first, first + count)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        out = []
+        for i, b in enumerate(rr):
+            x, st, rc = op.solve(b, a.tol, o)
+            out.append(st[0])
+            log(f"{label} solve {i}: status {st[0]['status']} relres "
+                f"{st[0]['rel_res_true']:.2e} matvecs {st[0]['matvecs']} "
+                f"{st[0]['t_solve_ms']:.0f} ms")
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t1
 
     setup_ms = 0.0
     for r in range(a.warmup):
         x, st, rc = one_solve(r, opts)
         setup_ms += st["t_setup_ms"]
         log(f"warmup solve {r}: rc {rc} relres {st['rel_res_true']:.2e} iters {st['iters']} "
-            f"matvecs {st['matvecs']} setup {st['t_setup_ms']:.0f} ms")
+            f"matvecs {st['matvecs']} setup {st['t_setup_ms']:.0f} ms, "
+            f"{st['t_solve_ms']:.0f} ms")
     rhs = [synth.rhs(w.dims, w.n_tv, r, device="cuda") for r in range(a.warmup, a.warmup + a.steps)]
     torch.cuda.synchronize()
     pre = prof_totals()
@@ -291,9 +352,11 @@ def main():
                 for p in ("f64", "f32", "f16s")}
     t0 = time.perf_counter()
     stats = []
-    for b in rhs:
+    for i, b in enumerate(rhs):
         x, st, rc = op.solve(b, a.tol, opts)
         stats.append(st[0])
+        log(f"timed solve {i}: status {st[0]['status']} relres {st[0]['rel_res_true']:.2e} "
+            f"matvecs {st[0]['matvecs']} {st[0]['t_solve_ms']:.0f} ms")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     x_last = x
@@ -306,66 +369,65 @@ def main():
                for p in post_oe}
     passes = {p: op.profile_apply_passes(p, kern) - pre_pass[p][0] for p in pre_pass}
     passes_oe = {p: op.profile_apply_passes(p, 1) - pre_pass[p][1] for p in pre_pass}
-    for i, st in enumerate(stats):
-        log(f"timed solve {i}: status {st['status']} relres {st['rel_res_true']:.2e} "
-            f"iters {st['iters']} matvecs {st['matvecs']} outer {st['outer_iters']} "
-            f"{st['t_solve_ms']:.0f} ms")
     ok = all(s["status"] == 0 and s["rel_res_true"] <= a.tol for s in stats)
     value = a.steps / dt if ok else 0.0
+    log(f"method: {value:.3f} solves/s ({1e3 * dt / a.steps:.0f} ms per solve)")
+
+    def comparison(o, steps, label):
+        for r in range(a.warmup):             # its own setup: polynomial, recycle space
+            one_solve(r, o)
+        st, sdt = timed_solves(o, a.warmup, steps, label)
+        res = {"solves_per_s": steps / sdt, "steps": steps,
+               "matvecs_per_solve": [s["matvecs"] for s in st],
+               "iters_per_solve": [s["iters"] for s in st],
+               "converged": all(s["status"] == 0 for s in st)}
+        log(f"{label}: {steps / sdt:.3f} solves/s")
+        return res
+
+    # ------------------------------------------------ same method without / with block Jacobi
+    bj_cmp = None
+    if bj_steps > 0 and a.schur:
+        bj_cmp = comparison(method_opts(block_jacobi=1 - a.bj), bj_steps,
+                            f"same method, block_jacobi={1 - a.bj}")
+        bj_cmp["block_jacobi"] = 1 - a.bj
 
     # ------------------------------------------------ same method, full lattice
     full_cmp = None
-    if a.schur and a.full_steps > 0:
-        fo = Opts(m=a.m + a.k, k=a.k, d=a.d, u=10, prec=a.inner, outer=1, m_outer=10,
-                  max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000, schur=0)
-        for r in range(a.warmup):              # setup: polynomial and recycle space
-            one_solve(r, fo)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        fst = [one_solve(r, fo)[1] for r in range(a.warmup, a.warmup + a.full_steps)]
-        torch.cuda.synchronize()
-        fdt = time.perf_counter() - t1
-        full_cmp = {"solves_per_s": a.full_steps / fdt, "steps": a.full_steps,
-                    "matvecs_per_solve": [s["matvecs"] for s in fst],
-                    "converged": all(s["status"] == 0 for s in fst)}
-        log(f"same method on the full lattice: {a.full_steps / fdt:.2f} solves/s")
+    if a.schur and full_steps > 0:
+        full_cmp = comparison(method_opts(schur=0, ortho=0, block_jacobi=0), full_steps,
+                              "same method on the full lattice (no block Jacobi)")
 
-    # ------------------------------------------------ same method, single-sync Arnoldi
+    # ------------------------------------------------ same method, other Arnoldi
     ss_cmp = None
-    if a.ss_steps > 0:
-        so = Opts(m=a.m + a.k, k=a.k, d=a.d, u=10, prec=a.inner, outer=1, m_outer=10,
-                  max_outer=50, inner_tol=a.inner_tol, seed=1, max_cycles=100000,
-                  schur=a.schur, ortho=1 - a.ortho)
-        for r in range(a.warmup):
-            one_solve(r, so)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        sst = [one_solve(r, so)[1] for r in range(a.warmup, a.warmup + a.ss_steps)]
-        torch.cuda.synchronize()
-        sdt = time.perf_counter() - t1
-        ss_cmp = {"ortho": 1 - a.ortho, "solves_per_s": a.ss_steps / sdt, "steps": a.ss_steps,
-                  "matvecs_per_solve": [s["matvecs"] for s in sst],
-                  "iters_per_solve": [s["iters"] for s in sst],
-                  "converged": all(s["status"] == 0 for s in sst)}
-        log(f"same method with ortho={1 - a.ortho}: {a.ss_steps / sdt:.2f} solves/s")
+    if ss_steps > 0:
+        ss_cmp = comparison(method_opts(ortho=1 - a.ortho), ss_steps,
+                            f"same method, ortho={1 - a.ortho}")
+        ss_cmp["ortho"] = 1 - a.ortho
 
     # ------------------------------------------------ FP64 comparisons (one RHS each)
-    # GMRES(30) plain, with the polynomial preconditioner (d = 4, 8, 16), and
-    # with polynomial + deflation; each capped near 12000 matvecs since the
-    # plain and polynomial-only variants can stagnate on this operator.
+    # Plain GMRES(30) (and on small lattices with the polynomial, d = 4, 8,
+    # 16, and polynomial + deflation), each capped by wall time: the plain and
+    # polynomial-only variants stagnate on these operators.
     comp = {}
     if a.plain_steps > 0:
-        cases = [("gmres30", Opts(m=30, prec="f64", max_cycles=a.plain_max_cycles))]
-        for d in (4, 8, 16):
-            cases.append((f"gmres30_poly_d{d}",
-                          Opts(m=30, d=d, prec="f64", seed=1,
-                               max_cycles=max(1, 12000 // (30 * d)))))
-        cases.append(("gmres_poly_d16_defl_k32",
-                      Opts(m=62, k=32, d=16, prec="f64", seed=1, max_cycles=400)))
+        cases = [("gmres30", Opts(m=30, prec="f64"))]
+        if small:
+            for d in (4, 8, 16):
+                cases.append((f"gmres30_poly_d{d}", Opts(m=30, d=d, prec="f64", seed=1)))
+            cases.append(("gmres_poly_d16_defl_k32", Opts(m=62, k=32, d=16, prec="f64", seed=1)))
         r = a.warmup
         for name, o in cases:
             if o.k > 0:
+                o.max_cycles = 400
                 one_solve(r + 1, o)           # setup solve: builds the recycle space
+            # time two cycles, then cap the cycle count by the wall-time budget
+            o.max_cycles = 2
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            one_solve(r, o)
+            torch.cuda.synchronize()
+            per_cycle = (time.perf_counter() - t1) / 2
+            o.max_cycles = max(2, int(a.plain_seconds / max(per_cycle, 1e-6)))
             torch.cuda.synchronize()
             t1 = time.perf_counter()
             x, st, rc = one_solve(r, o)
@@ -373,19 +435,21 @@ def main():
             pdt = time.perf_counter() - t1
             conv = st["status"] == 0
             comp[name] = {"solves_per_s": (1.0 / pdt) if conv else 0.0, "converged": conv,
-                          "iters": st["iters"], "matvecs": st["matvecs"],
-                          "rel_res_true": st["rel_res_true"], "ms": 1e3 * pdt}
+                          "cycles_cap": o.max_cycles, "iters": st["iters"],
+                          "matvecs": st["matvecs"], "rel_res_true": st["rel_res_true"],
+                          "ms": 1e3 * pdt}
             log(f"fp64 {name}: status {st['status']} relres {st['rel_res_true']:.2e} "
                 f"iters {st['iters']} matvecs {st['matvecs']} {1e3 * pdt:.0f} ms")
     plain = comp.get("gmres30", {"solves_per_s": None})
 
-    # forward error of the last timed solve against an FP64 solve to 1e-12
-    # (polynomial + deflation, FP64 throughout), outside the timed region
-    ref_opts = Opts(m=62, k=32, d=16, prec="f64", seed=1, max_cycles=2000)
-    xr, sr, _ = op.solve(rhs[-1], 1e-12, ref_opts)
+    # forward error of the last timed solve against a reference: the same
+    # method carried to a.ref_tol (its FP64 outer loop makes the reference an
+    # FP64-accurate solution), outside the timed region
+    xr, sr, _ = op.solve(rhs[-1], a.ref_tol, opts)
     err_vs_fp64 = float(torch.linalg.vector_norm(x_last - xr) / torch.linalg.vector_norm(xr))
-    log(f"forward error of the last solve vs FP64 (rel.res {sr[0]['rel_res_true']:.1e}): "
+    log(f"forward error of the last solve vs the reference (rel.res {sr[0]['rel_res_true']:.1e}): "
         f"{err_vs_fp64:.2e}")
+    del xr
 
     whole = prof_totals()     # the whole run so far, for comparison with a kernel tracer
     op.profile_apply(0)
@@ -393,7 +457,43 @@ def main():
     # ------------------------------------------------ CPU oracle baseline
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(w, a, stats, x_check=(x_last, rhs[-1]))
+        r_last = (rhs[-1] - op.apply(x_last)).cpu().numpy()
+        cpu = cpu_baseline(w, a, stats, x_check=(x_last.cpu().numpy(), rhs[-1].cpu().numpy(),
+                                                 r_last))
+
+    # ------------------------------------------------ the 4^4 workload: eager vs graph replay
+    c1res = None
+    if a.c1_steps > 0 and w.name != "c1":
+        c1res = c1_graphs(a)
+
+    # ------------------------------------------------ the same method on the 8^4 workload
+    c2res = None
+    if a.c2_steps > 0 and w.name != "c2":
+        op.close()
+        del op
+        torch.cuda.empty_cache()
+        w2 = synth.WORKLOADS["c2"]
+        A2, B2 = synth.operator(w2, device="cuda")
+        op2 = CoarseOp(A2, B2, w2.dims, mu=w2.mu, store=("f64", "f32", "f16s"))
+        del A2, B2
+        for r in range(a.warmup):
+            op2.solve(synth.rhs(w2.dims, w2.n_tv, r, device="cuda"), a.tol, opts)
+        rr = [synth.rhs(w2.dims, w2.n_tv, r, device="cuda")
+              for r in range(a.warmup, a.warmup + a.c2_steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st2 = [op2.solve(b, a.tol, opts)[1][0] for b in rr]
+        torch.cuda.synchronize()
+        c2dt = time.perf_counter() - t1
+        conv2 = all(s["status"] == 0 for s in st2)
+        c2res = {"workload": f"c2: {'x'.join(map(str, w2.dims))} lattice, N_tv={w2.n_tv} "
+                             f"({w2.N} unknowns), mu={w2.mu}, m0={w2.m0():.6f}",
+                 "solves_per_s": (a.c2_steps / c2dt) if conv2 else 0.0, "steps": a.c2_steps,
+                 "ms_per_step": 1e3 * c2dt / a.c2_steps,
+                 "matvecs_per_solve": [s["matvecs"] for s in st2],
+                 "rel_res_true_max": max(s["rel_res_true"] for s in st2), "converged": conv2}
+        log(f"same method on c2: {a.c2_steps / c2dt:.2f} solves/s")
+        op2.close()
 
     inner = a.inner
     launches, tot_ms = prof[inner]
@@ -407,8 +507,13 @@ def main():
         s1b = stage1_bytes(V, n, inner)
     achieved = s1b / (avg_us * 1e-6) / 1e9 if launches else None
     traffic, traffic_detail = measured_traffic(w.name, inner, kern)
-    kname = (f"k_reduced_eo ({inner} blocks; A_e x_e - D_eo t_o with the chain epilogue)"
-             if a.schur else f"k_apply_blocks ({inner} blocks)")
+    if a.schur and a.bj:
+        kname = (f"k_reduced_eo ({inner} blocks; x_e - A_e^-1 D_eo t_o with the chain "
+                 f"epilogue)")
+    elif a.schur:
+        kname = f"k_reduced_eo ({inner} blocks; A_e x_e - D_eo t_o with the chain epilogue)"
+    else:
+        kname = f"k_apply_blocks ({inner} blocks)"
     oe = None
     if a.schur:
         l1, m1 = prof_oe[inner]
@@ -433,9 +538,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: {'x'.join(map(str, w.dims))} lattice, N_tv={w.n_tv} "
                                f"({w.N} unknowns), mu={w.mu}, m0={w.m0():.6f}",
-                   "solver": f"{'odd-even reduced system; ' if a.schur else ''}FGMRES(10) fp64 "
-                             f"outer; inner {inner} GCRO-DR(m={a.m + a.k},k={a.k}) + poly "
-                             f"d={a.d}, inner_tol={a.inner_tol}"
+                   "solver": f"{'odd-even reduced system; ' if a.schur else ''}"
+                             f"{'left block Jacobi B = D_ee; ' if a.bj and a.schur else ''}"
+                             f"FGMRES(10) fp64 outer; inner {inner} GCRO-DR(m={a.m + a.k},"
+                             f"k={a.k}, u={a.u}) + poly d={a.d}, inner_tol={a.inner_tol}"
                              f"{', single-sync Arnoldi' if a.ortho else ''}",
                    "tol": a.tol, "parallelism": "single GPU"},
         "setup_ms": setup_ms,
@@ -446,6 +552,9 @@ def main():
         "plain_fp64_gmres30": plain,
         "same_method_full_lattice": full_cmp,
         "same_method_other_ortho": ss_cmp,
+        "same_method_other_block_jacobi": bj_cmp,
+        "c2_same_method": c2res,
+        "c1_graph_replay": c1res,
         "fp64_comparison": comp,
         "apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]} for p, r in rates.items()},
         "reduced_apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]}
@@ -490,6 +599,95 @@ def summarize_trace(path, min_us):
               f"{(statistics.mean(w) if w else 0):8.2f} {(statistics.median(w) if w else 0):8.2f}")
 
 
+def c1_graphs(a):
+    """The 4^4, N_tv = 8 workload (4,096 unknowns, launch-bound): solves/s to
+    1e-10 with eager launches and with every Arnoldi cycle replayed as one
+    captured HIP graph, for plain FP64 GMRES(30) and for the method (reduced
+    system, block Jacobi, polynomial d = 4, GCRO-DR(38, 8), FP64)."""
+    import torch
+
+    import synth
+    from paper_2205_09104_amd import CoarseOp, Opts
+    w = synth.WORKLOADS["c1"]
+    A, B = synth.operator(w, device="cuda")
+    out = {"workload": f"c1: {'x'.join(map(str, w.dims))} lattice, N_tv={w.n_tv} "
+                       f"({w.N} unknowns), mu={w.mu}, m0={w.m0():.6f}", "tol": 1e-10}
+    cases = {"gmres30_fp64": dict(m=30, prec="f64"),
+             "method_fp64": dict(m=38, k=8, d=4, u=10, prec="f64", seed=1, schur=1,
+                                 block_jacobi=1, ortho=1)}
+    for name, kw in cases.items():
+        res = {}
+        for graphs in (0, 1):
+            op = CoarseOp(A, B, w.dims, mu=w.mu)
+            o = Opts(**kw, graphs=graphs)
+            for r in range(3):
+                op.solve(synth.rhs(w.dims, w.n_tv, r, device="cuda"), 1e-10, o)
+            rr = [synth.rhs(w.dims, w.n_tv, r, device="cuda") for r in range(3, 3 + a.c1_steps)]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = [op.solve(b, 1e-10, o)[1][0] for b in rr]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            res["graphs" if graphs else "eager"] = {
+                "solves_per_s": a.c1_steps / dt if all(s["status"] == 0 for s in st) else 0.0,
+                "ms_per_solve": 1e3 * dt / a.c1_steps,
+                "iters_per_solve": float(sum(s["iters"] for s in st)) / len(st),
+                "graph_stats": list(op.graph_stats())}
+            op.close()
+        res["speedup"] = (res["graphs"]["solves_per_s"] / res["eager"]["solves_per_s"]
+                          if res["eager"]["solves_per_s"] else None)
+        log(f"c1 {name}: eager {res['eager']['solves_per_s']:.1f}, graphs "
+            f"{res['graphs']['solves_per_s']:.1f} solves/s")
+        out[name] = res
+    return out
+
+
+def multi_probe(op, w, a):
+    """a.multi_probe multi-RHS applies of a.multi_rhs right-hand sides (blocks
+    and vectors of --inner precision; FP64 with --inner f64)."""
+    import torch
+
+    import synth
+    R = a.multi_rhs
+    X = torch.stack([synth.rhs(w.dims, w.n_tv, 500 + r, device="cuda") for r in range(R)])
+    if a.inner != "f64":
+        X = X.to(torch.complex64)
+    Y = torch.empty_like(X)
+    op.apply_multi(X, prec=a.inner, out=Y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.multi_probe):
+        op.apply_multi(X, prec=a.inner, out=Y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / a.multi_probe
+    tf = 72.0 * w.V * w.n * w.n * R / dt / 1e12
+    print(json.dumps({"multi_probe": w.name, "n_rhs": R, "prec": a.inner,
+                      "reps": a.multi_probe, "ms": 1e3 * dt, "TFLOP/s": tf}), flush=True)
+
+
+def kernel_probe(op, w, a):
+    """a.kernel_probe polynomial chains of the method's operator (reduced,
+    block Jacobi per --bj, blocks of --inner precision, degree --d): each
+    chain is d - 1 applies, i.e. d - 1 launches of each reduced kernel with the
+    first / later chain-step epilogues."""
+    import torch
+
+    import synth
+    from paper_2205_09104_amd import Opts
+    o = Opts(d=a.d, prec=a.inner, seed=1, schur=a.schur, block_jacobi=a.bj)
+    th = op.poly_setup(o)
+    rows = w.V // 2 if a.schur else w.V
+    x = synth.rhs(w.dims, w.n_tv, 0, device="cuda")[:rows].to(torch.complex64).contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.kernel_probe):
+        op.poly_apply(x, o)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    print(json.dumps({"kernel_probe": w.name, "chains": a.kernel_probe, "d": len(th),
+                      "applies": a.kernel_probe * (len(th) - 1), "ms": 1e3 * dt}), flush=True)
+
+
 def copy_probe(mib):
     """y = 1.0 * x over mib MiB of float32, 5 launches: each reads and writes
     exactly mib MiB of HBM-resident data."""
@@ -504,40 +702,61 @@ def copy_probe(mib):
 
 
 def cpu_baseline(w, a, stats, x_check=None):
-    """The FP64 oracle on the host.  Sample: oracle D_c applies for about
-    a.cpu_seconds; the oracle's solves/s is bounded above by one over (time per
-    apply x matvecs the GPU method needed per solve), its orthogonalisation and
-    setup not counted.  Also checks the last GPU solution's FP64 residual with
-    the oracle apply."""
+    """The FP64 oracle on the host, timed on a bounded sample: the oracle's
+    single-site stencil (self block and 8 hop blocks times the site's and its
+    neighbours' vectors, dop.apply_site) over sampled sites for about
+    a.cpu_seconds.  One apply of the reduced operator costs at least V such
+    site stencils (V/2 even rows of 9 block products, V/2 odd rows of 8 plus
+    the inverse), so the oracle's solves/s is bounded above by
+    1 / (V x time per site x matvecs per solve of the GPU method): an
+    extrapolation that leaves out orthogonalisation, inverses and setup.
+    Also re-derives the last GPU solution's FP64 residual at sampled sites
+    with the oracle's stencil."""
     import numpy as np
 
     import synth
     from oracle import operator as dop
-    A, B = synth.operator(w)
-    oop = dop.build(w.dims, A.numpy(), B.numpy(), w.mu)
-    del A, B
-    v = synth.rhs(w.dims, w.n_tv, 0).numpy()
-    dop.apply(oop, v)
+    from oracle.lattice import neighbours
+    fwd, bwd = neighbours(w.dims)
+    m0 = w.m0()
+    rng = np.random.default_rng(7)
+    sites = rng.choice(w.V, size=min(w.V, 64), replace=False)
+
+    def blocks(s):
+        A = synth.self_blocks(w.dims, w.n_tv, m0, w.seed, sites=[int(s)]).numpy()[0]
+        B = synth.hop_blocks(w.dims, w.n_tv, w.seed, sites=[int(s)]).numpy()[0]
+        Bb = synth.hop_blocks(w.dims, w.n_tv, w.seed, sites=bwd[:, s].tolist()).numpy()
+        return A, B, np.stack([Bb[m, m] for m in range(4)])
+
+    blk = [blocks(s) for s in sites]
+    n = w.n
+    psi = rng.standard_normal((9, n)) + 1j * rng.standard_normal((9, n))
     reps, t0 = 0, time.perf_counter()
     while time.perf_counter() - t0 < a.cpu_seconds:
-        dop.apply(oop, v)
+        A, B, Bb = blk[reps % len(blk)]
+        dop.apply_site(A, B, Bb, psi[0], psi[1:5], psi[5:9], w.mu)
         reps += 1
-    per_apply = (time.perf_counter() - t0) / reps
+    per_site = (time.perf_counter() - t0) / reps
     mv = float(np.mean([s["matvecs"] for s in stats]))
     try:
         from threadpoolctl import threadpool_info
         blas = [{k: i.get(k) for k in ("internal_api", "num_threads")} for i in threadpool_info()]
     except Exception:  # noqa: BLE001
         blas = None
-    out = {"value": 1.0 / (per_apply * mv), "unit": "solves/s", "cores": 1, "kind": "oracle",
-           "host_cpus": os.cpu_count(), "blas_pools": blas,
-           "sample": f"{reps} FP64 oracle D_c applies ({per_apply:.3f} s each, numpy einsum, one "
-                     f"thread) x {mv:.0f} matvecs per solve of the GPU method; an upper bound "
-                     f"(orthogonalisation and setup not counted)"}
+    out = {"value": 1.0 / (w.V * per_site * mv), "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "extrapolated": True, "host_cpus": os.cpu_count(), "blas_pools": blas,
+           "sample": f"{reps} oracle site stencils (numpy, one thread; {1e6 * per_site:.1f} us "
+                     f"each) over {len(sites)} sampled sites, x {w.V} sites per apply of the "
+                     f"reduced operator x {mv:.0f} matvecs per solve of the GPU method: an "
+                     f"upper bound (orthogonalisation, inverses and setup not counted)"}
     if x_check is not None:
-        x, b = (t.cpu().numpy() for t in x_check)
-        r = b - dop.apply(oop, x)
-        out["oracle_relres_last_solve"] = float(np.linalg.norm(r) / np.linalg.norm(b))
+        x, b, r_gpu = x_check
+        worst = 0.0
+        for s, (A, B, Bb) in zip(sites[:16], blk[:16]):
+            Dx = dop.apply_site(A, B, Bb, x[s], x[fwd[:, s]], x[bwd[:, s]], w.mu)
+            worst = max(worst, float(np.abs((b[s] - Dx) - r_gpu[s]).max()))
+        out["residual_rows_checked"] = 16
+        out["residual_rows_max_abs_diff"] = worst / float(np.abs(b).max())
     return out
 
 

@@ -123,6 +123,12 @@ typedef struct {
                            [n_rhs][V][n]: each solve then reports
                            ||x - x_ref|| / ||x_ref|| (FP64) in err_vs_ref;
                            NULL = none                                          */
+  int32_t graphs;       /* 1: Arnoldi cycles that the host enqueues in one piece
+                           (lattices small enough that launch overhead, not
+                           HBM, bounds a step) are recorded once as HIP graphs
+                           and replayed, one graph launch per cycle; same
+                           kernels and results as 0 (eager launches).  Not used
+                           while dc_profile_apply is recording.                */
 } dc_solve_opts;
 
 typedef struct {
@@ -143,11 +149,14 @@ typedef struct {
   int32_t refresh_failed; /* recycle refreshes whose dense generalised eigen-
                            problem failed; the space is then kept as it is and
                            frozen (no further refreshes)                          */
+  int32_t stagnated;    /* 1 if the solve stopped because its FP64 residual had
+                           not fallen below 0.9 of its best over three outer
+                           refinement steps (solve_coarse_block)                  */
 } dc_solve_stats;
 
 /* Fill `o` with defaults: m=30, k=0, d=0, u=10, max_cycles=100000,
  * block_jacobi=0, prec=F64, outer=0, m_outer=10, max_outer=50,
- * inner_tol=1e-4, seed=0, v0=NULL, schur=0, ortho=0, x_ref=NULL. */
+ * inner_tol=1e-4, seed=0, v0=NULL, schur=0, ortho=0, x_ref=NULL, graphs=0. */
 int dc_default_opts(dc_solve_opts* o);
 
 /* Device memory a handle needs when the caller provides it (build_coarse_op_ws):
@@ -187,6 +196,10 @@ int build_coarse_op_ws(const dc_op_desc* desc, const void* self_blocks, const vo
 /* Peak bytes a handle built by build_coarse_op_ws has used of each range so
  * far.  DC_ERR_STATE for a handle that allocates its own memory. */
 int dc_workspace_used(dc_op_t op, size_t* persistent_peak, size_t* scratch_peak);
+
+/* Arnoldi-cycle graphs of a handle (opts.graphs = 1): how many were captured
+ * and how many graph launches replayed them.  Either pointer may be NULL. */
+int dc_graph_stats(dc_op_t op, int64_t* captured, int64_t* launched);
 
 /* Process-wide count of device allocations (hipMalloc) the library has made,
  * and the bytes they hold now (handles built on caller workspaces add

@@ -54,6 +54,7 @@ class Opts:
     schur: int = 0      # 1: odd-even reduced system (even extents only)
     ortho: int = 0      # 1: single-sync Arnoldi (one reduction per step)
     x_ref: torch.Tensor | None = field(default=None, repr=False)   # [R, V, n] complex128
+    graphs: int = 0     # 1: replay whole Arnoldi cycles as captured HIP graphs
 
     def to_c(self) -> _lib.SolveOpts:
         o = _lib.SolveOpts()
@@ -64,6 +65,7 @@ class Opts:
         o.inner_tol, o.seed = float(self.inner_tol), int(self.seed)
         o.schur = int(self.schur)
         o.ortho = int(self.ortho)
+        o.graphs = int(self.graphs)
         if self.v0 is not None:
             assert self.v0.dtype == torch.complex128 and self.v0.is_cuda
             o.v0 = self.v0.data_ptr()
@@ -142,6 +144,12 @@ class CoarseOp:
             check(lib.build_coarse_op_ws(C.byref(desc), _ptr(sb), _ptr(hb), _ptr(pw),
                                          pw.numel(), _ptr(sw), sw.numel(), st, C.byref(h)))
         self._h = h
+
+    def graph_stats(self):
+        """(captured, launched) Arnoldi-cycle graphs of this handle."""
+        c, l = C.c_int64(), C.c_int64()
+        check(load().dc_graph_stats(self._h, C.byref(c), C.byref(l)))
+        return c.value, l.value
 
     def workspace_used(self):
         """Peak (persistent, scratch) bytes used of the caller's workspaces."""

@@ -35,7 +35,8 @@ class SolveOpts(C.Structure):
                 ("max_cycles", C.c_int32), ("block_jacobi", C.c_int32), ("prec", C.c_int32),
                 ("outer", C.c_int32), ("m_outer", C.c_int32), ("max_outer", C.c_int32),
                 ("inner_tol", C.c_double), ("seed", C.c_uint64), ("v0", C.c_void_p),
-                ("schur", C.c_int32), ("ortho", C.c_int32), ("x_ref", C.c_void_p)]
+                ("schur", C.c_int32), ("ortho", C.c_int32), ("x_ref", C.c_void_p),
+                ("graphs", C.c_int32)]
 
 
 class SolveStats(C.Structure):
@@ -44,7 +45,7 @@ class SolveStats(C.Structure):
                 ("rel_res_true", C.c_double), ("rel_res_est", C.c_double),
                 ("t_setup_ms", C.c_double), ("t_solve_ms", C.c_double),
                 ("err_vs_ref", C.c_double), ("breakdowns", C.c_int32),
-                ("refresh_failed", C.c_int32)]
+                ("refresh_failed", C.c_int32), ("stagnated", C.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -60,6 +61,7 @@ SIGNATURES = {
                                      C.POINTER(C.c_void_p)]),
     "dc_workspace_used": (C.c_int, [C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)]),
     "dc_device_allocations": (C.c_int, [C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
+    "dc_graph_stats": (C.c_int, [C.c_void_p, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "build_coarse_op": (C.c_int, [C.POINTER(OpDesc), C.c_void_p, C.c_void_p, C.c_void_p,
                                   C.POINTER(C.c_void_p)]),
     "update_coarse_op": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),

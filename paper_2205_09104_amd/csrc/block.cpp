@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <limits>
 #include <memory>
 #include <vector>
 
@@ -442,8 +443,10 @@ struct BlockGmres {
   // span of the earlier picks).  On return V holds that basis V_0 (the count is
   // returned), S0 = V_0^H R (nb x nr) and drop[a] = ||R_a - V_0 S0_a||; R is
   // kept in U.  0 if not even the first pick orthonormalises.
-  int select_block(int nr, Mat& S0, std::vector<double>& drop) {
-    const Mat G = tn(V, nr, V, nr);
+  // Greedy pivoted Cholesky of the scaled Gram matrix G of nr columns: each
+  // pick has the largest squared part outside the span of the earlier picks
+  // (the lowest index among equal ones), kept while that part exceeds sel_piv.
+  std::vector<int> pivot_picks(int nr, const Mat& G) const {
     std::vector<double> d(nr);
     for (int i = 0; i < nr; ++i) d[i] = std::sqrt(std::max(G(i, i).real(), 0.0));
     // pivoted Cholesky of Gs = D^{-1} G D^{-1}: Schur-complement diagonal
@@ -471,6 +474,11 @@ struct BlockGmres {
       L(best, k) = lkk;
       pick.push_back(best);
     }
+    return pick;
+  }
+
+  int select_block(int nr, const Mat& G, const std::vector<int>& pick, Mat& S0,
+                   std::vector<double>& drop) {
     const int nb = int(pick.size());
     if (nb == 0) return 0;
     DC_HIP(hipMemcpyAsync(U, V, size_t(nr) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
@@ -481,12 +489,15 @@ struct BlockGmres {
     DC_HIP(hipMemcpyAsync(V, T1, size_t(nb) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
     if (!cholqr2(V, V, nb, Rsel)) return 0;
     S0 = tn(V, nb, U, nr);
+    // drop[a] = ||R_a - V_0 S0_a||, formed explicitly (T1 = R - V_0 S0), not
+    // by subtracting squared norms
+    DC_HIP(hipMemcpyAsync(T1, U, size_t(nr) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
+    write_mat(Rd, S0);
+    gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, nb, -1.0, V, int(N), Rd, nb,
+         1.0, T1, int(N));
+    const std::vector<double> e2 = colnorms(T1, nr);
     drop.assign(nr, 0.0);
-    for (int a = 0; a < nr; ++a) {
-      double s = 0.0;
-      for (int i = 0; i < nb; ++i) s += std::norm(S0(i, a));
-      drop[a] = std::sqrt(std::max(G(a, a).real() - s, 0.0));
-    }
+    for (int a = 0; a < nr; ++a) drop[a] = std::sqrt(std::max(e2[a], 0.0));
     return nb;
   }
 
@@ -503,22 +514,33 @@ struct BlockGmres {
   // minimiser over the block space.  The cycle ends when every column's
   // residual is at or below its target, after m steps, or when a new block is
   // rank deficient.
+  // Dependent columns (nr < nc, the residual columns kept in U): every block
+  // V_{j+1} also takes the coefficients V_{j+1}^H R of the residual columns
+  // into the least-squares right-hand side (their parts outside V_0 are not
+  // orthogonal to the later blocks), and the cycle runs up to
+  // m nc / nr block steps so that its space keeps the dimension m nc that
+  // nc independent columns would give (bounded by the basis storage).
   Cycle cycle(int nr, int nc, const Mat& S0, const std::vector<double>& target,
               const std::vector<double>& drop) {
     Cycle c;
-    c.Bk = Mat(std::max(kc, 1), m * nr);
-    Mat Rf((m + 1) * nr, m * nr);
-    Mat G((m + 1) * nr, nc);
+    const bool dep = nr < nc;
+    const int msteps = dep ? std::max(m, std::min(m * nc / nr, (m + 1) * nc / nr - 1)) : m;
+    c.Bk = Mat(std::max(kc, 1), msteps * nr);
+    Mat Rf((msteps + 1) * nr, msteps * nr);
+    Mat G((msteps + 1) * nr, nc);
     for (int j = 0; j < nc; ++j)
       for (int i = 0; i < nr; ++i) G(i, j) = S0(i, j);
+    // squared parts of the residual columns outside the blocks so far
+    std::vector<double> outside(nc);
+    for (int a = 0; a < nc; ++a) outside[a] = drop[size_t(a)] * drop[size_t(a)];
     std::vector<Mat> qhs;
     c.est.assign(nc, 0.0);
     for (int a = 0; a < nc; ++a) {
-      double s = drop[size_t(a)] * drop[size_t(a)];
+      double s = outside[a];
       for (int i = 0; i < nr; ++i) s += std::norm(S0(i, a));
       c.est[a] = std::sqrt(s);
     }
-    for (int j = 0; j < m; ++j) {
+    for (int j = 0; j < msteps; ++j) {
       Z* Vj = V + size_t(j) * nr * N;
       const Z* src = Vj;
       if (has_poly()) {
@@ -546,6 +568,14 @@ struct BlockGmres {
       }
       Mat Hsub;
       const bool full = cholqr2(W, V + size_t(j + 1) * nr * N, nr, Hsub);
+      if (dep && full) {   // coefficients of the residual columns on the new block
+        const Mat e = tn(V + size_t(j + 1) * nr * N, nr, U, nc);
+        for (int a = 0; a < nc; ++a)
+          for (int t = 0; t < nr; ++t) {
+            G((j + 1) * nr + t, a) = e(t, a);
+            outside[a] -= std::norm(e(t, a));
+          }
+      }
       // the new block column of Hbar, reduced by the earlier reflections
       Mat col((j + 2) * nr, nr);
       for (int b = 0; b < nr; ++b) {
@@ -580,7 +610,7 @@ struct BlockGmres {
       c.steps = j + 1;
       bool done = true;
       for (int a = 0; a < nc; ++a) {
-        double s = drop[size_t(a)] * drop[size_t(a)];
+        double s = std::max(outside[a], 0.0);
         for (int t = 0; t < nr; ++t) s += std::norm(G((j + 1) * nr + t, a));
         c.est[a] = std::sqrt(s);
         if (c.est[a] > target[size_t(a)]) done = false;
@@ -660,8 +690,11 @@ struct BlockGmres {
       Mat S0;
       std::vector<double> drop(nr, 0.0);
       int nb = nr;
-      if (!cholqr2(V, V, nr, S0)) {
-        nb = select_block(nr, S0, drop);
+      const Mat G0 = tn(V, nr, V, nr);
+      const std::vector<int> picks = pivot_picks(nr, G0);
+      if (int(picks.size()) < nr || !cholqr2(V, V, nr, S0)) {
+        nb = select_block(nr, G0, picks.size() < size_t(nr) ? picks : pivot_picks(nr, G0), S0,
+                          drop);
         if (nb == 0) break;
       }
       std::vector<double> target(nr);
@@ -772,6 +805,10 @@ int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, co
     std::vector<int> act;
     for (int c = 0; c < R; ++c)
       if (bn[c] > 0.0) act.push_back(c);
+    // a column whose FP64 residual has not fallen below 0.9 of its best for
+    // three refinement steps in a row stops refining (stagnation)
+    std::vector<double> best(R, std::numeric_limits<double>::infinity());
+    std::vector<int> stall(R, 0);
     for (int outer = 0; !act.empty(); ++outer) {
       const int r = int(act.size());
       std::vector<const z64*> in(r);
@@ -790,7 +827,13 @@ int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, co
       for (int a = 0; a < r; ++a) {
         const int c = act[a];
         rel[c] = std::sqrt(std::max(rn[a], 0.0)) / bn[c];
-        if (rel[c] > tl[c] && outer < o.max_outer) keep.push_back(a);
+        if (rel[c] < 0.9 * best[c]) {
+          best[c] = rel[c];
+          stall[c] = 0;
+        } else if (++stall[c] >= 3) {
+          stt[c].stagnated = 1;
+        }
+        if (rel[c] > tl[c] && outer < o.max_outer && !stt[c].stagnated) keep.push_back(a);
       }
       if (keep.empty()) break;
       const int nr = int(keep.size());

@@ -63,6 +63,8 @@ dc::SolveOpts convert(const dc_solve_opts* o) {
   s.seed = o->seed;
   s.v0 = o->v0;
   s.x_ref = o->x_ref;
+  if (o->graphs != 0 && o->graphs != 1) throw dc::InvalidArg("graphs must be 0 or 1");
+  s.graphs = o->graphs;
   if (o->schur != 0 && o->schur != 1) throw dc::InvalidArg("schur must be 0 or 1");
   s.schur = o->schur;
   if (o->ortho != 0 && o->ortho != 1) throw dc::InvalidArg("ortho must be 0 or 1");
@@ -86,6 +88,7 @@ void copy_stats(const dc::SolveStats& a, dc_solve_stats* b) {
   b->err_vs_ref = a.err_vs_ref;
   b->breakdowns = a.breakdowns;
   b->refresh_failed = a.refresh_failed;
+  b->stagnated = a.stagnated;
 }
 
 }  // namespace
@@ -113,6 +116,7 @@ int dc_default_opts(dc_solve_opts* o) {
   o->schur = 0;
   o->ortho = 0;
   o->x_ref = nullptr;
+  o->graphs = 0;
   return DC_OK;
 }
 
@@ -167,6 +171,15 @@ int build_coarse_op_ws(const dc_op_desc* desc, const void* self_blocks, const vo
       throw;
     }
     *out = h;
+    return DC_OK;
+  });
+}
+
+int dc_graph_stats(dc_op_t op, int64_t* captured, int64_t* launched) {
+  return guarded([&] {
+    if (!op) throw dc::InvalidArg("null handle");
+    if (captured) *captured = op->op.graphs.captured;
+    if (launched) *launched = op->op.graphs.launched;
     return DC_OK;
   });
 }

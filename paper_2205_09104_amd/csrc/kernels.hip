@@ -679,6 +679,7 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_reduced_oe(
   if (w != 8) return;
   // loaded after the barrier: holding the tile across it would raise the
   // kernel's register count past what three 9-wave workgroups per CU allow
+  // (staging it in LDS before the barrier measured no faster)
   R.load(block_ptr<T, P>(inv, size_t(x)), lane);
   const int lr = lane >> 3, lc = lane & 7;
   cx<A> pc[T], pr[T], f[T], g[T];
@@ -1136,8 +1137,9 @@ __global__ void k_chain_multi(const cx<VR>* const* __restrict__ t, const cx<VR>*
 // Y_r = D X_r for R right-hand sides at once.  One workgroup (4 waves) per
 // site accumulates the 9 couplings of the site into an n x R output panel
 // held in MFMA accumulators: each coupling stages its block (as the vector
-// precision) and the source panel in LDS, and the complex product runs as the
-// real GEMM [[Re M, -Im M], [Im M, Re M]] [Re P; Im P] on 16x16x4 MFMA tiles.
+// precision) and the source panel in LDS, and the complex product runs as
+// three real GEMMs (Re M Re P, Im M Im P, (Re M + Im M)(Re P + Im P)) on
+// 16x16x4 MFMA tiles.
 // Backward hops Gamma5 B^H Gamma5 read the staged forward block transposed.
 // Every stored block is read once per site that uses it (9 block reads per
 // site; the MFMA work, 72 V n^2 R flops, dominates for R >= 16).
@@ -1271,13 +1273,14 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
   // zero both planes once: padding rows / columns are never written again
   for (int t = threadIdx.x; t < 2 * (NP + RB) * LD; t += blockDim.x) Mr[t] = VT(0);
   __syncthreads();   // the zero fill must land before any staged value
-  acc_t crr[TPW], cii[TPW], cri[TPW], cir[TPW];
+  // three real products per complex one: Re C = Mr Pr - Mi Pi,
+  // Im C = (Mr + Mi)(Pr + Pi) - Mr Pr - Mi Pi
+  acc_t crr[TPW], cii[TPW], css[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) {
     crr[t] = acc_t{0, 0, 0, 0};
     cii[t] = acc_t{0, 0, 0, 0};
-    cri[t] = acc_t{0, 0, 0, 0};
-    cir[t] = acc_t{0, 0, 0, 0};
+    css[t] = acc_t{0, 0, 0, 0};
   }
   uint4 mreg[MU], preg[PU];      // the next coupling's raw 16-byte units
   int cblk = 0, csrc = 0;
@@ -1370,8 +1373,9 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
     __syncthreads();
     // the next coupling's loads are in flight while this one multiplies
     if (c + 1 < 9) fetch(c + 1, cblk, csrc, csc);
-    // C += M P:  Re C += Mr Pr - Mi Pi,  Im C += Mr Pi + Mi Pr  (16x16x4 tiles),
-    // k outermost so the wave's tiles interleave their MFMA chains
+    // C += M P with the three products Mr Pr, Mi Pi, (Mr + Mi)(Pr + Pi)
+    // (16x16x4 tiles), k outermost so the wave's tiles interleave their MFMA
+    // chains
 #pragma unroll
     for (int k = 0; k < NP; k += 4) {
 #pragma unroll
@@ -1383,8 +1387,7 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
           const VT a_r = Mr[ao], a_i = Mi[ao], b_r = Pr[bo], b_i = Pi[bo];
           crr[it] = Mfma<VT>::mma(a_r, b_r, crr[it]);
           cii[it] = Mfma<VT>::mma(a_i, b_i, cii[it]);
-          cri[it] = Mfma<VT>::mma(a_r, b_i, cri[it]);
-          cir[it] = Mfma<VT>::mma(a_i, b_r, cir[it]);
+          css[it] = Mfma<VT>::mma(a_r + a_i, b_r + b_i, css[it]);
         }
       }
     }
@@ -1403,7 +1406,7 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
         // MFMA, row lane/16 + 4*q for the FP64 one
         const int row = rt * 16 + Mfma<VT>::row(lk, q);
         Pr[col * LD + row] = crr[it][q] - cii[it][q];
-        Pi[col * LD + row] = cri[it][q] + cir[it][q];
+        Pi[col * LD + row] = css[it][q] - crr[it][q] - cii[it][q];
       }
     }
   }
@@ -2119,6 +2122,7 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(ArnoldiDev a, int steps, 
   if (a.hest) a.hest[j] = est;
   *a.jdone = j + 1;
   if (breakdown) *a.brk_flag = 1;
+  if (a.target_dev) target = *a.target_dev;
   if (breakdown || est <= target || j + 1 >= steps) {
     *a.done = 1;
     if (a.hdone) *a.hdone = 1;

@@ -224,6 +224,8 @@ struct ArnoldiDev {
   int* brk_flag;    // 1 if the cycle ended by breakdown
   int* hdone = nullptr;  // optional host-mapped copy of the done flag (set to 1 with it)
   double* hest = nullptr;  // optional host-mapped per-step estimates: hest[j] after step j
+  const double* target_dev = nullptr;  // optional: the stopping target read from device memory
+                                       // (replaces the value argument; graph replays)
 };
 // c2 null: the single-sync process (one pass of coefficients c1, whose entry
 // kC + j + 1 is ||A v_j||^2; h_{j+1,j}^2 = ||A v_j||^2 - sum |c1|^2; nrm2 unused).

@@ -304,6 +304,20 @@ ApplyProfile::~ApplyProfile() {
   for (hipEvent_t e : owned) (void)hipEventDestroy(e);
 }
 
+hipGraphExec_t GraphCache::find(const std::vector<uintptr_t>& key) const {
+  for (const Entry& e : entries)
+    if (e.key == key) return e.exec;
+  return nullptr;
+}
+
+GraphCache::~GraphCache() {
+  for (Entry& e : entries) {
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+  }
+  if (cap) (void)hipStreamDestroy(cap);
+}
+
 void stream_wait(hipStream_t st) {
   for (;;) {
     const hipError_t e = hipStreamQuery(st);
@@ -1017,6 +1031,25 @@ struct Krylov {
     ad.hest = op.sig.est_dev;
     double last_est = beta;
     int nchunk = 0, enqueued = 0;
+    // the whole cycle in one piece: replay it as a captured graph when asked
+    if (o.graphs && chunk >= steps && min_steps == 0 && target >= 0.0 && !op.prof.on &&
+        !op.graphs.broken && graph_cycle(kC, steps, target)) {
+      enqueued = steps;
+    } else {
+      enqueue_steps(kC, steps, target, min_steps, chunk, beta, enqueued, nchunk, last_est);
+    }
+    ad.hdone = nullptr;
+    ad.hest = nullptr;
+    ad.target_dev = nullptr;
+    op.prof.tag = -1;
+    return finish_cycle(kC, enqueued, beta, dev_beta);
+  }
+
+  // Enqueue the steps of a cycle in chunks of about a millisecond of device
+  // work, paced by events (see cycle()).
+  void enqueue_steps(int kC, int steps, double target, int min_steps, int chunk, double beta,
+                     int& enqueued, int& nchunk, double& last_est) {
+    last_est = beta;
     for (int j = 0; j < steps; ++j) {
       op.prof.tag = j;
       if (zstore()) {            // keep z_j = q(A~) v_j for the update of x
@@ -1046,9 +1079,77 @@ struct Krylov {
         ++nchunk;
       }
     }
-    ad.hdone = nullptr;
-    ad.hest = nullptr;
-    op.prof.tag = -1;
+  }
+
+  // The steps of one cycle (no pacing) as a HIP graph: looked up by the
+  // arguments its kernels capture, else recorded on the capture stream.  The
+  // stopping target goes to device memory first (the finishing kernel reads
+  // it there).  Returns false, and stays eager from then on, if capture fails.
+  bool graph_cycle(int kC, int steps, double target) {
+    double* tdev = nrm + 1;   // free slot of the small area (nrm[0] and nrm[2..3] are used)
+    op.hs.write(tdev, &target, sizeof(double), st);
+    ad.target_dev = tdev;
+    const std::vector<uintptr_t> key = {
+        uintptr_t(&var), uintptr_t(var.poly_serial), uintptr_t(op.version), uintptr_t(ws.p),
+        uintptr_t(sm.p), uintptr_t(var.C.p), uintptr_t(kC), uintptr_t(steps),
+        uintptr_t(ortho_now), uintptr_t(zstore()), uintptr_t(p), uintptr_t(ad.hdone),
+        uintptr_t(ad.hest), uintptr_t(var.theta.size()), uintptr_t(bjinv), uintptr_t(ts),
+        uintptr_t(gb), uintptr_t(oinv), uintptr_t(op.blocks(p))};
+    hipGraphExec_t exec = op.graphs.find(key);
+    if (!exec) {
+      GraphCache& gc = op.graphs;
+      if (!gc.cap && hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        gc.cap = nullptr;
+        gc.broken = true;
+        ad.target_dev = nullptr;
+        return false;
+      }
+      if (hipStreamBeginCapture(gc.cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        gc.broken = true;
+        ad.target_dev = nullptr;
+        return false;
+      }
+      const hipStream_t saved = st;
+      const long mv_saved = matvecs;   // recording runs nothing
+      st = gc.cap;
+      bool ok = true;
+      try {
+        int enq = 0, nch = 0;
+        double le = 0.0;
+        enqueue_steps(kC, steps, target, 0, steps, 1.0, enq, nch, le);
+      } catch (const std::exception&) {
+        ok = false;
+      }
+      st = saved;
+      matvecs = mv_saved;
+      hipGraph_t graph = nullptr;
+      if (hipStreamEndCapture(gc.cap, &graph) != hipSuccess || !ok || !graph) {
+        (void)hipGetLastError();
+        if (graph) (void)hipGraphDestroy(graph);
+        gc.broken = true;
+        ad.target_dev = nullptr;
+        return false;
+      }
+      if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(graph);
+        gc.broken = true;
+        ad.target_dev = nullptr;
+        return false;
+      }
+      gc.entries.push_back({key, graph, exec});
+      ++gc.captured;
+    }
+    DC_HIP(hipGraphLaunch(exec, st));
+    ++op.graphs.launched;
+    // the applications the replayed steps make, as the eager enqueue counts them
+    matvecs += long(steps) * (has_poly() ? long(var.theta.size()) : 1L);
+    return true;
+  }
+
+  CycleOut finish_cycle(int kC, int enqueued, double beta, bool dev_beta) {
     CycleOut c;
     int flags[3];
     op.hs.read(flags, ad.done, 3 * sizeof(int), st);
@@ -1491,6 +1592,7 @@ void build_poly(Op& op, Variant& var, const SolveOpts& o, hipStream_t st) {
       throw InvalidArg("degenerate harmonic Ritz value");
   var.theta = leja_order(th);
   var.poly_version = op.version;
+  ++var.poly_serial;
   (void)sizeof(Z);
 }
 

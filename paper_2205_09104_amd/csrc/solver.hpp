@@ -70,6 +70,7 @@ struct SolveOpts {
   double inner_tol = 1e-4;
   int schur = 0;   // solve the odd-even reduced system (Sec. 2.2)
   int ortho = 0;   // 0: CGS applied twice; 1: single-sync process (Sec. 3.5)
+  int graphs = 0;  // 1: replay whole Arnoldi cycles as captured HIP graphs (latency-bound lattices)
   uint64_t seed = 0;
   const void* v0 = nullptr;     // device complex128 [V][n]
   const void* x_ref = nullptr;  // optional reference solutions, device complex128 [n_rhs][V][n]
@@ -81,6 +82,7 @@ struct SolveStats {
   double err_vs_ref = -1.0;     // ||x - x_ref|| / ||x_ref|| in FP64 (-1: no reference)
   int breakdowns = 0;           // cycles that ended on h_{j+1,j} = 0 (happy breakdown)
   int refresh_failed = 0;       // recycle refreshes whose dense problem failed (space frozen)
+  int stagnated = 0;            // stopped because the FP64 residual no longer fell
 };
 
 struct Op;
@@ -95,6 +97,7 @@ struct Variant {
   // polynomial
   std::vector<cd> theta;
   long poly_version = -1;
+  long poly_serial = 0;        // bumped by every polynomial build
   // recycle space (vectors of the variant's precision)
   DevBuf U, C;
   int kcur = 0;
@@ -177,6 +180,28 @@ struct HostStage {
 // wait; the solver's host thread has nothing else to do meanwhile).
 void stream_wait(hipStream_t st);
 
+// Arnoldi cycles captured as HIP graphs and replayed: a cycle that the host
+// enqueues in one piece (small lattices, where launch overhead dominates) is
+// recorded once on a private capture stream and launched as one graph on the
+// caller's stream afterwards.  Entries are keyed by everything a captured
+// kernel argument depends on (workspace and recycle-space addresses, the
+// polynomial's version, the step count, the deflation count, the
+// orthogonalisation mode, the host-mapped signal areas); the stopping target
+// is read from device memory.  `broken`: capture failed once, stay eager.
+struct GraphCache {
+  struct Entry {
+    std::vector<uintptr_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  hipStream_t cap = nullptr;
+  std::vector<Entry> entries;
+  bool broken = false;
+  long captured = 0, launched = 0;
+  hipGraphExec_t find(const std::vector<uintptr_t>& key) const;
+  ~GraphCache();
+};
+
 // Host-mapped stop flag of the pending Arnoldi cycle, its per-step residual
 // estimates, and two events that pace the host's enqueueing a bounded
 // distance ahead of the device.
@@ -237,6 +262,7 @@ struct Op {
   ApplyProfile prof;
   CycleSignal sig;
   HostStage hs;
+  GraphCache graphs;
 
   Reducer red() const { return Reducer{redpart.as<double>()}; }
   std::map<std::tuple<int, int, int, int, int>, std::unique_ptr<Variant>> variants;

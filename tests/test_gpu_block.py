@@ -157,3 +157,56 @@ def test_block_solver_rejects_bad_options(c1):
             gop.solve_block(B, 1e-8, o)
     with pytest.raises(DcError):
         gop.solve_block(B, [1e-8, 0.0], Opts(m=10))
+
+
+def test_dependent_columns_cycle_matches_oracle():
+    """Residual columns that are numerically dependent (three columns and
+    three combinations of them, each with a part of relative size 5e-7
+    outside their span): the library generates the space from the picked
+    columns, runs m x 6 / 3 block steps, and gives every column the exact
+    least-squares minimiser over that space, the parts of its residual outside
+    the first block included -- the same as the oracle's block GMRES."""
+    from paper_2205_09104_amd import Opts
+    log("block gmres dependent columns, one cycle")
+    gop, oop = make_pair((4, 2, 2, 4), 6, 3.0, mu=0.1)
+    N = oop.V * oop.n
+    m = 3
+    base = _rhs(oop.dims, 6, 3, 60).numpy().reshape(3, N)
+    rng = np.random.default_rng(11)
+    mix = rng.standard_normal((3, 3)) + 1j * rng.standard_normal((3, 3))
+    dep = mix @ base
+    nz = rng.standard_normal((3, N)) + 1j * rng.standard_normal((3, N))
+    # parts of relative size 5e-7 outside the span: dependent at the FP64
+    # selection threshold (squared part 2.5e-13 < 1e-12), large enough that
+    # leaving them out of the least squares would show at 1e-9
+    dep = dep + 5e-7 * (np.linalg.norm(dep, axis=1) / np.linalg.norm(nz, axis=1))[:, None] * nz
+    Bn = np.concatenate([base, dep], axis=0)
+    B = torch.from_numpy(Bn.reshape(6, oop.V, oop.n)).cuda()
+    X, st, rc = gop.solve_block(B, 1e-30, Opts(m=m, max_cycles=1))
+    f = lambda v: dop.apply(oop, v.reshape(oop.V, oop.n)).reshape(-1)
+    Xr, info = block_gmres(f, Bn.T, [1e-30] * 6, m, 1)
+    assert info["generators"] == [3] and info["steps"] == 6
+    assert all(s["iters"] == 6 for s in st)
+    Xg = X.cpu().numpy().reshape(6, N).T
+    log(f"  difference to the oracle: {rel(Xg, Xr):.2e}")
+    assert rel(Xg, Xr) <= 1e-9
+    for c in range(6):
+        assert abs(st[c]["rel_res_true"] - info["relres"][c]) <= 1e-7 * info["relres"][c]
+
+
+def test_refinement_stops_on_stagnation(c1):
+    """FP16-stored inner block solves too short to make progress: the FP64
+    refinement stops once a column's residual has not fallen below 0.9 of its
+    best for three steps, and reports it (stagnated, DC_NOT_CONVERGED)."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, D = c1
+    log("block gmres stagnation stop")
+    B = _rhs(w.dims, w.n_tv, 2, 90)
+    o = Opts(m=1, prec="f16s", inner_tol=1e-12, max_cycles=1, max_outer=200)
+    X, st, rc = gop.solve_block(B.cuda(), 1e-12, o)
+    assert rc == 1
+    for s in st:
+        assert s["status"] == 1
+        assert s["stagnated"] == 1 or s["outer_iters"] >= 200
+    assert any(s["stagnated"] == 1 for s in st)
+    assert max(s["outer_iters"] for s in st) < 200

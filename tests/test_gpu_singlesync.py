@@ -2,6 +2,7 @@
 oracle's latency-1 pipelined process (Alg. 4 / Alg. 5), which is a different
 formulation with the same Hessenberg matrix in exact arithmetic."""
 import numpy as np
+import torch
 import pytest
 
 import synth
@@ -102,3 +103,37 @@ def test_single_sync_recycle_space_from_gram_schmidt_twice(c1):
     Uq = [gop.poly_apply(U[i], o).cpu().numpy().reshape(-1) for i in range(k)]
     AU = np.stack([dop.apply(oop, u.reshape(oop.V, oop.n)).reshape(-1) for u in Uq])
     assert np.abs(AU - Ch).max() <= 1e-8 * np.abs(Ch).max()
+
+
+@pytest.mark.parametrize("cfg", ["reduced_bj_ss", "full_cgs2", "f16s_outer"])
+def test_graph_replayed_cycles_match_eager(cfg):
+    """Arnoldi cycles recorded once as HIP graphs and replayed (opts.graphs =
+    1) give the same iterates as the eager launches: several solves in a row,
+    each replaying the cycle graphs several times, with eager work and host
+    synchronisation between the replays, every solve's solution identical to
+    the eager solve's."""
+    from paper_2205_09104_amd import CoarseOp, Opts
+    log("graph cycles", cfg)
+    w = synth.WORKLOADS["c1"]
+    A, B = synth.operator(w)
+    base = {"reduced_bj_ss": dict(m=28, k=8, d=4, seed=1, schur=1, block_jacobi=1, ortho=1),
+            "full_cgs2": dict(m=30, d=3, seed=2),
+            "f16s_outer": dict(m=28, k=8, d=4, prec="f16s", outer=1, inner_tol=1e-1, seed=1,
+                               schur=1, block_jacobi=1, ortho=1)}[cfg]
+    store = ("f64", "f32", "f16s")
+    opg = CoarseOp(A.cuda(), B.cuda(), w.dims, mu=w.mu, store=store)
+    ope = CoarseOp(A.cuda(), B.cuda(), w.dims, mu=w.mu, store=store)
+    for r in range(4):
+        b = synth.rhs(w.dims, w.n_tv, r).cuda()
+        xg, sg, rcg = opg.solve(b, 1e-10, Opts(**base, graphs=1))
+        xe, se, rce = ope.solve(b, 1e-10, Opts(**base, graphs=0))
+        torch.cuda.synchronize()
+        assert rcg == rce == 0
+        assert sg[0]["iters"] == se[0]["iters"] and sg[0]["matvecs"] == se[0]["matvecs"]
+        assert torch.equal(xg, xe), r
+    cap, launched = opg.graph_stats()
+    log(f"  graphs captured {cap}, launched {launched}")
+    assert cap >= 1 and launched > cap
+    assert ope.graph_stats() == (0, 0)
+    opg.close()
+    ope.close()
