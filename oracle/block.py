@@ -33,14 +33,26 @@ the parts of r_a outside V_0 are not orthogonal to the later blocks -- and
 its residual norm is sqrt(|| g_a - Hbar y_a ||^2 + ||r_a||^2 - ||g_a||^2).
 
 Deflation against a recycled pair (U, C) with C = A M U orthonormal (the
-GCRO-DR space of Sec. 3.4, frozen): every new residual block starts with
+GCRO-DR space of Sec. 3.4): every new residual block starts with
 x += M U C^H r, r -= C C^H r, the block Arnoldi runs on (I - C C^H) A M with
 B_k = C^H A M V, and column a's correction M (V y_a - U B_k y_a) leaves the
 residual r_a - V Hbar y_a (the C components cancel).
+
+Block recycling (the GCRO-DR update of Sec. 3.4 with the block relation in
+place of the single-vector one): a cycle of s = j nb basis vectors gives
+A M [U D, V_s] = [C, V_{s+nb}] G with D = diag(1 / ||u_i||) and
+G = [[D, B_k], [0, Hbar]] (without a recycle space G = Hbar).  The new space
+takes the k harmonic Ritz vectors of that relation with the smallest |theta|:
+G^H G z = theta G^H (What^H Vhat) z with Vhat = [U D, V_s], What =
+[C, V_{s+nb}] (What^H Vhat = [I_s; 0] without a recycle space); P_k their
+eigenvectors, [Q, R] = qr(G P_k), C = What Q, U = Vhat P_k R^{-1}.  It is
+built after the first cycle that has at least k basis vectors and refreshed
+after each later cycle until it has been updated u times.
 """
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg as sla
 
 
 def block_arnoldi(A, R0, m: int, targets=None, rank_tol: float = 1e-12):
@@ -168,13 +180,29 @@ def _cycle(Ablk, R, m, targets, sel_piv, C):
     return V, H[:(steps + 1) * nb, :steps * nb], Y, steps, est, Bk[:, :steps * nb], picks
 
 
+def harmonic_space(G, What, Vhat, k: int):
+    """The k harmonic Ritz vectors of A M Vhat = What G with the smallest
+    |theta| (G^H G z = theta G^H (What^H Vhat) z), as the recycle pair
+    (U, C): [Q, R] = qr(G P_k), C = What Q, U = Vhat P_k R^{-1}."""
+    WV = What.conj().T @ Vhat
+    theta, Z = sla.eig(G.conj().T @ G, G.conj().T @ WV)
+    mag = np.abs(theta)
+    mag[~np.isfinite(mag)] = np.inf
+    P = Z[:, np.argsort(mag, kind="stable")[:k]]
+    Q, Rr = np.linalg.qr(G @ P)
+    return Vhat @ P @ np.linalg.inv(Rr), What @ Q
+
+
 def block_gmres(A, B, tols, m: int, max_cycles: int, right=None, U=None, C=None,
-                sel_piv: float = 1e-12):
+                sel_piv: float = 1e-12, recycle=None, k: int = 0, u: int = 0):
     """Solve A X = B (N x R, per-column relative tolerances) with restarted
     block GMRES(m).  A and right act on single vectors.  U, C: an optional
     frozen recycle space (C = A right(U), orthonormal columns) to deflate
-    against.  Returns (X, info) with info = dict(cycles, steps, relres per
-    column, converged, generators: the generating-block size of each cycle)."""
+    against.  recycle: a state with fields U, C, updates (None: no
+    recycling) that the cycles build and refresh (k vectors, u updates) and
+    deflate against.  Returns (X, info) with info = dict(cycles, steps,
+    relres per column, converged, generators: the generating-block size of
+    each cycle)."""
     N, R = B.shape
     M = right or (lambda v: v)
     apply_block = lambda Vb: np.stack([A(M(Vb[:, c])) for c in range(Vb.shape[1])], axis=1)
@@ -192,6 +220,8 @@ def block_gmres(A, B, tols, m: int, max_cycles: int, right=None, U=None, C=None,
         if active.size == 0 or cycles >= max_cycles:
             break
         R0 = Rm[:, active]
+        if recycle is not None:
+            U, C = recycle.U, recycle.C
         if C is not None:
             coef = C.conj().T @ R0
             X[:, active] += Mblk(U @ coef)
@@ -212,5 +242,21 @@ def block_gmres(A, B, tols, m: int, max_cycles: int, right=None, U=None, C=None,
         if C is not None:
             corr = corr - U @ (Bk @ Y)
         X[:, active] += Mblk(corr)
+        if recycle is not None and k > 0:
+            Vw = np.concatenate(V[:j + 1], axis=1)
+            if C is None and Vm.shape[1] >= k:
+                recycle.U, recycle.C = harmonic_space(Hs, Vw, Vm, k)
+                recycle.updates = 1
+            elif C is not None and recycle.updates < u:
+                kk = U.shape[1]
+                dk = 1.0 / np.linalg.norm(U, axis=0)
+                G = np.zeros((kk + Hs.shape[0], kk + Hs.shape[1]), dtype=np.complex128)
+                G[:kk, :kk] = np.diag(dk)
+                G[:kk, kk:] = Bk
+                G[kk:, kk:] = Hs
+                recycle.U, recycle.C = harmonic_space(
+                    G, np.concatenate([C, Vw], axis=1),
+                    np.concatenate([U * dk[None, :], Vm], axis=1), kk)
+                recycle.updates += 1
     return X, {"cycles": cycles, "steps": steps, "relres": rel,
                "converged": bool(np.all(rel <= tols)), "generators": gens}

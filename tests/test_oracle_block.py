@@ -220,3 +220,105 @@ def test_deflated_block_gmres_converges_on_coarse_operator():
     rel = np.linalg.norm(B - D @ X, axis=0) / np.linalg.norm(B, axis=0)
     assert np.all(rel <= tols)
     assert info["steps"] < info0["steps"]
+
+
+def _invariant_error(U, M, k):
+    """How far span(U) is from the invariant subspace of M's k smallest-|lambda|
+    eigenvalues: the larger of the invariance residual of U and the mismatch
+    of the eigenvalues of U's Rayleigh-Ritz matrix (relative)."""
+    ev = np.linalg.eigvals(M)
+    smallest = ev[np.argsort(np.abs(ev))[:k]]
+    Mr = np.linalg.lstsq(U, M @ U, rcond=None)[0]
+    inv_res = np.linalg.norm(M @ U - U @ Mr) / np.linalg.norm(M @ U)
+    got = np.linalg.eigvals(Mr)
+    mism = max(max(np.min(np.abs(smallest - g)) for g in got),
+               max(np.min(np.abs(got - s)) for s in smallest))
+    return max(inv_res, mism / np.abs(smallest).max())
+
+
+def _block_recycle_error(stage, eig_fn=None):
+    """Block recycling on a 12 x 12 matrix with 3 right-hand sides, where one
+    block cycle spans the whole space: "build" -- 4 block steps from zero
+    (12 basis vectors), the space built from the block Hessenberg matrix;
+    "refresh" -- a random recycle pair that is not invariant (C = A U from a
+    QR of A U), then one deflated cycle of 3 block steps (which with U spans
+    C^12) and the refresh from G^H G z = theta G^H (What^H Vhat) z.  Either
+    way the harmonic Ritz pairs are exact eigenpairs, so span(U) must be the
+    invariant subspace of the 3 smallest-|lambda| eigenvalues."""
+    import oracle.block as ob
+    from oracle.gcrodr import RecycleState
+    M, rng = _matrix(N=12, seed=31)
+    A = lambda v: M @ v
+    B = rng.standard_normal((12, 3)) + 1j * rng.standard_normal((12, 3))
+    st = RecycleState()
+    m = 4
+    if stage == "refresh":
+        Uu = rng.standard_normal((12, 3)) + 1j * rng.standard_normal((12, 3))
+        C, Rr = np.linalg.qr(M @ Uu)
+        st.U, st.C, st.updates = Uu @ np.linalg.inv(Rr), C, 1
+        m = 3
+    saved = ob.sla
+    if eig_fn is not None:
+        class _Fake:
+            eig = staticmethod(eig_fn)
+        ob.sla = _Fake
+    try:
+        _, info = block_gmres(A, B, [1e-30] * 3, m, 1, recycle=st, k=3, u=10)
+    finally:
+        ob.sla = saved
+    assert info["cycles"] == 1 and st.updates == (2 if stage == "refresh" else 1)
+    # the pair's own relations hold for any choice of vectors
+    assert np.linalg.norm(st.C.conj().T @ st.C - np.eye(3)) <= 1e-12
+    assert np.linalg.norm(M @ st.U - st.C) <= 1e-10 * np.linalg.norm(st.C)
+    return _invariant_error(st.U, M, 3)
+
+
+@pytest.mark.parametrize("stage", ["build", "refresh"])
+def test_block_recycle_space_is_exact_when_the_cycle_spans_everything(stage):
+    """Pins the block form of the GCRO-DR space construction and refresh
+    (Sec. 3.4, with the block Arnoldi relation)."""
+    assert _block_recycle_error(stage) <= 1e-8
+
+
+@pytest.mark.parametrize("stage", ["build", "refresh"])
+@pytest.mark.parametrize("mistake", ["no_rhs_matrix", "swapped", "conjugated"])
+def test_block_recycle_pin_detects_wrong_eigenproblem(stage, mistake):
+    """Mistakes planted in the oracle's block recycling (on the CPU) fail the
+    pin above: dropping G^H What^H Vhat, swapping the two matrices (which
+    selects the largest |theta|), or conjugating the problem."""
+    import scipy.linalg as sla
+    wrong = {"no_rhs_matrix": lambda a, b: sla.eig(a),
+             "swapped": lambda a, b: sla.eig(b, a),
+             "conjugated": lambda a, b: sla.eig(a.conj(), b.conj())}[mistake]
+    assert _block_recycle_error(stage, wrong) > 1e-3
+
+
+def test_block_recycling_cuts_block_steps_on_coarse_operator():
+    """Block GMRES that builds and refreshes its own recycle space (k = 8,
+    u = 4) over two batches of right-hand sides of a small coarse operator:
+    every column to its tolerance, the second batch in fewer block steps than
+    without recycling, and the space it leaves satisfies C = A U, C^H C = I."""
+    from oracle.gcrodr import RecycleState
+    dims, ntv = (2, 2, 2, 2), 4
+    A0 = synth.self_blocks(dims, ntv, 3.5, 0).numpy()
+    Bh = synth.hop_blocks(dims, ntv, 0).numpy()
+    op = dop.build(dims, A0, Bh, 0.05)
+    f = lambda v: dop.apply(op, v.reshape(op.V, op.n)).reshape(-1)
+    D = dop.dense(op)
+    rng = np.random.default_rng(9)
+    N = op.V * op.n
+    st = RecycleState()
+    tols = np.array([1e-10, 1e-8, 1e-9, 1e-7])
+    B1 = rng.standard_normal((N, 4)) + 1j * rng.standard_normal((N, 4))
+    B2 = rng.standard_normal((N, 4)) + 1j * rng.standard_normal((N, 4))
+    X1, i1 = block_gmres(f, B1, tols, 6, 400, recycle=st, k=8, u=4)
+    X2, i2 = block_gmres(f, B2, tols, 6, 400, recycle=st, k=8, u=4)
+    X0, i0 = block_gmres(f, B2, tols, 6, 400)
+    assert i1["converged"] and i2["converged"] and i0["converged"]
+    for X, B in ((X1, B1), (X2, B2)):
+        rel = np.linalg.norm(B - D @ X, axis=0) / np.linalg.norm(B, axis=0)
+        assert np.all(rel <= tols)
+    assert st.updates == 4
+    assert i2["steps"] < i0["steps"]
+    assert np.linalg.norm(st.C.conj().T @ st.C - np.eye(8)) <= 1e-10
+    assert np.linalg.norm(D @ st.U - st.C) <= 1e-8 * np.linalg.norm(st.C)
