@@ -42,7 +42,7 @@ def parse():
                         "(the setup phase), so the timed solves see it frozen")
     p.add_argument("--workload", default="c3")
     p.add_argument("--tol", type=float, default=1e-8)
-    p.add_argument("--inner", default="f16s", choices=["f32", "f16s"])
+    p.add_argument("--inner", default="f16s", choices=["f64", "f32", "f16s"])
     p.add_argument("--d", type=int, default=24)
     p.add_argument("--k", type=int, default=384)
     p.add_argument("--bj", type=int, default=1, choices=[0, 1],
@@ -125,18 +125,20 @@ def stage1_bytes(V, n, prec):
     return V * (5 * n * n * sb + n * sv + extra)
 
 
-# HBM traffic of one launch of the roofline kernel on the 8^4, N_tv = 24
-# workload with FP16 blocks (kernel 2: the reduced operator's A_e - D_eo
-# kernel): rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per dispatch,
-# median over the 3439 launches that did work, almost all later chain steps),
-# each scaled by the ratio of true bytes to counter reading for a plain 1 GiB
-# elementwise copy (--copy-probe 1024: FETCH_SIZE 524300 KiB for 1 GiB read,
-# WRITE_SIZE 1048576 KiB for 1 GiB written).  Valid only for the apply source
-# it was taken on.
-TRAFFIC = {"workload": "c2", "prec": "f16s", "kernel": 2,
-           "fetch_kib": 85536.4375, "fetch_scale": 1048576.0 / 524300.0,
-           "write_kib": 1536.0, "write_scale": 1048576.0 / 1048576.0,
-           "apply_source_sha256": "5c0bd7055b182519b7fa68ec2d705e971feff8dffbdb3ffb1659f6be9aa48858"}
+# HBM traffic of one launch of the roofline kernel on the 16^3 x 32,
+# N_tv = 24 twisted-mass workload with FP16 blocks (kernel 2: the reduced
+# operator's x_e - A_e^-1 D_eo t_o kernel, later polynomial-chain step, the
+# launch that makes up 91% of the solves'): rocprofv3 --pmc FETCH_SIZE and
+# --pmc WRITE_SIZE (KiB per dispatch, median over 88 launches) of
+# `dc_kernel_probe chain 16 16 16 32 24 f16s 3 0.001`, each scaled by the
+# ratio of true bytes to counter reading for 1 GiB device copies
+# (`dc_kernel_probe copy 1024`: FETCH_SIZE 524299.5 KiB for 1 GiB read,
+# WRITE_SIZE 1048576 KiB for 1 GiB written).  Valid only for the apply
+# source it was taken on.
+TRAFFIC = {"workload": "c3", "prec": "f16s", "kernel": 2,
+           "fetch_kib": 2747144.5938, "fetch_scale": 1048576.0 / 524299.5,
+           "write_kib": 49152.0, "write_scale": 1048576.0 / 1048576.0,
+           "apply_source_sha256": "c8e500cee7fcac117f80ca2c973b4a32e1d8a41b767d85c44b92676e281a9223"}
 
 
 def apply_source_digest():

@@ -353,12 +353,19 @@ int solve_coarse_batch(dc_op_t op, const dc_solve_opts* opts, int32_t adjoint, i
  * targets, or when a new block is rank deficient.  Numerically dependent
  * residual columns: the space grows from a well-conditioned subset of them
  * (pivoted Cholesky of their scaled Gram matrix) and every column takes its
- * minimiser over it.  If opts->k > 0 and
- * solve_coarse built a recycle space for the same variant (prec, d, full
- * lattice), every cycle is deflated against it without refreshing it (Sec.
- * 3.4): new residual blocks start with x += q(A) U C^H r, r -= C C^H r, the
- * block Arnoldi runs on (I - C C^H) A, and each column's correction has the
- * recycled part -q(A) U B_k y.  Full lattice, no block Jacobi (schur,
+ * minimiser over it.  With opts->k > 0 the solve recycles (Sec. 3.4, in
+ * block form): if the variant (prec, d, full lattice) holds no recycle space
+ * of dimension k, the first cycle with at least k basis vectors builds one
+ * from the k harmonic Ritz vectors of its block Arnoldi relation with the
+ * smallest |theta|; the following cycles are deflated against it (new
+ * residual blocks start with x += q(A) U C^H r, r -= C C^H r, the block
+ * Arnoldi runs on (I - C C^H) A, each column's correction has the recycled
+ * part -q(A) U B_k y) and refresh it from the relation
+ * A q(A) [U D, V] = [C, V'] G until it has been updated opts->u times.  The
+ * space is the one solve_coarse uses for the same variant (either solver
+ * continues what the other built).  A cycle that ends on a rank-deficient
+ * block leaves the space unchanged; a failed dense eigenproblem freezes it and
+ * counts in stats.refresh_failed.  Full lattice, no block Jacobi (schur,
  * block_jacobi must be 0).
  * opts->prec F64: the block solve in FP64; F32 / F16S: an FP64
  * iterative-refinement loop (r = b - D x in FP64, block solve of D e = r to

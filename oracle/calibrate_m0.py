@@ -23,7 +23,15 @@ Two readings, by size:
   eigenvalues just outside the disk then lie at or across the origin's side
   of m0 - r, which is the near-null-mode situation the deflation targets.
 
+How close the limiting-disk reading comes on a given lattice is estimated
+(not calibrated) from the Ritz values of a k-step Arnoldi process (modified
+Gram-Schmidt, seeded Gaussian start) on D(m0): the leftmost Ritz value and
+the largest Ritz modulus give rho_ritz = min Re / max |.|, recorded with the
+residual norm |h_{k+1,k} e_k^T y| of the leftmost Ritz pair (how far it is
+from an eigenpair).
+
 Usage: python -m oracle.calibrate_m0 c1 c2 ...
+       python -m oracle.calibrate_m0 --ritz STEPS c2 ...   (adds the estimate)
 """
 from __future__ import annotations
 
@@ -90,12 +98,43 @@ def calibrate(name: str, dense_limit: int = 8192):
             "seconds": time.time() - t0}
 
 
+def ritz_estimate(name: str, steps: int, seed: int = 7):
+    """Leftmost Ritz value, largest Ritz modulus and their ratio for D(m0) of
+    workload `name` (its calibrated m0) from `steps` Arnoldi steps."""
+    import torch  # noqa: F401  (synth uses torch)
+    import synth
+    from .krylov import arnoldi
+    w = synth.WORKLOADS[name]
+    t0 = time.time()
+    A, B = synth.operator(w)
+    op = dop.build(w.dims, A.numpy(), B.numpy(), 0.0)
+    f = lambda v: dop.apply(op, v.reshape(op.V, op.n)).reshape(-1)
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(op.V * op.n) + 1j * rng.standard_normal(op.V * op.n)
+    ar = arnoldi(f, v, steps, "mgs")
+    j = ar.steps
+    theta, Y = sla.eig(ar.Hbar[:j, :j])
+    i = int(np.argmin(theta.real))
+    res = abs(ar.Hbar[j, j - 1]) * abs(Y[j - 1, i]) / np.linalg.norm(Y[:, i])
+    return {"rho_ritz": float(theta.real.min() / np.abs(theta).max()),
+            "ritz_min_re": float(theta.real.min()), "ritz_max_abs": float(np.abs(theta).max()),
+            "ritz_steps": int(j), "ritz_left_residual": float(res),
+            "ritz_seconds": time.time() - t0}
+
+
 def main(names):
     import synth
     path = synth.M0_TABLE
     tab = synth.load_m0_table()
+    ritz = 0
+    if names and names[0] == "--ritz":
+        ritz = int(names[1])
+        names = names[2:]
     for name in names:
-        tab[name] = calibrate(name)
+        if ritz:
+            tab[name].update(ritz_estimate(name, ritz))
+        else:
+            tab[name] = calibrate(name)
         print(name, tab[name], flush=True)
         with open(path + ".tmp", "w") as f:
             json.dump(tab, f, indent=1, sort_keys=True)

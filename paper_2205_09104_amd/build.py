@@ -48,11 +48,20 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     rocm_lib = os.path.join(os.path.dirname(os.path.dirname(_hipcc())), "lib")
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
-           f"-L{rocm_lib}", "-lrocblas", f"-Wl,-rpath,{rocm_lib}"]
+           f"-L{rocm_lib}", f"-Wl,-rpath,{rocm_lib}"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # the counter-collection driver (no torch), linked against the library
+    probe = os.path.join(HERE, "dc_kernel_probe")
+    cmd = [_hipcc(), "-O2", "-std=c++17", os.path.join(CSRC, "kernel_probe.cpp"), "-o",
+           probe + ".tmp", f"-L{HERE}", "-ldcsolve", f"-Wl,-rpath,{HERE}",
+           f"-Wl,-rpath,{rocm_lib}"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe link failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(probe + ".tmp", probe)
     if verbose:
         print("built", LIB)
     return LIB

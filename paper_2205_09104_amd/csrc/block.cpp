@@ -3,14 +3,15 @@
 // solver keeps one space per right-hand side).  The block matvec is the MFMA
 // multi-right-hand-side apply, the polynomial preconditioner of Sec. 3.3 runs
 // on whole blocks, block Gram-Schmidt (classical, twice) and the Cholesky QR
-// of each new block are tall-skinny complex GEMMs (rocBLAS), and the block
+// of each new block are tall-skinny complex products on MFMA tiles (the block
+// Gram and block update kernels), and the block
 // Hessenberg matrix is reduced by Householder transformations on the host as
 // it grows, which gives every column's least-squares residual after every
 // block step.  Reduced-precision blocks (FP32, FP16 + scale) run inside an
-// FP64 iterative-refinement loop.
+// FP64 iterative-refinement loop.  With k > 0 the solver deflates against the
+// variant's recycle space and builds and refreshes it from its own block
+// cycles (the GCRO-DR update with the block Arnoldi relation).
 #include "solver.hpp"
-
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <cmath>
@@ -21,89 +22,6 @@
 
 namespace dc {
 namespace {
-
-void blas_check(rocblas_status s) {
-  if (s != rocblas_status_success) throw BadState("rocBLAS call failed");
-}
-
-rocblas_handle blas_handle(Op& op, hipStream_t st) {
-  if (!op.blas) {
-    rocblas_handle h = nullptr;
-    blas_check(rocblas_create_handle(&h));
-    op.blas = std::shared_ptr<void>(static_cast<void*>(h), [](void* q) {
-      (void)rocblas_destroy_handle(static_cast<rocblas_handle>(q));
-    });
-  }
-  auto h = static_cast<rocblas_handle>(op.blas.get());
-  blas_check(rocblas_set_stream(h, st));
-  return h;
-}
-
-template <typename VR>
-struct Blas;
-template <>
-struct Blas<double> {
-  static void gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n,
-                   int k, cd al, const z64* A, int lda, const z64* B, int ldb, cd be, z64* C,
-                   int ldc) {
-    const rocblas_double_complex a(al.real(), al.imag()), b(be.real(), be.imag());
-    blas_check(rocblas_zgemm(h, ta, tb, m, n, k, &a,
-                             reinterpret_cast<const rocblas_double_complex*>(A), lda,
-                             reinterpret_cast<const rocblas_double_complex*>(B), ldb, &b,
-                             reinterpret_cast<rocblas_double_complex*>(C), ldc));
-  }
-  // C_p = A_p^H B_p for P chunks (strided)
-  static void gemm_cn_batched(rocblas_handle h, int m, int n, int k, const z64* A, int lda,
-                              long sa, const z64* B, int ldb, long sb, z64* C, int ldc, long sc,
-                              int P) {
-    const rocblas_double_complex a(1.0, 0.0), b(0.0, 0.0);
-    blas_check(rocblas_zgemm_strided_batched(
-        h, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n, k, &a,
-        reinterpret_cast<const rocblas_double_complex*>(A), lda, sa,
-        reinterpret_cast<const rocblas_double_complex*>(B), ldb, sb, &b,
-        reinterpret_cast<rocblas_double_complex*>(C), ldc, sc, P));
-  }
-  // y = A x (A: rows x cols, column-major)
-  static void gemv(rocblas_handle h, int rows, int cols, const z64* A, int lda, const z64* x,
-                   z64* y) {
-    const rocblas_double_complex a(1.0, 0.0), b(0.0, 0.0);
-    blas_check(rocblas_zgemv(h, rocblas_operation_none, rows, cols, &a,
-                             reinterpret_cast<const rocblas_double_complex*>(A), lda,
-                             reinterpret_cast<const rocblas_double_complex*>(x), 1, &b,
-                             reinterpret_cast<rocblas_double_complex*>(y), 1));
-  }
-};
-template <>
-struct Blas<float> {
-  static void gemm(rocblas_handle h, rocblas_operation ta, rocblas_operation tb, int m, int n,
-                   int k, cd al, const z32* A, int lda, const z32* B, int ldb, cd be, z32* C,
-                   int ldc) {
-    const rocblas_float_complex a(float(al.real()), float(al.imag()));
-    const rocblas_float_complex b(float(be.real()), float(be.imag()));
-    blas_check(rocblas_cgemm(h, ta, tb, m, n, k, &a,
-                             reinterpret_cast<const rocblas_float_complex*>(A), lda,
-                             reinterpret_cast<const rocblas_float_complex*>(B), ldb, &b,
-                             reinterpret_cast<rocblas_float_complex*>(C), ldc));
-  }
-  static void gemm_cn_batched(rocblas_handle h, int m, int n, int k, const z32* A, int lda,
-                              long sa, const z32* B, int ldb, long sb, z32* C, int ldc, long sc,
-                              int P) {
-    const rocblas_float_complex a(1.0f, 0.0f), b(0.0f, 0.0f);
-    blas_check(rocblas_cgemm_strided_batched(
-        h, rocblas_operation_conjugate_transpose, rocblas_operation_none, m, n, k, &a,
-        reinterpret_cast<const rocblas_float_complex*>(A), lda, sa,
-        reinterpret_cast<const rocblas_float_complex*>(B), ldb, sb, &b,
-        reinterpret_cast<rocblas_float_complex*>(C), ldc, sc, P));
-  }
-  static void gemv(rocblas_handle h, int rows, int cols, const z32* A, int lda, const z32* x,
-                   z32* y) {
-    const rocblas_float_complex a(1.0f, 0.0f), b(0.0f, 0.0f);
-    blas_check(rocblas_cgemv(h, rocblas_operation_none, rows, cols, &a,
-                             reinterpret_cast<const rocblas_float_complex*>(A), lda,
-                             reinterpret_cast<const rocblas_float_complex*>(x), 1, &b,
-                             reinterpret_cast<rocblas_float_complex*>(y), 1));
-  }
-};
 
 // Cholesky factor of a Hermitian r x r matrix after diagonal scaling:
 // G = D Gs D with D = diag(sqrt(G_ii)), Gs = L L^H; returns R = L^H D (upper,
@@ -177,19 +95,20 @@ template <typename VR>
 struct BlockGmres {
   using Z = cx<VR>;
   Op& op;
-  const Variant& var;
+  Variant& var;
   const SolveOpts& o;
   Prec p;
   hipStream_t st;
   size_t N;
   int m, Rmax;
-  rocblas_handle h;
   Z *V = nullptr, *Zb = nullptr, *W = nullptr, *T1 = nullptr, *TA = nullptr, *PROD = nullptr,
     *U = nullptr;
   Z *Hd = nullptr, *Gd = nullptr, *Rd = nullptr, *Yd = nullptr;
-  Z *Pt = nullptr, *Ones = nullptr, *Sum = nullptr;   // split-K partials, ones, their sum
+  Z* Pt = nullptr;      // per-chunk partial Gram products
+  z64* Sum = nullptr;   // their FP64 sum
   void** tabs = nullptr;
   long applies = 0;   // operator applications to single vectors
+  int refreshes = 0, refresh_failed = 0;   // recycle builds / refreshes, failed ones
   // frozen recycle space of the single-RHS solver's variant (GCRO-DR, Sec. 3.4):
   // the cycles run on (I - C C^H) A; kc = 0 without one
   int kc = 0;
@@ -197,10 +116,9 @@ struct BlockGmres {
   Z* Bd = nullptr;   // device C^H W, kc x r
 
   // apply_only: just the multi-apply (and its pointer tables), no Krylov workspace
-  BlockGmres(Op& op_, const Variant& v, const SolveOpts& o_, Prec p_, int R, hipStream_t st_,
+  BlockGmres(Op& op_, Variant& v, const SolveOpts& o_, Prec p_, int R, hipStream_t st_,
              bool apply_only = false)
       : op(op_), var(v), o(o_), p(p_), st(st_), N(op_.N()), m(std::max(o_.m, 1)), Rmax(R) {
-    h = blas_handle(op, st);
     const size_t vb = N * sizeof(Z) * size_t(R);
     const bool poly = has_poly();
     Op::BlockWS& b = (sizeof(VR) == 8) ? op.bk64 : op.bk32;
@@ -220,7 +138,12 @@ struct BlockGmres {
     const int kmax = std::max(o.k, 0);
     const size_t qrmax = std::max(size_t(m + 1) * R * R, size_t(kmax) * R);
     b.small.ensure(ns * sizeof(Z));
-    b.part.ensure((size_t(kChunks + 1) * qrmax + (kChunks + 1) + qrmax) * sizeof(Z));
+    // the Gram kernel's chunk partials (the most chunks a product takes is
+    // that of a single output tile) or the multidot path's FP64 results, then
+    // the FP64 sum
+    const size_t pbytes = std::max(size_t(block_gram_parts(N, 1, 1)) * qrmax * sizeof(Z),
+                                   qrmax * 2 * sizeof(double));
+    b.part.ensure(pbytes + qrmax * sizeof(z64));
     V = b.V.as<Z>();
     Zb = poly ? b.Z.as<Z>() : nullptr;
     W = b.W.as<Z>();
@@ -233,19 +156,16 @@ struct BlockGmres {
     Rd = Gd + size_t(R) * R;
     Yd = Rd + size_t(R) * R;
     Pt = b.part.as<Z>();
-    Ones = Pt + size_t(kChunks + 1) * qrmax;
-    Sum = Ones + (kChunks + 1);
-    {
-      std::vector<Z> ones(kChunks + 1, mk(VR(1), VR(0)));
-      op.hs.write(Ones, ones.data(), ones.size() * sizeof(Z), st);
+    Sum = reinterpret_cast<z64*>(b.part.as<unsigned char>() + pbytes);
+    if (o.k > 0) {
+      b.Bc.ensure(2 * size_t(o.k) * R * sizeof(Z));
+      Bd = b.Bc.as<Z>();
     }
     if (o.k > 0 && v.kcur > 0 && v.recycle_version == op.version && v.k_built == o.k) {
       kc = v.kcur;
       Cr = v.C.as<Z>();
       Ur = v.U.as<Z>();
       MUr = (v.mu_ok && poly) ? v.MU.as<Z>() : nullptr;
-      b.Bc.ensure(size_t(kc) * R * sizeof(Z) + size_t(kc) * R * sizeof(Z));
-      Bd = b.Bc.as<Z>();
     }
   }
 
@@ -254,14 +174,12 @@ struct BlockGmres {
   // applying the polynomial to U c
   void add_recycled(const Z* cdev, int r, const std::vector<Z*>& xcols) {
     if (has_poly() && !MUr) {
-      gemm(rocblas_operation_none, rocblas_operation_none, int(N), r, kc, 1.0, Ur, int(N), cdev, kc,
-           0.0, U, int(N));
+      update(Ur, kc, cdev, U, r, 1.0, 0.0);
       Q(U, W, r);
       for (int a = 0; a < r; ++a) launch_axpy(p, mk(1.0, 0.0), W + size_t(a) * N, xcols[a], N, st);
       return;
     }
-    gemm(rocblas_operation_none, rocblas_operation_none, int(N), r, kc, 1.0, has_poly() ? MUr : Ur,
-         int(N), cdev, kc, 0.0, U, int(N));
+    update(has_poly() ? MUr : Ur, kc, cdev, U, r, 1.0, 0.0);
     for (int a = 0; a < r; ++a) launch_axpy(p, mk(1.0, 0.0), U + size_t(a) * N, xcols[a], N, st);
   }
 
@@ -337,21 +255,18 @@ struct BlockGmres {
     }
   }
 
-  void gemm(rocblas_operation ta, rocblas_operation tb, int mm, int nn, int kk, cd al,
-            const Z* A, int lda, const Z* B, int ldb, cd be, Z* C, int ldc) {
-    Blas<VR>::gemm(h, ta, tb, mm, nn, kk, al, A, lda, B, ldb, be, C, ldc);
+  // C = be C + al A S (A: kk vectors, S: kk x nn on the device, C: nn vectors)
+  void update(const Z* A, int kk, const Z* S, Z* C, int nn, cd al, cd be) {
+    launch_block_update(p, A, kk, S, C, nn, N, mk(al.real(), al.imag()), mk(be.real(), be.imag()),
+                        st);
   }
 
   // A^H B for qa contiguous vectors A and rb contiguous vectors B, read to the
-  // host.  One GEMM has a q x r output and an inner dimension of N, too few
-  // output tiles to spread the reduction over the chip, so N is split into
-  // kChunks row ranges: a strided-batched GEMM forms the chunks' partial
-  // products side by side and a GEMV with a ones vector sums them (a remainder
-  // of fewer rows than a chunk adds one more partial).
-  // Narrow blocks (rb <= 16) take one multidot launch per column of B instead
-  // (grid-wide partials, double accumulation): faster there than the batched
-  // GEMM.
-  static constexpr int kChunks = 256;
+  // host.  The block Gram kernel splits the inner dimension N into row chunks
+  // (one output tile has too little work to spread over the chip) and sums
+  // the chunks' partial products in FP64.  Narrow blocks (rb <= 16) take one
+  // multidot launch per column of B instead (grid-wide partials, FP64
+  // accumulation throughout).
   Mat tn(const Z* A, int qa, const Z* B, int rb) {
     if (rb <= 16) {
       double* dd = reinterpret_cast<double*>(Pt);
@@ -368,26 +283,15 @@ struct BlockGmres {
       return M;
     }
     const size_t qr = size_t(qa) * rb;
-    const size_t L = N / kChunks;             // rows per chunk (0 for tiny N)
-    const int P = L ? kChunks : 0;
-    const size_t rem = N - size_t(P) * L;
-    const int parts = P + (rem ? 1 : 0);
-    Z* part = Pt;
-    if (P)
-      Blas<VR>::gemm_cn_batched(h, qa, rb, int(L), A, int(N), long(L), B, int(N), long(L), part,
-                                qa, long(qr), P);
-    if (rem)
-      gemm(rocblas_operation_conjugate_transpose, rocblas_operation_none, qa, rb, int(rem), 1.0,
-           A + size_t(P) * L, int(N), B + size_t(P) * L, int(N), 0.0, part + size_t(P) * qr, qa);
-    Blas<VR>::gemv(h, int(qr), parts, part, int(qr), Ones, Sum);
-    std::vector<Z> hbuf(qr);
-    op.hs.read(hbuf.data(), Sum, qr * sizeof(Z), st);
+    launch_block_gram(p, A, qa, B, rb, N, Pt, Sum, st);
+    std::vector<z64> hbuf(qr);
+    op.hs.read(hbuf.data(), Sum, qr * sizeof(z64), st);
     op.hs.wait(st);
     Mat M(qa, rb);
     for (int b = 0; b < rb; ++b)
       for (int i = 0; i < qa; ++i) {
-        const Z z = hbuf[size_t(b) * qa + i];
-        M(i, b) = cd(double(z.re), double(z.im));
+        const z64 z = hbuf[size_t(b) * qa + i];
+        M(i, b) = cd(z.re, z.im);
       }
     return M;
   }
@@ -429,8 +333,7 @@ struct BlockGmres {
       Mat R;
       if (!scaled_cholesky(G, piv, R)) return false;
       write_mat(Rd, tri_inverse(R));
-      gemm(rocblas_operation_none, rocblas_operation_none, int(N), r, r, 1.0, a, int(N), Rd, r,
-           0.0, b, int(N));
+      update(a, r, Rd, b, r, 1.0, 0.0);
       Rtot = matmul(R, Rtot);
     }
     return true;
@@ -493,8 +396,7 @@ struct BlockGmres {
     // by subtracting squared norms
     DC_HIP(hipMemcpyAsync(T1, U, size_t(nr) * N * sizeof(Z), hipMemcpyDeviceToDevice, st));
     write_mat(Rd, S0);
-    gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, nb, -1.0, V, int(N), Rd, nb,
-         1.0, T1, int(N));
+    update(V, nb, Rd, T1, nr, -1.0, 1.0);
     const std::vector<double> e2 = colnorms(T1, nr);
     drop.assign(nr, 0.0);
     for (int a = 0; a < nr; ++a) drop[a] = std::sqrt(std::max(e2[a], 0.0));
@@ -503,8 +405,10 @@ struct BlockGmres {
 
   struct Cycle {
     int steps = 0;
+    bool full = true;   // every block of the cycle had full rank
     Mat Y;          // (steps r) x r coefficients
     Mat Bk;         // kc x (m r): C^H A V of the deflated process
+    Mat Hb;         // the block Hessenberg matrix before its reduction
     std::vector<double> est;
   };
 
@@ -526,6 +430,7 @@ struct BlockGmres {
     const bool dep = nr < nc;
     const int msteps = dep ? std::max(m, std::min(m * nc / nr, (m + 1) * nc / nr - 1)) : m;
     c.Bk = Mat(std::max(kc, 1), msteps * nr);
+    c.Hb = Mat((msteps + 1) * nr, msteps * nr);
     Mat Rf((msteps + 1) * nr, msteps * nr);
     Mat G((msteps + 1) * nr, nc);
     for (int j = 0; j < nc; ++j)
@@ -554,15 +459,13 @@ struct BlockGmres {
         if (kc) {   // deflation: W -= C (C^H W), coefficients B_k
           const Mat bp = tn(Cr, kc, W, nr);
           write_mat(Bd, bp);
-          gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, kc, -1.0, Cr, int(N), Bd,
-               kc, 1.0, W, int(N));
+          update(Cr, kc, Bd, W, nr, -1.0, 1.0);
           for (int b = 0; b < nr; ++b)
             for (int i = 0; i < kc; ++i) c.Bk(i, j * nr + b) += bp(i, b);
         }
         const Mat hp = tn(V, q, W, nr);
         write_mat(Hd, hp);
-        gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, q, -1.0, V, int(N), Hd, q,
-             1.0, W, int(N));
+        update(V, q, Hd, W, nr, -1.0, 1.0);
         for (int b = 0; b < nr; ++b)
           for (int i = 0; i < q; ++i) hcol(i, b) += hp(i, b);
       }
@@ -581,7 +484,9 @@ struct BlockGmres {
       for (int b = 0; b < nr; ++b) {
         for (int i = 0; i < q; ++i) col(i, b) = hcol(i, b);
         for (int i = 0; i < nr; ++i) col(q + i, b) = full ? Hsub(i, b) : cd(0.0);
+        for (int i = 0; i < q + nr; ++i) c.Hb(i, j * nr + b) = col(i, b);
       }
+      c.full = full;
       for (int i = 0; i < j; ++i) {
         Mat sub(2 * nr, nr);
         for (int b = 0; b < nr; ++b)
@@ -627,6 +532,123 @@ struct BlockGmres {
         c.Y(i, b) = (std::abs(Rf(i, i)) > 0.0) ? t / Rf(i, i) : cd(0.0);
       }
     return c;
+  }
+
+  // Build (no recycle space yet) or refresh (fewer than u updates so far) the
+  // recycle space of the variant from a cycle's block relation
+  // A M [U D, V_s] = [C, V_{s+nb}] G, D = diag(1 / ||u_i||),
+  // G = [[D, B_k], [0, Hbar]] (G = Hbar without a space; the GCRO-DR update of
+  // Sec. 3.4 with the block Arnoldi relation): the k harmonic Ritz vectors of
+  // G^H G z = theta G^H (What^H Vhat) z with the smallest |theta|, P_k;
+  // [Q, R] = qr(G P_k), C = What Q, U = Vhat P_k R^{-1}, and M U by the same
+  // combination of the M V_j.  A cycle that ended on a rank-deficient block
+  // leaves the space as it is.  Returns true if the space changed.
+  bool recycle(const Cycle& c, int nb) {
+    if (o.k <= 0 || !c.full || c.steps == 0) return false;
+    const int s = c.steps * nb;
+    const bool build = kc == 0;
+    if (build ? s < o.k : var.updates >= o.u) return false;
+    const int k0 = build ? 0 : kc, kk = build ? o.k : kc;
+    const int nrow = k0 + s + nb, ncol = k0 + s;
+    std::vector<double> un(size_t(k0), 1.0);
+    if (!build) {
+      const std::vector<double> u2 = colnorms(Ur, kc);
+      for (int i = 0; i < kc; ++i) un[size_t(i)] = std::sqrt(std::max(u2[size_t(i)], 0.0));
+    }
+    Mat G(nrow, ncol), WV(nrow, ncol);
+    for (int i = 0; i < k0; ++i) {
+      G(i, i) = 1.0 / un[size_t(i)];
+      for (int q = 0; q < s; ++q) G(i, k0 + q) = c.Bk(i, q);
+    }
+    for (int i = 0; i < s + nb; ++i)
+      for (int q = 0; q < s; ++q) G(k0 + i, k0 + q) = c.Hb(i, q);
+    for (int i = 0; i < s; ++i) WV(k0 + i, k0 + i) = 1.0;   // V_{s+nb}^H V_s
+    if (!build) {   // C^H U D and V_{s+nb}^H U D
+      const Mat CU = tn(Cr, kc, Ur, kc);
+      const Mat VU = tn(V, s + nb, Ur, kc);
+      for (int q = 0; q < kc; ++q) {
+        for (int i = 0; i < kc; ++i) WV(i, q) = CU(i, q) / un[size_t(q)];
+        for (int i = 0; i < s + nb; ++i) WV(kc + i, q) = VU(i, q) / un[size_t(q)];
+      }
+    }
+    const Mat GH = adjoint(G);
+    Mat Bm = matmul(GH, WV), Am = matmul(GH, G);
+    std::vector<cd> th;
+    Mat Zv;
+    if (!lu_solve(Bm, Am) || !eig(Am, th, &Zv)) {   // Am <- Bm^{-1} Am
+      var.updates = o.u;                            // frozen, as in the single solver
+      ++refresh_failed;
+      return false;
+    }
+    const auto idx = smallest_k(th, kk);
+    Mat P(ncol, kk);
+    for (int t = 0; t < kk; ++t)
+      for (int i = 0; i < ncol; ++i) P(i, t) = Zv(i, idx[size_t(t)]);
+    Mat Qm, Rq;
+    qr_thin(matmul(G, P), Qm, Rq);
+    const Mat PR = matmul(P, tri_inverse(Rq));
+    // coefficients, output-major: C from [C, V_{s+nb}], U from [U, V_s] (D
+    // folded in), M U from [M U, M V_s]
+    std::vector<z64> cq(size_t(kk) * nrow), cu(size_t(kk) * ncol);
+    for (int r = 0; r < kk; ++r) {
+      for (int q = 0; q < nrow; ++q) cq[size_t(r) * nrow + q] = mk(Qm(q, r).real(), Qm(q, r).imag());
+      for (int q = 0; q < ncol; ++q) {
+        const cd v = q < k0 ? PR(q, r) / un[size_t(q)] : PR(q, r);
+        cu[size_t(r) * ncol + q] = mk(v.real(), v.imag());
+      }
+    }
+    Op::BlockWS& b = (sizeof(VR) == 8) ? op.bk64 : op.bk32;
+    b.rcoef.ensure((cq.size() + cu.size()) * sizeof(z64));
+    const bool mu = has_poly();
+    const bool mu_old = mu && k0 && !MUr;   // M U of the old space to be formed
+    b.rtmp.ensure(size_t(mu ? (mu_old ? 4 : 3) : 2) * kk * N * sizeof(Z));
+    z64* dq = b.rcoef.as<z64>();
+    z64* du = dq + cq.size();
+    op.hs.write(dq, cq.data(), cq.size() * sizeof(z64), st);
+    op.hs.write(du, cu.data(), cu.size() * sizeof(z64), st);
+    Z* Cn = b.rtmp.as<Z>();
+    Z* Un = Cn + size_t(kk) * N;
+    Z* MUn = Un + size_t(kk) * N;
+    const double* cqd = reinterpret_cast<const double*>(dq);
+    const double* cud = reinterpret_cast<const double*>(du);
+    launch_combine(p, k0 ? Cr : nullptr, k0, V, s + nb, N, cqd, kk, Cn, 0, st);
+    launch_combine(p, k0 ? Ur : nullptr, k0, V, s, N, cud, kk, Un, 0, st);
+    if (mu) {
+      // M U: from the kept M U, else by applying M to the old U (once)
+      const Z* mur = MUr;
+      if (mu_old) {   // M applied to the old U, Rmax columns at a time
+        Z* MUo = MUn + size_t(kk) * N;
+        for (int c0 = 0; c0 < kc; c0 += Rmax) {
+          const int r = std::min(Rmax, kc - c0);
+          Q(Ur + size_t(c0) * N, W, r);
+          DC_HIP(hipMemcpyAsync(MUo + size_t(c0) * N, W, size_t(r) * N * sizeof(Z),
+                                hipMemcpyDeviceToDevice, st));
+        }
+        mur = MUo;
+      }
+      launch_combine(p, k0 ? mur : nullptr, k0, Zb, s, N, cud, kk, MUn, 0, st);
+    }
+    const size_t vb = N * sizeof(Z) * size_t(kk);
+    var.U.ensure(vb);
+    var.C.ensure(vb);
+    if (mu) var.MU.ensure(vb);
+    DC_HIP(hipMemcpyAsync(var.C.p, Cn, vb, hipMemcpyDeviceToDevice, st));
+    DC_HIP(hipMemcpyAsync(var.U.p, Un, vb, hipMemcpyDeviceToDevice, st));
+    if (mu) DC_HIP(hipMemcpyAsync(var.MU.p, MUn, vb, hipMemcpyDeviceToDevice, st));
+    var.mu_ok = mu;
+    var.kcur = kk;
+    var.k_built = o.k;
+    var.recycle_version = op.version;
+    var.updates = build ? 1 : var.updates + 1;
+    kc = kk;
+    Cr = var.C.as<Z>();
+    Ur = var.U.as<Z>();
+    MUr = mu ? var.MU.as<Z>() : nullptr;
+    const std::vector<double> u2 = colnorms(Ur, kc);
+    var.unorm.assign(size_t(kc), 1.0);
+    for (int i = 0; i < kc; ++i) var.unorm[size_t(i)] = std::sqrt(std::max(u2[size_t(i)], 0.0));
+    ++refreshes;
+    return true;
   }
 
   // Solve D X = B for R columns (this precision) to relative tolerances tol,
@@ -679,8 +701,7 @@ struct BlockGmres {
       const int nr = int(act.size());
       if (kc) {   // new residuals with a recycle space: x += q(A) U C^H r; r -= C C^H r
         write_mat(Bd, tn(Cr, kc, V, nr));
-        gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, kc, -1.0, Cr, int(N), Bd, kc,
-             1.0, V, int(N));
+        update(Cr, kc, Bd, V, nr, -1.0, 1.0);
         std::vector<Z*> xc(nr);
         for (int a = 0; a < nr; ++a) xc[a] = X + size_t(act[a]) * N;
         add_recycled(Bd, nr, xc);
@@ -707,8 +728,7 @@ struct BlockGmres {
       const int s = c.steps * nb;
       if (s == 0) break;
       write_mat(Yd, c.Y);
-      gemm(rocblas_operation_none, rocblas_operation_none, int(N), nr, s, 1.0,
-           has_poly() ? Zb : V, int(N), Yd, s, 0.0, U, int(N));
+      update(has_poly() ? Zb : V, s, Yd, U, nr, 1.0, 0.0);
       std::vector<Z*> xc(nr);
       for (int a = 0; a < nr; ++a) {
         xc[a] = X + size_t(act[a]) * N;
@@ -727,6 +747,7 @@ struct BlockGmres {
         write_mat(Bd, By);
         add_recycled(Bd, nr, xc);
       }
+      recycle(c, nb);
     }
   }
 };
@@ -736,8 +757,8 @@ struct BlockGmres {
 int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, const double* tol,
                    int use_x0, hipStream_t st, SolveStats* stats) {
   if (op.caller_ws())
-    throw BadState("block GMRES allocates device memory (rocBLAS): not available on a handle "
-                   "built on caller workspaces");
+    throw BadState("block GMRES sizes its device buffers per call (the workspace query does "
+                   "not cover them): not available on a handle built on caller workspaces");
   if (R < 1) throw InvalidArg("n_rhs must be >= 1");
   if (!b || !x || !tol) throw InvalidArg("null pointer");
   if (o.schur) throw InvalidArg("the block solver works on the full lattice (schur = 0)");
@@ -789,6 +810,7 @@ int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, co
     BlockGmres<double> K(op, var, o, P64, R, st);
     K.solve(rhs, sol, R, tl, o.max_cycles, stt, rel);
     applies += K.applies;
+    for (SolveStats& x : stt) x.refresh_failed += K.refresh_failed;
   } else {
     // FP64 iterative refinement: r = rhs - D sol in FP64, the block solve of
     // D e = r in the reduced precision to inner_tol, sol += e
@@ -856,6 +878,7 @@ int op_solve_block(Op& op, const SolveOpts& o, int R, const void* b, void* x, co
       act = act2;
     }
     applies += K.applies;
+    for (SolveStats& x : stt) x.refresh_failed += K.refresh_failed;
   }
   applies += K64.applies;
   if (use_x0) {

@@ -4,6 +4,7 @@
 
 #include <hip/hip_ext.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <tuple>
@@ -1762,6 +1763,7 @@ __global__ __launch_bounds__(256) void k_multiaxpy_flat(const cx<VR>* w, cx<VR>*
 }
 
 constexpr int kCombR = 16;  // outputs per pass of the combine kernel
+constexpr int kCombMfmaMin = 16;   // from this many outputs on: the MFMA block update
 
 template <typename VR>
 __global__ __launch_bounds__(256) void k_combine(const cx<VR>* __restrict__ b0, int q0,
@@ -1977,6 +1979,251 @@ __global__ void k_gaussian(z64* out, size_t N, uint64_t seed, uint32_t stream_id
     double sn, cs;
     sincos(6.283185307179586477 * u2, &sn, &cs);
     out[i] = mk(r * cs, r * sn);
+  }
+}
+
+// ------------------------------------------------------------------ block products
+// The tall-skinny complex products of block GMRES (one Krylov space shared by
+// many right-hand sides) and of the recycle-space construction and refresh:
+// Gram matrices A^H B of two blocks of vectors and block updates
+// C = beta C + alpha A S with a small coefficient matrix S.  Both stage
+// 64-wide panels in LDS as real and imaginary planes with a padded stride and
+// multiply on 16x16x4 MFMA tiles with three real products per complex one;
+// wave w owns output row tile w and all four column tiles of a 64 x 64 output
+// tile.  VS is the storage type of the vectors, VC the type the products are
+// formed and accumulated in (FP32 vectors may be combined in FP64).
+constexpr int kBpT = 64;          // output tile edge
+constexpr int kBpK = 32;          // inner-dimension rows staged per LDS round
+constexpr int kBpLD = kBpK + 1;   // padded plane stride
+constexpr int kGramMaxParts = 256;
+
+// part[c] = A_c^H B_c for row chunk c = blockIdx.x (rows [c L, min(c L + L, N))),
+// output tile (blockIdx.y % tq, blockIdx.y / tq) of the qa x rb result, tq =
+// ceil(qa / 64); part layout [chunk][j qa + i].  A: qa vectors, B: rb vectors,
+// each N long with stride N.
+template <typename VS, typename VC>
+__global__ __launch_bounds__(256) void k_block_gram(const cx<VS>* __restrict__ A, int qa,
+                                                     const cx<VS>* __restrict__ B, int rb,
+                                                     size_t N, size_t L,
+                                                     cx<VC>* __restrict__ part) {
+  using acc_t = typename Mfma<VC>::acc_t;
+  __shared__ VC Ar[kBpT * kBpLD], Ai[kBpT * kBpLD], Br[kBpT * kBpLD], Bi[kBpT * kBpLD];
+  const int tq = (qa + kBpT - 1) / kBpT;
+  const int i0 = int(blockIdx.y % unsigned(tq)) * kBpT, j0 = int(blockIdx.y / unsigned(tq)) * kBpT;
+  const int ni = min(kBpT, qa - i0), nj = min(kBpT, rb - j0);
+  const size_t r0 = size_t(blockIdx.x) * L, r1 = min(N, r0 + L);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int nct = (nj + 15) / 16;    // column tiles with at least one column
+  acc_t prr[4], pii[4], pss[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    prr[t] = acc_t{0, 0, 0, 0};
+    pii[t] = acc_t{0, 0, 0, 0};
+    pss[t] = acc_t{0, 0, 0, 0};
+  }
+  // panels: column c of the tile, rows k0 .. k0 + 31 (consecutive threads
+  // read consecutive rows of one vector); thread t holds elements
+  // u = t + 256 e, e < 8, of each panel in registers: those of the next round
+  // are loaded while the current one multiplies
+  constexpr int EPT = kBpT * kBpK / 256;
+  cx<VS> ra[EPT], rb_[EPT];
+  auto fetch = [&](size_t k0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int u = int(threadIdx.x) + 256 * e;
+      const int c = u / kBpK, r = u % kBpK;
+      const size_t row = k0 + size_t(r);
+      ra[e] = mk(VS(0), VS(0));
+      rb_[e] = mk(VS(0), VS(0));
+      if (row < r1) {
+        if (c < ni) ra[e] = A[size_t(i0 + c) * N + row];
+        if (c < nj) rb_[e] = B[size_t(j0 + c) * N + row];
+      }
+    }
+  };
+  if (r0 < r1) fetch(r0);
+  for (size_t k0 = r0; k0 < r1; k0 += kBpK) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {   // A is conjugated here
+      const int u = int(threadIdx.x) + 256 * e;
+      const int c = u / kBpK, r = u % kBpK;
+      Ar[c * kBpLD + r] = VC(ra[e].re);
+      Ai[c * kBpLD + r] = -VC(ra[e].im);
+      Br[c * kBpLD + r] = VC(rb_[e].re);
+      Bi[c * kBpLD + r] = VC(rb_[e].im);
+    }
+    __syncthreads();
+    if (k0 + kBpK < r1) fetch(k0 + kBpK);
+    if (wave * 16 < ni) {
+#pragma unroll 2
+      for (int kk = 0; kk < kBpK; kk += 4) {
+        const int ao = (wave * 16 + l16) * kBpLD + kk + lk;
+        const VC a_r = Ar[ao], a_i = Ai[ao];
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+          if (ct < nct) {
+            const int bo = (ct * 16 + l16) * kBpLD + kk + lk;
+            const VC b_r = Br[bo], b_i = Bi[bo];
+            prr[ct] = Mfma<VC>::mma(a_r, b_r, prr[ct]);
+            pii[ct] = Mfma<VC>::mma(a_i, b_i, pii[ct]);
+            pss[ct] = Mfma<VC>::mma(a_r + a_i, b_r + b_i, pss[ct]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  const size_t qr = size_t(qa) * size_t(rb);
+  cx<VC>* out = part + size_t(blockIdx.x) * qr;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    const int j = ct * 16 + l16;
+    if (ct >= nct || j >= nj) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = wave * 16 + Mfma<VC>::row(lk, q);
+      if (i < ni)
+        out[size_t(j0 + j) * qa + (i0 + i)] =
+            mk(VC(prr[ct][q] - pii[ct][q]), VC(pss[ct][q] - prr[ct][q] - pii[ct][q]));
+    }
+  }
+}
+
+// out[e] = sum over the P chunks of part[c][e] (FP64, chunk order fixed)
+template <typename VC>
+__global__ void k_block_gram_sum(const cx<VC>* __restrict__ part, int P, size_t qr,
+                                 z64* __restrict__ out) {
+  const size_t e = size_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (e >= qr) return;
+  double re = 0.0, im = 0.0;
+  for (int c = 0; c < P; ++c) {
+    const cx<VC> z = part[size_t(c) * qr + e];
+    re += double(z.re);
+    im += double(z.im);
+  }
+  out[e] = mk(re, im);
+}
+
+// C[:, j] = beta C[:, j] + alpha sum_i A_i S[i + j ldS] for j < r, over the
+// k = q0 + q1 vectors A_i = b0 + i N (i < q0), b1 + (i - q0) N (after); C has r
+// vectors (each N long, stride N); S is column-major in the product type.
+// Workgroup t: column tile t % nct (nct = ceil(r / 64)), rows 64 (t / nct)
+// .. + 63, so the workgroups that share a row panel of the A_i run together.
+// C must not overlap the A_i.
+template <typename VS, typename VC>
+__global__ __launch_bounds__(256) void k_block_update(const cx<VS>* __restrict__ b0, int q0,
+                                                       const cx<VS>* __restrict__ b1, int q1,
+                                                       const cx<VC>* __restrict__ S, int ldS,
+                                                       cx<VS>* C, int r, size_t N, z64 alpha,
+                                                       z64 beta) {
+  using acc_t = typename Mfma<VC>::acc_t;
+  // four planes while multiplying ([row][kk] of A, [col][kk] of S); the
+  // 64 x 64 output planes ([col][row], stride 65) reuse them afterwards
+  constexpr int PL = kBpT * kBpLD;
+  __shared__ VC sm[4 * PL];
+  static_assert(2 * kBpT * (kBpT + 1) <= 4 * PL, "output planes fit");
+  VC* Ar = sm;
+  VC* Ai = sm + PL;
+  VC* Sr = sm + 2 * PL;
+  VC* Si = sm + 3 * PL;
+  const int k = q0 + q1;
+  const int nctile = (r + kBpT - 1) / kBpT;
+  const size_t row0 = size_t(blockIdx.x / unsigned(nctile)) * kBpT;
+  const int j0 = int(blockIdx.x % unsigned(nctile)) * kBpT;
+  const int nj = min(kBpT, r - j0);
+  const int nrow = int(min(size_t(kBpT), N - row0));
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int nct = (nj + 15) / 16;
+  acc_t prr[4], pii[4], pss[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    prr[t] = acc_t{0, 0, 0, 0};
+    pii[t] = acc_t{0, 0, 0, 0};
+    pss[t] = acc_t{0, 0, 0, 0};
+  }
+  // A panel: vector k0 + kk, rows row0 .. row0 + 63 (consecutive threads,
+  // consecutive rows); S panel: column j, rows k0 .. k0 + 31.  Thread t holds
+  // elements u = t + 256 e of each in registers; the next round's are loaded
+  // while the current one multiplies.
+  constexpr int EPT = kBpT * kBpK / 256;
+  cx<VS> ra[EPT];
+  cx<VC> rs[EPT];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int u = int(threadIdx.x) + 256 * e;
+      const int kk = u / kBpT, rr = u % kBpT;
+      const int i = k0 + kk;
+      ra[e] = mk(VS(0), VS(0));
+      if (i < k && rr < nrow)
+        ra[e] = (i < q0 ? b0 + size_t(i) * N : b1 + size_t(i - q0) * N)[row0 + rr];
+      const int j = u / kBpK, kq = u % kBpK;
+      rs[e] = mk(VC(0), VC(0));
+      if (j < nj && k0 + kq < k) rs[e] = S[size_t(j0 + j) * ldS + k0 + kq];
+    }
+  };
+  if (k > 0) fetch(0);
+  for (int k0 = 0; k0 < k; k0 += kBpK) {
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+      const int u = int(threadIdx.x) + 256 * e;
+      const int kk = u / kBpT, rr = u % kBpT;
+      Ar[rr * kBpLD + kk] = VC(ra[e].re);
+      Ai[rr * kBpLD + kk] = VC(ra[e].im);
+      const int j = u / kBpK, kq = u % kBpK;
+      Sr[j * kBpLD + kq] = rs[e].re;
+      Si[j * kBpLD + kq] = rs[e].im;
+    }
+    __syncthreads();
+    if (k0 + kBpK < k) fetch(k0 + kBpK);
+#pragma unroll 2
+    for (int kk = 0; kk < kBpK; kk += 4) {
+      const int ao = (wave * 16 + l16) * kBpLD + kk + lk;
+      const VC a_r = Ar[ao], a_i = Ai[ao];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        if (ct < nct) {
+          const int bo = (ct * 16 + l16) * kBpLD + kk + lk;
+          const VC b_r = Sr[bo], b_i = Si[bo];
+          prr[ct] = Mfma<VC>::mma(a_r, b_r, prr[ct]);
+          pii[ct] = Mfma<VC>::mma(a_i, b_i, pii[ct]);
+          pss[ct] = Mfma<VC>::mma(a_r + a_i, b_r + b_i, pss[ct]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // accumulators -> output planes [col][row] -> coalesced column stores
+  constexpr int OL = kBpT + 1;
+  VC* Or = sm;
+  VC* Oi = sm + kBpT * OL;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) {
+    if (ct >= nct) continue;
+    const int col = ct * 16 + l16;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int row = wave * 16 + Mfma<VC>::row(lk, q);
+      Or[col * OL + row] = prr[ct][q] - pii[ct][q];
+      Oi[col * OL + row] = pss[ct][q] - prr[ct][q] - pii[ct][q];
+    }
+  }
+  __syncthreads();
+  const bool keep = beta.re != 0.0 || beta.im != 0.0;
+  for (int u = threadIdx.x; u < kBpT * kBpT; u += 256) {
+    const int col = u / kBpT, rr = u % kBpT;
+    if (col >= nj || rr >= nrow) continue;
+    const double pr = double(Or[col * OL + rr]), pi = double(Oi[col * OL + rr]);
+    double yr = alpha.re * pr - alpha.im * pi, yi = alpha.re * pi + alpha.im * pr;
+    cx<VS>* c = C + size_t(j0 + col) * N + row0 + rr;
+    if (keep) {
+      const cx<VS> z = *c;
+      yr += beta.re * double(z.re) - beta.im * double(z.im);
+      yi += beta.re * double(z.im) + beta.im * double(z.re);
+    }
+    *c = mk(VS(yr), VS(yi));
   }
 }
 
@@ -2760,6 +3007,67 @@ void launch_multiaxpy_scaled(Prec p, void* w, const void* b0, int q0, const void
   multiaxpy_any(p, w, b0, q0, b1, q1, N, coef, 0, none, nullptr, scale, jdone, j, st);
 }
 
+int block_gram_parts(size_t N, int qa, int rb, size_t part_cap) {
+  // enough chunks that chunks x output tiles fill the chip twice over, each
+  // chunk at least 8 LDS rounds long, within the partials' capacity
+  const size_t tiles = size_t((qa + kBpT - 1) / kBpT) * size_t((rb + kBpT - 1) / kBpT);
+  size_t P = (2048 + tiles - 1) / std::max<size_t>(tiles, 1);
+  P = std::min<size_t>(P, kGramMaxParts);
+  P = std::min<size_t>(P, std::max<size_t>(N / (8 * kBpK), 1));
+  if (part_cap) P = std::min<size_t>(P, part_cap / std::max<size_t>(size_t(qa) * size_t(rb), 1));
+  return int(std::max<size_t>(P, 1));
+}
+
+template <typename VS, typename VC>
+static void block_gram_t(const void* A, int qa, const void* B, int rb, size_t N, size_t part_cap,
+                         void* part, z64* out, hipStream_t st) {
+  const int P0 = block_gram_parts(N, qa, rb, part_cap);
+  size_t L = (N + size_t(P0) - 1) / size_t(P0);
+  L = (L + kBpK - 1) / kBpK * kBpK;
+  const int P = int((N + L - 1) / L);
+  const unsigned tiles = unsigned((qa + kBpT - 1) / kBpT) * unsigned((rb + kBpT - 1) / kBpT);
+  const size_t qr = size_t(qa) * size_t(rb);
+  hipLaunchKernelGGL((k_block_gram<VS, VC>), dim3(unsigned(P), tiles), dim3(256), 0, st,
+                     static_cast<const cx<VS>*>(A), qa, static_cast<const cx<VS>*>(B), rb, N, L,
+                     static_cast<cx<VC>*>(part));
+  DC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_block_gram_sum<VC>, dim3(unsigned((qr + 255) / 256)), dim3(256), 0, st,
+                     static_cast<const cx<VC>*>(part), P, qr, out);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_block_gram(Prec p, const void* A, int qa, const void* B, int rb, size_t N, void* part,
+                       z64* out, hipStream_t st, bool fp64_products, size_t part_cap) {
+  if (qa <= 0 || rb <= 0) return;
+  if (p == P64)
+    block_gram_t<double, double>(A, qa, B, rb, N, part_cap, part, out, st);
+  else if (fp64_products)
+    block_gram_t<float, double>(A, qa, B, rb, N, part_cap, part, out, st);
+  else
+    block_gram_t<float, float>(A, qa, B, rb, N, part_cap, part, out, st);
+}
+
+template <typename VS, typename VC>
+static void block_update_t(const void* b0, int q0, const void* b1, int q1, const void* S, int ldS,
+                           void* C, int r, size_t N, z64 alpha, z64 beta, hipStream_t st) {
+  const size_t tiles = ((N + kBpT - 1) / kBpT) * size_t((r + kBpT - 1) / kBpT);
+  if (tiles > 0xffffffffull) throw InvalidArg("block update too large");
+  hipLaunchKernelGGL((k_block_update<VS, VC>), dim3(unsigned(tiles)), dim3(256), 0, st,
+                     static_cast<const cx<VS>*>(b0), q0, static_cast<const cx<VS>*>(b1), q1,
+                     static_cast<const cx<VC>*>(S), ldS, static_cast<cx<VS>*>(C), r, N, alpha,
+                     beta);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_block_update(Prec p, const void* A, int k, const void* S, void* C, int r, size_t N,
+                         z64 alpha, z64 beta, hipStream_t st) {
+  if (r <= 0 || N == 0) return;
+  if (p == P64)
+    block_update_t<double, double>(A, k, nullptr, 0, S, k, C, r, N, alpha, beta, st);
+  else
+    block_update_t<float, float>(A, k, nullptr, 0, S, k, C, r, N, alpha, beta, st);
+}
+
 void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
                     const double* coef, int R, void* out, int accumulate, hipStream_t st) {
   if (R <= 0) return;
@@ -2781,6 +3089,16 @@ void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size
                          static_cast<const z32*>(b1), q1, N, coef, static_cast<z32*>(out),
                          accumulate);
     DC_HIP(hipGetLastError());
+    return;
+  }
+  if (R >= kCombMfmaMin && q0 + q1 > 0) {
+    // many outputs: the MFMA block update with FP64 products and sums (the
+    // coefficients are FP64), out = sum + (accumulate ? out : 0)
+    const z64 one = mk(1.0, 0.0), beta = mk(accumulate ? 1.0 : 0.0, 0.0);
+    if (p == P64)
+      block_update_t<double, double>(b0, q0, b1, q1, coef, q0 + q1, out, R, N, one, beta, st);
+    else
+      block_update_t<float, double>(b0, q0, b1, q1, coef, q0 + q1, out, R, N, one, beta, st);
     return;
   }
   const int gy = (R + kCombR - 1) / kCombR;

@@ -165,9 +165,28 @@ void launch_multiaxpy_scaled(Prec p, void* w, const void* b0, int q0, const void
                              size_t N, const double* coef, const double* scale, const int* jdone,
                              int j, hipStream_t st);
 // out_r (= or +=) sum_q coef[r*Q + q] basis_q for r < R, Q = q0 + q1; coef
-// device complex; outputs are R vectors with stride N.
+// device complex; outputs are R vectors with stride N, not overlapping the
+// basis.  Products and sums in FP64 (16 or more outputs: on MFMA tiles).
 void launch_combine(Prec p, const void* b0, int q0, const void* b1, int q1, size_t N,
                     const double* coef, int R, void* out, int accumulate, hipStream_t st);
+// ---------------------------------------------------------------- block products
+// Number of row chunks the Gram product of qa and rb vectors of length N is
+// split into (at most 256; at most part_cap / (qa rb) when part_cap > 0).
+int block_gram_parts(size_t N, int qa, int rb, size_t part_cap = 0);
+// out = A^H B (qa x rb, column-major, FP64 complex; the chunks summed in FP64)
+// for qa vectors A and rb vectors B of N entries each (stride N) in the
+// precision's vector type, MFMA based.  The products are formed in FP64 for
+// FP64 vectors, and for FP32 vectors when fp64_products is set, else in FP32.
+// part: device scratch of block_gram_parts(N, qa, rb, part_cap) * qa * rb
+// complex values of the product type.
+void launch_block_gram(Prec p, const void* A, int qa, const void* B, int rb, size_t N, void* part,
+                       z64* out, hipStream_t st, bool fp64_products = false,
+                       size_t part_cap = 0);
+// C = beta C + alpha A S: A k vectors, C r vectors (N entries each, stride N),
+// S k x r column-major (leading dimension k) in the vector type; C must not
+// overlap A.  MFMA based, products in the vector type.
+void launch_block_update(Prec p, const void* A, int k, const void* S, void* C, int r, size_t N,
+                         z64 alpha, z64 beta, hipStream_t st);
 // out = in * (*scale_dev) (scale real, device) or in * s (if scale_dev null).
 void launch_scale(Prec p, const void* in, void* out, size_t N, const double* scale_dev,
                   double s, const int* done, hipStream_t st);

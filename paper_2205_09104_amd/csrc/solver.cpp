@@ -304,6 +304,16 @@ ApplyProfile::~ApplyProfile() {
   for (hipEvent_t e : owned) (void)hipEventDestroy(e);
 }
 
+void GraphCache::add(const std::vector<uintptr_t>& key, hipGraph_t graph, hipGraphExec_t exec) {
+  if (entries.size() >= kMaxEntries) {   // drop the oldest recording
+    Entry& e = entries.front();
+    if (e.exec) (void)hipGraphExecDestroy(e.exec);
+    if (e.graph) (void)hipGraphDestroy(e.graph);
+    entries.erase(entries.begin());
+  }
+  entries.push_back({key, graph, exec});
+}
+
 hipGraphExec_t GraphCache::find(const std::vector<uintptr_t>& key) const {
   for (const Entry& e : entries)
     if (e.key == key) return e.exec;
@@ -703,6 +713,14 @@ static std::vector<cd> gcrodr_lstsq(const Mat& Hbar, const Mat& Bk,
 // Device workspace of one Krylov solver instance: the basis (m + 2 vectors,
 // with a polynomial also the z_j), recycle refresh temporaries, 8 work
 // vectors, and the small arrays (coefficients, Hessenberg, B_k, Givens).
+// Device bytes of the recycle refresh's Gram products for kk recycled vectors
+// and up to mr Arnoldi vectors: C^H U, V^H U (FP64 complex) and the chunk
+// partials of either (at most kRefreshGramParts chunks of kk x mr).
+constexpr size_t kRefreshGramParts = 32;
+static size_t refresh_gram_bytes(int kk, int mr) {
+  return (size_t(kk) * kk + size_t(kk) * mr * (1 + kRefreshGramParts)) * sizeof(z64);
+}
+
 struct KrylovSizes {
   int kmax, ldh, nbasis, ktmp, nz, kz;
   size_t ws_bytes, sm_bytes;
@@ -1139,7 +1157,7 @@ struct Krylov {
         ad.target_dev = nullptr;
         return false;
       }
-      gc.entries.push_back({key, graph, exec});
+      gc.add(key, graph, exec);
       ++gc.captured;
     }
     DC_HIP(hipGraphLaunch(exec, st));
@@ -1493,18 +1511,26 @@ struct Krylov {
     const int nr = kk + jd + 1, nc = kk + jd;
     // What^H Vhat = [[C^H U D_k, 0], [V^H U D_k, I]]
     Mat WV(nr, nc);
-    // sized for the longest cycle (nr <= m + 1), so later refreshes reuse it
-    op.wvbuf.ensure(size_t(kk) * std::max(nr, o.m + 1) * 2 * sizeof(double));
-    double* wv = op.wvbuf.as<double>();
-    for (int i = 0; i < kk; ++i)   // all columns queued, then one read
-      launch_multidot(p, Cv(), kk, V(0), jd + 1, N, Uv() + size_t(i) * N, 0, op.red(),
-                      wv + size_t(i) * nr * 2, nullptr, st);
-    std::vector<double> h(size_t(kk) * nr * 2);
-    op.hs.read(h.data(), wv, h.size() * sizeof(double), st);
+    // C^H U and V_{jd+1}^H U as two MFMA Gram products formed in FP64; the
+    // buffer is sized for the longest cycle (jd + 1 <= m + 1), so later
+    // refreshes reuse it: both results, then the chunk partials
+    const size_t mr = size_t(std::max(nr - kk, o.m + 1));
+    op.wvbuf.ensure(refresh_gram_bytes(kk, int(mr)));
+    z64* sc = op.wvbuf.as<z64>();
+    z64* sv = sc + size_t(kk) * kk;
+    z64* part = sv + size_t(kk) * mr;
+    const size_t cap = kRefreshGramParts * size_t(kk) * mr;
+    launch_block_gram(p, Cv(), kk, Uv(), kk, N, part, sc, st, true, cap);
+    launch_block_gram(p, V(0), jd + 1, Uv(), kk, N, part, sv, st, true, cap);
+    std::vector<z64> hc(size_t(kk) * kk), hv(size_t(kk) * (jd + 1));
+    op.hs.read(hc.data(), sc, hc.size() * sizeof(z64), st);
+    op.hs.read(hv.data(), sv, hv.size() * sizeof(z64), st);
     op.hs.wait(st);
     for (int i = 0; i < kk; ++i)
-      for (int r = 0; r < nr; ++r)
-        WV(r, i) = cd(h[(size_t(i) * nr + r) * 2], h[(size_t(i) * nr + r) * 2 + 1]) / var.unorm[i];
+      for (int r = 0; r < nr; ++r) {
+        const z64 z = r < kk ? hc[size_t(i) * kk + r] : hv[size_t(i) * (jd + 1) + (r - kk)];
+        WV(r, i) = cd(z.re, z.im) / var.unorm[i];
+      }
     for (int jj = 0; jj < jd; ++jj) WV(kk + jj, kk + jj) = 1.0;
     const Mat GH = adjoint(G);
     Mat Bm = matmul(GH, WV);
@@ -2126,6 +2152,126 @@ struct Batch {
     return rn;
   }
 
+  // The Arnoldi steps of one lockstep cycle: per step one multi-apply chain
+  // over every active column of every operator, then each column's
+  // orthogonalisation (the device stops a column's steps once its estimate
+  // meets the target).
+  void enqueue_steps(int steps, const std::vector<std::vector<double>>& target) {
+    for (int j = 0; j < steps; ++j) {
+      Ahat(T_NFIX + j, T_NFIX + j + 1);
+      for (size_t gi = 0; gi < g.size(); ++gi) {
+        Group& gr = g[gi];
+        for (size_t a = 0; a < gr.act.size(); ++a)
+          gr.K[gr.act[a]]->orth_step(j, gr.var->kcur, steps, target[gi][a]);
+      }
+    }
+  }
+
+  // Whether every multi-apply of the active set already has its tile chosen
+  // (tuning times launches and cannot run inside a graph recording).
+  bool tiles_tuned() const {
+    int rmax = 0, cnt = 0, n = 0;
+    unsigned sites = 0;
+    for (const Group& gr : g) {
+      if (gr.act.empty()) continue;
+      rmax = std::max(rmax, int(gr.act.size()));
+      sites += unsigned(gr.op->V);
+      n = gr.op->n;
+      if (++cnt == kMaxMultiOps) {
+        if (!multi_tile_for(p, n, rmax, sites)) return false;
+        rmax = 0;
+        sites = 0;
+        cnt = 0;
+      }
+    }
+    return cnt == 0 || multi_tile_for(p, n, rmax, sites) != 0;
+  }
+
+  // The cycle's steps recorded once per active set and shape as a HIP graph
+  // and replayed as one launch per cycle (the batching configuration's one
+  // launch for a mixed batch): every kernel argument depends only on the key
+  // below; each column's stopping target is read from device memory.
+  bool graph_steps(int steps, const std::vector<std::vector<double>>& target) {
+    Op& op0 = *g[0].op;
+    GraphCache& gc = op0.graphs;
+    if (gc.broken || op0.prof.on || !tiles_tuned()) return false;
+    std::vector<uintptr_t> key = {0xBA7C4u, uintptr_t(tab.p), uintptr_t(steps), uintptr_t(p),
+                                  uintptr_t(ldh), uintptr_t(g.size())};
+    for (size_t gi = 0; gi < g.size(); ++gi) {
+      Group& gr = g[gi];
+      key.insert(key.end(), {uintptr_t(gr.op), uintptr_t(gr.var), uintptr_t(gr.var->poly_serial),
+                             uintptr_t(gr.op->version), uintptr_t(gr.var->kcur),
+                             uintptr_t(gr.var->C.p), uintptr_t(gr.act.size())});
+      for (size_t a = 0; a < gr.act.size(); ++a) {
+        Krylov<VR>& k = *gr.K[gr.act[a]];
+        key.insert(key.end(), {uintptr_t(gr.act[a]), uintptr_t(k.ws.p), uintptr_t(k.sm.p),
+                               uintptr_t(k.bjinv)});
+        double* tdev = k.nrm + 1;   // free slot of the column's small area
+        op0.hs.write(tdev, &target[gi][a], sizeof(double), st);
+        k.ad.target_dev = tdev;
+      }
+    }
+    auto clear_targets = [&]() {
+      for (Group& gr : g)
+        for (int c : gr.act) gr.K[c]->ad.target_dev = nullptr;
+    };
+    hipGraphExec_t exec = gc.find(key);
+    const long per_step = has_poly(*g[0].var) ? long(g[0].var->theta.size()) : 1L;
+    if (!exec) {
+      if (!gc.cap && hipStreamCreateWithFlags(&gc.cap, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        gc.cap = nullptr;
+        gc.broken = true;
+        clear_targets();
+        return false;
+      }
+      if (hipStreamBeginCapture(gc.cap, hipStreamCaptureModeRelaxed) != hipSuccess) {
+        (void)hipGetLastError();
+        gc.broken = true;
+        clear_targets();
+        return false;
+      }
+      // every launch of the steps goes to the capture stream while recording
+      const hipStream_t saved = st;
+      const long mv_saved = matvecs;   // recording runs nothing
+      st = gc.cap;
+      for (Group& gr : g)
+        for (int c : gr.act) gr.K[c]->st = gc.cap;
+      bool ok = true;
+      try {
+        enqueue_steps(steps, target);
+      } catch (const std::exception&) {
+        ok = false;
+      }
+      st = saved;
+      for (Group& gr : g)
+        for (int c : gr.act) gr.K[c]->st = saved;
+      matvecs = mv_saved;
+      hipGraph_t graph = nullptr;
+      if (hipStreamEndCapture(gc.cap, &graph) != hipSuccess || !ok || !graph) {
+        (void)hipGetLastError();
+        if (graph) (void)hipGraphDestroy(graph);
+        gc.broken = true;
+        clear_targets();
+        return false;
+      }
+      if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipGraphDestroy(graph);
+        gc.broken = true;
+        clear_targets();
+        return false;
+      }
+      gc.add(key, graph, exec);
+      ++gc.captured;
+    }
+    DC_HIP(hipGraphLaunch(exec, st));
+    ++gc.launched;
+    matvecs += long(steps) * per_step;   // the applications the replayed steps make
+    clear_targets();
+    return true;
+  }
+
   // Solve D_g x_{g,r} = b_{g,r} to tolerances tol[g][r]; stt, relres likewise indexed.
   void solve(bool use_x0, int max_cycles, const std::vector<std::vector<double>>& tol,
              std::vector<std::vector<SolveStats>>& stt, std::vector<std::vector<double>>& relres) {
@@ -2226,14 +2372,7 @@ struct Batch {
       int steps = ldh - 2;
       for (const Group& gr : g)
         if (!gr.act.empty()) steps = std::min(steps, steps_req - gr.var->kcur);
-      for (int j = 0; j < steps; ++j) {
-        Ahat(T_NFIX + j, T_NFIX + j + 1);
-        for (size_t gi = 0; gi < g.size(); ++gi) {
-          Group& gr = g[gi];
-          for (size_t a = 0; a < gr.act.size(); ++a)
-            gr.K[gr.act[a]]->orth_step(j, gr.var->kcur, steps, target[gi][a]);
-        }
-      }
+      if (!(o.graphs && graph_steps(steps, target))) enqueue_steps(steps, target);
       // per right-hand side: least squares and the update of x
       for (size_t gi = 0; gi < g.size(); ++gi) {
         Group& gr = g[gi];
@@ -2582,7 +2721,7 @@ void workspace_bytes(const int dims[4], int n_tv, int store, double mu, bool hos
     const KrylovSizes ko = krylov_sizes(Nsys, z64b, 0, 0, o.m_outer, true);
     run += size_t(nsign) * (R(ko.ws_bytes) + R(ko.sm_bytes)) + R(size_t(o.m_outer) * Nsys * z64b);
   }
-  if (o.k > 0) run += R(size_t(o.k) * (o.m + 1) * 2 * sizeof(double));
+  if (o.k > 0) run += R(refresh_gram_bytes(o.k, o.m + 1));
   if (o.d > 1 && !o.v0) run += R(Nsys * z64b);                     // polynomial start vector
   if (max_rhs > 0) run += R(2 * size_t(max_rhs) * sizeof(void*)); // multi-apply pointer table
   const size_t slack = 64 * Arena::kArenaAlign;

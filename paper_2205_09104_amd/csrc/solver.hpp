@@ -194,11 +194,13 @@ struct GraphCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
   };
+  static constexpr size_t kMaxEntries = 64;   // recordings kept (oldest dropped first)
   hipStream_t cap = nullptr;
   std::vector<Entry> entries;
   bool broken = false;
   long captured = 0, launched = 0;
   hipGraphExec_t find(const std::vector<uintptr_t>& key) const;
+  void add(const std::vector<uintptr_t>& key, hipGraph_t graph, hipGraphExec_t exec);
   ~GraphCache();
 };
 
@@ -245,13 +247,12 @@ struct Op {
   DevBuf esite, osite;
   DevBuf ts64, ts32;
   DevBuf rbe, rbo, rxe, rto;         // FP64 half vectors of the reduced solve's wrapper
-  DevBuf wvbuf;                      // recycle refresh: What^H U, one column per recycled vector
-  // block GMRES workspaces (FP64 and reduced-precision vectors) and the
-  // rocBLAS handle of its tall-skinny GEMMs (created on first use)
+  DevBuf wvbuf;                      // recycle refresh: What^H U and its Gram partials
+  // block GMRES workspaces (FP64 and reduced-precision vectors)
   struct BlockWS {
     DevBuf V, Z, W, T1, TA, PROD, U, small, tab, R, X, Bc, part, X0, E0, E;
+    DevBuf rcoef, rtmp;   // recycle build / refresh: coefficients, new U, C, q(A) U
   } bk64, bk32;
-  std::shared_ptr<void> blas;
   void* tmp_s(Prec p);
   DevBuf redpart;           // reducer scratch
   DevBuf scal;              // a few device doubles

@@ -8,7 +8,7 @@ import synth
 from oracle import operator as dop
 from oracle.block import block_gmres
 
-from .helpers import log, make_pair, oracle_relres, rel, workload_pair
+from .helpers import log, make_pair, oracle_relres, rand_vec, rel, workload_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -210,3 +210,122 @@ def test_refinement_stops_on_stagnation(c1):
         assert s["stagnated"] == 1 or s["outer_iters"] >= 200
     assert any(s["stagnated"] == 1 for s in st)
     assert max(s["outer_iters"] for s in st) < 200
+
+
+@pytest.mark.parametrize("dims,ntv,R,m", [((3, 3, 2, 2), 7, 20, 4),
+                                          ((4, 4, 2, 4), 6, 40, 3),
+                                          ((2, 2, 2, 2), 12, 70, 1)])
+def test_wide_block_cycle_matches_oracle(dims, ntv, R, m):
+    """Blocks of more than 16 columns take the MFMA Gram kernel: one cycle
+    with ragged row chunks (N = 504, not a multiple of 32 or 64), ragged
+    output tiles (20 and 40 columns, Krylov blocks of 20..120 vectors) and
+    more than one 64-column tile (70 columns) gives every column the oracle's
+    least-squares minimiser."""
+    from paper_2205_09104_amd import Opts
+    log("wide block cycle", dims, ntv, R, m)
+    gop, oop = make_pair(dims, ntv, 3.0, mu=0.1)
+    N = oop.V * oop.n
+    B = _rhs(oop.dims, ntv, R, 200)
+    X, st, rc = gop.solve_block(B.cuda(), 1e-30, Opts(m=m, max_cycles=1))
+    assert all(s["iters"] == m for s in st)
+    f = lambda v: dop.apply(oop, v.reshape(oop.V, oop.n)).reshape(-1)
+    Bn = B.numpy().reshape(R, N).T
+    Xr, info = block_gmres(f, Bn, [1e-30] * R, m, 1)
+    Xg = X.cpu().numpy().reshape(R, N).T
+    log(f"  difference to the oracle: {rel(Xg, Xr):.2e}")
+    assert rel(Xg, Xr) <= 1e-10
+    for c in range(R):
+        assert abs(st[c]["rel_res_true"] - info["relres"][c]) <= 1e-8 * info["relres"][c]
+
+
+@pytest.mark.parametrize("prec", ["f32", "f16s"])
+def test_wide_block_reduced_precision_solve(prec):
+    """24 columns in FP32 / FP16-stored inner block solves (MFMA Gram and
+    update kernels in FP32) inside the FP64 refinement: every column meets its
+    tolerance by the oracle's residual."""
+    from paper_2205_09104_amd import Opts
+    log("wide block reduced precision", prec)
+    gop, oop = make_pair((4, 4, 2, 4), 6, 3.0, mu=0.1, store=("f64", "f32", "f16s"))
+    R = 24
+    B = _rhs(oop.dims, 6, R, 300)
+    tols = np.array(synth.tolerances_loguniform(R, 1e-10, 1e-6, seed=5))
+    o = Opts(m=6, d=3, seed=1, prec=prec, inner_tol=1e-3, max_outer=40)
+    X, st, rc = gop.solve_block(B.cuda(), tols, o)
+    assert rc == 0, st
+    Xh = X.cpu().numpy()
+    for c in range(R):
+        assert oracle_relres(oop, Xh[c], B[c].numpy()) <= tols[c] * 1.0001
+
+
+def _principal_sines(X, Y):
+    """Sine of the largest principal angle between span(X) and span(Y)."""
+    qx, _ = np.linalg.qr(X)
+    qy, _ = np.linalg.qr(Y)
+    c = np.linalg.svd(qx.conj().T @ qy, compute_uv=False).min()
+    return float(np.sqrt(max(0.0, 1.0 - c * c)))
+
+
+@pytest.mark.parametrize("d", [0, 3])
+def test_block_recycling_matches_oracle(d):
+    """Block GMRES that builds its recycle space from its first cycle and
+    refreshes it from the next two (k = 6, u = 3, FP64, a tolerance never
+    met): after 1, 2 and 3 cycles the iterate matches the oracle's block
+    recycling from the same inputs (the polynomial of degree d from the same
+    start vector), and so do span(U) and span(C)."""
+    from oracle import poly as opoly
+    from oracle.gcrodr import RecycleState
+    from paper_2205_09104_amd import Opts
+    log("block recycling vs oracle, d", d)
+    gop, oop = make_pair((4, 2, 2, 4), 6, 3.0, mu=0.1)
+    N = oop.V * oop.n
+    R, m, k = 4, 6, 6
+    B = _rhs(oop.dims, 6, R, 400)
+    Bn = B.numpy().reshape(R, N).T
+    f = lambda v: dop.apply(oop, v.reshape(oop.V, oop.n)).reshape(-1)
+    v0 = rand_vec(oop.V, oop.n, 401)
+    right = None
+    if d > 1:
+        th, _ = opoly.build_polynomial(f, v0.numpy().reshape(-1), d)
+        right = lambda v: opoly.q_apply(f, th, v)
+    for cycles in (1, 2, 3):
+        gop.update(torch.as_tensor(oop.A0).cuda(), torch.as_tensor(oop.B).cuda())  # no space yet
+        o = Opts(m=m, k=k, u=3, d=d, v0=v0.cuda() if d > 1 else None, max_cycles=cycles)
+        X, st, rc = gop.solve_block(B.cuda(), 1e-30, o)
+        sr = RecycleState()
+        Xr, info = block_gmres(f, Bn, [1e-30] * R, m, cycles, right=right, recycle=sr, k=k, u=3)
+        Xg = X.cpu().numpy().reshape(R, N).T
+        U, Cm = gop.export_recycle(o)
+        su = _principal_sines(U.cpu().numpy().reshape(k, -1).T, sr.U)
+        sc = _principal_sines(Cm.cpu().numpy().reshape(k, -1).T, sr.C)
+        log(f"  cycles {cycles}: iterate {rel(Xg, Xr):.2e}, span U {su:.2e}, span C {sc:.2e}, "
+            f"updates {sr.updates}")
+        assert rel(Xg, Xr) <= 1e-9
+        assert su <= 1e-7 and sc <= 1e-7
+        assert all(s["refresh_failed"] == 0 for s in st)
+
+
+def test_block_recycling_cuts_block_steps(c1):
+    """Mixed precision (FP16-stored inner block solves): a second batch of
+    right-hand sides with the space the first batch built and refreshed
+    needs fewer block steps than the same batch without recycling; every
+    column meets its tolerance by the oracle's residual."""
+    from paper_2205_09104_amd import Opts
+    gop, oop, w, D = c1
+    log("block recycling, step count")
+    R = 6
+    tols = np.array(synth.tolerances_loguniform(R, 1e-10, 1e-6, seed=9))
+    B1 = _rhs(w.dims, w.n_tv, R, 500).cuda()
+    B2 = _rhs(w.dims, w.n_tv, R, 600).cuda()
+    base = dict(m=8, d=4, seed=1, prec="f16s", inner_tol=1e-2, max_outer=40)
+    X0, s0, rc0 = gop.solve_block(B2, tols, Opts(**base))
+    gop.update(torch.as_tensor(oop.A0).cuda(), torch.as_tensor(oop.B).cuda())
+    o = Opts(k=16, u=4, **base)
+    _, s1, rc1 = gop.solve_block(B1, tols, o)
+    X2, s2, rc2 = gop.solve_block(B2, tols, o)
+    assert rc0 == 0 and rc1 == 0 and rc2 == 0
+    it0, it2 = max(s["iters"] for s in s0), max(s["iters"] for s in s2)
+    log(f"  block steps without recycling {it0}, with {it2}")
+    assert it2 < it0
+    Xh = X2.cpu().numpy()
+    for c in range(R):
+        assert oracle_relres(oop, Xh[c], B2[c].cpu().numpy()) <= tols[c] * 1.0001

@@ -220,8 +220,8 @@ def _principal_cosines(X, Y):
     return np.linalg.svd(qx.conj().T @ qy, compute_uv=False)
 
 
-@pytest.mark.parametrize("bj", [0, 1])
-def test_recycle_space_matches_oracle(bj):
+@pytest.mark.parametrize("bj,k,m", [(0, 5, 25), (1, 5, 25), (1, 18, 32)])
+def test_recycle_space_matches_oracle(bj, k, m):
     """The recycle space itself against the oracle's, from the same polynomial
     start vector and right-hand side (FP64, Gram-Schmidt twice against the
     oracle's modified Gram-Schmidt): after the construction cycle (harmonic
@@ -229,15 +229,16 @@ def test_recycle_space_matches_oracle(bj):
     (generalised problem of the deflated cycle), span(C) and span(U) agree
     to principal angles below 1e-5.  Twisted mass 0.1 keeps the spectrum
     free of the conjugate pairs that would make the k-th smallest |theta|
-    ambiguous."""
+    ambiguous.  With k = 18 the new U and C are formed by the MFMA block
+    update (16 or more outputs) with FP64 products."""
     from paper_2205_09104_amd import Opts
-    log("recycle space vs oracle, bj", bj)
+    log("recycle space vs oracle, bj", bj, "k", k)
     dims, ntv, mu = (4, 4, 2, 2), 4, 0.1
     gop, oop = make_pair(dims, ntv, 3.0, mu=mu)
     ne = oop.V // 2
     b = rand_vec(oop.V, oop.n, 86, 0)
     v0 = rand_vec(ne, oop.n, 87, 0)
-    k, d, m = 5, 3, 25
+    d = 3
     for cycles in (1, 2):
         o = Opts(m=m, k=k, d=d, u=10, schur=1, block_jacobi=bj, v0=v0.cuda(),
                  max_cycles=cycles)

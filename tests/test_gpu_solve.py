@@ -390,3 +390,45 @@ def test_mixed_lattice_batch_rejects_bad_input():
         CoarseOp.solve_multi([a, c], [ba, bc], [1e-8, 1e-8], Opts(m=10))
     with pytest.raises(DcError):
         CoarseOp.solve_multi([a, a], [ba, ba], [1e-8, 1e-8], Opts(m=10))
+
+
+@pytest.mark.parametrize("cfg", ["poly", "bj"])
+def test_mixed_batch_graph_replay_matches_eager(cfg):
+    """The Arnoldi steps of each lockstep cycle of a mixed batch recorded once
+    per active set as a HIP graph and replayed (one launch per cycle): three
+    solves with graphs, with eager work and synchronisation between them, give
+    the eager solve's iterates and step counts; the first operator's cache
+    shows recordings and more replays than recordings."""
+    from paper_2205_09104_amd import CoarseOp, Opts
+    log("mixed batch graph replay", cfg)
+    store = ("f64", "f32", "f16s")
+    pairs = [make_pair((2, 2, 2, 2), 4, 3.2, store=store),
+             make_pair((3, 2, 2, 2), 4, 3.1, mu=0.05, store=store),
+             make_pair((4, 3, 2, 2), 4, 3.0, store=store)]
+    ops = [p[0] for p in pairs]
+    R = [2, 3, 1]
+    bs, tols = [], []
+    for i, ((gop, oop), r) in enumerate(zip(pairs, R)):
+        bs.append(torch.stack([rand_vec(oop.V, oop.n, 500 + 10 * i, j) for j in range(r)]).cuda())
+        tols.append(synth.tolerances_loguniform(r, 1e-10, 1e-7, seed=17 + i))
+    kw = {"poly": dict(m=20, d=4, seed=3), "bj": dict(m=20, d=4, block_jacobi=1, seed=3)}[cfg]
+    xe, se, rce = CoarseOp.solve_multi(ops, bs, tols, Opts(**kw))
+    assert rce == 0
+    c0, l0 = ops[0].graph_stats()
+    for rep in range(3):
+        xg, sg, rcg = CoarseOp.solve_multi(ops, bs, tols, Opts(graphs=1, **kw))
+        assert rcg == 0
+        for a, b, s1, s2 in zip(xg, xe, sg, se):
+            d = float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+            assert d <= 1e-14, (rep, d)
+            assert [s["iters"] for s in s1] == [s["iters"] for s in s2]
+        # eager work between the replays
+        y = ops[1].apply(bs[1][0])
+        torch.cuda.synchronize()
+        assert torch.isfinite(y).all()
+    c1, l1 = ops[0].graph_stats()
+    log(f"  recordings {c1 - c0}, replays {l1 - l0}")
+    assert c1 - c0 >= 1 and l1 - l0 > c1 - c0
+    for (gop, oop), x, b, t in zip(pairs, xg, bs, tols):
+        for j in range(b.shape[0]):
+            assert oracle_relres(oop, x[j].cpu().numpy(), b[j].cpu().numpy()) <= t[j]
