@@ -184,6 +184,25 @@ def measured_traffic(workload, prec, kernel):
                            "fetch_scale": t["fetch_scale"], "write_scale": t["write_scale"]}
 
 
+def m0_reading(w):
+    """How m0 was set for the workload (synth/m0.json): the calibration method,
+    the target ratio min Re eig / max |eig|, and where available the ratio the
+    Ritz values of a long Arnoldi run on the 8^4 lattice of the same family
+    give (an estimate: the leftmost Ritz pair is not converged)."""
+    import synth
+    tab = synth.load_m0_table()
+    e = tab.get(w.name, {})
+    out = {"method": e.get("method"), "rho_target": e.get("rho_target")}
+    if "rho_achieved" in e:
+        out["rho_achieved"] = e["rho_achieved"]
+    ref = e if "rho_ritz" in e else tab.get("c2", {})
+    if "rho_ritz" in ref:
+        out["rho_ritz_estimate"] = {k: ref[k] for k in ("rho_ritz", "ritz_min_re", "ritz_max_abs",
+                                                        "ritz_steps", "ritz_left_residual")}
+        out["rho_ritz_estimate"]["lattice"] = "8^4 (c2)" if ref is not e else w.name
+    return out
+
+
 def main():
     a = parse()
     if a.summarize_trace:
@@ -464,9 +483,14 @@ def main():
                                                  r_last))
 
     # ------------------------------------------------ the 4^4 workload: eager vs graph replay
-    c1res = None
+    c1res = mixres = None
     if a.c1_steps > 0 and w.name != "c1":
         c1res = c1_graphs(a)
+        try:
+            mixres = mixed_graphs(a)
+        except Exception as e:   # an extra key: reported, never fatal to the line
+            mixres = {"error": f"{type(e).__name__}: {e}"}
+            log(f"mixed batch graph replay failed: {e}")
 
     # ------------------------------------------------ the same method on the 8^4 workload
     c2res = None
@@ -545,7 +569,8 @@ def main():
                              f"FGMRES(10) fp64 outer; inner {inner} GCRO-DR(m={a.m + a.k},"
                              f"k={a.k}, u={a.u}) + poly d={a.d}, inner_tol={a.inner_tol}"
                              f"{', single-sync Arnoldi' if a.ortho else ''}",
-                   "tol": a.tol, "parallelism": "single GPU"},
+                   "tol": a.tol, "parallelism": "single GPU",
+                   "m0_reading": m0_reading(w)},
         "setup_ms": setup_ms,
         "iters_per_solve": [s["iters"] for s in stats],
         "matvecs_per_solve": [s["matvecs"] for s in stats],
@@ -557,6 +582,7 @@ def main():
         "same_method_other_block_jacobi": bj_cmp,
         "c2_same_method": c2res,
         "c1_graph_replay": c1res,
+        "mixed_batch_graph_replay": mixres,
         "fp64_comparison": comp,
         "apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]} for p, r in rates.items()},
         "reduced_apply_back_to_back": {p: {"us": r[0] * 1e3, "GB/s": r[1]}
@@ -641,6 +667,47 @@ def c1_graphs(a):
         log(f"c1 {name}: eager {res['eager']['solves_per_s']:.1f}, graphs "
             f"{res['graphs']['solves_per_s']:.1f} solves/s")
         out[name] = res
+    return out
+
+
+def mixed_graphs(a):
+    """A launch-bound mixed batch (4^4, 6x4^3 and 6^2x4^2 lattices of the 4^4
+    workload's family, N_tv = 8, two right-hand sides each, FP64, polynomial
+    d = 4, GMRES(20) in lockstep, tolerance 1e-10): batches/s with eager
+    launches and with each lockstep cycle's steps replayed as one HIP graph."""
+    import torch
+
+    import synth
+    from paper_2205_09104_amd import CoarseOp, Opts
+    w = synth.WORKLOADS["c1"]
+    dims_list = [(4, 4, 4, 4), (6, 4, 4, 4), (6, 6, 4, 4)]
+    ops, bs = [], []
+    for i, dims in enumerate(dims_list):
+        A = synth.self_blocks(dims, w.n_tv, w.m0(), w.seed, device="cuda")
+        B = synth.hop_blocks(dims, w.n_tv, w.seed, device="cuda")
+        ops.append(CoarseOp(A, B, dims))
+        bs.append(torch.stack([synth.rhs(dims, w.n_tv, 10 * i + r, device="cuda") for r in range(2)]))
+    tols = [[1e-10, 1e-10]] * len(ops)
+    out = {"lattices": ["x".join(map(str, d)) for d in dims_list], "n_tv": w.n_tv,
+           "rhs_per_lattice": 2, "tol": 1e-10}
+    for graphs in (0, 1):
+        o = Opts(m=20, d=4, seed=3, graphs=graphs)
+        CoarseOp.solve_multi(ops, bs, tols, o)       # polynomial, tile choice, recordings
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [CoarseOp.solve_multi(ops, bs, tols, o) for _ in range(a.c1_steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ok = all(rc == 0 for _, _, rc in sts)
+        out["graphs" if graphs else "eager"] = {
+            "batches_per_s": a.c1_steps / dt if ok else 0.0, "ms_per_batch": 1e3 * dt / a.c1_steps,
+            "graph_stats": list(ops[0].graph_stats())}
+    out["speedup"] = (out["graphs"]["batches_per_s"] / out["eager"]["batches_per_s"]
+                      if out["eager"]["batches_per_s"] else None)
+    log(f"mixed batch: eager {out['eager']['batches_per_s']:.1f}, graphs "
+        f"{out['graphs']['batches_per_s']:.1f} batches/s")
+    for op in ops:
+        op.close()
     return out
 
 
