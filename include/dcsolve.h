@@ -293,6 +293,15 @@ int dc_apply_block_jacobi(dc_op_t op, const void* in, void* out, void* stream);
 int dc_poly_setup(dc_op_t op, const dc_solve_opts* opts, void* stream,
                   double* theta_out, int32_t* d_used);
 
+/* Install the polynomial q of Sec. 3.3 from caller-given roots theta (host,
+ * 2*d doubles re, im; d == opts->d) for (opts->prec, opts->block_jacobi,
+ * opts->schur) instead of building it: the chain uses them in the given order
+ * (Leja order, Alg. 2, for stability), e.g. roots computed once for several
+ * handles of the same operator.  A recycle space of that variant built with
+ * another polynomial is dropped.  DC_ERR_INVALID for d != opts->d or a zero or
+ * non-finite root. */
+int dc_poly_set(dc_op_t op, const dc_solve_opts* opts, const double* theta, int32_t d);
+
 /* out = q(A~) in with the polynomial built for (opts->prec, opts->block_jacobi)
  * (Sec. 3.3, Newton-like form, d-1 applications); vectors as in dc_apply. */
 int dc_poly_apply(dc_op_t op, const dc_solve_opts* opts, const void* in, void* out,

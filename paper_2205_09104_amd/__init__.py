@@ -240,6 +240,16 @@ class CoarseOp:
                                    th.ctypes.data_as(C.POINTER(C.c_double)), C.byref(du)))
         return (th[0::2] + 1j * th[1::2])[:du.value]
 
+    def poly_set(self, theta, opts: Opts):
+        """Install the polynomial roots theta (complex, in chain order) for the
+        variant of opts (opts.d == len(theta))."""
+        th = np.asarray(theta, dtype=np.complex128)
+        buf = np.empty(2 * th.size, dtype=np.float64)
+        buf[0::2], buf[1::2] = th.real, th.imag
+        o = opts.to_c()
+        check(load().dc_poly_set(self._h, C.byref(o), buf.ctypes.data_as(C.POINTER(C.c_double)),
+                                 int(th.size)))
+
     def poly_apply(self, x: torch.Tensor, opts: Opts, stream=None):
         x = x.contiguous()
         out = torch.empty_like(x)

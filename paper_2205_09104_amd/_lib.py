@@ -76,6 +76,8 @@ SIGNATURES = {
     "dc_apply_multi": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_void_p,
                                  C.c_void_p, C.c_void_p]),
     "dc_apply_block_jacobi": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "dc_poly_set": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.POINTER(C.c_double),
+                              C.c_int32]),
     "dc_poly_setup": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p,
                                 C.POINTER(C.c_double), C.POINTER(C.c_int32)]),
     "dc_poly_apply": (C.c_int, [C.c_void_p, C.POINTER(SolveOpts), C.c_void_p, C.c_void_p,

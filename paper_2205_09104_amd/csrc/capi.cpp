@@ -314,6 +314,17 @@ int dc_poly_setup(dc_op_t op, const dc_solve_opts* opts, void* stream, double* t
   });
 }
 
+int dc_poly_set(dc_op_t op, const dc_solve_opts* opts, const double* theta, int32_t d) {
+  return guarded([&] {
+    if (!op || !opts || !theta) throw dc::InvalidArg("null handle, options or roots");
+    if (d < 1) throw dc::InvalidArg("d must be >= 1");
+    std::vector<dc::cd> th(static_cast<size_t>(d));
+    for (int i = 0; i < d; ++i) th[size_t(i)] = dc::cd(theta[2 * i], theta[2 * i + 1]);
+    dc::op_poly_set(op->op, convert(opts), th);
+    return DC_OK;
+  });
+}
+
 int dc_poly_apply(dc_op_t op, const dc_solve_opts* opts, const void* in, void* out, void* stream) {
   return guarded([&] {
     if (!op || !opts) throw dc::InvalidArg("null handle or options");

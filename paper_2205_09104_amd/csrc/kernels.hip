@@ -1219,12 +1219,24 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
   const int upl = (TT + epl - 1) / epl;                      // units per lane of a block
   const int nunits = 64 * upl;
   const int half = n >> 1;
-  // output tiles (16 x 16): RT row tiles x RB/16 column tiles, spread over the
-  // 4 waves (tile t = wave + 4 it); a partial right-hand-side tile computes on
-  // zero padding and stores only its Rc columns
+  // output tiles (16 x 16): RT row tiles x RB/16 column tiles; a partial
+  // right-hand-side tile computes on zero padding and stores only its Rc
+  // columns.  FP32 products: every wave gets the same share of MFMA work --
+  // the k range is split KS ways (KS = 4 / gcd(NT, 4)) and wave w takes k
+  // part w % KS of the TPW tiles (w / KS) TPW .. + TPW - 1 (3 row tiles x 1
+  // column tile, n = 48 with 16 right-hand sides, give each wave all 3 tiles
+  // over a quarter of k), the KS partial panels summed in LDS at the end.
+  // FP64 products keep one k range per tile (tile t = wave + 4 i): their
+  // wider accumulators would cost the occupancy the balance gains.
+  constexpr bool SPLIT = sizeof(VT) == 4;
   constexpr int RT = NP / 16;
   constexpr int NT = RT * (RB / 16);
-  constexpr int TPW = (NT + 3) / 4;     // tiles per wave
+  constexpr int KS = !SPLIT ? 1 : ((NT % 4 == 0) ? 1 : ((NT % 2 == 0) ? 2 : 4));
+  constexpr int TPW = SPLIT ? NT * KS / 4 : (NT + 3) / 4;   // tiles per wave
+  constexpr int KSTEPS = NP / 4 / KS;   // 4-deep k steps per wave
+  static_assert((NP / 4) % KS == 0, "k range splits evenly");
+  const int kpart = wave % KS, tile0 = (wave / KS) * TPW;
+  auto tile_of = [&](int it) { return SPLIT ? tile0 + it : wave + 4 * it; };
   // Staging with 16-byte loads.  Blocks: thread t takes units u = t + 256 s of
   // the tiled block (lane u % 64, unit u / 64 of that lane), each holding epl
   // entries whose (row, column) are fixed per thread and computed once.
@@ -1378,11 +1390,12 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
     // (16x16x4 tiles), k outermost so the wave's tiles interleave their MFMA
     // chains
 #pragma unroll
-    for (int k = 0; k < NP; k += 4) {
+    for (int ks = 0; ks < KSTEPS; ++ks) {
+      const int k = 4 * (kpart * KSTEPS + ks);
 #pragma unroll
       for (int it = 0; it < TPW; ++it) {
-        const int t = wave + 4 * it;
-        if (t < NT) {
+        const int t = tile_of(it);
+        if (SPLIT || t < NT) {   // split tiles always exist
           const int rt = t % RT, ct = t / RT;
           const int ao = (rt * 16 + l16) * LD + lk + k, bo = (ct * 16 + l16) * LD + lk + k;
           const VT a_r = Mr[ao], a_i = Mi[ao], b_r = Pr[bo], b_i = Pi[bo];
@@ -1394,24 +1407,35 @@ __global__ __launch_bounds__(256) void k_apply_multi(MultiOps ops) {
     }
     __syncthreads();
   }
-  // accumulators -> LDS panel planes (row r = right-hand side) -> coalesced stores
+  // accumulators -> LDS panel planes (row r = right-hand side) -> coalesced
+  // stores; the k parts add their partial panels one after another
 #pragma unroll
-  for (int it = 0; it < TPW; ++it) {
-    const int t = wave + 4 * it;
-    if (t < NT) {
-      const int rt = t % RT, ct = t / RT;
-      const int col = ct * 16 + l16;
+  for (int part = 0; part < KS; ++part) {
+    if (kpart == part) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        // accumulator value q of a lane: row 4*(lane/16)+q for the FP32 16x16x4
-        // MFMA, row lane/16 + 4*q for the FP64 one
-        const int row = rt * 16 + Mfma<VT>::row(lk, q);
-        Pr[col * LD + row] = crr[it][q] - cii[it][q];
-        Pi[col * LD + row] = css[it][q] - crr[it][q] - cii[it][q];
+      for (int it = 0; it < TPW; ++it) {
+        const int t = tile_of(it);
+        if (!SPLIT && t >= NT) continue;
+        const int rt = t % RT, ct = t / RT;
+        const int col = ct * 16 + l16;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          // accumulator value q of a lane: row 4*(lane/16)+q for the FP32
+          // 16x16x4 MFMA, row lane/16 + 4*q for the FP64 one
+          const int row = rt * 16 + Mfma<VT>::row(lk, q);
+          const VT re = crr[it][q] - cii[it][q], im = css[it][q] - crr[it][q] - cii[it][q];
+          if (part == 0) {
+            Pr[col * LD + row] = re;
+            Pi[col * LD + row] = im;
+          } else {
+            Pr[col * LD + row] += re;
+            Pi[col * LD + row] += im;
+          }
+        }
       }
     }
+    __syncthreads();
   }
-  __syncthreads();
   for (int t = threadIdx.x; t < Rc * n; t += blockDim.x) {
     const int r = t / n, i = t % n;
     cx<VT> z = mk(Pr[r * LD + i], Pi[r * LD + i]);
@@ -2800,7 +2824,7 @@ void launch_apply_multi_ops(Prec p, int n, const MultiOpDesc* desc, int n_ops, i
   if (rmax <= 0 || sites == 0) return;
   int rb = multi_tile_for(p, n, rmax, sites);
   if (rb == 0) {
-    // time every candidate (each fully overwrites the outputs with the same result)
+    // time every candidate (each fully overwrites the outputs)
     hipEvent_t e0, e1;
     DC_HIP(hipEventCreate(&e0));
     DC_HIP(hipEventCreate(&e1));
@@ -2824,7 +2848,8 @@ void launch_apply_multi_ops(Prec p, int n, const MultiOpDesc* desc, int n_ops, i
     (void)hipEventDestroy(e1);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[tune_key(p, n, rmax, sites)] = rb;
-    return;   // the last candidate's launches already wrote the outputs
+    // the outputs come from the chosen tile, as in every later call (the FP32
+    // tiles split their sums differently and agree only to rounding)
   }
   multi_dispatch(p, rb, ops, sites, rmax, st);
 }

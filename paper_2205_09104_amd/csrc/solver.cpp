@@ -1639,6 +1639,21 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
   return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
 }
 
+void op_poly_set(Op& op, const SolveOpts& o, const std::vector<cd>& theta) {
+  check_prec(op, o.prec);
+  if (theta.empty() || int(theta.size()) != o.d) throw InvalidArg("d must equal the number of roots");
+  for (const cd& t : theta)
+    if (!(std::abs(t) > 0.0) || !std::isfinite(t.real()) || !std::isfinite(t.imag()))
+      throw InvalidArg("polynomial roots must be finite and nonzero");
+  Variant& var = op.variant(o.prec, +1, o.block_jacobi ? 1 : 0, o.d, o.schur);
+  var.theta = theta;
+  var.poly_version = op.version;
+  ++var.poly_serial;
+  // a recycle space built with another polynomial no longer satisfies C = A q(A) U
+  var.kcur = 0;
+  var.mu_ok = false;
+}
+
 int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta) {
   check_prec(op, o.prec);
   if (o.d < 1) throw InvalidArg("d must be >= 1");

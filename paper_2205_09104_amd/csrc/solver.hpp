@@ -302,6 +302,9 @@ void op_apply_reduced_noalloc(Op& op, Prec p, int adjoint, const void* in, void*
                               hipStream_t st);
 void op_apply_multi(Op& op, Prec p, int adjoint, int R, const void* in, void* out, hipStream_t st);
 int op_poly_setup(Op& op, const SolveOpts& o, hipStream_t st, std::vector<cd>& theta);
+// Install caller-given polynomial roots (used in the given order) for the
+// variant of o; o.d must equal theta.size().
+void op_poly_set(Op& op, const SolveOpts& o, const std::vector<cd>& theta);
 void op_poly_apply(Op& op, const SolveOpts& o, const void* in, void* out, hipStream_t st);
 int op_arnoldi(Op& op, const SolveOpts& o, const void* v, int steps, hipStream_t st,
                std::vector<cd>& hbar);

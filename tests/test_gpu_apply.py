@@ -137,8 +137,12 @@ def test_apply_multi_matches_oracle(dims, ntv, R, mu):
 
 
 def test_apply_multi_tiles_agree_bitwise():
-    """Every right-hand-side tile of the multi-apply does the same arithmetic
-    per output entry; the autotuner picks one of them."""
+    """FP64: every right-hand-side tile of the multi-apply does the same
+    arithmetic per output entry (bitwise equal results).  FP32: the tiles
+    split the k range of the products differently between the waves (so that
+    every wave has the same MFMA work), so they agree to rounding (1e-6
+    relative).  The autotuner picks one of them and its result is that
+    tile's."""
     import paper_2205_09104_amd as dc
     log("apply multi tiles")
     gop, oop = make_pair((3, 2, 2, 2), 24, 2.5, mu=0.1, store=("f64", "f32"))
@@ -158,6 +162,7 @@ def test_apply_multi_tiles_agree_bitwise():
     finally:
         dc.set_multi_tile_mode(0)
     for mode in (32, 64):
-        assert torch.equal(outs[mode][0], outs[16][0]) and torch.equal(outs[mode][1], outs[16][1])
-    assert torch.equal(auto[0], outs[16][0]) and torch.equal(auto[1], outs[16][1])
+        assert torch.equal(outs[mode][0], outs[16][0])
+        assert rel(outs[mode][1].numpy(), outs[16][1].numpy()) <= 1e-6
     assert tiles[0] in (16, 32, 64) and tiles[1] in (16, 32, 64)
+    assert torch.equal(auto[0], outs[16][0]) and torch.equal(auto[1], outs[tiles[1]][1])

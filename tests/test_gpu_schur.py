@@ -135,8 +135,9 @@ def s_flat(oop):
 @pytest.mark.parametrize("d", [2, 5])
 def test_reduced_polynomial_chain(c1, d):
     """The reduced apply's chain epilogues (first and later steps of q(S))
-    against the oracle's chain with the same harmonic Ritz values (to 1e-12),
-    and those values against the oracle's own (same v0, Leja order, 1e-8)."""
+    against the oracle's chain with the same roots -- the oracle's, installed
+    in the handle (to 1e-12) -- and the roots the library builds against the
+    oracle's own (same v0, Leja order, 1e-8)."""
     from paper_2205_09104_amd import Opts
     gop, oop, w, b, xref = c1
     log("reduced poly chain", d)
@@ -148,8 +149,9 @@ def test_reduced_polynomial_chain(c1, d):
     assert len(th) == d
     assert np.max(np.abs(th - th_ref)) <= 1e-8 * np.abs(th_ref).max()
     x = rand_vec(ne, oop.n, 74)
+    gop.poly_set(th_ref, opts)
     got = gop.poly_apply(x.cuda(), opts).cpu().numpy()
-    want = opoly.q_apply(s_flat(oop), th, x.numpy().reshape(-1)).reshape(ne, oop.n)
+    want = opoly.q_apply(s_flat(oop), th_ref, x.numpy().reshape(-1)).reshape(ne, oop.n)
     assert rel(got, want) <= 1e-12
 
 

@@ -96,7 +96,8 @@ def test_reduced_bj_arnoldi_matches_oracle():
     assert np.abs(H - ref.Hbar).max() <= 1e-10 * np.abs(ref.Hbar).max()
     v0 = rand_vec(ne, oop.n, 82, 0)
     o = Opts(m=10, d=4, v0=v0.cuda(), schur=1, block_jacobi=1)
-    th = gop.poly_setup(o)
+    th, _ = opoly.build_polynomial(f, v0.numpy().reshape(-1), 4)
+    gop.poly_set(th, o)                  # the oracle's roots, installed in the handle
     H, s = gop.arnoldi(v.cuda(), 10, o)
     fq = lambda u: f(opoly.q_apply(f, th, u))
     ref = o_arnoldi(fq, v.numpy().reshape(-1), 10, "mgs")
@@ -107,8 +108,8 @@ def test_reduced_bj_arnoldi_matches_oracle():
 @pytest.mark.parametrize("d", [2, 6])
 def test_reduced_bj_polynomial(d):
     """Harmonic Ritz values of B^{-1} S in Leja order against the oracle's
-    (same v0) to 1e-8, and the fused chain q(B^{-1} S) x against the oracle's
-    chain with the same values to 1e-12."""
+    (same v0) to 1e-8, and the fused chain q(B^{-1} S) x with the oracle's
+    values installed in the handle against the oracle's chain to 1e-12."""
     from paper_2205_09104_amd import Opts
     log("reduced bj polynomial", d)
     gop, oop = make_pair((4, 2, 2, 2), 4, 3.0, mu=0.05)
@@ -121,8 +122,9 @@ def test_reduced_bj_polynomial(d):
     assert len(th) == d
     assert np.max(np.abs(th - th_ref)) <= 1e-8 * np.abs(th_ref).max()
     x = rand_vec(ne, oop.n, 84, 0)
+    gop.poly_set(th_ref, o)
     got = gop.poly_apply(x.cuda(), o).cpu().numpy()
-    want = opoly.q_apply(f, th, x.numpy().reshape(-1)).reshape(ne, oop.n)
+    want = opoly.q_apply(f, th_ref, x.numpy().reshape(-1)).reshape(ne, oop.n)
     assert rel(got, want) <= 1e-12
 
 
@@ -181,19 +183,21 @@ def test_reduced_bj_gmres_iterations_match_oracle(c1):
 
 def test_reduced_bj_recycle_invariants(c1):
     """GCRO-DR on B^{-1} S q(B^{-1} S): C^H C = I and C = A^ U with the oracle's
-    B^{-1} S and the library's harmonic Ritz values."""
+    B^{-1} S and the oracle's polynomial roots installed in the handle."""
     from paper_2205_09104_amd import Opts
     gop, oop, w, b, xref = c1
     log("reduced bj recycle invariants")
     k, d = 6, 3
+    ne = oop.V // 2
+    f = lambda u: schur.apply_bj(oop, u.reshape(ne, oop.n)).reshape(-1)
     opts = Opts(m=24 + k, k=k, d=d, u=10, seed=3, schur=1, block_jacobi=1)
+    # the polynomial: the oracle's roots from a fixed start vector, installed
+    th, _ = opoly.build_polynomial(f, rand_vec(ne, oop.n, 85, 0).numpy().reshape(-1), d)
+    gop.poly_set(th, opts)
     for r in range(2):
         x, st, rc = gop.solve(synth.rhs(w.dims, w.n_tv, 10 + r).cuda(), 1e-10, opts)
         assert rc == 0
-    th = gop.poly_setup(Opts(d=d, seed=3, schur=1, block_jacobi=1))
     U, Cm = gop.export_recycle(opts)
-    ne = oop.V // 2
-    f = lambda u: schur.apply_bj(oop, u.reshape(ne, oop.n)).reshape(-1)
     Ch = Cm.cpu().numpy().reshape(k, -1)
     assert np.allclose(Ch.conj() @ Ch.T, np.eye(k), atol=1e-10)
     AU = np.stack([f(opoly.q_apply(f, th, u)) for u in U.cpu().numpy().reshape(k, -1)])

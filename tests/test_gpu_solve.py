@@ -63,9 +63,11 @@ def test_polynomial_matches_oracle(c1, d):
     assert len(th) == d
     assert np.max(np.abs(th - th_ref)) <= 1e-8 * np.abs(th_ref).max()   # same Leja order
     x = rand_vec(oop.V, oop.n, 22)
+    # the chain against the oracle's chain with the same roots: the oracle's,
+    # installed in the handle
+    gop.poly_set(th_ref, opts)
     got = gop.poly_apply(x.cuda(), opts).cpu().numpy()
-    # the chain against the oracle's chain with the same harmonic Ritz values
-    want = opoly.q_apply(flat(oop), th, x.numpy().reshape(-1)).reshape(oop.V, oop.n)
+    want = opoly.q_apply(flat(oop), th_ref, x.numpy().reshape(-1)).reshape(oop.V, oop.n)
     assert rel(got, want) <= 1e-12
     # f32 chain with the f32 polynomial: close to the FP64 one
     o32 = Opts(d=d, v0=v0.cuda(), prec="f32")
