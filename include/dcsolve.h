@@ -297,9 +297,10 @@ int dc_poly_setup(dc_op_t op, const dc_solve_opts* opts, void* stream,
  * 2*d doubles re, im; d == opts->d) for (opts->prec, opts->block_jacobi,
  * opts->schur) instead of building it: the chain uses them in the given order
  * (Leja order, Alg. 2, for stability), e.g. roots computed once for several
- * handles of the same operator.  A recycle space of that variant built with
- * another polynomial is dropped.  DC_ERR_INVALID for d != opts->d or a zero or
- * non-finite root. */
+ * handles of the same operator.  It applies to D_c's own variant (adjoint
+ * solves with mu != 0 keep building theirs).  A recycle space of that variant
+ * built with another polynomial is dropped.  DC_ERR_INVALID for d != opts->d
+ * or a zero or non-finite root. */
 int dc_poly_set(dc_op_t op, const dc_solve_opts* opts, const double* theta, int32_t d);
 
 /* out = q(A~) in with the polynomial built for (opts->prec, opts->block_jacobi)
