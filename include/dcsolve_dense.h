@@ -28,6 +28,12 @@ int dc_dense_eig(int32_t n, const double* A, double* w, double* Z);
 int dc_dense_lstsq(int32_t rows, int32_t cols, const double* A, const double* b,
                    double* x, double* resnorm);
 
+/* Solve A X = B for A (n x n) and B (n x nrhs, overwritten with X) by LU
+ * with partial pivoting (the recycle refresh's generalised problem is
+ * reduced to a standard one this way).  DC_ERR_INVALID if A is singular to
+ * working precision. */
+int dc_dense_solve(int32_t n, const double* A, int32_t nrhs, double* B);
+
 /* Harmonic Ritz values of d Arnoldi steps (Sec. 3.3): eigenvalues of
  * H_d + |h_{d+1,d}|^2 f e_d^T with f = H_d^{-H} e_d; hbar is (d+1) x d. */
 int dc_harmonic_ritz(int32_t d, const double* hbar, double* theta);

@@ -444,6 +444,18 @@ def _colmajor(A):
     return np.ascontiguousarray(np.asarray(A, dtype=np.complex128).T).view(np.float64).ravel()
 
 
+def dense_solve(A: np.ndarray, B: np.ndarray):
+    """X with A X = B (host LU with partial pivoting of the library)."""
+    lib = load()
+    n = A.shape[0]
+    B2 = np.asarray(B, dtype=np.complex128).reshape(n, -1)
+    a = _colmajor(A)
+    b = _colmajor(B2).copy()      # written in place: never the caller's array
+    check(lib.dc_dense_solve(n, a.ctypes.data_as(C.POINTER(C.c_double)), B2.shape[1],
+                             b.ctypes.data_as(C.POINTER(C.c_double))))
+    return (b[0::2] + 1j * b[1::2]).reshape(B2.shape[1], n).T
+
+
 def dense_lstsq(A: np.ndarray, b: np.ndarray):
     lib = load()
     rows, cols = A.shape

@@ -117,6 +117,8 @@ SIGNATURES = {
     # host-only dense linear algebra
     "dc_dense_eig": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.POINTER(C.c_double)]),
+    "dc_dense_solve": (C.c_int, [C.c_int32, C.POINTER(C.c_double), C.c_int32,
+                                 C.POINTER(C.c_double)]),
     "dc_dense_lstsq": (C.c_int, [C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double), C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]),

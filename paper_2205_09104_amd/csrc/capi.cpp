@@ -582,6 +582,20 @@ int dc_dense_lstsq(int32_t rows, int32_t cols, const double* A, const double* b,
   });
 }
 
+int dc_dense_solve(int32_t n, const double* A, int32_t nrhs, double* B) {
+  return guarded([&] {
+    if (n < 1 || nrhs < 0 || !A || !B) throw dc::InvalidArg("bad arguments");
+    dc::Mat X = read_mat(n, nrhs, B);
+    if (!dc::lu_solve(read_mat(n, n, A), X)) throw dc::InvalidArg("singular matrix");
+    for (int j = 0; j < nrhs; ++j)
+      for (int i = 0; i < n; ++i) {
+        B[2 * (i + size_t(j) * n)] = X(i, j).real();
+        B[2 * (i + size_t(j) * n) + 1] = X(i, j).imag();
+      }
+    return DC_OK;
+  });
+}
+
 int dc_harmonic_ritz(int32_t d, const double* hbar, double* theta) {
   return guarded([&] {
     if (d < 1 || !hbar || !theta) throw dc::InvalidArg("bad arguments");

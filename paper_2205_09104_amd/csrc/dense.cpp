@@ -7,13 +7,46 @@
 
 namespace dc {
 
+// The inner loops below spell complex products out in real arithmetic on the
+// interleaved (re, im) storage: the library operator* of std::complex carries
+// a NaN/infinity recovery path that keeps these loops from vectorising.
+
+// y[0..n) += b x[0..n) (complex, contiguous)
+static inline void caxpy(int n, cd b, const cd* x, cd* y) {
+  const double br = b.real(), bi = b.imag();
+  const double* xd = reinterpret_cast<const double*>(x);
+  double* yd = reinterpret_cast<double*>(y);
+  for (int i = 0; i < n; ++i) {
+    const double xr = xd[2 * i], xi = xd[2 * i + 1];
+    yd[2 * i] += br * xr - bi * xi;
+    yd[2 * i + 1] += br * xi + bi * xr;
+  }
+}
+
+// sum_i conj(x_i) y_i (complex, contiguous)
+static inline cd cdotc(int n, const cd* x, const cd* y) {
+  const double* xd = reinterpret_cast<const double*>(x);
+  const double* yd = reinterpret_cast<const double*>(y);
+  double sr = 0.0, si = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double xr = xd[2 * i], xi = xd[2 * i + 1], yr = yd[2 * i], yi = yd[2 * i + 1];
+    sr += xr * yr + xi * yi;
+    si += xr * yi - xi * yr;
+  }
+  return cd(sr, si);
+}
+
+static inline cd cmul(cd a, cd b) {
+  return cd(a.real() * b.real() - a.imag() * b.imag(), a.real() * b.imag() + a.imag() * b.real());
+}
+
 Mat matmul(const Mat& A, const Mat& B) {
   Mat C(A.r, B.c);
   for (int j = 0; j < B.c; ++j)
     for (int k = 0; k < A.c; ++k) {
       const cd b = B(k, j);
       if (b == cd(0.0)) continue;
-      for (int i = 0; i < A.r; ++i) C(i, j) += A(i, k) * b;
+      caxpy(A.r, b, &A.a[size_t(k) * A.r], &C.a[size_t(j) * C.r]);
     }
   return C;
 }
@@ -51,23 +84,23 @@ static double householder(std::vector<cd>& v, double& alpha_abs) {
 // Apply (I - tau v v^H) from the left to rows k.. of columns c0..c1-1.
 static void reflect_left(Mat& A, int k, const std::vector<cd>& v, double tau, int c0, int c1) {
   if (tau == 0.0) return;
+  const int m = int(v.size());
   for (int j = c0; j < c1; ++j) {
-    cd s = 0.0;
-    for (size_t i = 0; i < v.size(); ++i) s += std::conj(v[i]) * A(k + int(i), j);
-    s *= tau;
-    for (size_t i = 0; i < v.size(); ++i) A(k + int(i), j) -= v[i] * s;
+    cd* col = &A(k, j);
+    const cd s = tau * cdotc(m, v.data(), col);
+    caxpy(m, -s, v.data(), col);
   }
 }
 
-// Apply (I - tau v v^H) from the right to columns k.. of rows r0..r1-1.
+// Apply (I - tau v v^H) from the right to columns k.. of rows r0..r1-1:
+// s = A v over the rows, then A -= tau s v^H, column by column.
 static void reflect_right(Mat& A, int k, const std::vector<cd>& v, double tau, int r0, int r1) {
-  if (tau == 0.0) return;
-  for (int i = r0; i < r1; ++i) {
-    cd s = 0.0;
-    for (size_t j = 0; j < v.size(); ++j) s += A(i, k + int(j)) * v[j];
-    s *= tau;
-    for (size_t j = 0; j < v.size(); ++j) A(i, k + int(j)) -= s * std::conj(v[j]);
-  }
+  if (tau == 0.0 || r1 <= r0) return;
+  const int rows = r1 - r0;
+  std::vector<cd> sv(size_t(rows), cd(0.0));
+  for (size_t j = 0; j < v.size(); ++j) caxpy(rows, v[j], &A(r0, k + int(j)), sv.data());
+  for (size_t j = 0; j < v.size(); ++j)
+    caxpy(rows, -tau * std::conj(v[j]), sv.data(), &A(r0, k + int(j)));
 }
 
 std::vector<cd> lstsq(const Mat& A0, const std::vector<cd>& b0, double* resnorm) {
@@ -140,18 +173,21 @@ bool lu_solve(const Mat& A0, Mat& B) {
       for (int j = 0; j < n; ++j) std::swap(A(k, j), A(p, j));
       for (int j = 0; j < B.c; ++j) std::swap(B(k, j), B(p, j));
     }
-    for (int i = k + 1; i < n; ++i) {
-      const cd l = A(i, k) / A(k, k);
-      A(i, k) = l;
-      for (int j = k + 1; j < n; ++j) A(i, j) -= l * A(k, j);
-      for (int j = 0; j < B.c; ++j) B(i, j) -= l * B(k, j);
-    }
+    // multipliers l_i = A(i,k) / A(k,k) in column k, then every later column
+    // of A and every column of B updated by a contiguous axpy
+    const cd inv = 1.0 / A(k, k);
+    const int below = n - k - 1;
+    for (int i = k + 1; i < n; ++i) A(i, k) = cmul(A(i, k), inv);
+    for (int j = k + 1; j < n; ++j) caxpy(below, -A(k, j), &A(k + 1, k), &A(k + 1, j));
+    for (int j = 0; j < B.c; ++j) caxpy(below, -B(k, j), &A(k + 1, k), &B(k + 1, j));
   }
+  // back substitution, column-oriented: x_i = b_i / A(i,i), then the rows
+  // above lose x_i A(0..i-1, i)
   for (int j = 0; j < B.c; ++j)
     for (int i = n - 1; i >= 0; --i) {
-      cd s = B(i, j);
-      for (int t = i + 1; t < n; ++t) s -= A(i, t) * B(t, j);
-      B(i, j) = s / A(i, i);
+      const cd x = B(i, j) / A(i, i);
+      B(i, j) = x;
+      if (i > 0) caxpy(i, -x, &A(0, i), &B(0, j));
     }
   return true;
 }
@@ -160,10 +196,10 @@ Mat tri_inverse(const Mat& R) {
   const int n = R.r;
   Mat X = Mat::eye(n);
   for (int j = 0; j < n; ++j)
-    for (int i = n - 1; i >= 0; --i) {
-      cd s = X(i, j);
-      for (int t = i + 1; t < n; ++t) s -= R(i, t) * X(t, j);
-      X(i, j) = s / R(i, i);
+    for (int i = j; i >= 0; --i) {   // column j of R^{-1} is zero below row j
+      const cd x = X(i, j) / R(i, i);
+      X(i, j) = x;
+      if (i > 0) caxpy(i, -x, &R(0, i), &X(0, j));
     }
   return X;
 }
@@ -181,6 +217,21 @@ static void hessenberg(Mat& H, Mat& Q) {
     reflect_right(H, k + 1, v, tau, 0, n);
     reflect_right(Q, k + 1, v, tau, 0, n);
     for (int i = k + 2; i < n; ++i) H(i, k) = 0.0;
+  }
+}
+
+// Columns x, y (length n) <- (c x + conj(s) y, -s x + c y): the right
+// multiplication of the pair by G^H.
+static inline void rot_cols(int n, double c, cd s, cd* x, cd* y) {
+  const double sr = s.real(), si = s.imag();
+  double* xd = reinterpret_cast<double*>(x);
+  double* yd = reinterpret_cast<double*>(y);
+  for (int i = 0; i < n; ++i) {
+    const double xr = xd[2 * i], xi = xd[2 * i + 1], yr = yd[2 * i], yi = yd[2 * i + 1];
+    xd[2 * i] = c * xr + sr * yr + si * yi;        // c x + conj(s) y
+    xd[2 * i + 1] = c * xi + sr * yi - si * yr;
+    yd[2 * i] = c * yr - (sr * xr - si * xi);      // -s x + c y
+    yd[2 * i + 1] = c * yi - (sr * xi + si * xr);
   }
 }
 
@@ -242,25 +293,26 @@ bool eig(const Mat& A, std::vector<cd>& w, Mat* Z) {
       double cs;
       cd sn;
       givens(x, y, cs, sn);
-      // rows k, k+1 (left multiplication by G)
-      for (int j = (k > l ? k - 1 : l); j < n; ++j) {
-        const cd t1 = H(k, j), t2 = H(k + 1, j);
-        H(k, j) = cs * t1 + sn * t2;
-        H(k + 1, j) = -std::conj(sn) * t1 + cs * t2;
+      // rows k, k+1 (left multiplication by G): the two entries of a column
+      // are adjacent in memory
+      {
+        const double sr = sn.real(), si = sn.imag();
+        const int j0 = (k > l ? k - 1 : l);
+        double* p = reinterpret_cast<double*>(&H(k, j0));
+        const size_t stride = 2 * size_t(H.r);
+        for (int j = j0; j < n; ++j, p += stride) {
+          const double ar = p[0], ai = p[1], br = p[2], bi = p[3];
+          p[0] = cs * ar + sr * br - si * bi;        // cs t1 + sn t2
+          p[1] = cs * ai + sr * bi + si * br;
+          p[2] = cs * br - (sr * ar + si * ai);      // -conj(sn) t1 + cs t2
+          p[3] = cs * bi - (sr * ai - si * ar);
+        }
       }
       if (k > l) H(k + 1, k - 1) = 0.0;      // the bulge just chased away
       // columns k, k+1 (right multiplication by G^H)
       const int rmax = std::min(k + 2, hi);
-      for (int i = 0; i <= rmax; ++i) {
-        const cd t1 = H(i, k), t2 = H(i, k + 1);
-        H(i, k) = cs * t1 + std::conj(sn) * t2;
-        H(i, k + 1) = -sn * t1 + cs * t2;
-      }
-      for (int i = 0; i < n; ++i) {
-        const cd t1 = Q(i, k), t2 = Q(i, k + 1);
-        Q(i, k) = cs * t1 + std::conj(sn) * t2;
-        Q(i, k + 1) = -sn * t1 + cs * t2;
-      }
+      rot_cols(rmax + 1, cs, sn, &H(0, k), &H(0, k + 1));
+      rot_cols(n, cs, sn, &Q(0, k), &Q(0, k + 1));
       if (k + 1 < hi) {
         x = H(k + 1, k);
         y = H(k + 2, k);
@@ -269,17 +321,20 @@ bool eig(const Mat& A, std::vector<cd>& w, Mat* Z) {
   }
   if (Z) {
     // H is now upper triangular (Schur form T); eigenvectors of T by back
-    // substitution, then Z = Q y, normalised.
+    // substitution (column-oriented: once y_j is known, the rows above
+    // collect H(0..j-1, j) y_j), then Z = Q y, normalised.
     Mat Y(n, n);
     const double small = eps * (hnorm > 0 ? hnorm : 1.0);
     for (int k = 0; k < n; ++k) {
-      Y(k, k) = 1.0;
+      cd* y = &Y(0, k);     // holds the partial sums above the row solved last
+      y[k] = 1.0;
+      if (k > 0) caxpy(k, cd(1.0), &H(0, k), y);
       for (int i = k - 1; i >= 0; --i) {
-        cd s = 0.0;
-        for (int j = i + 1; j <= k; ++j) s += H(i, j) * Y(j, k);
         cd den = H(i, i) - H(k, k);
         if (std::abs(den) < small) den = small;
-        Y(i, k) = -s / den;
+        const cd yi = -y[i] / den;
+        y[i] = yi;
+        if (i > 0) caxpy(i, yi, &H(0, i), y);
       }
     }
     *Z = matmul(Q, Y);

@@ -52,7 +52,7 @@ def test_default_opts_and_error_paths(lib):
 def test_dense_eig_matches_scipy():
     from paper_2205_09104_amd import dense_eig
     rng = np.random.default_rng(0)
-    for n in (1, 2, 5, 17, 40, 64):
+    for n in (1, 2, 5, 17, 40, 64, 230):
         A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
         ev, Z = dense_eig(A, vectors=True)
         ref = sla.eigvals(A)
@@ -73,6 +73,25 @@ def test_dense_eig_hessenberg_and_degenerate():
     assert max(np.min(np.abs(ref - e)) for e in ev) <= 1e-6
     J = np.diag(np.full(5, 2.0 + 1j))          # multiple eigenvalue, diagonal
     assert np.allclose(dense_eig(J), 2 + 1j)
+
+
+def test_dense_solve_matches_numpy():
+    """The LU solve of the recycle refresh against numpy, including a pivot
+    that must be taken (zero leading entry) and a singular matrix."""
+    from paper_2205_09104_amd import dense_solve
+    from paper_2205_09104_amd._lib import DcError
+    rng = np.random.default_rng(2)
+    for n, k in ((1, 1), (3, 2), (37, 5), (200, 41)):
+        A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+        if n > 1:
+            A[0, 0] = 0.0
+        B = rng.standard_normal((n, k)) + 1j * rng.standard_normal((n, k))
+        X = dense_solve(A, B)
+        ref = np.linalg.solve(A, B)
+        assert np.linalg.norm(X - ref) <= 1e-10 * np.linalg.norm(ref) * n
+    S = np.ones((4, 4), dtype=complex)
+    with pytest.raises(DcError):
+        dense_solve(S, np.ones((4, 1), dtype=complex))
 
 
 def test_dense_lstsq_matches_numpy():
