@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--workload", default="c3")
     p.add_argument("--tol", type=float, default=1e-8)
     p.add_argument("--inner", default="f16s", choices=["f64", "f32", "f16s"])
-    p.add_argument("--d", type=int, default=24)
+    p.add_argument("--d", type=int, default=32)
     p.add_argument("--k", type=int, default=384)
     p.add_argument("--bj", type=int, default=1, choices=[0, 1],
                    help="left block Jacobi (B = D_ee on the reduced system)")
