@@ -69,6 +69,9 @@ def parse():
                    help="timed solves of the same method on the 8^4 workload after the "
                         "headline (0: skip)")
     p.add_argument("--inner-tol", type=float, default=1e-1)
+    p.add_argument("--reduced-kernels", type=int, default=0, choices=[0, 1],
+                   help="reduced operator: 0 the single-read kernel pair where it applies, "
+                        "1 the two-kernel form")
     p.add_argument("--plain-steps", type=int, default=1)
     p.add_argument("--plain-seconds", type=float, default=15.0,
                    help="wall-time cap of each FP64 comparison solve (they can stagnate); "
@@ -126,19 +129,19 @@ def stage1_bytes(V, n, prec):
 
 
 # HBM traffic of one launch of the roofline kernel on the 16^3 x 32,
-# N_tv = 24 twisted-mass workload with FP16 blocks (kernel 2: the reduced
-# operator's x_e - A_e^-1 D_eo t_o kernel, later polynomial-chain step, the
-# launch that makes up 91% of the solves'): rocprofv3 --pmc FETCH_SIZE and
-# --pmc WRITE_SIZE (KiB per dispatch, median over 88 launches) of
+# N_tv = 24 twisted-mass workload with FP16 blocks (kernel 1 of the
+# single-read form: k_reduced_scatter, every launch of the solves' reduced
+# applies): rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB per
+# dispatch, median over 116 launches) of
 # `dc_kernel_probe chain 16 16 16 32 24 f16s 3 0.001`, each scaled by the
 # ratio of true bytes to counter reading for 1 GiB device copies
 # (`dc_kernel_probe copy 1024`: FETCH_SIZE 524299.5 KiB for 1 GiB read,
 # WRITE_SIZE 1048576 KiB for 1 GiB written).  Valid only for the apply
 # source it was taken on.
-TRAFFIC = {"workload": "c3", "prec": "f16s", "kernel": 2,
-           "fetch_kib": 2747144.5938, "fetch_scale": 1048576.0 / 524299.5,
-           "write_kib": 49152.0, "write_scale": 1048576.0 / 1048576.0,
-           "apply_source_sha256": "c8e500cee7fcac117f80ca2c973b4a32e1d8a41b767d85c44b92676e281a9223"}
+TRAFFIC = {"workload": "c3", "prec": "f16s", "kernel": 1,
+           "fetch_kib": 2722595.625, "fetch_scale": 1048576.0 / 524299.5,
+           "write_kib": 196609.421875, "write_scale": 1048576.0 / 1048576.0,
+           "apply_source_sha256": "a98c5c23ddd922b74b4ea7290a3efcd00de920d04402af4365a88de09e7a1494"}
 
 
 def apply_source_digest():
@@ -151,14 +154,18 @@ def apply_source_digest():
     return hashlib.sha256(src[a:b].encode()).hexdigest()
 
 
-def reduced_block_bytes(V, n, prec):
-    """Block bytes of one launch of either kernel of the reduced operator: per
-    row (V/2 of them) nine blocks and their FP16 scales -- the A_o^{-1} D_oe
-    kernel reads the 8 hop blocks of an odd site and its self-block inverse,
-    the A_e - D_eo kernel the 8 hop blocks of an even site and its self block."""
+def reduced_block_bytes(V, n, prec, blocks=9):
+    """Block bytes of one launch of a reduced-operator kernel that reads
+    `blocks` blocks (and their FP16 scales) per row, V/2 rows: nine for either
+    kernel of the two-kernel form (the A_o^{-1} D_oe kernel reads the 8 hop
+    blocks of an odd site and its self-block inverse, the A_e - D_eo kernel the
+    8 hop blocks of an even site and its self block or inverse) and for the
+    single-read form's scatter kernel (the 8 hop blocks of an odd site, each
+    used in both directions, and its inverse); one for its gather kernel (the
+    even site's self block or inverse)."""
     sb = {"f64": 16, "f32": 8, "f16s": 4}[prec]
-    extra = 9 * 4 if prec == "f16s" else 0
-    return (V // 2) * (9 * n * n * sb + extra)
+    extra = blocks * 4 if prec == "f16s" else 0
+    return (V // 2) * (blocks * n * n * sb + extra)
 
 
 def reduced_vec_bytes(V, n, prec):
@@ -167,10 +174,18 @@ def reduced_vec_bytes(V, n, prec):
 
 
 def reduced_apply_bytes(V, n, prec):
-    """Algorithmic bytes of one apply of the reduced operator: both kernels'
-    blocks, one read of the input and one write of the output (the odd-row
-    temporary between the kernels is this design's)."""
-    return 2 * reduced_block_bytes(V, n, prec) + 2 * reduced_vec_bytes(V, n, prec)
+    """Algorithmic bytes of one apply of the reduced operator: every stored
+    block read once (per even/odd site pair the 8 hop blocks joining them to
+    their neighbours and the two self blocks or inverses: ten), one read of the
+    input and one write of the output.  Intermediate vectors between kernels
+    are a design's own and not counted."""
+    return reduced_block_bytes(V, n, prec, blocks=10) + 2 * reduced_vec_bytes(V, n, prec)
+
+
+def single_read(prec, n):
+    """Whether the library's reduced applies take the single-read kernel pair
+    (its default for FP32 / FP16 blocks with n a multiple of 8, n <= 64)."""
+    return prec != "f64" and n % 8 == 0 and 8 <= n <= 64
 
 
 def measured_traffic(workload, prec, kernel):
@@ -242,7 +257,13 @@ def main():
     # HIP events on one in a.profile_every launches of the apply's block kernel
     op.profile_apply(a.profile_every)
 
-    kern = 2 if a.schur else 0     # the roofline kernel: D_eo stage, or the full block kernel
+    import paper_2205_09104_amd as dc
+    dc.set_reduced_kernels(a.reduced_kernels)
+    single = a.schur and a.reduced_kernels == 0 and single_read(a.inner, n)
+    # the roofline kernel: the single-read scatter kernel (slot 1), the D_eo
+    # kernel of the two-kernel form (slot 2), or the full-lattice block kernel
+    kern = (1 if single else 2) if a.schur else 0
+    other = 3 - kern if a.schur else None
 
     def prof_totals(kernel=None):
         kk = kern if kernel is None else kernel
@@ -368,8 +389,9 @@ def main():
     rhs = [synth.rhs(w.dims, w.n_tv, r, device="cuda") for r in range(a.warmup, a.warmup + a.steps)]
     torch.cuda.synchronize()
     pre = prof_totals()
-    pre_oe = prof_totals(1)
-    pre_pass = {p: (op.profile_apply_passes(p, kern), op.profile_apply_passes(p, 1))
+    pre_oe = prof_totals(other) if a.schur else None
+    pre_pass = {p: (op.profile_apply_passes(p, kern),
+                    op.profile_apply_passes(p, other) if a.schur else 0)
                 for p in ("f64", "f32", "f16s")}
     t0 = time.perf_counter()
     stats = []
@@ -382,14 +404,15 @@ def main():
     dt = time.perf_counter() - t0
     x_last = x
     post = prof_totals()
-    post_oe = prof_totals(1)
+    post_oe = prof_totals(other) if a.schur else None
     # timed-region block-kernel launches that did work: (count, ms) per
     # precision, and their vector passes
     prof = {p: (post[p][0][0] - pre[p][0][0], post[p][0][1] - pre[p][0][1]) for p in post}
-    prof_oe = {p: (post_oe[p][0][0] - pre_oe[p][0][0], post_oe[p][0][1] - pre_oe[p][0][1])
-               for p in post_oe}
+    prof_oe = ({p: (post_oe[p][0][0] - pre_oe[p][0][0], post_oe[p][0][1] - pre_oe[p][0][1])
+                for p in post_oe} if a.schur else {})
     passes = {p: op.profile_apply_passes(p, kern) - pre_pass[p][0] for p in pre_pass}
-    passes_oe = {p: op.profile_apply_passes(p, 1) - pre_pass[p][1] for p in pre_pass}
+    passes_oe = ({p: op.profile_apply_passes(p, other) - pre_pass[p][1] for p in pre_pass}
+                 if a.schur else {})
     ok = all(s["status"] == 0 and s["rel_res_true"] <= a.tol for s in stats)
     value = a.steps / dt if ok else 0.0
     log(f"method: {value:.3f} solves/s ({1e3 * dt / a.steps:.0f} ms per solve)")
@@ -529,15 +552,19 @@ def main():
     launches, tot_ms = prof[inner]
     avg_us = 1e3 * tot_ms / max(launches, 1)
     if a.schur:
-        # per launch: the nine blocks per row, plus the vector passes of its
-        # epilogue (2 to 5; summed over the timed launches by the library)
+        # per launch: the nine blocks per row, plus its vector passes (summed
+        # over the timed launches by the library: the scatter kernel x_e and its
+        # eight partial vectors; the D_eo kernel 2 to 5 with its epilogue)
         s1b = (launches * reduced_block_bytes(V, n, inner) +
                passes[inner] * reduced_vec_bytes(V, n, inner)) / max(launches, 1)
     else:
         s1b = stage1_bytes(V, n, inner)
     achieved = s1b / (avg_us * 1e-6) / 1e9 if launches else None
     traffic, traffic_detail = measured_traffic(w.name, inner, kern)
-    if a.schur and a.bj:
+    if single:
+        kname = (f"k_reduced_scatter ({inner} blocks; per odd row t_o = A_o^-1 D_oe x_e and, "
+                 f"from the same read of each hop block, the eight D_eo products of t_o)")
+    elif a.schur and a.bj:
         kname = (f"k_reduced_eo ({inner} blocks; x_e - A_e^-1 D_eo t_o with the chain "
                  f"epilogue)")
     elif a.schur:
@@ -548,9 +575,12 @@ def main():
     if a.schur:
         l1, m1 = prof_oe[inner]
         if l1:
-            b1 = (l1 * reduced_block_bytes(V, n, inner) +
+            b1 = (l1 * reduced_block_bytes(V, n, inner, blocks=1 if single else 9) +
                   passes_oe[inner] * reduced_vec_bytes(V, n, inner)) / l1
-            oe = {"kernel": f"k_reduced_oe ({inner} blocks; t_o = A_o^-1 D_oe x_e)",
+            oname = (f"k_reduced_gather ({inner} blocks; the eight partial vectors summed per "
+                     f"even row, A_e^-1 and the chain epilogue)" if single else
+                     f"k_reduced_oe ({inner} blocks; t_o = A_o^-1 D_oe x_e)")
+            oe = {"kernel": oname,
                   "timed_launches": l1, "avg_us": 1e3 * m1 / l1, "bytes_per_launch": b1,
                   "GB/s": b1 / (1e-3 * m1 / l1) / 1e9}
     line = {

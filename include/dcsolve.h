@@ -246,7 +246,8 @@ int dc_apply_reduced(dc_op_t op, int32_t prec, int32_t adjoint, const void* in, 
 
 /* dc_apply_reduced for callers that cannot allocate (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
- * kernels and result, with the odd-row temporary t_o = D_oo^{-1} D_oe in kept
+ * result, always through the two-kernel form of dc_set_reduced_kernels (equal
+ * bit for bit to the other), with the odd-row temporary t_o = D_oo^{-1} D_oe in kept
  * in a fixed device array of the library (64 MiB per GPU, held until the
  * process ends) instead of the handle's memory.  It calls no allocating
  * routine at all, so:
@@ -477,6 +478,18 @@ int dc_profile_apply_passes(dc_op_t op, int32_t prec, int32_t kernel, int64_t* p
  * output entry). */
 int dc_multi_tile(int32_t prec, int32_t n, int32_t n_rhs, int32_t sites);
 int dc_set_multi_tile_mode(int32_t mode);
+
+/* Kernel form of the reduced operator S = D_ee - D_eo D_oo^{-1} D_oe (Sec. 2.2,
+ * factored form) in dc_apply_reduced, dc_apply_reduced_bj and the reduced
+ * solves; process-wide.  mode 0 (default): for FP32 and FP16 blocks with n a
+ * multiple of 8 (n <= 64), one kernel over the odd rows reads every hop block
+ * once, forms D_oo^{-1} D_oe in and from the same read the D_eo products, and a
+ * second kernel sums those per even row (ten blocks read per even/odd site
+ * pair); FP64 and other n use the two-kernel form.  mode 1: always the
+ * two-kernel form (each kernel reads the hop blocks of its rows: eighteen
+ * blocks per pair).  The two forms add the same terms in the same order, so
+ * results are equal bit for bit.  Other values: DC_ERR_INVALID. */
+int dc_set_reduced_kernels(int32_t mode);
 
 /* Message of the last error on this thread ("" if none). */
 const char* dc_last_error(void);

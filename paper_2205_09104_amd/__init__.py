@@ -424,6 +424,13 @@ def set_multi_tile_mode(mode: int):
     check(load().dc_set_multi_tile_mode(int(mode)))
 
 
+def set_reduced_kernels(mode: int):
+    """Reduced operator's kernel form (process-wide): 0 the single-read pair
+    where it applies (FP32 / FP16 blocks, n a multiple of 8), 1 always the
+    two-kernel form; equal results."""
+    check(load().dc_set_reduced_kernels(int(mode)))
+
+
 def dense_eig(A: np.ndarray, vectors=False):
     lib = load()
     n = A.shape[0]

@@ -502,6 +502,13 @@ int dc_set_multi_tile_mode(int32_t mode) {
   });
 }
 
+int dc_set_reduced_kernels(int32_t mode) {
+  return guarded([&] {
+    dc::set_reduced_mode(mode);
+    return DC_OK;
+  });
+}
+
 int dc_profile_apply(dc_op_t op, int32_t every) {
   return guarded([&] {
     if (!op) throw dc::InvalidArg("null handle");

@@ -7,11 +7,13 @@
 //   dc_kernel_probe multi   L0 L1 L2 L3 n_tv prec n_rhs reps [mu]
 //   dc_kernel_probe reduced L0 L1 L2 L3 n_tv prec reps [mu]     (block Jacobi form)
 //   dc_kernel_probe chain   L0 L1 L2 L3 n_tv prec reps [mu]     (q(B^-1 S) chains, d = 24)
+//   dc_kernel_probe reduced2 | chain2 ...                      (the same, two-kernel form)
 //   dc_kernel_probe copy    MiB                                 (5 device copies)
 //
 // The chain mode runs the solver's polynomial-chain launches on the odd-even
 // reduced system with block Jacobi: each q application is d - 1 applies of
-// B^-1 S with the chain epilogues.
+// B^-1 S with the chain epilogues.  reduced / chain use the library's default
+// kernel form of the reduced operator, reduced2 / chain2 the two-kernel form.
 //
 // The copy mode calibrates byte counters: each copy reads and writes exactly
 // MiB mebibytes of HBM-resident data.
@@ -90,14 +92,15 @@ int main(int argc, char** argv) {
   if (argc < 9) {
     std::fprintf(stderr,
                  "usage: %s multi L0 L1 L2 L3 n_tv prec n_rhs reps [mu]\n"
-                 "       %s reduced|chain L0 L1 L2 L3 n_tv prec reps [mu]\n"
+                 "       %s reduced|chain|reduced2|chain2 L0 L1 L2 L3 n_tv prec reps [mu]\n"
                  "       %s copy MiB\n",
                  argv[0], argv[0], argv[0]);
     return 2;
   }
   const std::string mode = argv[1];
-  const bool multi = mode == "multi", chain = mode == "chain";
-  if (!multi && !chain && mode != "reduced") {
+  const bool two = mode == "reduced2" || mode == "chain2";
+  const bool multi = mode == "multi", chain = mode == "chain" || mode == "chain2";
+  if (!multi && !chain && mode != "reduced" && mode != "reduced2") {
     std::fprintf(stderr, "unknown mode %s\n", mode.c_str());
     return 2;
   }
@@ -159,6 +162,7 @@ int main(int argc, char** argv) {
   hip_ok(hipMalloc(&y, count * zb), "hipMalloc");
   hip_ok(hipMemcpy(x, zb == 16 ? static_cast<const void*>(h64.data()) : h32.data(), count * zb,
                    hipMemcpyHostToDevice), "hipMemcpy");
+  if (two) dc_ok(dc_set_reduced_kernels(1), "dc_set_reduced_kernels");
   dc_solve_opts po;
   dc_ok(dc_default_opts(&po), "dc_default_opts");
   po.d = 24;

@@ -880,6 +880,194 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_reduced_eo(
   }
 }
 
+// Single-read form of the same operator.  Each hop block couples exactly one
+// odd and one even site, so the odd row's workgroup can apply it in both
+// directions while it holds it: k_reduced_scatter forms t_o(x) as k_reduced_oe
+// does (same waves, same order), keeps the eight hop tiles in registers across
+// the barriers, and then applies each of them the other way to t_o(x), which
+// gives one of the eight D_eo products of the even neighbour it couples to.
+// Those go to hp[row][slot][n] of that even row: slots 0-3 its forward hops
+// B[e,mu] t_o(e+mu), 4-7 its backward hops Gamma5 B[e-mu,mu]^H Gamma5 t_o(e-mu);
+// every (row, slot) has exactly one writer.  k_reduced_gather then sums the
+// eight slots in that order and finishes the row with A_e (or A_e^{-1} for
+// block Jacobi) and the epilogue.  Per site pair ten blocks are read instead
+// of eighteen; the sums and signs are those of the two-kernel form, so the
+// results agree with it bit for bit.
+// FP16 tiles up to n = 48 fit three 9-wave workgroups per CU (7 waves per
+// SIMD, at most 72 registers) without spilling; larger tiles keep the default.
+template <int T, int P>
+constexpr int scatter_min_waves() { return (P == P16S && T <= 6) ? 7 : 1; }
+
+template <int T, int P>
+__global__ __launch_bounds__(64 * kRedWaves, (scatter_min_waves<T, P>())) void k_reduced_scatter(
+    const void* __restrict__ blocks, const float* __restrict__ scales,
+    const void* __restrict__ inv, const float* __restrict__ invsc,
+    const cx<typename VecOf<P>::R>* __restrict__ x_e, cx<typename VecOf<P>::R>* __restrict__ hp,
+    const int* __restrict__ nbr, const int* __restrict__ osite, int V, int n, int chunk,
+    const int* __restrict__ done) {
+  using A = typename Tile<T, P>::A;
+  using VR = typename VecOf<P>::R;
+  __shared__ cx<VR> part[8][64];
+  __shared__ cx<VR> tx[64];
+  if (done && *done) return;
+  const int b = blockIdx.x;
+  const int r = (b & 7) * chunk + (b >> 3);
+  if (r >= (V >> 1)) return;   // uniform per workgroup: no barrier is skipped by part of it
+  const int x = osite[r];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  TileRegs<T, P> R;
+  A s = A(1);
+  size_t dst = 0;   // element offset of this wave's D_eo product in hp
+  if (w < 4) {
+    const int item = 5 * x + 1 + w;
+    R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+    if (P == P16S) s = A(scales[item]);
+    const int src = nbr[w * V + x];
+    wave_product<T, P, true, 1>(R, s, x_e + size_t(src >> 1) * n, part[w], n, 0.0, lane);
+    dst = (size_t(src >> 1) * 8 + 4 + w) * n;        // backward hop mu = w of even x + mu
+  } else if (w < 8) {
+    const int mu = w - 4;
+    const int y = nbr[(4 + mu) * V + x];
+    const int item = 5 * y + 1 + mu;
+    R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+    if (P == P16S) s = A(scales[item]);
+    wave_product<T, P, true, 2>(R, s, x_e + size_t(y >> 1) * n, part[w], n, 0.0, lane);
+    dst = (size_t(y >> 1) * 8 + mu) * n;             // forward hop mu of even x - mu
+  } else {
+    R.load(block_ptr<T, P>(inv, size_t(x)), lane);   // this wave's only block
+  }
+  __syncthreads();
+  if (w == 8) {
+    const int lr = lane >> 3, lc = lane & 7;
+    cx<A> pc[T], pr[T], f[T], g[T];
+    A npc_im[T], npr_re[T];
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      const int col = lc * T + q;
+      cx<VR> t = part[0][col];
+#pragma unroll
+      for (int k = 1; k < 8; ++k) {
+        t.re += part[k][col].re;
+        t.im += part[k][col].im;
+      }
+      pc[q] = mk(A(t.re), A(t.im));
+      npc_im[q] = -pc[q].im;
+      pr[q] = mk(A(0), A(0));
+      npr_re[q] = A(0);
+      f[q] = mk(A(0), A(0));
+      g[q] = mk(A(0), A(0));
+    }
+    tile_products<T, P, true, false>(R, pc, npc_im, pr, npr_re, f, g);
+    const A si = (P == P16S) ? A(invsc[x]) : A(1);
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      f[q].re = sum_row8(f[q].re) * si;
+      f[q].im = sum_row8(f[q].im) * si;
+    }
+    if (lc == 0) {
+#pragma unroll
+      for (int q = 0; q < T; ++q) tx[lr * T + q] = mk(VR(f[q].re), VR(f[q].im));
+    }
+  }
+  __syncthreads();
+  if (w < 4)
+    wave_product<T, P, true, 2>(R, s, tx, hp + dst, n, 0.0, lane);
+  else if (w < 8)
+    wave_product<T, P, true, 1>(R, s, tx, hp + dst, n, 0.0, lane);
+}
+
+// Second kernel of the single-read form: one wave per even row r (site
+// x = esite[r]).  The eight slots of hp[r], negated and summed in slot order,
+// are the hop terms k_reduced_eo sums from its own products; the row is then
+// finished as there: BJ x_e + A_e^{-1} (sum), else A_e x_e (+ i tm Gamma5 x_e)
+// with the terms added one by one, and the epilogue.
+template <int T, int P, int EPI, bool BJ>
+__global__ __launch_bounds__(64) void k_reduced_gather(
+    const void* __restrict__ blocks, const float* __restrict__ scales,
+    const void* __restrict__ einv, const float* __restrict__ einvsc,
+    const cx<typename VecOf<P>::R>* x_e, const cx<typename VecOf<P>::R>* __restrict__ hp,
+    const int* __restrict__ esite, int V, int n, int chunk, double tm,
+    cx<typename VecOf<P>::R>* out, const cx<typename VecOf<P>::R>* e, cx<typename VecOf<P>::R>* y,
+    z64 c0, z64 ca, z64 cb, const int* __restrict__ done) {
+  using A = typename Tile<T, P>::A;
+  using VR = typename VecOf<P>::R;
+  __shared__ cx<VR> self_part[64];
+  __shared__ cx<VR> tsum[64];
+  if (done && *done) return;
+  const int b = blockIdx.x;
+  const int r = (b & 7) * chunk + (b >> 3);
+  if (r >= (V >> 1)) return;
+  const int x = esite[r];
+  const int lane = threadIdx.x;
+  TileRegs<T, P> R;
+  if (BJ) R.load(block_ptr<T, P>(einv, size_t(x)), lane);
+  cx<VR> h[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    h[k] = mk(VR(0), VR(0));
+    if (lane < n) h[k] = hp[(size_t(r) * 8 + k) * n + lane];
+  }
+  if constexpr (BJ) {
+    cx<VR> t = mk(-h[0].re, -h[0].im);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+      t.re += -h[k].re;
+      t.im += -h[k].im;
+    }
+    tsum[lane] = t;
+    __syncthreads();
+    const int lr = lane >> 3, lc = lane & 7;
+    cx<A> pc[T], pr[T], f[T], g[T];
+    A npc_im[T], npr_re[T];
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      const cx<VR> u = tsum[lc * T + q];
+      pc[q] = mk(A(u.re), A(u.im));
+      npc_im[q] = -pc[q].im;
+      pr[q] = mk(A(0), A(0));
+      npr_re[q] = A(0);
+      f[q] = mk(A(0), A(0));
+      g[q] = mk(A(0), A(0));
+    }
+    tile_products<T, P, true, false>(R, pc, npc_im, pr, npr_re, f, g);
+    const A s = (P == P16S) ? A(einvsc[x]) : A(1);
+    cx<A> mine = mk(A(0), A(0));
+#pragma unroll
+    for (int q = 0; q < T; ++q) {
+      const A fr = sum_row8(f[q].re) * s, fi = sum_row8(f[q].im) * s;
+      if (q == lc) mine = mk(fr, fi);
+    }
+    const int row = lr * T + lc;
+    if (lc >= T) return;
+    const size_t i = size_t(r) * n + row;
+    cx<VR> o = mk(VR(mine.re), VR(mine.im));
+    if (x_e) {
+      const cx<VR> xv = x_e[i];
+      o.re += xv.re;
+      o.im += xv.im;
+    }
+    reduced_epilogue<EPI>(i, o, out, e, y, c0, ca, cb);
+  } else {
+    if (x_e) {
+      const int item = 5 * x;
+      R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+      const A s = (P == P16S) ? A(scales[item]) : A(1);
+      wave_product<T, P, true, 0>(R, s, x_e + size_t(r) * n, self_part, n, tm, lane);
+    } else {
+      self_part[lane] = mk(VR(0), VR(0));
+    }
+    __syncthreads();
+    if (lane >= n) return;
+    cx<VR> o = self_part[lane];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      o.re += -h[k].re;
+      o.im += -h[k].im;
+    }
+    reduced_epilogue<EPI>(size_t(r) * n + lane, o, out, e, y, c0, ca, cb);
+  }
+}
+
 // Sum of the 9 slots in a fixed order: self, forward hops, backward hops.
 template <typename VR>
 __device__ inline cx<VR> gather5(const cx<VR>* __restrict__ gbuf, size_t i, int n) {
@@ -2675,6 +2863,135 @@ void launch_reduced_eo(Prec p, int epi, int n, int V, const void* blocks, const 
   if (p == P64) reduced_eo_P<P64>(DC_ARGS);
   else if (p == P32) reduced_eo_P<P32>(DC_ARGS);
   else reduced_eo_P<P16S>(DC_ARGS);
+#undef DC_ARGS
+}
+
+namespace {
+int g_reduced_mode = 0;
+}
+
+void set_reduced_mode(int mode) {
+  if (mode < 0 || mode > 1) throw InvalidArg("reduced kernel mode must be 0 or 1");
+  g_reduced_mode = mode;
+}
+
+int reduced_mode() { return g_reduced_mode; }
+
+bool reduced_single_read(Prec p, int n) {
+  return g_reduced_mode != 1 && p != P64 && n % 8 == 0 && n >= 8 && n <= 64;
+}
+
+template <int P>
+static void reduced_scatter_T(int n, int V, const void* blocks, const float* scales,
+                              const void* inv, const float* invsc, const void* x_e, void* hp,
+                              const int* nbr, const int* osite, const int* done, hipStream_t st,
+                              hipEvent_t ev0, hipEvent_t ev1) {
+  using VR = typename VecOf<P>::R;
+  const int rows = V / 2;
+  const int chunk = (rows + 7) / 8;
+  const dim3 grid(unsigned(chunk) * 8u), block(64 * kRedWaves);
+  const auto* xe = static_cast<const cx<VR>*>(x_e);
+  auto* h = static_cast<cx<VR>*>(hp);
+  switch (n / 8) {
+#define DC_CASE(TV)                                                                          \
+  case TV:                                                                                   \
+    hipExtLaunchKernelGGL((k_reduced_scatter<TV, P>), grid, block, 0, st, ev0, ev1, 0, blocks, \
+                          scales, inv, invsc, xe, h, nbr, osite, V, n, chunk, done);         \
+    break;
+    DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
+#undef DC_CASE
+    default:
+      throw InvalidArg("the single-read reduced kernels need n = 8, 16, ..., 64");
+  }
+  DC_HIP(hipGetLastError());
+}
+
+void launch_reduced_scatter(Prec p, int n, int V, const void* blocks, const float* scales,
+                            const void* inv, const float* invsc, const void* x_e, void* hp,
+                            const int* nbr, const int* osite, const int* done, hipStream_t st,
+                            hipEvent_t ev0, hipEvent_t ev1) {
+  if (V < 2 || V % 2) throw InvalidArg("the reduced operator needs an even number of sites");
+  if (p == P64 || n % 8 || n < 8 || n > 64)
+    throw InvalidArg("the single-read reduced kernels take FP32 / FP16 blocks with n = 8, ..., 64");
+  if (p == P16S && (!scales || !invsc)) throw InvalidArg("FP16 blocks need their scales");
+  if (!x_e || !hp || !inv) throw InvalidArg("null pointer");
+  if (p == P32) reduced_scatter_T<P32>(n, V, blocks, scales, inv, invsc, x_e, hp, nbr, osite, done, st, ev0, ev1);
+  else reduced_scatter_T<P16S>(n, V, blocks, scales, inv, invsc, x_e, hp, nbr, osite, done, st, ev0, ev1);
+}
+
+template <int P, int EPI, bool BJ>
+static void reduced_gather_T(int n, int V, const void* blocks, const float* scales,
+                             const void* einv, const float* einvsc, const void* x_e,
+                             const void* hp, const int* esite, double tm, void* out,
+                             const void* e, void* y, z64 c0, z64 ca, z64 cb, const int* done,
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  using VR = typename VecOf<P>::R;
+  const int rows = V / 2;
+  const int chunk = (rows + 7) / 8;
+  const dim3 grid(unsigned(chunk) * 8u), block(64);
+  const auto* xe = static_cast<const cx<VR>*>(x_e);
+  const auto* h = static_cast<const cx<VR>*>(hp);
+  auto* o = static_cast<cx<VR>*>(out);
+  const auto* ee = static_cast<const cx<VR>*>(e);
+  auto* yy = static_cast<cx<VR>*>(y);
+  switch (n / 8) {
+#define DC_CASE(TV)                                                                            \
+  case TV:                                                                                     \
+    hipExtLaunchKernelGGL((k_reduced_gather<TV, P, EPI, BJ>), grid, block, 0, st, ev0, ev1, 0, \
+                          blocks, scales, einv, einvsc, xe, h, esite, V, n, chunk, tm, o, ee, yy, \
+                          c0, ca, cb, done);                                                   \
+    break;
+    DC_CASE(1) DC_CASE(2) DC_CASE(3) DC_CASE(4) DC_CASE(5) DC_CASE(6) DC_CASE(7) DC_CASE(8)
+#undef DC_CASE
+    default:
+      throw InvalidArg("the single-read reduced kernels need n = 8, 16, ..., 64");
+  }
+  DC_HIP(hipGetLastError());
+}
+
+template <int P>
+static void reduced_gather_P(int epi, int n, int V, const void* blocks, const float* scales,
+                             const void* einv, const float* einvsc, const void* x_e,
+                             const void* hp, const int* esite, double tm, void* out,
+                             const void* e, void* y, z64 c0, z64 ca, z64 cb, const int* done,
+                             hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+#define DC_ARGS n, V, blocks, scales, einv, einvsc, x_e, hp, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1
+  if (einv) {
+    switch (epi) {
+      case 0: reduced_gather_T<P, 0, true>(DC_ARGS); break;
+      case 1: reduced_gather_T<P, 1, true>(DC_ARGS); break;
+      default: reduced_gather_T<P, 2, true>(DC_ARGS); break;
+    }
+    return;
+  }
+  switch (epi) {
+    case 0: reduced_gather_T<P, 0, false>(DC_ARGS); break;
+    case 1: reduced_gather_T<P, 1, false>(DC_ARGS); break;
+    case 2: reduced_gather_T<P, 2, false>(DC_ARGS); break;
+    default: reduced_gather_T<P, 3, false>(DC_ARGS); break;
+  }
+#undef DC_ARGS
+}
+
+void launch_reduced_gather(Prec p, int epi, int n, int V, const void* blocks,
+                           const float* scales, const void* einv, const float* einvsc,
+                           const void* x_e, const void* hp, const int* esite, double tm,
+                           void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
+                           const int* done, hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  if (epi < 0 || epi > 3) throw InvalidArg("reduced epilogue must be 0..3");
+  if (einv && epi == 3) throw InvalidArg("the residual epilogue takes the unpreconditioned operator");
+  if (p == P64 || n % 8 || n < 8 || n > 64)
+    throw InvalidArg("the single-read reduced kernels take FP32 / FP16 blocks with n = 8, ..., 64");
+  if (p == P16S && ((einv && !einvsc) || (!einv && !scales)))
+    throw InvalidArg("FP16 blocks need their scales");
+  if (V < 2 || V % 2) throw InvalidArg("the reduced operator needs an even number of sites");
+  if (!hp || !out) throw InvalidArg("null vector pointer");
+  if (einv && !x_e) throw InvalidArg("block Jacobi needs x_e");
+  if ((epi == 1 || epi == 3) && !e) throw InvalidArg("null epilogue input");
+  if ((epi == 1 || epi == 2) && !y) throw InvalidArg("null chain output");
+#define DC_ARGS epi, n, V, blocks, scales, einv, einvsc, x_e, hp, esite, tm, out, e, y, c0, ca, cb, done, st, ev0, ev1
+  if (p == P32) reduced_gather_P<P32>(DC_ARGS);
+  else reduced_gather_P<P16S>(DC_ARGS);
 #undef DC_ARGS
 }
 

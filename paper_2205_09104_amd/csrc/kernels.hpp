@@ -106,6 +106,29 @@ void launch_reduced_eo(Prec p, int epi, int n, int V, const void* blocks, const 
                        const int* nbr, const int* esite, double tm, void* out, const void* e,
                        void* y, z64 c0, z64 ca, z64 cb, const int* done, hipStream_t st,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Single-read form of the same operator (FP32 / FP16 blocks, n a multiple of
+// 8 up to 64): launch_reduced_scatter forms t_o as launch_reduced_oe does and,
+// from the same read of each hop block, the eight D_eo products of t_o that each
+// even row needs, into hp: [V/2][8][n] vectors of the vector precision (slots
+// 0-3 forward hops mu, 4-7 backward hops mu); launch_reduced_gather sums them
+// and finishes the rows as launch_reduced_eo does (same arguments, hp in place
+// of t_o).  Results equal the two-kernel form's bit for bit.
+void launch_reduced_scatter(Prec p, int n, int V, const void* blocks, const float* scales,
+                            const void* inv, const float* invsc, const void* x_e, void* hp,
+                            const int* nbr, const int* osite, const int* done, hipStream_t st,
+                            hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+void launch_reduced_gather(Prec p, int epi, int n, int V, const void* blocks,
+                           const float* scales, const void* einv, const float* einvsc,
+                           const void* x_e, const void* hp, const int* esite, double tm,
+                           void* out, const void* e, void* y, z64 c0, z64 ca, z64 cb,
+                           const int* done, hipStream_t st, hipEvent_t ev0 = nullptr,
+                           hipEvent_t ev1 = nullptr);
+// Which form the solver's reduced applies take (process-wide): mode 0
+// (default) the single-read pair where it applies (reduced_single_read), 1
+// always the two-kernel form.
+void set_reduced_mode(int mode);
+int reduced_mode();
+bool reduced_single_read(Prec p, int n);
 // split a full-lattice vector into its compressed even and odd halves, or merge
 // them back (dir 0: split, 1: merge); esite/osite: int32 [V/2] row -> site
 void launch_oddeven_split(Prec p, int n, int half_sites, const int* esite, const int* osite,

@@ -501,6 +501,47 @@ static void reduced_eo(Op& op, Prec p, int epi, const void* einv, const float* e
   }
 }
 
+// The single-read pair (launch_reduced_scatter / launch_reduced_gather), timed
+// in the same slots as the two-kernel form's first and second kernel.  hp is
+// the full-lattice apply's partial buffer (V x 9 x n vectors, at least the
+// V/2 x 8 x n the pair needs); the two uses never overlap on the stream.
+static void reduced_scatter(Op& op, Prec p, const void* inv, const float* invsc,
+                            const void* x_e, void* hp, const int* done, hipStream_t st) {
+  ApplyProfile& pr = op.prof;
+  hipEvent_t a = nullptr, b = nullptr;
+  const int slot = 3 + prec_slot(p);
+  if (pr.sample(slot)) {
+    if (pr.tag < 0 && pr.recs.size() >= 2048) pr.flush();
+    if (!pr.take(&a, &b)) ++pr.missed;
+  }
+  launch_reduced_scatter(p, op.n, op.V, op.blocks(p), op.scales(p), inv, invsc, x_e, hp,
+                         op.nbr.as<int>(), op.osite.as<int>(), done, st, a, b);
+  // x_e read once, eight partial vectors written
+  if (a) pr.recs.push_back({a, b, slot, done ? pr.tag : -1, false, 9});
+}
+
+static void reduced_gather(Op& op, Prec p, int epi, const void* einv, const float* einvsc,
+                           const void* x_e, const void* hp, double tm, void* out, const void* e,
+                           void* y, z64 c0, z64 ca, z64 cb, const int* done, hipStream_t st) {
+  ApplyProfile& pr = op.prof;
+  hipEvent_t a = nullptr, b = nullptr;
+  const int slot = 6 + prec_slot(p);
+  if (pr.sample(slot)) {
+    if (pr.tag < 0 && pr.recs.size() >= 2048) pr.flush();
+    if (!pr.take(&a, &b)) ++pr.missed;
+  }
+  launch_reduced_gather(p, epi, op.n, op.V, op.blocks(p), op.scales(p), einv, einvsc, x_e, hp,
+                        op.esite.as<int>(), tm, out, e, y, c0, ca, cb, done, st, a, b);
+  if (a) {
+    // the eight partial vectors, x_e, the epilogue's inputs, and the writes
+    int passes = 8 + (x_e ? 1 : 0);
+    if ((epi == 1 || epi == 3) && e != x_e) ++passes;
+    if (epi == 2) passes += (out != x_e ? 1 : 0) + 1;
+    passes += (epi == 1 || epi == 2) ? 2 : 1;
+    pr.recs.push_back({a, b, slot, done ? pr.tag : -1, false, passes});
+  }
+}
+
 void op_profile(Op& op, int every) {
   if (every < 0) throw InvalidArg("sampling period must be >= 0");
   op.prof.reset();
@@ -602,9 +643,16 @@ void op_apply_reduced(Op& op, Prec p, int adjoint, int block_jacobi, const void*
     src = out;
   }
   const z64 z = mk(0.0, 0.0);
-  reduced_oe(op, p, inv, invsc, src, ts, nullptr, st);
-  // the D_eo kernel reads src only on its own row before writing that row of out
-  reduced_eo(op, p, 0, bj_e, bj_esc, src, ts, tm, out, nullptr, nullptr, z, z, z, nullptr, st);
+  if (reduced_single_read(p, op.n)) {
+    void* hp = op.gbuf(p);
+    reduced_scatter(op, p, inv, invsc, src, hp, nullptr, st);
+    reduced_gather(op, p, 0, bj_e, bj_esc, src, hp, tm, out, nullptr, nullptr, z, z, z, nullptr,
+                   st);
+  } else {
+    reduced_oe(op, p, inv, invsc, src, ts, nullptr, st);
+    // the D_eo kernel reads src only on its own row before writing that row of out
+    reduced_eo(op, p, 0, bj_e, bj_esc, src, ts, tm, out, nullptr, nullptr, z, z, z, nullptr, st);
+  }
   if (adjoint) launch_gamma5(p, out, out, half, op.n, st);
 }
 
@@ -806,9 +854,8 @@ struct Krylov {
       oinv = bj_blocks(b, p);
       oinvsc = (p == P16S) ? b.sc16.as<float>() : nullptr;
       ts = static_cast<Z*>(op.tmp_s(p));
-    } else {
-      gb = op.gbuf(p);
     }
+    gb = op.gbuf(p);   // full-lattice partials, or the single-read pair's hp
     if (v.bj) {
       const Op::BJ& b = op.ensure_bj(v.sign, st);
       bjinv = bj_blocks(b, p);
@@ -884,6 +931,12 @@ struct Krylov {
   void reduced(const Z* in, int epi, Z* out, const Z* e, Z* y, z64 c0, z64 ca, z64 cb,
                const int* done) {
     const bool lbj = bjinv && epi != 3;
+    if (reduced_single_read(p, op.n)) {
+      reduced_scatter(op, p, oinv, oinvsc, in, gb, done, st);
+      reduced_gather(op, p, epi, lbj ? bjinv : nullptr, lbj ? bjsc : nullptr, in, gb, tm, out, e,
+                     y, c0, ca, cb, done, st);
+      return;
+    }
     reduced_oe(op, p, oinv, oinvsc, in, ts, done, st);
     reduced_eo(op, p, epi, lbj ? bjinv : nullptr, lbj ? bjsc : nullptr, in, ts, tm, out, e, y,
                c0, ca, cb, done, st);
