@@ -139,9 +139,9 @@ def stage1_bytes(V, n, prec):
 # WRITE_SIZE 1048576 KiB for 1 GiB written).  Valid only for the apply
 # source it was taken on.
 TRAFFIC = {"workload": "c3", "prec": "f16s", "kernel": 1,
-           "fetch_kib": 2722595.625, "fetch_scale": 1048576.0 / 524299.5,
-           "write_kib": 196609.421875, "write_scale": 1048576.0 / 1048576.0,
-           "apply_source_sha256": "a98c5c23ddd922b74b4ea7290a3efcd00de920d04402af4365a88de09e7a1494"}
+           "fetch_kib": 2697056.625, "fetch_scale": 1048576.0 / 524299.5,
+           "write_kib": 196610.40625, "write_scale": 1048576.0 / 1048576.0,
+           "apply_source_sha256": "dda0ff2aaa16e0f8773e008b6331767753e29bd54322e54355adb4e8c90050c4"}
 
 
 def apply_source_digest():

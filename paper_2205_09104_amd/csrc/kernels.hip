@@ -359,6 +359,7 @@ template <int T, int P>
 struct TileRegs {
   cx<typename Tile<T, P>::A> m[T * T];
   __device__ void load(const void* base, int lane) { Tile<T, P>::load(base, lane, m); }
+  __device__ void load_stream(const void* base, int lane) { load(base, lane); }
   __device__ float re(int e) const { return m[e].re; }
 };
 
@@ -372,6 +373,19 @@ struct TileRegs<T, P16S> {
 #pragma unroll
     for (int u = 0; u < UNITS; ++u) {
       const uint4 v = p[u * 64 + lane];
+      w[4 * u] = v.x;
+      w[4 * u + 1] = v.y;
+      w[4 * u + 2] = v.z;
+      w[4 * u + 3] = v.w;
+    }
+  }
+  // the same with non-temporal loads, for tiles that one launch reads once
+  __device__ void load_stream(const void* base, int lane) {
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4* p = static_cast<const u32x4*>(base);
+#pragma unroll
+    for (int u = 0; u < UNITS; ++u) {
+      const u32x4 v = __builtin_nontemporal_load(p + u * 64 + lane);
       w[4 * u] = v.x;
       w[4 * u + 1] = v.y;
       w[4 * u + 2] = v.z;
@@ -883,23 +897,31 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_reduced_eo(
 // Single-read form of the same operator.  Each hop block couples exactly one
 // odd and one even site, so the odd row's workgroup can apply it in both
 // directions while it holds it: k_reduced_scatter forms t_o(x) as k_reduced_oe
-// does (same waves, same order), keeps the eight hop tiles in registers across
-// the barriers, and then applies each of them the other way to t_o(x), which
-// gives one of the eight D_eo products of the even neighbour it couples to.
-// Those go to hp[row][slot][n] of that even row: slots 0-3 its forward hops
+// does (same products, same order), keeps the eight hop tiles in registers
+// across the barriers, and then applies each of them the other way to t_o(x),
+// which gives one of the eight D_eo products of the even neighbour it couples
+// to.  Those go to hp[row][slot][n] of that even row: slots 0-3 its forward hops
 // B[e,mu] t_o(e+mu), 4-7 its backward hops Gamma5 B[e-mu,mu]^H Gamma5 t_o(e-mu);
 // every (row, slot) has exactly one writer.  k_reduced_gather then sums the
 // eight slots in that order and finishes the row with A_e (or A_e^{-1} for
 // block Jacobi) and the epilogue.  Per site pair ten blocks are read instead
 // of eighteen; the sums and signs are those of the two-kernel form, so the
 // results agree with it bit for bit.
-// FP16 tiles up to n = 48 fit three 9-wave workgroups per CU (7 waves per
-// SIMD, at most 72 registers) without spilling; larger tiles keep the default.
+//
+// Eight waves per workgroup, one per hop tile; the tiles are loaded
+// non-temporally (one launch reads each once).  The odd site's inverse tile is
+// staged in LDS and its product with the summed hop products is split over the
+// eight waves: wave w takes rows w T .. w T + T - 1, which lane group lr = w
+// holds in the one-wave tile layout; its lane (a, lc) forms the partial sum
+// that lane (w, lc) forms for row a there, and the same row reduction over lc
+// finishes it.  FP16 tiles up to n = 48 fit three workgroups per CU (7 waves
+// per SIMD, 70 registers, no spill); at 8 waves per SIMD the registers spill
+// and the kernel runs slower.
 template <int T, int P>
 constexpr int scatter_min_waves() { return (P == P16S && T <= 6) ? 7 : 1; }
 
 template <int T, int P>
-__global__ __launch_bounds__(64 * kRedWaves, (scatter_min_waves<T, P>())) void k_reduced_scatter(
+__global__ __launch_bounds__(512, (scatter_min_waves<T, P>())) void k_reduced_scatter(
     const void* __restrict__ blocks, const float* __restrict__ scales,
     const void* __restrict__ inv, const float* __restrict__ invsc,
     const cx<typename VecOf<P>::R>* __restrict__ x_e, cx<typename VecOf<P>::R>* __restrict__ hp,
@@ -907,72 +929,93 @@ __global__ __launch_bounds__(64 * kRedWaves, (scatter_min_waves<T, P>())) void k
     const int* __restrict__ done) {
   using A = typename Tile<T, P>::A;
   using VR = typename VecOf<P>::R;
+  constexpr int UNITS = Tile<T, P>::UNITS;
   __shared__ cx<VR> part[8][64];
+  __shared__ cx<VR> tsum[64];
   __shared__ cx<VR> tx[64];
+  __shared__ uint4 inv_lds[UNITS * 64];
   if (done && *done) return;
   const int b = blockIdx.x;
   const int r = (b & 7) * chunk + (b >> 3);
   if (r >= (V >> 1)) return;   // uniform per workgroup: no barrier is skipped by part of it
   const int x = osite[r];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  {
+    const uint4* ip = block_ptr<T, P>(inv, size_t(x));
+    for (int u = w; u < UNITS; u += 8) inv_lds[u * 64 + lane] = ip[u * 64 + lane];
+  }
   TileRegs<T, P> R;
   A s = A(1);
   size_t dst = 0;   // element offset of this wave's D_eo product in hp
   if (w < 4) {
     const int item = 5 * x + 1 + w;
-    R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+    R.load_stream(block_ptr<T, P>(blocks, size_t(item)), lane);
     if (P == P16S) s = A(scales[item]);
     const int src = nbr[w * V + x];
     wave_product<T, P, true, 1>(R, s, x_e + size_t(src >> 1) * n, part[w], n, 0.0, lane);
     dst = (size_t(src >> 1) * 8 + 4 + w) * n;        // backward hop mu = w of even x + mu
-  } else if (w < 8) {
+  } else {
     const int mu = w - 4;
     const int y = nbr[(4 + mu) * V + x];
     const int item = 5 * y + 1 + mu;
-    R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+    R.load_stream(block_ptr<T, P>(blocks, size_t(item)), lane);
     if (P == P16S) s = A(scales[item]);
     wave_product<T, P, true, 2>(R, s, x_e + size_t(y >> 1) * n, part[w], n, 0.0, lane);
     dst = (size_t(y >> 1) * 8 + mu) * n;             // forward hop mu of even x - mu
-  } else {
-    R.load(block_ptr<T, P>(inv, size_t(x)), lane);   // this wave's only block
   }
   __syncthreads();
-  if (w == 8) {
-    const int lr = lane >> 3, lc = lane & 7;
-    cx<A> pc[T], pr[T], f[T], g[T];
-    A npc_im[T], npr_re[T];
-#pragma unroll
-    for (int q = 0; q < T; ++q) {
-      const int col = lc * T + q;
-      cx<VR> t = part[0][col];
+  if (w == 0) {   // the eight products summed in a fixed order
+    cx<VR> t = mk(VR(0), VR(0));
+    if (lane < n) {
+      t = part[0][lane];
 #pragma unroll
       for (int k = 1; k < 8; ++k) {
-        t.re += part[k][col].re;
-        t.im += part[k][col].im;
+        t.re += part[k][lane].re;
+        t.im += part[k][lane].im;
       }
-      pc[q] = mk(A(t.re), A(t.im));
-      npc_im[q] = -pc[q].im;
-      pr[q] = mk(A(0), A(0));
-      npr_re[q] = A(0);
-      f[q] = mk(A(0), A(0));
-      g[q] = mk(A(0), A(0));
     }
-    tile_products<T, P, true, false>(R, pc, npc_im, pr, npr_re, f, g);
+    tsum[lane] = t;
+  }
+  __syncthreads();
+  {
+    // rows w T + a of A_o^{-1} tsum: lane (a, lc) forms sum_c z[wT+a][lc T+c]
+    // tsum[lc T + c] over its T columns (the tile element a T + c of layout
+    // lane w*8 + lc), the row reduction adds the eight lanes of a row
+    const int a = lane >> 3, lc = lane & 7;
+    const int src_lane = w * 8 + lc;
+    cx<A> f = mk(A(0), A(0));
+    if (a < T) {
+#pragma unroll
+      for (int c = 0; c < T; ++c) {
+        const int e = a * T + c;
+        const cx<VR> t = tsum[lc * T + c];
+        const A pr_ = A(t.re), pi_ = A(t.im);
+        A zr, zi;
+        if constexpr (P == P16S) {
+          const uint4 q = inv_lds[(e >> 2) * 64 + src_lane];
+          const uint32_t word = (e & 3) == 0 ? q.x : (e & 3) == 1 ? q.y : (e & 3) == 2 ? q.z : q.w;
+          zr = lo_h(word);
+          zi = hi_h(word);
+        } else {
+          const float4 q = reinterpret_cast<const float4*>(inv_lds)[(e >> 1) * 64 + src_lane];
+          zr = (e & 1) ? q.z : q.x;
+          zi = (e & 1) ? q.w : q.y;
+        }
+        f.re = fma(zr, pr_, f.re);
+        f.re = fma(zi, -pi_, f.re);
+        f.im = fma(zr, pi_, f.im);
+        f.im = fma(zi, pr_, f.im);
+      }
+    }
     const A si = (P == P16S) ? A(invsc[x]) : A(1);
-#pragma unroll
-    for (int q = 0; q < T; ++q) {
-      f[q].re = sum_row8(f[q].re) * si;
-      f[q].im = sum_row8(f[q].im) * si;
-    }
-    if (lc == 0) {
-#pragma unroll
-      for (int q = 0; q < T; ++q) tx[lr * T + q] = mk(VR(f[q].re), VR(f[q].im));
-    }
+    f.re = sum_row8(f.re) * si;
+    f.im = sum_row8(f.im) * si;
+    if (lc == 0 && a < T) tx[w * T + a] = mk(VR(f.re), VR(f.im));
   }
   __syncthreads();
   if (w < 4)
     wave_product<T, P, true, 2>(R, s, tx, hp + dst, n, 0.0, lane);
-  else if (w < 8)
+  else
     wave_product<T, P, true, 1>(R, s, tx, hp + dst, n, 0.0, lane);
 }
 
@@ -2889,7 +2932,7 @@ static void reduced_scatter_T(int n, int V, const void* blocks, const float* sca
   using VR = typename VecOf<P>::R;
   const int rows = V / 2;
   const int chunk = (rows + 7) / 8;
-  const dim3 grid(unsigned(chunk) * 8u), block(64 * kRedWaves);
+  const dim3 grid(unsigned(chunk) * 8u), block(512);
   const auto* xe = static_cast<const cx<VR>*>(x_e);
   auto* h = static_cast<cx<VR>*>(hp);
   switch (n / 8) {
