@@ -43,7 +43,7 @@ def parse():
     p.add_argument("--workload", default="c3")
     p.add_argument("--tol", type=float, default=1e-8)
     p.add_argument("--inner", default="f16s", choices=["f64", "f32", "f16s"])
-    p.add_argument("--d", type=int, default=32)
+    p.add_argument("--d", type=int, default=96)
     p.add_argument("--k", type=int, default=384)
     p.add_argument("--bj", type=int, default=1, choices=[0, 1],
                    help="left block Jacobi (B = D_ee on the reduced system)")
@@ -525,9 +525,11 @@ def main():
         A2, B2 = synth.operator(w2, device="cuda")
         op2 = CoarseOp(A2, B2, w2.dims, mu=w2.mu, store=("f64", "f32", "f16s"))
         del A2, B2
-        # the same method; at most 10 recycle refreshes, which the warm-up
-        # solves complete (this lattice's solves take one or two cycles each)
-        opts2 = method_opts(u=min(a.u, 10))
+        # the same method with at most 10 recycle refreshes, which the warm-up
+        # solves complete (this lattice's solves take one or two cycles each),
+        # and a polynomial of degree at most 32: on this smaller lattice a
+        # degree-64 polynomial needs about twice the matvecs
+        opts2 = method_opts(u=min(a.u, 10), d=min(a.d, 32))
         for r in range(a.warmup):
             op2.solve(synth.rhs(w2.dims, w2.n_tv, r, device="cuda"), a.tol, opts2)
         rr = [synth.rhs(w2.dims, w2.n_tv, r, device="cuda")
@@ -540,7 +542,7 @@ def main():
         conv2 = all(s["status"] == 0 for s in st2)
         c2res = {"workload": f"c2: {'x'.join(map(str, w2.dims))} lattice, N_tv={w2.n_tv} "
                              f"({w2.N} unknowns), mu={w2.mu}, m0={w2.m0():.6f}",
-                 "u": opts2.u,
+                 "u": opts2.u, "d": opts2.d,
                  "solves_per_s": (a.c2_steps / c2dt) if conv2 else 0.0, "steps": a.c2_steps,
                  "ms_per_step": 1e3 * c2dt / a.c2_steps,
                  "matvecs_per_solve": [s["matvecs"] for s in st2],
