@@ -431,6 +431,12 @@ def set_reduced_kernels(mode: int):
     check(load().dc_set_reduced_kernels(int(mode)))
 
 
+def set_batch_gram_schmidt(batched: int):
+    """Lockstep batched solves: 1 (default) one launch per Gram-Schmidt pass for
+    up to 16 columns, 0 one launch sequence per column; equal results."""
+    check(load().dc_set_batch_gram_schmidt(int(batched)))
+
+
 def dense_eig(A: np.ndarray, vectors=False):
     lib = load()
     n = A.shape[0]

@@ -502,6 +502,13 @@ int dc_set_multi_tile_mode(int32_t mode) {
   });
 }
 
+int dc_set_batch_gram_schmidt(int32_t batched) {
+  return guarded([&] {
+    dc::set_batch_gram_schmidt(batched);
+    return DC_OK;
+  });
+}
+
 int dc_set_reduced_kernels(int32_t mode) {
   return guarded([&] {
     dc::set_reduced_mode(mode);

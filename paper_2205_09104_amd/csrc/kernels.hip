@@ -61,7 +61,7 @@ __device__ inline cx<R> ld(const cx<R>* p) {
 // kernel (k_finalize) sums the partials of each value in a fixed order, so
 // every reduction is deterministic.
 template <int W>
-__device__ void block_partials(double (&v)[W], double* partials) {
+__device__ void block_partials_at(double (&v)[W], double* partials, int bid, int nblk) {
   __shared__ double sh[16][W];
   const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
@@ -73,8 +73,6 @@ __device__ void block_partials(double (&v)[W], double* partials) {
     if (lane == 0) sh[wave][t] = s;
   }
   __syncthreads();
-  const int bid = blockIdx.x + blockIdx.y * gridDim.x;
-  const int nblk = gridDim.x * gridDim.y;
   if (threadIdx.x < W) {
     double s = 0.0;
     for (int w = 0; w < nw; ++w) s += sh[w][threadIdx.x];
@@ -82,17 +80,26 @@ __device__ void block_partials(double (&v)[W], double* partials) {
   }
 }
 
+template <int W>
+__device__ void block_partials(double (&v)[W], double* partials) {
+  block_partials_at<W>(v, partials, blockIdx.x + blockIdx.y * gridDim.x, gridDim.x * gridDim.y);
+}
+
 // result[v] = sum_b partials[v * nparts + b]; one 64-lane wave per value.
-__global__ __launch_bounds__(64) void k_finalize(const double* __restrict__ partials, int nparts,
-                                                 double* __restrict__ result,
-                                                 const int* __restrict__ done) {
-  if (done && *done) return;
-  const int v = blockIdx.x;
+__device__ inline void finalize_value(const double* __restrict__ partials, int nparts,
+                                      double* __restrict__ result, int v) {
   double s = 0.0;
   for (int b = threadIdx.x; b < nparts; b += 64) s += partials[size_t(v) * nparts + b];
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) s += shfl_xor(s, o);
   if (threadIdx.x == 0) result[v] = s;
+}
+
+__global__ __launch_bounds__(64) void k_finalize(const double* __restrict__ partials, int nparts,
+                                                 double* __restrict__ result,
+                                                 const int* __restrict__ done) {
+  if (done && *done) return;
+  finalize_value(partials, nparts, result, blockIdx.x);
 }
 
 // ------------------------------------------------------------------ layout
@@ -1785,16 +1792,16 @@ __device__ inline double wave_sum_many(double (&acc)[V], int lane) {
   return v;
 }
 
-// result value v = blockIdx.y * 2G + t of the group; t = 2*(q - g0) + re/im
+// result value v = by * 2G + t of the group; t = 2*(q - g0) + re/im.  Block
+// bx of gx along the vector, by along the values (blockIdx of a plain launch).
 template <typename VR, int G>
-__global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0, int q0,
-                                                  const cx<VR>* __restrict__ b1, int q1,
-                                                  size_t N, const cx<VR>* __restrict__ w,
-                                                  int want_norm, Reducer red,
-                                                  const int* __restrict__ done) {
-  if (done && *done) return;
+__device__ __forceinline__ void multidot_body(const cx<VR>* __restrict__ b0, int q0,
+                                              const cx<VR>* __restrict__ b1, int q1, size_t N,
+                                              const cx<VR>* __restrict__ w,
+                                              double* __restrict__ partials, int bx, int gx,
+                                              int by) {
   const int Qb = q0 + q1;
-  const int g0 = blockIdx.y * G;
+  const int g0 = by * G;
   const cx<VR>* ptr[G];
 #pragma unroll
   for (int t = 0; t < G; ++t) {
@@ -1805,8 +1812,8 @@ __global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0,
 #pragma unroll
   for (int t = 0; t < 2 * G; ++t) acc[t] = 0.0;
   const size_t chunk = size_t(blockDim.x) * kDotE;
-  const size_t stride = size_t(gridDim.x) * chunk;
-  for (size_t base = size_t(blockIdx.x) * chunk + threadIdx.x; base < N; base += stride) {
+  const size_t stride = size_t(gx) * chunk;
+  for (size_t base = size_t(bx) * chunk + threadIdx.x; base < N; base += stride) {
     size_t idx[kDotE];
     double wr[kDotE], wi[kDotE];
 #pragma unroll
@@ -1837,19 +1844,28 @@ __global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0,
         acc[2 * t + 1] = fma(vr, wi[e], fma(-vi, wr[e], acc[2 * t + 1]));  // Im conj(v) w
       }
   }
-  (void)want_norm;
   __shared__ double sh[4][2 * G];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const double s = wave_sum_many<2 * G>(acc, lane);
   constexpr int kSpan = 64 / (2 * G);   // lanes holding the same value
   if (lane % kSpan == 0) sh[wave][lane / kSpan] = s;
   __syncthreads();
-  const int gx = gridDim.x;
   if (threadIdx.x < 2 * G) {
     double s = 0.0;
     for (int wv2 = 0; wv2 < int(blockDim.x >> 6); ++wv2) s += sh[wv2][threadIdx.x];
-    red.partials[(size_t(blockIdx.y) * 2 * G + threadIdx.x) * gx + blockIdx.x] = s;
+    partials[(size_t(by) * 2 * G + threadIdx.x) * gx + bx] = s;
   }
+}
+
+template <typename VR, int G>
+__global__ __launch_bounds__(256) void k_multidot(const cx<VR>* __restrict__ b0, int q0,
+                                                  const cx<VR>* __restrict__ b1, int q1,
+                                                  size_t N, const cx<VR>* __restrict__ w,
+                                                  int want_norm, Reducer red,
+                                                  const int* __restrict__ done) {
+  if (done && *done) return;
+  (void)want_norm;
+  multidot_body<VR, G>(b0, q0, b1, q1, N, w, red.partials, blockIdx.x, gridDim.x, blockIdx.y);
 }
 
 // The update kernels split the basis between the kSplitWaves waves of a
@@ -1899,27 +1915,20 @@ __device__ inline void split_sums(const cx<VR>* __restrict__ b0, int q0,
 // out = (w - sum_q coef_q basis_q) (times *scale when scale is given; then the
 // launch belongs to Arnoldi step j and runs only if that step's bookkeeping
 // ran, *jdone == j + 1, instead of checking the stop flag).  out may be w.
+// Block bx of gx (blockIdx.x / gridDim.x of a plain launch); sc scales the result.
 template <typename VR>
-__global__ __launch_bounds__(256) void k_multiaxpy(const cx<VR>* w, cx<VR>* out,
-                                                   const cx<VR>* __restrict__ b0, int q0,
-                                                   const cx<VR>* __restrict__ b1, int q1,
-                                                   size_t N, const double* __restrict__ coef,
-                                                   int want_norm, Reducer red,
-                                                   const int* __restrict__ done,
-                                                   const double* __restrict__ scale,
-                                                   const int* __restrict__ jdone, int j) {
-  if (scale) {
-    if (*jdone != j + 1) return;
-  } else if (done && *done) {
-    return;
-  }
-  const double sc = scale ? *scale : 1.0;
+__device__ __forceinline__ void multiaxpy_split_body(const cx<VR>* w, cx<VR>* out,
+                                                     const cx<VR>* __restrict__ b0, int q0,
+                                                     const cx<VR>* __restrict__ b1, int q1,
+                                                     size_t N, const double* __restrict__ coef,
+                                                     int want_norm, double* partials, double sc,
+                                                     int bx, int gx) {
   const int Q = q0 + q1;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   __shared__ double part[kSplitWaves][kDotE][2][64];
   double nacc[1] = {0.0};
   const size_t span = size_t(64) * kDotE;
-  for (size_t base = size_t(blockIdx.x) * span; base < N; base += size_t(gridDim.x) * span) {
+  for (size_t base = size_t(bx) * span; base < N; base += size_t(gx) * span) {
     size_t idx[kDotE];
     double sr[kDotE], si[kDotE];
     split_sums<VR>(b0, q0, b1, N, Q, coef, base, lane, wave, idx, sr, si);
@@ -1948,13 +1957,11 @@ __global__ __launch_bounds__(256) void k_multiaxpy(const cx<VR>* w, cx<VR>* out,
     }
     __syncthreads();
   }
-  if (want_norm) block_partials<1>(nacc, red.partials);
+  if (want_norm) block_partials_at<1>(nacc, partials, bx, gx);
 }
 
-// Bases of at most one chunk (kAxpyG vectors): nothing to split between the
-// waves, so each thread takes its own kDotE elements through the whole basis.
 template <typename VR>
-__global__ __launch_bounds__(256) void k_multiaxpy_flat(const cx<VR>* w, cx<VR>* out,
+__global__ __launch_bounds__(256) void k_multiaxpy(const cx<VR>* w, cx<VR>* out,
                                                    const cx<VR>* __restrict__ b0, int q0,
                                                    const cx<VR>* __restrict__ b1, int q1,
                                                    size_t N, const double* __restrict__ coef,
@@ -1967,12 +1974,24 @@ __global__ __launch_bounds__(256) void k_multiaxpy_flat(const cx<VR>* w, cx<VR>*
   } else if (done && *done) {
     return;
   }
-  const double sc = scale ? *scale : 1.0;
+  multiaxpy_split_body<VR>(w, out, b0, q0, b1, q1, N, coef, want_norm, red.partials,
+                           scale ? *scale : 1.0, blockIdx.x, gridDim.x);
+}
+
+// Bases of at most one chunk (kAxpyG vectors): nothing to split between the
+// waves, so each thread takes its own kDotE elements through the whole basis.
+template <typename VR>
+__device__ __forceinline__ void multiaxpy_flat_body(const cx<VR>* w, cx<VR>* out,
+                                                    const cx<VR>* __restrict__ b0, int q0,
+                                                    const cx<VR>* __restrict__ b1, int q1,
+                                                    size_t N, const double* __restrict__ coef,
+                                                    int want_norm, double* partials, double sc,
+                                                    int bx, int gx) {
   const int Q = q0 + q1;
   double nacc[1] = {0.0};
   const size_t chunk = size_t(blockDim.x) * kDotE;
-  const size_t stride = size_t(gridDim.x) * chunk;
-  for (size_t base = size_t(blockIdx.x) * chunk + threadIdx.x; base < N; base += stride) {
+  const size_t stride = size_t(gx) * chunk;
+  for (size_t base = size_t(bx) * chunk + threadIdx.x; base < N; base += stride) {
     size_t idx[kDotE];
     double sr[kDotE], si[kDotE];
 #pragma unroll
@@ -2014,7 +2033,25 @@ __global__ __launch_bounds__(256) void k_multiaxpy_flat(const cx<VR>* w, cx<VR>*
       }
     }
   }
-  if (want_norm) block_partials<1>(nacc, red.partials);
+  if (want_norm) block_partials_at<1>(nacc, partials, bx, gx);
+}
+
+template <typename VR>
+__global__ __launch_bounds__(256) void k_multiaxpy_flat(const cx<VR>* w, cx<VR>* out,
+                                                   const cx<VR>* __restrict__ b0, int q0,
+                                                   const cx<VR>* __restrict__ b1, int q1,
+                                                   size_t N, const double* __restrict__ coef,
+                                                   int want_norm, Reducer red,
+                                                   const int* __restrict__ done,
+                                                   const double* __restrict__ scale,
+                                                   const int* __restrict__ jdone, int j) {
+  if (scale) {
+    if (*jdone != j + 1) return;
+  } else if (done && *done) {
+    return;
+  }
+  multiaxpy_flat_body<VR>(w, out, b0, q0, b1, q1, N, coef, want_norm, red.partials,
+                          scale ? *scale : 1.0, blockIdx.x, gridDim.x);
 }
 
 constexpr int kCombR = 16;  // outputs per pass of the combine kernel
@@ -2524,10 +2561,10 @@ constexpr int kFinishLds = 512;  // Hessenberg column length staged in LDS
 // Single-sync process (c2 null, Sec. 3.5): the coefficients come from one pass
 // and h_{j+1,j}^2 = ||A v_j||^2 - sum |coefficients|^2 (nrm2 unused); a value
 // at or below (brk ||A v_j||)^2 is a breakdown.
-__global__ __launch_bounds__(64) void k_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j,
-                                                       const double* c1, const double* c2,
-                                                       const double* nrm2, double target,
-                                                       double brk) {
+__device__ __forceinline__ void arnoldi_finish_body(const ArnoldiDev& a, int steps, int kC, int j,
+                                                    const double* c1, const double* c2,
+                                                    const double* nrm2, double target,
+                                                    double brk) {
   if (*a.done) return;
   __shared__ double hcol[2 * (kFinishLds + 2)], csl[kFinishLds], snl[2 * kFinishLds];
   const bool staged = j + 2 <= kFinishLds;
@@ -2628,6 +2665,76 @@ __global__ __launch_bounds__(64) void k_arnoldi_finish(ArnoldiDev a, int steps, 
   if (breakdown || est <= target || j + 1 >= steps) {
     *a.done = 1;
     if (a.hdone) *a.hdone = 1;
+  }
+}
+
+__global__ __launch_bounds__(64) void k_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j,
+                                                       const double* c1, const double* c2,
+                                                       const double* nrm2, double target,
+                                                       double brk) {
+  arnoldi_finish_body(a, steps, kC, j, c1, c2, nrm2, target, brk);
+}
+
+// ------------------------------------------------------------------ batched Gram-Schmidt
+// The launches of one classical Gram-Schmidt step for up to kOrthCols
+// independent columns (a lockstep batch) at once: blockIdx.z is the column,
+// and each column runs exactly the blocks, partial layout and sums of its own
+// single launch (its grid extent gx; the launch covers the largest), so its
+// results are those of the per-column launches bit for bit.
+template <typename VR, int G>
+__global__ __launch_bounds__(256) void k_multidot_cols(OrthCols t) {
+  if (int(blockIdx.z) >= t.count) return;
+  const OrthCol& a = t.c[blockIdx.z];
+  if (a.done && *a.done) return;
+  if (blockIdx.x >= a.gx) return;
+  multidot_body<VR, G>(static_cast<const cx<VR>*>(a.b0), a.q0, static_cast<const cx<VR>*>(a.b1),
+                       a.q1, a.N, static_cast<const cx<VR>*>(a.w), a.partials, int(blockIdx.x),
+                       int(a.gx), int(blockIdx.y));
+}
+
+__global__ __launch_bounds__(64) void k_finalize_cols(OrthCols t) {
+  if (int(blockIdx.z) >= t.count) return;
+  const OrthCol& a = t.c[blockIdx.z];
+  if (a.done && *a.done) return;
+  finalize_value(a.partials, int(a.gx), a.result, int(blockIdx.x));
+}
+
+template <typename VR, bool SPLIT>
+__global__ __launch_bounds__(256) void k_multiaxpy_cols(OrthCols t, int want_norm) {
+  if (int(blockIdx.z) >= t.count) return;
+  const OrthCol& a = t.c[blockIdx.z];
+  if (a.done && *a.done) return;
+  if (blockIdx.x >= a.gx) return;
+  cx<VR>* w = static_cast<cx<VR>*>(a.w);
+  const cx<VR>* b0 = static_cast<const cx<VR>*>(a.b0);
+  const cx<VR>* b1 = static_cast<const cx<VR>*>(a.b1);
+  if constexpr (SPLIT)
+    multiaxpy_split_body<VR>(w, w, b0, a.q0, b1, a.q1, a.N, a.coef, want_norm, a.partials, 1.0,
+                             int(blockIdx.x), int(a.gx));
+  else
+    multiaxpy_flat_body<VR>(w, w, b0, a.q0, b1, a.q1, a.N, a.coef, want_norm, a.partials, 1.0,
+                            int(blockIdx.x), int(a.gx));
+}
+
+__global__ __launch_bounds__(64) void k_arnoldi_finish_cols(FinishCols t, int steps, int j,
+                                                            double brk) {
+  if (int(blockIdx.x) >= t.count) return;
+  const FinishCol& f = t.c[blockIdx.x];
+  arnoldi_finish_body(f.a, steps, f.kC, j, f.c1, f.c2, f.nrm2, f.target, brk);
+}
+
+template <typename VR>
+__global__ void k_scale_step_cols(ScaleCols t, int j) {
+  if (int(blockIdx.z) >= t.count) return;
+  const int c = int(blockIdx.z);
+  if (*t.jdone[c] != j + 1) return;
+  const double sc = *t.inv_h[c];
+  cx<VR>* v = static_cast<cx<VR>*>(t.v[c]);
+  const size_t N = t.N[c];
+  const size_t stride = size_t(gridDim.x) * blockDim.x;
+  for (size_t i = size_t(blockIdx.x) * blockDim.x + threadIdx.x; i < N; i += stride) {
+    const cx<VR> z = v[i];
+    v[i] = mk(VR(double(z.re) * sc), VR(double(z.im) * sc));
   }
 }
 
@@ -3383,6 +3490,114 @@ void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, i
   const unsigned nb = multiaxpy_any(p, w, b0, q0, b1, q1, N, coef, want_norm, red, done, nullptr,
                                     nullptr, 0, st);
   if (want_norm) finalize(red.partials, 1, int(nb), result, done, st);
+}
+
+namespace {
+int g_batch_gs = 1;
+}
+
+void set_batch_gram_schmidt(int batched) {
+  if (batched != 0 && batched != 1) throw InvalidArg("batched Gram-Schmidt mode must be 0 or 1");
+  g_batch_gs = batched;
+}
+
+int batch_gram_schmidt() { return g_batch_gs; }
+
+static void check_cols(int count) {
+  if (count < 0 || count > kOrthCols) throw InvalidArg("column table holds 0..16 columns");
+}
+
+static int common_q(const OrthCols& t) {
+  const int Q = t.c[0].q0 + t.c[0].q1;
+  for (int c = 1; c < t.count; ++c)
+    if (t.c[c].q0 + t.c[c].q1 != Q) throw InvalidArg("batched columns need equal basis sizes");
+  return Q;
+}
+
+template <typename VR, int G>
+static void multidot_cols_g(OrthCols t, int Q, hipStream_t st) {
+  const int gy = (Q + G - 1) / G;
+  unsigned gmax = 1;
+  for (int c = 0; c < t.count; ++c) {
+    t.c[c].gx = dot_blocks(t.c[c].N, gy * 2 * G);   // as its own launch would take
+    gmax = std::max(gmax, t.c[c].gx);
+  }
+  hipLaunchKernelGGL((k_multidot_cols<VR, G>), dim3(gmax, unsigned(gy), unsigned(t.count)),
+                     dim3(256), 0, st, t);
+  DC_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_finalize_cols, dim3(unsigned(2 * Q), 1u, unsigned(t.count)), dim3(64), 0,
+                     st, t);
+  DC_HIP(hipGetLastError());
+}
+
+template <typename VR>
+static void multidot_cols_t(const OrthCols& t, int Q, hipStream_t st) {
+  if (Q <= 2) multidot_cols_g<VR, 2>(t, Q, st);
+  else if (Q <= 4) multidot_cols_g<VR, 4>(t, Q, st);
+  else if (Q <= 8) multidot_cols_g<VR, 8>(t, Q, st);
+  else multidot_cols_g<VR, 16>(t, Q, st);
+}
+
+void launch_multidot_cols(Prec p, const OrthCols& t, int want_norm, hipStream_t st) {
+  check_cols(t.count);
+  if (t.count == 0) return;
+  const int Q = common_q(t) + (want_norm ? 1 : 0);
+  if (Q == 0) return;
+  if (p == P64) multidot_cols_t<double>(t, Q, st);
+  else multidot_cols_t<float>(t, Q, st);
+}
+
+void launch_multiaxpy_cols(Prec p, const OrthCols& t0, int want_norm, hipStream_t st) {
+  check_cols(t0.count);
+  if (t0.count == 0) return;
+  const int Q = common_q(t0);
+  if (Q == 0 && !want_norm) return;
+  OrthCols t = t0;
+  // the grid of each column's own launch (multiaxpy_any)
+  const bool split = Q > kAxpyG;
+  const size_t per = split ? size_t(64) * kDotE : size_t(256) * kDotE;
+  const size_t cap = split ? 4096 : 2048;
+  unsigned gmax = 1;
+  for (int c = 0; c < t.count; ++c) {
+    size_t nb = (t.c[c].N + per - 1) / per;
+    if (nb > cap) nb = cap;
+    if (nb < 1) nb = 1;
+    t.c[c].gx = unsigned(nb);
+    gmax = std::max(gmax, t.c[c].gx);
+  }
+  const dim3 grid(gmax, 1u, unsigned(t.count));
+  if (p == P64) {
+    if (split) hipLaunchKernelGGL((k_multiaxpy_cols<double, true>), grid, dim3(256), 0, st, t, want_norm);
+    else hipLaunchKernelGGL((k_multiaxpy_cols<double, false>), grid, dim3(256), 0, st, t, want_norm);
+  } else {
+    if (split) hipLaunchKernelGGL((k_multiaxpy_cols<float, true>), grid, dim3(256), 0, st, t, want_norm);
+    else hipLaunchKernelGGL((k_multiaxpy_cols<float, false>), grid, dim3(256), 0, st, t, want_norm);
+  }
+  DC_HIP(hipGetLastError());
+  if (want_norm) {
+    hipLaunchKernelGGL(k_finalize_cols, dim3(1u, 1u, unsigned(t.count)), dim3(64), 0, st, t);
+    DC_HIP(hipGetLastError());
+  }
+}
+
+void launch_arnoldi_finish_cols(const FinishCols& t, int steps, int j, double brk,
+                                hipStream_t st) {
+  check_cols(t.count);
+  if (t.count == 0) return;
+  hipLaunchKernelGGL(k_arnoldi_finish_cols, dim3(unsigned(t.count)), dim3(64), 0, st, t, steps, j,
+                     brk);
+  DC_HIP(hipGetLastError());
+}
+
+void launch_scale_step_cols(Prec p, const ScaleCols& t, int j, hipStream_t st) {
+  check_cols(t.count);
+  if (t.count == 0) return;
+  size_t nmax = 1;
+  for (int c = 0; c < t.count; ++c) nmax = std::max(nmax, t.N[c]);
+  const dim3 grid(grid_for(nmax, 256), 1u, unsigned(t.count)), block(256);
+  if (p == P64) hipLaunchKernelGGL(k_scale_step_cols<double>, grid, block, 0, st, t, j);
+  else hipLaunchKernelGGL(k_scale_step_cols<float>, grid, block, 0, st, t, j);
+  DC_HIP(hipGetLastError());
 }
 
 void launch_multiaxpy_scaled(Prec p, void* w, const void* b0, int q0, const void* b1, int q1,

@@ -277,6 +277,62 @@ void launch_arnoldi_finish(ArnoldiDev a, int steps, int kC, int j, const double*
 // beta_dev: take beta from device memory instead
 void launch_arnoldi_init(ArnoldiDev a, double beta, hipStream_t st,
                          const double* beta_dev = nullptr);
+
+// Batched Gram-Schmidt: the launches of one classical Gram-Schmidt step (as
+// launch_multidot / launch_multiaxpy / launch_arnoldi_finish /
+// launch_scale_step) for up to kOrthCols independent columns at once, each
+// column with its own basis, vector length, reduction partials and stop flag.
+// Every column takes exactly the grid, partial layout and sums of its own
+// launch, so results are the per-column launches' bit for bit.  The columns of
+// one call need equal basis sizes q0 + q1; the tables travel as kernel
+// arguments (graph capture records them).
+constexpr int kOrthCols = 16;
+struct OrthCol {
+  const void* b0 = nullptr;      // basis part 0: q0 vectors of N (or null)
+  const void* b1 = nullptr;      // basis part 1: q1 vectors of N
+  void* w = nullptr;             // the column's vector (updated in place)
+  double* partials = nullptr;    // the column's own reduction partials (kRedCap doubles)
+  double* result = nullptr;      // dots: 2 (q0 + q1 [+ 1 norm]) doubles; update: the norm
+  const double* coef = nullptr;  // update coefficients (complex, q0 + q1)
+  const int* done = nullptr;     // the column's stop flag (null: never stops)
+  size_t N = 0;
+  int q0 = 0, q1 = 0;
+  unsigned gx = 0;               // set by the launchers
+};
+struct OrthCols {
+  OrthCol c[kOrthCols];
+  int count = 0;
+};
+// result = [b0 b1]^H w (and ||w||^2 after them if want_norm), per column
+void launch_multidot_cols(Prec p, const OrthCols& t, int want_norm, hipStream_t st);
+// w -= [b0 b1] coef per column; with want_norm result = ||w||^2 after it
+void launch_multiaxpy_cols(Prec p, const OrthCols& t, int want_norm, hipStream_t st);
+struct FinishCol {
+  ArnoldiDev a;
+  const double* c1 = nullptr;
+  const double* c2 = nullptr;
+  const double* nrm2 = nullptr;
+  double target = 0.0;
+  int kC = 0;
+};
+struct FinishCols {
+  FinishCol c[kOrthCols];
+  int count = 0;
+};
+void launch_arnoldi_finish_cols(const FinishCols& t, int steps, int j, double brk,
+                                hipStream_t st);
+struct ScaleCols {
+  void* v[kOrthCols] = {};
+  size_t N[kOrthCols] = {};
+  const double* inv_h[kOrthCols] = {};
+  const int* jdone[kOrthCols] = {};
+  int count = 0;
+};
+void launch_scale_step_cols(Prec p, const ScaleCols& t, int j, hipStream_t st);
+// Whether lockstep batches use these (1, default) or one launch sequence per
+// column (0); process-wide, equal results.
+void set_batch_gram_schmidt(int batched);
+int batch_gram_schmidt();
 // out[0] = sqrt(*nrm2), out[1] = its reciprocal (0 for a zero norm); device pointers
 void launch_norm_root(const double* nrm2, double* out, hipStream_t st);
 

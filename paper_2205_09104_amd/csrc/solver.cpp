@@ -116,7 +116,8 @@ void Op::bind_arenas() {
   bind(esite, P, "parity table");
   bind(osite, P, "parity table");
   for (DevBuf* b : {&gbuf64, &gbuf32, &ts64, &ts32, &rbe, &rbo, &rxe, &rto, &wvbuf, &redpart, &scal,
-                    &t64a, &t64b, &t32a, &t32b, &zouter, &ptrs, &bx64, &bb64, &b32, &x32, &r64})
+                    &t64a, &t64b, &t32a, &t32b, &zouter, &ptrs, &bpart, &bx64, &bb64, &b32, &x32,
+                    &r64})
     bind(*b, S, "vector scratch");
   for (BlockWS* w : {&bk64, &bk32})
     for (DevBuf* b : {&w->V, &w->Z, &w->W, &w->T1, &w->TA, &w->PROD, &w->U, &w->small, &w->tab,
@@ -2055,6 +2056,9 @@ struct Batch {
     ldh = std::max(o.m, std::max(o.d, 1)) + 2;  // as every Krylov object of the batch
     for (const Group& gr : g)
       if (!gr.K.empty() && gr.K[0]->ldh != ldh) throw BadState("batched Krylov size mismatch");
+    size_t cols = 0;
+    for (int r : R) cols += size_t(r);
+    ops[0]->bpart.ensure(std::max<size_t>(cols, 1) * kRedCap * sizeof(double));
   }
 
   // device pointer array of slot s of group gi (T_NFIX + j: basis vector j)
@@ -2227,11 +2231,88 @@ struct Batch {
   void enqueue_steps(int steps, const std::vector<std::vector<double>>& target) {
     for (int j = 0; j < steps; ++j) {
       Ahat(T_NFIX + j, T_NFIX + j + 1);
+      if (batch_gram_schmidt()) {
+        orth_batched(j, steps, target);
+        continue;
+      }
       for (size_t gi = 0; gi < g.size(); ++gi) {
         Group& gr = g[gi];
         for (size_t a = 0; a < gr.act.size(); ++a)
           gr.K[gr.act[a]]->orth_step(j, gr.var->kcur, steps, target[gi][a]);
       }
+    }
+  }
+
+  // Step j's Gram-Schmidt (classical, twice) of every active column, one
+  // launch per pass for up to kOrthCols columns of equal deflation-space size:
+  // the launches of Krylov::orth_step with ortho = 0, for many columns at once
+  // (same sums, so the same results), each column with its own slice of the
+  // batch's reduction partials.
+  void orth_batched(int j, int steps, const std::vector<std::vector<double>>& target) {
+    struct Col {
+      Krylov<VR>* k;
+      int kC;
+      double target;
+    };
+    std::vector<Col> cols;
+    for (size_t gi = 0; gi < g.size(); ++gi) {
+      Group& gr = g[gi];
+      for (size_t a = 0; a < gr.act.size(); ++a)
+        cols.push_back({gr.K[gr.act[a]].get(), gr.var->kcur, target[gi][a]});
+    }
+    std::stable_sort(cols.begin(), cols.end(),
+                     [](const Col& x, const Col& y) { return x.kC < y.kC; });
+    double* part = g[0].op->bpart.template as<double>();
+    for (size_t s0 = 0; s0 < cols.size();) {
+      size_t e = s0;
+      while (e < cols.size() && e - s0 < size_t(kOrthCols) && cols[e].kC == cols[s0].kC) ++e;
+      OrthCols d1, a1, d2, a2;
+      FinishCols f;
+      ScaleCols sc;
+      double brk = 0.0;
+      for (size_t i = s0; i < e; ++i) {
+        Krylov<VR>& k = *cols[i].k;
+        const int c = int(i - s0);
+        OrthCol base;
+        base.b0 = cols[i].kC ? k.Cv() : nullptr;
+        base.q0 = cols[i].kC;
+        base.b1 = k.V(0);
+        base.q1 = j + 1;
+        base.w = k.V(j + 1);
+        base.N = k.N;
+        base.done = k.ad.done;
+        base.partials = part + i * size_t(kRedCap);
+        d1.c[c] = base;
+        d1.c[c].result = k.res1;
+        a1.c[c] = base;
+        a1.c[c].coef = k.res1;
+        a1.c[c].result = k.nrm;
+        d2.c[c] = base;
+        d2.c[c].result = k.res2;
+        a2.c[c] = base;
+        a2.c[c].coef = k.res2;
+        a2.c[c].result = k.nrm;
+        f.c[c].a = k.ad;
+        f.c[c].c1 = k.res1;
+        f.c[c].c2 = k.res2;
+        f.c[c].nrm2 = k.nrm;
+        f.c[c].target = cols[i].target;
+        f.c[c].kC = cols[i].kC;
+        sc.v[c] = k.V(j + 1);
+        sc.N[c] = k.N;
+        sc.inv_h[c] = k.ad.inv_h;
+        sc.jdone[c] = k.ad.jdone;
+        brk = k.brk;
+      }
+      const int n = int(e - s0);
+      d1.count = a1.count = d2.count = a2.count = f.count = sc.count = n;
+      launch_multidot_cols(p, d1, 1, st);
+      launch_multiaxpy_cols(p, a1, 0, st);
+      launch_multidot_cols(p, d2, 0, st);
+      launch_multiaxpy_cols(p, a2, 1, st);
+      launch_arnoldi_finish_cols(f, steps, j, brk, st);
+      launch_scale_step_cols(p, sc, j, st);
+      s0 = e;
     }
   }
 
@@ -2264,7 +2345,8 @@ struct Batch {
     GraphCache& gc = op0.graphs;
     if (gc.broken || op0.prof.on || !tiles_tuned()) return false;
     std::vector<uintptr_t> key = {0xBA7C4u, uintptr_t(tab.p), uintptr_t(steps), uintptr_t(p),
-                                  uintptr_t(ldh), uintptr_t(g.size())};
+                                  uintptr_t(ldh), uintptr_t(g.size()), uintptr_t(op0.bpart.p),
+                                  uintptr_t(batch_gram_schmidt())};
     for (size_t gi = 0; gi < g.size(); ++gi) {
       Group& gr = g[gi];
       key.insert(key.end(), {uintptr_t(gr.op), uintptr_t(gr.var), uintptr_t(gr.var->poly_serial),

@@ -258,6 +258,7 @@ struct Op {
   DevBuf scal;              // a few device doubles
   DevBuf t64a, t64b, t32a, t32b, zouter;  // per-solve vector scratch, kept across calls
   DevBuf ptrs;              // device pointer arrays of the multi-RHS apply
+  DevBuf bpart;             // lockstep batches: per-column reduction partials
   std::vector<DevBuf> bws, bsm;            // per right-hand-side workspaces of batched solves
   DevBuf bx64, bb64, b32, x32, r64;        // batched-solve vectors
   ApplyProfile prof;

@@ -394,6 +394,54 @@ def test_mixed_lattice_batch_rejects_bad_input():
         CoarseOp.solve_multi([a, a], [ba, ba], [1e-8, 1e-8], Opts(m=10))
 
 
+@pytest.mark.parametrize("cfg", ["poly", "bj", "recycle"])
+def test_batched_gram_schmidt_equals_per_column(cfg):
+    """Lockstep mixed batch with the Gram-Schmidt passes of all columns in one
+    launch each (default) against one launch sequence per column: the same
+    iterates bit for bit and the same step counts, eager and graph-replayed.
+    "recycle": every operator first builds a recycle space in a single solve,
+    so the batch deflates against it (a non-empty first basis part)."""
+    import paper_2205_09104_amd as dc
+    from paper_2205_09104_amd import CoarseOp, Opts
+    log("batched gram-schmidt", cfg)
+    pairs = [make_pair((2, 2, 2, 2), 4, 3.2), make_pair((3, 2, 2, 2), 4, 3.1, mu=0.05),
+             make_pair((4, 3, 2, 2), 4, 3.0)]
+    ops = [p[0] for p in pairs]
+    R = [2, 3, 1]
+    bs, tols = [], []
+    for i, ((gop, oop), r) in enumerate(zip(pairs, R)):
+        bs.append(torch.stack([rand_vec(oop.V, oop.n, 700 + 10 * i, j) for j in range(r)]).cuda())
+        tols.append(synth.tolerances_loguniform(r, 1e-10, 1e-7, seed=37 + i))
+    kw = {"poly": dict(m=20, d=4, seed=3), "bj": dict(m=20, d=4, block_jacobi=1, seed=3),
+          "recycle": dict(m=26, k=6, d=4, u=2, seed=3)}[cfg]
+    if cfg == "recycle":
+        for (gop, oop) in pairs:
+            b0 = rand_vec(oop.V, oop.n, 799, 0).cuda()
+            _, st, rc = gop.solve(b0, 1e-10, Opts(**kw))
+            assert rc == 0
+    res = {}
+    try:
+        for mode in (0, 1):
+            dc.set_batch_gram_schmidt(mode)
+            for graphs in (0, 1):
+                x, st, rc = CoarseOp.solve_multi(ops, bs, tols, Opts(graphs=graphs, **kw))
+                assert rc == 0
+                res[(mode, graphs)] = ([xi.cpu() for xi in x],
+                                       [[s["iters"] for s in sg] for sg in st])
+    finally:
+        dc.set_batch_gram_schmidt(1)
+    ref_x, ref_it = res[(0, 0)]
+    for key, (x, it) in res.items():
+        assert it == ref_it, key
+        for a, b in zip(x, ref_x):
+            assert torch.equal(a, b), key
+    for (gop, oop), x, b, t in zip(pairs, ref_x, bs, tols):
+        for j in range(b.shape[0]):
+            assert oracle_relres(oop, x[j].numpy(), b[j].cpu().numpy()) <= t[j]
+    with pytest.raises(Exception):
+        dc.set_batch_gram_schmidt(2)
+
+
 @pytest.mark.parametrize("cfg", ["poly", "bj"])
 def test_mixed_batch_graph_replay_matches_eager(cfg):
     """The Arnoldi steps of each lockstep cycle of a mixed batch recorded once
