@@ -709,8 +709,10 @@ def c1_graphs(a):
 def mixed_graphs(a):
     """A launch-bound mixed batch (4^4, 6x4^3 and 6^2x4^2 lattices of the 4^4
     workload's family, N_tv = 8, two right-hand sides each, FP64, polynomial
-    d = 4, GMRES(20) in lockstep, tolerance 1e-10): batches/s with eager
-    launches and with each lockstep cycle's steps replayed as one HIP graph."""
+    d = 4, GMRES(20) in lockstep, tolerance 1e-10): batches/s with the
+    Gram-Schmidt and chain launches per column / per operator, batched (one
+    launch for all columns), and batched with each lockstep cycle's steps
+    replayed as one HIP graph."""
     import torch
 
     import synth
@@ -726,22 +728,30 @@ def mixed_graphs(a):
     tols = [[1e-10, 1e-10]] * len(ops)
     out = {"lattices": ["x".join(map(str, d)) for d in dims_list], "n_tv": w.n_tv,
            "rhs_per_lattice": 2, "tol": 1e-10}
-    for graphs in (0, 1):
-        o = Opts(m=20, d=4, seed=3, graphs=graphs)
-        CoarseOp.solve_multi(ops, bs, tols, o)       # polynomial, tile choice, recordings
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        sts = [CoarseOp.solve_multi(ops, bs, tols, o) for _ in range(a.c1_steps)]
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        ok = all(rc == 0 for _, _, rc in sts)
-        out["graphs" if graphs else "eager"] = {
-            "batches_per_s": a.c1_steps / dt if ok else 0.0, "ms_per_batch": 1e3 * dt / a.c1_steps,
-            "graph_stats": list(ops[0].graph_stats())}
+    import paper_2205_09104_amd as dc
+    # per_column: the Gram-Schmidt passes and chain steps launched per column
+    # and per operator; eager / graphs: batched launches (the default)
+    try:
+        for name, graphs, batched in (("per_column", 0, 0), ("eager", 0, 1), ("graphs", 1, 1)):
+            dc.set_batch_launches(batched)
+            o = Opts(m=20, d=4, seed=3, graphs=graphs)
+            CoarseOp.solve_multi(ops, bs, tols, o)       # polynomial, tile choice, recordings
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sts = [CoarseOp.solve_multi(ops, bs, tols, o) for _ in range(a.c1_steps)]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            ok = all(rc == 0 for _, _, rc in sts)
+            out[name] = {"batches_per_s": a.c1_steps / dt if ok else 0.0,
+                         "ms_per_batch": 1e3 * dt / a.c1_steps,
+                         "graph_stats": list(ops[0].graph_stats())}
+    finally:
+        dc.set_batch_launches(1)
     out["speedup"] = (out["graphs"]["batches_per_s"] / out["eager"]["batches_per_s"]
                       if out["eager"]["batches_per_s"] else None)
-    log(f"mixed batch: eager {out['eager']['batches_per_s']:.1f}, graphs "
-        f"{out['graphs']['batches_per_s']:.1f} batches/s")
+    log(f"mixed batch: per-column launches {out['per_column']['batches_per_s']:.1f}, batched "
+        f"eager {out['eager']['batches_per_s']:.1f}, graphs {out['graphs']['batches_per_s']:.1f} "
+        f"batches/s")
     for op in ops:
         op.close()
     return out

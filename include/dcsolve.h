@@ -491,15 +491,16 @@ int dc_set_multi_tile_mode(int32_t mode);
  * results are equal bit for bit.  Other values: DC_ERR_INVALID. */
 int dc_set_reduced_kernels(int32_t mode);
 
-/* Gram-Schmidt launches of the lockstep batched solves (solve_coarse_batch,
- * solve_coarse_multi; classical Gram-Schmidt applied twice, Alg. 1 with the
- * re-orthogonalisation): batched = 1 (default) takes every pass of one
- * Arnoldi step for up to 16 columns with the same deflation-space size in one
- * launch, batched = 0 one launch sequence per column.  Each column's sums are
- * the same either way, so results are equal bit for bit; the batched form
- * removes most launches of a step on lattices small enough that launches,
- * not HBM, bound it.  Process-wide.  Other values: DC_ERR_INVALID. */
-int dc_set_batch_gram_schmidt(int32_t batched);
+/* Launches of the lockstep batched solves (solve_coarse_batch,
+ * solve_coarse_multi): batched = 1 (default) takes every pass of one Arnoldi
+ * step's classical Gram-Schmidt (applied twice) for up to 16 columns with the
+ * same deflation-space size in one launch, and each polynomial chain step
+ * (Sec. 3.3) of up to 8 operators in one launch; batched = 0 launches them per
+ * column and per operator.  Each column's sums are the same either way, so
+ * results are equal bit for bit; the batched form removes most launches of a
+ * step on lattices small enough that launches, not HBM, bound it.
+ * Process-wide.  Other values: DC_ERR_INVALID. */
+int dc_set_batch_launches(int32_t batched);
 
 /* Message of the last error on this thread ("" if none). */
 const char* dc_last_error(void);

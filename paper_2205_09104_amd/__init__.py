@@ -431,10 +431,11 @@ def set_reduced_kernels(mode: int):
     check(load().dc_set_reduced_kernels(int(mode)))
 
 
-def set_batch_gram_schmidt(batched: int):
+def set_batch_launches(batched: int):
     """Lockstep batched solves: 1 (default) one launch per Gram-Schmidt pass for
-    up to 16 columns, 0 one launch sequence per column; equal results."""
-    check(load().dc_set_batch_gram_schmidt(int(batched)))
+    up to 16 columns and per chain step for up to 8 operators, 0 launches per
+    column and per operator; equal results."""
+    check(load().dc_set_batch_launches(int(batched)))
 
 
 def dense_eig(A: np.ndarray, vectors=False):

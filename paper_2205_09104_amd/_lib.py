@@ -109,7 +109,7 @@ SIGNATURES = {
     "dc_multi_tile": (C.c_int, [C.c_int32, C.c_int32, C.c_int32, C.c_int32]),
     "dc_set_multi_tile_mode": (C.c_int, [C.c_int32]),
     "dc_set_reduced_kernels": (C.c_int, [C.c_int32]),
-    "dc_set_batch_gram_schmidt": (C.c_int, [C.c_int32]),
+    "dc_set_batch_launches": (C.c_int, [C.c_int32]),
     "dc_profile_apply": (C.c_int, [C.c_void_p, C.c_int32]),
     "dc_profile_apply_read": (C.c_int, [C.c_void_p, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
                                         C.POINTER(C.c_double), C.POINTER(C.c_int64),

@@ -502,9 +502,9 @@ int dc_set_multi_tile_mode(int32_t mode) {
   });
 }
 
-int dc_set_batch_gram_schmidt(int32_t batched) {
+int dc_set_batch_launches(int32_t batched) {
   return guarded([&] {
-    dc::set_batch_gram_schmidt(batched);
+    dc::set_batch_launches(batched);
     return DC_OK;
   });
 }

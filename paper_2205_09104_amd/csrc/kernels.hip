@@ -1348,10 +1348,11 @@ __global__ __launch_bounds__(64) void k_block_jacobi(
 //   prod_r = v_r - ca t_r;  y_r = c0 v_r + cb prod_r,
 // later steps: prod_r -= ca t_r;  y_r += cb prod_r  (t_r = A~ of the chain input).
 template <typename VR>
-__global__ void k_chain_multi(const cx<VR>* const* __restrict__ t, const cx<VR>* const* __restrict__ v,
-                              cx<VR>* const* __restrict__ prod, cx<VR>* const* __restrict__ y,
-                              size_t N, z64 c0, z64 ca, z64 cb, int first) {
-  const int r = blockIdx.y;
+__device__ __forceinline__ void chain_multi_body(const cx<VR>* const* __restrict__ t,
+                                                 const cx<VR>* const* __restrict__ v,
+                                                 cx<VR>* const* __restrict__ prod,
+                                                 cx<VR>* const* __restrict__ y, size_t N, z64 c0,
+                                                 z64 ca, z64 cb, int first, int r) {
   const cx<VR>* tr = t[r];
   cx<VR>* pr = prod[r];
   cx<VR>* yr = y[r];
@@ -1370,6 +1371,26 @@ __global__ void k_chain_multi(const cx<VR>* const* __restrict__ t, const cx<VR>*
     yy.im += br * p.im + bi * p.re;
     yr[i] = yy;
   }
+}
+
+template <typename VR>
+__global__ void k_chain_multi(const cx<VR>* const* __restrict__ t, const cx<VR>* const* __restrict__ v,
+                              cx<VR>* const* __restrict__ prod, cx<VR>* const* __restrict__ y,
+                              size_t N, z64 c0, z64 ca, z64 cb, int first) {
+  chain_multi_body<VR>(t, v, prod, y, N, c0, ca, cb, first, blockIdx.y);
+}
+
+// The chain step of several operators' column sets in one launch: blockIdx.z
+// is the operator, blockIdx.y its column (elementwise, so any grid gives the
+// per-operator launches' results).
+template <typename VR>
+__global__ void k_chain_groups(ChainGroups g, int first) {
+  const int gi = int(blockIdx.z), r = int(blockIdx.y);
+  if (gi >= g.count || r >= g.R[gi]) return;
+  chain_multi_body<VR>(static_cast<const cx<VR>* const*>(g.t[gi]),
+                       static_cast<const cx<VR>* const*>(g.v[gi]),
+                       static_cast<cx<VR>* const*>(g.prod[gi]), static_cast<cx<VR>* const*>(g.y[gi]),
+                       g.N[gi], g.c0[gi], g.ca[gi], g.cb[gi], first, r);
 }
 
 // ------------------------------------------------------------------ multi-RHS apply
@@ -3192,6 +3213,24 @@ void launch_chain_multi(Prec p, const void* const* t, const void* const* v, void
   DC_HIP(hipGetLastError());
 }
 
+void launch_chain_groups(Prec p, const ChainGroups& g, int first, hipStream_t st) {
+  if (g.count < 0 || g.count > kChainGroups) throw InvalidArg("chain table holds 0..8 operators");
+  if (g.count == 0) return;
+  size_t nmax = 1;
+  int rmax = 0;
+  for (int i = 0; i < g.count; ++i) {
+    if (g.R[i] < 0) throw InvalidArg("negative column count");
+    if (first && g.R[i] > 0 && !g.v[i]) throw InvalidArg("the first chain step needs v");
+    nmax = std::max(nmax, g.N[i]);
+    rmax = std::max(rmax, g.R[i]);
+  }
+  if (rmax == 0) return;
+  const dim3 grid(grid_for(nmax, 256, 512), unsigned(rmax), unsigned(g.count)), block(256);
+  if (p == P64) hipLaunchKernelGGL(k_chain_groups<double>, grid, block, 0, st, g, first);
+  else hipLaunchKernelGGL(k_chain_groups<float>, grid, block, 0, st, g, first);
+  DC_HIP(hipGetLastError());
+}
+
 size_t multi_lds_bytes(int n, bool dbl, int rb) {
   const int np = multi_np(n);
   return size_t(2) * (size_t(np) + rb) * (np + 1) * (dbl ? sizeof(double) : sizeof(float));
@@ -3493,15 +3532,15 @@ void launch_multiaxpy(Prec p, void* w, const void* b0, int q0, const void* b1, i
 }
 
 namespace {
-int g_batch_gs = 1;
+int g_batch_launches = 1;
 }
 
-void set_batch_gram_schmidt(int batched) {
-  if (batched != 0 && batched != 1) throw InvalidArg("batched Gram-Schmidt mode must be 0 or 1");
-  g_batch_gs = batched;
+void set_batch_launches(int batched) {
+  if (batched != 0 && batched != 1) throw InvalidArg("batched launch mode must be 0 or 1");
+  g_batch_launches = batched;
 }
 
-int batch_gram_schmidt() { return g_batch_gs; }
+int batch_launches() { return g_batch_launches; }
 
 static void check_cols(int count) {
   if (count < 0 || count > kOrthCols) throw InvalidArg("column table holds 0..16 columns");

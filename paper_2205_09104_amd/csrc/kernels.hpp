@@ -329,10 +329,25 @@ struct ScaleCols {
   int count = 0;
 };
 void launch_scale_step_cols(Prec p, const ScaleCols& t, int j, hipStream_t st);
-// Whether lockstep batches use these (1, default) or one launch sequence per
-// column (0); process-wide, equal results.
-void set_batch_gram_schmidt(int batched);
-int batch_gram_schmidt();
+// launch_chain_multi for up to kChainGroups operators' column sets in one
+// launch (each with its own pointer tables, length and coefficients).
+constexpr int kChainGroups = 8;
+struct ChainGroups {
+  const void* t[kChainGroups] = {};
+  const void* v[kChainGroups] = {};
+  const void* prod[kChainGroups] = {};
+  const void* y[kChainGroups] = {};
+  size_t N[kChainGroups] = {};
+  int R[kChainGroups] = {};
+  z64 c0[kChainGroups] = {}, ca[kChainGroups] = {}, cb[kChainGroups] = {};
+  int count = 0;
+};
+void launch_chain_groups(Prec p, const ChainGroups& g, int first, hipStream_t st);
+// Whether lockstep batches use the column / operator tables above (1,
+// default) or launch per column and per operator (0); process-wide, equal
+// results.
+void set_batch_launches(int batched);
+int batch_launches();
 // out[0] = sqrt(*nrm2), out[1] = its reciprocal (0 for a zero norm); device pointers
 void launch_norm_root(const double* nrm2, double* out, hipStream_t st);
 

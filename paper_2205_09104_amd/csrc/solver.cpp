@@ -2166,28 +2166,53 @@ struct Batch {
       return;
     }
     A(in, T_TA);
+    chain_step(in, out, 1);
+    for (int i = 2; i < d; ++i) {
+      A(T_PROD, T_TA);
+      chain_step(in, out, i);
+    }
+  }
+
+  // Chain step i (1: the first) of every group with active columns: slot
+  // T_PROD and slot out from slot T_TA (and slot in for the first), with the
+  // group's own roots; one launch for up to kChainGroups groups, or one per
+  // group when the batch runs its launches per column.
+  void chain_step(int in, int out, int i) {
+    auto inv = [](cd t) { const cd r = 1.0 / t; return mk(r.real(), r.imag()); };
+    const bool first = i == 1;
+    ChainGroups cg;
+    auto flush = [&]() {
+      launch_chain_groups(p, cg, first ? 1 : 0, st);
+      cg = ChainGroups{};
+    };
     for (size_t gi = 0; gi < g.size(); ++gi) {
       const Group& gr = g[gi];
       if (gr.act.empty()) continue;
       const auto& th = gr.var->theta;
-      launch_chain_multi(p, reinterpret_cast<const void* const*>(slot(int(gi), T_TA)),
-                         reinterpret_cast<const void* const*>(slot(int(gi), in)),
-                         reinterpret_cast<void* const*>(slot(int(gi), T_PROD)),
-                         reinterpret_cast<void* const*>(slot(int(gi), out)), int(gr.act.size()),
-                         gr.N, inv(th[0]), inv(th[0]), inv(th[1]), 1, st);
-    }
-    for (int i = 2; i < d; ++i) {
-      A(T_PROD, T_TA);
-      for (size_t gi = 0; gi < g.size(); ++gi) {
-        const Group& gr = g[gi];
-        if (gr.act.empty()) continue;
-        const auto& th = gr.var->theta;
-        launch_chain_multi(p, reinterpret_cast<const void* const*>(slot(int(gi), T_TA)), nullptr,
-                           reinterpret_cast<void* const*>(slot(int(gi), T_PROD)),
-                           reinterpret_cast<void* const*>(slot(int(gi), out)), int(gr.act.size()),
-                           gr.N, mk(0.0, 0.0), inv(th[i - 1]), inv(th[i]), 0, st);
+      const z64 c0 = first ? inv(th[0]) : mk(0.0, 0.0);
+      const z64 ca = inv(th[i - 1]), cb = inv(th[i]);
+      const void* const* tv = reinterpret_cast<const void* const*>(slot(int(gi), T_TA));
+      const void* const* vv = first ? reinterpret_cast<const void* const*>(slot(int(gi), in)) : nullptr;
+      void* const* pv = reinterpret_cast<void* const*>(slot(int(gi), T_PROD));
+      void* const* yv = reinterpret_cast<void* const*>(slot(int(gi), out));
+      if (!batch_launches()) {
+        launch_chain_multi(p, tv, vv, pv, yv, int(gr.act.size()), gr.N, c0, ca, cb, first ? 1 : 0,
+                           st);
+        continue;
       }
+      const int c = cg.count++;
+      cg.t[c] = tv;
+      cg.v[c] = vv;
+      cg.prod[c] = pv;
+      cg.y[c] = yv;
+      cg.N[c] = gr.N;
+      cg.R[c] = int(gr.act.size());
+      cg.c0[c] = c0;
+      cg.ca[c] = ca;
+      cg.cb[c] = cb;
+      if (cg.count == kChainGroups) flush();
     }
+    if (cg.count) flush();
   }
 
   void Ahat(int in, int out) {
@@ -2231,7 +2256,7 @@ struct Batch {
   void enqueue_steps(int steps, const std::vector<std::vector<double>>& target) {
     for (int j = 0; j < steps; ++j) {
       Ahat(T_NFIX + j, T_NFIX + j + 1);
-      if (batch_gram_schmidt()) {
+      if (batch_launches()) {
         orth_batched(j, steps, target);
         continue;
       }
@@ -2346,7 +2371,7 @@ struct Batch {
     if (gc.broken || op0.prof.on || !tiles_tuned()) return false;
     std::vector<uintptr_t> key = {0xBA7C4u, uintptr_t(tab.p), uintptr_t(steps), uintptr_t(p),
                                   uintptr_t(ldh), uintptr_t(g.size()), uintptr_t(op0.bpart.p),
-                                  uintptr_t(batch_gram_schmidt())};
+                                  uintptr_t(batch_launches())};
     for (size_t gi = 0; gi < g.size(); ++gi) {
       Group& gr = g[gi];
       key.insert(key.end(), {uintptr_t(gr.op), uintptr_t(gr.var), uintptr_t(gr.var->poly_serial),

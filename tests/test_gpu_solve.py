@@ -395,15 +395,16 @@ def test_mixed_lattice_batch_rejects_bad_input():
 
 
 @pytest.mark.parametrize("cfg", ["poly", "bj", "recycle"])
-def test_batched_gram_schmidt_equals_per_column(cfg):
-    """Lockstep mixed batch with the Gram-Schmidt passes of all columns in one
-    launch each (default) against one launch sequence per column: the same
-    iterates bit for bit and the same step counts, eager and graph-replayed.
+def test_batched_launches_equal_per_column(cfg):
+    """Lockstep mixed batch with the Gram-Schmidt passes of all columns and the
+    chain steps of all operators in one launch each (default) against launches
+    per column and per operator: the same iterates bit for bit and the same
+    step counts, eager and graph-replayed.
     "recycle": every operator first builds a recycle space in a single solve,
     so the batch deflates against it (a non-empty first basis part)."""
     import paper_2205_09104_amd as dc
     from paper_2205_09104_amd import CoarseOp, Opts
-    log("batched gram-schmidt", cfg)
+    log("batched launches", cfg)
     pairs = [make_pair((2, 2, 2, 2), 4, 3.2), make_pair((3, 2, 2, 2), 4, 3.1, mu=0.05),
              make_pair((4, 3, 2, 2), 4, 3.0)]
     ops = [p[0] for p in pairs]
@@ -422,14 +423,14 @@ def test_batched_gram_schmidt_equals_per_column(cfg):
     res = {}
     try:
         for mode in (0, 1):
-            dc.set_batch_gram_schmidt(mode)
+            dc.set_batch_launches(mode)
             for graphs in (0, 1):
                 x, st, rc = CoarseOp.solve_multi(ops, bs, tols, Opts(graphs=graphs, **kw))
                 assert rc == 0
                 res[(mode, graphs)] = ([xi.cpu() for xi in x],
                                        [[s["iters"] for s in sg] for sg in st])
     finally:
-        dc.set_batch_gram_schmidt(1)
+        dc.set_batch_launches(1)
     ref_x, ref_it = res[(0, 0)]
     for key, (x, it) in res.items():
         assert it == ref_it, key
@@ -439,7 +440,7 @@ def test_batched_gram_schmidt_equals_per_column(cfg):
         for j in range(b.shape[0]):
             assert oracle_relres(oop, x[j].numpy(), b[j].cpu().numpy()) <= t[j]
     with pytest.raises(Exception):
-        dc.set_batch_gram_schmidt(2)
+        dc.set_batch_launches(2)
 
 
 @pytest.mark.parametrize("cfg", ["poly", "bj"])
