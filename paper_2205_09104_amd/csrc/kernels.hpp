@@ -329,6 +329,10 @@ struct ScaleCols {
   int count = 0;
 };
 void launch_scale_step_cols(Prec p, const ScaleCols& t, int j, hipStream_t st);
+// the tables travel as kernel arguments, which must stay within 4 KB
+static_assert(sizeof(OrthCols) + 16 <= 4096, "column table too large for kernel arguments");
+static_assert(sizeof(FinishCols) + 32 <= 4096, "finish table too large for kernel arguments");
+static_assert(sizeof(ScaleCols) + 16 <= 4096, "scale table too large for kernel arguments");
 // launch_chain_multi for up to kChainGroups operators' column sets in one
 // launch (each with its own pointer tables, length and coefficients).
 constexpr int kChainGroups = 8;
@@ -343,6 +347,7 @@ struct ChainGroups {
   int count = 0;
 };
 void launch_chain_groups(Prec p, const ChainGroups& g, int first, hipStream_t st);
+static_assert(sizeof(ChainGroups) + 16 <= 4096, "chain table too large for kernel arguments");
 // Whether lockstep batches use the column / operator tables above (1,
 // default) or launch per column and per operator (0); process-wide, equal
 // results.
