@@ -47,7 +47,7 @@ def parse():
     p.add_argument("--k", type=int, default=384)
     p.add_argument("--bj", type=int, default=1, choices=[0, 1],
                    help="left block Jacobi (B = D_ee on the reduced system)")
-    p.add_argument("--u", type=int, default=40, help="recycle-space refreshes before freezing")
+    p.add_argument("--u", type=int, default=30, help="recycle-space refreshes before freezing")
     p.add_argument("--schur", type=int, default=1, choices=[0, 1],
                    help="solve the odd-even reduced system (1) or the full lattice (0)")
     p.add_argument("--full-steps", type=int, default=-1,
@@ -68,7 +68,7 @@ def parse():
     p.add_argument("--c2-steps", type=int, default=16,
                    help="timed solves of the same method on the 8^4 workload after the "
                         "headline (0: skip)")
-    p.add_argument("--inner-tol", type=float, default=1e-1)
+    p.add_argument("--inner-tol", type=float, default=5e-2)
     p.add_argument("--reduced-kernels", type=int, default=0, choices=[0, 1],
                    help="reduced operator: 0 the single-read kernel pair where it applies, "
                         "1 the two-kernel form")
