@@ -99,6 +99,11 @@ def parse():
                    help="only build the workload's operator and run this many multi-RHS (MFMA) "
                         "applies of --multi-rhs right-hand sides in --inner precision, for "
                         "kernel traces and hardware counters")
+    p.add_argument("--mixed-probe", type=int, default=0, metavar="BATCHES",
+                   help="only run this many solves of the launch-bound mixed batch (4^4, 6x4^3, "
+                        "6^2x4^2; eager) with --batch-launches, for kernel traces")
+    p.add_argument("--batch-launches", type=int, default=1, choices=[0, 1],
+                   help="lockstep batches: 1 batched Gram-Schmidt and chain launches, 0 per column")
     p.add_argument("--copy-probe", type=int, default=0, metavar="MiB",
                    help="only run a plain elementwise copy of this many MiB (read + write), "
                         "the reference for scaling HBM byte counters")
@@ -231,6 +236,9 @@ def main():
 
     if a.copy_probe:
         copy_probe(a.copy_probe)
+        return
+    if a.mixed_probe:
+        mixed_probe(a)
         return
 
     import synth
@@ -715,17 +723,8 @@ def mixed_graphs(a):
     replayed as one HIP graph."""
     import torch
 
-    import synth
     from paper_2205_09104_amd import CoarseOp, Opts
-    w = synth.WORKLOADS["c1"]
-    dims_list = [(4, 4, 4, 4), (6, 4, 4, 4), (6, 6, 4, 4)]
-    ops, bs = [], []
-    for i, dims in enumerate(dims_list):
-        A = synth.self_blocks(dims, w.n_tv, w.m0(), w.seed, device="cuda")
-        B = synth.hop_blocks(dims, w.n_tv, w.seed, device="cuda")
-        ops.append(CoarseOp(A, B, dims))
-        bs.append(torch.stack([synth.rhs(dims, w.n_tv, 10 * i + r, device="cuda") for r in range(2)]))
-    tols = [[1e-10, 1e-10]] * len(ops)
+    dims_list, w, ops, bs, tols = mixed_batch()
     out = {"lattices": ["x".join(map(str, d)) for d in dims_list], "n_tv": w.n_tv,
            "rhs_per_lattice": 2, "tol": 1e-10}
     import paper_2205_09104_amd as dc
@@ -755,6 +754,48 @@ def mixed_graphs(a):
     for op in ops:
         op.close()
     return out
+
+
+def mixed_batch(device="cuda"):
+    """The launch-bound mixed batch: operators, right-hand sides, tolerances."""
+    import torch
+
+    import synth
+    from paper_2205_09104_amd import CoarseOp
+    w = synth.WORKLOADS["c1"]
+    dims_list = [(4, 4, 4, 4), (6, 4, 4, 4), (6, 6, 4, 4)]
+    ops, bs = [], []
+    for i, dims in enumerate(dims_list):
+        A = synth.self_blocks(dims, w.n_tv, w.m0(), w.seed, device=device)
+        B = synth.hop_blocks(dims, w.n_tv, w.seed, device=device)
+        ops.append(CoarseOp(A, B, dims))
+        bs.append(torch.stack([synth.rhs(dims, w.n_tv, 10 * i + r, device=device) for r in range(2)]))
+    return dims_list, w, ops, bs, [[1e-10, 1e-10]] * len(ops)
+
+
+def mixed_probe(a):
+    """a.mixed_probe eager solves of the mixed batch with a.batch_launches (after
+    one untimed solve), printing batches/s and the lockstep step counts."""
+    import torch
+
+    import paper_2205_09104_amd as dc
+    from paper_2205_09104_amd import CoarseOp, Opts
+    _, _, ops, bs, tols = mixed_batch()
+    dc.set_batch_launches(a.batch_launches)
+    o = Opts(m=20, d=4, seed=3)
+    CoarseOp.solve_multi(ops, bs, tols, o)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(a.mixed_probe):
+        _, st, rc = CoarseOp.solve_multi(ops, bs, tols, o)
+        assert rc == 0
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    steps = [max(s["iters"] for s in sg) for sg in st]
+    log(f"mixed probe, batch launches {a.batch_launches}: {a.mixed_probe / dt:.1f} batches/s, "
+        f"lockstep steps per operator {steps}")
+    for op in ops:
+        op.close()
 
 
 def multi_probe(op, w, a):
