@@ -488,7 +488,8 @@ int dc_set_multi_tile_mode(int32_t mode);
  * pair); FP64 and other n use the two-kernel form.  mode 1: always the
  * two-kernel form (each kernel reads the hop blocks of its rows: eighteen
  * blocks per pair).  The two forms add the same terms in the same order, so
- * results are equal bit for bit.  Other values: DC_ERR_INVALID. */
+ * results are equal bit for bit.  Other values: DC_ERR_INVALID.  Set it while
+ * no call of the library runs on another thread. */
 int dc_set_reduced_kernels(int32_t mode);
 
 /* Launches of the lockstep batched solves (solve_coarse_batch,
@@ -499,7 +500,8 @@ int dc_set_reduced_kernels(int32_t mode);
  * column and per operator.  Each column's sums are the same either way, so
  * results are equal bit for bit; the batched form removes most launches of a
  * step on lattices small enough that launches, not HBM, bound it.
- * Process-wide.  Other values: DC_ERR_INVALID. */
+ * Process-wide; set it while no call of the library runs on another thread.
+ * Other values: DC_ERR_INVALID. */
 int dc_set_batch_launches(int32_t batched);
 
 /* Message of the last error on this thread ("" if none). */
