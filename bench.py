@@ -144,9 +144,9 @@ def stage1_bytes(V, n, prec):
 # WRITE_SIZE 1048576 KiB for 1 GiB written).  Valid only for the apply
 # source it was taken on.
 TRAFFIC = {"workload": "c3", "prec": "f16s", "kernel": 1,
-           "fetch_kib": 2697056.625, "fetch_scale": 1048576.0 / 524299.5,
-           "write_kib": 196610.40625, "write_scale": 1048576.0 / 1048576.0,
-           "apply_source_sha256": "dda0ff2aaa16e0f8773e008b6331767753e29bd54322e54355adb4e8c90050c4"}
+           "fetch_kib": 2696996.0, "fetch_scale": 1048576.0 / 524299.5,
+           "write_kib": 196610.1875, "write_scale": 1048576.0 / 1048576.0,
+           "apply_source_sha256": "43cc144ec0a389f60a8a257000baef54b081f700817b708daa8b6647d7a5af35"}
 
 
 def apply_source_digest():

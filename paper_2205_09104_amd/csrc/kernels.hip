@@ -915,8 +915,8 @@ __global__ __launch_bounds__(64 * kRedWaves) void k_reduced_eo(
 // of eighteen; the sums and signs are those of the two-kernel form, so the
 // results agree with it bit for bit.
 //
-// Eight waves per workgroup, one per hop tile; the tiles are loaded
-// non-temporally (one launch reads each once).  The odd site's inverse tile is
+// Eight waves per workgroup, one per hop tile; the tiles and the inverse are
+// loaded non-temporally (one launch reads each once).  The odd site's inverse tile is
 // staged in LDS and its product with the summed hop products is split over the
 // eight waves: wave w takes rows w T .. w T + T - 1, which lane group lr = w
 // holds in the one-wave tile layout; its lane (a, lc) forms the partial sum
@@ -949,7 +949,11 @@ __global__ __launch_bounds__(512, (scatter_min_waves<T, P>())) void k_reduced_sc
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   {
     const uint4* ip = block_ptr<T, P>(inv, size_t(x));
-    for (int u = w; u < UNITS; u += 8) inv_lds[u * 64 + lane] = ip[u * 64 + lane];
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    for (int u = w; u < UNITS; u += 8) {   // read once per launch: non-temporal
+      const u32x4 q = __builtin_nontemporal_load(reinterpret_cast<const u32x4*>(ip) + u * 64 + lane);
+      inv_lds[u * 64 + lane] = make_uint4(q.x, q.y, q.z, q.w);
+    }
   }
   TileRegs<T, P> R;
   A s = A(1);
@@ -1027,7 +1031,7 @@ __global__ __launch_bounds__(512, (scatter_min_waves<T, P>())) void k_reduced_sc
 }
 
 // Second kernel of the single-read form: one wave per even row r (site
-// x = esite[r]).  The eight slots of hp[r], negated and summed in slot order,
+// x = esite[r]); its block is loaded non-temporally (read once per launch).  The eight slots of hp[r], negated and summed in slot order,
 // are the hop terms k_reduced_eo sums from its own products; the row is then
 // finished as there: BJ x_e + A_e^{-1} (sum), else A_e x_e (+ i tm Gamma5 x_e)
 // with the terms added one by one, and the epilogue.
@@ -1050,7 +1054,7 @@ __global__ __launch_bounds__(64) void k_reduced_gather(
   const int x = esite[r];
   const int lane = threadIdx.x;
   TileRegs<T, P> R;
-  if (BJ) R.load(block_ptr<T, P>(einv, size_t(x)), lane);
+  if (BJ) R.load_stream(block_ptr<T, P>(einv, size_t(x)), lane);
   cx<VR> h[8];
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
@@ -1100,7 +1104,7 @@ __global__ __launch_bounds__(64) void k_reduced_gather(
   } else {
     if (x_e) {
       const int item = 5 * x;
-      R.load(block_ptr<T, P>(blocks, size_t(item)), lane);
+      R.load_stream(block_ptr<T, P>(blocks, size_t(item)), lane);
       const A s = (P == P16S) ? A(scales[item]) : A(1);
       wave_product<T, P, true, 0>(R, s, x_e + size_t(r) * n, self_part, n, tm, lane);
     } else {
