@@ -49,6 +49,18 @@ def test_default_opts_and_error_paths(lib):
     assert lib.solve_coarse(None, None, 1, None, None, None, 0, None, None) == _lib.DC_ERR_INVALID
 
 
+def test_process_wide_switches_validate_their_argument(lib):
+    """The kernel-form switches take 0 or 1 (no device work); anything else is
+    DC_ERR_INVALID with a message, and the setting stays as it was."""
+    from paper_2205_09104_amd import _lib
+    for fn in (lib.dc_set_reduced_kernels, lib.dc_set_batch_launches):
+        for bad in (-1, 2, 7):
+            assert fn(bad) == _lib.DC_ERR_INVALID
+            assert lib.dc_last_error().decode()
+    assert lib.dc_set_reduced_kernels(1) == 0 and lib.dc_set_reduced_kernels(0) == 0
+    assert lib.dc_set_batch_launches(0) == 0 and lib.dc_set_batch_launches(1) == 0
+
+
 def test_dense_eig_matches_scipy():
     from paper_2205_09104_amd import dense_eig
     rng = np.random.default_rng(0)
